@@ -1,0 +1,100 @@
+"""Seeded input generator: published RNG vectors, determinism, cleaning rules."""
+import numpy as np
+import pytest
+
+import graphgen
+
+
+def test_splitmix64_reference_vectors():
+    # First outputs of SplitMix64 seeded with 0 and with 1234567 (Vigna's
+    # reference implementation, splitmix64.c).
+    assert graphgen.splitmix64_draw(0, 0) == 0xE220A8397B1DCDAF
+    assert graphgen.splitmix64_draw(1234567, 0) == 6457827717110365317
+    assert graphgen.splitmix64_draw(1234567, 1) == 3203168211198807973
+
+
+def _check_clean(g, weighted):
+    off, col = g.offsets, g.col
+    assert off[0] == 0 and np.all(np.diff(off) >= 0) and off[-1] == col.size
+    src = np.repeat(np.arange(g.n), np.diff(off))
+    assert not np.any(src == col), "self-loop kept"
+    # rows sorted strictly increasing => no duplicates
+    same_row = src[1:] == src[:-1]
+    assert np.all(col[1:][same_row] > col[:-1][same_row])
+    assert col.min() >= 0 and col.max() < g.n
+    if weighted:
+        assert g.weights is not None and g.weights.size == col.size
+
+
+def test_rmat_deterministic_and_thread_independent():
+    g1 = graphgen.rmat(12, 8, seed=3, weights=(1, 255, 9), nthreads=1)
+    g2 = graphgen.rmat(12, 8, seed=3, weights=(1, 255, 9), nthreads=5)
+    assert np.array_equal(g1.offsets, g2.offsets)
+    assert np.array_equal(g1.col, g2.col)
+    assert np.array_equal(g1.weights, g2.weights)
+    g3 = graphgen.rmat(12, 8, seed=4, weights=(1, 255, 9))
+    assert not (g3.m == g1.m and np.array_equal(g3.col, g1.col))
+    _check_clean(g1, True)
+    assert g1.weights.min() >= 1 and g1.weights.max() <= 255
+    assert g1.m <= 8 << 12
+
+
+def test_rmat_quadrant_skew():
+    # With a=0.57, b=c=0.19 the top bit of src is 0 with probability a+b=0.76
+    # for every generated edge; dedup removes mostly low-id duplicates, so
+    # check on a graph large enough to be dominated by distinct edges.
+    g = graphgen.rmat(16, 4, seed=11)
+    src = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    frac_low = np.mean(src < g.n // 2)
+    assert 0.70 < frac_low < 0.80
+    frac_low_dst = np.mean(g.col < g.n // 2)
+    assert 0.70 < frac_low_dst < 0.80
+    # vertex 0 is the hub (no permutation)
+    assert np.argmax(np.diff(g.offsets)) == 0
+
+
+def test_symmetrize():
+    g = graphgen.rmat(11, 8, seed=2, symmetrize=True)
+    _check_clean(g, False)
+    src = np.repeat(np.arange(g.n), np.diff(g.offsets)).astype(np.int64)
+    fwd = set(zip(src.tolist(), g.col.tolist()))
+    assert all((v, u) in fwd for (u, v) in fwd)
+
+
+def test_uniform_generator():
+    g = graphgen.uniform(12, 1 << 15, seed=1)
+    _check_clean(g, False)
+    deg = np.diff(g.offsets)
+    # uniform endpoints: no hub far above the mean
+    assert deg.max() < 8 * deg.mean() + 10
+
+
+def test_dedup_keeps_min_weight():
+    g = graphgen.from_edges(3, [0, 0, 0, 1, 1], [1, 1, 2, 1, 2], [7, 3, 5, 4, 9])
+    assert g.offsets.tolist() == [0, 2, 3, 3]
+    assert g.col.tolist() == [1, 2, 2]
+    assert g.weights.tolist() == [3, 5, 9]
+
+
+def test_bounded_draws_range_and_uniformity():
+    x = graphgen.bounded_draws(7, 3, 200000, 1, 255)
+    assert x.min() == 1 and x.max() == 255
+    counts = np.bincount(x, minlength=256)[1:]
+    expected = x.size / 255
+    chi2 = np.sum((counts - expected) ** 2 / expected)
+    assert chi2 < 400  # 254 dof; mean 254, sd ~22.5
+
+
+def test_poisson_arrivals_rate():
+    t = graphgen.poisson_arrivals(2000.0, 20000, seed=4000)
+    assert np.all(np.diff(t) > 0)
+    rate = t.size / t[-1]
+    assert 1900 < rate < 2100
+
+
+@pytest.mark.parametrize("i", [0, 13, 31])
+def test_batched_recipe_shapes(i):
+    scale = 12 + (9 * i) // 32
+    g = graphgen.recipes.batched_graph(i) if scale <= 16 else None
+    if g is not None:
+        assert g.n == 1 << scale
