@@ -1,0 +1,210 @@
+/*
+ * seraph.h -- C ABI of libseraph, an MI355X (gfx950) engine for Seraph's
+ * method: repeated in-GPU pull iteration of resident in-edge subgraphs with
+ * predictive vertex updating, while the next subgraph streams from pinned
+ * host memory (Li, "Scaling Up Large-Scale Graph Processing for
+ * GPU-Accelerated Heterogeneous Systems", arXiv 1806.00762).
+ *
+ * Conventions (all entry points):
+ *   - Every function that can fail returns sr_status: 0 = SR_OK, < 0 = error.
+ *     No C++ exception crosses the ABI. On error, out-parameters are left
+ *     untouched and sr_ctx_last_error() holds a message for the context.
+ *   - Pointers marked "host" must point to host memory; "device" to memory
+ *     on the context's GPU. The caller owns every buffer it passes; the
+ *     library copies what it keeps before returning (except where stated).
+ *   - Handles are not thread-safe, except sr_server_submit / sr_server_poll,
+ *     which may be called from any thread while the server runs.
+ *   - Vertex ids are int32 in [0, n). Unreached vertices and unset values
+ *     read back as SR_INF (BFS, SSSP) -- see sr_read_values.
+ *   - All device memory the library allocates for a context is charged to
+ *     the context's device budget; an allocation that would exceed it fails
+ *     with SR_EBUDGET before any device call is made.
+ */
+#ifndef SERAPH_H
+#define SERAPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SR_ABI_VERSION 1
+#define SR_INF 0xFFFFFFFFu
+
+typedef enum {
+  SR_OK = 0,
+  SR_EINVAL = -1,    /* bad argument (null handle, id out of range, bad flags) */
+  SR_ENOMEM = -2,    /* host allocation failed */
+  SR_EBUDGET = -3,   /* device budget cannot hold what the call needs */
+  SR_EDEVICE = -4,   /* HIP runtime error, or no device on a host-only context */
+  SR_ENOTCONV = -5,  /* max_passes reached before convergence (values readable) */
+  SR_ESTATE = -6,    /* call not valid in the handle's current state */
+  SR_EBUSY = -7      /* server queue full / resource in use */
+} sr_status;
+
+/* Vertex programs. BFS, CC and SSSP are the evaluated algorithms (Section 5.1);
+ * PageRank is named in Section 4.3 and defined here as
+ *   x[v] = (1-d) t[v] + d (sum_{u->v} x[u]/outdeg(u) + D t[v]),
+ *   D = sum of x over vertices without out-edges,
+ * with t uniform (SR_PAGERANK) or the unit vector of `source` (SR_PPR). */
+typedef enum { SR_BFS = 0, SR_SSSP = 1, SR_CC = 2, SR_PAGERANK = 3, SR_PPR = 4 } sr_algo;
+
+/* Predictive vertex updating (Section 4). STRONG uses the Table I
+ * thresholds (BFS, SSSP, CC only); WEAK uses the state-transition diagram of
+ * Section 4.3 / Fig. 6; DEFAULT picks STRONG for BFS and CC and WEAK for SSSP
+ * and PageRank, as the paper evaluates them (Section 4.3 Discussion, 5.1). */
+typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAULT = 3 } sr_pvu_mode;
+
+/* sr_graph_load_csr flags */
+#define SR_LOAD_SYMMETRIZE 0x1u  /* build in-edges of the undirected graph (needed for CC) */
+
+/* sr_run_params.flags */
+#define SR_RUN_AUDIT_PVU 0x1u     /* also evaluate skipped vertices; count would-be changes
+                                     (mispredictions) without applying them */
+#define SR_RUN_FORCE_STREAM 0x2u  /* stream pages through slots even if the graph fits */
+#define SR_RUN_RESUME 0x4u        /* continue from the values/state left by the last run */
+
+/* stop reasons reported in sr_run_stats.stop_reason */
+#define SR_STOP_CONVERGED 1   /* a full un-predicted pass changed nothing (min programs)
+                                 or its L1 change fell below tol_l1 (PageRank) */
+#define SR_STOP_FP32_FLOOR 2  /* PageRank: L1 stalled below 1e-6 for 3 full passes */
+#define SR_STOP_MAX_PASSES 3
+
+typedef struct sr_ctx sr_ctx;
+typedef struct sr_graph sr_graph;
+typedef struct sr_server sr_server;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` with a device-memory budget in
+ * bytes (0 = the device's free memory). device = -1 creates a host-only
+ * context: graphs can be loaded, partitioned and inspected, but sr_run and
+ * every other device call return SR_EDEVICE. *out receives the handle. */
+sr_status sr_ctx_create(int device, uint64_t device_budget_bytes, sr_ctx **out);
+void sr_ctx_destroy(sr_ctx *ctx);
+/* Message of the last error on this context ("" if none). Valid until the
+ * next call on the context. ctx may be NULL (then: last sr_ctx_create error). */
+const char *sr_ctx_last_error(const sr_ctx *ctx);
+/* Use caller-owned hipStream_t handles (e.g. torch.cuda streams) for compute
+ * and for host-to-device page copies. NULL restores the library's own
+ * streams. The streams must outlive their use by the context. */
+sr_status sr_ctx_set_streams(sr_ctx *ctx, void *compute_stream, void *copy_stream);
+/* Device bytes currently charged to the budget, and the budget itself. */
+sr_status sr_ctx_memory(const sr_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
+
+/* ------------------------------------------------------------------ graph */
+
+/* Load G = (V, E, w) given as an OUT-edge CSR on the host: the heads of the
+ * arcs leaving u are col_idx[row_offsets[u] .. row_offsets[u+1]-1], weights
+ * (may be NULL = unweighted) aligned with col_idx. n >= 1, m >= 0,
+ * row_offsets[0] = 0, row_offsets[n] = m, non-decreasing, col_idx in [0,n).
+ * The library keeps the graph the way the paper does (Section 3.1, Subgraph
+ * Organization): as in-edges (CSC, i.e. the CSR of the transpose), later cut
+ * into pages of consecutive destination vertices. With SR_LOAD_SYMMETRIZE
+ * the in-edges of the undirected graph (arcs in both directions, duplicates
+ * removed) are kept instead. Out-degrees of the input are kept for PageRank.
+ * Inputs are copied; the caller may free them on return. */
+sr_status sr_graph_load_csr(sr_ctx *ctx, int32_t n, int64_t m, const int64_t *row_offsets,
+                            const int32_t *col_idx, const uint32_t *weights, uint32_t flags,
+                            sr_graph **out);
+
+/* Cut the in-edge CSR into pages (Section 3.1: CSC pages of consecutive
+ * destination vertices with their incoming edges, no destination array).
+ * Pages hold about m / num_parts in-edges each; a vertex is never split
+ * across pages, so a page may exceed that by one in-degree. num_parts = 0
+ * picks the smallest count whose largest page fits a slot of the context's
+ * budget; num_slots (>= 2, 0 = 4) is the number of page slots of the
+ * pipelined window (Section 3.2: num_slots-1 pages computed while one is
+ * copied). Pages live in pinned host memory owned by the graph. */
+sr_status sr_graph_partition(sr_graph *g, int32_t num_parts, int32_t num_slots);
+
+typedef struct {
+  int32_t n;
+  int64_t m;                 /* in-edges kept (after symmetrization) */
+  int32_t weighted;
+  int32_t symmetric;         /* loaded with SR_LOAD_SYMMETRIZE */
+  int32_t num_parts;         /* 0 before sr_graph_partition */
+  int32_t num_slots;
+  uint64_t graph_bytes;      /* in-CSR bytes: 4(n+1) + 4m (+ 4m weights) */
+  uint64_t page_bytes_total; /* sum of page buffer bytes (incl. work lists) */
+  uint64_t max_page_bytes;
+  int32_t resident;          /* pages currently resident on the device */
+} sr_graph_info;
+sr_status sr_graph_info_get(const sr_graph *g, sr_graph_info *out);
+
+/* Read-only view of page `page` (host pointers into the graph's pinned
+ * pages; valid until the graph is repartitioned or destroyed). offsets are
+ * rebased to 0 (n_p + 1 entries); src holds global source vertex ids. */
+typedef struct {
+  int32_t v_begin, v_end;    /* destination vertex range [v_begin, v_end) */
+  int64_t num_edges;
+  const int32_t *offsets;
+  const int32_t *src;
+  const uint32_t *weights;   /* NULL if unweighted */
+  uint64_t bytes;            /* bytes of the page buffer */
+} sr_page_view;
+sr_status sr_graph_page(const sr_graph *g, int32_t page, sr_page_view *out);
+void sr_graph_destroy(sr_graph *g);
+
+/* -------------------------------------------------------------------- run */
+
+/* Weak-predictor state diagram (Section 4.3: user-defined, the engine's
+ * input). States 0..num_states-1 (<= 8); bit i of attempt_mask set = state i
+ * attempts an update; an attempting state moves to on_success[i] if the
+ * value changed and on_fail[i] otherwise; a dormant state always moves to
+ * on_fail[i]. Every state must lead back to an attempting state. */
+typedef struct {
+  uint8_t num_states, initial_state, attempt_mask;
+  uint8_t on_success[8], on_fail[8];
+} sr_pvu_diagram;
+
+/* The default diagram: attempt states {0,1,5}, dormant {2,3,4}; 0 -ok-> 0,
+ * 0 -fail-> 5, 5 -ok-> 0, 5 -fail-> 3, 3 -> 2 -> 1, 1 -ok-> 0, 1 -fail-> 4,
+ * 4 -> 3 (the text of Section 4.3; the 4 -> 3 edge is a reading of Fig. 6). */
+sr_status sr_pvu_default_diagram(sr_pvu_diagram *out);
+
+typedef struct {
+  sr_algo algo;
+  int32_t source;            /* BFS/SSSP source, PPR seed; ignored otherwise */
+  double damping;            /* PageRank d (0 = 0.85) */
+  double tol_l1;             /* PageRank stop: L1 change of a full pass (0 = 1e-9) */
+  int32_t max_passes;        /* 0 = 10000 */
+  int32_t max_inner_iters;   /* sweeps of a window before it slides (A4 re-entry bound); 0 = 4 */
+  sr_pvu_mode pvu;
+  const sr_pvu_diagram *diagram; /* NULL = default diagram */
+  float pr_change_eps;       /* PageRank: |new-old| > eps counts as a valid update */
+  uint32_t flags;            /* SR_RUN_* */
+} sr_run_params;
+
+typedef struct {
+  int32_t passes, sweeps, verify_passes, converged, stop_reason;
+  int64_t edges_scanned;     /* in-edges read by attempted vertices */
+  int64_t vertices_attempted, vertices_skipped, mispredicted;
+  uint64_t h2d_bytes;        /* page bytes copied host -> device */
+  double kernel_ms;          /* summed sweep-kernel time (HIP events) */
+  double h2d_ms;             /* summed page-copy time (HIP events) */
+  double wall_ms;            /* host wall time of sr_run */
+  double final_l1;           /* PageRank: L1 change of the last full pass */
+  int64_t state_hist[8];     /* weak predictor: vertex-sweeps spent in each state */
+  uint64_t algo_bytes;       /* algorithmic bytes of all sweeps (see DESIGN) */
+} sr_run_stats;
+
+/* Run a vertex program to convergence on the graph (partitioned with
+ * defaults if it was not). Pages are resident when the graph fits the
+ * budget and SR_RUN_FORCE_STREAM is not set, otherwise they stream through
+ * the slot window with up to max_inner_iters sweeps per window (Section
+ * 3.2). Returns SR_ENOTCONV if max_passes ran out (values stay readable).
+ * stats may be NULL. */
+sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_stats *stats);
+
+/* Copy the last run's vertex values to host memory: uint32 per vertex for
+ * BFS (levels), SSSP (distances) and CC (labels), SR_INF if unreached;
+ * float32 ranks for PageRank/PPR. dst_bytes must be >= 4n. */
+sr_status sr_read_values(const sr_graph *g, void *host_dst, uint64_t dst_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SERAPH_H */

@@ -1,0 +1,262 @@
+"""Python binding of libseraph (include/seraph.h): an MI355X engine for
+Seraph's streamed, predictively-updated subgraph iteration (arXiv 1806.00762).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library. There is no fallback; if ``libseraph.so`` has not been built, any
+use raises immediately.
+
+Low-level names mirror the C ABI (``sr_ctx_create``, ``sr_run`` ...); the
+``Context`` / ``Graph`` classes wrap them for tests and benchmarks.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libseraph.so")
+
+# --- enums / flags (seraph.h) ------------------------------------------------
+SR_OK, SR_EINVAL, SR_ENOMEM, SR_EBUDGET, SR_EDEVICE, SR_ENOTCONV, SR_ESTATE, SR_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
+SR_BFS, SR_SSSP, SR_CC, SR_PAGERANK, SR_PPR = 0, 1, 2, 3, 4
+SR_PVU_OFF, SR_PVU_STRONG, SR_PVU_WEAK, SR_PVU_DEFAULT = 0, 1, 2, 3
+SR_LOAD_SYMMETRIZE = 0x1
+SR_RUN_AUDIT_PVU, SR_RUN_FORCE_STREAM, SR_RUN_RESUME = 0x1, 0x2, 0x4
+SR_STOP_CONVERGED, SR_STOP_FP32_FLOOR, SR_STOP_MAX_PASSES = 1, 2, 3
+SR_INF = 0xFFFFFFFF
+
+ALGOS = {"bfs": SR_BFS, "sssp": SR_SSSP, "cc": SR_CC, "pagerank": SR_PAGERANK, "pr": SR_PAGERANK,
+         "ppr": SR_PPR}
+PVUS = {"off": SR_PVU_OFF, "strong": SR_PVU_STRONG, "weak": SR_PVU_WEAK, "default": SR_PVU_DEFAULT}
+_STATUS_NAMES = {0: "SR_OK", -1: "SR_EINVAL", -2: "SR_ENOMEM", -3: "SR_EBUDGET", -4: "SR_EDEVICE",
+                 -5: "SR_ENOTCONV", -6: "SR_ESTATE", -7: "SR_EBUSY"}
+
+
+class sr_graph_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("weighted", ctypes.c_int32),
+                ("symmetric", ctypes.c_int32), ("num_parts", ctypes.c_int32),
+                ("num_slots", ctypes.c_int32), ("graph_bytes", ctypes.c_uint64),
+                ("page_bytes_total", ctypes.c_uint64), ("max_page_bytes", ctypes.c_uint64),
+                ("resident", ctypes.c_int32)]
+
+
+class sr_page_view(ctypes.Structure):
+    _fields_ = [("v_begin", ctypes.c_int32), ("v_end", ctypes.c_int32), ("num_edges", ctypes.c_int64),
+                ("offsets", ctypes.POINTER(ctypes.c_int32)), ("src", ctypes.POINTER(ctypes.c_int32)),
+                ("weights", ctypes.POINTER(ctypes.c_uint32)), ("bytes", ctypes.c_uint64)]
+
+
+class sr_pvu_diagram(ctypes.Structure):
+    _fields_ = [("num_states", ctypes.c_uint8), ("initial_state", ctypes.c_uint8),
+                ("attempt_mask", ctypes.c_uint8), ("on_success", ctypes.c_uint8 * 8),
+                ("on_fail", ctypes.c_uint8 * 8)]
+
+
+class sr_run_params(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int), ("source", ctypes.c_int32), ("damping", ctypes.c_double),
+                ("tol_l1", ctypes.c_double), ("max_passes", ctypes.c_int32),
+                ("max_inner_iters", ctypes.c_int32), ("pvu", ctypes.c_int),
+                ("diagram", ctypes.POINTER(sr_pvu_diagram)), ("pr_change_eps", ctypes.c_float),
+                ("flags", ctypes.c_uint32)]
+
+
+class sr_run_stats(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("verify_passes", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("stop_reason", ctypes.c_int32),
+                ("edges_scanned", ctypes.c_int64), ("vertices_attempted", ctypes.c_int64),
+                ("vertices_skipped", ctypes.c_int64), ("mispredicted", ctypes.c_int64),
+                ("h2d_bytes", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
+                ("h2d_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
+                ("final_l1", ctypes.c_double), ("state_hist", ctypes.c_int64 * 8),
+                ("algo_bytes", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["state_hist"] = list(self.state_hist)
+        return d
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "sr_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "sr_ctx_destroy": (None, [_P]),
+    "sr_ctx_last_error": (ctypes.c_char_p, [_P]),
+    "sr_ctx_set_streams": (ctypes.c_int, [_P, _P, _P]),
+    "sr_ctx_memory": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+    "sr_graph_load_csr": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, ctypes.c_uint32,
+                                         ctypes.POINTER(_P)]),
+    "sr_graph_partition": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "sr_graph_info_get": (ctypes.c_int, [_P, ctypes.POINTER(sr_graph_info)]),
+    "sr_graph_page": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(sr_page_view)]),
+    "sr_graph_destroy": (None, [_P]),
+    "sr_pvu_default_diagram": (ctypes.c_int, [ctypes.POINTER(sr_pvu_diagram)]),
+    "sr_run": (ctypes.c_int, [_P, ctypes.POINTER(sr_run_params), ctypes.POINTER(sr_run_stats)]),
+    "sr_read_values": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
+}
+EXTRA_SIGNATURES: dict = {}
+
+_lib = None
+
+
+def lib():
+    """Load libseraph.so (raises if it has not been built: no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libseraph.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    l = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in {**_SIGNATURES, **EXTRA_SIGNATURES}.items():
+        fn = getattr(l, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = l
+    return l
+
+
+def exported_symbols() -> list:
+    return sorted(set(_SIGNATURES) | set(EXTRA_SIGNATURES))
+
+
+class SeraphError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(rc: int, ctx_ptr=None):
+    if rc != SR_OK:
+        msg = lib().sr_ctx_last_error(ctx_ptr)
+        raise SeraphError(rc, msg.decode() if msg else "")
+
+
+def default_diagram() -> sr_pvu_diagram:
+    d = sr_pvu_diagram()
+    _check(lib().sr_pvu_default_diagram(ctypes.byref(d)))
+    return d
+
+
+def make_diagram(num_states, initial, attempt_states, on_success, on_fail) -> sr_pvu_diagram:
+    d = sr_pvu_diagram()
+    d.num_states = num_states
+    d.initial_state = initial
+    d.attempt_mask = sum(1 << s for s in attempt_states)
+    for i in range(8):
+        d.on_success[i] = on_success[i] if i < len(on_success) else 0
+        d.on_fail[i] = on_fail[i] if i < len(on_fail) else 0
+    return d
+
+
+class Context:
+    """A device (or host-only, device=-1) context with a device-memory budget."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        h = _P()
+        rc = lib().sr_ctx_create(device, budget_bytes, ctypes.byref(h))
+        _check(rc, None)
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().sr_ctx_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_streams(self, compute: int = 0, copy: int = 0):
+        """hipStream_t handles as integers (e.g. torch.cuda.Stream().cuda_stream)."""
+        _check(lib().sr_ctx_set_streams(self.h, _P(compute or None), _P(copy or None)), self.h)
+
+    def memory(self):
+        u, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().sr_ctx_memory(self.h, ctypes.byref(u), ctypes.byref(b)), self.h)
+        return u.value, b.value
+
+    def load(self, g, symmetrize: bool = False, weights: Optional[bool] = None) -> "Graph":
+        return Graph(self, g, symmetrize=symmetrize, weights=weights)
+
+
+class Graph:
+    """A graph loaded into a context (C handle sr_graph)."""
+
+    def __init__(self, ctx: Context, g, symmetrize=False, weights=None):
+        self.ctx = ctx
+        off = np.ascontiguousarray(g.offsets, dtype=np.int64)
+        col = np.ascontiguousarray(g.col, dtype=np.int32)
+        w = getattr(g, "weights", None)
+        if weights is False:
+            w = None
+        if w is not None:
+            w = np.ascontiguousarray(w, dtype=np.uint32)
+        h = _P()
+        rc = lib().sr_graph_load_csr(ctx.h, int(g.n), int(off[-1]), off.ctypes.data, col.ctypes.data,
+                                     None if w is None else w.ctypes.data,
+                                     SR_LOAD_SYMMETRIZE if symmetrize else 0, ctypes.byref(h))
+        _check(rc, ctx.h)
+        self.h = h
+        self.n = int(g.n)
+
+    def close(self):
+        if self.h:
+            lib().sr_graph_destroy(self.h)
+            self.h = None
+
+    def partition(self, num_parts: int = 0, num_slots: int = 0):
+        _check(lib().sr_graph_partition(self.h, num_parts, num_slots), self.ctx.h)
+
+    def info(self) -> dict:
+        i = sr_graph_info()
+        _check(lib().sr_graph_info_get(self.h, ctypes.byref(i)), self.ctx.h)
+        return {k: getattr(i, k) for k, _ in i._fields_}
+
+    def page(self, p: int) -> dict:
+        v = sr_page_view()
+        _check(lib().sr_graph_page(self.h, p, ctypes.byref(v)), self.ctx.h)
+        npv = v.v_end - v.v_begin
+        off = np.ctypeslib.as_array(v.offsets, shape=(npv + 1,)).copy()
+        ne = int(v.num_edges)
+        src = np.ctypeslib.as_array(v.src, shape=(ne,)).copy() if ne else np.zeros(0, np.int32)
+        w = None
+        if bool(v.weights) and ne:
+            w = np.ctypeslib.as_array(v.weights, shape=(ne,)).copy()
+        return {"v_begin": v.v_begin, "v_end": v.v_end, "offsets": off, "src": src, "weights": w,
+                "bytes": int(v.bytes)}
+
+    def run(self, algo, source: int = 0, pvu="default", damping: float = 0.85, tol_l1: float = 1e-9,
+            max_passes: int = 0, max_inner_iters: int = 0, diagram: Optional[sr_pvu_diagram] = None,
+            pr_change_eps: float = 0.0, audit: bool = False, force_stream: bool = False,
+            resume: bool = False, check: bool = True) -> dict:
+        p = sr_run_params()
+        p.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        p.source = source
+        p.damping = damping
+        p.tol_l1 = tol_l1
+        p.max_passes = max_passes
+        p.max_inner_iters = max_inner_iters
+        p.pvu = PVUS[pvu] if isinstance(pvu, str) else int(pvu)
+        p.diagram = ctypes.pointer(diagram) if diagram is not None else None
+        p.pr_change_eps = pr_change_eps
+        p.flags = ((SR_RUN_AUDIT_PVU if audit else 0) | (SR_RUN_FORCE_STREAM if force_stream else 0)
+                   | (SR_RUN_RESUME if resume else 0))
+        st = sr_run_stats()
+        rc = lib().sr_run(self.h, ctypes.byref(p), ctypes.byref(st))
+        d = st.as_dict()
+        d["status"] = rc
+        if check and rc not in (SR_OK,):
+            _check(rc, self.ctx.h)
+        return d
+
+    def values(self, dtype=None) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.uint32)
+        _check(lib().sr_read_values(self.h, out.ctypes.data, out.nbytes), self.ctx.h)
+        if dtype is not None:
+            return out.view(dtype)
+        return out

@@ -1,0 +1,133 @@
+// common.hpp -- internal layout shared by the host runtime and the gfx950
+// kernels of libseraph: page buffer format, degree bins, sweep control
+// block, per-sweep records. Not part of the public ABI (include/seraph.h).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace sr {
+
+constexpr uint32_t INF = 0xFFFFFFFFu;
+constexpr uint32_t PAGE_MAGIC = 0x53525047u;  // "SRPG"
+
+// Degree bins of a page (Section 3.1 pages, load-balanced for wave64).
+// A vertex with in-degree d >= 1 goes to
+//   bin b in [0, 5]  if 2^b <= d < 2^(b+1): a group of 2^b lanes, <= 2 edges per lane
+//   bin 6            if 64 <= d <= HEAVY: one wavefront per vertex
+//   bin 7            if d > HEAVY: split into CHUNK-edge chunks, one wavefront
+//                    per chunk, partial results combined by the last chunk
+//   bin 8            if d = 0: a pull can never change a min program's value
+//                    there, so only PageRank (whose value also depends on the
+//                    dangling mass) visits this bin.
+constexpr int NBINS = 9;
+constexpr int BIN_WAVE = 6;
+constexpr int BIN_CHUNK = 7;
+constexpr int BIN_ZERO = 8;
+constexpr int HEAVY = 2048;
+constexpr int CHUNK = 2048;
+
+constexpr int BLOCK = 256;        // threads per workgroup (4 wavefronts)
+constexpr int WAVES = BLOCK / 64;
+
+// vertices per block for bins 0..6 and chunks per block for bin 7
+constexpr int SMALL_ROUNDS = 4;   // vertices per lane group in bins 0..5
+constexpr int WAVE_ROUNDS = 2;    // vertices per wavefront in bin 6
+__host__ __device__ constexpr int bin_items_per_block(int b) {
+  return b < BIN_WAVE ? (BLOCK >> b) * SMALL_ROUNDS
+                      : (b == BIN_WAVE ? WAVES * WAVE_ROUNDS : (b == BIN_CHUNK ? WAVES : BLOCK * 4));
+}
+
+// A heavy-vertex chunk: edges [e_begin, e_end) of local vertex vl; `first`
+// is the index (in the page's chunk list) of the vertex's first chunk and
+// `count` its number of chunks.
+struct Chunk {
+  int32_t vl;
+  int32_t e_begin, e_end;
+  int32_t first_count;  // first | (count << 20), as uint32: first < 2^20, count < 2^12
+};
+
+// First 256 bytes of every page buffer. Section offsets are in bytes from
+// the buffer start, all multiples of 256. The weight section is last so
+// unweighted programs copy only the prefix [0, bytes_unweighted).
+struct alignas(256) PageHeader {
+  uint32_t magic;
+  int32_t v_begin;
+  int32_t n_p;
+  int32_t n_chunks;
+  int64_t m_p;
+  uint64_t off_offsets;   // int32[n_p + 1], rebased to 0
+  uint64_t off_bins;      // int32 local vertex ids, bins 0..6 and 8 back to back
+  uint64_t off_chunks;    // Chunk[n_chunks]
+  uint64_t off_src;       // int32[m_p], global source ids
+  uint64_t off_w;         // uint32[m_p] (weighted graphs only)
+  uint64_t bytes_unweighted;
+  uint64_t bytes_total;
+  int32_t bin_count[NBINS];      // bin 7: number of chunks
+  int32_t bin_start[NBINS];      // start of bin b in the bins section (not bin 7)
+  int32_t n_heavy;               // vertices in bin 7
+  int32_t max_indeg;
+};
+static_assert(sizeof(PageHeader) == 256, "page header is one 256-byte line");
+
+enum Algo : int32_t { A_BFS = 0, A_SSSP = 1, A_CC = 2, A_PR = 3, A_PPR = 4 };
+enum Pvu : int32_t { P_OFF = 0, P_STRONG = 1, P_WEAK = 2 };
+
+// Weak predictor diagram in device-friendly form.
+struct Diagram {
+  uint32_t num_states, initial, attempt_mask, pad;
+  uint8_t succ[8], fail[8];
+};
+
+// Per-sweep host-visible record (written by the last block of each sweep
+// into a pinned, device-mapped ring).
+struct SweepRecord {
+  uint64_t seq;
+  uint64_t changed;
+  uint64_t edges;
+  uint64_t attempted;
+  uint64_t skipped;
+  uint64_t mispred;
+  double l1;
+  uint32_t min_changed;
+  uint32_t threshold;     // strong threshold this sweep used
+  uint32_t phase;         // 0 normal, 1 verification
+  uint32_t done_after;    // control state after this sweep's end-of-pass step
+  uint32_t pass_after;
+  uint32_t stop_reason;
+  uint64_t hist[8];
+  double dangling;        // PageRank dangling mass after the sweep
+  double pass_l1_closed;  // L1 of the pass closed by this sweep (if any)
+};
+
+// Device-resident control block of one run. The sweeps and the end-of-pass
+// step read and update it, so a whole resident solve can be enqueued (or
+// captured) without host round trips.
+struct Ctl {
+  // current pass configuration
+  uint32_t threshold;     // strong: skip vertices with value <= threshold
+  uint32_t phase;         // 1 = verification pass (prediction off)
+  uint32_t done;          // converged or stopped: sweeps become no-ops
+  uint32_t pass;          // passes completed
+  uint32_t stop_reason;
+  uint32_t blocks_done;
+  uint32_t sweep_seq;
+  uint32_t no_improve;
+  // current sweep accumulators
+  unsigned long long sw_changed, sw_edges, sw_attempted, sw_skipped, sw_mispred;
+  unsigned long long sw_hist[8];
+  uint32_t sw_min_changed, pad0;
+  double sw_l1, sw_ddelta;
+  // current pass accumulators
+  unsigned long long pass_changed;
+  uint32_t pass_min_changed, pad1;
+  double pass_l1;
+  double best_l1;
+  double dangling;        // PageRank: D used by the sweeps
+  // run constants
+  int32_t algo, pvu, max_passes, always_verify;
+  double tol_l1;
+  double floor_cap;
+};
+
+}  // namespace sr

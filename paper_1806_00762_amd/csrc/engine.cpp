@@ -1,0 +1,784 @@
+// engine.cpp -- C ABI of libseraph: contexts with a device-memory budget,
+// graph loading and partitioning, and the pass scheduler of Seraph
+// (Section 3.2 pipelined subgraph iteration; Section 4 predictive vertex
+// updating with the all-pull verification pass of Section 4.3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "engine.hpp"
+
+using namespace sr;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+#define HIP_TRY(ctx, expr, what)                   \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return (ctx)->hip_fail(e_, what); \
+  } while (0)
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr uint32_t RING = 4096;
+
+}  // namespace
+
+// ------------------------------------------------------------ allocation
+
+sr_status sr_ctx::dalloc(void **p, uint64_t bytes, const char *what) {
+  *p = nullptr;
+  if (host_only) return fail(SR_EDEVICE, "host-only context has no device");
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~255ull;
+  if (used + bytes > budget)
+    return fail(SR_EBUDGET, std::string("device budget exceeded allocating ") + what + " (" +
+                                std::to_string(bytes) + " B, used " + std::to_string(used) +
+                                " of " + std::to_string(budget) + ")");
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) { *p = nullptr; return hip_fail(e, what); }
+  used += bytes;
+  allocs[*p] = bytes;
+  return SR_OK;
+}
+
+void sr_ctx::dfree(void *p) {
+  if (!p) return;
+  auto it = allocs.find(p);
+  if (it != allocs.end()) {
+    used -= it->second;
+    allocs.erase(it);
+  }
+  (void)hipFree(p);
+}
+
+// --------------------------------------------------------------- context
+
+extern "C" sr_status sr_ctx_create(int device, uint64_t budget, sr_ctx **out) {
+  if (!out) { g_create_err = "out is NULL"; return SR_EINVAL; }
+  sr_ctx *c = new (std::nothrow) sr_ctx();
+  if (!c) { g_create_err = "out of host memory"; return SR_ENOMEM; }
+  c->device = device;
+  c->host_only = device < 0;
+  if (!c->host_only) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+      g_create_err = "no such HIP device";
+      delete c;
+      return SR_EDEVICE;
+    }
+    hipError_t e = hipSetDevice(device);
+    size_t freeb = 0, totalb = 0;
+    if (e == hipSuccess) e = hipMemGetInfo(&freeb, &totalb);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own_compute, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own_copy, hipStreamNonBlocking);
+    void *ring = nullptr;
+    if (e == hipSuccess) e = hipHostMalloc(&ring, sizeof(SweepRecord) * RING, hipHostMallocMapped);
+    if (e != hipSuccess) {
+      g_create_err = std::string("HIP init failed: ") + hipGetErrorString(e);
+      if (c->own_compute) (void)hipStreamDestroy(c->own_compute);
+      if (c->own_copy) (void)hipStreamDestroy(c->own_copy);
+      delete c;
+      return SR_EDEVICE;
+    }
+    c->ring_host = (SweepRecord *)ring;
+    std::memset(c->ring_host, 0xFF, sizeof(SweepRecord) * RING);
+    void *dptr = nullptr;
+    if (hipHostGetDevicePointer(&dptr, ring, 0) != hipSuccess) dptr = ring;
+    c->ring_dev = (SweepRecord *)dptr;
+    c->ring_mask = RING - 1;
+    c->compute = c->own_compute;
+    c->copy = c->own_copy;
+    c->budget = budget ? budget : (uint64_t)freeb;
+  } else {
+    c->budget = budget;
+  }
+  *out = c;
+  return SR_OK;
+}
+
+extern "C" void sr_ctx_destroy(sr_ctx *c) {
+  if (!c) return;
+  if (!c->host_only) {
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c->allocs) (void)hipFree(kv.first);
+    if (c->ring_host) (void)hipHostFree(c->ring_host);
+    if (c->own_compute) (void)hipStreamDestroy(c->own_compute);
+    if (c->own_copy) (void)hipStreamDestroy(c->own_copy);
+  }
+  delete c;
+}
+
+extern "C" const char *sr_ctx_last_error(const sr_ctx *c) {
+  return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+extern "C" sr_status sr_ctx_set_streams(sr_ctx *c, void *compute, void *copy) {
+  if (!c) return SR_EINVAL;
+  if (c->host_only) return c->fail(SR_EDEVICE, "host-only context has no device");
+  c->compute = compute ? (hipStream_t)compute : c->own_compute;
+  c->copy = copy ? (hipStream_t)copy : c->own_copy;
+  return SR_OK;
+}
+
+extern "C" sr_status sr_ctx_memory(const sr_ctx *c, uint64_t *used, uint64_t *budget) {
+  if (!c || !used || !budget) return SR_EINVAL;
+  *used = c->used;
+  *budget = c->budget;
+  return SR_OK;
+}
+
+// ----------------------------------------------------------------- graph
+
+static void release_residency(sr_graph *g) {
+  auto &r = g->res;
+  for (auto p : r.buf) g->ctx->dfree(p);
+  for (auto p : r.partial) g->ctx->dfree(p);
+  for (auto p : r.arrive) g->ctx->dfree(p);
+  r = Residency();
+}
+
+static void release_state(sr_graph *g) {
+  auto &s = g->state;
+  g->ctx->dfree(s.value);
+  g->ctx->dfree(s.contrib);
+  g->ctx->dfree(s.inv_outdeg);
+  g->ctx->dfree(s.status);
+  g->ctx->dfree(s.ctl);
+  s = RunState();
+}
+
+extern "C" sr_status sr_graph_load_csr(sr_ctx *c, int32_t n, int64_t m, const int64_t *ro,
+                                       const int32_t *ci, const uint32_t *w, uint32_t flags,
+                                       sr_graph **out) {
+  if (!c) return SR_EINVAL;
+  if (!out || !ro || (m > 0 && !ci)) return c->fail(SR_EINVAL, "null argument");
+  if (n < 1 || m < 0) return c->fail(SR_EINVAL, "need n >= 1 and m >= 0");
+  if (flags & ~SR_LOAD_SYMMETRIZE) return c->fail(SR_EINVAL, "unknown load flags");
+  if (ro[0] != 0 || ro[n] != m) return c->fail(SR_EINVAL, "row_offsets must start at 0 and end at m");
+  for (int32_t u = 0; u < n; ++u)
+    if (ro[u + 1] < ro[u]) return c->fail(SR_EINVAL, "row_offsets must be non-decreasing");
+  for (int64_t e = 0; e < m; ++e)
+    if (ci[e] < 0 || ci[e] >= n) return c->fail(SR_EINVAL, "col_idx out of range at " + std::to_string(e));
+  if (m > INT32_MAX) return c->fail(SR_EINVAL, "m must be below 2^31");
+  sr_graph *g = new (std::nothrow) sr_graph();
+  if (!g) return c->fail(SR_ENOMEM, "out of host memory");
+  g->ctx = c;
+  g->n = n;
+  g->weighted = w != nullptr;
+  g->symmetric = (flags & SR_LOAD_SYMMETRIZE) != 0;
+  sr_status st;
+  try {
+    st = build_in_csr(g, ro, ci, w, g->symmetric);
+  } catch (const std::bad_alloc &) {
+    st = c->fail(SR_ENOMEM, "out of host memory building in-edges");
+  }
+  if (st != SR_OK) { delete g; return st; }
+  *out = g;
+  return SR_OK;
+}
+
+static uint64_t state_bytes(int32_t n, int algo) {
+  uint64_t b = 4ull * n + 1ull * n + sizeof(Ctl) + 4096;
+  if (algo == A_PR || algo == A_PPR) b += 8ull * n;
+  return b;
+}
+
+// bytes of the page prefix an algorithm needs on the device
+static uint64_t need_bytes(const Page &p, bool weights) {
+  return weights ? p.hdr.bytes_total : p.hdr.bytes_unweighted;
+}
+
+static uint64_t scratch_bytes(const Page &p) {
+  uint64_t c = (uint64_t)std::max<int32_t>(p.hdr.n_chunks, 1);
+  return 2 * (((4 * c) + 255) & ~255ull);
+}
+
+extern "C" sr_status sr_graph_partition(sr_graph *g, int32_t nparts, int32_t nslots) {
+  if (!g) return SR_EINVAL;
+  sr_ctx *c = g->ctx;
+  if (nparts < 0) return c->fail(SR_EINVAL, "num_parts must be >= 0");
+  if (nslots == 0) nslots = 4;
+  if (nslots < 2 || nslots > MAXW + 1) return c->fail(SR_EINVAL, "num_slots must be in [2, 17]");
+  if (g->ctx->host_only == false) { (void)hipSetDevice(c->device); (void)hipDeviceSynchronize(); }
+  release_residency(g);
+  g->nslots = nslots;
+  g->auto_parts = nparts == 0;
+  if (nparts == 0) {
+    // smallest part count whose largest page (with weights) fits one slot
+    // of the budget left after the vertex state of a min program
+    uint64_t total = graph_bytes(g);
+    uint64_t st = state_bytes(g->n, A_SSSP);
+    if (c->budget <= st) return c->fail(SR_EBUDGET, "budget cannot hold the vertex state");
+    uint64_t slot = (c->budget - st) / (uint64_t)nslots;
+    int32_t P = (int32_t)std::max<uint64_t>(1, (total + slot - 1) / std::max<uint64_t>(slot, 1));
+    for (int iter = 0; iter < 64; ++iter) {
+      sr_status s = sr::make_pages(g, P);
+      if (s != SR_OK) return s;
+      uint64_t mx = 0, sum = 0;
+      for (auto &p : g->pages) { mx = std::max(mx, p.bytes + scratch_bytes(p)); sum += p.bytes + scratch_bytes(p); }
+      if (sum + st <= c->budget || mx <= slot || c->host_only) break;
+      P = P + std::max<int32_t>(1, P / 8);
+      if (P > g->n) return c->fail(SR_EBUDGET, "no partition fits the budget");
+    }
+    return SR_OK;
+  }
+  return sr::make_pages(g, nparts);
+}
+
+extern "C" sr_status sr_graph_info_get(const sr_graph *g, sr_graph_info *o) {
+  if (!g || !o) return SR_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->n = g->n;
+  o->m = g->m;
+  o->weighted = g->weighted;
+  o->symmetric = g->symmetric;
+  o->num_parts = (int32_t)g->pages.size();
+  o->num_slots = g->nslots;
+  o->graph_bytes = graph_bytes(g);
+  for (auto &p : g->pages) {
+    o->page_bytes_total += p.bytes;
+    o->max_page_bytes = std::max(o->max_page_bytes, p.bytes);
+  }
+  o->resident = g->res.resident;
+  return SR_OK;
+}
+
+extern "C" sr_status sr_graph_page(const sr_graph *g, int32_t page, sr_page_view *o) {
+  if (!g || !o) return SR_EINVAL;
+  if (page < 0 || page >= (int32_t)g->pages.size()) return g->ctx->fail(SR_EINVAL, "page out of range");
+  const Page &p = g->pages[page];
+  o->v_begin = p.hdr.v_begin;
+  o->v_end = p.hdr.v_begin + p.hdr.n_p;
+  o->num_edges = p.hdr.m_p;
+  o->offsets = (const int32_t *)(p.host + p.hdr.off_offsets);
+  o->src = (const int32_t *)(p.host + p.hdr.off_src);
+  o->weights = g->weighted ? (const uint32_t *)(p.host + p.hdr.off_w) : nullptr;
+  o->bytes = p.bytes;
+  return SR_OK;
+}
+
+extern "C" void sr_graph_destroy(sr_graph *g) {
+  if (!g) return;
+  if (!g->ctx->host_only) {
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipDeviceSynchronize();
+    release_residency(g);
+    release_state(g);
+  }
+  sr::free_pages(g);
+  delete g;
+}
+
+extern "C" sr_status sr_pvu_default_diagram(sr_pvu_diagram *d) {
+  if (!d) return SR_EINVAL;
+  std::memset(d, 0, sizeof(*d));
+  d->num_states = 6;
+  d->initial_state = 0;
+  d->attempt_mask = (1u << 0) | (1u << 1) | (1u << 5);
+  const uint8_t succ[8] = {0, 0, 1, 2, 3, 0, 0, 0};
+  const uint8_t fail[8] = {5, 4, 1, 2, 3, 3, 0, 0};
+  std::memcpy(d->on_success, succ, 8);
+  std::memcpy(d->on_fail, fail, 8);
+  return SR_OK;
+}
+
+// ------------------------------------------------------------------- run
+
+namespace {
+
+struct Launch {
+  SweepArgs a;
+  int algo;
+};
+
+// Algorithmic bytes of one sweep (see DESIGN: per visited vertex the bin
+// entry and the gate read, per attempted vertex its two offsets, per
+// scanned edge the source id, the weight (SSSP) and the gathered value, per
+// changed vertex the value write; PageRank also writes rank and contrib and
+// reads 1/outdeg per attempted vertex).
+uint64_t algo_bytes(int algo, int pvu, const SweepRecord &r) {
+  uint64_t visited = r.attempted + r.skipped;
+  uint64_t eb = (algo == A_SSSP) ? 12 : 8;
+  uint64_t b = r.edges * eb + visited * 8 + r.attempted * 8;
+  if (pvu == P_WEAK) b += visited * 1;
+  if (algo == A_PR || algo == A_PPR) b += r.attempted * 12;
+  else b += r.changed * 4;
+  return b;
+}
+
+// Validate a diagram: states < 8, every transition in range, and from every
+// state some attempting state is reachable via on_fail steps.
+bool valid_diagram(const sr_pvu_diagram &d) {
+  if (d.num_states < 1 || d.num_states > 8 || d.initial_state >= d.num_states) return false;
+  for (int i = 0; i < d.num_states; ++i)
+    if (d.on_success[i] >= d.num_states || d.on_fail[i] >= d.num_states) return false;
+  for (int i = 0; i < d.num_states; ++i) {
+    int s = i;
+    bool ok = false;
+    for (int k = 0; k <= d.num_states; ++k) {
+      if ((d.attempt_mask >> s) & 1) { ok = true; break; }
+      s = d.on_fail[s];
+    }
+    if (!ok) return false;
+  }
+  return true;
+}
+
+struct Runner {
+  sr_graph *g;
+  sr_ctx *c;
+  int algo, pvu;
+  sr_run_params prm;
+  Diagram dia;
+  bool weights;
+  sr_run_stats st{};
+  uint64_t seq_next = 0;  // next expected sweep record
+  // timing events: a free list, and start/end pairs not yet read
+  std::vector<hipEvent_t> ev_all, ev_free;
+  struct Pair { hipEvent_t a, b; bool copy; };
+  std::vector<Pair> pending;
+
+  ~Runner() {
+    for (auto e : ev_all) (void)hipEventDestroy(e);
+  }
+  hipEvent_t ev() {
+    if (!ev_free.empty()) { hipEvent_t e = ev_free.back(); ev_free.pop_back(); return e; }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ev_all.push_back(e);
+    return e;
+  }
+  void track(hipEvent_t a, hipEvent_t b, bool copy) {
+    if (a && b) pending.push_back({a, b, copy});
+    else { if (a) ev_free.push_back(a); if (b) ev_free.push_back(b); }
+  }
+  // read the timings of completed pairs; pairs still in flight stay pending
+  void harvest_events() {
+    std::vector<Pair> keep;
+    for (auto &p : pending) {
+      if (hipEventQuery(p.b) != hipSuccess) { keep.push_back(p); continue; }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) (p.copy ? st.h2d_ms : st.kernel_ms) += ms;
+      ev_free.push_back(p.a);
+      ev_free.push_back(p.b);
+    }
+    pending.swap(keep);
+  }
+
+  // harvest event timings and sweep records up to what the device wrote
+  sr_status harvest(bool *done) {
+    harvest_events();
+    for (;;) {
+      const SweepRecord &r = c->ring_host[seq_next & c->ring_mask];
+      if (r.seq != seq_next) break;
+      if (r.attempted + r.skipped > 0 || r.edges > 0) st.sweeps++;
+      st.edges_scanned += (int64_t)r.edges;
+      st.vertices_attempted += (int64_t)r.attempted;
+      st.vertices_skipped += (int64_t)r.skipped;
+      st.mispredicted += (int64_t)r.mispred;
+      for (int i = 0; i < 8; ++i) st.state_hist[i] += (int64_t)r.hist[i];
+      st.algo_bytes += algo_bytes(algo, pvu, r);
+      if (r.pass_l1_closed >= 0.0) {
+        st.final_l1 = r.pass_l1_closed;
+        if (r.phase == 1) st.verify_passes++;
+      }
+      st.passes = (int32_t)r.pass_after;
+      if (r.done_after) {
+        *done = true;
+        st.stop_reason = (int32_t)r.stop_reason;
+      }
+      seq_next++;
+    }
+    return SR_OK;
+  }
+
+  sr_status launch(const SweepArgs &a) {
+    hipEvent_t e0 = ev(), e1 = ev();
+    if (e0) (void)hipEventRecord(e0, c->compute);
+    hipError_t e = launch_sweep(algo, a, c->compute);
+    if (e != hipSuccess) return c->hip_fail(e, "sweep launch");
+    if (e1) (void)hipEventRecord(e1, c->compute);
+    track(e0, e1, false);
+    return SR_OK;
+  }
+
+  // Fill the per-launch fields for pages [list] resident at bufs.
+  sr_status make_args(const std::vector<int32_t> &pages, const std::vector<int32_t> &slots,
+                      int end_of_pass, SweepArgs &a) {
+    std::memset(&a, 0, sizeof(a));
+    a.nent = (int32_t)pages.size();
+    a.end_of_pass = end_of_pass;
+    a.n = g->n;
+    a.audit = (prm.flags & SR_RUN_AUDIT_PVU) ? 1 : 0;
+    a.pr_seed = algo == A_PPR ? prm.source : -1;
+    a.damping = (float)prm.damping;
+    a.pr_eps = prm.pr_change_eps;
+    a.ctl = g->state.ctl;
+    a.ring = c->ring_dev;
+    a.ring_mask = c->ring_mask;
+    a.value = g->state.value;
+    a.contrib = g->state.contrib;
+    a.inv_outdeg = g->state.inv_outdeg;
+    a.status = g->state.status;
+    a.dia = dia;
+    int32_t blk = 0;
+    a.blk_prefix[0] = 0;
+    const bool pr = algo == A_PR || algo == A_PPR;
+    for (size_t i = 0; i < pages.size(); ++i) {
+      const PageHeader &h = g->pages[pages[i]].hdr;
+      for (int b = 0; b < NBINS; ++b) {
+        int nb = (b == BIN_ZERO && !pr) ? 0 : bin_blocks(h, b);
+        blk += nb;
+        a.blk_prefix[i * NBINS + b + 1] = blk;
+      }
+      a.base[i] = g->res.buf[slots[i]];
+      a.partial[i] = g->res.partial[slots[i]];
+      a.arrive[i] = g->res.arrive[slots[i]];
+    }
+    a.nblocks = std::max<int32_t>(blk, 1);  // an empty window still closes its sweep
+    return SR_OK;
+  }
+
+  sr_status sync_compute() {
+    hipError_t e = hipStreamSynchronize(c->compute);
+    if (e != hipSuccess) return c->hip_fail(e, "compute stream");
+    return SR_OK;
+  }
+};
+
+}  // namespace
+
+static sr_status ensure_state(sr_graph *g, int algo) {
+  sr_ctx *c = g->ctx;
+  auto &s = g->state;
+  const bool pr = algo == A_PR || algo == A_PPR;
+  if (s.n == g->n && s.value && s.ctl && (!pr || s.contrib)) {
+    s.algo = algo;
+    return SR_OK;
+  }
+  release_state(g);
+  sr_status st;
+  if ((st = c->dalloc((void **)&s.value, 4ull * g->n, "vertex values")) != SR_OK) return st;
+  if ((st = c->dalloc((void **)&s.status, 1ull * g->n, "predictor states")) != SR_OK) return st;
+  if ((st = c->dalloc((void **)&s.ctl, sizeof(Ctl), "control block")) != SR_OK) return st;
+  if (pr) {
+    if ((st = c->dalloc((void **)&s.contrib, 4ull * g->n, "pagerank contrib")) != SR_OK) return st;
+    if ((st = c->dalloc((void **)&s.inv_outdeg, 4ull * g->n, "pagerank 1/outdeg")) != SR_OK) return st;
+    std::vector<float> iod(g->n);
+    for (int32_t v = 0; v < g->n; ++v) iod[v] = g->outdeg[v] ? 1.0f / (float)g->outdeg[v] : 0.0f;
+    hipError_t e = hipMemcpy(s.inv_outdeg, iod.data(), 4ull * g->n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return c->hip_fail(e, "copy 1/outdeg");
+  }
+  s.n = g->n;
+  s.algo = algo;
+  return SR_OK;
+}
+
+// Make the pages resident (all of them) or allocate the streaming slots.
+static sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream) {
+  sr_ctx *c = g->ctx;
+  auto &r = g->res;
+  uint64_t all = 0, mx = 0, smx = 0;
+  for (auto &p : g->pages) {
+    all += need_bytes(p, weights) + scratch_bytes(p);
+    mx = std::max(mx, need_bytes(p, weights));
+    smx = std::max(smx, scratch_bytes(p));
+  }
+  const uint64_t freeb = c->budget - c->used + [&] {
+    uint64_t mine = 0;
+    for (auto p : r.buf) { auto it = c->allocs.find(p); if (it != c->allocs.end()) mine += it->second; }
+    for (auto p : r.partial) { auto it = c->allocs.find(p); if (it != c->allocs.end()) mine += it->second; }
+    for (auto p : r.arrive) { auto it = c->allocs.find(p); if (it != c->allocs.end()) mine += it->second; }
+    return mine;
+  }();
+  const bool want_resident = !force_stream && all + 4096 <= freeb;
+  if (want_resident && r.resident && (r.weights || !weights)) return SR_OK;
+  if (!want_resident && !r.resident && r.nslots == g->nslots && r.slot_bytes >= mx &&
+      (r.weights || !weights) && !r.buf.empty())
+    return SR_OK;
+  release_residency(g);
+  sr_status st;
+  if (want_resident) {
+    r.resident = true;
+    r.weights = weights;
+    for (size_t i = 0; i < g->pages.size(); ++i) {
+      auto &p = g->pages[i];
+      void *b = nullptr, *pa = nullptr, *ar = nullptr;
+      uint64_t nb = need_bytes(p, weights);
+      uint64_t sc = (4ull * std::max<int32_t>(p.hdr.n_chunks, 1) + 255) & ~255ull;
+      if ((st = c->dalloc(&b, nb, "resident page")) != SR_OK) { release_residency(g); return st; }
+      r.buf.push_back((char *)b);
+      if ((st = c->dalloc(&pa, sc, "chunk partials")) != SR_OK) { release_residency(g); return st; }
+      r.partial.push_back((uint32_t *)pa);
+      if ((st = c->dalloc(&ar, sc, "chunk arrivals")) != SR_OK) { release_residency(g); return st; }
+      r.arrive.push_back((uint32_t *)ar);
+      hipError_t e = hipMemcpyAsync(b, p.host, nb, hipMemcpyHostToDevice, c->copy);
+      if (e == hipSuccess) e = launch_fill_u32((uint32_t *)ar, 0u, sc / 4, c->copy);
+      if (e != hipSuccess) { release_residency(g); return c->hip_fail(e, "resident page copy"); }
+      r.slot_page.push_back((int32_t)i);
+    }
+    hipError_t e = hipStreamSynchronize(c->copy);
+    if (e != hipSuccess) { release_residency(g); return c->hip_fail(e, "resident page copy"); }
+    return SR_OK;
+  }
+  // streaming: nslots slots of the largest page
+  const int32_t S = g->nslots;
+  if ((uint64_t)S * (mx + smx) + 4096 > freeb)
+    return c->fail(SR_EBUDGET, "budget cannot hold " + std::to_string(S) + " slots of " +
+                                   std::to_string(mx) + " B; partition into more parts");
+  r.resident = false;
+  r.weights = weights;
+  r.nslots = S;
+  r.slot_bytes = mx;
+  for (int32_t s = 0; s < S; ++s) {
+    void *b = nullptr, *pa = nullptr, *ar = nullptr;
+    if ((st = c->dalloc(&b, mx, "page slot")) != SR_OK) { release_residency(g); return st; }
+    r.buf.push_back((char *)b);
+    if ((st = c->dalloc(&pa, smx / 2, "chunk partials")) != SR_OK) { release_residency(g); return st; }
+    r.partial.push_back((uint32_t *)pa);
+    if ((st = c->dalloc(&ar, smx / 2, "chunk arrivals")) != SR_OK) { release_residency(g); return st; }
+    r.arrive.push_back((uint32_t *)ar);
+    hipError_t e = launch_fill_u32((uint32_t *)ar, 0u, smx / 8, c->copy);
+    if (e != hipSuccess) { release_residency(g); return c->hip_fail(e, "slot init"); }
+    r.slot_page.push_back(-1);
+  }
+  hipError_t e = hipStreamSynchronize(c->copy);
+  if (e != hipSuccess) { release_residency(g); return c->hip_fail(e, "slot init"); }
+  return SR_OK;
+}
+
+extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_stats *stats) {
+  if (!g || !params) return g ? g->ctx->fail(SR_EINVAL, "params is NULL") : SR_EINVAL;
+  sr_ctx *c = g->ctx;
+  if (c->host_only) return c->fail(SR_EDEVICE, "host-only context cannot run");
+  const double t0 = now_ms();
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  Runner R;
+  R.g = g;
+  R.c = c;
+  R.prm = *params;
+  sr_run_params &p = R.prm;
+  if (p.algo < SR_BFS || p.algo > SR_PPR) return c->fail(SR_EINVAL, "unknown algorithm");
+  R.algo = (int)p.algo;
+  if (p.damping == 0.0) p.damping = 0.85;
+  if (!(p.damping > 0.0 && p.damping < 1.0)) return c->fail(SR_EINVAL, "damping must be in (0,1)");
+  if (p.tol_l1 == 0.0) p.tol_l1 = 1e-9;
+  if (p.max_passes == 0) p.max_passes = 10000;
+  if (p.max_inner_iters == 0) p.max_inner_iters = 4;
+  if (p.max_passes < 0 || p.max_inner_iters < 0) return c->fail(SR_EINVAL, "negative limits");
+  if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_FORCE_STREAM | SR_RUN_RESUME))
+    return c->fail(SR_EINVAL, "unknown run flags");
+  const bool pr = R.algo == A_PR || R.algo == A_PPR;
+  if (p.pvu == SR_PVU_DEFAULT) p.pvu = (R.algo == A_BFS || R.algo == A_CC) ? SR_PVU_STRONG : SR_PVU_WEAK;
+  if (p.pvu < SR_PVU_OFF || p.pvu > SR_PVU_WEAK) return c->fail(SR_EINVAL, "unknown pvu mode");
+  if (pr && p.pvu == SR_PVU_STRONG) return c->fail(SR_EINVAL, "PageRank has no strong condition (Table I)");
+  R.pvu = (int)p.pvu;
+  if ((R.algo == A_BFS || R.algo == A_SSSP || R.algo == A_PPR) && (p.source < 0 || p.source >= g->n))
+    return c->fail(SR_EINVAL, "source out of range");
+  if (R.algo == A_CC && !g->symmetric)
+    return c->fail(SR_EINVAL, "CC needs the undirected graph: load with SR_LOAD_SYMMETRIZE");
+  if (R.algo == A_SSSP && !g->weighted) return c->fail(SR_EINVAL, "SSSP needs weights");
+  sr_pvu_diagram d;
+  if (p.diagram) d = *p.diagram; else sr_pvu_default_diagram(&d);
+  if (!valid_diagram(d)) return c->fail(SR_EINVAL, "invalid predictor diagram");
+  std::memset(&R.dia, 0, sizeof(R.dia));
+  R.dia.num_states = d.num_states;
+  R.dia.initial = d.initial_state;
+  R.dia.attempt_mask = d.attempt_mask;
+  std::memcpy(R.dia.succ, d.on_success, 8);
+  std::memcpy(R.dia.fail, d.on_fail, 8);
+  R.weights = R.algo == A_SSSP;
+  const bool resume = (p.flags & SR_RUN_RESUME) != 0;
+  if (resume && (!g->state.valid || g->state.algo != R.algo))
+    return c->fail(SR_ESTATE, "nothing to resume for this algorithm");
+
+  sr_status s;
+  if (g->pages.empty())
+    if ((s = sr_graph_partition(g, 0, 0)) != SR_OK) return s;
+  if ((s = ensure_state(g, R.algo)) != SR_OK) return s;
+  s = ensure_residency(g, R.weights, (p.flags & SR_RUN_FORCE_STREAM) != 0);
+  if (s == SR_EBUDGET && g->auto_parts) {
+    // pages sized for a min program do not fit next to this state: recut
+    uint64_t st_b = state_bytes(g->n, R.algo);
+    if (c->budget > st_b + c->used) {
+      for (int32_t P = (int32_t)g->pages.size() * 2; P <= g->n && s == SR_EBUDGET; P *= 2) {
+        release_residency(g);
+        if ((s = sr::make_pages(g, P)) != SR_OK) return s;
+        s = ensure_residency(g, R.weights, (p.flags & SR_RUN_FORCE_STREAM) != 0);
+      }
+    }
+  }
+  if (s != SR_OK) return s;
+
+  // initial values, predictor states and control block
+  RunState &rs = g->state;
+  Ctl init;
+  std::memset(&init, 0, sizeof(init));
+  init.threshold = 0;  // value 0 is final for every min program (source, global minimum label)
+  init.phase = 0;
+  init.sw_min_changed = INF;
+  init.pass_min_changed = INF;
+  init.best_l1 = 1e300;
+  init.algo = R.algo;
+  init.pvu = R.pvu;
+  init.max_passes = p.max_passes;
+  init.tol_l1 = p.tol_l1;
+  init.floor_cap = 1e-6;
+  // a PageRank pass of single plain sweeps is already a verification pass
+  init.always_verify = 0;
+  if (pr && R.pvu == P_OFF && (p.max_inner_iters == 1 || g->res.resident)) init.phase = 1;
+  if (pr) {
+    double D = 0.0;
+    if (R.algo == A_PR) {
+      int64_t nd = 0;
+      for (int32_t v = 0; v < g->n; ++v) nd += g->outdeg[v] == 0;
+      D = (double)(float)(1.0f / (float)g->n) * (double)nd;
+    } else {
+      D = g->outdeg[p.source] == 0 ? 1.0 : 0.0;
+    }
+    init.dangling = D;
+  }
+  hipError_t e = hipSuccess;
+  if (!resume) {
+    if (pr) e = launch_init_pr((float *)rs.value, rs.contrib, rs.inv_outdeg, g->n,
+                               R.algo == A_PPR ? p.source : -1, c->compute);
+    else e = launch_init_min(R.algo, rs.value, g->n, p.source, c->compute);
+    if (e == hipSuccess) e = launch_fill_u8(rs.status, (uint8_t)d.initial_state, (size_t)g->n, c->compute);
+  }
+  if (resume) {
+    // keep values and predictor states; restart the pass bookkeeping
+    init.phase = init.phase;  // thresholds restart from the safe initial value
+  }
+  if (e == hipSuccess) e = launch_init_ctl(rs.ctl, init, c->compute);
+  if (e != hipSuccess) return c->hip_fail(e, "init");
+  // fresh record numbering for this run
+  for (uint32_t i = 0; i < RING; ++i) c->ring_host[i].seq = ~0ull;
+  R.seq_next = 0;
+  rs.valid = true;
+
+  bool done = false;
+  if (g->res.resident) {
+    // Every sweep covers every page and closes a pass; the control block
+    // carries thresholds and phases between sweeps, so sweeps are enqueued
+    // in batches with one host check per batch.
+    std::vector<std::vector<int32_t>> groups;
+    for (int32_t i = 0; i < (int32_t)g->pages.size(); i += MAXW) {
+      std::vector<int32_t> grp;
+      for (int32_t j = i; j < std::min<int32_t>(i + MAXW, (int32_t)g->pages.size()); ++j) grp.push_back(j);
+      groups.push_back(grp);
+    }
+    std::vector<SweepArgs> args(groups.size());
+    for (size_t k = 0; k < groups.size(); ++k)
+      R.make_args(groups[k], groups[k], k + 1 == groups.size() ? 1 : 0, args[k]);
+    const int batch = 4;
+    int32_t launched = 0;
+    while (!done) {
+      for (int b = 0; b < batch; ++b) {
+        for (auto &a : args)
+          if ((s = R.launch(a)) != SR_OK) return s;
+        launched++;
+      }
+      if ((s = R.sync_compute()) != SR_OK) return s;
+      R.harvest(&done);
+      if (launched > p.max_passes + 8) break;
+    }
+  } else {
+    // Pipelined subgraph iteration (Section 3.2): a window of W = S-1 slots is
+    // swept while the next page is copied into the remaining slot; each window
+    // is swept until the copy lands (re-entry), max_inner_iters, or a sweep
+    // without change; then the window slides by one page.
+    const int32_t P = (int32_t)g->pages.size();
+    const int32_t S = g->res.nslots;
+    const int32_t W = S - 1;
+    std::vector<hipEvent_t> copy_done(S, nullptr);
+    hipEvent_t step_done = nullptr;
+    std::vector<hipEvent_t> own;
+    auto mk = [&]() { hipEvent_t ev; if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return (hipEvent_t) nullptr; own.push_back(ev); return ev; };
+    for (int32_t i = 0; i < S; ++i) copy_done[i] = mk();
+    step_done = mk();
+    struct Cleanup { std::vector<hipEvent_t> *v; ~Cleanup() { for (auto e : *v) (void)hipEventDestroy(e); } } cl{&own};
+    for (auto ev : own) if (!ev) return c->fail(SR_EDEVICE, "event creation failed");
+    auto copy_page = [&](int32_t page, hipEvent_t wait) -> sr_status {
+      int32_t slot = page % S;
+      if (wait) HIP_TRY(c, hipStreamWaitEvent(c->copy, wait, 0), "copy wait");
+      hipEvent_t a = R.ev(), b = R.ev();
+      uint64_t nb = need_bytes(g->pages[page], R.weights);
+      if (a) (void)hipEventRecord(a, c->copy);
+      HIP_TRY(c, hipMemcpyAsync(g->res.buf[slot], g->pages[page].host, nb, hipMemcpyHostToDevice, c->copy),
+              "page copy");
+      if (b) (void)hipEventRecord(b, c->copy);
+      R.track(a, b, true);
+      HIP_TRY(c, hipEventRecord(copy_done[slot], c->copy), "copy event");
+      g->res.slot_page[slot] = page;
+      R.st.h2d_bytes += nb;
+      return SR_OK;
+    };
+    int32_t pass = 0;
+    while (!done) {
+      // pass start: the whole device is idle (host synced at the last pass end)
+      if ((s = copy_page(0, nullptr)) != SR_OK) return s;
+      for (int32_t j = 0; j < P && !done; ++j) {
+        HIP_TRY(c, hipStreamWaitEvent(c->compute, copy_done[j % S], 0), "compute wait");
+        bool copying = false;
+        if (j + 1 < P) {
+          // slot of page j+1-S was last used by step j-1 (already enqueued)
+          if ((s = copy_page(j + 1, j > 0 ? step_done : nullptr)) != SR_OK) return s;
+          copying = true;
+        }
+        std::vector<int32_t> wp, ws;
+        for (int32_t q = std::max(0, j - W + 1); q <= j; ++q) { wp.push_back(q); ws.push_back(q % S); }
+        SweepArgs a;
+        R.make_args(wp, ws, 0, a);
+        for (int32_t it = 0; it < p.max_inner_iters; ++it) {
+          if ((s = R.launch(a)) != SR_OK) return s;
+          if ((s = R.sync_compute()) != SR_OK) return s;
+          const uint64_t before = R.seq_next;
+          R.harvest(&done);
+          if (done) break;
+          bool changed = false;
+          for (uint64_t q = before; q < R.seq_next; ++q) changed |= c->ring_host[q & c->ring_mask].changed > 0;
+          if (!changed) break;                      // the window reached its local fixed point
+          if (copying && hipEventQuery(copy_done[(j + 1) % S]) == hipSuccess) break;  // slide
+        }
+        HIP_TRY(c, hipEventRecord(step_done, c->compute), "step event");
+      }
+      if (done) break;
+      HIP_TRY(c, launch_end_pass(g->state.ctl, c->ring_dev, c->ring_mask, c->compute), "end pass");
+      if ((s = R.sync_compute()) != SR_OK) return s;
+      R.harvest(&done);
+      pass++;
+      if (pass > p.max_passes + 2) break;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->copy), "copy stream");
+    R.harvest_events();
+  }
+  R.st.converged = R.st.stop_reason == SR_STOP_CONVERGED || R.st.stop_reason == SR_STOP_FP32_FLOOR;
+  R.st.wall_ms = now_ms() - t0;
+  if (stats) *stats = R.st;
+  if (R.st.stop_reason == SR_STOP_MAX_PASSES || !done)
+    return c->fail(SR_ENOTCONV, "max_passes reached before convergence");
+  return SR_OK;
+}
+
+extern "C" sr_status sr_read_values(const sr_graph *g, void *dst, uint64_t bytes) {
+  if (!g || !dst) return g ? g->ctx->fail(SR_EINVAL, "dst is NULL") : SR_EINVAL;
+  sr_ctx *c = g->ctx;
+  if (c->host_only) return c->fail(SR_EDEVICE, "host-only context has no values");
+  if (!g->state.valid) return c->fail(SR_ESTATE, "no run has produced values");
+  if (bytes < 4ull * g->n) return c->fail(SR_EINVAL, "dst_bytes < 4n");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  HIP_TRY(c, hipMemcpyAsync(dst, g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute), "read values");
+  HIP_TRY(c, hipStreamSynchronize(c->compute), "read values");
+  return SR_OK;
+}

@@ -1,0 +1,106 @@
+// engine.hpp -- host-side objects behind the C ABI handles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/seraph.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace sr {
+
+// Pinned host page buffer (Section 3.1 CSC page) plus a copy of its header.
+struct Page {
+  char *host = nullptr;     // pinned (device context) or aligned malloc (host-only)
+  uint64_t bytes = 0;
+  PageHeader hdr{};
+};
+
+// Per-run device state; kept after a run so values can be read back and a
+// later run can resume from them.
+struct RunState {
+  int algo = -1;
+  int32_t n = 0;
+  uint32_t *value = nullptr;
+  float *contrib = nullptr;
+  float *inv_outdeg = nullptr;
+  uint8_t *status = nullptr;
+  Ctl *ctl = nullptr;
+  bool valid = false;
+};
+
+// Device residency of the pages: either all pages resident, or num_slots
+// slot buffers the pages stream through.
+struct Residency {
+  bool resident = false;
+  bool weights = false;            // page prefix with weights copied
+  int32_t nslots = 0;
+  uint64_t slot_bytes = 0;
+  std::vector<char *> buf;         // resident: one per page; streaming: one per slot
+  std::vector<uint32_t *> partial; // heavy-vertex scratch, same indexing as buf
+  std::vector<uint32_t *> arrive;
+  std::vector<int32_t> slot_page;  // streaming: page currently in slot (-1 none)
+  uint32_t max_chunks = 0;
+};
+
+}  // namespace sr
+
+struct sr_ctx {
+  int device = -1;
+  bool host_only = true;
+  uint64_t budget = 0;
+  uint64_t used = 0;
+  mutable std::string err;
+  hipStream_t own_compute = nullptr, own_copy = nullptr;
+  hipStream_t compute = nullptr, copy = nullptr;
+  std::unordered_map<void *, uint64_t> allocs;
+  // host-mapped per-sweep record ring
+  sr::SweepRecord *ring_host = nullptr;
+  sr::SweepRecord *ring_dev = nullptr;
+  uint32_t ring_mask = 0;
+  std::mutex mu;
+
+  sr_status fail(sr_status st, const std::string &msg) const {
+    err = msg;
+    return st;
+  }
+  sr_status hip_fail(hipError_t e, const char *what) const {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return SR_EDEVICE;
+  }
+  // budgeted device allocation
+  sr_status dalloc(void **p, uint64_t bytes, const char *what);
+  void dfree(void *p);
+};
+
+struct sr_graph {
+  sr_ctx *ctx = nullptr;
+  int32_t n = 0;
+  int64_t m = 0;
+  bool weighted = false, symmetric = false;
+  std::vector<int64_t> in_off;
+  std::vector<int32_t> in_src;
+  std::vector<uint32_t> in_w;
+  std::vector<int32_t> outdeg;
+  int32_t nparts = 0, nslots = 0;
+  bool auto_parts = false;
+  std::vector<sr::Page> pages;
+  sr::Residency res;
+  sr::RunState state;
+};
+
+namespace sr {
+// graph_host.cpp
+sr_status build_in_csr(sr_graph *g, const int64_t *row_offsets, const int32_t *col_idx,
+                       const uint32_t *weights, bool symmetrize);
+sr_status make_pages(sr_graph *g, int32_t nparts);
+void free_pages(sr_graph *g);
+uint64_t graph_bytes(const sr_graph *g);
+int host_threads();
+}  // namespace sr

@@ -1,0 +1,283 @@
+// graph_host.cpp -- host preparation of the streamed graph (Section 3.1):
+// the in-edge CSR ("CSC") of the input, cut into pages of consecutive
+// destination vertices with their incoming edges and no destination array.
+// Each page also carries its degree-bin lists so the GPU can load-balance a
+// page without any device-side preprocessing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "engine.hpp"
+
+namespace sr {
+
+int host_threads() {
+  unsigned t = std::thread::hardware_concurrency();
+  if (const char *e = getenv("SR_HOST_THREADS")) t = (unsigned)atoi(e);
+  if (t < 1) t = 1;
+  if (t > 32) t = 32;
+  return (int)t;
+}
+
+template <class F>
+static void parallel_for(int64_t n, int T, F f, int64_t min_n = 4096) {
+  if (T <= 1 || n < min_n) { f(0, 0, n); return; }
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t) {
+    int64_t lo = n * t / T, hi = n * (t + 1) / T;
+    th.emplace_back([=, &f] { f(t, lo, hi); });
+  }
+  for (auto &x : th) x.join();
+}
+
+uint64_t graph_bytes(const sr_graph *g) {
+  return 4ull * ((uint64_t)g->n + 1) + 4ull * (uint64_t)g->m * (g->weighted ? 2 : 1);
+}
+
+// Transpose (and optionally symmetrize) the out-edge CSR into in-edges.
+// Counting sort by destination with per-thread cursors over contiguous
+// source ranges, so every in-row lists its sources in increasing order and
+// the result does not depend on the thread count.
+sr_status build_in_csr(sr_graph *g, const int64_t *ro, const int32_t *ci, const uint32_t *wi,
+                       bool symmetrize) {
+  const int32_t n = g->n;
+  const int64_t m_in = ro[n];
+  const int T = host_threads();
+  g->outdeg.resize(n);
+  for (int32_t u = 0; u < n; ++u) g->outdeg[u] = (int32_t)(ro[u + 1] - ro[u]);
+
+  // arcs to place: u->v for every input arc, plus v->u when symmetrizing
+  std::vector<std::vector<int32_t>> cnt(T, std::vector<int32_t>());
+  for (auto &c : cnt) c.assign((size_t)n, 0);
+  parallel_for(n, T, [&](int t, int64_t lo, int64_t hi) {
+    auto &c = cnt[t];
+    for (int64_t u = lo; u < hi; ++u)
+      for (int64_t e = ro[u]; e < ro[u + 1]; ++e) {
+        c[ci[e]]++;
+        if (symmetrize) c[u]++;
+      }
+  });
+  std::vector<int64_t> start((size_t)n + 1, 0);
+  {
+    std::vector<int64_t> tot((size_t)n, 0);
+    parallel_for(n, T, [&](int, int64_t lo, int64_t hi) {
+      for (int64_t v = lo; v < hi; ++v) {
+        int64_t s = 0;
+        for (int t = 0; t < T; ++t) s += cnt[t][v];
+        tot[v] = s;
+      }
+    });
+    for (int32_t v = 0; v < n; ++v) start[v + 1] = start[v] + tot[v];
+    parallel_for(n, T, [&](int, int64_t lo, int64_t hi) {
+      for (int64_t v = lo; v < hi; ++v) {
+        int64_t cur = 0;
+        for (int t = 0; t < T; ++t) { int32_t c0 = cnt[t][v]; cnt[t][v] = (int32_t)cur; cur += c0; }
+      }
+    });
+  }
+  const int64_t arcs = start[n];
+  if (arcs > INT32_MAX) return g->ctx->fail(SR_EINVAL, "more than 2^31-1 in-edges: int32 page offsets overflow");
+  std::vector<int32_t> src((size_t)arcs);
+  std::vector<uint32_t> w(wi ? (size_t)arcs : 0);
+  parallel_for(n, T, [&](int t, int64_t lo, int64_t hi) {
+    auto &c = cnt[t];
+    for (int64_t u = lo; u < hi; ++u)
+      for (int64_t e = ro[u]; e < ro[u + 1]; ++e) {
+        int32_t v = ci[e];
+        int64_t pos = start[v] + c[v]++;
+        src[pos] = (int32_t)u;
+        if (wi) w[pos] = wi[e];
+        if (symmetrize) {
+          int64_t p2 = start[u] + c[u]++;
+          src[p2] = v;
+          if (wi) w[p2] = wi[e];
+        }
+      }
+  });
+  cnt.clear();
+  cnt.shrink_to_fit();
+  if (!symmetrize) {
+    // rows already list sources in increasing order (sources visited in order)
+    g->in_off = std::move(start);
+    g->in_src = std::move(src);
+    g->in_w = std::move(w);
+    g->m = m_in;
+    return SR_OK;
+  }
+  // Symmetrized rows interleave both directions: sort each row by source and
+  // drop repeated sources, keeping the smallest weight.
+  std::vector<int64_t> keep((size_t)n + 1, 0);
+  parallel_for(n, T, [&](int, int64_t lo, int64_t hi) {
+    std::vector<uint64_t> tmp;
+    for (int64_t v = lo; v < hi; ++v) {
+      int64_t a = start[v], b = start[v + 1];
+      tmp.resize((size_t)(b - a));
+      for (int64_t i = a; i < b; ++i)
+        tmp[i - a] = ((uint64_t)(uint32_t)src[i] << 32) | (wi ? w[i] : 0u);
+      std::sort(tmp.begin(), tmp.end());
+      int64_t k = 0;
+      for (size_t i = 0; i < tmp.size(); ++i) {
+        if (k > 0 && (tmp[i] >> 32) == (uint64_t)(uint32_t)src[a + k - 1]) continue;
+        src[a + k] = (int32_t)(tmp[i] >> 32);
+        if (wi) w[a + k] = (uint32_t)tmp[i];
+        ++k;
+      }
+      keep[v] = k;
+    }
+  });
+  g->in_off.assign((size_t)n + 1, 0);
+  for (int32_t v = 0; v < n; ++v) g->in_off[v + 1] = g->in_off[v] + keep[v];
+  const int64_t m2 = g->in_off[n];
+  g->in_src.resize((size_t)m2);
+  if (wi) g->in_w.resize((size_t)m2);
+  parallel_for(n, T, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t v = lo; v < hi; ++v) {
+      std::memcpy(&g->in_src[g->in_off[v]], &src[start[v]], sizeof(int32_t) * (size_t)keep[v]);
+      if (wi) std::memcpy(&g->in_w[g->in_off[v]], &w[start[v]], sizeof(uint32_t) * (size_t)keep[v]);
+    }
+  });
+  g->m = m2;
+  return SR_OK;
+}
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+static char *alloc_page_buffer(sr_ctx *ctx, uint64_t bytes) {
+  if (ctx->host_only) return (char *)std::aligned_alloc(256, align256(bytes));
+  void *p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+  return (char *)p;
+}
+
+static void free_page_buffer(sr_ctx *ctx, char *p) {
+  if (!p) return;
+  if (ctx->host_only) std::free(p);
+  else (void)hipHostFree(p);
+}
+
+void free_pages(sr_graph *g) {
+  for (auto &p : g->pages) free_page_buffer(g->ctx, p.host);
+  g->pages.clear();
+}
+
+// Fill one page buffer for destination range [vb, ve).
+static void fill_page(const sr_graph *g, int32_t vb, int32_t ve, Page &pg) {
+  PageHeader &h = pg.hdr;
+  const int64_t eb = g->in_off[vb];
+  const int32_t np = ve - vb;
+  const int64_t mp = g->in_off[ve] - eb;
+  char *buf = pg.host;
+  std::memcpy(buf, &h, sizeof(PageHeader));
+  int32_t *off = (int32_t *)(buf + h.off_offsets);
+  for (int32_t i = 0; i <= np; ++i) off[i] = (int32_t)(g->in_off[vb + i] - eb);
+  int32_t *bins = (int32_t *)(buf + h.off_bins);
+  int32_t cur[NBINS];
+  for (int b = 0; b < NBINS; ++b) cur[b] = h.bin_start[b];
+  Chunk *ch = (Chunk *)(buf + h.off_chunks);
+  int32_t nch = 0;
+  for (int32_t i = 0; i < np; ++i) {
+    int64_t d = g->in_off[vb + i + 1] - g->in_off[vb + i];
+    if (d == 0) { bins[cur[BIN_ZERO]++] = i; continue; }
+    if (d > HEAVY) {
+      int32_t count = (int32_t)((d + CHUNK - 1) / CHUNK);
+      int32_t first = nch;
+      for (int32_t c = 0; c < count; ++c) {
+        Chunk k;
+        k.vl = i;
+        k.e_begin = off[i] + c * CHUNK;
+        k.e_end = (int32_t)std::min<int64_t>(off[i] + (int64_t)(c + 1) * CHUNK, off[i + 1]);
+        k.first_count = (int32_t)((uint32_t)first | ((uint32_t)count << 20));
+        ch[nch++] = k;
+      }
+      continue;
+    }
+    int b = d >= 64 ? BIN_WAVE : 31 - __builtin_clz((uint32_t)d);
+    bins[cur[b]++] = i;
+  }
+  std::memcpy(buf + h.off_src, &g->in_src[eb], sizeof(int32_t) * (size_t)mp);
+  if (g->weighted) std::memcpy(buf + h.off_w, &g->in_w[eb], sizeof(uint32_t) * (size_t)mp);
+}
+
+// Header (sizes, bin counts, section offsets) of the page [vb, ve).
+static PageHeader page_header(const sr_graph *g, int32_t vb, int32_t ve) {
+  PageHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.magic = PAGE_MAGIC;
+  h.v_begin = vb;
+  h.n_p = ve - vb;
+  h.m_p = g->in_off[ve] - g->in_off[vb];
+  int32_t chunks = 0, heavy = 0, maxd = 0;
+  for (int32_t v = vb; v < ve; ++v) {
+    int64_t d = g->in_off[v + 1] - g->in_off[v];
+    maxd = std::max<int32_t>(maxd, (int32_t)d);
+    if (d == 0) { h.bin_count[BIN_ZERO]++; continue; }
+    if (d > HEAVY) { heavy++; chunks += (int32_t)((d + CHUNK - 1) / CHUNK); continue; }
+    int b = d >= 64 ? BIN_WAVE : 31 - __builtin_clz((uint32_t)d);
+    h.bin_count[b]++;
+  }
+  h.bin_count[BIN_CHUNK] = chunks;
+  h.n_chunks = chunks;
+  h.n_heavy = heavy;
+  h.max_indeg = maxd;
+  int32_t s = 0;
+  for (int b = 0; b < NBINS; ++b) {
+    if (b == BIN_CHUNK) continue;
+    h.bin_start[b] = s;
+    s += h.bin_count[b];
+  }
+  uint64_t o = sizeof(PageHeader);
+  h.off_offsets = o; o = align256(o + 4ull * ((uint64_t)h.n_p + 1));
+  h.off_bins = o;    o = align256(o + 4ull * (uint64_t)s);
+  h.off_chunks = o;  o = align256(o + sizeof(Chunk) * (uint64_t)chunks);
+  h.off_src = o;     o = align256(o + 4ull * (uint64_t)h.m_p);
+  h.bytes_unweighted = o;
+  h.off_w = o;
+  if (g->weighted) o = align256(o + 4ull * (uint64_t)h.m_p);
+  h.bytes_total = o;
+  return h;
+}
+
+// Equal-edge split into nparts contiguous destination ranges: boundary i is
+// the first vertex whose in-edges start at or after ceil(i * m / nparts).
+// Empty ranges (a vertex heavier than m / nparts) are dropped.
+sr_status make_pages(sr_graph *g, int32_t nparts) {
+  if (nparts < 1) return g->ctx->fail(SR_EINVAL, "num_parts must be >= 1");
+  if (nparts > g->n) nparts = g->n;
+  std::vector<int32_t> bounds;
+  bounds.push_back(0);
+  for (int32_t i = 1; i < nparts; ++i) {
+    int64_t target = (g->m * (int64_t)i + nparts - 1) / nparts;
+    int32_t b = (int32_t)(std::lower_bound(g->in_off.begin(), g->in_off.end(), target) - g->in_off.begin());
+    b = std::min(b, g->n);
+    if (b > bounds.back() && b < g->n) bounds.push_back(b);
+  }
+  bounds.push_back(g->n);
+  free_pages(g);
+  const int32_t P = (int32_t)bounds.size() - 1;
+  g->pages.resize(P);
+  for (int32_t p = 0; p < P; ++p) {
+    g->pages[p].hdr = page_header(g, bounds[p], bounds[p + 1]);
+    if ((uint32_t)g->pages[p].hdr.n_chunks >= (1u << 20))
+      return g->ctx->fail(SR_EINVAL, "page has too many heavy-vertex chunks; use more parts");
+    if (g->pages[p].hdr.max_indeg > CHUNK * 4095)
+      return g->ctx->fail(SR_EINVAL, "in-degree above 8.3M is not supported");
+    g->pages[p].bytes = g->pages[p].hdr.bytes_total;
+    g->pages[p].host = alloc_page_buffer(g->ctx, g->pages[p].bytes);
+    if (!g->pages[p].host) {
+      free_pages(g);
+      return g->ctx->fail(SR_ENOMEM, "page buffer allocation failed");
+    }
+  }
+  const int T = std::min<int>(host_threads(), P);
+  parallel_for(P, T > 0 ? T : 1, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t p = lo; p < hi; ++p) fill_page(g, bounds[p], bounds[p + 1], g->pages[p]);
+  }, 2);
+  g->nparts = P;
+  return SR_OK;
+}
+
+}  // namespace sr

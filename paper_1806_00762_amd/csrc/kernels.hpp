@@ -1,0 +1,52 @@
+// kernels.hpp -- launch interface of the gfx950 sweep kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace sr {
+
+constexpr int MAXW = 16;  // pages per sweep launch
+
+// Arguments of one window sweep (Section 3.2: the resident pages of the
+// window are swept together as one "super subgraph").
+struct SweepArgs {
+  int32_t nent;            // pages in this launch
+  int32_t end_of_pass;     // the last block of this launch closes the pass
+  int32_t n;               // vertices of the graph
+  int32_t audit;           // evaluate skipped vertices too, count would-be changes
+  int32_t pr_seed;         // personalized PageRank seed, -1 = uniform teleport
+  int32_t nblocks;         // grid size (for the last-block detection)
+  float damping;
+  float pr_eps;
+  Ctl *ctl;                // device control block
+  SweepRecord *ring;       // host-mapped per-sweep records
+  uint32_t ring_mask;
+  uint32_t *value;         // BFS level / SSSP distance / CC label (u32), or PageRank rank (f32 bits)
+  float *contrib;          // PageRank: rank / outdeg, gathered by the pull
+  const float *inv_outdeg; // PageRank: 1 / outdeg (0 for dangling vertices)
+  uint8_t *status;         // weak predictor state per vertex
+  Diagram dia;
+  int32_t blk_prefix[MAXW * NBINS + 1];  // cumulative blocks over (page, bin)
+  const char *base[MAXW];                // page buffers on the device
+  uint32_t *partial[MAXW];               // heavy-vertex chunk partials, per page
+  uint32_t *arrive[MAXW];                // heavy-vertex arrival counters, per page
+};
+
+// Blocks a page needs for bin b.
+inline int bin_blocks(const PageHeader &h, int b) {
+  int cnt = h.bin_count[b];
+  int per = bin_items_per_block(b);
+  return (cnt + per - 1) / per;
+}
+
+hipError_t launch_sweep(int algo, const SweepArgs &a, hipStream_t s);
+hipError_t launch_end_pass(Ctl *ctl, SweepRecord *ring, uint32_t ring_mask, hipStream_t s);
+hipError_t launch_init_min(int algo, uint32_t *value, int32_t n, int32_t source, hipStream_t s);
+hipError_t launch_init_pr(float *rank, float *contrib, const float *inv_outdeg, int32_t n,
+                          int32_t seed, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t count, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
+hipError_t launch_init_ctl(Ctl *ctl, const Ctl &init, hipStream_t s);
+
+}  // namespace sr

@@ -1,0 +1,118 @@
+"""The C ABI library loads, exports every symbol include/seraph.h declares,
+and its host-side graph logic (in-edge CSR, equal-edge pages, argument
+checks) works without a GPU through a host-only context."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import graphgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sr():
+    import paper_1806_00762_amd as sr
+    if not os.path.exists(sr.LIB_PATH):
+        from paper_1806_00762_amd import _build
+        _build.build()
+    sr.lib()
+    return sr
+
+
+def declared_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(sr_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_exports_every_declared_symbol(sr):
+    out = subprocess.run(["nm", "-D", "--defined-only", sr.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (sr_[a-z0-9_]+)", out))
+    declared = declared_functions()
+    assert declared, "no declarations found"
+    missing = declared - exported
+    assert not missing, f"declared but not exported: {sorted(missing)}"
+    # the binding knows every declared function
+    assert declared <= set(sr.exported_symbols())
+
+
+def test_host_only_context_refuses_device_work(sr):
+    c = sr.Context(-1, 1 << 30)
+    g = c.load(graphgen.rmat(8, 4, seed=1, weights=(1, 9, 2)))
+    with pytest.raises(sr.SeraphError) as e:
+        g.run("sssp")
+    assert e.value.status == sr.SR_EDEVICE
+    g.close(); c.close()
+
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_in_csr_and_pages(sr, sym):
+    c = sr.Context(-1, 1 << 30)
+    src = graphgen.rmat(11, 8, seed=5, weights=(1, 255, 3))
+    G = c.load(src, symmetrize=sym)
+    A = sp.csr_matrix((src.weights.astype(np.int64), src.col, src.offsets), shape=(src.n, src.n))
+    if sym:
+        A = A.maximum(A.T) if False else A
+        # min weight over both directions, union of arcs
+        B = A.T.tocsr()
+        Ad = A.toarray(); Bd = B.toarray()
+        both = (Ad > 0) & (Bd > 0)
+        M = np.where(both, np.minimum(Ad, Bd), Ad + Bd)
+        np.fill_diagonal(M, 0)
+        IN = sp.csr_matrix(M.T)
+    else:
+        IN = A.T.tocsr()
+    IN.sort_indices()
+    for parts in (1, 3, 7):
+        G.partition(parts, 4)
+        info = G.info()
+        assert info["m"] == IN.nnz
+        offs, srcs, ws, vb = [0], [], [], 0
+        for p in range(info["num_parts"]):
+            pg = G.page(p)
+            assert pg["v_begin"] == vb
+            vb = pg["v_end"]
+            offs.extend((pg["offsets"][1:] + offs[-1]).tolist())
+            srcs.append(pg["src"]); ws.append(pg["weights"])
+            # equal-edge split: a page exceeds m/parts by at most one in-degree
+            maxdeg = int(np.diff(IN.indptr).max())
+            assert pg["offsets"][-1] <= -(-IN.nnz // parts) + maxdeg
+        assert vb == src.n
+        assert np.array_equal(np.array(offs), IN.indptr)
+        assert np.array_equal(np.concatenate(srcs), IN.indices)
+        assert np.array_equal(np.concatenate(ws), IN.data.astype(np.uint32))
+    G.close(); c.close()
+
+
+def test_argument_checks(sr):
+    c = sr.Context(-1, 1 << 30)
+    bad = graphgen.Graph(3, np.array([0, 1, 2, 2]), np.array([1, 5], dtype=np.int32), None)
+    with pytest.raises(sr.SeraphError) as e:
+        c.load(bad)
+    assert e.value.status == sr.SR_EINVAL
+    bad = graphgen.Graph(3, np.array([0, 2, 1, 2]), np.array([1, 2], dtype=np.int32), None)
+    with pytest.raises(sr.SeraphError):
+        c.load(bad)
+    g = c.load(graphgen.rmat(6, 4, seed=1))
+    with pytest.raises(sr.SeraphError):
+        g.partition(-1, 4)
+    with pytest.raises(sr.SeraphError):
+        g.partition(2, 1)
+    g.close(); c.close()
+
+
+def test_default_diagram_matches_reading(sr):
+    import oracle
+    d = sr.default_diagram()
+    ns, init, mask, succ, fail = oracle.weak_default_diagram()
+    assert d.num_states == ns and d.initial_state == init and d.attempt_mask == mask
+    assert list(d.on_success) == succ and list(d.on_fail) == fail

@@ -1,0 +1,177 @@
+"""GPU parity through the C ABI: every vertex program x predictor mode x
+schedule against the CPU oracle. Integer programs must be bit-exact;
+PageRank / personalized PageRank within 1e-6 max-abs of the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+PR_TOL = 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sr():
+    import paper_1806_00762_amd as sr
+    sr.lib()
+    return sr
+
+
+@pytest.fixture(scope="module")
+def ctx(sr):
+    c = sr.Context(0, 0)
+    yield c
+    c.close()
+
+
+GRAPHS = {
+    "rmat10w": lambda: graphgen.rmat(10, 8, seed=3, weights=(1, 255, 4)),
+    "rmat14w": lambda: graphgen.rmat(14, 16, seed=14, weights=(1, 255, 5)),
+    "rmat16w": lambda: graphgen.rmat(16, 16, seed=16, weights=(1, 255, 6)),
+    "uniform12w": lambda: graphgen.uniform(12, 1 << 15, seed=9, weights=(1, 255, 7)),
+}
+_cache = {}
+
+
+def graph(name):
+    if name not in _cache:
+        _cache[name] = GRAPHS[name]()
+    return _cache[name]
+
+
+SCHEDULES = {
+    "resident": dict(parts=1, slots=4, force=False, inner=4),
+    "res4": dict(parts=4, slots=4, force=False, inner=1),
+    "s2p4i4": dict(parts=4, slots=2, force=True, inner=4),
+    "s4p7i1": dict(parts=7, slots=4, force=True, inner=1),
+    "s3p3i4": dict(parts=3, slots=3, force=True, inner=4),
+}
+
+
+def run_case(sr, ctx, g, algo, pvu, sched, source=0, symmetrize=False, audit=False):
+    s = SCHEDULES[sched]
+    G = ctx.load(g, symmetrize=symmetrize)
+    try:
+        G.partition(s["parts"], s["slots"])
+        st = G.run(algo, source=source, pvu=pvu, max_inner_iters=s["inner"], force_stream=s["force"],
+                   audit=audit, max_passes=5000)
+        vals = G.values()
+    finally:
+        G.close()
+    return vals, st
+
+
+@pytest.mark.parametrize("gname", ["rmat10w", "rmat14w", "uniform12w"])
+@pytest.mark.parametrize("sched", list(SCHEDULES))
+@pytest.mark.parametrize("pvu", ["off", "strong", "weak"])
+def test_sssp_bfs(sr, ctx, gname, sched, pvu):
+    g = graph(gname)
+    src = int(np.argmax(np.diff(g.offsets)))
+    say(f"case sssp/bfs {gname} {sched} {pvu} src={src}")
+    ref = oracle.sssp(g, src)
+    got, st = run_case(sr, ctx, g, "sssp", pvu, sched, source=src)
+    assert st["converged"] == 1
+    assert np.array_equal(got, ref), f"{np.sum(got != ref)} mismatches"
+    refb = oracle.bfs(g, src)
+    got, st = run_case(sr, ctx, g, "bfs", pvu, sched, source=src)
+    assert np.array_equal(got, refb), f"{np.sum(got != refb)} mismatches"
+
+
+@pytest.mark.parametrize("gname", ["rmat10w", "rmat14w", "uniform12w"])
+@pytest.mark.parametrize("sched", list(SCHEDULES))
+@pytest.mark.parametrize("pvu", ["off", "strong", "weak"])
+def test_cc(sr, ctx, gname, sched, pvu):
+    g = graph(gname)
+    say(f"case cc {gname} {sched} {pvu}")
+    ref = oracle.cc(g)
+    got, st = run_case(sr, ctx, g, "cc", pvu, sched, symmetrize=True)
+    assert st["converged"] == 1
+    assert np.array_equal(got, ref), f"{np.sum(got != ref)} mismatches"
+
+
+@pytest.mark.parametrize("gname", ["rmat10w", "rmat16w", "uniform12w"])
+@pytest.mark.parametrize("sched", ["resident", "s2p4i4", "s4p7i1"])
+@pytest.mark.parametrize("pvu", ["off", "weak"])
+def test_pagerank(sr, ctx, gname, sched, pvu):
+    g = graph(gname)
+    say(f"case pagerank {gname} {sched} {pvu}")
+    ref, _, _ = oracle.pagerank(g, tol=1e-13)
+    got, st = run_case(sr, ctx, g, "pagerank", pvu, sched)
+    x = got.view(np.float32).astype(np.float64)
+    err = np.max(np.abs(x - ref))
+    say(f"  max-abs {err:.3e} passes {st['passes']} stop {st['stop_reason']} l1 {st['final_l1']:.3e}")
+    assert st["converged"] == 1
+    assert err <= PR_TOL
+    assert abs(x.sum() - 1.0) < 1e-4
+
+
+@pytest.mark.parametrize("gname", ["rmat10w", "rmat14w"])
+@pytest.mark.parametrize("sched", ["resident", "s3p3i4"])
+def test_ppr(sr, ctx, gname, sched):
+    g = graph(gname)
+    seeds = graphgen.sources_with_outedges(g, 3, seed=2000)
+    for s in seeds:
+        say(f"case ppr {gname} {sched} seed={s}")
+        ref, _, _ = oracle.pagerank(g, seed=int(s), tol=1e-13)
+        got, st = run_case(sr, ctx, g, "ppr", "weak", sched, source=int(s))
+        x = got.view(np.float32).astype(np.float64)
+        err = np.max(np.abs(x - ref))
+        say(f"  max-abs {err:.3e}")
+        assert err <= PR_TOL
+
+
+def test_strong_pvu_audit_no_misprediction(sr, ctx):
+    """Table I conditions are sound: audited skips never hide a change."""
+    g = graph("rmat14w")
+    for algo, sym in (("sssp", False), ("bfs", False), ("cc", True)):
+        for sched in ("resident", "s3p3i4"):
+            say(f"case audit strong {algo} {sched}")
+            got, st = run_case(sr, ctx, g, algo, "strong", sched, symmetrize=sym, audit=True)
+            assert st["mispredicted"] == 0
+            assert st["vertices_skipped"] > 0
+
+
+def test_weak_pvu_skips_and_recovers(sr, ctx):
+    g = graph("rmat14w")
+    say("case weak audit sssp")
+    got, st = run_case(sr, ctx, g, "sssp", "weak", "resident", audit=True)
+    assert np.array_equal(got, oracle.sssp(g, 0))
+    assert st["vertices_skipped"] > 0
+    assert st["verify_passes"] >= 1
+    assert sum(st["state_hist"][2:5]) > 0
+
+
+def test_tiny_graphs(sr, ctx):
+    cases = [
+        graphgen.from_edges(1, [], [], []),
+        graphgen.from_edges(2, [0], [1], [5]),
+        graphgen.from_edges(5, [0, 1, 2, 3], [1, 2, 3, 4], [1, 2, 3, 4]),
+        graphgen.from_edges(4, [1, 2], [2, 3], [7, 7]),  # source 0 isolated
+    ]
+    for g in cases:
+        for sched in ("resident", "s2p4i4"):
+            say(f"case tiny n={g.n} m={g.m} {sched}")
+            got, _ = run_case(sr, ctx, g, "sssp", "weak", sched)
+            assert np.array_equal(got, oracle.sssp(g, 0))
+            got, _ = run_case(sr, ctx, g, "cc", "strong", sched, symmetrize=True)
+            assert np.array_equal(got, oracle.cc(g))
+
+
+def test_exhaustive_cc_n5_sample(sr, ctx):
+    import itertools
+    pairs = list(itertools.combinations(range(5), 2))
+    r = np.random.default_rng(3)
+    for mask in r.choice(1 << len(pairs), size=48, replace=False):
+        es = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
+        g = graphgen.from_edges(5, [u for u, _ in es], [v for _, v in es])
+        got, _ = run_case(sr, ctx, g, "cc", "strong", "resident", symmetrize=True)
+        assert np.array_equal(got, oracle.cc(g)), mask
