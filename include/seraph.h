@@ -204,6 +204,84 @@ sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_stats *stats);
  * float32 ranks for PageRank/PPR. dst_bytes must be >= 4n. */
 sr_status sr_read_values(const sr_graph *g, void *host_dst, uint64_t dst_bytes);
 
+
+/* ---------------------------------------------------------------- batched */
+
+/* Many instances in one launch: beyond the paper, which runs one program
+ * at a time. Instances are grouped per graph in groups of width K (8);
+ * values of a group are laid out [vertex][K] so every in-edge read and
+ * every neighbour gather is shared by the K instances. All groups of all
+ * graphs are swept by one persistent kernel whose blocks take work items
+ * from a device queue; the sweep is captured once in a HIP graph and
+ * replayed until every instance has converged (PPR: L1 change of a sweep
+ * below tol_l1, or the FP32 floor rule; SSSP/BFS: a sweep without change,
+ * with the Table I strong conditions per instance). The persistent grid
+ * size and the items taken per queue access are chosen by a built-in
+ * autotuner (timed candidate sweeps), cached per process and in the JSON
+ * file named by SR_TUNE_CACHE if set. Graphs must fit the budget resident. */
+typedef struct {
+  sr_graph *g;
+  sr_algo algo;      /* SR_PPR, SR_SSSP or SR_BFS; one family per call
+                        (PPR alone, or any mix of SSSP and BFS) */
+  int32_t source;    /* PPR seed or SSSP/BFS source */
+} sr_instance;
+
+typedef struct {
+  int32_t sweeps;        /* graph replays (one sweep of every group each) */
+  int32_t groups;        /* instance groups of width group_width */
+  int32_t group_width;
+  int32_t grid_blocks;   /* persistent grid chosen by the autotuner */
+  int32_t grab;          /* work items per queue access */
+  int32_t tuned;         /* 1: the autotuner ran in this call, 0: cached */
+  double kernel_ms;      /* device time of the replays (HIP events) */
+  double wall_ms;        /* host wall time of the whole call */
+  uint64_t algo_bytes;   /* algorithmic bytes of all sweeps */
+} sr_batch_stats;
+
+/* Run `count` instances to convergence. host_dsts[i] (host, 4n_i bytes)
+ * receives instance i's values (f32 ranks for PPR, u32 levels/distances
+ * with SR_INF unreached). common supplies damping, tol_l1, max_passes
+ * (sweep cap) and pvu (SSSP/BFS: OFF or STRONG; DEFAULT = STRONG; PPR:
+ * OFF). per_instance (may be NULL) receives count records; batch_stats may
+ * be NULL. */
+sr_status sr_batch_run(sr_ctx *ctx, const sr_instance *instances, int32_t count,
+                       const sr_run_params *common, void *const *host_dsts,
+                       sr_run_stats *per_instance, sr_batch_stats *batch_stats);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A continuous-batching query server (beyond the paper): SSSP and BFS
+ * source queries on resident graphs. Each graph owns max_slots_per_graph
+ * (8 or 16) query slots whose state (4 B distance per vertex per slot) is
+ * allocated up front if state_budget_bytes allows, else as many slots as
+ * fit. A progress thread admits queued queries into free slots as they
+ * free up, sweeps every graph with active slots (one multi-source sweep
+ * per graph, all its active slots together), retires converged slots (a
+ * sweep without change under the Table I strong conditions), copies their
+ * values to host and records latency = completion - submission. */
+sr_status sr_server_create(sr_ctx *ctx, sr_graph *const *graphs, int32_t ngraphs,
+                           uint64_t state_budget_bytes, int32_t max_slots_per_graph,
+                           sr_server **out);
+/* Queue a query (thread-safe). algo is SR_SSSP or SR_BFS. *ticket
+ * identifies it for sr_server_poll. SR_EBUSY if the queue holds 1M
+ * queries. */
+sr_status sr_server_submit(sr_server *srv, int32_t graph, sr_algo algo, int32_t source,
+                           uint64_t *ticket);
+/* Non-blocking poll (thread-safe). When the query is done, *done = 1, its
+ * values are copied to host_dst (if not NULL, bytes >= 4n) and *latency_ms
+ * is set; the result is then released (a later poll returns SR_EINVAL). */
+sr_status sr_server_poll(sr_server *srv, uint64_t ticket, void *host_dst, uint64_t bytes,
+                         int *done, double *latency_ms);
+typedef struct {
+  uint64_t submitted, completed, sweeps;
+  int32_t slots_per_graph[8];
+  double busy_ms;        /* progress-thread time spent with work in flight */
+} sr_server_stats;
+sr_status sr_server_stats_get(sr_server *srv, sr_server_stats *out);
+/* Stop the progress thread after finishing admitted queries, free the
+ * server's device state. Results not yet polled are discarded. */
+sr_status sr_server_destroy(sr_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -96,7 +96,34 @@ _SIGNATURES = {
     "sr_run": (ctypes.c_int, [_P, ctypes.POINTER(sr_run_params), ctypes.POINTER(sr_run_stats)]),
     "sr_read_values": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
 }
-EXTRA_SIGNATURES: dict = {}
+class sr_instance(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("algo", ctypes.c_int), ("source", ctypes.c_int32)]
+
+
+class sr_batch_stats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("groups", ctypes.c_int32), ("group_width", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("grab", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double), ("wall_ms", ctypes.c_double), ("algo_bytes", ctypes.c_uint64)]
+
+
+class sr_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("sweeps", ctypes.c_uint64),
+                ("slots_per_graph", ctypes.c_int32 * 8), ("busy_ms", ctypes.c_double)]
+
+
+EXTRA_SIGNATURES: dict = {
+    "sr_batch_run": (ctypes.c_int, [_P, ctypes.POINTER(sr_instance), ctypes.c_int32, ctypes.POINTER(sr_run_params),
+                                    ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(sr_run_stats),
+                                    ctypes.POINTER(sr_batch_stats)]),
+    "sr_server_create": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_uint64,
+                                        ctypes.c_int32, ctypes.POINTER(_P)]),
+    "sr_server_submit": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "sr_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_double)]),
+    "sr_server_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(sr_server_stats)]),
+    "sr_server_destroy": (ctypes.c_int, [_P]),
+}
 
 _lib = None
 
@@ -260,3 +287,76 @@ class Graph:
         if dtype is not None:
             return out.view(dtype)
         return out
+
+
+def batch_run(ctx: Context, instances, damping: float = 0.85, tol_l1: float = 1e-9, max_sweeps: int = 0,
+              pvu="default", check: bool = True):
+    """Run [(Graph, algo, source), ...] to convergence in one batched call.
+    Returns (list of value arrays, list of per-instance stats, batch stats)."""
+    cnt = len(instances)
+    arr = (sr_instance * cnt)()
+    outs = []
+    for i, (G, algo, src) in enumerate(instances):
+        arr[i].g = G.h.value if isinstance(G.h, ctypes.c_void_p) else G.h
+        arr[i].algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        arr[i].source = int(src)
+        outs.append(np.empty(G.n, dtype=np.uint32))
+    dsts = (ctypes.c_void_p * cnt)(*[o.ctypes.data for o in outs])
+    p = sr_run_params()
+    p.damping = damping
+    p.tol_l1 = tol_l1
+    p.max_passes = max_sweeps
+    p.pvu = PVUS[pvu] if isinstance(pvu, str) else int(pvu)
+    per = (sr_run_stats * cnt)()
+    bs = sr_batch_stats()
+    rc = lib().sr_batch_run(ctx.h, arr, cnt, ctypes.byref(p), dsts, per, ctypes.byref(bs))
+    if check and rc != SR_OK:
+        _check(rc, ctx.h)
+    return outs, [per[i].as_dict() for i in range(cnt)], {k: getattr(bs, k) for k, _ in bs._fields_}
+
+
+class Server:
+    """Continuous-batching SSSP/BFS query server over resident graphs."""
+
+    def __init__(self, ctx: Context, graphs, state_budget_bytes: int = 0, slots: int = 16):
+        self.ctx = ctx
+        self.graphs = list(graphs)
+        arr = (ctypes.c_void_p * len(self.graphs))(*[G.h.value if isinstance(G.h, ctypes.c_void_p) else G.h
+                                                     for G in self.graphs])
+        h = _P()
+        _check(lib().sr_server_create(ctx.h, arr, len(self.graphs), state_budget_bytes, slots, ctypes.byref(h)),
+               ctx.h)
+        self.h = h
+
+    def submit(self, graph: int, algo, source: int) -> int:
+        t = ctypes.c_uint64()
+        rc = lib().sr_server_submit(self.h, graph, ALGOS[algo] if isinstance(algo, str) else int(algo), source,
+                                    ctypes.byref(t))
+        if rc != SR_OK:
+            raise SeraphError(rc, "submit failed")
+        return t.value
+
+    def poll(self, ticket: int, out: Optional[np.ndarray] = None):
+        """(done, latency_ms); fills `out` (uint32[n]) when done."""
+        done = ctypes.c_int(0)
+        lat = ctypes.c_double(0.0)
+        ptr = out.ctypes.data if out is not None else None
+        nbytes = out.nbytes if out is not None else 0
+        rc = lib().sr_server_poll(self.h, ticket, ptr, nbytes, ctypes.byref(done), ctypes.byref(lat))
+        if rc != SR_OK:
+            raise SeraphError(rc, "poll failed")
+        return bool(done.value), lat.value
+
+    def stats(self) -> dict:
+        s = sr_server_stats()
+        _check(lib().sr_server_stats_get(self.h, ctypes.byref(s)), self.ctx.h)
+        d = {k: getattr(s, k) for k, _ in s._fields_}
+        d["slots_per_graph"] = list(s.slots_per_graph)[:len(self.graphs)]
+        return d
+
+    def close(self):
+        if self.h:
+            rc = lib().sr_server_destroy(self.h)
+            self.h = None
+            if rc != SR_OK:
+                raise SeraphError(rc, "server ended with an error")

@@ -1,0 +1,486 @@
+// batch.hip -- multi-instance pull sweep for gfx950: K instances (K = 8 or
+// 16) of personalized PageRank, SSSP or BFS on resident graphs, several
+// graphs in one persistent launch. A wavefront is split into 64/K edge
+// lanes x K instance lanes: the K lanes of one edge lane load the same
+// in-edge source (one broadcast load) and gather the K contiguous values of
+// that neighbour (one 4K-byte access), so every index and weight read is
+// shared by K instances. Blocks take work items from a device queue until
+// it is empty; the last block to finish closes the sweep for every instance
+// (convergence, thresholds, PageRank dangling mass) so the launch can be
+// replayed from a captured graph with no host work in between.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "batch.hpp"
+
+namespace sr {
+namespace {
+
+constexpr int MI_ROUNDS = 4;
+
+template <typename T>
+__device__ inline T shfl_xor(T v, int m) { return __shfl_xor(v, m, 64); }
+
+template <typename T>
+__device__ inline T ld_agent(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline void st_agent(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace
+
+// vertices (bins 0..6, 8) or chunks (bin 7) per work item of the multi-
+// instance sweep with K instance lanes
+__host__ __device__ inline int mi_items_per_block(int b, int K) {
+  const int EL = 64 / K;
+  if (b <= 5) {
+    int GE = (1 << b) < EL ? (1 << b) : EL;
+    return WAVES * MI_ROUNDS * (EL / GE);
+  }
+  if (b == BIN_WAVE || b == BIN_CHUNK) return WAVES;
+  return MI_ROUNDS * (BLOCK / K);
+}
+
+namespace {
+
+template <int ALGO>
+constexpr bool mi_pr() { return ALGO == A_PPR; }
+
+// Per-lane state of one instance column for the current item.
+struct Lane {
+  uint32_t active, unit, threshold;
+  int32_t source;
+  float dangling;
+};
+
+template <int ALGO, int K>
+struct MiRed {
+  using T = typename std::conditional<mi_pr<ALGO>(), float, uint32_t>::type;
+  __device__ static inline T identity() {
+    if constexpr (mi_pr<ALGO>()) return 0.0f; else return INF;
+  }
+  __device__ static inline T combine(T a, T b) {
+    if constexpr (mi_pr<ALGO>()) return a + b; else return min(a, b);
+  }
+  __device__ static inline T edge(const MiGroup &g, int32_t u, uint32_t w, int k, const Lane &ln) {
+    if constexpr (mi_pr<ALGO>()) {
+      return g.contrib[(size_t)u * K + k];
+    } else {
+      uint32_t x = g.value[(size_t)u * K + k];
+      if (x == INF) return INF;
+      uint64_t c = (uint64_t)x + (ln.unit ? 1ull : (uint64_t)w);
+      return c >= (uint64_t)INF ? INF : (uint32_t)c;
+    }
+  }
+  __device__ static inline uint32_t bits(T v) {
+    if constexpr (mi_pr<ALGO>()) return __float_as_uint(v); else return v;
+  }
+  __device__ static inline T from_bits(uint32_t b) {
+    if constexpr (mi_pr<ALGO>()) return __uint_as_float(b); else return b;
+  }
+};
+
+struct MiAcc {
+  uint32_t changed = 0, min_changed = INF, edges = 0;
+  double l1 = 0.0, ddelta = 0.0;
+};
+
+template <int ALGO, int K>
+__device__ inline bool mi_attempt(const MiGroup &g, int32_t v, int k, const Lane &ln, uint32_t &old) {
+  old = g.value[(size_t)v * K + k];
+  if (!ln.active) return false;
+  if constexpr (!mi_pr<ALGO>()) {
+    if (g.pvu == P_STRONG && old <= ln.threshold) return false;  // Table I
+  }
+  return true;
+}
+
+template <int ALGO, int K>
+__device__ inline void mi_epilogue(const MiGroup &g, int32_t v, int k, const Lane &ln, uint32_t old,
+                                   typename MiRed<ALGO, K>::T red, uint32_t deg, float damping, MiAcc &acc) {
+  acc.edges += deg;
+  const size_t i = (size_t)v * K + k;
+  if constexpr (mi_pr<ALGO>()) {
+    float t = (v == ln.source) ? 1.0f : 0.0f;
+    float oldf = __uint_as_float(old);
+    float nv = (1.0f - damping) * t + damping * (red + ln.dangling * t);
+    g.value[i] = __float_as_uint(nv);
+    float iod = g.inv_outdeg[v];
+    g.contrib[i] = nv * iod;
+    double dd = (double)nv - (double)oldf;
+    acc.l1 += fabs(dd);
+    if (iod == 0.0f) acc.ddelta += dd;
+    if (nv != oldf) acc.changed++;
+  } else {
+    uint32_t nv = min(old, red);
+    if (nv < old) {
+      g.value[i] = nv;
+      acc.changed++;
+      acc.min_changed = min(acc.min_changed, nv);
+    }
+  }
+}
+
+// lanes with the same instance k reduce over the 64/K edge lanes; lanes
+// 0..K-1 then publish the per-instance totals
+template <int ALGO, int K>
+__device__ inline void mi_flush(const MiGroup &g, MiAcc &acc) {
+  const int lane = threadIdx.x % 64;
+#pragma unroll
+  for (int m = K; m < 64; m <<= 1) {
+    acc.changed += shfl_xor(acc.changed, m);
+    acc.min_changed = min(acc.min_changed, shfl_xor(acc.min_changed, m));
+    acc.edges += shfl_xor(acc.edges, m);
+    if constexpr (mi_pr<ALGO>()) {
+      acc.l1 += shfl_xor(acc.l1, m);
+      acc.ddelta += shfl_xor(acc.ddelta, m);
+    }
+  }
+  if (lane < K) {
+    MiInst &in = g.inst[lane];
+    if (acc.changed) atomicAdd(&in.sw_changed, acc.changed);
+    if (acc.min_changed != INF) atomicMin(&in.sw_min_changed, acc.min_changed);
+    if (acc.edges) atomicAdd(&in.sw_edges, (unsigned long long)acc.edges);
+    if constexpr (mi_pr<ALGO>()) {
+      if (acc.l1 != 0.0) atomicAdd(&in.sw_l1, acc.l1);
+      if (acc.ddelta != 0.0) atomicAdd(&in.sw_ddelta, acc.ddelta);
+    }
+  }
+  acc = MiAcc();
+}
+
+// bins 0..5: GE edge lanes per vertex (GE = min(2^b, 64/K)), MI_ROUNDS
+// rounds of 64/K/GE vertices per wavefront
+template <int ALGO, int K, int GE>
+__device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h, int bin, int item,
+                         const Lane &ln, float damping, MiAcc &acc) {
+  using R = MiRed<ALGO, K>;
+  using T = typename R::T;
+  constexpr int EL = 64 / K;
+  constexpr int VPW = EL / GE;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int k = lane % K, el = lane / K, vs = el / GE, ein = el % GE;
+  const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
+  const int32_t *bins = reinterpret_cast<const int32_t *>(base + h->off_bins) + h->bin_start[bin];
+  const int32_t *src = reinterpret_cast<const int32_t *>(base + h->off_src);
+  const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
+  const int cnt = h->bin_count[bin];
+  const int vb = h->v_begin;
+  int32_t vl[MI_ROUNDS], beg[MI_ROUNDS], end[MI_ROUNDS];
+  uint32_t old[MI_ROUNDS];
+  bool att[MI_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < MI_ROUNDS; ++r) {
+    int idx = ((item * WAVES + wave) * MI_ROUNDS + r) * VPW + vs;
+    vl[r] = idx < cnt ? bins[idx] : -1;
+    beg[r] = 0; end[r] = 0; att[r] = false; old[r] = 0;
+    if (vl[r] >= 0) {
+      beg[r] = off[vl[r]];
+      end[r] = off[vl[r] + 1];
+      att[r] = mi_attempt<ALGO, K>(g, vb + vl[r], k, ln, old[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < MI_ROUNDS; ++r) {
+    T x = R::identity();
+    if (att[r]) {
+      for (int e = beg[r] + ein; e < end[r]; e += GE) {
+        int32_t u = src[e];
+        uint32_t w = (ALGO == A_SSSP && g.has_w) ? wt[e] : 1u;
+        x = R::combine(x, R::edge(g, u, w, k, ln));
+      }
+    }
+#pragma unroll
+    for (int m = K; m < K * GE; m <<= 1) x = R::combine(x, shfl_xor(x, m));
+    if (att[r] && ein == 0)
+      mi_epilogue<ALGO, K>(g, vb + vl[r], k, ln, old[r], x, (uint32_t)(end[r] - beg[r]), damping, acc);
+  }
+}
+
+// bin 6 (wave per vertex) and bin 7 (wave per chunk) share the edge loop
+template <int ALGO, int K>
+__device__ inline typename MiRed<ALGO, K>::T mi_edges(const MiGroup &g, const int32_t *src, const uint32_t *wt,
+                                                      int32_t e0, int32_t e1, int k, int el, const Lane &ln) {
+  using R = MiRed<ALGO, K>;
+  using T = typename R::T;
+  constexpr int EL = 64 / K;
+  T x = R::identity();
+  int e = e0 + el;
+  for (; e + 3 * EL < e1; e += 4 * EL) {
+    int32_t u0 = src[e], u1 = src[e + EL], u2 = src[e + 2 * EL], u3 = src[e + 3 * EL];
+    uint32_t w0 = 1, w1 = 1, w2 = 1, w3 = 1;
+    if (ALGO == A_SSSP && g.has_w) { w0 = wt[e]; w1 = wt[e + EL]; w2 = wt[e + 2 * EL]; w3 = wt[e + 3 * EL]; }
+    T y0 = R::edge(g, u0, w0, k, ln), y1 = R::edge(g, u1, w1, k, ln);
+    T y2 = R::edge(g, u2, w2, k, ln), y3 = R::edge(g, u3, w3, k, ln);
+    x = R::combine(x, R::combine(R::combine(y0, y1), R::combine(y2, y3)));
+  }
+  for (; e < e1; e += EL) x = R::combine(x, R::edge(g, src[e], (ALGO == A_SSSP && g.has_w) ? wt[e] : 1u, k, ln));
+#pragma unroll
+  for (int m = K; m < 64; m <<= 1) x = R::combine(x, shfl_xor(x, m));
+  return x;
+}
+
+template <int ALGO, int K>
+__device__ void mi_wave(const MiGroup &g, const char *base, const PageHeader *h, int item, const Lane &ln,
+                        float damping, MiAcc &acc) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, k = lane % K, el = lane / K;
+  int idx = item * WAVES + wave;
+  if (idx >= h->bin_count[BIN_WAVE]) return;
+  const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
+  const int32_t vl = reinterpret_cast<const int32_t *>(base + h->off_bins)[h->bin_start[BIN_WAVE] + idx];
+  const int32_t *src = reinterpret_cast<const int32_t *>(base + h->off_src);
+  const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
+  const int32_t v = h->v_begin + vl;
+  uint32_t old;
+  bool att = mi_attempt<ALGO, K>(g, v, k, ln, old);
+  // lanes of inactive instances still help with the shared index loads
+  bool any = __any(att);
+  if (!any) return;
+  auto x = mi_edges<ALGO, K>(g, src, wt, off[vl], off[vl + 1], k, el, ln);
+  if (att && el == 0) mi_epilogue<ALGO, K>(g, v, k, ln, old, x, (uint32_t)(off[vl + 1] - off[vl]), damping, acc);
+}
+
+template <int ALGO, int K>
+__device__ void mi_chunk(const MiGroup &g, const MiUnit &u, const char *base, const PageHeader *h, int item,
+                         const Lane &ln, float damping, MiAcc &acc) {
+  using R = MiRed<ALGO, K>;
+  using T = typename R::T;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, k = lane % K, el = lane / K;
+  int idx = item * WAVES + wave;
+  if (idx >= h->bin_count[BIN_CHUNK]) return;
+  const Chunk c = reinterpret_cast<const Chunk *>(base + h->off_chunks)[idx];
+  const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
+  const int32_t *src = reinterpret_cast<const int32_t *>(base + h->off_src);
+  const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
+  const int32_t v = h->v_begin + c.vl;
+  const int first = (int)((uint32_t)c.first_count & 0xFFFFFu), count = (int)((uint32_t)c.first_count >> 20);
+  uint32_t old;
+  bool att = mi_attempt<ALGO, K>(g, v, k, ln, old);
+  T x = R::identity();
+  if (__any(att)) x = mi_edges<ALGO, K>(g, src, wt, c.e_begin, c.e_end, k, el, ln);
+  // every chunk arrives (also when no instance attempts) so the counter of
+  // the vertex always returns to zero
+  if (el == 0) st_agent(&u.partial[(size_t)idx * K + k], R::bits(x));
+  __threadfence();
+  uint32_t ticket = 0;
+  if (lane == 0) ticket = atomicAdd(&u.arrive[first], 1u);
+  ticket = __shfl(ticket, 0, 64);
+  if (ticket != (uint32_t)(count - 1)) return;
+  __threadfence();
+  if (el == 0) {
+    T tot = R::identity();
+    for (int j = 0; j < count; ++j) tot = R::combine(tot, R::from_bits(ld_agent(&u.partial[(size_t)(first + j) * K + k])));
+    if (att) mi_epilogue<ALGO, K>(g, v, k, ln, old, tot, (uint32_t)(off[c.vl + 1] - off[c.vl]), damping, acc);
+  }
+  if (lane == 0) st_agent(&u.arrive[first], 0u);
+}
+
+template <int ALGO, int K>
+__device__ void mi_zero(const MiGroup &g, const char *base, const PageHeader *h, int item, const Lane &ln,
+                        float damping, MiAcc &acc) {
+  const int k = threadIdx.x % K, vs = threadIdx.x / K;
+  const int32_t *bins = reinterpret_cast<const int32_t *>(base + h->off_bins) + h->bin_start[BIN_ZERO];
+  const int cnt = h->bin_count[BIN_ZERO];
+  for (int r = 0; r < MI_ROUNDS; ++r) {
+    int idx = (item * MI_ROUNDS + r) * (BLOCK / K) + vs;
+    if (idx >= cnt) break;
+    int32_t v = h->v_begin + bins[idx];
+    uint32_t old;
+    if (mi_attempt<ALGO, K>(g, v, k, ln, old))
+      mi_epilogue<ALGO, K>(g, v, k, ln, old, typename MiRed<ALGO, K>::T(0), 0u, damping, acc);
+  }
+}
+
+// close the sweep for every instance: convergence, thresholds, dangling mass
+template <int ALGO, int K>
+__device__ void mi_close(const MiArgs &a) {
+  __shared__ uint32_t s_rem;
+  if (threadIdx.x == 0) s_rem = 0;
+  for (int gi = threadIdx.x; gi < a.ngroups; gi += BLOCK) st_agent(&a.group_active[gi], 0u);
+  __syncthreads();
+  const int total = a.ngroups * K;
+  for (int i = threadIdx.x; i < total; i += BLOCK) {
+    MiInst &in = a.groups[i / K].inst[i % K];
+    if (!ld_agent(&in.active)) continue;
+    uint32_t changed = ld_agent(&in.sw_changed);
+    uint32_t minc = ld_agent(&in.sw_min_changed);
+    double l1 = ld_agent(&in.sw_l1), dd = ld_agent(&in.sw_ddelta);
+    in.edges_total += ld_agent(&in.sw_edges);
+    in.sweeps += 1;
+    bool done = false;
+    if constexpr (mi_pr<ALGO>()) {
+      in.dangling += dd;
+      in.last_l1 = l1;
+      if (l1 < in.best_l1) { in.best_l1 = l1; in.no_improve = 0; }
+      else in.no_improve += 1;
+      if (l1 < a.tol_l1) { done = true; in.stop_reason = 1; }
+      else if (l1 < a.floor_cap && in.no_improve >= 3) { done = true; in.stop_reason = 2; }
+    } else {
+      if (changed == 0) { done = true; in.stop_reason = 1; }
+      else if (a.groups[i / K].pvu == P_STRONG) in.threshold = in.unit ? in.sweeps : minc;
+    }
+    if (!done && (int32_t)in.sweeps >= a.max_sweeps) { done = true; in.stop_reason = 3; }
+    if (a.tuning) done = false;
+    st_agent(&in.sw_changed, 0u);
+    st_agent(&in.sw_min_changed, INF);
+    st_agent(&in.sw_edges, 0ull);
+    st_agent(&in.sw_l1, 0.0);
+    st_agent(&in.sw_ddelta, 0.0);
+    if (done) { in.done = 1; st_agent(&in.active, 0u); }
+    else { atomicAdd(&s_rem, 1u); atomicAdd(&a.group_active[i / K], 1u); }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.ctl->remaining = s_rem;
+    a.ctl->sweeps += 1;
+    if (a.host_remaining) *a.host_remaining = s_rem;
+    st_agent(&a.ctl->queue, 0u);
+    st_agent(&a.ctl->blocks_done, 0u);
+    __threadfence_system();
+  }
+}
+
+template <int ALGO, int K>
+__global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
+  if (a.ctl->remaining == 0 && !a.tuning) return;  // everything converged: replays are no-ops
+  __shared__ int32_t s_base;
+  __shared__ uint32_t s_last;
+  const int lane = threadIdx.x % 64, k = lane % K;
+  for (;;) {
+    if (threadIdx.x == 0) s_base = (int32_t)atomicAdd(&a.ctl->queue, (uint32_t)a.grab);
+    __syncthreads();
+    const int32_t base = s_base;
+    __syncthreads();
+    if (base >= a.total_items) break;
+    const int32_t end = min(base + a.grab, a.total_items);
+    for (int32_t it = base; it < end; ++it) {
+      int lo = 0, hi = a.nunits;  // unit_prefix[lo] <= it < unit_prefix[hi]
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (a.unit_prefix[mid] <= it) lo = mid; else hi = mid;
+      }
+      const MiUnit &u = a.units[lo];
+      if (a.group_active[u.group] == 0) continue;  // no live instance in this group
+      const MiGroup &g = a.groups[u.group];
+      int local = it - a.unit_prefix[lo];
+      int bin = 0;
+      while (bin < NBINS - 1 && u.blk_prefix[bin + 1] <= local) ++bin;
+      const int item = local - u.blk_prefix[bin];
+      const char *base_p = u.page;
+      const PageHeader *h = reinterpret_cast<const PageHeader *>(base_p);
+      const MiInst &in = g.inst[k];
+      Lane ln;
+      ln.active = in.active;
+      ln.unit = in.unit;
+      ln.threshold = in.threshold;
+      ln.source = in.source;
+      ln.dangling = (float)in.dangling;
+      MiAcc acc;
+      switch (bin) {
+        case 0: mi_small<ALGO, K, 1>(g, base_p, h, 0, item, ln, a.damping, acc); break;
+        case 1: mi_small<ALGO, K, (2 < 64 / K ? 2 : 64 / K)>(g, base_p, h, 1, item, ln, a.damping, acc); break;
+        case 2: mi_small<ALGO, K, (4 < 64 / K ? 4 : 64 / K)>(g, base_p, h, 2, item, ln, a.damping, acc); break;
+        case 3: mi_small<ALGO, K, (8 < 64 / K ? 8 : 64 / K)>(g, base_p, h, 3, item, ln, a.damping, acc); break;
+        case 4: mi_small<ALGO, K, (16 < 64 / K ? 16 : 64 / K)>(g, base_p, h, 4, item, ln, a.damping, acc); break;
+        case 5: mi_small<ALGO, K, (32 < 64 / K ? 32 : 64 / K)>(g, base_p, h, 5, item, ln, a.damping, acc); break;
+        case BIN_WAVE: mi_wave<ALGO, K>(g, base_p, h, item, ln, a.damping, acc); break;
+        case BIN_CHUNK: mi_chunk<ALGO, K>(g, u, base_p, h, item, ln, a.damping, acc); break;
+        default:
+          if constexpr (mi_pr<ALGO>()) mi_zero<ALGO, K>(g, base_p, h, item, ln, a.damping, acc);
+          break;
+      }
+      mi_flush<ALGO, K>(g, acc);
+    }
+  }
+  // the last block to finish closes the sweep
+  if (threadIdx.x == 0) {
+    __threadfence();
+    uint32_t t = atomicAdd(&a.ctl->blocks_done, 1u);
+    s_last = (t == (uint32_t)(a.nblocks - 1)) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    mi_close<ALGO, K>(a);
+  }
+}
+
+template <int ALGO, int K>
+__global__ void mi_init_column_kernel(uint32_t *value, float *contrib, const float *inv_outdeg, int32_t n,
+                                      int32_t col, int32_t source) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  size_t i = (size_t)v * K + col;
+  if constexpr (mi_pr<ALGO>()) {
+    float x = v == source ? 1.0f : 0.0f;
+    value[i] = __float_as_uint(x);
+    contrib[i] = x * inv_outdeg[v];
+  } else {
+    value[i] = v == source ? 0u : INF;
+  }
+}
+
+__global__ void mi_set_inst_kernel(MiInst *dst, MiInst val) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = val;
+}
+
+__global__ void mi_set_ctl_kernel(MiCtl *dst, MiCtl val) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = val;
+}
+
+template <int K>
+__global__ void mi_extract_kernel(const uint32_t *value, int32_t n, int32_t col, uint32_t *out) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) out[v] = value[(size_t)v * K + col];
+}
+
+}  // namespace
+
+int mi_items_per_block_host(int b, int K) { return mi_items_per_block(b, K); }
+
+hipError_t launch_mi_sweep(int algo, int K, const MiArgs &a, hipStream_t s) {
+  dim3 grid(a.nblocks), block(BLOCK);
+  if (a.nblocks <= 0) return hipErrorInvalidValue;
+  if (algo == A_PPR && K == 8) hipLaunchKernelGGL((mi_sweep_kernel<A_PPR, 8>), grid, block, 0, s, a);
+  else if (algo == A_PPR && K == 16) hipLaunchKernelGGL((mi_sweep_kernel<A_PPR, 16>), grid, block, 0, s, a);
+  else if (algo == A_SSSP && K == 8) hipLaunchKernelGGL((mi_sweep_kernel<A_SSSP, 8>), grid, block, 0, s, a);
+  else if (algo == A_SSSP && K == 16) hipLaunchKernelGGL((mi_sweep_kernel<A_SSSP, 16>), grid, block, 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contrib, const float *inv_outdeg,
+                                 int32_t n, int32_t col, int32_t source, hipStream_t s) {
+  dim3 grid((n + 255) / 256), block(256);
+  if (algo == A_PPR && K == 8) hipLaunchKernelGGL((mi_init_column_kernel<A_PPR, 8>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
+  else if (algo == A_PPR && K == 16) hipLaunchKernelGGL((mi_init_column_kernel<A_PPR, 16>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
+  else if (algo == A_SSSP && K == 8) hipLaunchKernelGGL((mi_init_column_kernel<A_SSSP, 8>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
+  else if (algo == A_SSSP && K == 16) hipLaunchKernelGGL((mi_init_column_kernel<A_SSSP, 16>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_mi_extract(int K, const uint32_t *value, int32_t n, int32_t col, uint32_t *out, hipStream_t s) {
+  dim3 grid((n + 255) / 256), block(256);
+  if (K == 8) hipLaunchKernelGGL(mi_extract_kernel<8>, grid, block, 0, s, value, n, col, out);
+  else if (K == 16) hipLaunchKernelGGL(mi_extract_kernel<16>, grid, block, 0, s, value, n, col, out);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace sr
+
+namespace sr {
+hipError_t launch_mi_set_inst(MiInst *dst, const MiInst &val, hipStream_t s) {
+  hipLaunchKernelGGL(mi_set_inst_kernel, dim3(1), dim3(64), 0, s, dst, val);
+  return hipGetLastError();
+}
+hipError_t launch_mi_set_ctl(MiCtl *dst, const MiCtl &val, hipStream_t s) {
+  hipLaunchKernelGGL(mi_set_ctl_kernel, dim3(1), dim3(64), 0, s, dst, val);
+  return hipGetLastError();
+}
+}  // namespace sr

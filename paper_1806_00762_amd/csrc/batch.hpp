@@ -1,0 +1,91 @@
+// batch.hpp -- multi-instance sweeps: K instances of one vertex program on
+// one resident graph share every in-edge read; values are laid out
+// [vertex][K] so the gather of one neighbour serves all K instances with one
+// contiguous 4K-byte access. Used by sr_batch_run and by the query server.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace sr {
+
+// Per-instance control (device memory), one per column of a group.
+struct MiInst {
+  uint32_t active;       // 1 = running this sweep
+  uint32_t unit;         // min programs: 1 = BFS (unit weights), 0 = SSSP
+  int32_t source;        // SSSP/BFS source or PPR seed
+  uint32_t threshold;    // strong predictor threshold (min programs)
+  uint32_t sweeps;       // sweeps done since admission
+  uint32_t done;         // converged
+  uint32_t stop_reason;
+  uint32_t no_improve;
+  // accumulators of the current sweep
+  uint32_t sw_changed;
+  uint32_t sw_min_changed;
+  unsigned long long sw_edges;
+  double sw_l1;
+  double sw_ddelta;
+  // PageRank state
+  double dangling;
+  double best_l1;
+  double last_l1;
+  unsigned long long edges_total;
+  uint32_t pad[2];
+};
+
+// One group: K columns over one graph.
+struct MiGroup {
+  uint32_t *value;          // [n][K] u32 distances/levels, or f32 ranks
+  float *contrib;           // [n][K] PPR only
+  const float *inv_outdeg;  // [n] PPR only
+  MiInst *inst;             // [K]
+  int32_t n;
+  int32_t pvu;              // P_OFF or P_STRONG
+  int32_t has_w;            // the resident pages carry weights (read only then)
+  int32_t pad;
+};
+
+// One unit of work: a resident page of a group's graph.
+struct MiUnit {
+  int32_t group;
+  int32_t pad;
+  const char *page;
+  uint32_t *partial;        // [n_chunks][K]
+  uint32_t *arrive;         // [n_chunks]
+  int32_t blk_prefix[NBINS + 1];  // items per bin within this unit
+};
+
+// Global control of a batched sweep (device memory).
+struct MiCtl {
+  uint32_t queue;           // next work item (persistent grid)
+  uint32_t blocks_done;
+  uint32_t remaining;       // instances still active after the last sweep
+  uint32_t sweeps;
+};
+
+struct MiArgs {
+  const MiGroup *groups;
+  const MiUnit *units;
+  const int32_t *unit_prefix;  // [nunits + 1] items
+  int32_t ngroups, nunits;
+  int32_t total_items;
+  int32_t grab;             // items taken per queue access
+  int32_t nblocks;
+  float damping;
+  double tol_l1, floor_cap;
+  int32_t max_sweeps;
+  int32_t tuning;           // 1: never retire instances (timing runs)
+  MiCtl *ctl;
+  uint32_t *group_active;   // [ngroups] active instances per group (0: group skipped)
+  uint32_t *host_remaining; // host-mapped copy of ctl->remaining
+};
+
+int mi_items_per_block_host(int b, int K);
+hipError_t launch_mi_sweep(int algo, int K, const MiArgs &a, hipStream_t s);
+hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contrib, const float *inv_outdeg,
+                                 int32_t n, int32_t col, int32_t source, hipStream_t s);
+hipError_t launch_mi_set_inst(MiInst *dst, const MiInst &val, hipStream_t s);
+hipError_t launch_mi_set_ctl(MiCtl *dst, const MiCtl &val, hipStream_t s);
+hipError_t launch_mi_extract(int K, const uint32_t *value, int32_t n, int32_t col, uint32_t *out, hipStream_t s);
+
+}  // namespace sr

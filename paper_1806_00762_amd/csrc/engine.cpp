@@ -140,7 +140,7 @@ extern "C" sr_status sr_ctx_memory(const sr_ctx *c, uint64_t *used, uint64_t *bu
 
 // ----------------------------------------------------------------- graph
 
-static void release_residency(sr_graph *g) {
+void sr::release_residency(sr_graph *g) {
   auto &r = g->res;
   for (auto p : r.buf) g->ctx->dfree(p);
   for (auto p : r.partial) g->ctx->dfree(p);
@@ -210,6 +210,7 @@ extern "C" sr_status sr_graph_partition(sr_graph *g, int32_t nparts, int32_t nsl
   if (nparts < 0) return c->fail(SR_EINVAL, "num_parts must be >= 0");
   if (nslots == 0) nslots = 4;
   if (nslots < 2 || nslots > MAXW + 1) return c->fail(SR_EINVAL, "num_slots must be in [2, 17]");
+  if (g->server_refs > 0) return c->fail(SR_EBUSY, "graph is attached to a server");
   if (g->ctx->host_only == false) { (void)hipSetDevice(c->device); (void)hipDeviceSynchronize(); }
   release_residency(g);
   g->nslots = nslots;
@@ -269,7 +270,7 @@ extern "C" sr_status sr_graph_page(const sr_graph *g, int32_t page, sr_page_view
 }
 
 extern "C" void sr_graph_destroy(sr_graph *g) {
-  if (!g) return;
+  if (!g || g->server_refs > 0) return;  // destroy the server first
   if (!g->ctx->host_only) {
     (void)hipSetDevice(g->ctx->device);
     (void)hipDeviceSynchronize();
@@ -486,7 +487,7 @@ static sr_status ensure_state(sr_graph *g, int algo) {
 }
 
 // Make the pages resident (all of them) or allocate the streaming slots.
-static sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream) {
+sr_status sr::ensure_residency(sr_graph *g, bool weights, bool force_stream) {
   sr_ctx *c = g->ctx;
   auto &r = g->res;
   uint64_t all = 0, mx = 0, smx = 0;
@@ -562,6 +563,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (!g || !params) return g ? g->ctx->fail(SR_EINVAL, "params is NULL") : SR_EINVAL;
   sr_ctx *c = g->ctx;
   if (c->host_only) return c->fail(SR_EDEVICE, "host-only context cannot run");
+  if (g->server_refs > 0) return c->fail(SR_EBUSY, "graph is attached to a server");
   const double t0 = now_ms();
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   Runner R;

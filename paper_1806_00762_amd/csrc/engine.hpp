@@ -93,6 +93,7 @@ struct sr_graph {
   std::vector<sr::Page> pages;
   sr::Residency res;
   sr::RunState state;
+  int server_refs = 0;  // servers holding the resident pages (no re-residency meanwhile)
 };
 
 namespace sr {
@@ -103,4 +104,7 @@ sr_status make_pages(sr_graph *g, int32_t nparts);
 void free_pages(sr_graph *g);
 uint64_t graph_bytes(const sr_graph *g);
 int host_threads();
+// engine.cpp
+sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream);
+void release_residency(sr_graph *g);
 }  // namespace sr

@@ -1,0 +1,342 @@
+// server.cpp -- continuous-batching SSSP/BFS query server over resident
+// graphs. Each graph owns one multi-instance group of K slot columns; a
+// progress thread admits queued queries into free slots as soon as slots
+// (and a result buffer) free up, runs one multi-instance sweep over every
+// graph with live slots per iteration, and retires slots whose sweep changed
+// nothing (the Table I strong conditions keep the skips exact), moving the
+// column into a device result buffer that sr_server_poll copies to the
+// caller. Queries admitted later simply start in their own column while
+// older ones continue: no query waits for a batch boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "mi_plan.hpp"
+
+using namespace sr;
+
+namespace {
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+enum QState { Q_QUEUED = 0, Q_RUNNING = 1, Q_DONE = 2, Q_READING = 3 };
+
+struct Query {
+  int32_t graph;
+  int32_t algo;
+  int32_t source;
+  double t_submit = 0, t_done = 0;
+  int state = Q_QUEUED;
+  int slot = -1;
+  uint32_t *result = nullptr;  // device result buffer once done
+};
+}  // namespace
+
+struct sr_server {
+  sr_ctx *c = nullptr;
+  std::vector<sr_graph *> graphs;
+  MiPlan *plan = nullptr;
+  int K = 8;
+  std::vector<int> usable;                       // concurrent slots per graph
+  std::vector<std::vector<uint64_t>> slot_ticket;  // per graph, per column (0 = free)
+  std::vector<std::vector<uint32_t *>> free_results;  // device result buffers per graph
+  std::unordered_map<uint64_t, Query> q;
+  std::deque<uint64_t> queue;
+  uint64_t next_ticket = 1;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::thread th;
+  bool stop = false;
+  hipStream_t stream = nullptr, poll_stream = nullptr;
+  std::atomic<uint64_t> submitted{0}, completed{0}, sweeps{0};
+  double busy_ms = 0;
+  sr_status thread_error = SR_OK;
+  std::string thread_msg;
+
+  void progress();
+};
+
+void sr_server::progress() {
+  (void)hipSetDevice(c->device);
+  const int G = (int)graphs.size();
+  std::vector<MiInst> ih((size_t)G * K);
+  while (true) {
+    bool any_active = false;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      // admission: FIFO, skipping queries whose graph has no free slot
+      for (auto it = queue.begin(); it != queue.end();) {
+        Query &qq = q[*it];
+        int gi = qq.graph;
+        int col = -1;
+        int busy = 0;
+        for (int k = 0; k < K; ++k) busy += slot_ticket[gi][k] != 0;
+        if (busy < usable[gi] && !free_results[gi].empty())
+          for (int k = 0; k < K; ++k)
+            if (slot_ticket[gi][k] == 0) { col = k; break; }
+        if (col < 0) { ++it; continue; }
+        qq.slot = col;
+        qq.state = Q_RUNNING;
+        qq.result = free_results[gi].back();
+        free_results[gi].pop_back();
+        slot_ticket[gi][col] = *it;
+        sr_status s = plan->set_column(gi, col, qq.source, qq.algo == SR_BFS, true, stream);
+        if (s != SR_OK) { thread_error = s; thread_msg = c->err; }
+        it = queue.erase(it);
+      }
+      for (int gi = 0; gi < G; ++gi)
+        for (int k = 0; k < K; ++k) any_active |= slot_ticket[gi][k] != 0;
+      if (!any_active) {
+        if (stop) break;
+        cv.wait_for(lk, std::chrono::milliseconds(1));
+        continue;
+      }
+    }
+    const double t0 = now_ms();
+    // device view of live slots: per-group counts and the total
+    std::vector<uint32_t> gact(G, 0);
+    uint32_t total = 0;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (int gi = 0; gi < G; ++gi)
+        for (int k = 0; k < K; ++k) {
+          uint64_t t = slot_ticket[gi][k];
+          if (t && q[t].state == Q_RUNNING) { gact[gi]++; total++; }
+        }
+    }
+    hipError_t e = hipMemcpyAsync(plan->args.group_active, gact.data(), 4ull * G, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && plan->set_remaining(total, stream) != SR_OK) e = hipErrorUnknown;
+    if (e == hipSuccess && plan->launch(stream) != SR_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    for (int gi = 0; gi < G && e == hipSuccess; ++gi)
+      e = hipMemcpyAsync(&ih[(size_t)gi * K], plan->groups[gi].inst, sizeof(MiInst) * K, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      std::lock_guard<std::mutex> lk(mu);
+      thread_error = SR_EDEVICE;
+      thread_msg = std::string("server sweep: ") + hipGetErrorString(e);
+      break;
+    }
+    sweeps++;
+    // retire converged slots into their result buffers
+    std::vector<std::pair<uint64_t, int>> finished;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (int gi = 0; gi < G; ++gi)
+        for (int k = 0; k < K; ++k) {
+          uint64_t t = slot_ticket[gi][k];
+          if (!t) continue;
+          const MiInst &r = ih[(size_t)gi * K + k];
+          if (r.done) finished.push_back({t, gi * K + k});
+        }
+    }
+    for (auto &f : finished) {
+      int gi = f.second / K, k = f.second % K;
+      uint32_t *dst;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        dst = q[f.first].result;
+      }
+      e = launch_mi_extract(K, plan->groups[gi].value, plan->groups[gi].n, k, dst, stream);
+      if (e != hipSuccess) break;
+    }
+    if (!finished.empty() && e == hipSuccess) e = hipStreamSynchronize(stream);
+    const double t1 = now_ms();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      busy_ms += t1 - t0;
+      for (auto &f : finished) {
+        int gi = f.second / K, k = f.second % K;
+        Query &qq = q[f.first];
+        qq.state = Q_DONE;
+        qq.t_done = t1;
+        slot_ticket[gi][k] = 0;
+        completed++;
+      }
+      if (e != hipSuccess) {
+        thread_error = SR_EDEVICE;
+        thread_msg = std::string("server retire: ") + hipGetErrorString(e);
+        break;
+      }
+    }
+  }
+}
+
+extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_t ngraphs, uint64_t state_budget,
+                                      int32_t max_slots, sr_server **out) {
+  if (!c) return SR_EINVAL;
+  if (!graphs || ngraphs < 1 || ngraphs > 8 || !out) return c->fail(SR_EINVAL, "need 1..8 graphs and out");
+  if (max_slots != 8 && max_slots != 16) return c->fail(SR_EINVAL, "max_slots_per_graph must be 8 or 16");
+  if (c->host_only) return c->fail(SR_EDEVICE, "host-only context cannot serve");
+  hipError_t he = hipSetDevice(c->device);
+  if (he != hipSuccess) return c->hip_fail(he, "set device");
+  for (int i = 0; i < ngraphs; ++i)
+    if (!graphs[i] || graphs[i]->ctx != c) return c->fail(SR_EINVAL, "graph missing or from another context");
+  sr_server *s = new sr_server();
+  s->c = c;
+  s->K = max_slots;
+  s->graphs.assign(graphs, graphs + ngraphs);
+  auto fail = [&](sr_status st) { delete s->plan; delete s; return st; };
+  sr_status st;
+  for (auto *g : s->graphs) {
+    if (g->pages.empty())
+      if ((st = sr_graph_partition(g, 1, 0)) != SR_OK) return fail(st);
+    if ((st = ensure_residency(g, g->weighted, false)) != SR_OK) return fail(st);
+    if (!g->res.resident) return fail(c->fail(SR_EBUDGET, "served graphs must fit the budget resident"));
+    if (g->server_refs > 0) return fail(c->fail(SR_EBUSY, "graph is attached to another server"));
+  }
+  // per graph: K slot columns (4 B per vertex each) plus result buffers;
+  // the state budget decides how many queries each graph runs at once
+  uint64_t col_bytes = 0, per_result = 0;
+  for (auto *g : s->graphs) { col_bytes += 4ull * g->n * s->K; per_result += 4ull * g->n; }
+  if (state_budget && col_bytes + per_result > state_budget)
+    return fail(c->fail(SR_EBUDGET, "state budget cannot hold the slot columns and one result per graph"));
+  uint64_t left = state_budget ? state_budget - col_bytes : ~0ull;
+  int R = (int)std::min<uint64_t>(s->K, left / std::max<uint64_t>(per_result, 1));
+  s->plan = new MiPlan(c, A_SSSP, s->K);
+  for (auto *g : s->graphs) {
+    int gi;
+    if ((st = s->plan->add_group(g, P_STRONG, &gi)) != SR_OK) return fail(st);
+  }
+  if ((st = s->plan->finalize(0.85, 1e-9, 1 << 30)) != SR_OK) return fail(st);
+  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->poll_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(c->fail(SR_EDEVICE, "stream creation failed"));
+  s->usable.assign(ngraphs, R);
+  s->slot_ticket.assign(ngraphs, std::vector<uint64_t>(s->K, 0));
+  s->free_results.resize(ngraphs);
+  for (int gi = 0; gi < ngraphs; ++gi) {
+    for (int r = 0; r < R; ++r) {
+      uint32_t *b = nullptr;
+      if ((st = s->plan->alloc((void **)&b, 4ull * s->graphs[gi]->n, "result buffer")) != SR_OK) return fail(st);
+      s->free_results[gi].push_back(b);
+    }
+    for (int k = 0; k < s->K; ++k)
+      if ((st = s->plan->set_column(gi, k, -1, false, false, s->stream)) != SR_OK) return fail(st);
+  }
+  // the schedule autotuner times the multi-source sweep with every column live
+  {
+    for (int gi = 0; gi < ngraphs; ++gi)
+      for (int k = 0; k < s->K; ++k)
+        if ((st = s->plan->set_column(gi, k, 0, false, true, s->stream)) != SR_OK) return fail(st);
+    std::vector<uint32_t> gact(ngraphs, (uint32_t)s->K);
+    if (hipMemcpyAsync(s->plan->args.group_active, gact.data(), 4ull * ngraphs, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+      return fail(c->fail(SR_EDEVICE, "server init"));
+    if ((st = s->plan->set_remaining((uint32_t)(ngraphs * s->K), s->stream)) != SR_OK) return fail(st);
+    char key[128];
+    uint64_t m = 0;
+    for (auto *g : s->graphs) m += (uint64_t)g->m;
+    std::snprintf(key, sizeof(key), "serve_K%d_g%d_items%d_m%llu", s->K, ngraphs, s->plan->args.total_items / 64,
+                  (unsigned long long)(m >> 20));
+    if ((st = s->plan->autotune(s->stream, key)) != SR_OK) return fail(st);
+    for (int gi = 0; gi < ngraphs; ++gi)
+      for (int k = 0; k < s->K; ++k)
+        if ((st = s->plan->set_column(gi, k, -1, false, false, s->stream)) != SR_OK) return fail(st);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(c->fail(SR_EDEVICE, "server init"));
+  }
+  for (auto *g : s->graphs) g->server_refs++;
+  s->th = std::thread([s] { s->progress(); });
+  *out = s;
+  return SR_OK;
+}
+
+extern "C" sr_status sr_server_submit(sr_server *s, int32_t graph, sr_algo algo, int32_t source, uint64_t *ticket) {
+  if (!s || !ticket) return SR_EINVAL;
+  if (graph < 0 || graph >= (int32_t)s->graphs.size()) return SR_EINVAL;
+  if (algo != SR_SSSP && algo != SR_BFS) return SR_EINVAL;
+  sr_graph *g = s->graphs[graph];
+  if (source < 0 || source >= g->n) return SR_EINVAL;
+  if (algo == SR_SSSP && !g->weighted) return SR_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return SR_ESTATE;
+  if (s->thread_error != SR_OK) return s->thread_error;
+  if (s->queue.size() >= (1u << 20)) return SR_EBUSY;
+  uint64_t t = s->next_ticket++;
+  Query qq;
+  qq.graph = graph;
+  qq.algo = algo;
+  qq.source = source;
+  qq.t_submit = now_ms();
+  s->q[t] = qq;
+  s->queue.push_back(t);
+  s->submitted++;
+  *ticket = t;
+  s->cv.notify_one();
+  return SR_OK;
+}
+
+extern "C" sr_status sr_server_poll(sr_server *s, uint64_t ticket, void *dst, uint64_t bytes, int *done,
+                                    double *latency_ms) {
+  if (!s || !done) return SR_EINVAL;
+  uint32_t *res = nullptr;
+  int32_t n = 0, gi = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->q.find(ticket);
+    if (it == s->q.end()) return SR_EINVAL;
+    if (s->thread_error != SR_OK && it->second.state != Q_DONE) return s->thread_error;
+    if (it->second.state != Q_DONE) { *done = 0; return SR_OK; }
+    gi = it->second.graph;
+    n = s->graphs[gi]->n;
+    if (dst && bytes < 4ull * n) return SR_EINVAL;
+    it->second.state = Q_READING;
+    res = it->second.result;
+    if (latency_ms) *latency_ms = it->second.t_done - it->second.t_submit;
+  }
+  hipError_t e = hipSuccess;
+  if (dst) {
+    (void)hipSetDevice(s->c->device);
+    e = hipMemcpyAsync(dst, res, 4ull * n, hipMemcpyDeviceToHost, s->poll_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->poll_stream);
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->free_results[gi].push_back(res);
+  s->q.erase(ticket);
+  s->cv.notify_one();
+  if (e != hipSuccess) return SR_EDEVICE;
+  *done = 1;
+  return SR_OK;
+}
+
+extern "C" sr_status sr_server_stats_get(sr_server *s, sr_server_stats *o) {
+  if (!s || !o) return SR_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->submitted = s->submitted;
+  o->completed = s->completed;
+  o->sweeps = s->sweeps;
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (size_t i = 0; i < s->usable.size() && i < 8; ++i) o->slots_per_graph[i] = s->usable[i];
+  o->busy_ms = s->busy_ms;
+  return SR_OK;
+}
+
+extern "C" sr_status sr_server_destroy(sr_server *s) {
+  if (!s) return SR_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->queue.clear();  // not yet admitted: dropped
+    s->cv.notify_all();
+  }
+  if (s->th.joinable()) s->th.join();
+  (void)hipSetDevice(s->c->device);
+  (void)hipDeviceSynchronize();
+  sr_status st = s->thread_error;
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->poll_stream) (void)hipStreamDestroy(s->poll_stream);
+  delete s->plan;
+  for (auto *g : s->graphs) g->server_refs--;
+  delete s;
+  return st;
+}

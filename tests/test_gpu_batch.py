@@ -1,0 +1,85 @@
+"""Batched multi-instance runs through sr_batch_run: every instance equals
+its oracle (PPR within 1e-6 max-abs, SSSP/BFS bit-exact) and its solo run."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sr():
+    import paper_1806_00762_amd as sr
+    sr.lib()
+    return sr
+
+
+@pytest.fixture(scope="module")
+def ctx(sr):
+    c = sr.Context(0, 0)
+    yield c
+    c.close()
+
+
+def test_batched_ppr_uneven_graphs(sr, ctx):
+    graphs = [graphgen.rmat(s, ef, seed=500 + s) for s, ef in ((10, 8), (12, 16), (13, 32), (11, 8))]
+    Gs = [ctx.load(g) for g in graphs]
+    insts = []
+    for gi, g in enumerate(graphs):
+        # 11 instances on some graphs: one full group of 8 and a partial group
+        k = 11 if gi % 2 == 0 else 5
+        for s in graphgen.sources_with_outedges(g, k, seed=2000 + gi):
+            insts.append((gi, int(s)))
+    say(f"case batched ppr {len(insts)} instances over {len(graphs)} graphs")
+    outs, per, bs = sr.batch_run(ctx, [(Gs[gi], "ppr", s) for gi, s in insts])
+    say(f"  batch stats {bs}")
+    worst = 0.0
+    for (gi, s), x, st in zip(insts, outs, per):
+        ref, _, _ = oracle.pagerank(graphs[gi], seed=s, tol=1e-13)
+        err = float(np.max(np.abs(x.view(np.float32).astype(np.float64) - ref)))
+        worst = max(worst, err)
+        assert st["converged"] == 1
+        assert err <= 1e-6, (gi, s, err)
+    say(f"  worst max-abs {worst:.3e}")
+    for G in Gs:
+        G.close()
+
+
+def test_batched_sssp_bfs_mix_matches_oracle_and_solo(sr, ctx):
+    graphs = [graphgen.rmat(12, 16, seed=61, weights=(1, 255, 62)), graphgen.rmat(14, 8, seed=63, weights=(1, 255, 64))]
+    Gs = [ctx.load(g) for g in graphs]
+    insts = []
+    for gi, g in enumerate(graphs):
+        for j, s in enumerate(graphgen.sources_with_outedges(g, 10, seed=3000 + gi)):
+            insts.append((gi, "sssp" if j % 2 == 0 else "bfs", int(s)))
+    say(f"case batched sssp/bfs {len(insts)}")
+    outs, per, bs = sr.batch_run(ctx, [(Gs[gi], a, s) for gi, a, s in insts])
+    for (gi, a, s), x, st in zip(insts, outs, per):
+        ref = oracle.sssp(graphs[gi], s) if a == "sssp" else oracle.bfs(graphs[gi], s)
+        assert np.array_equal(x, ref), (gi, a, s, int(np.sum(x != ref)))
+    # solo runs agree bit-for-bit
+    for gi, a, s in insts[:4]:
+        Gs[gi].run(a, source=s)
+        assert np.array_equal(Gs[gi].values(), outs[insts.index((gi, a, s))])
+    for G in Gs:
+        G.close()
+
+
+def test_batched_pvu_off_equals_strong(sr, ctx):
+    g = graphgen.rmat(12, 16, seed=71, weights=(1, 255, 72))
+    G = ctx.load(g)
+    srcs = [int(s) for s in graphgen.sources_with_outedges(g, 8, seed=9)]
+    a, _, _ = sr.batch_run(ctx, [(G, "sssp", s) for s in srcs], pvu="off")
+    b, _, _ = sr.batch_run(ctx, [(G, "sssp", s) for s in srcs], pvu="strong")
+    for x, y, s in zip(a, b, srcs):
+        assert np.array_equal(x, y)
+        assert np.array_equal(x, oracle.sssp(g, s))
+    G.close()

@@ -1,0 +1,97 @@
+"""Continuous-batching query server: queries admitted while others run give
+exactly the result they give alone (solo sr_run) and the oracle's."""
+import time
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sr():
+    import paper_1806_00762_amd as sr
+    sr.lib()
+    return sr
+
+
+def wait_all(srv, tickets, outs, timeout=60.0):
+    lat = {}
+    t0 = time.time()
+    pending = set(tickets)
+    while pending and time.time() - t0 < timeout:
+        for t in list(pending):
+            done, l = srv.poll(t, outs[t])
+            if done:
+                lat[t] = l
+                pending.discard(t)
+        time.sleep(0.0005)
+    assert not pending, f"{len(pending)} queries not done"
+    return lat
+
+
+@pytest.mark.parametrize("slots", [8, 16])
+def test_server_alone_vs_mix(sr, slots):
+    graphs = [graphgen.rmat(12, 16, seed=81, weights=(1, 255, 82)),
+              graphgen.rmat(14, 8, seed=83, weights=(1, 255, 84))]
+    ctx = sr.Context(0, 0)
+    Gs = [ctx.load(g) for g in graphs]
+    srv = sr.Server(ctx, Gs, state_budget_bytes=0, slots=slots)
+    say(f"case server slots={slots} stats {srv.stats()}")
+    reqs = []
+    r = np.random.default_rng(slots)
+    for i in range(60):
+        gi = int(r.integers(0, 2))
+        algo = "sssp" if r.random() < 0.5 else "bfs"
+        src = int(graphgen.sources_with_outedges(graphs[gi], 1, seed=100 + i)[0])
+        reqs.append((gi, algo, src))
+    tickets, outs = [], {}
+    # first wave, then a second wave submitted while the first is running
+    for k, (gi, algo, src) in enumerate(reqs):
+        t = srv.submit(gi, algo, src)
+        tickets.append(t)
+        outs[t] = np.empty(graphs[gi].n, dtype=np.uint32)
+        if k == 30:
+            time.sleep(0.002)
+    lat = wait_all(srv, tickets, outs)
+    st = srv.stats()
+    say(f"  stats {st}; p50 {np.percentile(list(lat.values()), 50):.2f} ms")
+    assert st["completed"] == len(reqs)
+    for t, (gi, algo, src) in zip(tickets, reqs):
+        ref = oracle.sssp(graphs[gi], src) if algo == "sssp" else oracle.bfs(graphs[gi], src)
+        assert np.array_equal(outs[t], ref), (gi, algo, src)
+    srv.close()
+    # alone: the same queries through sr_run one at a time
+    for t, (gi, algo, src) in list(zip(tickets, reqs))[:10]:
+        Gs[gi].run(algo, source=src)
+        assert np.array_equal(Gs[gi].values(), outs[t])
+    for G in Gs:
+        G.close()
+    ctx.close()
+
+
+def test_server_rejects_bad_requests(sr):
+    g = graphgen.rmat(10, 8, seed=5)  # unweighted: SSSP refused, BFS fine
+    ctx = sr.Context(0, 0)
+    G = ctx.load(g)
+    srv = sr.Server(ctx, [G], slots=8)
+    with pytest.raises(sr.SeraphError):
+        srv.submit(0, "sssp", 0)
+    with pytest.raises(sr.SeraphError):
+        srv.submit(1, "bfs", 0)
+    with pytest.raises(sr.SeraphError):
+        srv.submit(0, "bfs", g.n)
+    t = srv.submit(0, "bfs", 0)
+    out = np.empty(g.n, dtype=np.uint32)
+    lat = wait_all(srv, [t], {t: out})
+    assert np.array_equal(out, oracle.bfs(g, 0))
+    srv.close()
+    G.close()
+    ctx.close()
