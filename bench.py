@@ -107,6 +107,20 @@ def bench_sssp22(args):
         "passes_per_solve": stats[-1]["passes"],
         "sweeps_per_solve": stats[-1]["sweeps"],
     }
+    other = "weak" if args.pvu == "strong" else "strong"
+    okw = dict(run_kw, pvu=other)
+    G.run("sssp", **okw)
+    sync()
+    t0 = time.perf_counter()
+    ost = [G.run("sssp", **okw) for _ in range(args.steps)]
+    sync()
+    oel = time.perf_counter() - t0
+    assert np.array_equal(G.values(), dist)
+    res["pvu_" + other] = {"solve_gteps": round(g.m * args.steps / oel / 1e9, 4),
+                           "ms_per_solve": round(oel * 1e3 / args.steps, 3),
+                           "passes_per_solve": ost[-1]["passes"],
+                           "h2d_bytes_per_solve": ost[-1]["h2d_bytes"],
+                           "sweep_GBps": round(sum(s["algo_bytes"] for s in ost) / (sum(s["kernel_ms"] for s in ost) * 1e-3) / 1e9, 1)}
     if args.resident:
         ctx2 = sr.Context(0, 0)
         G2 = ctx2.load(g)
@@ -141,6 +155,170 @@ def bench_sssp22(args):
     return res
 
 
+def bench_batched(args):
+    """256 personalized-PageRank instances over 32 R-MAT graphs (scales 12-20,
+    edge factor 8/16/32), 8 seeds per graph: one batched call vs a loop of
+    single-instance solves on the same GPU."""
+    import graphgen
+    import oracle
+    import paper_1806_00762_amd as sr
+    t = time.perf_counter()
+    graphs = [graphgen.recipes.batched_graph(i) for i in range(32)]
+    log(f"[bench] batched: generated 32 graphs, m total {sum(g.m for g in graphs)} in {time.perf_counter() - t:.1f}s")
+    ctx = sr.Context(0, 0)
+    Gs = [ctx.load(g) for g in graphs]
+    for G in Gs:
+        G.partition(1, 4)
+    insts = []
+    for gi, g in enumerate(graphs):
+        for s in graphgen.sources_with_outedges(g, 8, seed=2000 + gi):
+            insts.append((gi, int(s)))
+    sr.batch_run(ctx, [(Gs[gi], "ppr", s) for gi, s in insts])   # warm-up and autotune
+    sync()
+    t0 = time.perf_counter()
+    outs, per, bs = sr.batch_run(ctx, [(Gs[gi], "ppr", s) for gi, s in insts])
+    sync()
+    tb = time.perf_counter() - t0
+    # plain: the same instances one solve at a time through sr_run
+    # (a strided sample, so every graph size is represented)
+    stride = max(1, len(insts) // args.plain_sample)
+    sample = insts[::stride]
+    nplain = len(sample)
+    Gs[insts[0][0]].run("ppr", source=insts[0][1], pvu="off", max_inner_iters=1)
+    sync()
+    t0 = time.perf_counter()
+    for gi, s in sample:
+        Gs[gi].run("ppr", source=s, pvu="off", max_inner_iters=1)
+    sync()
+    tp = (time.perf_counter() - t0) / nplain
+    # accuracy: certified bound ||x - x*||_1 <= ||T(x) - x||_1 / (1-d) for every instance,
+    # exact max-abs against the FP64 oracle for the instances on graphs of scale <= 16
+    bound_max, exact_max, nexact = 0.0, 0.0, 0
+    for (gi, s), x in zip(insts, outs):
+        xf = x.view(np.float32).astype(np.float64)
+        res = oracle.pagerank_residual(graphs[gi], xf, seed=s)
+        bound_max = max(bound_max, res / 0.15)
+        if graphs[gi].n <= 1 << 16:
+            ref, _, _ = oracle.pagerank(graphs[gi], seed=s, tol=1e-13)
+            exact_max = max(exact_max, float(np.max(np.abs(xf - ref))))
+            nexact += 1
+    for G in Gs:
+        G.close()
+    ctx.close()
+    return {"workload": "ppr256_over_32_rmat_s12-20_ef8-32", "instances": len(insts),
+            "solves_per_s": round(len(insts) / tb, 1), "batched_ms": round(tb * 1e3, 2),
+            "plain_solves_per_s": round(1.0 / tp, 1), "plain_sample": nplain,
+            "speedup_vs_plain": round(tp * len(insts) / tb, 2),
+            "sweeps": bs["sweeps"], "grid_blocks": bs["grid_blocks"], "grab": bs["grab"],
+            "sweep_GBps": round(bs["algo_bytes"] / (bs["kernel_ms"] * 1e-3) / 1e9, 1) if bs["kernel_ms"] else None,
+            "max_abs_exact": exact_max, "max_abs_exact_instances": nexact,
+            "max_abs_certified_bound": bound_max, "dtype": "f32"}
+
+
+def bench_served(args):
+    """Poisson stream of SSSP/BFS queries over 3 resident R-MAT graphs (scales
+    20, 22, 23; ef 16; weights [1, 255]) through the continuous-batching
+    server, vs solo solves of the same queries."""
+    import threading
+    import graphgen
+    import oracle
+    import paper_1806_00762_amd as sr
+    t = time.perf_counter()
+    graphs = [graphgen.recipes.serving_graph(s) for s in (20, 22, 23)]
+    log(f"[bench] served: generated graphs in {time.perf_counter() - t:.1f}s")
+    ctx = sr.Context(0, 0)
+    Gs = [ctx.load(g) for g in graphs]
+    for G in Gs:
+        G.partition(1, 4)
+    nreq = args.requests
+    arr = graphgen.poisson_arrivals(args.rate, nreq, seed=4000)
+    pick = graphgen.bounded_draws(4001, 1, nreq, 0, 2)
+    kind = graphgen.bounded_draws(4002, 1, nreq, 0, 1)
+    srcs = [graphgen.sources_with_outedges(graphs[gi], nreq, seed=4003 + gi) for gi in range(3)]
+    reqs = [(int(pick[i]), "sssp" if kind[i] == 0 else "bfs", int(srcs[int(pick[i])][i])) for i in range(nreq)]
+    srv = sr.Server(ctx, Gs, state_budget_bytes=0, slots=args.serve_slots)
+    tickets = [None] * nreq
+    t0 = time.perf_counter()
+
+    def producer():
+        for i, (gi, algo, s) in enumerate(reqs):
+            delay = arr[i] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = srv.submit(gi, algo, s)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    check = set(range(0, nreq, max(1, nreq // 12)))
+    outs = {i: np.empty(graphs[reqs[i][0]].n, dtype=np.uint32) for i in check}
+    lat = [None] * nreq
+    pending = set(range(nreq))
+    while pending:
+        for i in list(pending):
+            if tickets[i] is None:
+                continue
+            done, l = srv.poll(tickets[i], outs.get(i))
+            if done:
+                lat[i] = l
+                pending.discard(i)
+        time.sleep(0.0002)
+        if time.perf_counter() - t0 > args.served_timeout:
+            break
+    th.join()
+    elapsed = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    ok = 0
+    for i in check:
+        gi, algo, s = reqs[i]
+        if lat[i] is None:
+            continue
+        ref = oracle.sssp(graphs[gi], s) if algo == "sssp" else oracle.bfs(graphs[gi], s)
+        ok += int(np.array_equal(outs[i], ref))
+    # plain: the same kind of queries solved one at a time
+    nplain = args.plain_sample
+    Gs[0].run("sssp", source=reqs[0][2] if reqs[0][0] == 0 else 0)
+    sync()
+    tp0 = time.perf_counter()
+    for gi, algo, s in reqs[:nplain]:
+        Gs[gi].run(algo, source=s)
+    sync()
+    tp = (time.perf_counter() - tp0) / nplain
+    for G in Gs:
+        G.close()
+    ctx.close()
+    done_lat = np.array([x for x in lat if x is not None])
+    return {"workload": "poisson2000_sssp_bfs_rmat20_22_23_ef16", "requests": nreq,
+            "completed": int(done_lat.size), "offered_qps": args.rate,
+            "achieved_qps": round(done_lat.size / elapsed, 1),
+            "p50_ms": round(float(np.percentile(done_lat, 50)), 2) if done_lat.size else None,
+            "p99_ms": round(float(np.percentile(done_lat, 99)), 2) if done_lat.size else None,
+            "plain_solves_per_s": round(1.0 / tp, 1), "plain_sample": nplain,
+            "sweeps": st["sweeps"], "slots_per_graph": st["slots_per_graph"],
+            "checked_vs_oracle": f"{ok}/{len(check)} bit-exact"}
+
+
+def copy_calibration():
+    """A plain streaming kernel of known size: out = in * 1 over 2^28 float32
+    (1 GiB read + 1 GiB written per launch), 5 launches. Its HBM counters
+    scale the sweep's counters to bytes; its rate is the measured copy peak."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    return {"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 6,
+            "ms_per_launch": round(ms, 4), "copy_GBps": round(8 * n / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,9 +326,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--inner", type=int, default=8)
-    ap.add_argument("--pvu", default="weak")
+    ap.add_argument("--pvu", default="strong",
+                    help="predictor of the timed solves (the other one is reported beside it)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--resident", action="store_true", help="also time the resident solve")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and served legs")
+    ap.add_argument("--plain-sample", type=int, default=32)
+    ap.add_argument("--requests", type=int, default=20000)
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain copy kernel of known size (for HBM counter scaling)")
+    ap.add_argument("--served-timeout", type=float, default=90.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this engine runs a single device "
@@ -158,7 +345,15 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.init()
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration()), flush=True)
+        return
     res = bench_sssp22(args)
+    if not args.no_extras:
+        res["batched"] = bench_batched(args)
+        log(f"[bench] batched: {res['batched']}")
+        res["served"] = bench_served(args)
+        log(f"[bench] served: {res['served']}")
     print(json.dumps(res), flush=True)
 
 

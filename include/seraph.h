@@ -59,6 +59,8 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
 
 /* sr_graph_load_csr flags */
 #define SR_LOAD_SYMMETRIZE 0x1u  /* build in-edges of the undirected graph (needed for CC) */
+#define SR_LOAD_SYMMETRIC 0x2u   /* the input is already symmetric with sorted rows: in-edges =
+                                    out-edges; verified (SR_EINVAL if not), marks the graph undirected */
 
 /* sr_run_params.flags */
 #define SR_RUN_AUDIT_PVU 0x1u     /* also evaluate skipped vertices; count would-be changes
@@ -136,14 +138,18 @@ sr_status sr_graph_info_get(const sr_graph *g, sr_graph_info *out);
 
 /* Read-only view of page `page` (host pointers into the graph's pinned
  * pages; valid until the graph is repartitioned or destroyed). offsets are
- * rebased to 0 (n_p + 1 entries); src holds global source vertex ids. */
+ * rebased to 0 (n_p + 1 entries); src holds global source vertex ids.
+ * Weights are stored as uint8 when every weight of the graph is below 256
+ * (lossless; fewer bytes to stream), else as uint32. */
 typedef struct {
   int32_t v_begin, v_end;    /* destination vertex range [v_begin, v_end) */
   int64_t num_edges;
   const int32_t *offsets;
   const int32_t *src;
-  const uint32_t *weights;   /* NULL if unweighted */
+  const void *weights;       /* NULL if unweighted */
+  int32_t weight_bytes;      /* 1 or 4 (0 if unweighted) */
   uint64_t bytes;            /* bytes of the page buffer */
+  uint64_t stream_bytes;     /* prefix a single-instance sweep copies (with weights) */
 } sr_page_view;
 sr_status sr_graph_page(const sr_graph *g, int32_t page, sr_page_view *out);
 void sr_graph_destroy(sr_graph *g);

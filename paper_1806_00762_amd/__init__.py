@@ -24,6 +24,7 @@ SR_OK, SR_EINVAL, SR_ENOMEM, SR_EBUDGET, SR_EDEVICE, SR_ENOTCONV, SR_ESTATE, SR_
 SR_BFS, SR_SSSP, SR_CC, SR_PAGERANK, SR_PPR = 0, 1, 2, 3, 4
 SR_PVU_OFF, SR_PVU_STRONG, SR_PVU_WEAK, SR_PVU_DEFAULT = 0, 1, 2, 3
 SR_LOAD_SYMMETRIZE = 0x1
+SR_LOAD_SYMMETRIC = 0x2
 SR_RUN_AUDIT_PVU, SR_RUN_FORCE_STREAM, SR_RUN_RESUME = 0x1, 0x2, 0x4
 SR_STOP_CONVERGED, SR_STOP_FP32_FLOOR, SR_STOP_MAX_PASSES = 1, 2, 3
 SR_INF = 0xFFFFFFFF
@@ -46,7 +47,8 @@ class sr_graph_info(ctypes.Structure):
 class sr_page_view(ctypes.Structure):
     _fields_ = [("v_begin", ctypes.c_int32), ("v_end", ctypes.c_int32), ("num_edges", ctypes.c_int64),
                 ("offsets", ctypes.POINTER(ctypes.c_int32)), ("src", ctypes.POINTER(ctypes.c_int32)),
-                ("weights", ctypes.POINTER(ctypes.c_uint32)), ("bytes", ctypes.c_uint64)]
+                ("weights", ctypes.c_void_p), ("weight_bytes", ctypes.c_int32), ("bytes", ctypes.c_uint64),
+                ("stream_bytes", ctypes.c_uint64)]
 
 
 class sr_pvu_diagram(ctypes.Structure):
@@ -207,14 +209,14 @@ class Context:
         _check(lib().sr_ctx_memory(self.h, ctypes.byref(u), ctypes.byref(b)), self.h)
         return u.value, b.value
 
-    def load(self, g, symmetrize: bool = False, weights: Optional[bool] = None) -> "Graph":
-        return Graph(self, g, symmetrize=symmetrize, weights=weights)
+    def load(self, g, symmetrize: bool = False, weights: Optional[bool] = None, symmetric: bool = False) -> "Graph":
+        return Graph(self, g, symmetrize=symmetrize, weights=weights, symmetric=symmetric)
 
 
 class Graph:
     """A graph loaded into a context (C handle sr_graph)."""
 
-    def __init__(self, ctx: Context, g, symmetrize=False, weights=None):
+    def __init__(self, ctx: Context, g, symmetrize=False, weights=None, symmetric=False):
         self.ctx = ctx
         off = np.ascontiguousarray(g.offsets, dtype=np.int64)
         col = np.ascontiguousarray(g.col, dtype=np.int32)
@@ -226,7 +228,8 @@ class Graph:
         h = _P()
         rc = lib().sr_graph_load_csr(ctx.h, int(g.n), int(off[-1]), off.ctypes.data, col.ctypes.data,
                                      None if w is None else w.ctypes.data,
-                                     SR_LOAD_SYMMETRIZE if symmetrize else 0, ctypes.byref(h))
+                                     (SR_LOAD_SYMMETRIZE if symmetrize else 0) | (SR_LOAD_SYMMETRIC if symmetric else 0),
+                                     ctypes.byref(h))
         _check(rc, ctx.h)
         self.h = h
         self.n = int(g.n)
@@ -252,10 +255,11 @@ class Graph:
         ne = int(v.num_edges)
         src = np.ctypeslib.as_array(v.src, shape=(ne,)).copy() if ne else np.zeros(0, np.int32)
         w = None
-        if bool(v.weights) and ne:
-            w = np.ctypeslib.as_array(v.weights, shape=(ne,)).copy()
+        if v.weights and ne:
+            ct = ctypes.c_uint8 if v.weight_bytes == 1 else ctypes.c_uint32
+            w = np.ctypeslib.as_array(ctypes.cast(v.weights, ctypes.POINTER(ct)), shape=(ne,)).astype(np.uint32)
         return {"v_begin": v.v_begin, "v_end": v.v_end, "offsets": off, "src": src, "weights": w,
-                "bytes": int(v.bytes)}
+                "weight_bytes": v.weight_bytes, "bytes": int(v.bytes), "stream_bytes": int(v.stream_bytes)}
 
     def run(self, algo, source: int = 0, pvu="default", damping: float = 0.85, tol_l1: float = 1e-9,
             max_passes: int = 0, max_inner_iters: int = 0, diagram: Optional[sr_pvu_diagram] = None,

@@ -5,9 +5,11 @@
 // in-edge source (one broadcast load) and gather the K contiguous values of
 // that neighbour (one 4K-byte access), so every index and weight read is
 // shared by K instances. Blocks take work items from a device queue until
-// it is empty; the last block to finish closes the sweep for every instance
-// (convergence, thresholds, PageRank dangling mass) so the launch can be
-// replayed from a captured graph with no host work in between.
+// it is empty and accumulate per-instance counters in LDS, flushed once per
+// block; a one-block close kernel then combines the heavy-vertex chunks and
+// closes the sweep for every instance (convergence, thresholds, PageRank
+// dangling mass). The pair is replayed from a captured graph with no host
+// work in between; no fence is executed inside the sweep.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -15,22 +17,13 @@
 #include "batch.hpp"
 
 namespace sr {
-namespace {
 
+namespace {
 constexpr int MI_ROUNDS = 4;
+constexpr int MI_CLOSE_THREADS = 1024;
 
 template <typename T>
 __device__ inline T shfl_xor(T v, int m) { return __shfl_xor(v, m, 64); }
-
-template <typename T>
-__device__ inline T ld_agent(const T *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ inline void st_agent(T *p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 }  // namespace
 
 // vertices (bins 0..6, 8) or chunks (bin 7) per work item of the multi-
@@ -56,6 +49,16 @@ struct Lane {
   int32_t source;
   float dangling;
 };
+
+__device__ inline Lane lane_of(const MiInst &in) {
+  Lane ln;
+  ln.active = in.active;
+  ln.unit = in.unit;
+  ln.threshold = in.threshold;
+  ln.source = in.source;
+  ln.dangling = (float)in.dangling;
+  return ln;
+}
 
 template <int ALGO, int K>
 struct MiRed {
@@ -88,6 +91,34 @@ struct MiAcc {
   uint32_t changed = 0, min_changed = INF, edges = 0;
   double l1 = 0.0, ddelta = 0.0;
 };
+
+// Per-instance counters of one block, in LDS (instance i = group * K + k).
+struct MiLds {
+  uint32_t changed, min_changed, edges, pad;
+  double l1, ddelta;
+};
+
+__device__ inline void lds_clear(MiLds *lds, int n, int nthreads) {
+  for (int i = threadIdx.x; i < n; i += nthreads) {
+    lds[i].changed = 0;
+    lds[i].min_changed = INF;
+    lds[i].edges = 0;
+    lds[i].pad = 0;
+    lds[i].l1 = 0.0;
+    lds[i].ddelta = 0.0;
+  }
+}
+
+template <int ALGO>
+__device__ inline void lds_add(MiLds &e, const MiAcc &acc) {
+  if (acc.changed) atomicAdd(&e.changed, acc.changed);
+  if (acc.min_changed != INF) atomicMin(&e.min_changed, acc.min_changed);
+  if (acc.edges) atomicAdd(&e.edges, acc.edges);
+  if constexpr (mi_pr<ALGO>()) {
+    if (acc.l1 != 0.0) atomicAdd(&e.l1, acc.l1);
+    if (acc.ddelta != 0.0) atomicAdd(&e.ddelta, acc.ddelta);
+  }
+}
 
 template <int ALGO, int K>
 __device__ inline bool mi_attempt(const MiGroup &g, int32_t v, int k, const Lane &ln, uint32_t &old) {
@@ -126,9 +157,9 @@ __device__ inline void mi_epilogue(const MiGroup &g, int32_t v, int k, const Lan
 }
 
 // lanes with the same instance k reduce over the 64/K edge lanes; lanes
-// 0..K-1 then publish the per-instance totals
+// 0..K-1 add the per-instance totals to the block's LDS counters
 template <int ALGO, int K>
-__device__ inline void mi_flush(const MiGroup &g, MiAcc &acc) {
+__device__ inline void mi_flush(MiLds *lds, int group, MiAcc &acc) {
   const int lane = threadIdx.x % 64;
 #pragma unroll
   for (int m = K; m < 64; m <<= 1) {
@@ -140,16 +171,7 @@ __device__ inline void mi_flush(const MiGroup &g, MiAcc &acc) {
       acc.ddelta += shfl_xor(acc.ddelta, m);
     }
   }
-  if (lane < K) {
-    MiInst &in = g.inst[lane];
-    if (acc.changed) atomicAdd(&in.sw_changed, acc.changed);
-    if (acc.min_changed != INF) atomicMin(&in.sw_min_changed, acc.min_changed);
-    if (acc.edges) atomicAdd(&in.sw_edges, (unsigned long long)acc.edges);
-    if constexpr (mi_pr<ALGO>()) {
-      if (acc.l1 != 0.0) atomicAdd(&in.sw_l1, acc.l1);
-      if (acc.ddelta != 0.0) atomicAdd(&in.sw_ddelta, acc.ddelta);
-    }
-  }
+  if (lane < K) lds_add<ALGO>(lds[group * K + lane], acc);
   acc = MiAcc();
 }
 
@@ -190,7 +212,7 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
     if (att[r]) {
       for (int e = beg[r] + ein; e < end[r]; e += GE) {
         int32_t u = src[e];
-        uint32_t w = (ALGO == A_SSSP && g.has_w) ? wt[e] : 1u;
+        uint32_t w = (ALGO == A_SSSP && g.has_w) ? (g.w8 ? (uint32_t)reinterpret_cast<const uint8_t *>(wt)[e] : wt[e]) : 1u;
         x = R::combine(x, R::edge(g, u, w, k, ln));
       }
     }
@@ -201,7 +223,7 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
   }
 }
 
-// bin 6 (wave per vertex) and bin 7 (wave per chunk) share the edge loop
+// edge loop of bins 6 and 7: 64/K edge lanes, 4 edges in flight per lane
 template <int ALGO, int K>
 __device__ inline typename MiRed<ALGO, K>::T mi_edges(const MiGroup &g, const int32_t *src, const uint32_t *wt,
                                                       int32_t e0, int32_t e1, int k, int el, const Lane &ln) {
@@ -213,17 +235,29 @@ __device__ inline typename MiRed<ALGO, K>::T mi_edges(const MiGroup &g, const in
   for (; e + 3 * EL < e1; e += 4 * EL) {
     int32_t u0 = src[e], u1 = src[e + EL], u2 = src[e + 2 * EL], u3 = src[e + 3 * EL];
     uint32_t w0 = 1, w1 = 1, w2 = 1, w3 = 1;
-    if (ALGO == A_SSSP && g.has_w) { w0 = wt[e]; w1 = wt[e + EL]; w2 = wt[e + 2 * EL]; w3 = wt[e + 3 * EL]; }
+    if (ALGO == A_SSSP && g.has_w) {
+      if (g.w8) {
+        const uint8_t *w8 = reinterpret_cast<const uint8_t *>(wt);
+        w0 = w8[e]; w1 = w8[e + EL]; w2 = w8[e + 2 * EL]; w3 = w8[e + 3 * EL];
+      } else {
+        w0 = wt[e]; w1 = wt[e + EL]; w2 = wt[e + 2 * EL]; w3 = wt[e + 3 * EL];
+      }
+    }
     T y0 = R::edge(g, u0, w0, k, ln), y1 = R::edge(g, u1, w1, k, ln);
     T y2 = R::edge(g, u2, w2, k, ln), y3 = R::edge(g, u3, w3, k, ln);
     x = R::combine(x, R::combine(R::combine(y0, y1), R::combine(y2, y3)));
   }
-  for (; e < e1; e += EL) x = R::combine(x, R::edge(g, src[e], (ALGO == A_SSSP && g.has_w) ? wt[e] : 1u, k, ln));
+  for (; e < e1; e += EL) {
+    uint32_t w = 1u;
+    if (ALGO == A_SSSP && g.has_w) w = g.w8 ? (uint32_t)reinterpret_cast<const uint8_t *>(wt)[e] : wt[e];
+    x = R::combine(x, R::edge(g, src[e], w, k, ln));
+  }
 #pragma unroll
   for (int m = K; m < 64; m <<= 1) x = R::combine(x, shfl_xor(x, m));
   return x;
 }
 
+// bin 6: one wavefront per vertex
 template <int ALGO, int K>
 __device__ void mi_wave(const MiGroup &g, const char *base, const PageHeader *h, int item, const Lane &ln,
                         float damping, MiAcc &acc) {
@@ -237,48 +271,33 @@ __device__ void mi_wave(const MiGroup &g, const char *base, const PageHeader *h,
   const int32_t v = h->v_begin + vl;
   uint32_t old;
   bool att = mi_attempt<ALGO, K>(g, v, k, ln, old);
-  // lanes of inactive instances still help with the shared index loads
-  bool any = __any(att);
-  if (!any) return;
+  if (!__any(att)) return;  // lanes of other instances still share the index loads
   auto x = mi_edges<ALGO, K>(g, src, wt, off[vl], off[vl + 1], k, el, ln);
   if (att && el == 0) mi_epilogue<ALGO, K>(g, v, k, ln, old, x, (uint32_t)(off[vl + 1] - off[vl]), damping, acc);
 }
 
+// bin 7: one wavefront per chunk; the partial of each instance column is a
+// plain store, combined by the close kernel after the sweep
 template <int ALGO, int K>
 __device__ void mi_chunk(const MiGroup &g, const MiUnit &u, const char *base, const PageHeader *h, int item,
-                         const Lane &ln, float damping, MiAcc &acc) {
+                         const Lane &ln) {
   using R = MiRed<ALGO, K>;
   using T = typename R::T;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, k = lane % K, el = lane / K;
   int idx = item * WAVES + wave;
   if (idx >= h->bin_count[BIN_CHUNK]) return;
   const Chunk c = reinterpret_cast<const Chunk *>(base + h->off_chunks)[idx];
-  const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
   const int32_t *src = reinterpret_cast<const int32_t *>(base + h->off_src);
   const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
   const int32_t v = h->v_begin + c.vl;
-  const int first = (int)((uint32_t)c.first_count & 0xFFFFFu), count = (int)((uint32_t)c.first_count >> 20);
   uint32_t old;
   bool att = mi_attempt<ALGO, K>(g, v, k, ln, old);
   T x = R::identity();
   if (__any(att)) x = mi_edges<ALGO, K>(g, src, wt, c.e_begin, c.e_end, k, el, ln);
-  // every chunk arrives (also when no instance attempts) so the counter of
-  // the vertex always returns to zero
-  if (el == 0) st_agent(&u.partial[(size_t)idx * K + k], R::bits(x));
-  __threadfence();
-  uint32_t ticket = 0;
-  if (lane == 0) ticket = atomicAdd(&u.arrive[first], 1u);
-  ticket = __shfl(ticket, 0, 64);
-  if (ticket != (uint32_t)(count - 1)) return;
-  __threadfence();
-  if (el == 0) {
-    T tot = R::identity();
-    for (int j = 0; j < count; ++j) tot = R::combine(tot, R::from_bits(ld_agent(&u.partial[(size_t)(first + j) * K + k])));
-    if (att) mi_epilogue<ALGO, K>(g, v, k, ln, old, tot, (uint32_t)(off[c.vl + 1] - off[c.vl]), damping, acc);
-  }
-  if (lane == 0) st_agent(&u.arrive[first], 0u);
+  if (el == 0) u.partial[(size_t)idx * K + k] = R::bits(x);
 }
 
+// bin 8 (PPR only): zero in-degree, the value still follows the teleport term
 template <int ALGO, int K>
 __device__ void mi_zero(const MiGroup &g, const char *base, const PageHeader *h, int item, const Lane &ln,
                         float damping, MiAcc &acc) {
@@ -295,21 +314,121 @@ __device__ void mi_zero(const MiGroup &g, const char *base, const PageHeader *h,
   }
 }
 
-// close the sweep for every instance: convergence, thresholds, dangling mass
 template <int ALGO, int K>
-__device__ void mi_close(const MiArgs &a) {
-  __shared__ uint32_t s_rem;
-  if (threadIdx.x == 0) s_rem = 0;
-  for (int gi = threadIdx.x; gi < a.ngroups; gi += BLOCK) st_agent(&a.group_active[gi], 0u);
+__global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
+  if (a.ctl->remaining == 0 && !a.tuning) return;  // everything converged: replays are no-ops
+  extern __shared__ MiLds lds[];
+  __shared__ int32_t s_base;
+  const int ninst = a.ngroups * K;
+  lds_clear(lds, ninst, BLOCK);
+  const int lane = threadIdx.x % 64, k = lane % K;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_base = (int32_t)atomicAdd(&a.ctl->queue, (uint32_t)a.grab);
+    __syncthreads();
+    const int32_t base = s_base;
+    if (base >= a.total_items) break;
+    const int32_t end = min(base + a.grab, a.total_items);
+    for (int32_t it = base; it < end; ++it) {
+      int lo = 0, hi = a.nunits;  // unit_prefix[lo] <= it < unit_prefix[hi]
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (a.unit_prefix[mid] <= it) lo = mid; else hi = mid;
+      }
+      const MiUnit &u = a.units[lo];
+      if (a.group_active[u.group] == 0) continue;  // no live instance in this group
+      const MiGroup &g = a.groups[u.group];
+      const int local = it - a.unit_prefix[lo];
+      int bin = 0;
+      while (bin < NBINS - 1 && u.blk_prefix[bin + 1] <= local) ++bin;
+      const int item = local - u.blk_prefix[bin];
+      const char *bp = u.page;
+      const PageHeader *h = reinterpret_cast<const PageHeader *>(bp);
+      const Lane ln = lane_of(g.inst[k]);
+      MiAcc acc;
+      switch (bin) {
+        case 0: mi_small<ALGO, K, 1>(g, bp, h, 0, item, ln, a.damping, acc); break;
+        case 1: mi_small<ALGO, K, (2 < 64 / K ? 2 : 64 / K)>(g, bp, h, 1, item, ln, a.damping, acc); break;
+        case 2: mi_small<ALGO, K, (4 < 64 / K ? 4 : 64 / K)>(g, bp, h, 2, item, ln, a.damping, acc); break;
+        case 3: mi_small<ALGO, K, (8 < 64 / K ? 8 : 64 / K)>(g, bp, h, 3, item, ln, a.damping, acc); break;
+        case 4: mi_small<ALGO, K, (16 < 64 / K ? 16 : 64 / K)>(g, bp, h, 4, item, ln, a.damping, acc); break;
+        case 5: mi_small<ALGO, K, (32 < 64 / K ? 32 : 64 / K)>(g, bp, h, 5, item, ln, a.damping, acc); break;
+        case BIN_WAVE: mi_wave<ALGO, K>(g, bp, h, item, ln, a.damping, acc); break;
+        case BIN_CHUNK: mi_chunk<ALGO, K>(g, u, bp, h, item, ln); break;
+        default:
+          if constexpr (mi_pr<ALGO>()) mi_zero<ALGO, K>(g, bp, h, item, ln, a.damping, acc);
+          break;
+      }
+      mi_flush<ALGO, K>(lds, u.group, acc);
+    }
+  }
+  // publish this block's per-instance counters (device-scope atomics on
+  // distinct instance records; the close kernel reads them after the sweep)
   __syncthreads();
-  const int total = a.ngroups * K;
-  for (int i = threadIdx.x; i < total; i += BLOCK) {
+  for (int i = threadIdx.x; i < ninst; i += BLOCK) {
+    const MiLds &e = lds[i];
+    if (e.changed == 0 && e.edges == 0 && e.min_changed == INF && e.l1 == 0.0 && e.ddelta == 0.0) continue;
     MiInst &in = a.groups[i / K].inst[i % K];
-    if (!ld_agent(&in.active)) continue;
-    uint32_t changed = ld_agent(&in.sw_changed);
-    uint32_t minc = ld_agent(&in.sw_min_changed);
-    double l1 = ld_agent(&in.sw_l1), dd = ld_agent(&in.sw_ddelta);
-    in.edges_total += ld_agent(&in.sw_edges);
+    if (e.changed) atomicAdd(&in.sw_changed, e.changed);
+    if (e.min_changed != INF) atomicMin(&in.sw_min_changed, e.min_changed);
+    if (e.edges) atomicAdd(&in.sw_edges, (unsigned long long)e.edges);
+    if constexpr (mi_pr<ALGO>()) {
+      if (e.l1 != 0.0) atomicAdd(&in.sw_l1, e.l1);
+      if (e.ddelta != 0.0) atomicAdd(&in.sw_ddelta, e.ddelta);
+    }
+  }
+}
+
+// Close a sweep: combine the chunk partials of every heavy vertex of every
+// live group (chunk order) and run their epilogues, then close every
+// instance (convergence, thresholds, dangling mass) and reset the queue.
+// One block, launched after the sweep.
+template <int ALGO, int K>
+__global__ void __launch_bounds__(MI_CLOSE_THREADS) mi_close_kernel(MiArgs a) {
+  using R = MiRed<ALGO, K>;
+  using T = typename R::T;
+  if (a.ctl->remaining == 0 && !a.tuning) return;
+  extern __shared__ MiLds lds[];
+  __shared__ uint32_t s_rem;
+  const int ninst = a.ngroups * K;
+  lds_clear(lds, ninst, MI_CLOSE_THREADS);
+  if (threadIdx.x == 0) s_rem = 0;
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = MI_CLOSE_THREADS / 64;
+  if (lane < K) {
+    for (int ui = 0; ui < a.nunits; ++ui) {
+      const MiUnit &u = a.units[ui];
+      if (a.group_active[u.group] == 0) continue;
+      const MiGroup &g = a.groups[u.group];
+      const PageHeader *h = reinterpret_cast<const PageHeader *>(u.page);
+      const Heavy *hv = reinterpret_cast<const Heavy *>(u.page + h->off_heavy);
+      const int32_t *off = reinterpret_cast<const int32_t *>(u.page + h->off_offsets);
+      const Lane ln = lane_of(g.inst[lane]);
+      for (int i = wave; i < h->n_heavy; i += nw) {
+        const Heavy x = hv[i];
+        const int first = (int)((uint32_t)x.first_count & 0xFFFFFu), count = (int)((uint32_t)x.first_count >> 20);
+        const int32_t v = h->v_begin + x.vl;
+        uint32_t old;
+        if (!mi_attempt<ALGO, K>(g, v, lane, ln, old)) continue;
+        T t = R::identity();
+        for (int j = 0; j < count; ++j) t = R::combine(t, R::from_bits(u.partial[(size_t)(first + j) * K + lane]));
+        MiAcc acc;
+        mi_epilogue<ALGO, K>(g, v, lane, ln, old, t, (uint32_t)(off[x.vl + 1] - off[x.vl]), a.damping, acc);
+        lds_add<ALGO>(lds[u.group * K + lane], acc);
+      }
+    }
+  }
+  __syncthreads();
+  for (int gi = threadIdx.x; gi < a.ngroups; gi += MI_CLOSE_THREADS) a.group_active[gi] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < ninst; i += MI_CLOSE_THREADS) {
+    MiInst &in = a.groups[i / K].inst[i % K];
+    if (!in.active) continue;
+    const MiLds &e = lds[i];
+    const uint32_t changed = in.sw_changed + e.changed;
+    const uint32_t minc = min(in.sw_min_changed, e.min_changed);
+    const double l1 = in.sw_l1 + e.l1, dd = in.sw_ddelta + e.ddelta;
+    in.edges_total += in.sw_edges + e.edges;
     in.sweeps += 1;
     bool done = false;
     if constexpr (mi_pr<ALGO>()) {
@@ -325,87 +444,21 @@ __device__ void mi_close(const MiArgs &a) {
     }
     if (!done && (int32_t)in.sweeps >= a.max_sweeps) { done = true; in.stop_reason = 3; }
     if (a.tuning) done = false;
-    st_agent(&in.sw_changed, 0u);
-    st_agent(&in.sw_min_changed, INF);
-    st_agent(&in.sw_edges, 0ull);
-    st_agent(&in.sw_l1, 0.0);
-    st_agent(&in.sw_ddelta, 0.0);
-    if (done) { in.done = 1; st_agent(&in.active, 0u); }
+    in.sw_changed = 0;
+    in.sw_min_changed = INF;
+    in.sw_edges = 0;
+    in.sw_l1 = 0.0;
+    in.sw_ddelta = 0.0;
+    if (done) { in.done = 1; in.active = 0; }
     else { atomicAdd(&s_rem, 1u); atomicAdd(&a.group_active[i / K], 1u); }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     a.ctl->remaining = s_rem;
     a.ctl->sweeps += 1;
+    a.ctl->queue = 0;
     if (a.host_remaining) *a.host_remaining = s_rem;
-    st_agent(&a.ctl->queue, 0u);
-    st_agent(&a.ctl->blocks_done, 0u);
     __threadfence_system();
-  }
-}
-
-template <int ALGO, int K>
-__global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
-  if (a.ctl->remaining == 0 && !a.tuning) return;  // everything converged: replays are no-ops
-  __shared__ int32_t s_base;
-  __shared__ uint32_t s_last;
-  const int lane = threadIdx.x % 64, k = lane % K;
-  for (;;) {
-    if (threadIdx.x == 0) s_base = (int32_t)atomicAdd(&a.ctl->queue, (uint32_t)a.grab);
-    __syncthreads();
-    const int32_t base = s_base;
-    __syncthreads();
-    if (base >= a.total_items) break;
-    const int32_t end = min(base + a.grab, a.total_items);
-    for (int32_t it = base; it < end; ++it) {
-      int lo = 0, hi = a.nunits;  // unit_prefix[lo] <= it < unit_prefix[hi]
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (a.unit_prefix[mid] <= it) lo = mid; else hi = mid;
-      }
-      const MiUnit &u = a.units[lo];
-      if (a.group_active[u.group] == 0) continue;  // no live instance in this group
-      const MiGroup &g = a.groups[u.group];
-      int local = it - a.unit_prefix[lo];
-      int bin = 0;
-      while (bin < NBINS - 1 && u.blk_prefix[bin + 1] <= local) ++bin;
-      const int item = local - u.blk_prefix[bin];
-      const char *base_p = u.page;
-      const PageHeader *h = reinterpret_cast<const PageHeader *>(base_p);
-      const MiInst &in = g.inst[k];
-      Lane ln;
-      ln.active = in.active;
-      ln.unit = in.unit;
-      ln.threshold = in.threshold;
-      ln.source = in.source;
-      ln.dangling = (float)in.dangling;
-      MiAcc acc;
-      switch (bin) {
-        case 0: mi_small<ALGO, K, 1>(g, base_p, h, 0, item, ln, a.damping, acc); break;
-        case 1: mi_small<ALGO, K, (2 < 64 / K ? 2 : 64 / K)>(g, base_p, h, 1, item, ln, a.damping, acc); break;
-        case 2: mi_small<ALGO, K, (4 < 64 / K ? 4 : 64 / K)>(g, base_p, h, 2, item, ln, a.damping, acc); break;
-        case 3: mi_small<ALGO, K, (8 < 64 / K ? 8 : 64 / K)>(g, base_p, h, 3, item, ln, a.damping, acc); break;
-        case 4: mi_small<ALGO, K, (16 < 64 / K ? 16 : 64 / K)>(g, base_p, h, 4, item, ln, a.damping, acc); break;
-        case 5: mi_small<ALGO, K, (32 < 64 / K ? 32 : 64 / K)>(g, base_p, h, 5, item, ln, a.damping, acc); break;
-        case BIN_WAVE: mi_wave<ALGO, K>(g, base_p, h, item, ln, a.damping, acc); break;
-        case BIN_CHUNK: mi_chunk<ALGO, K>(g, u, base_p, h, item, ln, a.damping, acc); break;
-        default:
-          if constexpr (mi_pr<ALGO>()) mi_zero<ALGO, K>(g, base_p, h, item, ln, a.damping, acc);
-          break;
-      }
-      mi_flush<ALGO, K>(g, acc);
-    }
-  }
-  // the last block to finish closes the sweep
-  if (threadIdx.x == 0) {
-    __threadfence();
-    uint32_t t = atomicAdd(&a.ctl->blocks_done, 1u);
-    s_last = (t == (uint32_t)(a.nblocks - 1)) ? 1u : 0u;
-  }
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    mi_close<ALGO, K>(a);
   }
 }
 
@@ -438,17 +491,24 @@ __global__ void mi_extract_kernel(const uint32_t *value, int32_t n, int32_t col,
   if (v < n) out[v] = value[(size_t)v * K + col];
 }
 
+template <int ALGO, int K>
+void mi_pair(const MiArgs &a, hipStream_t s) {
+  const size_t lds = sizeof(MiLds) * (size_t)a.ngroups * K;
+  hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
+  hipLaunchKernelGGL((mi_close_kernel<ALGO, K>), dim3(1), dim3(MI_CLOSE_THREADS), lds, s, a);
+}
+
 }  // namespace
 
 int mi_items_per_block_host(int b, int K) { return mi_items_per_block(b, K); }
 
 hipError_t launch_mi_sweep(int algo, int K, const MiArgs &a, hipStream_t s) {
-  dim3 grid(a.nblocks), block(BLOCK);
   if (a.nblocks <= 0) return hipErrorInvalidValue;
-  if (algo == A_PPR && K == 8) hipLaunchKernelGGL((mi_sweep_kernel<A_PPR, 8>), grid, block, 0, s, a);
-  else if (algo == A_PPR && K == 16) hipLaunchKernelGGL((mi_sweep_kernel<A_PPR, 16>), grid, block, 0, s, a);
-  else if (algo == A_SSSP && K == 8) hipLaunchKernelGGL((mi_sweep_kernel<A_SSSP, 8>), grid, block, 0, s, a);
-  else if (algo == A_SSSP && K == 16) hipLaunchKernelGGL((mi_sweep_kernel<A_SSSP, 16>), grid, block, 0, s, a);
+  if (a.ngroups * K > MI_MAX_INSTANCES) return hipErrorInvalidValue;
+  if (algo == A_PPR && K == 8) mi_pair<A_PPR, 8>(a, s);
+  else if (algo == A_PPR && K == 16) mi_pair<A_PPR, 16>(a, s);
+  else if (algo == A_SSSP && K == 8) mi_pair<A_SSSP, 8>(a, s);
+  else if (algo == A_SSSP && K == 16) mi_pair<A_SSSP, 16>(a, s);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -472,15 +532,14 @@ hipError_t launch_mi_extract(int K, const uint32_t *value, int32_t n, int32_t co
   return hipGetLastError();
 }
 
-}  // namespace sr
-
-namespace sr {
 hipError_t launch_mi_set_inst(MiInst *dst, const MiInst &val, hipStream_t s) {
   hipLaunchKernelGGL(mi_set_inst_kernel, dim3(1), dim3(64), 0, s, dst, val);
   return hipGetLastError();
 }
+
 hipError_t launch_mi_set_ctl(MiCtl *dst, const MiCtl &val, hipStream_t s) {
   hipLaunchKernelGGL(mi_set_ctl_kernel, dim3(1), dim3(64), 0, s, dst, val);
   return hipGetLastError();
 }
+
 }  // namespace sr

@@ -9,6 +9,9 @@
 
 namespace sr {
 
+// instances of one plan (their counters live in LDS during a sweep)
+constexpr int MI_MAX_INSTANCES = 1024;
+
 // Per-instance control (device memory), one per column of a group.
 struct MiInst {
   uint32_t active;       // 1 = running this sweep
@@ -42,7 +45,7 @@ struct MiGroup {
   int32_t n;
   int32_t pvu;              // P_OFF or P_STRONG
   int32_t has_w;            // the resident pages carry weights (read only then)
-  int32_t pad;
+  int32_t w8;               // weights stored as u8
 };
 
 // One unit of work: a resident page of a group's graph.
@@ -51,14 +54,13 @@ struct MiUnit {
   int32_t pad;
   const char *page;
   uint32_t *partial;        // [n_chunks][K]
-  uint32_t *arrive;         // [n_chunks]
   int32_t blk_prefix[NBINS + 1];  // items per bin within this unit
 };
 
 // Global control of a batched sweep (device memory).
 struct MiCtl {
   uint32_t queue;           // next work item (persistent grid)
-  uint32_t blocks_done;
+  uint32_t pad;
   uint32_t remaining;       // instances still active after the last sweep
   uint32_t sweeps;
 };

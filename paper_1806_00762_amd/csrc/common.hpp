@@ -30,6 +30,11 @@ constexpr int CHUNK = 2048;
 constexpr int BLOCK = 256;        // threads per workgroup (4 wavefronts)
 constexpr int WAVES = BLOCK / 64;
 
+// Tiles of the single-instance sweep: runs of consecutive non-heavy
+// vertices with at most TILE_V vertices and TILE_E in-edges, one block each.
+constexpr int TILE_V = 2 * BLOCK;
+constexpr int TILE_E = HEAVY;
+
 // vertices per block for bins 0..6 and chunks per block for bin 7
 constexpr int SMALL_ROUNDS = 4;   // vertices per lane group in bins 0..5
 constexpr int WAVE_ROUNDS = 2;    // vertices per wavefront in bin 6
@@ -47,9 +52,25 @@ struct Chunk {
   int32_t first_count;  // first | (count << 20), as uint32: first < 2^20, count < 2^12
 };
 
+// A heavy vertex (bin 7): local id and its chunk range, packed like Chunk.
+struct Heavy {
+  int32_t vl;
+  int32_t first_count;
+};
+
+// Per-block sweep counters, written with plain stores by every block of a
+// sweep and reduced by the close kernel after the sweep has finished.
+struct BlockAcc {
+  uint32_t changed, attempted, skipped, mispred, edges, min_changed;
+  uint32_t hist[8];
+  double l1, ddelta;
+};
+
 // First 256 bytes of every page buffer. Section offsets are in bytes from
-// the buffer start, all multiples of 256. The weight section is last so
-// unweighted programs copy only the prefix [0, bytes_unweighted).
+// the buffer start, all multiples of 256. Sections are ordered so that each
+// use copies a prefix: header, offsets, tiles, chunks, heavy list, sources
+// (unweighted programs stop here), weights (single-instance sweeps stop
+// here), degree-bin lists (multi-instance sweeps).
 struct alignas(256) PageHeader {
   uint32_t magic;
   int32_t v_begin;
@@ -59,14 +80,19 @@ struct alignas(256) PageHeader {
   uint64_t off_offsets;   // int32[n_p + 1], rebased to 0
   uint64_t off_bins;      // int32 local vertex ids, bins 0..6 and 8 back to back
   uint64_t off_chunks;    // Chunk[n_chunks]
+  uint64_t off_heavy;     // Heavy[n_heavy]: the vertices of bin 7, one entry each
+  uint64_t off_tiles;     // int32 pairs [v_begin, v_end) of the n_tiles tiles
   uint64_t off_src;       // int32[m_p], global source ids
-  uint64_t off_w;         // uint32[m_p] (weighted graphs only)
-  uint64_t bytes_unweighted;
-  uint64_t bytes_total;
+  uint64_t off_w;         // weights, w_bytes each (weighted graphs only)
+  uint64_t bytes_unweighted;  // prefix a program without weights needs
+  uint64_t bytes_weighted;    // prefix with weights (single-instance sweeps)
+  uint64_t bytes_total;       // everything, bin lists of the multi-instance sweep included
   int32_t bin_count[NBINS];      // bin 7: number of chunks
   int32_t bin_start[NBINS];      // start of bin b in the bins section (not bin 7)
   int32_t n_heavy;               // vertices in bin 7
   int32_t max_indeg;
+  int32_t n_tiles;
+  int32_t w_bytes;               // 1 (all weights < 256, stored as u8) or 4
 };
 static_assert(sizeof(PageHeader) == 256, "page header is one 256-byte line");
 
@@ -81,7 +107,7 @@ struct Diagram {
 
 // Per-sweep host-visible record (written by the last block of each sweep
 // into a pinned, device-mapped ring).
-struct SweepRecord {
+struct alignas(16) SweepRecord {
   uint64_t seq;
   uint64_t changed;
   uint64_t edges;
@@ -99,6 +125,7 @@ struct SweepRecord {
   double dangling;        // PageRank dangling mass after the sweep
   double pass_l1_closed;  // L1 of the pass closed by this sweep (if any)
 };
+static_assert(sizeof(SweepRecord) % 16 == 0, "record copied in 16-byte words");
 
 // Device-resident control block of one run. The sweeps and the end-of-pass
 // step read and update it, so a whole resident solve can be enqueued (or

@@ -144,7 +144,6 @@ void sr::release_residency(sr_graph *g) {
   auto &r = g->res;
   for (auto p : r.buf) g->ctx->dfree(p);
   for (auto p : r.partial) g->ctx->dfree(p);
-  for (auto p : r.arrive) g->ctx->dfree(p);
   r = Residency();
 }
 
@@ -155,6 +154,7 @@ static void release_state(sr_graph *g) {
   g->ctx->dfree(s.inv_outdeg);
   g->ctx->dfree(s.status);
   g->ctx->dfree(s.ctl);
+  g->ctx->dfree(s.blk);
   s = RunState();
 }
 
@@ -164,7 +164,9 @@ extern "C" sr_status sr_graph_load_csr(sr_ctx *c, int32_t n, int64_t m, const in
   if (!c) return SR_EINVAL;
   if (!out || !ro || (m > 0 && !ci)) return c->fail(SR_EINVAL, "null argument");
   if (n < 1 || m < 0) return c->fail(SR_EINVAL, "need n >= 1 and m >= 0");
-  if (flags & ~SR_LOAD_SYMMETRIZE) return c->fail(SR_EINVAL, "unknown load flags");
+  if (flags & ~(SR_LOAD_SYMMETRIZE | SR_LOAD_SYMMETRIC)) return c->fail(SR_EINVAL, "unknown load flags");
+  if ((flags & SR_LOAD_SYMMETRIZE) && (flags & SR_LOAD_SYMMETRIC))
+    return c->fail(SR_EINVAL, "SR_LOAD_SYMMETRIZE and SR_LOAD_SYMMETRIC are exclusive");
   if (ro[0] != 0 || ro[n] != m) return c->fail(SR_EINVAL, "row_offsets must start at 0 and end at m");
   for (int32_t u = 0; u < n; ++u)
     if (ro[u + 1] < ro[u]) return c->fail(SR_EINVAL, "row_offsets must be non-decreasing");
@@ -176,12 +178,24 @@ extern "C" sr_status sr_graph_load_csr(sr_ctx *c, int32_t n, int64_t m, const in
   g->ctx = c;
   g->n = n;
   g->weighted = w != nullptr;
-  g->symmetric = (flags & SR_LOAD_SYMMETRIZE) != 0;
+  g->symmetric = (flags & (SR_LOAD_SYMMETRIZE | SR_LOAD_SYMMETRIC)) != 0;
   sr_status st;
   try {
-    st = build_in_csr(g, ro, ci, w, g->symmetric);
+    st = build_in_csr(g, ro, ci, w, (flags & SR_LOAD_SYMMETRIZE) != 0);
   } catch (const std::bad_alloc &) {
     st = c->fail(SR_ENOMEM, "out of host memory building in-edges");
+  }
+  if (st == SR_OK && g->weighted) {
+    uint32_t mx = 0;
+    for (uint32_t x : g->in_w) mx = std::max(mx, x);
+    g->w8 = mx <= 0xFFu;  // weights stored losslessly as u8 in the pages
+  }
+  if (st == SR_OK && (flags & SR_LOAD_SYMMETRIC)) {
+    // the transpose of a symmetric graph with sorted rows is the graph itself
+    bool same = g->m == m && std::equal(g->in_off.begin(), g->in_off.end(), ro) &&
+                std::equal(g->in_src.begin(), g->in_src.end(), ci) &&
+                (!w || std::equal(g->in_w.begin(), g->in_w.end(), w));
+    if (!same) st = c->fail(SR_EINVAL, "SR_LOAD_SYMMETRIC: input is not symmetric (or rows are not sorted)");
   }
   if (st != SR_OK) { delete g; return st; }
   *out = g;
@@ -194,14 +208,14 @@ static uint64_t state_bytes(int32_t n, int algo) {
   return b;
 }
 
-// bytes of the page prefix an algorithm needs on the device
-static uint64_t need_bytes(const Page &p, bool weights) {
-  return weights ? p.hdr.bytes_total : p.hdr.bytes_unweighted;
+// bytes of the page prefix a use needs on the device
+static uint64_t need_bytes(const Page &p, bool weights, bool bins = false) {
+  return bins ? p.hdr.bytes_total : (weights ? p.hdr.bytes_weighted : p.hdr.bytes_unweighted);
 }
 
 static uint64_t scratch_bytes(const Page &p) {
   uint64_t c = (uint64_t)std::max<int32_t>(p.hdr.n_chunks, 1);
-  return 2 * (((4 * c) + 255) & ~255ull);
+  return ((4 * c) + 255) & ~255ull;
 }
 
 extern "C" sr_status sr_graph_partition(sr_graph *g, int32_t nparts, int32_t nslots) {
@@ -264,8 +278,10 @@ extern "C" sr_status sr_graph_page(const sr_graph *g, int32_t page, sr_page_view
   o->num_edges = p.hdr.m_p;
   o->offsets = (const int32_t *)(p.host + p.hdr.off_offsets);
   o->src = (const int32_t *)(p.host + p.hdr.off_src);
-  o->weights = g->weighted ? (const uint32_t *)(p.host + p.hdr.off_w) : nullptr;
+  o->weights = g->weighted ? (const void *)(p.host + p.hdr.off_w) : nullptr;
+  o->weight_bytes = g->weighted ? p.hdr.w_bytes : 0;
   o->bytes = p.bytes;
+  o->stream_bytes = p.hdr.bytes_weighted;
   return SR_OK;
 }
 
@@ -435,19 +451,18 @@ struct Runner {
     a.dia = dia;
     int32_t blk = 0;
     a.blk_prefix[0] = 0;
-    const bool pr = algo == A_PR || algo == A_PPR;
     for (size_t i = 0; i < pages.size(); ++i) {
       const PageHeader &h = g->pages[pages[i]].hdr;
-      for (int b = 0; b < NBINS; ++b) {
-        int nb = (b == BIN_ZERO && !pr) ? 0 : bin_blocks(h, b);
-        blk += nb;
-        a.blk_prefix[i * NBINS + b + 1] = blk;
+      for (int sec = 0; sec < NSEC; ++sec) {
+        blk += sec_blocks(h, sec);
+        a.blk_prefix[i * NSEC + sec + 1] = blk;
       }
       a.base[i] = g->res.buf[slots[i]];
       a.partial[i] = g->res.partial[slots[i]];
-      a.arrive[i] = g->res.arrive[slots[i]];
     }
+    a.blk = g->state.blk;
     a.nblocks = std::max<int32_t>(blk, 1);  // an empty window still closes its sweep
+    if (a.nblocks > g->state.blk_cap) return c->fail(SR_EINVAL, "internal: block records too small");
     return SR_OK;
   }
 
@@ -487,45 +502,43 @@ static sr_status ensure_state(sr_graph *g, int algo) {
 }
 
 // Make the pages resident (all of them) or allocate the streaming slots.
-sr_status sr::ensure_residency(sr_graph *g, bool weights, bool force_stream) {
+sr_status sr::ensure_residency(sr_graph *g, bool weights, bool force_stream, bool bins) {
   sr_ctx *c = g->ctx;
   auto &r = g->res;
   uint64_t all = 0, mx = 0, smx = 0;
   for (auto &p : g->pages) {
-    all += need_bytes(p, weights) + scratch_bytes(p);
-    mx = std::max(mx, need_bytes(p, weights));
+    all += need_bytes(p, weights, bins) + scratch_bytes(p);
+    mx = std::max(mx, need_bytes(p, weights, bins));
     smx = std::max(smx, scratch_bytes(p));
   }
   const uint64_t freeb = c->budget - c->used + [&] {
     uint64_t mine = 0;
     for (auto p : r.buf) { auto it = c->allocs.find(p); if (it != c->allocs.end()) mine += it->second; }
     for (auto p : r.partial) { auto it = c->allocs.find(p); if (it != c->allocs.end()) mine += it->second; }
-    for (auto p : r.arrive) { auto it = c->allocs.find(p); if (it != c->allocs.end()) mine += it->second; }
     return mine;
   }();
   const bool want_resident = !force_stream && all + 4096 <= freeb;
-  if (want_resident && r.resident && (r.weights || !weights)) return SR_OK;
+  if (want_resident && r.resident && (r.weights || !weights) && (r.bins || !bins)) return SR_OK;
   if (!want_resident && !r.resident && r.nslots == g->nslots && r.slot_bytes >= mx &&
       (r.weights || !weights) && !r.buf.empty())
     return SR_OK;
+  if (bins && !want_resident) return c->fail(SR_EBUDGET, "multi-instance runs need the graph resident");
   release_residency(g);
   sr_status st;
   if (want_resident) {
     r.resident = true;
     r.weights = weights;
+    r.bins = bins;
     for (size_t i = 0; i < g->pages.size(); ++i) {
       auto &p = g->pages[i];
-      void *b = nullptr, *pa = nullptr, *ar = nullptr;
-      uint64_t nb = need_bytes(p, weights);
-      uint64_t sc = (4ull * std::max<int32_t>(p.hdr.n_chunks, 1) + 255) & ~255ull;
+      void *b = nullptr, *pa = nullptr;
+      uint64_t nb = need_bytes(p, weights, bins);
+      uint64_t sc = scratch_bytes(p);
       if ((st = c->dalloc(&b, nb, "resident page")) != SR_OK) { release_residency(g); return st; }
       r.buf.push_back((char *)b);
       if ((st = c->dalloc(&pa, sc, "chunk partials")) != SR_OK) { release_residency(g); return st; }
       r.partial.push_back((uint32_t *)pa);
-      if ((st = c->dalloc(&ar, sc, "chunk arrivals")) != SR_OK) { release_residency(g); return st; }
-      r.arrive.push_back((uint32_t *)ar);
       hipError_t e = hipMemcpyAsync(b, p.host, nb, hipMemcpyHostToDevice, c->copy);
-      if (e == hipSuccess) e = launch_fill_u32((uint32_t *)ar, 0u, sc / 4, c->copy);
       if (e != hipSuccess) { release_residency(g); return c->hip_fail(e, "resident page copy"); }
       r.slot_page.push_back((int32_t)i);
     }
@@ -543,19 +556,13 @@ sr_status sr::ensure_residency(sr_graph *g, bool weights, bool force_stream) {
   r.nslots = S;
   r.slot_bytes = mx;
   for (int32_t s = 0; s < S; ++s) {
-    void *b = nullptr, *pa = nullptr, *ar = nullptr;
+    void *b = nullptr, *pa = nullptr;
     if ((st = c->dalloc(&b, mx, "page slot")) != SR_OK) { release_residency(g); return st; }
     r.buf.push_back((char *)b);
-    if ((st = c->dalloc(&pa, smx / 2, "chunk partials")) != SR_OK) { release_residency(g); return st; }
+    if ((st = c->dalloc(&pa, smx, "chunk partials")) != SR_OK) { release_residency(g); return st; }
     r.partial.push_back((uint32_t *)pa);
-    if ((st = c->dalloc(&ar, smx / 2, "chunk arrivals")) != SR_OK) { release_residency(g); return st; }
-    r.arrive.push_back((uint32_t *)ar);
-    hipError_t e = launch_fill_u32((uint32_t *)ar, 0u, smx / 8, c->copy);
-    if (e != hipSuccess) { release_residency(g); return c->hip_fail(e, "slot init"); }
     r.slot_page.push_back(-1);
   }
-  hipError_t e = hipStreamSynchronize(c->copy);
-  if (e != hipSuccess) { release_residency(g); return c->hip_fail(e, "slot init"); }
   return SR_OK;
 }
 
@@ -622,6 +629,26 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     }
   }
   if (s != SR_OK) return s;
+  {
+    // block records: the largest launch is a group of up to MAXW resident
+    // pages, or a window of num_slots-1 consecutive streamed pages
+    std::vector<int64_t> pb(g->pages.size());
+    for (size_t i = 0; i < g->pages.size(); ++i) pb[i] = sec_blocks(g->pages[i].hdr, 0) + sec_blocks(g->pages[i].hdr, 1);
+    const size_t win = g->res.resident ? (size_t)MAXW : (size_t)std::max(1, g->res.nslots - 1);
+    int64_t cap = 1;
+    for (size_t i = 0; i < pb.size(); ++i) {
+      int64_t sum = 0;
+      for (size_t j = i; j < std::min(pb.size(), i + win); ++j) sum += pb[j];
+      cap = std::max(cap, sum);
+    }
+    if (cap > g->state.blk_cap) {
+      c->dfree(g->state.blk);
+      g->state.blk = nullptr;
+      g->state.blk_cap = 0;
+      if ((s = c->dalloc((void **)&g->state.blk, sizeof(BlockAcc) * (uint64_t)cap, "block records")) != SR_OK) return s;
+      g->state.blk_cap = (int32_t)cap;
+    }
+  }
 
   // initial values, predictor states and control block
   RunState &rs = g->state;
@@ -699,7 +726,10 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     // Pipelined subgraph iteration (Section 3.2): a window of W = S-1 slots is
     // swept while the next page is copied into the remaining slot; each window
     // is swept until the copy lands (re-entry), max_inner_iters, or a sweep
-    // without change; then the window slides by one page.
+    // without change; then the window slides by one page. Pages go in
+    // increasing order every pass (in R-MAT graphs, whose low ids carry most
+    // edges, this order propagates furthest per pass); a page still in a slot
+    // from the previous pass is not copied again.
     const int32_t P = (int32_t)g->pages.size();
     const int32_t S = g->res.nslots;
     const int32_t W = S - 1;
@@ -711,9 +741,13 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     step_done = mk();
     struct Cleanup { std::vector<hipEvent_t> *v; ~Cleanup() { for (auto e : *v) (void)hipEventDestroy(e); } } cl{&own};
     for (auto ev : own) if (!ev) return c->fail(SR_EDEVICE, "event creation failed");
-    auto copy_page = [&](int32_t page, hipEvent_t wait) -> sr_status {
-      int32_t slot = page % S;
-      if (wait) HIP_TRY(c, hipStreamWaitEvent(c->copy, wait, 0), "copy wait");
+    std::vector<int32_t> &slot_page = g->res.slot_page;
+    std::fill(slot_page.begin(), slot_page.end(), -1);  // slot contents of older runs are not trusted
+    std::vector<int32_t> page_slot(P, -1);
+    std::vector<int64_t> last_use(S, -1);   // step counter of the last window that used each slot
+    int64_t step_clock = 0;
+    auto copy_page = [&](int32_t page, int32_t slot, bool wait_prev) -> sr_status {
+      if (wait_prev) HIP_TRY(c, hipStreamWaitEvent(c->copy, step_done, 0), "copy wait");
       hipEvent_t a = R.ev(), b = R.ev();
       uint64_t nb = need_bytes(g->pages[page], R.weights);
       if (a) (void)hipEventRecord(a, c->copy);
@@ -722,26 +756,49 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       if (b) (void)hipEventRecord(b, c->copy);
       R.track(a, b, true);
       HIP_TRY(c, hipEventRecord(copy_done[slot], c->copy), "copy event");
-      g->res.slot_page[slot] = page;
+      if (slot_page[slot] >= 0) page_slot[slot_page[slot]] = -1;
+      slot_page[slot] = page;
+      page_slot[page] = slot;
       R.st.h2d_bytes += nb;
       return SR_OK;
     };
+    // a slot for `page` that no page of the current window occupies (least
+    // recently used first)
+    auto free_slot = [&](const std::vector<int32_t> &window) -> int32_t {
+      int32_t best = -1;
+      for (int32_t sl = 0; sl < S; ++sl) {
+        bool used = false;
+        for (int32_t q : window) used |= page_slot[q] == sl;
+        if (used) continue;
+        if (best < 0 || last_use[sl] < last_use[best]) best = sl;
+      }
+      return best;
+    };
     int32_t pass = 0;
+    std::vector<int32_t> ord(P);
     while (!done) {
-      // pass start: the whole device is idle (host synced at the last pass end)
-      if ((s = copy_page(0, nullptr)) != SR_OK) return s;
+      for (int32_t i = 0; i < P; ++i) ord[i] = i;
+      // pass start: every earlier sweep has finished (host synced at the pass end)
+      if (page_slot[ord[0]] < 0) {
+        if ((s = copy_page(ord[0], free_slot({}), false)) != SR_OK) return s;
+      }
       for (int32_t j = 0; j < P && !done; ++j) {
-        HIP_TRY(c, hipStreamWaitEvent(c->compute, copy_done[j % S], 0), "compute wait");
+        std::vector<int32_t> win;
+        for (int32_t q = std::max(0, j - W + 1); q <= j; ++q) win.push_back(ord[q]);
+        for (int32_t q : win) HIP_TRY(c, hipStreamWaitEvent(c->compute, copy_done[page_slot[q]], 0), "compute wait");
         bool copying = false;
-        if (j + 1 < P) {
-          // slot of page j+1-S was last used by step j-1 (already enqueued)
-          if ((s = copy_page(j + 1, j > 0 ? step_done : nullptr)) != SR_OK) return s;
+        int32_t next_slot = -1;
+        if (j + 1 < P && page_slot[ord[j + 1]] < 0) {
+          // the free slot was last read by the previous step's sweeps
+          next_slot = free_slot(win);
+          if ((s = copy_page(ord[j + 1], next_slot, j > 0 || pass > 0)) != SR_OK) return s;
           copying = true;
         }
-        std::vector<int32_t> wp, ws;
-        for (int32_t q = std::max(0, j - W + 1); q <= j; ++q) { wp.push_back(q); ws.push_back(q % S); }
+        std::vector<int32_t> ws;
+        for (int32_t q : win) { ws.push_back(page_slot[q]); last_use[page_slot[q]] = step_clock; }
+        ++step_clock;
         SweepArgs a;
-        R.make_args(wp, ws, 0, a);
+        if ((s = R.make_args(win, ws, 0, a)) != SR_OK) return s;
         for (int32_t it = 0; it < p.max_inner_iters; ++it) {
           if ((s = R.launch(a)) != SR_OK) return s;
           if ((s = R.sync_compute()) != SR_OK) return s;
@@ -751,7 +808,8 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
           bool changed = false;
           for (uint64_t q = before; q < R.seq_next; ++q) changed |= c->ring_host[q & c->ring_mask].changed > 0;
           if (!changed) break;                      // the window reached its local fixed point
-          if (copying && hipEventQuery(copy_done[(j + 1) % S]) == hipSuccess) break;  // slide
+          if (!copying) break;                      // nothing in flight to wait for
+          if (hipEventQuery(copy_done[next_slot]) == hipSuccess) break;  // next page landed: slide
         }
         HIP_TRY(c, hipEventRecord(step_done, c->compute), "step event");
       }

@@ -32,6 +32,8 @@ struct RunState {
   float *inv_outdeg = nullptr;
   uint8_t *status = nullptr;
   Ctl *ctl = nullptr;
+  BlockAcc *blk = nullptr;  // per-block sweep records
+  int32_t blk_cap = 0;
   bool valid = false;
 };
 
@@ -40,11 +42,11 @@ struct RunState {
 struct Residency {
   bool resident = false;
   bool weights = false;            // page prefix with weights copied
+  bool bins = false;               // page prefix with the bin lists copied
   int32_t nslots = 0;
   uint64_t slot_bytes = 0;
   std::vector<char *> buf;         // resident: one per page; streaming: one per slot
-  std::vector<uint32_t *> partial; // heavy-vertex scratch, same indexing as buf
-  std::vector<uint32_t *> arrive;
+  std::vector<uint32_t *> partial; // heavy-vertex chunk partials, same indexing as buf
   std::vector<int32_t> slot_page;  // streaming: page currently in slot (-1 none)
   uint32_t max_chunks = 0;
 };
@@ -84,6 +86,7 @@ struct sr_graph {
   int32_t n = 0;
   int64_t m = 0;
   bool weighted = false, symmetric = false;
+  bool w8 = false;  // every weight fits in 8 bits: pages store u8 weights
   std::vector<int64_t> in_off;
   std::vector<int32_t> in_src;
   std::vector<uint32_t> in_w;
@@ -105,6 +108,6 @@ void free_pages(sr_graph *g);
 uint64_t graph_bytes(const sr_graph *g);
 int host_threads();
 // engine.cpp
-sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream);
+sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream, bool bins = false);
 void release_residency(sr_graph *g);
 }  // namespace sr

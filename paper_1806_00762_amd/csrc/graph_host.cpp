@@ -178,13 +178,17 @@ static void fill_page(const sr_graph *g, int32_t vb, int32_t ve, Page &pg) {
   int32_t cur[NBINS];
   for (int b = 0; b < NBINS; ++b) cur[b] = h.bin_start[b];
   Chunk *ch = (Chunk *)(buf + h.off_chunks);
-  int32_t nch = 0;
+  Heavy *hv = (Heavy *)(buf + h.off_heavy);
+  int32_t nch = 0, nhv = 0;
   for (int32_t i = 0; i < np; ++i) {
     int64_t d = g->in_off[vb + i + 1] - g->in_off[vb + i];
     if (d == 0) { bins[cur[BIN_ZERO]++] = i; continue; }
     if (d > HEAVY) {
       int32_t count = (int32_t)((d + CHUNK - 1) / CHUNK);
       int32_t first = nch;
+      hv[nhv].vl = i;
+      hv[nhv].first_count = (int32_t)((uint32_t)first | ((uint32_t)count << 20));
+      nhv++;
       for (int32_t c = 0; c < count; ++c) {
         Chunk k;
         k.vl = i;
@@ -198,8 +202,32 @@ static void fill_page(const sr_graph *g, int32_t vb, int32_t ve, Page &pg) {
     int b = d >= 64 ? BIN_WAVE : 31 - __builtin_clz((uint32_t)d);
     bins[cur[b]++] = i;
   }
+  {
+    int32_t *tl = (int32_t *)(buf + h.off_tiles);
+    int32_t nt = 0, tv = 0, t0 = 0;
+    int64_t te = 0;
+    bool open = false;
+    for (int32_t i = 0; i < np; ++i) {
+      int64_t d = g->in_off[vb + i + 1] - g->in_off[vb + i];
+      if (d > HEAVY) {
+        if (open) { tl[2 * nt] = t0; tl[2 * nt + 1] = i; nt++; open = false; }
+        continue;
+      }
+      if (open && (tv + 1 > TILE_V || te + d > TILE_E)) { tl[2 * nt] = t0; tl[2 * nt + 1] = i; nt++; open = false; }
+      if (!open) { open = true; t0 = i; tv = 0; te = 0; }
+      tv++; te += d;
+    }
+    if (open) { tl[2 * nt] = t0; tl[2 * nt + 1] = np; nt++; }
+  }
   std::memcpy(buf + h.off_src, &g->in_src[eb], sizeof(int32_t) * (size_t)mp);
-  if (g->weighted) std::memcpy(buf + h.off_w, &g->in_w[eb], sizeof(uint32_t) * (size_t)mp);
+  if (g->weighted) {
+    if (h.w_bytes == 1) {
+      uint8_t *w8 = (uint8_t *)(buf + h.off_w);
+      for (int64_t e = 0; e < mp; ++e) w8[e] = (uint8_t)g->in_w[eb + e];
+    } else {
+      std::memcpy(buf + h.off_w, &g->in_w[eb], sizeof(uint32_t) * (size_t)mp);
+    }
+  }
 }
 
 // Header (sizes, bin counts, section offsets) of the page [vb, ve).
@@ -229,14 +257,33 @@ static PageHeader page_header(const sr_graph *g, int32_t vb, int32_t ve) {
     h.bin_start[b] = s;
     s += h.bin_count[b];
   }
+  h.w_bytes = g->weighted ? (g->w8 ? 1 : 4) : 0;
   uint64_t o = sizeof(PageHeader);
   h.off_offsets = o; o = align256(o + 4ull * ((uint64_t)h.n_p + 1));
-  h.off_bins = o;    o = align256(o + 4ull * (uint64_t)s);
+  // tiles: greedy runs of consecutive non-heavy vertices
+  {
+    int32_t nt = 0, tv = 0;
+    int64_t te = 0;
+    bool open = false;
+    for (int32_t v = vb; v < ve; ++v) {
+      int64_t d = g->in_off[v + 1] - g->in_off[v];
+      if (d > HEAVY) { if (open) { nt++; open = false; } continue; }
+      if (open && (tv + 1 > TILE_V || te + d > TILE_E)) { nt++; open = false; }
+      if (!open) { open = true; tv = 0; te = 0; }
+      tv++; te += d;
+    }
+    if (open) nt++;
+    h.n_tiles = nt;
+  }
+  h.off_tiles = o;   o = align256(o + 8ull * (uint64_t)h.n_tiles);
   h.off_chunks = o;  o = align256(o + sizeof(Chunk) * (uint64_t)chunks);
+  h.off_heavy = o;   o = align256(o + sizeof(Heavy) * (uint64_t)heavy);
   h.off_src = o;     o = align256(o + 4ull * (uint64_t)h.m_p);
   h.bytes_unweighted = o;
   h.off_w = o;
-  if (g->weighted) o = align256(o + 4ull * (uint64_t)h.m_p);
+  if (g->weighted) o = align256(o + (uint64_t)h.w_bytes * (uint64_t)h.m_p);
+  h.bytes_weighted = o;
+  h.off_bins = o;    o = align256(o + 4ull * (uint64_t)s);
   h.bytes_total = o;
   return h;
 }

@@ -56,11 +56,13 @@ struct PageCtx {
   int32_t v_begin;
   const int32_t *off;
   const int32_t *bins;
+  const int32_t *tiles;
   const Chunk *chunks;
   const int32_t *src;
   const uint32_t *w;
+  const uint8_t *w8;         // weights as u8 when the page stores them so (else null)
   int32_t bin_count, bin_start;
-  uint32_t *partial, *arrive;
+  uint32_t *partial;
 };
 
 // Thread-local sweep counters, reduced per block at the end.
@@ -106,6 +108,11 @@ __device__ inline Gate gate_of(const Run &r, int32_t v) {
     g.attempt = (r.dia->attempt_mask >> g.st) & 1u;
   }
   return g;
+}
+
+// Weight of page-local in-edge e (u8 or u32 storage).
+__device__ inline uint32_t weight_at(const PageCtx &p, int32_t e) {
+  return p.w8 ? (uint32_t)p.w8[e] : p.w[e];
 }
 
 // Contribution of one in-edge (u -> v, weight w) to the reduction.
@@ -180,13 +187,11 @@ __device__ inline void epilogue(const Run &r, int32_t v, const Gate &g, bool com
       }
     }
   }
-  if (g.attempt) {
-    acc.attempted++;
-    acc.edges += deg;
-  } else {
-    acc.skipped++;
-  }
-  if (changed) acc.changed++;
+  const uint32_t att = g.attempt ? 1u : 0u;
+  acc.attempted += att;
+  acc.skipped += 1u - att;
+  acc.edges += att * deg;
+  acc.changed += changed ? 1u : 0u;
   // predictor state (Fig. 6): success/fail edge for attempting states, the
   // unconditional step for dormant ones; a verification pass resets the
   // vertices it changes to the initial state.
@@ -199,113 +204,157 @@ __device__ inline void epilogue(const Run &r, int32_t v, const Gate &g, bool com
   }
 }
 
-// ---------------------------------------------------- bins 0..5 and bin 8
-// G lanes per vertex (G = 1..32), each lane <= 2 in-edges; every group
-// handles SMALL_ROUNDS vertices whose loads are all issued before use.
-template <int ALGO, int G>
-__device__ void sweep_small(const Run &r, const PageCtx &p, int item, Acc &acc) {
-  using R = Red<ALGO>;
-  using T = typename R::T;
-  constexpr int NG = BLOCK / G;
-  constexpr int RR = SMALL_ROUNDS;
-  const int grp = threadIdx.x / G, lane = threadIdx.x % G;
-  const int base = item * NG * RR + grp;
-  int32_t vl[RR];
-  int32_t beg[RR], end[RR];
-  Gate gt[RR];
-  bool comp[RR];
-#pragma unroll
-  for (int k = 0; k < RR; ++k) gt[k] = Gate{false, 0, 0u};
-#pragma unroll
-  for (int k = 0; k < RR; ++k) {
-    int idx = base + k * NG;
-    vl[k] = idx < p.bin_count ? p.bins[p.bin_start + idx] : -1;
-  }
-#pragma unroll
-  for (int k = 0; k < RR; ++k) {
-    beg[k] = 0; end[k] = 0; comp[k] = false;
-    if (vl[k] >= 0) {
-      beg[k] = p.off[vl[k]];
-      end[k] = p.off[vl[k] + 1];
-      gt[k] = gate_of(r, p.v_begin + vl[k]);
-      comp[k] = gt[k].attempt || r.audit;
-    }
-  }
-  T red[RR];
-  if constexpr (G >= 1) {
-    int32_t s0[RR], s1[RR];
-    uint32_t w0[RR], w1[RR];
-#pragma unroll
-    for (int k = 0; k < RR; ++k) {
-      int e0 = beg[k] + lane, e1 = e0 + G;
-      bool a0 = comp[k] && e0 < end[k], a1 = comp[k] && e1 < end[k];
-      s0[k] = a0 ? p.src[e0] : -1;
-      s1[k] = a1 ? p.src[e1] : -1;
-      if (ALGO == A_SSSP) {
-        w0[k] = a0 ? p.w[e0] : 0u;
-        w1[k] = a1 ? p.w[e1] : 0u;
-      } else {
-        w0[k] = w1[k] = 0u;
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < RR; ++k) {
-      T x = R::identity();
-      if (s0[k] >= 0) x = R::combine(x, R::edge(r, s0[k], w0[k]));
-      if (s1[k] >= 0) x = R::combine(x, R::edge(r, s1[k], w1[k]));
-#pragma unroll
-      for (int m = G / 2; m >= 1; m >>= 1) x = R::combine(x, shfl_xor(x, m));
-      red[k] = x;
-    }
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < RR; ++k)
-      if (vl[k] >= 0)
-        epilogue<ALGO>(r, p.v_begin + vl[k], gt[k], comp[k], red[k], (uint32_t)(end[k] - beg[k]), acc);
-  }
-}
+// ------------------------------------------------------------------ tiles
+// One block per tile of consecutive vertices (<= TILE_V vertices, <= TILE_E
+// in-edges). Phase 1 gates the vertices (two consecutive ones per thread)
+// and compacts the attempting ones with a block-wide scan into LDS. Phase 2
+// assigns every thread 8 consecutive positions of the compacted edge list
+// (merge-path style: one binary search, then a forward walk), so the in-edge
+// reads of a wavefront cover one contiguous range; the 8 source loads and 8
+// gathers of a thread are independent, and runs of edges of the same vertex
+// are reduced in registers before one LDS atomic. Phase 3 runs the
+// epilogues.
+constexpr int EDGES_PER_THREAD = TILE_E / BLOCK;
 
-// ----------------------------------------------------------------- bin 6
-// One wavefront per vertex, 64 <= d <= HEAVY; 4 loads in flight per lane.
+struct TileLds {
+  int32_t pos[TILE_V + 1];  // first compacted edge position of each attempting vertex
+  int32_t eb[TILE_V];       // its first in-edge (page-local)
+  int32_t vl[TILE_V];       // its page-local vertex id
+  uint32_t acc[TILE_V];     // reduction (u32 min, or f32 sum bits)
+  uint32_t old[TILE_V];
+  uint8_t att[TILE_V];
+  uint8_t st[TILE_V];
+  int32_t wsum[WAVES][2];
+};
+
 template <int ALGO>
-__device__ void sweep_wave(const Run &r, const PageCtx &p, int item, Acc &acc) {
+__device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, TileLds &s) {
   using R = Red<ALGO>;
   using T = typename R::T;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-#pragma unroll 1
-  for (int k = 0; k < WAVE_ROUNDS; ++k) {
-    int idx = (item * WAVE_ROUNDS + k) * WAVES + wave;
-    if (idx >= p.bin_count) break;
-    int32_t vl = p.bins[p.bin_start + idx];
-    int32_t v = p.v_begin + vl;
-    int32_t beg = p.off[vl], end = p.off[vl + 1];
-    Gate g = gate_of(r, v);
-    bool comp = g.attempt || r.audit;
-    T x = R::identity();
-    if (comp) {
-      int e = beg + lane;
-      for (; e + 192 < end; e += 256) {
-        int32_t u0 = p.src[e], u1 = p.src[e + 64], u2 = p.src[e + 128], u3 = p.src[e + 192];
-        uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        if (ALGO == A_SSSP) { a0 = p.w[e]; a1 = p.w[e + 64]; a2 = p.w[e + 128]; a3 = p.w[e + 192]; }
-        T y0 = R::edge(r, u0, a0), y1 = R::edge(r, u1, a1), y2 = R::edge(r, u2, a2), y3 = R::edge(r, u3, a3);
-        x = R::combine(x, R::combine(R::combine(y0, y1), R::combine(y2, y3)));
-      }
-      for (; e < end; e += 64) x = R::combine(x, R::edge(r, p.src[e], ALGO == A_SSSP ? p.w[e] : 0u));
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int32_t t0 = p.tiles[2 * item], t1 = p.tiles[2 * item + 1];
+  const int nv = t1 - t0;
+  // phase 1: gate, degrees, block scan of (attempting vertices, their edges)
+  int32_t lv[2], eb[2], d[2];
+  Gate gt[2];
+  bool act[2];
 #pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) x = R::combine(x, shfl_xor(x, m));
+  for (int j = 0; j < 2; ++j) {
+    const int i = 2 * tid + j;
+    lv[j] = t0 + i;
+    act[j] = false;
+    eb[j] = 0;
+    d[j] = 0;
+    gt[j] = Gate{false, 0, 0u};
+    if (i < nv) {
+      eb[j] = p.off[lv[j]];
+      d[j] = p.off[lv[j] + 1] - eb[j];
+      gt[j] = gate_of(r, p.v_begin + lv[j]);
+      act[j] = (gt[j].attempt || r.audit) && (d[j] > 0 || is_pr<ALGO>());
     }
-    if (lane == 0) epilogue<ALGO>(r, v, g, comp, x, (uint32_t)(end - beg), acc);
+  }
+  int na = (int)act[0] + (int)act[1];
+  int ne = (act[0] ? d[0] : 0) + (act[1] ? d[1] : 0);
+  int ina = na, ine = ne;  // inclusive scan within the wavefront
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    int a = __shfl_up(ina, m, 64), b = __shfl_up(ine, m, 64);
+    if (lane >= m) { ina += a; ine += b; }
+  }
+  if (lane == 63) { s.wsum[wave][0] = ina; s.wsum[wave][1] = ine; }
+  __syncthreads();
+  int ka = 0, pe = 0, Kt = 0, At = 0;
+  for (int w = 0; w < WAVES; ++w) {
+    if (w < wave) { ka += s.wsum[w][0]; pe += s.wsum[w][1]; }
+    Kt += s.wsum[w][0];
+    At += s.wsum[w][1];
+  }
+  ka += ina - na;
+  pe += ine - ne;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (act[j]) {
+      s.pos[ka] = pe;
+      s.eb[ka] = eb[j];
+      s.vl[ka] = lv[j];
+      s.acc[ka] = R::bits(R::identity());
+      s.old[ka] = gt[j].old;
+      s.att[ka] = gt[j].attempt ? 1 : 0;
+      s.st[ka] = gt[j].st;
+      ++ka;
+      pe += d[j];
+    } else if (2 * tid + j < nv) {
+      // not pulled this sweep: skipped by the predictor, or no in-edge
+      epilogue<ALGO>(r, p.v_begin + lv[j], gt[j], false, R::identity(), (uint32_t)d[j], acc);
+    }
+  }
+  if (tid == 0) s.pos[Kt] = At;
+  __syncthreads();
+  // phase 2: 8 consecutive compacted edge positions per thread
+  const int p0 = tid * EDGES_PER_THREAD;
+  if (p0 < At) {
+    int lo = 0, hi = Kt;  // pos[lo] <= p0 < pos[hi]
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (s.pos[mid] <= p0) lo = mid; else hi = mid;
+    }
+    int kk[EDGES_PER_THREAD];
+    int32_t e[EDGES_PER_THREAD];
+    int k = lo;
+    int next = s.pos[k + 1];
+#pragma unroll
+    for (int j = 0; j < EDGES_PER_THREAD; ++j) {
+      const int q = p0 + j;
+      while (q >= next && k + 1 < Kt) { ++k; next = s.pos[k + 1]; }
+      kk[j] = q < At ? k : -1;
+      e[j] = s.eb[k] + (q - s.pos[k]);
+    }
+    int32_t u[EDGES_PER_THREAD];
+    uint32_t w[EDGES_PER_THREAD];
+#pragma unroll
+    for (int j = 0; j < EDGES_PER_THREAD; ++j) {
+      u[j] = kk[j] >= 0 ? p.src[e[j]] : 0;
+      w[j] = (ALGO == A_SSSP && kk[j] >= 0) ? weight_at(p, e[j]) : 0u;
+    }
+    T x[EDGES_PER_THREAD];
+#pragma unroll
+    for (int j = 0; j < EDGES_PER_THREAD; ++j) x[j] = kk[j] >= 0 ? R::edge(r, u[j], w[j]) : R::identity();
+    int ck = kk[0];
+    T cur = x[0];
+#pragma unroll
+    for (int j = 1; j < EDGES_PER_THREAD; ++j) {
+      if (kk[j] == ck) {
+        cur = R::combine(cur, x[j]);
+      } else {
+        if (ck >= 0) {
+          if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
+          else atomicMin(&s.acc[ck], cur);
+        }
+        ck = kk[j];
+        cur = x[j];
+      }
+    }
+    if (ck >= 0) {
+      if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
+      else atomicMin(&s.acc[ck], cur);
+    }
+  }
+  __syncthreads();
+  // phase 3: epilogues of the pulled vertices
+  for (int k = tid; k < Kt; k += BLOCK) {
+    Gate g{s.att[k] != 0, s.st[k], s.old[k]};
+    epilogue<ALGO>(r, p.v_begin + s.vl[k], g, true, R::from_bits(s.acc[k]),
+                   (uint32_t)(s.pos[k + 1] - s.pos[k]), acc);
   }
 }
 
 // ----------------------------------------------------------------- bin 7
-// One wavefront per CHUNK edges of a heavy vertex; the last chunk of the
-// vertex to arrive combines the partials in chunk order and runs the
-// epilogue (fence + arrival counter, the classic last-block pattern).
+// One wavefront per CHUNK edges of a heavy vertex. Each chunk stores its
+// partial (plain store); the close kernel, after the sweep has finished,
+// combines the partials of every heavy vertex in chunk order and runs its
+// epilogue, so no fence or arrival counter is needed inside the sweep.
 template <int ALGO>
-__device__ void sweep_chunk(const Run &r, const PageCtx &p, int item, Acc &acc) {
+__device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
   using R = Red<ALGO>;
   using T = typename R::T;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -313,7 +362,6 @@ __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item, Acc &acc) 
   if (idx >= p.bin_count) return;
   Chunk c = p.chunks[idx];
   int32_t v = p.v_begin + c.vl;
-  int first = (int)((uint32_t)c.first_count & 0xFFFFFu), count = (int)((uint32_t)c.first_count >> 20);
   Gate g = gate_of(r, v);
   bool comp = g.attempt || r.audit;
   T x = R::identity();
@@ -322,29 +370,15 @@ __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item, Acc &acc) 
     for (; e + 192 < c.e_end; e += 256) {
       int32_t u0 = p.src[e], u1 = p.src[e + 64], u2 = p.src[e + 128], u3 = p.src[e + 192];
       uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-      if (ALGO == A_SSSP) { a0 = p.w[e]; a1 = p.w[e + 64]; a2 = p.w[e + 128]; a3 = p.w[e + 192]; }
+      if (ALGO == A_SSSP) { a0 = weight_at(p, e); a1 = weight_at(p, e + 64); a2 = weight_at(p, e + 128); a3 = weight_at(p, e + 192); }
       T y0 = R::edge(r, u0, a0), y1 = R::edge(r, u1, a1), y2 = R::edge(r, u2, a2), y3 = R::edge(r, u3, a3);
       x = R::combine(x, R::combine(R::combine(y0, y1), R::combine(y2, y3)));
     }
-    for (; e < c.e_end; e += 64) x = R::combine(x, R::edge(r, p.src[e], ALGO == A_SSSP ? p.w[e] : 0u));
+    for (; e < c.e_end; e += 64) x = R::combine(x, R::edge(r, p.src[e], ALGO == A_SSSP ? weight_at(p, e) : 0u));
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) x = R::combine(x, shfl_xor(x, m));
   }
-  if (lane != 0) return;
-  int32_t beg = p.off[c.vl], end = p.off[c.vl + 1];
-  if (count == 1) {
-    epilogue<ALGO>(r, v, g, comp, x, (uint32_t)(end - beg), acc);
-    return;
-  }
-  st_agent(&p.partial[idx], R::bits(x));
-  __threadfence();
-  uint32_t ticket = atomicAdd(&p.arrive[first], 1u);
-  if (ticket != (uint32_t)(count - 1)) return;
-  __threadfence();
-  T tot = R::identity();
-  for (int j = 0; j < count; ++j) tot = R::combine(tot, R::from_bits(ld_agent(&p.partial[first + j])));
-  st_agent(&p.arrive[first], 0u);
-  epilogue<ALGO>(r, v, g, comp, tot, (uint32_t)(end - beg), acc);
+  if (lane == 0) p.partial[idx] = R::bits(x);
 }
 
 // ------------------------------------------------------ end of pass logic
@@ -396,45 +430,47 @@ __device__ void close_pass(Ctl *c, SweepRecord *rec) {
   }
 }
 
-// Fold the sweep accumulators into the pass and publish the sweep record.
-__device__ void close_sweep(Ctl *c, SweepRecord *ring, uint32_t mask, int end_of_pass) {
-  uint32_t seq = c->sweep_seq;
-  SweepRecord *rec = ring ? &ring[seq & mask] : nullptr;
-  unsigned long long changed = ld_agent(&c->sw_changed);
-  uint32_t minc = ld_agent(&c->sw_min_changed);
-  double l1 = ld_agent(&c->sw_l1), dd = ld_agent(&c->sw_ddelta);
-  if (rec) {
-    rec->seq = seq;
-    rec->changed = changed;
-    rec->edges = ld_agent(&c->sw_edges);
-    rec->attempted = ld_agent(&c->sw_attempted);
-    rec->skipped = ld_agent(&c->sw_skipped);
-    rec->mispred = ld_agent(&c->sw_mispred);
-    rec->l1 = l1;
-    rec->min_changed = minc;
-    rec->threshold = c->threshold;
-    rec->phase = c->phase;
-    for (int i = 0; i < 8; ++i) rec->hist[i] = ld_agent(&c->sw_hist[i]);
-    rec->pass_l1_closed = -1.0;
-  }
-  c->pass_changed += changed;
-  c->pass_min_changed = min(c->pass_min_changed, minc);
-  c->pass_l1 += l1;
-  c->dangling += dd;
-  st_agent(&c->sw_changed, 0ull); st_agent(&c->sw_edges, 0ull);
-  st_agent(&c->sw_attempted, 0ull); st_agent(&c->sw_skipped, 0ull);
-  st_agent(&c->sw_mispred, 0ull);
-  for (int i = 0; i < 8; ++i) st_agent(&c->sw_hist[i], 0ull);
-  st_agent(&c->sw_min_changed, INF);
-  st_agent(&c->sw_l1, 0.0); st_agent(&c->sw_ddelta, 0.0);
+// Totals of one sweep, as reduced by the close kernel.
+struct SweepTotals {
+  unsigned long long changed, edges, attempted, skipped, mispred, hist[8];
+  uint32_t min_changed;
+  double l1, ddelta;
+};
+
+// Fold a sweep into the pass (one thread) and fill its record in `rec`
+// (LDS); the caller copies the record to the host ring with wide stores.
+__device__ void close_sweep(Ctl *c, SweepRecord *rec, int end_of_pass, const SweepTotals &t) {
+  const uint32_t seq = c->sweep_seq;
+  rec->seq = seq;
+  rec->changed = t.changed;
+  rec->edges = t.edges;
+  rec->attempted = t.attempted;
+  rec->skipped = t.skipped;
+  rec->mispred = t.mispred;
+  rec->l1 = t.l1;
+  rec->min_changed = t.min_changed;
+  rec->threshold = c->threshold;
+  rec->phase = c->phase;
+  for (int i = 0; i < 8; ++i) rec->hist[i] = t.hist[i];
+  rec->pass_l1_closed = -1.0;
+  c->pass_changed += t.changed;
+  c->pass_min_changed = min(c->pass_min_changed, t.min_changed);
+  c->pass_l1 += t.l1;
+  c->dangling += t.ddelta;
   c->sweep_seq = seq + 1;
   if (end_of_pass) close_pass(c, rec);
-  if (rec) {
-    if (!end_of_pass) { rec->done_after = c->done; rec->pass_after = c->pass; rec->stop_reason = c->stop_reason; }
-    rec->dangling = c->dangling;
-  }
-  st_agent(&c->blocks_done, 0u);
-  __threadfence_system();
+  if (!end_of_pass) { rec->done_after = c->done; rec->pass_after = c->pass; rec->stop_reason = c->stop_reason; }
+  rec->dangling = c->dangling;
+}
+
+// Copy a record staged in LDS to the host-mapped ring: one 16-byte store
+// per thread of the first wavefront, so the PCIe writes go out together.
+__device__ inline void publish_record(const SweepRecord *src, SweepRecord *dst) {
+  static_assert(sizeof(SweepRecord) % 16 == 0, "record is a whole number of 16-byte words");
+  constexpr int WORDS = sizeof(SweepRecord) / 16;
+  static_assert(WORDS <= 64, "one wavefront writes the record");
+  if (threadIdx.x < WORDS)
+    reinterpret_cast<uint4 *>(dst)[threadIdx.x] = reinterpret_cast<const uint4 *>(src)[threadIdx.x];
 }
 
 // ------------------------------------------------------------ the sweep
@@ -445,29 +481,31 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   __shared__ uint32_t s_hist[8];
   __shared__ uint32_t s_u32[WAVES][6];
   __shared__ double s_f64[WAVES][2];
+  __shared__ TileLds s_tile;
   if (threadIdx.x < 8) s_hist[threadIdx.x] = 0;
 
-  // locate (page, bin, item) of this block
+  // locate (page, section, item) of this block: section 0 = tiles, 1 = chunks
   const int b = blockIdx.x;
-  int lo = 0, hi = a.nent * NBINS;  // prefix[lo] <= b < prefix[hi]
+  int lo = 0, hi = a.nent * NSEC;  // prefix[lo] <= b < prefix[hi]
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
     if (a.blk_prefix[mid] <= b) lo = mid; else hi = mid;
   }
-  const int ent = lo / NBINS, bin = lo % NBINS, item = b - a.blk_prefix[lo];
+  const int ent = lo / NSEC, sec = lo % NSEC, item = b - a.blk_prefix[lo];
   const char *base = a.base[ent];
   const PageHeader *h = reinterpret_cast<const PageHeader *>(base);
   PageCtx p;
   p.v_begin = h->v_begin;
   p.off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
   p.bins = reinterpret_cast<const int32_t *>(base + h->off_bins);
+  p.tiles = reinterpret_cast<const int32_t *>(base + h->off_tiles);
   p.chunks = reinterpret_cast<const Chunk *>(base + h->off_chunks);
   p.src = reinterpret_cast<const int32_t *>(base + h->off_src);
   p.w = reinterpret_cast<const uint32_t *>(base + h->off_w);
-  p.bin_count = h->bin_count[bin];
-  p.bin_start = h->bin_start[bin];
+  p.w8 = h->w_bytes == 1 ? reinterpret_cast<const uint8_t *>(base + h->off_w) : nullptr;
+  p.bin_count = h->bin_count[BIN_CHUNK];
+  p.bin_start = 0;
   p.partial = a.partial[ent];
-  p.arrive = a.arrive[ent];
 
   Run r;
   r.algo = ALGO;
@@ -491,33 +529,13 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   Acc acc;
   // a launch over pages without any work still runs one block, so the
   // sweep (and the pass) is closed the same way
-  const int active_bin = b < a.blk_prefix[a.nent * NBINS] ? bin : -1;
-  switch (active_bin) {
-    case -1: break;
-    case 0: sweep_small<ALGO, 1>(r, p, item, acc); break;
-    case 1: sweep_small<ALGO, 2>(r, p, item, acc); break;
-    case 2: sweep_small<ALGO, 4>(r, p, item, acc); break;
-    case 3: sweep_small<ALGO, 8>(r, p, item, acc); break;
-    case 4: sweep_small<ALGO, 16>(r, p, item, acc); break;
-    case 5: sweep_small<ALGO, 32>(r, p, item, acc); break;
-    case BIN_WAVE: sweep_wave<ALGO>(r, p, item, acc); break;
-    case BIN_CHUNK: sweep_chunk<ALGO>(r, p, item, acc); break;
-    case BIN_ZERO:
-      if constexpr (is_pr<ALGO>()) {
-        // zero in-degree: the pull sum is empty, the value still follows D
-        for (int k = 0; k < 4; ++k) {
-          int idx = (item * 4 + k) * BLOCK + threadIdx.x;
-          if (idx < p.bin_count) {
-            int32_t v = p.v_begin + p.bins[p.bin_start + idx];
-            Gate g = gate_of(r, v);
-            epilogue<ALGO>(r, v, g, g.attempt || r.audit, 0.0f, 0u, acc);
-          }
-        }
-      }
-      break;
+  if (b < a.blk_prefix[a.nent * NSEC]) {
+    if (sec == 0) sweep_tile<ALGO>(r, p, item, acc, s_tile);
+    else sweep_chunk<ALGO>(r, p, item);
   }
 
-  // block reduction of the counters, one set of atomics per block
+  // block reduction of the counters into this block's record (plain stores;
+  // the close kernel reads them after the sweep)
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   uint32_t v0 = wave_sum_u32(acc.changed), v1 = wave_sum_u32(acc.attempted),
            v2 = wave_sum_u32(acc.skipped), v3 = wave_sum_u32(acc.mispred),
@@ -531,51 +549,145 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
-    uint32_t mn = INF;
-    double g0 = 0.0, g1 = 0.0;
+    BlockAcc rec;
+    rec.changed = rec.attempted = rec.skipped = rec.mispred = rec.edges = 0;
+    rec.min_changed = INF;
+    rec.l1 = rec.ddelta = 0.0;
     for (int w = 0; w < WAVES; ++w) {
-      t0 += s_u32[w][0]; t1 += s_u32[w][1]; t2 += s_u32[w][2]; t3 += s_u32[w][3]; t4 += s_u32[w][4];
-      mn = min(mn, s_u32[w][5]);
-      g0 += s_f64[w][0]; g1 += s_f64[w][1];
+      rec.changed += s_u32[w][0]; rec.attempted += s_u32[w][1]; rec.skipped += s_u32[w][2];
+      rec.mispred += s_u32[w][3]; rec.edges += s_u32[w][4];
+      rec.min_changed = min(rec.min_changed, s_u32[w][5]);
+      rec.l1 += s_f64[w][0]; rec.ddelta += s_f64[w][1];
     }
-    if (t0) atomicAdd(&ctl->sw_changed, t0);
-    if (t1) atomicAdd(&ctl->sw_attempted, t1);
-    if (t2) atomicAdd(&ctl->sw_skipped, t2);
-    if (t3) atomicAdd(&ctl->sw_mispred, t3);
-    if (t4) atomicAdd(&ctl->sw_edges, t4);
-    if (mn != INF) atomicMin(&ctl->sw_min_changed, mn);
-    if constexpr (is_pr<ALGO>()) {
-      if (g0 != 0.0) atomicAdd(&ctl->sw_l1, g0);
-      if (g1 != 0.0) atomicAdd(&ctl->sw_ddelta, g1);
-    }
-    for (int i = 0; i < 8; ++i)
-      if (s_hist[i]) atomicAdd(&ctl->sw_hist[i], (unsigned long long)s_hist[i]);
-    __threadfence();
-    uint32_t ticket = atomicAdd(&ctl->blocks_done, 1u);
-    if (ticket == (uint32_t)(a.nblocks - 1)) {
-      __threadfence();
-      close_sweep(ctl, a.ring, a.ring_mask, a.end_of_pass);
-    }
+    for (int i = 0; i < 8; ++i) rec.hist[i] = s_hist[i];
+    a.blk[blockIdx.x] = rec;
   }
 }
 
-__global__ void end_pass_kernel(Ctl *ctl, SweepRecord *ring, uint32_t mask) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Close a sweep: combine the chunk partials of every heavy vertex (chunk
+// order, so PageRank sums are reproducible), run their epilogues, reduce
+// the per-block records, and fold the totals into the control block (and
+// close the pass). One block of CLOSE_THREADS threads, after the sweep.
+constexpr int CLOSE_THREADS = 1024;
+
+template <int ALGO>
+__global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
+  using R = Red<ALGO>;
+  using T = typename R::T;
+  Ctl *ctl = a.ctl;
   if (ctl->done) return;
-  // a pass closed on its own gets a record of its own (no sweep counters)
-  uint32_t seq = ctl->sweep_seq;
-  SweepRecord *rec = ring ? &ring[seq & mask] : nullptr;
-  if (rec) {
-    rec->seq = seq; rec->changed = 0; rec->edges = 0; rec->attempted = 0; rec->skipped = 0;
-    rec->mispred = 0; rec->l1 = 0.0; rec->min_changed = INF; rec->threshold = ctl->threshold;
-    rec->phase = ctl->phase;
-    for (int i = 0; i < 8; ++i) rec->hist[i] = 0;
+  __shared__ uint32_t s_hist[8];
+  __shared__ unsigned long long s_red[CLOSE_THREADS / 64][6];
+  __shared__ uint32_t s_min[CLOSE_THREADS / 64];
+  __shared__ double s_fl[CLOSE_THREADS / 64][2];
+  __shared__ __align__(16) SweepRecord s_rec;
+  if (threadIdx.x < 8) s_hist[threadIdx.x] = 0;
+  Run r;
+  r.algo = ALGO;
+  r.pvu = ctl->pvu;
+  r.phase = ctl->phase;
+  r.audit = a.audit && r.phase == 0 && r.pvu != P_OFF;
+  r.threshold = ctl->threshold;
+  r.value = a.value;
+  r.contrib = a.contrib;
+  r.inv_outdeg = a.inv_outdeg;
+  r.status = a.status;
+  r.dia = &a.dia;
+  r.damping = a.damping;
+  r.pr_eps = a.pr_eps;
+  r.base_uniform = 1.0f / (float)a.n;
+  r.dangling = (float)ctl->dangling;
+  r.pr_seed = a.pr_seed;
+  r.hist = s_hist;
+  __syncthreads();
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = CLOSE_THREADS / 64;
+  Acc acc;
+  // one thread per heavy vertex: its chunk partials are independent loads
+  for (int ent = 0; ent < a.nent; ++ent) {
+    const char *base = a.base[ent];
+    const PageHeader *h = reinterpret_cast<const PageHeader *>(base);
+    const Heavy *hv = reinterpret_cast<const Heavy *>(base + h->off_heavy);
+    const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
+    const uint32_t *part = a.partial[ent];
+    for (int i = threadIdx.x; i < h->n_heavy; i += CLOSE_THREADS) {
+      const Heavy x = hv[i];
+      const int first = (int)((uint32_t)x.first_count & 0xFFFFFu), count = (int)((uint32_t)x.first_count >> 20);
+      const int32_t v = h->v_begin + x.vl;
+      Gate g = gate_of(r, v);
+      bool comp = g.attempt || r.audit;
+      T t = R::identity();
+      if (comp) {
+        int j = 0;
+        for (; j + 4 <= count; j += 4) {
+          T y0 = R::from_bits(part[first + j]), y1 = R::from_bits(part[first + j + 1]);
+          T y2 = R::from_bits(part[first + j + 2]), y3 = R::from_bits(part[first + j + 3]);
+          t = R::combine(t, R::combine(R::combine(y0, y1), R::combine(y2, y3)));
+        }
+        for (; j < count; ++j) t = R::combine(t, R::from_bits(part[first + j]));
+      }
+      epilogue<ALGO>(r, v, g, comp, t, (uint32_t)(off[x.vl + 1] - off[x.vl]), acc);
+    }
   }
-  ctl->sweep_seq = seq + 1;
-  close_pass(ctl, rec);
-  if (rec) rec->dangling = ctl->dangling;
-  __threadfence_system();
+  // per-block records of the sweep
+  unsigned long long c0 = acc.changed, c1 = acc.attempted, c2 = acc.skipped, c3 = acc.mispred, c4 = acc.edges;
+  uint32_t mn = acc.min_changed;
+  double l1 = acc.l1, dd = acc.ddelta;
+  const bool weak = r.pvu == P_WEAK;
+  for (int i = threadIdx.x; i < a.nblocks; i += CLOSE_THREADS) {
+    const BlockAcc &b = a.blk[i];
+    c0 += b.changed; c1 += b.attempted; c2 += b.skipped; c3 += b.mispred; c4 += b.edges;
+    mn = min(mn, b.min_changed);
+    l1 += b.l1; dd += b.ddelta;
+    if (weak)
+      for (int k = 0; k < 8; ++k)
+        if (b.hist[k]) atomicAdd(&s_hist[k], b.hist[k]);
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    c0 += shfl_xor(c0, m); c1 += shfl_xor(c1, m); c2 += shfl_xor(c2, m);
+    c3 += shfl_xor(c3, m); c4 += shfl_xor(c4, m);
+    mn = min(mn, shfl_xor(mn, m));
+    l1 += shfl_xor(l1, m); dd += shfl_xor(dd, m);
+  }
+  if (lane == 0) {
+    s_red[wave][0] = c0; s_red[wave][1] = c1; s_red[wave][2] = c2; s_red[wave][3] = c3; s_red[wave][4] = c4;
+    s_min[wave] = mn;
+    s_fl[wave][0] = l1; s_fl[wave][1] = dd;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    SweepTotals t{};
+    t.min_changed = INF;
+    for (int w = 0; w < nw; ++w) {
+      t.changed += s_red[w][0]; t.attempted += s_red[w][1]; t.skipped += s_red[w][2];
+      t.mispred += s_red[w][3]; t.edges += s_red[w][4];
+      t.min_changed = min(t.min_changed, s_min[w]);
+      t.l1 += s_fl[w][0]; t.ddelta += s_fl[w][1];
+    }
+    for (int k = 0; k < 8; ++k) t.hist[k] = s_hist[k];  // block records and heavy vertices
+    close_sweep(ctl, &s_rec, a.end_of_pass, t);
+  }
+  __syncthreads();
+  if (a.ring) publish_record(&s_rec, &a.ring[s_rec.seq & a.ring_mask]);
+}
+
+__global__ void end_pass_kernel(Ctl *ctl, SweepRecord *ring, uint32_t mask) {
+  // a pass closed on its own gets a record of its own (no sweep counters)
+  __shared__ __align__(16) SweepRecord s_rec;
+  if (ctl->done) return;
+  if (threadIdx.x == 0) {
+    const uint32_t seq = ctl->sweep_seq;
+    SweepRecord &rec = s_rec;
+    rec.seq = seq; rec.changed = 0; rec.edges = 0; rec.attempted = 0; rec.skipped = 0;
+    rec.mispred = 0; rec.l1 = 0.0; rec.min_changed = INF; rec.threshold = ctl->threshold;
+    rec.phase = ctl->phase;
+    for (int i = 0; i < 8; ++i) rec.hist[i] = 0;
+    ctl->sweep_seq = seq + 1;
+    close_pass(ctl, &rec);
+    rec.dangling = ctl->dangling;
+  }
+  __syncthreads();
+  if (ring) publish_record(&s_rec, &ring[s_rec.seq & mask]);
 }
 
 template <int ALGO>
@@ -613,15 +725,20 @@ __global__ void init_ctl_kernel(Ctl *ctl, Ctl init) {
 
 }  // namespace
 
+template <int ALGO>
+static void launch_pair(const SweepArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(sweep_kernel<ALGO>, dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+  hipLaunchKernelGGL(close_kernel<ALGO>, dim3(1), dim3(CLOSE_THREADS), 0, s, a);
+}
+
 hipError_t launch_sweep(int algo, const SweepArgs &a, hipStream_t s) {
   if (a.nblocks <= 0) return hipErrorInvalidValue;
-  dim3 grid(a.nblocks), block(BLOCK);
   switch (algo) {
-    case A_BFS: hipLaunchKernelGGL(sweep_kernel<A_BFS>, grid, block, 0, s, a); break;
-    case A_SSSP: hipLaunchKernelGGL(sweep_kernel<A_SSSP>, grid, block, 0, s, a); break;
-    case A_CC: hipLaunchKernelGGL(sweep_kernel<A_CC>, grid, block, 0, s, a); break;
-    case A_PR: hipLaunchKernelGGL(sweep_kernel<A_PR>, grid, block, 0, s, a); break;
-    case A_PPR: hipLaunchKernelGGL(sweep_kernel<A_PPR>, grid, block, 0, s, a); break;
+    case A_BFS: launch_pair<A_BFS>(a, s); break;
+    case A_SSSP: launch_pair<A_SSSP>(a, s); break;
+    case A_CC: launch_pair<A_CC>(a, s); break;
+    case A_PR: launch_pair<A_PR>(a, s); break;
+    case A_PPR: launch_pair<A_PPR>(a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -7,6 +7,7 @@
 namespace sr {
 
 constexpr int MAXW = 16;  // pages per sweep launch
+constexpr int NSEC = 2;   // work sections of a page: tiles, heavy-vertex chunks
 
 // Arguments of one window sweep (Section 3.2: the resident pages of the
 // window are swept together as one "super subgraph").
@@ -26,18 +27,16 @@ struct SweepArgs {
   float *contrib;          // PageRank: rank / outdeg, gathered by the pull
   const float *inv_outdeg; // PageRank: 1 / outdeg (0 for dangling vertices)
   uint8_t *status;         // weak predictor state per vertex
+  BlockAcc *blk;           // one counter record per block of the sweep
   Diagram dia;
-  int32_t blk_prefix[MAXW * NBINS + 1];  // cumulative blocks over (page, bin)
+  int32_t blk_prefix[MAXW * NSEC + 1];   // cumulative blocks over (page, section)
   const char *base[MAXW];                // page buffers on the device
   uint32_t *partial[MAXW];               // heavy-vertex chunk partials, per page
-  uint32_t *arrive[MAXW];                // heavy-vertex arrival counters, per page
 };
 
-// Blocks a page needs for bin b.
-inline int bin_blocks(const PageHeader &h, int b) {
-  int cnt = h.bin_count[b];
-  int per = bin_items_per_block(b);
-  return (cnt + per - 1) / per;
+// Blocks a page needs for section sec (0: one per tile, 1: WAVES chunks each).
+inline int sec_blocks(const PageHeader &h, int sec) {
+  return sec == 0 ? h.n_tiles : (h.n_chunks + WAVES - 1) / WAVES;
 }
 
 hipError_t launch_sweep(int algo, const SweepArgs &a, hipStream_t s);

@@ -69,6 +69,7 @@ sr_status MiPlan::add_group(sr_graph *g, int pvu, int *out_index) {
   gr.n = g->n;
   gr.pvu = pvu;
   gr.has_w = (algo == A_SSSP && g->res.resident && g->res.weights) ? 1 : 0;
+  gr.w8 = g->w8 ? 1 : 0;
   sr_status s;
   if ((s = alloc((void **)&gr.value, 4ull * g->n * K, "instance values")) != SR_OK) return s;
   if (algo == A_PPR) {
@@ -111,9 +112,6 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
       u.page = g->res.buf[p];
       uint64_t nch = (uint64_t)std::max<int32_t>(h.n_chunks, 1);
       if ((s = alloc((void **)&u.partial, 4ull * nch * K, "chunk partials")) != SR_OK) return s;
-      if ((s = alloc((void **)&u.arrive, 4ull * nch, "chunk arrivals")) != SR_OK) return s;
-      hipError_t e = launch_fill_u32(u.arrive, 0u, nch, c->compute);
-      if (e != hipSuccess) return c->hip_fail(e, "arrival init");
       int32_t acc = 0;
       u.blk_prefix[0] = 0;
       for (int b = 0; b < NBINS; ++b) {
@@ -127,6 +125,8 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
     }
   }
   if (units.empty()) return c->fail(SR_EINVAL, "no work units");
+  if ((int)groups.size() * K > MI_MAX_INSTANCES)
+    return c->fail(SR_EINVAL, "too many instances in one call (at most " + std::to_string(MI_MAX_INSTANCES) + ")");
   if ((s = alloc((void **)&d_groups, sizeof(MiGroup) * groups.size(), "group table")) != SR_OK) return s;
   if ((s = alloc((void **)&d_units, sizeof(MiUnit) * units.size(), "unit table")) != SR_OK) return s;
   if ((s = alloc((void **)&d_prefix, 4ull * unit_prefix.size(), "unit prefix")) != SR_OK) return s;
@@ -332,7 +332,7 @@ extern "C" sr_status sr_batch_run(sr_ctx *c, const sr_instance *inst, int32_t co
     if (g->server_refs > 0) return c->fail(SR_EBUSY, "graph is attached to a server");
     if (g->pages.empty())
       if ((s = sr_graph_partition(g, 1, 0)) != SR_OK) return s;
-    if ((s = ensure_residency(g, weights, false)) != SR_OK) return s;
+    if ((s = ensure_residency(g, weights, false, true)) != SR_OK) return s;
     if (!g->res.resident) return c->fail(SR_EBUDGET, "a batched graph does not fit the budget resident");
     int gi = -1, col = K;
     for (int32_t i = 0; i < count; ++i) {

@@ -192,7 +192,7 @@ extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_
   for (auto *g : s->graphs) {
     if (g->pages.empty())
       if ((st = sr_graph_partition(g, 1, 0)) != SR_OK) return fail(st);
-    if ((st = ensure_residency(g, g->weighted, false)) != SR_OK) return fail(st);
+    if ((st = ensure_residency(g, g->weighted, false, true)) != SR_OK) return fail(st);
     if (!g->res.resident) return fail(c->fail(SR_EBUDGET, "served graphs must fit the budget resident"));
     if (g->server_refs > 0) return fail(c->fail(SR_EBUSY, "graph is attached to another server"));
   }

@@ -116,3 +116,31 @@ def test_default_diagram_matches_reading(sr):
     ns, init, mask, succ, fail = oracle.weak_default_diagram()
     assert d.num_states == ns and d.initial_state == init and d.attempt_mask == mask
     assert list(d.on_success) == succ and list(d.on_fail) == fail
+
+
+def test_symmetric_flag_verifies(sr):
+    c = sr.Context(-1, 1 << 30)
+    sym = graphgen.rmat(10, 8, seed=7, symmetrize=True)
+    G = c.load(sym, symmetric=True)
+    assert G.info()["symmetric"] == 1
+    G.close()
+    with pytest.raises(sr.SeraphError) as e:
+        c.load(graphgen.rmat(10, 8, seed=7), symmetric=True)
+    assert e.value.status == sr.SR_EINVAL
+    c.close()
+
+
+def test_wide_weights_kept_as_u32(sr):
+    """Weights >= 256 are stored as u32; below 256 as u8 (both lossless)."""
+    c = sr.Context(-1, 1 << 30)
+    for hi, width in ((255, 1), (70000, 4)):
+        src = graphgen.rmat(9, 8, seed=2, weights=(1, hi, 3))
+        G = c.load(src)
+        G.partition(2, 4)
+        ws = np.concatenate([G.page(p)["weights"] for p in range(G.info()["num_parts"])])
+        assert G.page(0)["weight_bytes"] == width
+        A = sp.csr_matrix((src.weights.astype(np.int64), src.col, src.offsets), shape=(src.n, src.n)).T.tocsr()
+        A.sort_indices()
+        assert np.array_equal(ws, A.data.astype(np.uint32))
+        G.close()
+    c.close()

@@ -175,3 +175,18 @@ def test_exhaustive_cc_n5_sample(sr, ctx):
         g = graphgen.from_edges(5, [u for u, _ in es], [v for _, v in es])
         got, _ = run_case(sr, ctx, g, "cc", "strong", "resident", symmetrize=True)
         assert np.array_equal(got, oracle.cc(g)), mask
+
+
+def test_wide_weights_u32_path(sr, ctx):
+    """Weights above 255 keep u32 storage; single-instance and batched SSSP agree with the oracle."""
+    g = graphgen.rmat(12, 16, seed=91, weights=(1, 70000, 92))
+    for sched in ("resident", "s3p3i4"):
+        say(f"case wide weights {sched}")
+        got, st = run_case(sr, ctx, g, "sssp", "weak", sched, source=0)
+        assert np.array_equal(got, oracle.sssp(g, 0))
+    G = ctx.load(g)
+    srcs = [int(s) for s in graphgen.sources_with_outedges(g, 5, seed=93)]
+    outs, _, _ = sr.batch_run(ctx, [(G, "sssp", s) for s in srcs])
+    for s, x in zip(srcs, outs):
+        assert np.array_equal(x, oracle.sssp(g, s))
+    G.close()

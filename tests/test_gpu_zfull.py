@@ -1,0 +1,166 @@
+"""Full-size workloads: PageRank on R-MAT scale 16 (4 equal-edge pages, up to
+4 in-GPU sweeps per page per pass), streamed SSSP on R-MAT scale 22 under a
+device budget of 1/4 of the graph bytes (the benchmark's configuration),
+streamed CC on R-MAT scale 24 / edge factor 32 and its uniform twin, the
+256-instance batched PPR set, and a Poisson serving stream. Each result is
+compared with the oracle (bit-exact for integer programs, 1e-6 max-abs for
+PageRank)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sr():
+    import paper_1806_00762_amd as sr
+    sr.lib()
+    return sr
+
+
+def test_pagerank_s16_four_pages_four_inner(sr):
+    g = graphgen.recipes.pagerank_s16()
+    ref, _, _ = oracle.pagerank(g, tol=1e-13)
+    with sr.Context(0, 0) as ctx:
+        G = ctx.load(g)
+        G.partition(4, 2)   # one page resident at a time, iterated up to 4 times
+        for pvu in ("weak", "off"):
+            st = G.run("pagerank", pvu=pvu, max_inner_iters=4, force_stream=True, tol_l1=1e-9)
+            x = G.values(np.float32).astype(np.float64)
+            err = float(np.max(np.abs(x - ref)))
+            say(f"pagerank s16 {pvu}: max-abs {err:.3e} passes {st['passes']} stop {st['stop_reason']} "
+                f"L1 {st['final_l1']:.3e}")
+            assert st["stop_reason"] in (1, 2)
+            assert err <= 1e-6
+            assert G.info()["num_parts"] == 4
+        G.close()
+
+
+def test_sssp_s22_streamed_quarter_budget(sr):
+    t = time.time()
+    g = graphgen.recipes.sssp_s22()
+    ref = oracle.sssp(g, 0)
+    say(f"sssp s22 gen+oracle {time.time() - t:.1f}s")
+    budget = (4 * (g.n + 1) + 8 * g.m) // 4
+    with sr.Context(0, budget) as ctx:
+        G = ctx.load(g)
+        G.partition(0, 4)
+        info = G.info()
+        assert info["num_parts"] >= 4 and info["resident"] == 0
+        for pvu in ("weak", "strong", "off"):
+            st = G.run("sssp", source=0, pvu=pvu, max_inner_iters=8, force_stream=True)
+            d = G.values()
+            say(f"sssp s22 {pvu}: passes {st['passes']} h2d {st['h2d_bytes'] / 1e6:.0f} MB wall {st['wall_ms']:.0f} ms")
+            assert np.array_equal(d, ref)
+            assert st["h2d_bytes"] >= info["graph_bytes"]
+            used, cap = ctx.memory()
+            assert used <= cap == budget
+        G.close()
+
+
+def _cc_streamed(sr, g, name):
+    t = time.time()
+    ref = oracle.cc(g)
+    say(f"{name}: union-find {time.time() - t:.1f}s, components {len(np.unique(ref))}")
+    gbytes = 4 * (g.n + 1) + 4 * g.m
+    # pages stream through slots worth 1/4 of the graph next to the vertex state
+    budget = gbytes // 4 + 5 * g.n + (1 << 20)
+    with sr.Context(0, budget) as ctx:
+        t = time.time()
+        G = ctx.load(g, symmetric=True)
+        G.partition(0, 4)
+        say(f"{name}: load+partition {time.time() - t:.1f}s, pages {G.info()['num_parts']}")
+        st = G.run("cc", pvu="strong", max_inner_iters=4, force_stream=True)
+        lab = G.values()
+        say(f"{name}: passes {st['passes']} wall {st['wall_ms']:.0f} ms h2d {st['h2d_bytes'] / 1e9:.2f} GB")
+        assert np.array_equal(lab, ref)
+        G.close()
+
+
+def test_cc_rmat_s24_ef32_streamed(sr):
+    t = time.time()
+    g = graphgen.recipes.cc_rmat_s24()
+    say(f"cc rmat24: generated m={g.m} in {time.time() - t:.1f}s")
+    _cc_streamed(sr, g, "cc rmat24")
+
+
+def test_cc_uniform_twin_s24_streamed(sr):
+    t = time.time()
+    g = graphgen.recipes.cc_uniform_s24()
+    say(f"cc uniform24: generated m={g.m} in {time.time() - t:.1f}s")
+    _cc_streamed(sr, g, "cc uniform24")
+
+
+def test_batched_ppr_256_over_32_graphs(sr):
+    graphs = [graphgen.recipes.batched_graph(i) for i in range(32)]
+    with sr.Context(0, 0) as ctx:
+        Gs = [ctx.load(g) for g in graphs]
+        insts = [(gi, int(s)) for gi, g in enumerate(graphs)
+                 for s in graphgen.sources_with_outedges(g, 8, seed=2000 + gi)]
+        outs, per, bs = sr.batch_run(ctx, [(Gs[gi], "ppr", s) for gi, s in insts])
+        say(f"batched ppr: {bs}")
+        worst_bound, worst_exact = 0.0, 0.0
+        for (gi, s), x, st in zip(insts, outs, per):
+            assert st["converged"] == 1
+            xf = x.view(np.float32).astype(np.float64)
+            bound = oracle.pagerank_residual(graphs[gi], xf, seed=s) / 0.15
+            worst_bound = max(worst_bound, bound)
+            if graphs[gi].n <= 1 << 15:
+                ref, _, _ = oracle.pagerank(graphs[gi], seed=s, tol=1e-13)
+                err = float(np.max(np.abs(xf - ref)))
+                worst_exact = max(worst_exact, err)
+                assert err <= 1e-6
+        say(f"batched ppr: worst exact max-abs {worst_exact:.3e}, worst certified L1 bound {worst_bound:.3e}")
+        assert worst_bound <= 1e-5
+        for G in Gs:
+            G.close()
+
+
+def test_serving_stream_three_graphs(sr):
+    graphs = [graphgen.recipes.serving_graph(s) for s in (20, 22, 23)]
+    nreq = 1500
+    arr = graphgen.poisson_arrivals(2000.0, nreq, seed=4000)
+    pick = graphgen.bounded_draws(4001, 1, nreq, 0, 2)
+    kind = graphgen.bounded_draws(4002, 1, nreq, 0, 1)
+    srcs = [graphgen.sources_with_outedges(graphs[gi], nreq, seed=4003 + gi) for gi in range(3)]
+    reqs = [(int(pick[i]), "sssp" if kind[i] == 0 else "bfs", int(srcs[int(pick[i])][i])) for i in range(nreq)]
+    with sr.Context(0, 0) as ctx:
+        Gs = [ctx.load(g) for g in graphs]
+        srv = sr.Server(ctx, Gs, slots=16)
+        t0 = time.time()
+        tickets = []
+        for i, (gi, algo, s) in enumerate(reqs):
+            while time.time() - t0 < arr[i]:
+                time.sleep(0.0001)
+            tickets.append(srv.submit(gi, algo, s))
+        check = list(range(0, nreq, 100))
+        outs = {i: np.empty(graphs[reqs[i][0]].n, dtype=np.uint32) for i in check}
+        pending = set(range(nreq))
+        lat = {}
+        while pending and time.time() - t0 < 100:
+            for i in list(pending):
+                done, l = srv.poll(tickets[i], outs.get(i))
+                if done:
+                    lat[i] = l
+                    pending.discard(i)
+            time.sleep(0.0005)
+        assert not pending
+        say(f"serving: p50 {np.percentile(list(lat.values()), 50):.1f} ms p99 "
+            f"{np.percentile(list(lat.values()), 99):.1f} ms, {srv.stats()}")
+        srv.close()
+        for i in check:
+            gi, algo, s = reqs[i]
+            ref = oracle.sssp(graphs[gi], s) if algo == "sssp" else oracle.bfs(graphs[gi], s)
+            assert np.array_equal(outs[i], ref), (i, gi, algo, s)
+        for G in Gs:
+            G.close()
