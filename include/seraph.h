@@ -67,6 +67,9 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
                                      (mispredictions) without applying them */
 #define SR_RUN_FORCE_STREAM 0x2u  /* stream pages through slots even if the graph fits */
 #define SR_RUN_RESUME 0x4u        /* continue from the values/state left by the last run */
+#define SR_RUN_FIXED_INNER 0x8u   /* every window step runs exactly max_inner_iters sweeps; with
+                                     num_slots = 2 this is CLIP's loaded-data re-entry (Section 3.2),
+                                     with max_inner_iters = 1 the single-pass baseline of Section 5.4 */
 
 /* stop reasons reported in sr_run_stats.stop_reason */
 #define SR_STOP_CONVERGED 1   /* a full un-predicted pass changed nothing (min programs)
@@ -204,6 +207,19 @@ typedef struct {
  * 3.2). Returns SR_ENOTCONV if max_passes ran out (values stay readable).
  * stats may be NULL. */
 sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_stats *stats);
+
+/* Per-sweep trace of the last sr_run (the Fig. 10 / Section 5.4 instrumentation):
+ * one record per sweep, in order. */
+typedef struct {
+  int32_t pass;              /* passes completed before this sweep */
+  int32_t phase;             /* 1 = verification sweep (prediction off) */
+  int64_t changed, attempted, skipped, edges;
+  int64_t state_hist[8];     /* weak predictor: vertices visited in each state */
+  double l1;                 /* PageRank: L1 change of the sweep */
+} sr_sweep_record;
+/* Copy up to max records of the last run into out (host); *count receives
+ * the number of sweeps the run made (may exceed max). */
+sr_status sr_run_sweeps(const sr_graph *g, sr_sweep_record *out, int32_t max, int32_t *count);
 
 /* Copy the last run's vertex values to host memory: uint32 per vertex for
  * BFS (levels), SSSP (distances) and CC (labels), SR_INF if unreached;

@@ -25,7 +25,7 @@ SR_BFS, SR_SSSP, SR_CC, SR_PAGERANK, SR_PPR = 0, 1, 2, 3, 4
 SR_PVU_OFF, SR_PVU_STRONG, SR_PVU_WEAK, SR_PVU_DEFAULT = 0, 1, 2, 3
 SR_LOAD_SYMMETRIZE = 0x1
 SR_LOAD_SYMMETRIC = 0x2
-SR_RUN_AUDIT_PVU, SR_RUN_FORCE_STREAM, SR_RUN_RESUME = 0x1, 0x2, 0x4
+SR_RUN_AUDIT_PVU, SR_RUN_FORCE_STREAM, SR_RUN_RESUME, SR_RUN_FIXED_INNER = 0x1, 0x2, 0x4, 0x8
 SR_STOP_CONVERGED, SR_STOP_FP32_FLOOR, SR_STOP_MAX_PASSES = 1, 2, 3
 SR_INF = 0xFFFFFFFF
 
@@ -81,6 +81,12 @@ class sr_run_stats(ctypes.Structure):
         return d
 
 
+class sr_sweep_record(ctypes.Structure):
+    _fields_ = [("pass_", ctypes.c_int32), ("phase", ctypes.c_int32), ("changed", ctypes.c_int64),
+                ("attempted", ctypes.c_int64), ("skipped", ctypes.c_int64), ("edges", ctypes.c_int64),
+                ("state_hist", ctypes.c_int64 * 8), ("l1", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _SIGNATURES = {
     "sr_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_P)]),
@@ -97,6 +103,8 @@ _SIGNATURES = {
     "sr_pvu_default_diagram": (ctypes.c_int, [ctypes.POINTER(sr_pvu_diagram)]),
     "sr_run": (ctypes.c_int, [_P, ctypes.POINTER(sr_run_params), ctypes.POINTER(sr_run_stats)]),
     "sr_read_values": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
+    "sr_run_sweeps": (ctypes.c_int, [_P, ctypes.POINTER(sr_sweep_record), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32)]),
 }
 class sr_instance(ctypes.Structure):
     _fields_ = [("g", ctypes.c_void_p), ("algo", ctypes.c_int), ("source", ctypes.c_int32)]
@@ -264,7 +272,7 @@ class Graph:
     def run(self, algo, source: int = 0, pvu="default", damping: float = 0.85, tol_l1: float = 1e-9,
             max_passes: int = 0, max_inner_iters: int = 0, diagram: Optional[sr_pvu_diagram] = None,
             pr_change_eps: float = 0.0, audit: bool = False, force_stream: bool = False,
-            resume: bool = False, check: bool = True) -> dict:
+            resume: bool = False, fixed_inner: bool = False, check: bool = True) -> dict:
         p = sr_run_params()
         p.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
         p.source = source
@@ -276,7 +284,7 @@ class Graph:
         p.diagram = ctypes.pointer(diagram) if diagram is not None else None
         p.pr_change_eps = pr_change_eps
         p.flags = ((SR_RUN_AUDIT_PVU if audit else 0) | (SR_RUN_FORCE_STREAM if force_stream else 0)
-                   | (SR_RUN_RESUME if resume else 0))
+                   | (SR_RUN_RESUME if resume else 0) | (SR_RUN_FIXED_INNER if fixed_inner else 0))
         st = sr_run_stats()
         rc = lib().sr_run(self.h, ctypes.byref(p), ctypes.byref(st))
         d = st.as_dict()
@@ -284,6 +292,20 @@ class Graph:
         if check and rc not in (SR_OK,):
             _check(rc, self.ctx.h)
         return d
+
+    def sweeps(self) -> list:
+        """Per-sweep trace of the last run: pass, phase, changed/attempted/skipped vertices,
+        scanned edges, weak-predictor state histogram, PageRank L1."""
+        cnt = ctypes.c_int32()
+        _check(lib().sr_run_sweeps(self.h, None, 0, ctypes.byref(cnt)), self.ctx.h)
+        arr = (sr_sweep_record * max(cnt.value, 1))()
+        _check(lib().sr_run_sweeps(self.h, arr, cnt.value, ctypes.byref(cnt)), self.ctx.h)
+        out = []
+        for i in range(cnt.value):
+            r = arr[i]
+            out.append({"pass": r.pass_, "phase": r.phase, "changed": r.changed, "attempted": r.attempted,
+                        "skipped": r.skipped, "edges": r.edges, "state_hist": list(r.state_hist), "l1": r.l1})
+        return out
 
     def values(self, dtype=None) -> np.ndarray:
         out = np.empty(self.n, dtype=np.uint32)

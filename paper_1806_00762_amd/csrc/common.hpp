@@ -31,9 +31,11 @@ constexpr int BLOCK = 256;        // threads per workgroup (4 wavefronts)
 constexpr int WAVES = BLOCK / 64;
 
 // Tiles of the single-instance sweep: runs of consecutive non-heavy
-// vertices with at most TILE_V vertices and TILE_E in-edges, one block each.
+// vertices with at most TILE_V vertices and tile_e in-edges (a page
+// parameter, TILE_E_MIN or TILE_E_MAX), one block each.
 constexpr int TILE_V = 2 * BLOCK;
-constexpr int TILE_E = HEAVY;
+constexpr int TILE_E_MIN = 8 * BLOCK;
+constexpr int TILE_E_MAX = 16 * BLOCK;
 
 // vertices per block for bins 0..6 and chunks per block for bin 7
 constexpr int SMALL_ROUNDS = 4;   // vertices per lane group in bins 0..5
@@ -93,6 +95,7 @@ struct alignas(256) PageHeader {
   int32_t max_indeg;
   int32_t n_tiles;
   int32_t w_bytes;               // 1 (all weights < 256, stored as u8) or 4
+  int32_t tile_e;                // in-edge cap of a tile: TILE_E_MIN or TILE_E_MAX
 };
 static_assert(sizeof(PageHeader) == 256, "page header is one 256-byte line");
 

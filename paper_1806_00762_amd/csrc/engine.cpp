@@ -399,7 +399,20 @@ struct Runner {
     for (;;) {
       const SweepRecord &r = c->ring_host[seq_next & c->ring_mask];
       if (r.seq != seq_next) break;
-      if (r.attempted + r.skipped > 0 || r.edges > 0) st.sweeps++;
+      if (r.attempted + r.skipped > 0 || r.edges > 0) {
+        st.sweeps++;
+        sr_sweep_record sw;
+        std::memset(&sw, 0, sizeof(sw));
+        sw.pass = (int32_t)(r.pass_l1_closed >= 0.0 ? r.pass_after - 1 : r.pass_after);
+        sw.phase = (int32_t)r.phase;
+        sw.changed = (int64_t)r.changed;
+        sw.attempted = (int64_t)r.attempted;
+        sw.skipped = (int64_t)r.skipped;
+        sw.edges = (int64_t)r.edges;
+        for (int i = 0; i < 8; ++i) sw.state_hist[i] = (int64_t)r.hist[i];
+        sw.l1 = r.l1;
+        g->sweeps.push_back(sw);
+      }
       st.edges_scanned += (int64_t)r.edges;
       st.vertices_attempted += (int64_t)r.attempted;
       st.vertices_skipped += (int64_t)r.skipped;
@@ -462,6 +475,7 @@ struct Runner {
     }
     a.blk = g->state.blk;
     a.nblocks = std::max<int32_t>(blk, 1);  // an empty window still closes its sweep
+    a.tile_e = pages.empty() ? TILE_E_MIN : g->pages[pages[0]].hdr.tile_e;
     if (a.nblocks > g->state.blk_cap) return c->fail(SR_EINVAL, "internal: block records too small");
     return SR_OK;
   }
@@ -586,7 +600,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (p.max_passes == 0) p.max_passes = 10000;
   if (p.max_inner_iters == 0) p.max_inner_iters = 4;
   if (p.max_passes < 0 || p.max_inner_iters < 0) return c->fail(SR_EINVAL, "negative limits");
-  if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_FORCE_STREAM | SR_RUN_RESUME))
+  if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_FORCE_STREAM | SR_RUN_RESUME | SR_RUN_FIXED_INNER))
     return c->fail(SR_EINVAL, "unknown run flags");
   const bool pr = R.algo == A_PR || R.algo == A_PPR;
   if (p.pvu == SR_PVU_DEFAULT) p.pvu = (R.algo == A_BFS || R.algo == A_CC) ? SR_PVU_STRONG : SR_PVU_WEAK;
@@ -693,6 +707,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (e != hipSuccess) return c->hip_fail(e, "init");
   // fresh record numbering for this run
   for (uint32_t i = 0; i < RING; ++i) c->ring_host[i].seq = ~0ull;
+  g->sweeps.clear();
   R.seq_next = 0;
   rs.valid = true;
 
@@ -775,6 +790,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       return best;
     };
     int32_t pass = 0;
+    const bool fixed_inner = (p.flags & SR_RUN_FIXED_INNER) != 0;
     std::vector<int32_t> ord(P);
     while (!done) {
       for (int32_t i = 0; i < P; ++i) ord[i] = i;
@@ -807,6 +823,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
           if (done) break;
           bool changed = false;
           for (uint64_t q = before; q < R.seq_next; ++q) changed |= c->ring_host[q & c->ring_mask].changed > 0;
+          if (fixed_inner) continue;                // fixed re-entry count (ablation schedules)
           if (!changed) break;                      // the window reached its local fixed point
           if (!copying) break;                      // nothing in flight to wait for
           if (hipEventQuery(copy_done[next_slot]) == hipSuccess) break;  // next page landed: slide
@@ -828,6 +845,14 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (stats) *stats = R.st;
   if (R.st.stop_reason == SR_STOP_MAX_PASSES || !done)
     return c->fail(SR_ENOTCONV, "max_passes reached before convergence");
+  return SR_OK;
+}
+
+extern "C" sr_status sr_run_sweeps(const sr_graph *g, sr_sweep_record *out, int32_t max, int32_t *count) {
+  if (!g || !count || max < 0 || (max > 0 && !out)) return g ? g->ctx->fail(SR_EINVAL, "bad arguments") : SR_EINVAL;
+  const int32_t n = (int32_t)g->sweeps.size();
+  for (int32_t i = 0; i < std::min(n, max); ++i) out[i] = g->sweeps[i];
+  *count = n;
   return SR_OK;
 }
 

@@ -97,6 +97,7 @@ struct sr_graph {
   sr::Residency res;
   sr::RunState state;
   int server_refs = 0;  // servers holding the resident pages (no re-residency meanwhile)
+  std::vector<sr_sweep_record> sweeps;  // per-sweep trace of the last run
 };
 
 namespace sr {
@@ -107,6 +108,7 @@ sr_status make_pages(sr_graph *g, int32_t nparts);
 void free_pages(sr_graph *g);
 uint64_t graph_bytes(const sr_graph *g);
 int host_threads();
+int tile_edges();
 // engine.cpp
 sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream, bool bins = false);
 void release_residency(sr_graph *g);

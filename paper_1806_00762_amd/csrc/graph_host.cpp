@@ -34,6 +34,13 @@ static void parallel_for(int64_t n, int T, F f, int64_t min_n = 4096) {
   for (auto &x : th) x.join();
 }
 
+// In-edges per tile (SR_TILE_E = 2048 or 4096; 2048 unless set).
+int tile_edges() {
+  const char *e = getenv("SR_TILE_E");
+  if (e && atoi(e) >= TILE_E_MAX) return TILE_E_MAX;
+  return TILE_E_MIN;
+}
+
 uint64_t graph_bytes(const sr_graph *g) {
   return 4ull * ((uint64_t)g->n + 1) + 4ull * (uint64_t)g->m * (g->weighted ? 2 : 1);
 }
@@ -213,7 +220,7 @@ static void fill_page(const sr_graph *g, int32_t vb, int32_t ve, Page &pg) {
         if (open) { tl[2 * nt] = t0; tl[2 * nt + 1] = i; nt++; open = false; }
         continue;
       }
-      if (open && (tv + 1 > TILE_V || te + d > TILE_E)) { tl[2 * nt] = t0; tl[2 * nt + 1] = i; nt++; open = false; }
+      if (open && (tv + 1 > TILE_V || te + d > h.tile_e)) { tl[2 * nt] = t0; tl[2 * nt + 1] = i; nt++; open = false; }
       if (!open) { open = true; t0 = i; tv = 0; te = 0; }
       tv++; te += d;
     }
@@ -258,6 +265,7 @@ static PageHeader page_header(const sr_graph *g, int32_t vb, int32_t ve) {
     s += h.bin_count[b];
   }
   h.w_bytes = g->weighted ? (g->w8 ? 1 : 4) : 0;
+  h.tile_e = tile_edges();
   uint64_t o = sizeof(PageHeader);
   h.off_offsets = o; o = align256(o + 4ull * ((uint64_t)h.n_p + 1));
   // tiles: greedy runs of consecutive non-heavy vertices
@@ -268,7 +276,7 @@ static PageHeader page_header(const sr_graph *g, int32_t vb, int32_t ve) {
     for (int32_t v = vb; v < ve; ++v) {
       int64_t d = g->in_off[v + 1] - g->in_off[v];
       if (d > HEAVY) { if (open) { nt++; open = false; } continue; }
-      if (open && (tv + 1 > TILE_V || te + d > TILE_E)) { nt++; open = false; }
+      if (open && (tv + 1 > TILE_V || te + d > h.tile_e)) { nt++; open = false; }
       if (!open) { open = true; tv = 0; te = 0; }
       tv++; te += d;
     }

@@ -205,16 +205,15 @@ __device__ inline void epilogue(const Run &r, int32_t v, const Gate &g, bool com
 }
 
 // ------------------------------------------------------------------ tiles
-// One block per tile of consecutive vertices (<= TILE_V vertices, <= TILE_E
+// One block per tile of consecutive vertices (<= TILE_V vertices, <= tile_e
 // in-edges). Phase 1 gates the vertices (two consecutive ones per thread)
 // and compacts the attempting ones with a block-wide scan into LDS. Phase 2
-// assigns every thread 8 consecutive positions of the compacted edge list
+// assigns every thread tile_e/256 consecutive positions of the compacted edge list
 // (merge-path style: one binary search, then a forward walk), so the in-edge
-// reads of a wavefront cover one contiguous range; the 8 source loads and 8
+// reads of a wavefront cover one contiguous range; the source loads and
 // gathers of a thread are independent, and runs of edges of the same vertex
 // are reduced in registers before one LDS atomic. Phase 3 runs the
 // epilogues.
-constexpr int EDGES_PER_THREAD = TILE_E / BLOCK;
 
 struct TileLds {
   int32_t pos[TILE_V + 1];  // first compacted edge position of each attempting vertex
@@ -227,7 +226,7 @@ struct TileLds {
   int32_t wsum[WAVES][2];
 };
 
-template <int ALGO>
+template <int ALGO, int EDGES_PER_THREAD>
 __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, TileLds &s) {
   using R = Red<ALGO>;
   using T = typename R::T;
@@ -290,7 +289,7 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
   }
   if (tid == 0) s.pos[Kt] = At;
   __syncthreads();
-  // phase 2: 8 consecutive compacted edge positions per thread
+  // phase 2: EDGES_PER_THREAD consecutive compacted edge positions per thread
   const int p0 = tid * EDGES_PER_THREAD;
   if (p0 < At) {
     int lo = 0, hi = Kt;  // pos[lo] <= p0 < pos[hi]
@@ -474,7 +473,7 @@ __device__ inline void publish_record(const SweepRecord *src, SweepRecord *dst) 
 }
 
 // ------------------------------------------------------------ the sweep
-template <int ALGO>
+template <int ALGO, int EPT>
 __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   Ctl *ctl = a.ctl;
   if (ctl->done) return;  // converged: every block leaves before counting
@@ -530,7 +529,7 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   // a launch over pages without any work still runs one block, so the
   // sweep (and the pass) is closed the same way
   if (b < a.blk_prefix[a.nent * NSEC]) {
-    if (sec == 0) sweep_tile<ALGO>(r, p, item, acc, s_tile);
+    if (sec == 0) sweep_tile<ALGO, EPT>(r, p, item, acc, s_tile);
     else sweep_chunk<ALGO>(r, p, item);
   }
 
@@ -727,7 +726,10 @@ __global__ void init_ctl_kernel(Ctl *ctl, Ctl init) {
 
 template <int ALGO>
 static void launch_pair(const SweepArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(sweep_kernel<ALGO>, dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+  if (a.tile_e == TILE_E_MAX)
+    hipLaunchKernelGGL((sweep_kernel<ALGO, TILE_E_MAX / BLOCK>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+  else
+    hipLaunchKernelGGL((sweep_kernel<ALGO, TILE_E_MIN / BLOCK>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
   hipLaunchKernelGGL(close_kernel<ALGO>, dim3(1), dim3(CLOSE_THREADS), 0, s, a);
 }
 
