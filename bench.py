@@ -31,6 +31,24 @@ H2D_PEAK_GBS = 64.0        # PCIe 5.0 x16, one direction, nominal
 METRIC = "GTEPS & HBM GB/s fraction per subgraph pass; batched/served vs plain solves/s"
 
 
+def kernel_traffic(name):
+    """HBM traffic of a launch of the sweep kernel, from the rocprofv3 counter
+    summary committed under profiles/ (FETCH_SIZE and WRITE_SIZE per dispatch,
+    scaled by the copy-kernel calibration). None when the kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name + "_traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    j = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1806_00762_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != j["source_sha256"]:
+        return None, None
+    return j["traffic_bytes_per_launch"], j["algo_bytes_per_launch_same_runs"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -55,7 +73,8 @@ def bench_sssp22(args):
     info = G.info()
     log(f"[bench] loaded+partitioned in {time.perf_counter() - t:.1f}s: {info['num_parts']} pages, "
         f"budget {budget / 1e6:.1f} MB, graph {gbytes / 1e6:.1f} MB")
-    run_kw = dict(source=0, pvu=args.pvu, max_inner_iters=args.inner, force_stream=True)
+    run_kw = dict(source=0, pvu=args.pvu, max_inner_iters=args.inner, force_stream=True,
+                  copy_depth=args.copy_depth)
     for i in range(args.warmup):
         st = G.run("sssp", **run_kw)
         log(f"[bench] warmup {i}: {st['wall_ms']:.1f} ms, passes {st['passes']}")
@@ -77,6 +96,7 @@ def bench_sssp22(args):
     h2d_ms = sum(s["h2d_ms"] for s in stats)
     scanned = sum(s["edges_scanned"] for s in stats)
     achieved = algo_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic, traffic_algo = kernel_traffic("sweep_kernel_sssp_rmat22_streamed")
     res = {
         "metric": METRIC,
         "value": round(g.m * args.steps / elapsed / 1e9, 4),
@@ -93,10 +113,11 @@ def bench_sssp22(args):
         "config": {"workload": "sssp_rmat22_ef16_w1-255_src0_streamed_budget_quarter",
                    "n": g.n, "m": g.m, "pages": info["num_parts"], "slots": args.slots,
                    "device_budget_bytes": budget, "graph_bytes": gbytes,
-                   "pvu": args.pvu, "max_inner_iters": args.inner},
+                   "pvu": args.pvu, "max_inner_iters": args.inner, "copy_depth": args.copy_depth},
         "roofline": {"bound": "hbm", "kernel": "sweep_kernel<SSSP>",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_algo_bytes_per_launch": traffic_algo,
                      "algo_bytes_per_launch": round(algo_bytes / max(sweeps, 1)),
                      "avg_launch_us": round(kernel_ms * 1e3 / max(sweeps, 1), 2)},
         "h2d": {"achieved": round(h2d_bytes / (h2d_ms * 1e-3) / 1e9, 2) if h2d_ms else None,
@@ -107,20 +128,24 @@ def bench_sssp22(args):
         "passes_per_solve": stats[-1]["passes"],
         "sweeps_per_solve": stats[-1]["sweeps"],
     }
-    other = "weak" if args.pvu == "strong" else "strong"
-    okw = dict(run_kw, pvu=other)
-    G.run("sssp", **okw)
-    sync()
-    t0 = time.perf_counter()
-    ost = [G.run("sssp", **okw) for _ in range(args.steps)]
-    sync()
-    oel = time.perf_counter() - t0
-    assert np.array_equal(G.values(), dist)
-    res["pvu_" + other] = {"solve_gteps": round(g.m * args.steps / oel / 1e9, 4),
-                           "ms_per_solve": round(oel * 1e3 / args.steps, 3),
-                           "passes_per_solve": ost[-1]["passes"],
-                           "h2d_bytes_per_solve": ost[-1]["h2d_bytes"],
-                           "sweep_GBps": round(sum(s["algo_bytes"] for s in ost) / (sum(s["kernel_ms"] for s in ost) * 1e-3) / 1e9, 1)}
+    if not args.no_other:
+        other = "weak" if args.pvu == "strong" else "strong"
+        okw = dict(run_kw, pvu=other)
+        G.run("sssp", **okw)
+        sync()
+        t0 = time.perf_counter()
+        ost = [G.run("sssp", **okw) for _ in range(args.steps)]
+        sync()
+        oel = time.perf_counter() - t0
+        assert np.array_equal(G.values(), dist)
+        res["pvu_" + other] = {"solve_gteps": round(g.m * args.steps / oel / 1e9, 4),
+                               "ms_per_solve": round(oel * 1e3 / args.steps, 3),
+                               "passes_per_solve": ost[-1]["passes"],
+                               "h2d_bytes_per_solve": ost[-1]["h2d_bytes"],
+                               "sweep_GBps": round(sum(s["algo_bytes"] for s in ost) /
+                                                   (sum(s["kernel_ms"] for s in ost) * 1e-3) / 1e9, 1)}
+    if args.ablation:
+        res["ablation"] = ablation(args, G, info["num_parts"], dist)
     if args.resident:
         ctx2 = sr.Context(0, 0)
         G2 = ctx2.load(g)
@@ -143,16 +168,62 @@ def bench_sssp22(args):
         ctx2.close()
     if not args.no_cpu:
         import oracle
+        solves = 0
         t0 = time.perf_counter()
-        ref = oracle.sssp(g, 0)
-        tc = time.perf_counter() - t0
-        res["cpu_baseline"] = {"value": round(g.m / tc / 1e9, 5), "unit": "GTEPS", "cores": 1,
+        while True:
+            ref = oracle.sssp(g, 0)
+            solves += 1
+            tc = time.perf_counter() - t0
+            if tc >= args.cpu_seconds:
+                break
+        res["cpu_baseline"] = {"value": round(g.m * solves / tc / 1e9, 5), "unit": "GTEPS", "cores": 1,
                                "kind": "oracle",
-                               "sample": f"one full Dijkstra solve of the same graph from vertex 0 ({tc:.2f} s)"}
+                               "sample": f"{solves} full Dijkstra solves of the same graph from vertex 0 "
+                                         f"({tc:.1f} s, one thread)"}
         res["parity"] = "bit-exact" if np.array_equal(ref, dist) else f"MISMATCH {int(np.sum(ref != dist))}"
     G.close()
     ctx.close()
     return res
+
+
+def ablation(args, G, parts, dist):
+    """Section 5.4 schedules on the same streamed pages (same page count):
+    baseline = two slots, each page swept once per pass; rsi = two slots, each
+    page re-entered MRT = 2 times (the paper's MRT for SSSP); psi = the
+    pipelined window of S-1 pages with adaptive re-entry, prediction off; then
+    psi with each predictor. Reports solve time, passes, sweeps, streamed bytes,
+    and for the weak predictor the per-pass changed / skipped vertices (the
+    status curves of Fig. 10)."""
+    scheds = [("baseline", 2, 1, True, "off", 1), ("rsi_mrt2", 2, 2, True, "off", 1),
+              ("psi", args.slots, args.inner, False, "off", 1),
+              ("psi_strong", args.slots, args.inner, False, "strong", 1),
+              ("psi_weak", args.slots, args.inner, False, "weak", 1),
+              ("psi_strong_depth2", args.slots, args.inner, False, "strong", 2),
+              ("psi_strong_s5_depth2", 5, args.inner, False, "strong", 2)]
+    out = {}
+    for name, slots, inner, fixed, pvu, depth in scheds:
+        G.partition(parts, slots)
+        kw = dict(source=0, pvu=pvu, max_inner_iters=inner, force_stream=True, fixed_inner=fixed,
+                  copy_depth=depth)
+        G.run("sssp", **kw)
+        sync()
+        t0 = time.perf_counter()
+        st = G.run("sssp", **kw)
+        sync()
+        el = time.perf_counter() - t0
+        assert np.array_equal(G.values(), dist), name
+        row = {"ms_per_solve": round(el * 1e3, 2), "passes": st["passes"], "sweeps": st["sweeps"],
+               "edges_scanned": st["edges_scanned"], "h2d_bytes": st["h2d_bytes"],
+               "kernel_ms": round(st["kernel_ms"], 2), "h2d_ms": round(st["h2d_ms"], 2)}
+        if pvu == "weak":
+            tr = G.sweeps()
+            np_ = st["passes"]
+            row["per_pass_changed"] = [sum(r["changed"] for r in tr if r["pass"] == k) for k in range(np_)]
+            row["per_pass_skipped"] = [sum(r["skipped"] for r in tr if r["pass"] == k) for k in range(np_)]
+        out[name] = row
+        log(f"[bench] ablation {name}: {row['ms_per_solve']} ms, {row['passes']} passes, {row['sweeps']} sweeps")
+    G.partition(parts, args.slots)
+    return out
 
 
 def bench_batched(args):
@@ -338,10 +409,17 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (for HBM counter scaling)")
     ap.add_argument("--served-timeout", type=float, default=90.0)
+    ap.add_argument("--copy-depth", type=int, default=1,
+                    help="page copies kept in flight ahead of the window (1 = the paper's layout)")
+    ap.add_argument("--no-other", action="store_true", help="skip the other predictor's solves")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also time the Section 5.4 schedules (baseline, re-entry, pipelined, +predictors)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU work of the oracle baseline (repeated solves)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this engine runs a single device "
-              "(see DESIGN.md for how the pass would shard over several).", file=sys.stderr)
+        print("bench.py measures one GPU only: the engine runs on a single device; "
+              "run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.init()

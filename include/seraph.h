@@ -141,16 +141,18 @@ sr_status sr_graph_info_get(const sr_graph *g, sr_graph_info *out);
 
 /* Read-only view of page `page` (host pointers into the graph's pinned
  * pages; valid until the graph is repartitioned or destroyed). offsets are
- * rebased to 0 (n_p + 1 entries); src holds global source vertex ids.
- * Weights are stored as uint8 when every weight of the graph is below 256
- * (lossless; fewer bytes to stream), else as uint32. */
+ * rebased to 0 (n_p + 1 entries); src holds one 32-bit word per in-edge.
+ * When every weight of the graph is below 256 and n <= 2^24, the weight is
+ * packed into the edge word (lossless; 4 instead of 8 bytes per weighted
+ * edge to stream): src_packed = 1, word = source | weight << 24, weights =
+ * NULL. Otherwise src holds the source id and weights (uint32) follow. */
 typedef struct {
   int32_t v_begin, v_end;    /* destination vertex range [v_begin, v_end) */
   int64_t num_edges;
   const int32_t *offsets;
-  const int32_t *src;
-  const void *weights;       /* NULL if unweighted */
-  int32_t weight_bytes;      /* 1 or 4 (0 if unweighted) */
+  const uint32_t *src;       /* source id, or source | weight << 24 when src_packed */
+  const uint32_t *weights;   /* NULL if unweighted or packed */
+  int32_t src_packed;        /* 1: weights live in the top byte of src */
   uint64_t bytes;            /* bytes of the page buffer */
   uint64_t stream_bytes;     /* prefix a single-instance sweep copies (with weights) */
 } sr_page_view;
@@ -180,11 +182,14 @@ typedef struct {
   double damping;            /* PageRank d (0 = 0.85) */
   double tol_l1;             /* PageRank stop: L1 change of a full pass (0 = 1e-9) */
   int32_t max_passes;        /* 0 = 10000 */
-  int32_t max_inner_iters;   /* sweeps of a window before it slides (A4 re-entry bound); 0 = 4 */
+  int32_t max_inner_iters;   /* sweeps of a window before it slides (Section 3.2 re-entry bound); 0 = 4 */
   sr_pvu_mode pvu;
   const sr_pvu_diagram *diagram; /* NULL = default diagram */
   float pr_change_eps;       /* PageRank: |new-old| > eps counts as a valid update */
   uint32_t flags;            /* SR_RUN_* */
+  int32_t copy_depth;        /* streamed pages: copies kept in flight ahead of the window (0 = 1,
+                                the paper's S-1 computing + 1 transferring slots); with depth D
+                                the window holds num_slots - D pages. 1 <= D < num_slots. */
 } sr_run_params;
 
 typedef struct {

@@ -46,9 +46,9 @@ class sr_graph_info(ctypes.Structure):
 
 class sr_page_view(ctypes.Structure):
     _fields_ = [("v_begin", ctypes.c_int32), ("v_end", ctypes.c_int32), ("num_edges", ctypes.c_int64),
-                ("offsets", ctypes.POINTER(ctypes.c_int32)), ("src", ctypes.POINTER(ctypes.c_int32)),
-                ("weights", ctypes.c_void_p), ("weight_bytes", ctypes.c_int32), ("bytes", ctypes.c_uint64),
-                ("stream_bytes", ctypes.c_uint64)]
+                ("offsets", ctypes.POINTER(ctypes.c_int32)), ("src", ctypes.POINTER(ctypes.c_uint32)),
+                ("weights", ctypes.POINTER(ctypes.c_uint32)), ("src_packed", ctypes.c_int32),
+                ("bytes", ctypes.c_uint64), ("stream_bytes", ctypes.c_uint64)]
 
 
 class sr_pvu_diagram(ctypes.Structure):
@@ -62,7 +62,7 @@ class sr_run_params(ctypes.Structure):
                 ("tol_l1", ctypes.c_double), ("max_passes", ctypes.c_int32),
                 ("max_inner_iters", ctypes.c_int32), ("pvu", ctypes.c_int),
                 ("diagram", ctypes.POINTER(sr_pvu_diagram)), ("pr_change_eps", ctypes.c_float),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("copy_depth", ctypes.c_int32)]
 
 
 class sr_run_stats(ctypes.Structure):
@@ -261,18 +261,22 @@ class Graph:
         npv = v.v_end - v.v_begin
         off = np.ctypeslib.as_array(v.offsets, shape=(npv + 1,)).copy()
         ne = int(v.num_edges)
-        src = np.ctypeslib.as_array(v.src, shape=(ne,)).copy() if ne else np.zeros(0, np.int32)
+        words = np.ctypeslib.as_array(v.src, shape=(ne,)).copy() if ne else np.zeros(0, np.uint32)
         w = None
-        if v.weights and ne:
-            ct = ctypes.c_uint8 if v.weight_bytes == 1 else ctypes.c_uint32
-            w = np.ctypeslib.as_array(ctypes.cast(v.weights, ctypes.POINTER(ct)), shape=(ne,)).astype(np.uint32)
+        if v.src_packed:
+            src = (words & 0xFFFFFF).astype(np.int32)
+            w = (words >> 24).astype(np.uint32)
+        else:
+            src = words.view(np.int32)
+            if v.weights and ne:
+                w = np.ctypeslib.as_array(v.weights, shape=(ne,)).copy()
         return {"v_begin": v.v_begin, "v_end": v.v_end, "offsets": off, "src": src, "weights": w,
-                "weight_bytes": v.weight_bytes, "bytes": int(v.bytes), "stream_bytes": int(v.stream_bytes)}
+                "src_packed": bool(v.src_packed), "bytes": int(v.bytes), "stream_bytes": int(v.stream_bytes)}
 
     def run(self, algo, source: int = 0, pvu="default", damping: float = 0.85, tol_l1: float = 1e-9,
             max_passes: int = 0, max_inner_iters: int = 0, diagram: Optional[sr_pvu_diagram] = None,
             pr_change_eps: float = 0.0, audit: bool = False, force_stream: bool = False,
-            resume: bool = False, fixed_inner: bool = False, check: bool = True) -> dict:
+            resume: bool = False, fixed_inner: bool = False, copy_depth: int = 0, check: bool = True) -> dict:
         p = sr_run_params()
         p.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
         p.source = source
@@ -285,6 +289,7 @@ class Graph:
         p.pr_change_eps = pr_change_eps
         p.flags = ((SR_RUN_AUDIT_PVU if audit else 0) | (SR_RUN_FORCE_STREAM if force_stream else 0)
                    | (SR_RUN_RESUME if resume else 0) | (SR_RUN_FIXED_INNER if fixed_inner else 0))
+        p.copy_depth = copy_depth
         st = sr_run_stats()
         rc = lib().sr_run(self.h, ctypes.byref(p), ctypes.byref(st))
         d = st.as_dict()

@@ -177,6 +177,13 @@ __device__ inline void mi_flush(MiLds *lds, int group, MiAcc &acc) {
 
 // bins 0..5: GE edge lanes per vertex (GE = min(2^b, 64/K)), MI_ROUNDS
 // rounds of 64/K/GE vertices per wavefront
+// Weight of in-edge e with edge word q (1 for unweighted programs).
+template <int ALGO>
+__device__ inline uint32_t mi_weight(const MiGroup &g, uint32_t q, const uint32_t *wt, int32_t e) {
+  if (ALGO != A_SSSP || !g.has_w) return 1u;
+  return g.packed ? q >> 24 : wt[e];
+}
+
 template <int ALGO, int K, int GE>
 __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h, int bin, int item,
                          const Lane &ln, float damping, MiAcc &acc) {
@@ -188,7 +195,7 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
   const int k = lane % K, el = lane / K, vs = el / GE, ein = el % GE;
   const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
   const int32_t *bins = reinterpret_cast<const int32_t *>(base + h->off_bins) + h->bin_start[bin];
-  const int32_t *src = reinterpret_cast<const int32_t *>(base + h->off_src);
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(base + h->off_src);
   const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
   const int cnt = h->bin_count[bin];
   const int vb = h->v_begin;
@@ -211,9 +218,8 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
     T x = R::identity();
     if (att[r]) {
       for (int e = beg[r] + ein; e < end[r]; e += GE) {
-        int32_t u = src[e];
-        uint32_t w = (ALGO == A_SSSP && g.has_w) ? (g.w8 ? (uint32_t)reinterpret_cast<const uint8_t *>(wt)[e] : wt[e]) : 1u;
-        x = R::combine(x, R::edge(g, u, w, k, ln));
+        const uint32_t q = src[e];
+        x = R::combine(x, R::edge(g, (int32_t)(q & g.src_mask), mi_weight<ALGO>(g, q, wt, e), k, ln));
       }
     }
 #pragma unroll
@@ -225,7 +231,7 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
 
 // edge loop of bins 6 and 7: 64/K edge lanes, 4 edges in flight per lane
 template <int ALGO, int K>
-__device__ inline typename MiRed<ALGO, K>::T mi_edges(const MiGroup &g, const int32_t *src, const uint32_t *wt,
+__device__ inline typename MiRed<ALGO, K>::T mi_edges(const MiGroup &g, const uint32_t *src, const uint32_t *wt,
                                                       int32_t e0, int32_t e1, int k, int el, const Lane &ln) {
   using R = MiRed<ALGO, K>;
   using T = typename R::T;
@@ -233,24 +239,17 @@ __device__ inline typename MiRed<ALGO, K>::T mi_edges(const MiGroup &g, const in
   T x = R::identity();
   int e = e0 + el;
   for (; e + 3 * EL < e1; e += 4 * EL) {
-    int32_t u0 = src[e], u1 = src[e + EL], u2 = src[e + 2 * EL], u3 = src[e + 3 * EL];
-    uint32_t w0 = 1, w1 = 1, w2 = 1, w3 = 1;
-    if (ALGO == A_SSSP && g.has_w) {
-      if (g.w8) {
-        const uint8_t *w8 = reinterpret_cast<const uint8_t *>(wt);
-        w0 = w8[e]; w1 = w8[e + EL]; w2 = w8[e + 2 * EL]; w3 = w8[e + 3 * EL];
-      } else {
-        w0 = wt[e]; w1 = wt[e + EL]; w2 = wt[e + 2 * EL]; w3 = wt[e + 3 * EL];
-      }
-    }
-    T y0 = R::edge(g, u0, w0, k, ln), y1 = R::edge(g, u1, w1, k, ln);
-    T y2 = R::edge(g, u2, w2, k, ln), y3 = R::edge(g, u3, w3, k, ln);
+    const uint32_t q0 = src[e], q1 = src[e + EL], q2 = src[e + 2 * EL], q3 = src[e + 3 * EL];
+    const uint32_t w0 = mi_weight<ALGO>(g, q0, wt, e), w1 = mi_weight<ALGO>(g, q1, wt, e + EL);
+    const uint32_t w2 = mi_weight<ALGO>(g, q2, wt, e + 2 * EL), w3 = mi_weight<ALGO>(g, q3, wt, e + 3 * EL);
+    const uint32_t m = g.src_mask;
+    T y0 = R::edge(g, (int32_t)(q0 & m), w0, k, ln), y1 = R::edge(g, (int32_t)(q1 & m), w1, k, ln);
+    T y2 = R::edge(g, (int32_t)(q2 & m), w2, k, ln), y3 = R::edge(g, (int32_t)(q3 & m), w3, k, ln);
     x = R::combine(x, R::combine(R::combine(y0, y1), R::combine(y2, y3)));
   }
   for (; e < e1; e += EL) {
-    uint32_t w = 1u;
-    if (ALGO == A_SSSP && g.has_w) w = g.w8 ? (uint32_t)reinterpret_cast<const uint8_t *>(wt)[e] : wt[e];
-    x = R::combine(x, R::edge(g, src[e], w, k, ln));
+    const uint32_t q = src[e];
+    x = R::combine(x, R::edge(g, (int32_t)(q & g.src_mask), mi_weight<ALGO>(g, q, wt, e), k, ln));
   }
 #pragma unroll
   for (int m = K; m < 64; m <<= 1) x = R::combine(x, shfl_xor(x, m));
@@ -266,7 +265,7 @@ __device__ void mi_wave(const MiGroup &g, const char *base, const PageHeader *h,
   if (idx >= h->bin_count[BIN_WAVE]) return;
   const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
   const int32_t vl = reinterpret_cast<const int32_t *>(base + h->off_bins)[h->bin_start[BIN_WAVE] + idx];
-  const int32_t *src = reinterpret_cast<const int32_t *>(base + h->off_src);
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(base + h->off_src);
   const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
   const int32_t v = h->v_begin + vl;
   uint32_t old;
@@ -287,7 +286,7 @@ __device__ void mi_chunk(const MiGroup &g, const MiUnit &u, const char *base, co
   int idx = item * WAVES + wave;
   if (idx >= h->bin_count[BIN_CHUNK]) return;
   const Chunk c = reinterpret_cast<const Chunk *>(base + h->off_chunks)[idx];
-  const int32_t *src = reinterpret_cast<const int32_t *>(base + h->off_src);
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(base + h->off_src);
   const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
   const int32_t v = h->v_begin + c.vl;
   uint32_t old;

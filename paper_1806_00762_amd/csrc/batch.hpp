@@ -44,8 +44,9 @@ struct MiGroup {
   MiInst *inst;             // [K]
   int32_t n;
   int32_t pvu;              // P_OFF or P_STRONG
-  int32_t has_w;            // the resident pages carry weights (read only then)
-  int32_t w8;               // weights stored as u8
+  int32_t has_w;            // SSSP on weighted pages (weights read only then)
+  int32_t packed;           // edge words carry the weight in their top byte
+  uint32_t src_mask;        // source id bits of an edge word
 };
 
 // One unit of work: a resident page of a group's graph.

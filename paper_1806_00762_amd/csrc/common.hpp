@@ -62,17 +62,30 @@ struct Heavy {
 
 // Per-block sweep counters, written with plain stores by every block of a
 // sweep and reduced by the close kernel after the sweep has finished.
-struct BlockAcc {
-  uint32_t changed, attempted, skipped, mispred, edges, min_changed;
-  uint32_t hist[8];
-  double l1, ddelta;
+// Sweep counters: every block of a sweep adds its totals with device-scope
+// atomics into one of NSTRIPE stripes (block id modulo NSTRIPE), so no block
+// waits on another and no fence is needed; the close kernel reads each
+// stripe back and resets it with atomic exchanges. Floating sums travel as
+// fixed point (FIX_ONE = 2^54) so they add exactly and in any order.
+constexpr int NSTRIPE = 64;
+constexpr double FIX_ONE = 18014398509481984.0;  // 2^54
+struct alignas(128) Stripe {
+  unsigned long long ca;       // changed | attempted << 32
+  unsigned long long sm;       // skipped | mispred << 32
+  unsigned long long edges;
+  unsigned long long l1;       // PageRank: sum |delta|, fixed point
+  unsigned long long dd;       // PageRank: dangling-mass change, two's complement fixed point
+  unsigned long long hist[4];  // weak predictor states, two 32-bit counts per word
+  uint32_t min_changed;        // smallest new value among changed vertices (min programs)
 };
+static_assert(sizeof(Stripe) == 128, "one stripe per 128-byte line");
 
 // First 256 bytes of every page buffer. Section offsets are in bytes from
 // the buffer start, all multiples of 256. Sections are ordered so that each
 // use copies a prefix: header, offsets, tiles, chunks, heavy list, sources
 // (unweighted programs stop here), weights (single-instance sweeps stop
 // here), degree-bin lists (multi-instance sweeps).
+constexpr uint32_t PACKED_SRC_MASK = 0x00FFFFFFu;  // source id bits of a packed edge word
 struct alignas(256) PageHeader {
   uint32_t magic;
   int32_t v_begin;
@@ -84,8 +97,8 @@ struct alignas(256) PageHeader {
   uint64_t off_chunks;    // Chunk[n_chunks]
   uint64_t off_heavy;     // Heavy[n_heavy]: the vertices of bin 7, one entry each
   uint64_t off_tiles;     // int32 pairs [v_begin, v_end) of the n_tiles tiles
-  uint64_t off_src;       // int32[m_p], global source ids
-  uint64_t off_w;         // weights, w_bytes each (weighted graphs only)
+  uint64_t off_src;       // u32[m_p]: global source id, or source | weight << 24 when packed
+  uint64_t off_w;         // u32 weights (weighted graphs that are not packed)
   uint64_t bytes_unweighted;  // prefix a program without weights needs
   uint64_t bytes_weighted;    // prefix with weights (single-instance sweeps)
   uint64_t bytes_total;       // everything, bin lists of the multi-instance sweep included
@@ -94,8 +107,9 @@ struct alignas(256) PageHeader {
   int32_t n_heavy;               // vertices in bin 7
   int32_t max_indeg;
   int32_t n_tiles;
-  int32_t w_bytes;               // 1 (all weights < 256, stored as u8) or 4
+  int32_t w_bytes;               // 4: separate u32 weight section; 0: none (unweighted or packed)
   int32_t tile_e;                // in-edge cap of a tile: TILE_E_MIN or TILE_E_MAX
+  int32_t packed;                // edge words carry the weight in their top byte
 };
 static_assert(sizeof(PageHeader) == 256, "page header is one 256-byte line");
 
@@ -140,14 +154,9 @@ struct Ctl {
   uint32_t done;          // converged or stopped: sweeps become no-ops
   uint32_t pass;          // passes completed
   uint32_t stop_reason;
-  uint32_t blocks_done;
   uint32_t sweep_seq;
   uint32_t no_improve;
-  // current sweep accumulators
-  unsigned long long sw_changed, sw_edges, sw_attempted, sw_skipped, sw_mispred;
-  unsigned long long sw_hist[8];
-  uint32_t sw_min_changed, pad0;
-  double sw_l1, sw_ddelta;
+  uint32_t pad0;
   // current pass accumulators
   unsigned long long pass_changed;
   uint32_t pass_min_changed, pad1;
@@ -155,9 +164,10 @@ struct Ctl {
   double best_l1;
   double dangling;        // PageRank: D used by the sweeps
   // run constants
-  int32_t algo, pvu, max_passes, always_verify;
+  int32_t algo, pvu, max_passes, pad2;
   double tol_l1;
   double floor_cap;
 };
+static_assert(sizeof(Ctl) % 4 == 0, "the control block is copied as 32-bit words");
 
 }  // namespace sr

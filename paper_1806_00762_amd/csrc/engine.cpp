@@ -154,7 +154,7 @@ static void release_state(sr_graph *g) {
   g->ctx->dfree(s.inv_outdeg);
   g->ctx->dfree(s.status);
   g->ctx->dfree(s.ctl);
-  g->ctx->dfree(s.blk);
+  g->ctx->dfree(s.stripes);
   s = RunState();
 }
 
@@ -188,7 +188,7 @@ extern "C" sr_status sr_graph_load_csr(sr_ctx *c, int32_t n, int64_t m, const in
   if (st == SR_OK && g->weighted) {
     uint32_t mx = 0;
     for (uint32_t x : g->in_w) mx = std::max(mx, x);
-    g->w8 = mx <= 0xFFu;  // weights stored losslessly as u8 in the pages
+    g->packed = mx <= 0xFFu && (int64_t)g->n <= (int64_t)1 << 24;  // lossless packed edge words
   }
   if (st == SR_OK && (flags & SR_LOAD_SYMMETRIC)) {
     // the transpose of a symmetric graph with sorted rows is the graph itself
@@ -203,7 +203,7 @@ extern "C" sr_status sr_graph_load_csr(sr_ctx *c, int32_t n, int64_t m, const in
 }
 
 static uint64_t state_bytes(int32_t n, int algo) {
-  uint64_t b = 4ull * n + 1ull * n + sizeof(Ctl) + 4096;
+  uint64_t b = 4ull * n + 1ull * n + sizeof(Ctl) + sizeof(Stripe) * NSTRIPE + 4096;
   if (algo == A_PR || algo == A_PPR) b += 8ull * n;
   return b;
 }
@@ -215,7 +215,7 @@ static uint64_t need_bytes(const Page &p, bool weights, bool bins = false) {
 
 static uint64_t scratch_bytes(const Page &p) {
   uint64_t c = (uint64_t)std::max<int32_t>(p.hdr.n_chunks, 1);
-  return ((4 * c) + 255) & ~255ull;
+  return ((8 * c) + 255) & ~255ull;
 }
 
 extern "C" sr_status sr_graph_partition(sr_graph *g, int32_t nparts, int32_t nslots) {
@@ -277,9 +277,9 @@ extern "C" sr_status sr_graph_page(const sr_graph *g, int32_t page, sr_page_view
   o->v_end = p.hdr.v_begin + p.hdr.n_p;
   o->num_edges = p.hdr.m_p;
   o->offsets = (const int32_t *)(p.host + p.hdr.off_offsets);
-  o->src = (const int32_t *)(p.host + p.hdr.off_src);
-  o->weights = g->weighted ? (const void *)(p.host + p.hdr.off_w) : nullptr;
-  o->weight_bytes = g->weighted ? p.hdr.w_bytes : 0;
+  o->src = (const uint32_t *)(p.host + p.hdr.off_src);
+  o->weights = p.hdr.w_bytes == 4 ? (const uint32_t *)(p.host + p.hdr.off_w) : nullptr;
+  o->src_packed = p.hdr.packed;
   o->bytes = p.bytes;
   o->stream_bytes = p.hdr.bytes_weighted;
   return SR_OK;
@@ -319,16 +319,17 @@ struct Launch {
   int algo;
 };
 
-// Algorithmic bytes of one sweep (see DESIGN: per visited vertex the bin
-// entry and the gate read, per attempted vertex its two offsets, per
-// scanned edge the source id, the weight (SSSP) and the gathered value, per
-// changed vertex the value write; PageRank also writes rank and contrib and
-// reads 1/outdeg per attempted vertex).
-uint64_t algo_bytes(int algo, int pvu, const SweepRecord &r) {
-  uint64_t visited = r.attempted + r.skipped;
-  uint64_t eb = (algo == A_SSSP) ? 12 : 8;
-  uint64_t b = r.edges * eb + visited * 8 + r.attempted * 8;
-  if (pvu == P_WEAK) b += visited * 1;
+// Algorithmic bytes of one sweep: per visited vertex its offset and the
+// gate's value read (weak prediction: status read and write); per scanned
+// in-edge the edge word, a separate u32 weight when the page is not packed
+// (SSSP), and the gathered value; per changed vertex the value write;
+// PageRank also writes rank and contrib and reads 1/outdeg per attempted
+// vertex.
+uint64_t algo_bytes(int algo, int pvu, bool sep_weights, const SweepRecord &r) {
+  const uint64_t visited = r.attempted + r.skipped;
+  const uint64_t eb = (algo == A_SSSP && sep_weights) ? 12 : 8;
+  uint64_t b = r.edges * eb + visited * 8;
+  if (pvu == P_WEAK) b += visited * 2;
   if (algo == A_PR || algo == A_PPR) b += r.attempted * 12;
   else b += r.changed * 4;
   return b;
@@ -418,7 +419,7 @@ struct Runner {
       st.vertices_skipped += (int64_t)r.skipped;
       st.mispredicted += (int64_t)r.mispred;
       for (int i = 0; i < 8; ++i) st.state_hist[i] += (int64_t)r.hist[i];
-      st.algo_bytes += algo_bytes(algo, pvu, r);
+      st.algo_bytes += algo_bytes(algo, pvu, g->weighted && !g->packed, r);
       if (r.pass_l1_closed >= 0.0) {
         st.final_l1 = r.pass_l1_closed;
         if (r.phase == 1) st.verify_passes++;
@@ -473,10 +474,9 @@ struct Runner {
       a.base[i] = g->res.buf[slots[i]];
       a.partial[i] = g->res.partial[slots[i]];
     }
-    a.blk = g->state.blk;
+    a.stripes = g->state.stripes;
     a.nblocks = std::max<int32_t>(blk, 1);  // an empty window still closes its sweep
     a.tile_e = pages.empty() ? TILE_E_MIN : g->pages[pages[0]].hdr.tile_e;
-    if (a.nblocks > g->state.blk_cap) return c->fail(SR_EINVAL, "internal: block records too small");
     return SR_OK;
   }
 
@@ -493,7 +493,7 @@ static sr_status ensure_state(sr_graph *g, int algo) {
   sr_ctx *c = g->ctx;
   auto &s = g->state;
   const bool pr = algo == A_PR || algo == A_PPR;
-  if (s.n == g->n && s.value && s.ctl && (!pr || s.contrib)) {
+  if (s.n == g->n && s.value && s.ctl && s.stripes && (!pr || s.contrib)) {
     s.algo = algo;
     return SR_OK;
   }
@@ -502,6 +502,7 @@ static sr_status ensure_state(sr_graph *g, int algo) {
   if ((st = c->dalloc((void **)&s.value, 4ull * g->n, "vertex values")) != SR_OK) return st;
   if ((st = c->dalloc((void **)&s.status, 1ull * g->n, "predictor states")) != SR_OK) return st;
   if ((st = c->dalloc((void **)&s.ctl, sizeof(Ctl), "control block")) != SR_OK) return st;
+  if ((st = c->dalloc((void **)&s.stripes, sizeof(Stripe) * NSTRIPE, "counter stripes")) != SR_OK) return st;
   if (pr) {
     if ((st = c->dalloc((void **)&s.contrib, 4ull * g->n, "pagerank contrib")) != SR_OK) return st;
     if ((st = c->dalloc((void **)&s.inv_outdeg, 4ull * g->n, "pagerank 1/outdeg")) != SR_OK) return st;
@@ -551,7 +552,8 @@ sr_status sr::ensure_residency(sr_graph *g, bool weights, bool force_stream, boo
       if ((st = c->dalloc(&b, nb, "resident page")) != SR_OK) { release_residency(g); return st; }
       r.buf.push_back((char *)b);
       if ((st = c->dalloc(&pa, sc, "chunk partials")) != SR_OK) { release_residency(g); return st; }
-      r.partial.push_back((uint32_t *)pa);
+      r.partial.push_back((unsigned long long *)pa);
+      r.partial_words.push_back(sc / 8);
       hipError_t e = hipMemcpyAsync(b, p.host, nb, hipMemcpyHostToDevice, c->copy);
       if (e != hipSuccess) { release_residency(g); return c->hip_fail(e, "resident page copy"); }
       r.slot_page.push_back((int32_t)i);
@@ -574,7 +576,8 @@ sr_status sr::ensure_residency(sr_graph *g, bool weights, bool force_stream, boo
     if ((st = c->dalloc(&b, mx, "page slot")) != SR_OK) { release_residency(g); return st; }
     r.buf.push_back((char *)b);
     if ((st = c->dalloc(&pa, smx, "chunk partials")) != SR_OK) { release_residency(g); return st; }
-    r.partial.push_back((uint32_t *)pa);
+    r.partial.push_back((unsigned long long *)pa);
+    r.partial_words.push_back(smx / 8);
     r.slot_page.push_back(-1);
   }
   return SR_OK;
@@ -643,26 +646,9 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     }
   }
   if (s != SR_OK) return s;
-  {
-    // block records: the largest launch is a group of up to MAXW resident
-    // pages, or a window of num_slots-1 consecutive streamed pages
-    std::vector<int64_t> pb(g->pages.size());
-    for (size_t i = 0; i < g->pages.size(); ++i) pb[i] = sec_blocks(g->pages[i].hdr, 0) + sec_blocks(g->pages[i].hdr, 1);
-    const size_t win = g->res.resident ? (size_t)MAXW : (size_t)std::max(1, g->res.nslots - 1);
-    int64_t cap = 1;
-    for (size_t i = 0; i < pb.size(); ++i) {
-      int64_t sum = 0;
-      for (size_t j = i; j < std::min(pb.size(), i + win); ++j) sum += pb[j];
-      cap = std::max(cap, sum);
-    }
-    if (cap > g->state.blk_cap) {
-      c->dfree(g->state.blk);
-      g->state.blk = nullptr;
-      g->state.blk_cap = 0;
-      if ((s = c->dalloc((void **)&g->state.blk, sizeof(BlockAcc) * (uint64_t)cap, "block records")) != SR_OK) return s;
-      g->state.blk_cap = (int32_t)cap;
-    }
-  }
+  const int32_t depth = p.copy_depth == 0 ? 1 : p.copy_depth;
+  if (!g->res.resident && (depth < 1 || depth >= g->res.nslots))
+    return c->fail(SR_EINVAL, "copy_depth must be in [1, num_slots)");
 
   // initial values, predictor states and control block
   RunState &rs = g->state;
@@ -670,7 +656,6 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   std::memset(&init, 0, sizeof(init));
   init.threshold = 0;  // value 0 is final for every min program (source, global minimum label)
   init.phase = 0;
-  init.sw_min_changed = INF;
   init.pass_min_changed = INF;
   init.best_l1 = 1e300;
   init.algo = R.algo;
@@ -679,7 +664,6 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   init.tol_l1 = p.tol_l1;
   init.floor_cap = 1e-6;
   // a PageRank pass of single plain sweeps is already a verification pass
-  init.always_verify = 0;
   if (pr && R.pvu == P_OFF && (p.max_inner_iters == 1 || g->res.resident)) init.phase = 1;
   if (pr) {
     double D = 0.0;
@@ -704,6 +688,14 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     init.phase = init.phase;  // thresholds restart from the safe initial value
   }
   if (e == hipSuccess) e = launch_init_ctl(rs.ctl, init, c->compute);
+  if (e == hipSuccess) e = launch_init_stripes(rs.stripes, c->compute);
+  // heavy-vertex accumulators start at the reduction's identity (min: all
+  // ones; PageRank: fixed-point zero); the close kernel restores it after
+  // every sweep
+  for (size_t i = 0; i < g->res.partial.size() && e == hipSuccess; ++i) {
+    const uint64_t words = g->res.partial_words[i];
+    e = launch_fill_u32((uint32_t *)g->res.partial[i], pr ? 0u : INF, 2 * words, c->compute);
+  }
   if (e != hipSuccess) return c->hip_fail(e, "init");
   // fresh record numbering for this run
   for (uint32_t i = 0; i < RING; ++i) c->ring_host[i].seq = ~0ull;
@@ -738,16 +730,19 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       if (launched > p.max_passes + 8) break;
     }
   } else {
-    // Pipelined subgraph iteration (Section 3.2): a window of W = S-1 slots is
-    // swept while the next page is copied into the remaining slot; each window
-    // is swept until the copy lands (re-entry), max_inner_iters, or a sweep
-    // without change; then the window slides by one page. Pages go in
-    // increasing order every pass (in R-MAT graphs, whose low ids carry most
-    // edges, this order propagates furthest per pass); a page still in a slot
-    // from the previous pass is not copied again.
+    // Pipelined subgraph iteration (Section 3.2): a window of W = S-D slots is
+    // swept while the next D pages are copied into the remaining slots (the
+    // paper's layout is D = 1); each window is swept until the page it takes
+    // next has landed (re-entry), max_inner_iters, or a sweep without change;
+    // then the window slides by one page. Pages go in increasing order every
+    // pass (in R-MAT graphs, whose low ids carry most edges, this order
+    // propagates furthest per pass); the last steps of a pass already fetch
+    // the first pages of the next one, and a page still in a slot is not
+    // copied again.
     const int32_t P = (int32_t)g->pages.size();
     const int32_t S = g->res.nslots;
-    const int32_t W = S - 1;
+    const int32_t D = depth;
+    const int32_t W = S - D;
     std::vector<hipEvent_t> copy_done(S, nullptr);
     hipEvent_t step_done = nullptr;
     std::vector<hipEvent_t> own;
@@ -777,13 +772,12 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       R.st.h2d_bytes += nb;
       return SR_OK;
     };
-    // a slot for `page` that no page of the current window occupies (least
-    // recently used first)
-    auto free_slot = [&](const std::vector<int32_t> &window) -> int32_t {
+    // a slot that holds none of the pages in `keep` (least recently used first)
+    auto free_slot = [&](const std::vector<int32_t> &keep) -> int32_t {
       int32_t best = -1;
       for (int32_t sl = 0; sl < S; ++sl) {
         bool used = false;
-        for (int32_t q : window) used |= page_slot[q] == sl;
+        for (int32_t q : keep) used |= page_slot[q] == sl;
         if (used) continue;
         if (best < 0 || last_use[sl] < last_use[best]) best = sl;
       }
@@ -792,8 +786,8 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     int32_t pass = 0;
     const bool fixed_inner = (p.flags & SR_RUN_FIXED_INNER) != 0;
     std::vector<int32_t> ord(P);
+    for (int32_t i = 0; i < P; ++i) ord[i] = i;
     while (!done) {
-      for (int32_t i = 0; i < P; ++i) ord[i] = i;
       // pass start: every earlier sweep has finished (host synced at the pass end)
       if (page_slot[ord[0]] < 0) {
         if ((s = copy_page(ord[0], free_slot({}), false)) != SR_OK) return s;
@@ -802,14 +796,22 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
         std::vector<int32_t> win;
         for (int32_t q = std::max(0, j - W + 1); q <= j; ++q) win.push_back(ord[q]);
         for (int32_t q : win) HIP_TRY(c, hipStreamWaitEvent(c->compute, copy_done[page_slot[q]], 0), "compute wait");
-        bool copying = false;
-        int32_t next_slot = -1;
-        if (j + 1 < P && page_slot[ord[j + 1]] < 0) {
-          // the free slot was last read by the previous step's sweeps
-          next_slot = free_slot(win);
-          if ((s = copy_page(ord[j + 1], next_slot, j > 0 || pass > 0)) != SR_OK) return s;
-          copying = true;
+        // keep the next D pages coming (past the pass end: the next pass's
+        // first pages); a free slot was last read by an earlier step's sweeps
+        std::vector<int32_t> keep = win;
+        for (int32_t q = 1; q <= D; ++q) {
+          const int32_t page = ord[(j + q) % P];
+          if (std::find(keep.begin(), keep.end(), page) != keep.end()) continue;
+          if (page_slot[page] < 0) {
+            const int32_t sl = free_slot(keep);
+            if (sl < 0) break;
+            if ((s = copy_page(page, sl, j > 0 || pass > 0)) != SR_OK) return s;
+          }
+          keep.push_back(page);
         }
+        // the window slides once the page it takes next has landed
+        const int32_t next_slot = page_slot[ord[(j + 1) % P]];
+        const bool copying = next_slot >= 0 && hipEventQuery(copy_done[next_slot]) != hipSuccess;
         std::vector<int32_t> ws;
         for (int32_t q : win) { ws.push_back(page_slot[q]); last_use[page_slot[q]] = step_clock; }
         ++step_clock;

@@ -32,8 +32,7 @@ struct RunState {
   float *inv_outdeg = nullptr;
   uint8_t *status = nullptr;
   Ctl *ctl = nullptr;
-  BlockAcc *blk = nullptr;  // per-block sweep records
-  int32_t blk_cap = 0;
+  Stripe *stripes = nullptr;  // NSTRIPE sweep counter stripes
   bool valid = false;
 };
 
@@ -46,7 +45,8 @@ struct Residency {
   int32_t nslots = 0;
   uint64_t slot_bytes = 0;
   std::vector<char *> buf;         // resident: one per page; streaming: one per slot
-  std::vector<uint32_t *> partial; // heavy-vertex chunk partials, same indexing as buf
+  std::vector<unsigned long long *> partial;  // heavy-vertex accumulators, same indexing as buf
+  std::vector<uint64_t> partial_words;        // 64-bit words of each accumulator buffer
   std::vector<int32_t> slot_page;  // streaming: page currently in slot (-1 none)
   uint32_t max_chunks = 0;
 };
@@ -86,7 +86,7 @@ struct sr_graph {
   int32_t n = 0;
   int64_t m = 0;
   bool weighted = false, symmetric = false;
-  bool w8 = false;  // every weight fits in 8 bits: pages store u8 weights
+  bool packed = false;  // weights < 256 and n <= 2^24: pages store source | weight << 24
   std::vector<int64_t> in_off;
   std::vector<int32_t> in_src;
   std::vector<uint32_t> in_w;

@@ -226,14 +226,12 @@ static void fill_page(const sr_graph *g, int32_t vb, int32_t ve, Page &pg) {
     }
     if (open) { tl[2 * nt] = t0; tl[2 * nt + 1] = np; nt++; }
   }
-  std::memcpy(buf + h.off_src, &g->in_src[eb], sizeof(int32_t) * (size_t)mp);
-  if (g->weighted) {
-    if (h.w_bytes == 1) {
-      uint8_t *w8 = (uint8_t *)(buf + h.off_w);
-      for (int64_t e = 0; e < mp; ++e) w8[e] = (uint8_t)g->in_w[eb + e];
-    } else {
-      std::memcpy(buf + h.off_w, &g->in_w[eb], sizeof(uint32_t) * (size_t)mp);
-    }
+  if (h.packed) {
+    uint32_t *words = (uint32_t *)(buf + h.off_src);
+    for (int64_t e = 0; e < mp; ++e) words[e] = (uint32_t)g->in_src[eb + e] | g->in_w[eb + e] << 24;
+  } else {
+    std::memcpy(buf + h.off_src, &g->in_src[eb], sizeof(int32_t) * (size_t)mp);
+    if (h.w_bytes == 4) std::memcpy(buf + h.off_w, &g->in_w[eb], sizeof(uint32_t) * (size_t)mp);
   }
 }
 
@@ -264,7 +262,8 @@ static PageHeader page_header(const sr_graph *g, int32_t vb, int32_t ve) {
     h.bin_start[b] = s;
     s += h.bin_count[b];
   }
-  h.w_bytes = g->weighted ? (g->w8 ? 1 : 4) : 0;
+  h.packed = g->weighted && g->packed ? 1 : 0;
+  h.w_bytes = g->weighted && !g->packed ? 4 : 0;
   h.tile_e = tile_edges();
   uint64_t o = sizeof(PageHeader);
   h.off_offsets = o; o = align256(o + 4ull * ((uint64_t)h.n_p + 1));
@@ -289,7 +288,7 @@ static PageHeader page_header(const sr_graph *g, int32_t vb, int32_t ve) {
   h.off_src = o;     o = align256(o + 4ull * (uint64_t)h.m_p);
   h.bytes_unweighted = o;
   h.off_w = o;
-  if (g->weighted) o = align256(o + (uint64_t)h.w_bytes * (uint64_t)h.m_p);
+  o = align256(o + (uint64_t)h.w_bytes * (uint64_t)h.m_p);
   h.bytes_weighted = o;
   h.off_bins = o;    o = align256(o + 4ull * (uint64_t)s);
   h.bytes_total = o;

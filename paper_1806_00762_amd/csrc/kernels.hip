@@ -58,11 +58,12 @@ struct PageCtx {
   const int32_t *bins;
   const int32_t *tiles;
   const Chunk *chunks;
-  const int32_t *src;
-  const uint32_t *w;
-  const uint8_t *w8;         // weights as u8 when the page stores them so (else null)
+  const uint32_t *src;       // edge words: source id, or source | weight << 24 when packed
+  const uint32_t *w;         // separate u32 weights (unpacked weighted pages)
+  uint32_t src_mask;         // source id bits of an edge word
+  int32_t packed;
   int32_t bin_count, bin_start;
-  uint32_t *partial;
+  unsigned long long *partial;  // heavy-vertex accumulators, at each vertex's first chunk
 };
 
 // Thread-local sweep counters, reduced per block at the end.
@@ -110,9 +111,10 @@ __device__ inline Gate gate_of(const Run &r, int32_t v) {
   return g;
 }
 
-// Weight of page-local in-edge e (u8 or u32 storage).
-__device__ inline uint32_t weight_at(const PageCtx &p, int32_t e) {
-  return p.w8 ? (uint32_t)p.w8[e] : p.w[e];
+// Source and weight of page-local in-edge e from its edge word.
+__device__ inline int32_t src_of(const PageCtx &p, uint32_t word) { return (int32_t)(word & p.src_mask); }
+__device__ inline uint32_t weight_of(const PageCtx &p, uint32_t word, int32_t e) {
+  return p.packed ? word >> 24 : p.w[e];
 }
 
 // Contribution of one in-edge (u -> v, weight w) to the reduction.
@@ -312,8 +314,9 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
     uint32_t w[EDGES_PER_THREAD];
 #pragma unroll
     for (int j = 0; j < EDGES_PER_THREAD; ++j) {
-      u[j] = kk[j] >= 0 ? p.src[e[j]] : 0;
-      w[j] = (ALGO == A_SSSP && kk[j] >= 0) ? weight_at(p, e[j]) : 0u;
+      const uint32_t word = kk[j] >= 0 ? p.src[e[j]] : 0u;
+      u[j] = src_of(p, word);
+      w[j] = (ALGO == A_SSSP && kk[j] >= 0) ? weight_of(p, word, e[j]) : 0u;
     }
     T x[EDGES_PER_THREAD];
 #pragma unroll
@@ -348,10 +351,11 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
 }
 
 // ----------------------------------------------------------------- bin 7
-// One wavefront per CHUNK edges of a heavy vertex. Each chunk stores its
-// partial (plain store); the close kernel, after the sweep has finished,
-// combines the partials of every heavy vertex in chunk order and runs its
-// epilogue, so no fence or arrival counter is needed inside the sweep.
+// One wavefront per CHUNK edges of a heavy vertex. Each chunk folds its
+// partial into the vertex's accumulator with one device-scope atomic (min,
+// or an exact fixed-point add for PageRank sums); the close kernel, after
+// the sweep has finished, takes the accumulator (resetting it) and runs the
+// vertex's epilogue, so no fence or arrival counter is needed in the sweep.
 template <int ALGO>
 __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
   using R = Red<ALGO>;
@@ -367,17 +371,28 @@ __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
   if (comp) {
     int e = c.e_begin + lane;
     for (; e + 192 < c.e_end; e += 256) {
-      int32_t u0 = p.src[e], u1 = p.src[e + 64], u2 = p.src[e + 128], u3 = p.src[e + 192];
+      const uint32_t q0 = p.src[e], q1 = p.src[e + 64], q2 = p.src[e + 128], q3 = p.src[e + 192];
       uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-      if (ALGO == A_SSSP) { a0 = weight_at(p, e); a1 = weight_at(p, e + 64); a2 = weight_at(p, e + 128); a3 = weight_at(p, e + 192); }
-      T y0 = R::edge(r, u0, a0), y1 = R::edge(r, u1, a1), y2 = R::edge(r, u2, a2), y3 = R::edge(r, u3, a3);
+      if (ALGO == A_SSSP) {
+        a0 = weight_of(p, q0, e); a1 = weight_of(p, q1, e + 64);
+        a2 = weight_of(p, q2, e + 128); a3 = weight_of(p, q3, e + 192);
+      }
+      T y0 = R::edge(r, src_of(p, q0), a0), y1 = R::edge(r, src_of(p, q1), a1);
+      T y2 = R::edge(r, src_of(p, q2), a2), y3 = R::edge(r, src_of(p, q3), a3);
       x = R::combine(x, R::combine(R::combine(y0, y1), R::combine(y2, y3)));
     }
-    for (; e < c.e_end; e += 64) x = R::combine(x, R::edge(r, p.src[e], ALGO == A_SSSP ? weight_at(p, e) : 0u));
+    for (; e < c.e_end; e += 64) {
+      const uint32_t q = p.src[e];
+      x = R::combine(x, R::edge(r, src_of(p, q), ALGO == A_SSSP ? weight_of(p, q, e) : 0u));
+    }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) x = R::combine(x, shfl_xor(x, m));
   }
-  if (lane == 0) p.partial[idx] = R::bits(x);
+  if (comp && lane == 0) {
+    unsigned long long *slot = &p.partial[(uint32_t)c.first_count & 0xFFFFFu];
+    if constexpr (is_pr<ALGO>()) atomicAdd(slot, (unsigned long long)llrint((double)x * FIX_ONE));
+    else atomicMin(reinterpret_cast<uint32_t *>(slot), R::bits(x));
+  }
 }
 
 // ------------------------------------------------------ end of pass logic
@@ -499,9 +514,10 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   p.bins = reinterpret_cast<const int32_t *>(base + h->off_bins);
   p.tiles = reinterpret_cast<const int32_t *>(base + h->off_tiles);
   p.chunks = reinterpret_cast<const Chunk *>(base + h->off_chunks);
-  p.src = reinterpret_cast<const int32_t *>(base + h->off_src);
+  p.src = reinterpret_cast<const uint32_t *>(base + h->off_src);
   p.w = reinterpret_cast<const uint32_t *>(base + h->off_w);
-  p.w8 = h->w_bytes == 1 ? reinterpret_cast<const uint8_t *>(base + h->off_w) : nullptr;
+  p.packed = h->packed;
+  p.src_mask = h->packed ? PACKED_SRC_MASK : 0xFFFFFFFFu;
   p.bin_count = h->bin_count[BIN_CHUNK];
   p.bin_start = 0;
   p.partial = a.partial[ent];
@@ -533,8 +549,8 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
     else sweep_chunk<ALGO>(r, p, item);
   }
 
-  // block reduction of the counters into this block's record (plain stores;
-  // the close kernel reads them after the sweep)
+  // block reduction of the counters, then one set of device-scope atomics
+  // into this block's stripe (no block waits for another)
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   uint32_t v0 = wave_sum_u32(acc.changed), v1 = wave_sum_u32(acc.attempted),
            v2 = wave_sum_u32(acc.skipped), v3 = wave_sum_u32(acc.mispred),
@@ -548,45 +564,79 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    BlockAcc rec;
-    rec.changed = rec.attempted = rec.skipped = rec.mispred = rec.edges = 0;
-    rec.min_changed = INF;
-    rec.l1 = rec.ddelta = 0.0;
+    unsigned long long ch = 0, at = 0, sk = 0, mp = 0, ed = 0;
+    uint32_t mn = INF;
+    double l1 = 0.0, dd = 0.0;
     for (int w = 0; w < WAVES; ++w) {
-      rec.changed += s_u32[w][0]; rec.attempted += s_u32[w][1]; rec.skipped += s_u32[w][2];
-      rec.mispred += s_u32[w][3]; rec.edges += s_u32[w][4];
-      rec.min_changed = min(rec.min_changed, s_u32[w][5]);
-      rec.l1 += s_f64[w][0]; rec.ddelta += s_f64[w][1];
+      ch += s_u32[w][0]; at += s_u32[w][1]; sk += s_u32[w][2]; mp += s_u32[w][3]; ed += s_u32[w][4];
+      mn = min(mn, s_u32[w][5]);
+      l1 += s_f64[w][0]; dd += s_f64[w][1];
     }
-    for (int i = 0; i < 8; ++i) rec.hist[i] = s_hist[i];
-    a.blk[blockIdx.x] = rec;
+    Stripe &st = a.stripes[blockIdx.x % NSTRIPE];
+    if (ch | at) atomicAdd(&st.ca, ch | at << 32);
+    if (sk | mp) atomicAdd(&st.sm, sk | mp << 32);
+    if (ed) atomicAdd(&st.edges, ed);
+    if (mn != INF) atomicMin(&st.min_changed, mn);
+    if constexpr (is_pr<ALGO>()) {
+      if (l1 != 0.0) atomicAdd(&st.l1, (unsigned long long)llrint(l1 * FIX_ONE));
+      if (dd != 0.0) atomicAdd(&st.dd, (unsigned long long)llrint(dd * FIX_ONE));
+    }
+  }
+  if (r.pvu == P_WEAK && threadIdx.x < 4) {
+    const unsigned long long hw = (unsigned long long)s_hist[2 * threadIdx.x] |
+                                  (unsigned long long)s_hist[2 * threadIdx.x + 1] << 32;
+    if (hw) atomicAdd(&a.stripes[blockIdx.x % NSTRIPE].hist[threadIdx.x], hw);
   }
 }
 
-// Close a sweep: combine the chunk partials of every heavy vertex (chunk
-// order, so PageRank sums are reproducible), run their epilogues, reduce
-// the per-block records, and fold the totals into the control block (and
-// close the pass). One block of CLOSE_THREADS threads, after the sweep.
+// Close a sweep: take the accumulator of every heavy vertex (resetting it)
+// and run its epilogue, take the counter stripes (resetting them), and fold
+// the totals into the control block (and close the pass). One block of
+// CLOSE_THREADS threads, after the sweep.
 constexpr int CLOSE_THREADS = 1024;
 
 template <int ALGO>
 __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   using R = Red<ALGO>;
   using T = typename R::T;
-  Ctl *ctl = a.ctl;
-  if (ctl->done) return;
+  constexpr int CW = sizeof(Ctl) / 4;
+  static_assert(CW <= 64 && NSTRIPE <= 64, "the first wavefront stages the control block, the second takes the stripes");
+  __shared__ Ctl s_ctl;
   __shared__ uint32_t s_hist[8];
-  __shared__ unsigned long long s_red[CLOSE_THREADS / 64][6];
+  __shared__ unsigned long long s_red[CLOSE_THREADS / 64][5];
   __shared__ uint32_t s_min[CLOSE_THREADS / 64];
   __shared__ double s_fl[CLOSE_THREADS / 64][2];
   __shared__ __align__(16) SweepRecord s_rec;
-  if (threadIdx.x < 8) s_hist[threadIdx.x] = 0;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, nw = CLOSE_THREADS / 64;
+  // independent loads first: the control block is staged in LDS (all of the
+  // close logic then runs on the copy), and the second wavefront takes the
+  // counter stripes (a stripe is the identity when its sweep did nothing)
+  if (tid < CW) reinterpret_cast<uint32_t *>(&s_ctl)[tid] = reinterpret_cast<const uint32_t *>(a.ctl)[tid];
+  if (tid < 8) s_hist[tid] = 0;
+  unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, hw[4] = {0, 0, 0, 0};
+  uint32_t mn = INF;
+  double l1 = 0.0, dd = 0.0;
+  if (wave == 1 && lane < NSTRIPE) {
+    Stripe &st = a.stripes[lane];
+    const unsigned long long ca = atomicExch(&st.ca, 0ull), sm = atomicExch(&st.sm, 0ull);
+    c0 = ca & 0xFFFFFFFFull; c1 = ca >> 32;
+    c2 = sm & 0xFFFFFFFFull; c3 = sm >> 32;
+    c4 = atomicExch(&st.edges, 0ull);
+    mn = atomicExch(&st.min_changed, INF);
+    if constexpr (is_pr<ALGO>()) {
+      l1 = (double)atomicExch(&st.l1, 0ull) / FIX_ONE;
+      dd = (double)(long long)atomicExch(&st.dd, 0ull) / FIX_ONE;
+    }
+    for (int k = 0; k < 4; ++k) hw[k] = atomicExch(&st.hist[k], 0ull);
+  }
+  __syncthreads();
+  if (s_ctl.done) return;  // the sweep was a no-op as well
   Run r;
   r.algo = ALGO;
-  r.pvu = ctl->pvu;
-  r.phase = ctl->phase;
+  r.pvu = s_ctl.pvu;
+  r.phase = s_ctl.phase;
   r.audit = a.audit && r.phase == 0 && r.pvu != P_OFF;
-  r.threshold = ctl->threshold;
+  r.threshold = s_ctl.threshold;
   r.value = a.value;
   r.contrib = a.contrib;
   r.inv_outdeg = a.inv_outdeg;
@@ -595,52 +645,42 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   r.damping = a.damping;
   r.pr_eps = a.pr_eps;
   r.base_uniform = 1.0f / (float)a.n;
-  r.dangling = (float)ctl->dangling;
+  r.dangling = (float)s_ctl.dangling;
   r.pr_seed = a.pr_seed;
   r.hist = s_hist;
-  __syncthreads();
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = CLOSE_THREADS / 64;
+  for (int k = 0; k < 4; ++k) {
+    if (hw[k]) {
+      atomicAdd(&s_hist[2 * k], (uint32_t)(hw[k] & 0xFFFFFFFFull));
+      atomicAdd(&s_hist[2 * k + 1], (uint32_t)(hw[k] >> 32));
+    }
+  }
   Acc acc;
-  // one thread per heavy vertex: its chunk partials are independent loads
+  // one thread per heavy vertex: one exchange takes its accumulated
+  // reduction and leaves the identity for the next sweep
   for (int ent = 0; ent < a.nent; ++ent) {
     const char *base = a.base[ent];
     const PageHeader *h = reinterpret_cast<const PageHeader *>(base);
     const Heavy *hv = reinterpret_cast<const Heavy *>(base + h->off_heavy);
     const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
-    const uint32_t *part = a.partial[ent];
-    for (int i = threadIdx.x; i < h->n_heavy; i += CLOSE_THREADS) {
+    unsigned long long *part = a.partial[ent];
+    for (int i = tid; i < h->n_heavy; i += CLOSE_THREADS) {
       const Heavy x = hv[i];
-      const int first = (int)((uint32_t)x.first_count & 0xFFFFFu), count = (int)((uint32_t)x.first_count >> 20);
+      const uint32_t first = (uint32_t)x.first_count & 0xFFFFFu;
       const int32_t v = h->v_begin + x.vl;
+      // taken even when the gate says skip, so every accumulator is back at
+      // the identity when the next sweep starts
+      T t;
+      if constexpr (is_pr<ALGO>()) t = (float)((double)(long long)atomicExch(&part[first], 0ull) / FIX_ONE);
+      else t = R::from_bits(atomicExch(reinterpret_cast<uint32_t *>(&part[first]), INF));
       Gate g = gate_of(r, v);
       bool comp = g.attempt || r.audit;
-      T t = R::identity();
-      if (comp) {
-        int j = 0;
-        for (; j + 4 <= count; j += 4) {
-          T y0 = R::from_bits(part[first + j]), y1 = R::from_bits(part[first + j + 1]);
-          T y2 = R::from_bits(part[first + j + 2]), y3 = R::from_bits(part[first + j + 3]);
-          t = R::combine(t, R::combine(R::combine(y0, y1), R::combine(y2, y3)));
-        }
-        for (; j < count; ++j) t = R::combine(t, R::from_bits(part[first + j]));
-      }
+      if (!comp) t = R::identity();
       epilogue<ALGO>(r, v, g, comp, t, (uint32_t)(off[x.vl + 1] - off[x.vl]), acc);
     }
   }
-  // per-block records of the sweep
-  unsigned long long c0 = acc.changed, c1 = acc.attempted, c2 = acc.skipped, c3 = acc.mispred, c4 = acc.edges;
-  uint32_t mn = acc.min_changed;
-  double l1 = acc.l1, dd = acc.ddelta;
-  const bool weak = r.pvu == P_WEAK;
-  for (int i = threadIdx.x; i < a.nblocks; i += CLOSE_THREADS) {
-    const BlockAcc &b = a.blk[i];
-    c0 += b.changed; c1 += b.attempted; c2 += b.skipped; c3 += b.mispred; c4 += b.edges;
-    mn = min(mn, b.min_changed);
-    l1 += b.l1; dd += b.ddelta;
-    if (weak)
-      for (int k = 0; k < 8; ++k)
-        if (b.hist[k]) atomicAdd(&s_hist[k], b.hist[k]);
-  }
+  c0 += acc.changed; c1 += acc.attempted; c2 += acc.skipped; c3 += acc.mispred; c4 += acc.edges;
+  mn = min(mn, acc.min_changed);
+  l1 += acc.l1; dd += acc.ddelta;
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
     c0 += shfl_xor(c0, m); c1 += shfl_xor(c1, m); c2 += shfl_xor(c2, m);
@@ -654,7 +694,7 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
     s_fl[wave][0] = l1; s_fl[wave][1] = dd;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     SweepTotals t{};
     t.min_changed = INF;
     for (int w = 0; w < nw; ++w) {
@@ -663,10 +703,11 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
       t.min_changed = min(t.min_changed, s_min[w]);
       t.l1 += s_fl[w][0]; t.ddelta += s_fl[w][1];
     }
-    for (int k = 0; k < 8; ++k) t.hist[k] = s_hist[k];  // block records and heavy vertices
-    close_sweep(ctl, &s_rec, a.end_of_pass, t);
+    for (int k = 0; k < 8; ++k) t.hist[k] = s_hist[k];  // sweep blocks and heavy vertices
+    close_sweep(&s_ctl, &s_rec, a.end_of_pass, t);
   }
   __syncthreads();
+  if (tid < CW) reinterpret_cast<uint32_t *>(a.ctl)[tid] = reinterpret_cast<const uint32_t *>(&s_ctl)[tid];
   if (a.ring) publish_record(&s_rec, &a.ring[s_rec.seq & a.ring_mask]);
 }
 
@@ -716,6 +757,17 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, size_t count) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (; i < count; i += stride) p[i] = v;
+}
+
+__global__ void init_stripes_kernel(Stripe *s) {
+  const int i = threadIdx.x;
+  if (i < NSTRIPE) {
+    Stripe z;
+    z.ca = z.sm = z.edges = z.l1 = z.dd = 0ull;
+    for (int k = 0; k < 4; ++k) z.hist[k] = 0ull;
+    z.min_changed = INF;
+    s[i] = z;
+  }
 }
 
 __global__ void init_ctl_kernel(Ctl *ctl, Ctl init) {
@@ -778,6 +830,11 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s)
   size_t blocks = (count + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_stripes(Stripe *s, hipStream_t st) {
+  hipLaunchKernelGGL(init_stripes_kernel, dim3(1), dim3(NSTRIPE), 0, st, s);
   return hipGetLastError();
 }
 

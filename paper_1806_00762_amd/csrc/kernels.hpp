@@ -28,11 +28,11 @@ struct SweepArgs {
   float *contrib;          // PageRank: rank / outdeg, gathered by the pull
   const float *inv_outdeg; // PageRank: 1 / outdeg (0 for dangling vertices)
   uint8_t *status;         // weak predictor state per vertex
-  BlockAcc *blk;           // one counter record per block of the sweep
+  Stripe *stripes;         // NSTRIPE counter stripes (identity outside a sweep)
   Diagram dia;
   int32_t blk_prefix[MAXW * NSEC + 1];   // cumulative blocks over (page, section)
   const char *base[MAXW];                // page buffers on the device
-  uint32_t *partial[MAXW];               // heavy-vertex chunk partials, per page
+  unsigned long long *partial[MAXW];     // heavy-vertex accumulators (at each vertex's first chunk), per page
 };
 
 // Blocks a page needs for section sec (0: one per tile, 1: WAVES chunks each).
@@ -47,6 +47,7 @@ hipError_t launch_init_pr(float *rank, float *contrib, const float *inv_outdeg, 
                           int32_t seed, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
+hipError_t launch_init_stripes(Stripe *s, hipStream_t st);
 hipError_t launch_init_ctl(Ctl *ctl, const Ctl &init, hipStream_t s);
 
 }  // namespace sr

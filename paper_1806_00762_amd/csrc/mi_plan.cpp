@@ -69,7 +69,8 @@ sr_status MiPlan::add_group(sr_graph *g, int pvu, int *out_index) {
   gr.n = g->n;
   gr.pvu = pvu;
   gr.has_w = (algo == A_SSSP && g->res.resident && g->res.weights) ? 1 : 0;
-  gr.w8 = g->w8 ? 1 : 0;
+  gr.packed = g->packed ? 1 : 0;
+  gr.src_mask = g->packed ? PACKED_SRC_MASK : 0xFFFFFFFFu;
   sr_status s;
   if ((s = alloc((void **)&gr.value, 4ull * g->n * K, "instance values")) != SR_OK) return s;
   if (algo == A_PPR) {
@@ -440,7 +441,8 @@ extern "C" sr_status sr_batch_run(sr_ctx *c, const sr_instance *inst, int32_t co
   // read once per sweep per group while the group has a live instance
   for (size_t gi = 0; gi < plan.groups.size(); ++gi) {
     sr_graph *g = plan.group_graph[gi];
-    uint64_t per_sweep = (uint64_t)g->m * (plan.algo == A_SSSP && g->res.weights ? 8 : 4) + 12ull * g->n;
+    const bool sep_w = plan.algo == A_SSSP && g->weighted && !g->packed;
+    uint64_t per_sweep = (uint64_t)g->m * (sep_w ? 8 : 4) + 12ull * g->n;
     algo_bytes += per_sweep * (uint64_t)group_sweeps[gi];
   }
   if (bst) {

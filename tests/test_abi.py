@@ -131,16 +131,39 @@ def test_symmetric_flag_verifies(sr):
 
 
 def test_wide_weights_kept_as_u32(sr):
-    """Weights >= 256 are stored as u32; below 256 as u8 (both lossless)."""
+    """Weights >= 256 keep a separate u32 section; below 256 they are packed
+    into the top byte of the edge word (both lossless)."""
     c = sr.Context(-1, 1 << 30)
-    for hi, width in ((255, 1), (70000, 4)):
+    for hi, packed in ((255, True), (70000, False)):
         src = graphgen.rmat(9, 8, seed=2, weights=(1, hi, 3))
         G = c.load(src)
         G.partition(2, 4)
-        ws = np.concatenate([G.page(p)["weights"] for p in range(G.info()["num_parts"])])
-        assert G.page(0)["weight_bytes"] == width
+        pages = [G.page(p) for p in range(G.info()["num_parts"])]
+        ws = np.concatenate([pg["weights"] for pg in pages])
+        srcs = np.concatenate([pg["src"] for pg in pages])
+        assert all(pg["src_packed"] == packed for pg in pages)
         A = sp.csr_matrix((src.weights.astype(np.int64), src.col, src.offsets), shape=(src.n, src.n)).T.tocsr()
         A.sort_indices()
         assert np.array_equal(ws, A.data.astype(np.uint32))
+        assert np.array_equal(srcs, A.indices)
+        # a packed page streams 4 bytes per weighted edge, an unpacked one 8
+        m_p = sum(len(pg["src"]) for pg in pages)
+        stream = sum(pg["stream_bytes"] for pg in pages)
+        assert (stream < 8 * m_p) == packed
         G.close()
+    c.close()
+
+
+def test_packing_needs_24_bit_ids(sr):
+    """Above 2^24 vertices the source id needs the top byte: weights stay separate."""
+    c = sr.Context(-1, 1 << 31)
+    n = (1 << 24) + 2
+    g = graphgen.from_edges(n, [0, n - 1, 5], [n - 1, 3, 0], [7, 9, 11])
+    G = c.load(g)
+    G.partition(1, 2)
+    pg = G.page(0)
+    assert not pg["src_packed"]
+    assert sorted(pg["src"].tolist()) == [0, 5, n - 1]
+    assert sorted(pg["weights"].tolist()) == [7, 9, 11]
+    G.close()
     c.close()
