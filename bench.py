@@ -409,7 +409,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (for HBM counter scaling)")
     ap.add_argument("--served-timeout", type=float, default=90.0)
-    ap.add_argument("--copy-depth", type=int, default=1,
+    ap.add_argument("--copy-depth", type=int, default=2,
                     help="page copies kept in flight ahead of the window (1 = the paper's layout)")
     ap.add_argument("--no-other", action="store_true", help="skip the other predictor's solves")
     ap.add_argument("--ablation", action="store_true",

@@ -117,12 +117,14 @@ sr_status sr_graph_load_csr(sr_ctx *ctx, int32_t n, int64_t m, const int64_t *ro
 
 /* Cut the in-edge CSR into pages (Section 3.1: CSC pages of consecutive
  * destination vertices with their incoming edges, no destination array).
- * Pages hold about m / num_parts in-edges each; a vertex is never split
- * across pages, so a page may exceed that by one in-degree. num_parts = 0
- * picks the smallest count whose largest page fits a slot of the context's
- * budget; num_slots (>= 2, 0 = 4) is the number of page slots of the
- * pipelined window (Section 3.2: num_slots-1 pages computed while one is
- * copied). Pages live in pinned host memory owned by the graph. */
+ * Pages carry about equal streamed bytes (4 per vertex offset plus 4 per
+ * edge word, 8 with separate weights); a vertex is never split across
+ * pages, so a page may exceed the share by one vertex. num_parts = 0 picks
+ * the smallest count whose largest page fits a slot of the context's
+ * budget; num_slots (2..17, 0 = 4) is the number of page slots of the
+ * pipelined window (Section 3.2: num_slots - copy_depth pages computed while
+ * copy_depth pages are copied). Pages live in pinned host memory owned by
+ * the graph. */
 sr_status sr_graph_partition(sr_graph *g, int32_t num_parts, int32_t num_slots);
 
 typedef struct {

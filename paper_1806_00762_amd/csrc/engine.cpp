@@ -232,21 +232,12 @@ extern "C" sr_status sr_graph_partition(sr_graph *g, int32_t nparts, int32_t nsl
   if (nparts == 0) {
     // smallest part count whose largest page (with weights) fits one slot
     // of the budget left after the vertex state of a min program
-    uint64_t total = graph_bytes(g);
     uint64_t st = state_bytes(g->n, A_SSSP);
     if (c->budget <= st) return c->fail(SR_EBUDGET, "budget cannot hold the vertex state");
-    uint64_t slot = (c->budget - st) / (uint64_t)nslots;
-    int32_t P = (int32_t)std::max<uint64_t>(1, (total + slot - 1) / std::max<uint64_t>(slot, 1));
-    for (int iter = 0; iter < 64; ++iter) {
-      sr_status s = sr::make_pages(g, P);
-      if (s != SR_OK) return s;
-      uint64_t mx = 0, sum = 0;
-      for (auto &p : g->pages) { mx = std::max(mx, p.bytes + scratch_bytes(p)); sum += p.bytes + scratch_bytes(p); }
-      if (sum + st <= c->budget || mx <= slot || c->host_only) break;
-      P = P + std::max<int32_t>(1, P / 8);
-      if (P > g->n) return c->fail(SR_EBUDGET, "no partition fits the budget");
-    }
-    return SR_OK;
+    const uint64_t slot = (c->budget - st) / (uint64_t)nslots - 4096;
+    const int32_t P = sr::auto_parts(g, slot);
+    if (P < 1) return c->fail(SR_EBUDGET, "no partition fits the budget");
+    return sr::make_pages(g, P);
   }
   return sr::make_pages(g, nparts);
 }

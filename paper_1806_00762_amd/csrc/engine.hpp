@@ -105,6 +105,9 @@ namespace sr {
 sr_status build_in_csr(sr_graph *g, const int64_t *row_offsets, const int32_t *col_idx,
                        const uint32_t *weights, bool symmetrize);
 sr_status make_pages(sr_graph *g, int32_t nparts);
+// Smallest page count whose largest streamed page (with its chunk scratch)
+// fits slot_bytes; -1 if none does.
+int32_t auto_parts(const sr_graph *g, uint64_t slot_bytes);
 void free_pages(sr_graph *g);
 uint64_t graph_bytes(const sr_graph *g);
 int host_threads();

@@ -1,5 +1,5 @@
 """The C ABI library loads, exports every symbol include/seraph.h declares,
-and its host-side graph logic (in-edge CSR, equal-edge pages, argument
+and its host-side graph logic (in-edge CSR, equal-byte pages, argument
 checks) works without a GPU through a host-only context."""
 import os
 import re
@@ -83,9 +83,14 @@ def test_in_csr_and_pages(sr, sym):
             vb = pg["v_end"]
             offs.extend((pg["offsets"][1:] + offs[-1]).tolist())
             srcs.append(pg["src"]); ws.append(pg["weights"])
-            # equal-edge split: a page exceeds m/parts by at most one in-degree
-            maxdeg = int(np.diff(IN.indptr).max())
-            assert pg["offsets"][-1] <= -(-IN.nnz // parts) + maxdeg
+            # equal-byte split: a page's streamed bytes (4 per vertex, 4 per
+            # edge word, 4 more per edge for separate weights) exceed
+            # total/parts by at most one vertex's bytes
+            eb = 8 if (pg["weights"] is not None and not pg["src_packed"]) else 4
+            maxcost = 4 + eb * int(np.diff(IN.indptr).max())
+            total = 4 * src.n + eb * IN.nnz
+            cost = 4 * (pg["v_end"] - pg["v_begin"]) + eb * int(pg["offsets"][-1])
+            assert cost <= -(-total // parts) + maxcost
         assert vb == src.n
         assert np.array_equal(np.array(offs), IN.indptr)
         assert np.array_equal(np.concatenate(srcs), IN.indices)

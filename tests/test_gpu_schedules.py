@@ -98,7 +98,7 @@ def test_zigzag_reentry_vs_pipelined(sr, ctx):
         check_trace(st, tr)
         res[sched] = st
     # re-entry of a lone page cannot advance a chain that leaves the page
-    # (the equal-edge split puts b0 on a's page: one hop of gain at most)
+    # (the page split puts b0 on a's page: one hop of gain at most)
     assert res["rsi"]["passes"] >= res["baseline"]["passes"] - 1
     assert res["rsi"]["sweeps"] > 2 * res["baseline"]["sweeps"]
     # the window of both pages advances >= 4 hops a pass instead of 2

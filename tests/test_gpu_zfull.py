@@ -1,4 +1,4 @@
-"""Full-size workloads: PageRank on R-MAT scale 16 (4 equal-edge pages, up to
+"""Full-size workloads: PageRank on R-MAT scale 16 (4 equal-byte pages, up to
 4 in-GPU sweeps per page per pass), streamed SSSP on R-MAT scale 22 under a
 device budget of 1/4 of the graph bytes (the benchmark's configuration),
 streamed CC on R-MAT scale 24 / edge factor 32 and its uniform twin, the
