@@ -198,8 +198,7 @@ def ablation(args, G, parts, dist):
               ("psi", args.slots, args.inner, False, "off", 1),
               ("psi_strong", args.slots, args.inner, False, "strong", 1),
               ("psi_weak", args.slots, args.inner, False, "weak", 1),
-              ("psi_strong_depth2", args.slots, args.inner, False, "strong", 2),
-              ("psi_strong_s5_depth2", 5, args.inner, False, "strong", 2)]
+              ("psi_strong_depth2", args.slots, args.inner, False, "strong", 2)]
     out = {}
     for name, slots, inner, fixed, pvu, depth in scheds:
         G.partition(parts, slots)
@@ -215,7 +214,7 @@ def ablation(args, G, parts, dist):
         row = {"ms_per_solve": round(el * 1e3, 2), "passes": st["passes"], "sweeps": st["sweeps"],
                "edges_scanned": st["edges_scanned"], "h2d_bytes": st["h2d_bytes"],
                "kernel_ms": round(st["kernel_ms"], 2), "h2d_ms": round(st["h2d_ms"], 2)}
-        if pvu == "weak":
+        if pvu != "off":
             tr = G.sweeps()
             np_ = st["passes"]
             row["per_pass_changed"] = [sum(r["changed"] for r in tr if r["pass"] == k) for k in range(np_)]
@@ -394,7 +393,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--inner", type=int, default=8)
     ap.add_argument("--pvu", default="strong",
