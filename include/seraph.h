@@ -67,6 +67,10 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
                                      (mispredictions) without applying them */
 #define SR_RUN_FORCE_STREAM 0x2u  /* stream pages through slots even if the graph fits */
 #define SR_RUN_RESUME 0x4u        /* continue from the values/state left by the last run */
+#define SR_RUN_HETERO 0x10u       /* heterogeneous model of Section 3.1: once a pass of a min
+                                     program (BFS/SSSP/CC, strong or no prediction) changes at most
+                                     sparse_switch vertices, the host finishes the run with push
+                                     relaxations from that pass's frontier (the sparse stage) */
 #define SR_RUN_FIXED_INNER 0x8u   /* every window step runs exactly max_inner_iters sweeps; with
                                      num_slots = 2 this is CLIP's loaded-data re-entry (Section 3.2),
                                      with max_inner_iters = 1 the single-pass baseline of Section 5.4 */
@@ -192,6 +196,8 @@ typedef struct {
   int32_t copy_depth;        /* streamed pages: copies kept in flight ahead of the window (0 = 1,
                                 the paper's S-1 computing + 1 transferring slots); with depth D
                                 the window holds num_slots - D pages. 1 <= D < num_slots. */
+  int32_t sparse_switch;     /* SR_RUN_HETERO: frontier size that switches to the host sparse
+                                stage (0 = max(1024, n / 512)) */
 } sr_run_params;
 
 typedef struct {
@@ -204,7 +210,13 @@ typedef struct {
   double wall_ms;            /* host wall time of sr_run */
   double final_l1;           /* PageRank: L1 change of the last full pass */
   int64_t state_hist[8];     /* weak predictor: vertex-sweeps spent in each state */
-  uint64_t algo_bytes;       /* algorithmic bytes of all sweeps (see DESIGN) */
+  uint64_t algo_bytes;       /* algorithmic bytes of all sweeps: edge words, gathered values,
+                                offsets, gate reads, value writes */
+  int32_t sparse_stage;      /* SR_RUN_HETERO: 1 if the host sparse stage finished the run */
+  int32_t sparse_rounds;     /* push rounds of the sparse stage */
+  int64_t sparse_frontier;   /* vertices it started from (changed in the last device pass) */
+  int64_t sparse_relaxations;/* edges it relaxed */
+  double sparse_ms;          /* its wall time, transfers included */
 } sr_run_stats;
 
 /* Run a vertex program to convergence on the graph (partitioned with

@@ -155,6 +155,8 @@ static void release_state(sr_graph *g) {
   g->ctx->dfree(s.status);
   g->ctx->dfree(s.ctl);
   g->ctx->dfree(s.stripes);
+  g->ctx->dfree(s.frontier);
+  g->ctx->dfree(s.fr_count);
   s = RunState();
 }
 
@@ -353,6 +355,9 @@ struct Runner {
   bool weights;
   sr_run_stats st{};
   uint64_t seq_next = 0;  // next expected sweep record
+  uint64_t cur_pass_changed = 0;            // vertices changed so far in the open pass
+  uint64_t last_pass_changed = ~0ull;       // ... in the last closed pass
+  int32_t collect = 0;                      // sweeps append changed vertices to the frontier
   // timing events: a free list, and start/end pairs not yet read
   std::vector<hipEvent_t> ev_all, ev_free;
   struct Pair { hipEvent_t a, b; bool copy; };
@@ -411,7 +416,10 @@ struct Runner {
       st.mispredicted += (int64_t)r.mispred;
       for (int i = 0; i < 8; ++i) st.state_hist[i] += (int64_t)r.hist[i];
       st.algo_bytes += algo_bytes(algo, pvu, g->weighted && !g->packed, r);
+      cur_pass_changed += r.changed;
       if (r.pass_l1_closed >= 0.0) {
+        last_pass_changed = cur_pass_changed;
+        cur_pass_changed = 0;
         st.final_l1 = r.pass_l1_closed;
         if (r.phase == 1) st.verify_passes++;
       }
@@ -466,6 +474,10 @@ struct Runner {
       a.partial[i] = g->res.partial[slots[i]];
     }
     a.stripes = g->state.stripes;
+    a.collect = collect;
+    a.frontier = g->state.frontier;
+    a.fr_count = g->state.fr_count;
+    a.fr_cap = g->state.fr_cap;
     a.nblocks = std::max<int32_t>(blk, 1);  // an empty window still closes its sweep
     a.tile_e = pages.empty() ? TILE_E_MIN : g->pages[pages[0]].hdr.tile_e;
     return SR_OK;
@@ -594,10 +606,14 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (p.max_passes == 0) p.max_passes = 10000;
   if (p.max_inner_iters == 0) p.max_inner_iters = 4;
   if (p.max_passes < 0 || p.max_inner_iters < 0) return c->fail(SR_EINVAL, "negative limits");
-  if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_FORCE_STREAM | SR_RUN_RESUME | SR_RUN_FIXED_INNER))
+  if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_FORCE_STREAM | SR_RUN_RESUME | SR_RUN_FIXED_INNER | SR_RUN_HETERO))
     return c->fail(SR_EINVAL, "unknown run flags");
   const bool pr = R.algo == A_PR || R.algo == A_PPR;
-  if (p.pvu == SR_PVU_DEFAULT) p.pvu = (R.algo == A_BFS || R.algo == A_CC) ? SR_PVU_STRONG : SR_PVU_WEAK;
+  // defaults (Section 4.3 discussion): BFS/CC strong, SSSP/PageRank weak;
+  // with the host sparse stage SSSP takes the strong conditions too
+  if (p.pvu == SR_PVU_DEFAULT)
+    p.pvu = (R.algo == A_BFS || R.algo == A_CC || (R.algo == A_SSSP && (p.flags & SR_RUN_HETERO)))
+                ? SR_PVU_STRONG : SR_PVU_WEAK;
   if (p.pvu < SR_PVU_OFF || p.pvu > SR_PVU_WEAK) return c->fail(SR_EINVAL, "unknown pvu mode");
   if (pr && p.pvu == SR_PVU_STRONG) return c->fail(SR_EINVAL, "PageRank has no strong condition (Table I)");
   R.pvu = (int)p.pvu;
@@ -638,6 +654,27 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   }
   if (s != SR_OK) return s;
   const int32_t depth = p.copy_depth == 0 ? 1 : p.copy_depth;
+  // heterogeneous model (Section 3.1): a host sparse stage finishes the run
+  // once a pass changes few vertices; exact when every vertex of that pass
+  // was pulled or provably final (strong or no prediction)
+  const bool hetero = (p.flags & SR_RUN_HETERO) != 0;
+  uint32_t sparse_thr = 0;
+  if (hetero) {
+    if (pr) return c->fail(SR_EINVAL, "the sparse stage serves BFS, SSSP and CC");
+    if (R.pvu == P_WEAK) return c->fail(SR_EINVAL, "the sparse stage needs strong or no prediction");
+    if (p.sparse_switch < 0) return c->fail(SR_EINVAL, "sparse_switch must be >= 0");
+    sparse_thr = p.sparse_switch > 0 ? (uint32_t)p.sparse_switch : (uint32_t)std::max<int32_t>(1024, g->n / 512);
+    sparse_thr = std::min<uint32_t>(sparse_thr, (uint32_t)g->n);
+    if (g->state.fr_cap < sparse_thr) {
+      c->dfree(g->state.frontier);
+      g->state.frontier = nullptr;
+      g->state.fr_cap = 0;
+      if ((s = c->dalloc((void **)&g->state.frontier, 4ull * sparse_thr, "pass frontier")) != SR_OK) return s;
+      g->state.fr_cap = sparse_thr;
+    }
+    if (!g->state.fr_count && (s = c->dalloc((void **)&g->state.fr_count, 256, "frontier count")) != SR_OK)
+      return s;
+  }
   if (!g->res.resident && (depth < 1 || depth >= g->res.nslots))
     return c->fail(SR_EINVAL, "copy_depth must be in [1, num_slots)");
 
@@ -694,6 +731,51 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   R.seq_next = 0;
   rs.valid = true;
 
+  // Host sparse stage (Section 3.1). A pass collects the vertices it changes
+  // once the pass before changed few enough; when a pass changed at most
+  // sparse_thr vertices and all were collected, the host pushes from them to
+  // the fixed point. Every edge whose source did not change in that pass is
+  // already satisfied (its target was pulled after the source's last change,
+  // or is final by Table I), so the push from the frontier is exact.
+  auto begin_pass = [&]() -> sr_status {
+    R.collect = (hetero && (R.last_pass_changed <= 32ull * sparse_thr || (uint64_t)g->n <= 32ull * sparse_thr)) ? 1 : 0;
+    if (R.collect) {
+      hipError_t e2 = launch_fill_u32(g->state.fr_count, 0u, 1, c->compute);
+      if (e2 != hipSuccess) return c->hip_fail(e2, "frontier reset");
+    }
+    return SR_OK;
+  };
+  auto sparse_stage = [&](bool *fin) -> sr_status {
+    *fin = false;
+    if (!R.collect || R.last_pass_changed > sparse_thr) return SR_OK;
+    const double t1 = now_ms();
+    uint32_t cnt = 0;
+    HIP_TRY(c, hipMemcpyAsync(&cnt, g->state.fr_count, 4, hipMemcpyDeviceToHost, c->compute), "frontier count");
+    HIP_TRY(c, hipStreamSynchronize(c->compute), "frontier count");
+    if (cnt > g->state.fr_cap) return SR_OK;  // incomplete: the device goes on
+    std::vector<uint32_t> val((size_t)g->n), fr((size_t)cnt + 1);
+    HIP_TRY(c, hipMemcpyAsync(val.data(), g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute),
+            "values to host");
+    if (cnt)
+      HIP_TRY(c, hipMemcpyAsync(fr.data(), g->state.frontier, 4ull * cnt, hipMemcpyDeviceToHost, c->compute),
+              "frontier to host");
+    HIP_TRY(c, hipStreamSynchronize(c->compute), "values to host");
+    sr::build_out_csr(g);
+    int32_t rounds = 0;
+    const int64_t relaxed = sr::sparse_push(g, R.algo, val.data(), fr.data(), (int64_t)cnt, &rounds);
+    HIP_TRY(c, hipMemcpyAsync(g->state.value, val.data(), 4ull * g->n, hipMemcpyHostToDevice, c->compute),
+            "values to device");
+    HIP_TRY(c, hipStreamSynchronize(c->compute), "values to device");
+    R.st.sparse_stage = 1;
+    R.st.sparse_rounds = rounds;
+    R.st.sparse_frontier = (int64_t)cnt;
+    R.st.sparse_relaxations = relaxed;
+    R.st.sparse_ms = now_ms() - t1;
+    R.st.stop_reason = SR_STOP_CONVERGED;
+    *fin = true;
+    return SR_OK;
+  };
+
   bool done = false;
   if (g->res.resident) {
     // Every sweep covers every page and closes a pass; the control block
@@ -711,13 +793,23 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     const int batch = 4;
     int32_t launched = 0;
     while (!done) {
-      for (int b = 0; b < batch; ++b) {
-        for (auto &a : args)
+      if ((s = begin_pass()) != SR_OK) return s;
+      // a collecting pass runs alone so its frontier can be handed over
+      const int nb = R.collect ? 1 : batch;
+      for (int b = 0; b < nb; ++b) {
+        for (auto &a : args) {
+          a.collect = R.collect;
           if ((s = R.launch(a)) != SR_OK) return s;
+        }
         launched++;
       }
       if ((s = R.sync_compute()) != SR_OK) return s;
       R.harvest(&done);
+      if (!done) {
+        bool fin = false;
+        if ((s = sparse_stage(&fin)) != SR_OK) return s;
+        done = fin;
+      }
       if (launched > p.max_passes + 8) break;
     }
   } else {
@@ -780,6 +872,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     for (int32_t i = 0; i < P; ++i) ord[i] = i;
     while (!done) {
       // pass start: every earlier sweep has finished (host synced at the pass end)
+      if ((s = begin_pass()) != SR_OK) return s;
       if (page_slot[ord[0]] < 0) {
         if ((s = copy_page(ord[0], free_slot({}), false)) != SR_OK) return s;
       }
@@ -827,6 +920,11 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       HIP_TRY(c, launch_end_pass(g->state.ctl, c->ring_dev, c->ring_mask, c->compute), "end pass");
       if ((s = R.sync_compute()) != SR_OK) return s;
       R.harvest(&done);
+      if (!done) {
+        bool fin = false;
+        if ((s = sparse_stage(&fin)) != SR_OK) return s;
+        done = fin;
+      }
       pass++;
       if (pass > p.max_passes + 2) break;
     }

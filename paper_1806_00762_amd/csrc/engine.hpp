@@ -33,6 +33,9 @@ struct RunState {
   uint8_t *status = nullptr;
   Ctl *ctl = nullptr;
   Stripe *stripes = nullptr;  // NSTRIPE sweep counter stripes
+  uint32_t *frontier = nullptr;  // vertices changed in a pass (host sparse stage)
+  uint32_t *fr_count = nullptr;
+  uint32_t fr_cap = 0;
   bool valid = false;
 };
 
@@ -98,6 +101,11 @@ struct sr_graph {
   sr::RunState state;
   int server_refs = 0;  // servers holding the resident pages (no re-residency meanwhile)
   std::vector<sr_sweep_record> sweeps;  // per-sweep trace of the last run
+  // out-edge CSR for the host sparse stage (built on first use)
+  bool out_built = false;
+  std::vector<int64_t> out_off;
+  std::vector<int32_t> out_dst;
+  std::vector<uint32_t> out_w;
 };
 
 namespace sr {
@@ -112,6 +120,10 @@ void free_pages(sr_graph *g);
 uint64_t graph_bytes(const sr_graph *g);
 int host_threads();
 int tile_edges();
+// sparse.cpp
+void build_out_csr(sr_graph *g);
+int64_t sparse_push(const sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
+                    int32_t *rounds);
 // engine.cpp
 sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream, bool bins = false);
 void release_residency(sr_graph *g);

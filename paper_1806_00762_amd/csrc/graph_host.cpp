@@ -17,6 +17,7 @@ namespace sr {
 
 int host_threads() {
   unsigned t = std::thread::hardware_concurrency();
+  if (const char *e = getenv("OMP_NUM_THREADS")) t = (unsigned)atoi(e);
   if (const char *e = getenv("SR_HOST_THREADS")) t = (unsigned)atoi(e);
   if (t < 1) t = 1;
   if (t > 32) t = 32;

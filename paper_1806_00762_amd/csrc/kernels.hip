@@ -85,6 +85,10 @@ struct Run {
   float damping, pr_eps, base_uniform, dangling;
   int32_t pr_seed;
   uint32_t *hist;  // LDS histogram of predictor states
+  // frontier of the pass (vertices that changed), for the host sparse stage
+  int32_t collect;
+  uint32_t *frontier, *fr_count;
+  uint32_t fr_cap;
 };
 
 // Gate: does vertex v attempt a pull this sweep? (Section 4.) Returns the
@@ -155,7 +159,7 @@ struct Red {
 // Epilogue of one vertex: compare, write, advance the predictor state,
 // count. `computed` says whether red holds the pull result.
 template <int ALGO>
-__device__ inline void epilogue(const Run &r, int32_t v, const Gate &g, bool computed,
+__device__ inline bool epilogue(const Run &r, int32_t v, const Gate &g, bool computed,
                                 typename Red<ALGO>::T red, uint32_t deg, Acc &acc) {
   bool changed = false;
   if (computed) {
@@ -203,6 +207,26 @@ __device__ inline void epilogue(const Run &r, int32_t v, const Gate &g, bool com
     uint8_t nx = (g.attempt && changed) ? r.dia->succ[g.st] : r.dia->fail[g.st];
     if (nx != g.st) r.status[v] = nx;
     atomicAdd(&r.hist[g.st], 1u);
+  }
+  return changed;
+}
+
+// Append the changed vertices of the active lanes to the pass frontier:
+// one counter atomic per wavefront; entries past the capacity are counted
+// but dropped (the host then knows the frontier is incomplete). Call from
+// converged control flow of the wavefront.
+__device__ inline void frontier_push(const Run &r, bool changed, int32_t v) {
+  if (!r.collect) return;
+  const unsigned long long m = __ballot(changed);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x % 64;
+  const int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(r.fr_count, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (changed) {
+    const uint32_t i = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (i < r.fr_cap) r.frontier[i] = (uint32_t)v;
   }
 }
 
@@ -345,8 +369,9 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
   // phase 3: epilogues of the pulled vertices
   for (int k = tid; k < Kt; k += BLOCK) {
     Gate g{s.att[k] != 0, s.st[k], s.old[k]};
-    epilogue<ALGO>(r, p.v_begin + s.vl[k], g, true, R::from_bits(s.acc[k]),
-                   (uint32_t)(s.pos[k + 1] - s.pos[k]), acc);
+    const bool ch = epilogue<ALGO>(r, p.v_begin + s.vl[k], g, true, R::from_bits(s.acc[k]),
+                                   (uint32_t)(s.pos[k + 1] - s.pos[k]), acc);
+    frontier_push(r, ch, p.v_begin + s.vl[k]);
   }
 }
 
@@ -539,6 +564,10 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   r.dangling = (float)ctl->dangling;
   r.pr_seed = a.pr_seed;
   r.hist = s_hist;
+  r.collect = a.collect;
+  r.frontier = a.frontier;
+  r.fr_count = a.fr_count;
+  r.fr_cap = a.fr_cap;
   __syncthreads();
 
   Acc acc;
@@ -648,6 +677,10 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   r.dangling = (float)s_ctl.dangling;
   r.pr_seed = a.pr_seed;
   r.hist = s_hist;
+  r.collect = a.collect;
+  r.frontier = a.frontier;
+  r.fr_count = a.fr_count;
+  r.fr_cap = a.fr_cap;
   for (int k = 0; k < 4; ++k) {
     if (hw[k]) {
       atomicAdd(&s_hist[2 * k], (uint32_t)(hw[k] & 0xFFFFFFFFull));
@@ -675,7 +708,8 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
       Gate g = gate_of(r, v);
       bool comp = g.attempt || r.audit;
       if (!comp) t = R::identity();
-      epilogue<ALGO>(r, v, g, comp, t, (uint32_t)(off[x.vl + 1] - off[x.vl]), acc);
+      const bool ch = epilogue<ALGO>(r, v, g, comp, t, (uint32_t)(off[x.vl + 1] - off[x.vl]), acc);
+      frontier_push(r, ch, v);
     }
   }
   c0 += acc.changed; c1 += acc.attempted; c2 += acc.skipped; c3 += acc.mispred; c4 += acc.edges;

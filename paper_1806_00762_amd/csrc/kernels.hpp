@@ -29,6 +29,10 @@ struct SweepArgs {
   const float *inv_outdeg; // PageRank: 1 / outdeg (0 for dangling vertices)
   uint8_t *status;         // weak predictor state per vertex
   Stripe *stripes;         // NSTRIPE counter stripes (identity outside a sweep)
+  int32_t collect;         // append changed vertices to the pass frontier
+  uint32_t fr_cap;         // frontier capacity (entries)
+  uint32_t *frontier;      // vertices changed in this pass (host sparse stage)
+  uint32_t *fr_count;      // entries appended (may exceed fr_cap: then incomplete)
   Diagram dia;
   int32_t blk_prefix[MAXW * NSEC + 1];   // cumulative blocks over (page, section)
   const char *base[MAXW];                // page buffers on the device

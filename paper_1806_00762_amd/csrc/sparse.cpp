@@ -1,0 +1,112 @@
+// sparse.cpp -- the sparse stage of the heterogeneous execution model
+// (Section 3.1): once few vertices change per pass, the host finishes the
+// run by pushing relaxations along out-edges from the compressed frontier
+// (the vertices the last device pass changed), instead of streaming every
+// page through the GPU again.
+#include <algorithm>
+#include <cstring>
+#include <thread>
+
+#include "engine.hpp"
+
+namespace sr {
+
+// Out-edge CSR of the graph, rebuilt once from the in-edge CSR by a
+// counting sort on the source and kept with the graph.
+void build_out_csr(sr_graph *g) {
+  if (g->out_built) return;
+  const int32_t n = g->n;
+  const int64_t m = g->m;
+  std::vector<int64_t> off((size_t)n + 1, 0);
+  for (int64_t e = 0; e < m; ++e) off[(size_t)g->in_src[e] + 1]++;
+  for (int32_t v = 0; v < n; ++v) off[v + 1] += off[v];
+  g->out_dst.assign((size_t)m, 0);
+  if (g->weighted) g->out_w.assign((size_t)m, 0);
+  std::vector<int64_t> cur(off.begin(), off.end() - 1);
+  for (int32_t v = 0; v < n; ++v)
+    for (int64_t e = g->in_off[v]; e < g->in_off[v + 1]; ++e) {
+      const int64_t k = cur[g->in_src[e]]++;
+      g->out_dst[k] = v;
+      if (g->weighted) g->out_w[k] = g->in_w[e];
+    }
+  g->out_off = std::move(off);
+  g->out_built = true;
+}
+
+// Candidate value of v through the edge u -> v (weight w), with the device
+// sweep's arithmetic: CC passes the label, BFS adds one level, SSSP adds the
+// weight; INF stays INF and sums saturate at INF.
+static inline uint32_t relax_value(int algo, uint32_t xu, uint32_t w) {
+  if (algo == A_CC) return xu;
+  if (xu == INF) return INF;
+  const uint64_t c = (uint64_t)xu + (algo == A_SSSP ? (uint64_t)w : 1ull);
+  return c >= (uint64_t)INF ? INF : (uint32_t)c;
+}
+
+// Push from the frontier until no value decreases: rounds of label
+// correction, each round's list split over host threads, atomic minimum on
+// the values and an in-list flag per vertex. Monotone min relaxations reach
+// the same least fixed point in any order, so the result is exact.
+int64_t sparse_push(const sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
+                    int32_t *rounds_out) {
+  const int32_t n = g->n;
+  std::vector<uint8_t> inq((size_t)n, 0);
+  std::vector<int32_t> cur;
+  cur.reserve((size_t)nf);
+  for (int64_t i = 0; i < nf; ++i) {
+    const uint32_t v = front[i];
+    if (v < (uint32_t)n && !inq[v]) { inq[v] = 1; cur.push_back((int32_t)v); }
+  }
+  const int T = host_threads();
+  int64_t relaxed = 0;
+  int32_t rounds = 0;
+  std::vector<std::vector<int32_t>> next(T);
+  std::vector<int64_t> cnt(T);
+  while (!cur.empty()) {
+    ++rounds;
+    for (int32_t u : cur) inq[u] = 0;  // a later decrease puts u back
+    auto work = [&](int t, size_t lo, size_t hi) {
+      auto &nx = next[t];
+      int64_t c = 0;
+      for (size_t i = lo; i < hi; ++i) {
+        const int32_t u = cur[i];
+        const uint32_t xu = __atomic_load_n(&val[u], __ATOMIC_RELAXED);
+        if (xu == INF && algo != A_CC) continue;
+        for (int64_t e = g->out_off[u]; e < g->out_off[u + 1]; ++e) {
+          const int32_t v = g->out_dst[e];
+          const uint32_t nd = relax_value(algo, xu, g->weighted ? g->out_w[e] : 1u);
+          ++c;
+          uint32_t old = __atomic_load_n(&val[v], __ATOMIC_RELAXED);
+          bool lowered = false;
+          while (nd < old) {
+            if (__atomic_compare_exchange_n(&val[v], &old, nd, true, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+              lowered = true;
+              break;
+            }
+          }
+          if (lowered && __atomic_exchange_n(&inq[v], (uint8_t)1, __ATOMIC_RELAXED) == 0) nx.push_back(v);
+        }
+      }
+      cnt[t] = c;
+    };
+    const int use = (int)std::min<size_t>((size_t)T, std::max<size_t>(1, cur.size() / 256));
+    for (int t = 0; t < T; ++t) { next[t].clear(); cnt[t] = 0; }
+    if (use <= 1) {
+      work(0, 0, cur.size());
+    } else {
+      std::vector<std::thread> th;
+      for (int t = 0; t < use; ++t)
+        th.emplace_back(work, t, cur.size() * t / use, cur.size() * (t + 1) / use);
+      for (auto &x : th) x.join();
+    }
+    cur.clear();
+    for (int t = 0; t < T; ++t) {
+      relaxed += cnt[t];
+      cur.insert(cur.end(), next[t].begin(), next[t].end());
+    }
+  }
+  if (rounds_out) *rounds_out = rounds;
+  return relaxed;
+}
+
+}  // namespace sr

@@ -1,0 +1,134 @@
+"""Heterogeneous execution (Section 3.1): the device runs dense pull passes
+and, once a pass changes few vertices, the host finishes with push
+relaxations from that pass's frontier. The result must equal the oracle
+exactly, whatever the switch point, schedule or graph."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sr():
+    import paper_1806_00762_amd as sr
+    sr.lib()
+    return sr
+
+
+@pytest.fixture(scope="module")
+def ctx(sr):
+    c = sr.Context(0, 0)
+    yield c
+    c.close()
+
+
+GRAPHS = {
+    "rmat14w": lambda: graphgen.rmat(14, 16, seed=14, weights=(1, 255, 5)),
+    "uniform12w": lambda: graphgen.uniform(12, 1 << 15, seed=9, weights=(1, 255, 7)),
+}
+_cache = {}
+
+
+def graph(name):
+    if name not in _cache:
+        _cache[name] = GRAPHS[name]()
+    return _cache[name]
+
+
+SCHED = {
+    "resident": dict(parts=1, slots=4, force=False, depth=0),
+    "s3p3": dict(parts=3, slots=3, force=True, depth=1),
+    "s4p7d2": dict(parts=7, slots=4, force=True, depth=2),
+}
+
+
+def run(ctx, g, algo, sched, sym=False, source=0, **kw):
+    s = SCHED[sched]
+    G = ctx.load(g, symmetrize=sym)
+    try:
+        G.partition(s["parts"], s["slots"])
+        st = G.run(algo, source=source, max_inner_iters=4, force_stream=s["force"], copy_depth=s["depth"],
+                   hetero=True, max_passes=5000, **kw)
+        return G.values(), st
+    finally:
+        G.close()
+
+
+@pytest.mark.parametrize("gname", list(GRAPHS))
+@pytest.mark.parametrize("sched", list(SCHED))
+@pytest.mark.parametrize("switch", [0, 64, 1 << 30])
+def test_hetero_exact(sr, ctx, gname, sched, switch):
+    g = graph(gname)
+    src = int(np.argmax(np.diff(g.offsets)))
+    cases = (("sssp", oracle.sssp(g, src), False), ("bfs", oracle.bfs(g, src), False), ("cc", oracle.cc(g), True))
+    for algo, ref, sym in cases:
+        for pvu in ("strong", "off"):
+            got, st = run(ctx, g, algo, sched, sym=sym, source=src, pvu=pvu, sparse_switch=switch)
+            say(f"case hetero {gname} {sched} switch={switch} {algo} {pvu}: passes {st['passes']} "
+                f"sparse {st['sparse_stage']} frontier {st['sparse_frontier']} rounds {st['sparse_rounds']}")
+            assert st["converged"] == 1
+            assert np.array_equal(got, ref), f"{algo} {pvu}: {np.sum(got != ref)} mismatches"
+    if switch == 1 << 30:
+        # a switch threshold above n hands over after the first complete pass
+        assert st["sparse_stage"] == 1
+
+
+def test_hetero_triggers_and_saves_passes(sr, ctx):
+    g = graph("rmat14w")
+    src = int(np.argmax(np.diff(g.offsets)))
+    G = ctx.load(g)
+    try:
+        G.partition(7, 4)
+        base = G.run("sssp", source=src, pvu="strong", force_stream=True)
+        ref = G.values()
+        het = G.run("sssp", source=src, pvu="strong", force_stream=True, hetero=True, sparse_switch=2048)
+        assert np.array_equal(G.values(), ref)
+        assert np.array_equal(ref, oracle.sssp(g, src))
+        say(f"case hetero passes {het['passes']} vs {base['passes']}, frontier {het['sparse_frontier']}")
+        assert het["sparse_stage"] == 1
+        assert het["passes"] < base["passes"]
+        assert 0 < het["sparse_frontier"] <= 2048
+    finally:
+        G.close()
+
+
+def test_hetero_refused_cases(sr, ctx):
+    g = graph("rmat14w")
+    G = ctx.load(g)
+    try:
+        G.partition(1, 4)
+        for algo, pvu in (("sssp", "weak"), ("pagerank", "weak"), ("pagerank", "off")):
+            with pytest.raises(sr.SeraphError) as e:
+                G.run(algo, source=0, pvu=pvu, hetero=True)
+            assert e.value.status == sr.SR_EINVAL
+        with pytest.raises(sr.SeraphError):
+            G.run("sssp", source=0, pvu="strong", hetero=True, sparse_switch=-1)
+        st = G.run("sssp", source=0, hetero=True)  # default prediction becomes strong
+        assert np.array_equal(G.values(), oracle.sssp(g, 0))
+    finally:
+        G.close()
+
+
+def test_hetero_tiny_graphs(sr, ctx):
+    cases = [
+        graphgen.from_edges(1, [], [], []),
+        graphgen.from_edges(2, [0], [1], [5]),
+        graphgen.from_edges(5, [0, 1, 2, 3], [1, 2, 3, 4], [1, 2, 3, 4]),
+        graphgen.from_edges(4, [1, 2], [2, 3], [7, 7]),
+    ]
+    for g in cases:
+        for sched in ("resident", "s3p3"):
+            got, _ = run(ctx, g, "sssp", sched, pvu="strong", sparse_switch=1 << 30)
+            assert np.array_equal(got, oracle.sssp(g, 0))
+            got, _ = run(ctx, g, "cc", sched, sym=True, pvu="strong", sparse_switch=1 << 30)
+            assert np.array_equal(got, oracle.cc(g))

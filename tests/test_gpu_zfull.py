@@ -57,10 +57,13 @@ def test_sssp_s22_streamed_quarter_budget(sr):
         G.partition(0, 4)
         info = G.info()
         assert info["num_parts"] >= 4 and info["resident"] == 0
-        for pvu in ("weak", "strong", "off"):
-            st = G.run("sssp", source=0, pvu=pvu, max_inner_iters=8, force_stream=True)
+        configs = [("weak", {}), ("strong", {}), ("off", {}), ("strong", {"copy_depth": 2}),
+                   ("strong", {"copy_depth": 2, "hetero": True})]
+        for pvu, kw in configs:
+            st = G.run("sssp", source=0, pvu=pvu, max_inner_iters=8, force_stream=True, **kw)
             d = G.values()
-            say(f"sssp s22 {pvu}: passes {st['passes']} h2d {st['h2d_bytes'] / 1e6:.0f} MB wall {st['wall_ms']:.0f} ms")
+            say(f"sssp s22 {pvu} {kw}: passes {st['passes']} h2d {st['h2d_bytes'] / 1e6:.0f} MB "
+                f"wall {st['wall_ms']:.0f} ms sparse {st['sparse_stage']} frontier {st['sparse_frontier']}")
             assert np.array_equal(d, ref)
             assert st["h2d_bytes"] >= info["graph_bytes"]
             used, cap = ctx.memory()
