@@ -204,22 +204,35 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
   bool att[MI_ROUNDS];
 #pragma unroll
   for (int r = 0; r < MI_ROUNDS; ++r) {
-    int idx = ((item * WAVES + wave) * MI_ROUNDS + r) * VPW + vs;
-    vl[r] = idx < cnt ? bins[idx] : -1;
-    beg[r] = 0; end[r] = 0; att[r] = false; old[r] = 0;
-    if (vl[r] >= 0) {
-      beg[r] = off[vl[r]];
-      end[r] = off[vl[r] + 1];
-      att[r] = mi_attempt<ALGO, K>(g, vb + vl[r], k, ln, old[r]);
-    }
+    // loads are unconditional (lanes past the bin reread its first vertex)
+    // so the rounds' bin, offset and value loads overlap
+    const int idx = ((item * WAVES + wave) * MI_ROUNDS + r) * VPW + vs;
+    const bool ok = idx < cnt;
+    vl[r] = cnt > 0 ? bins[ok ? idx : 0] : 0;  // an empty bin rereads the page's vertex 0
+    beg[r] = off[vl[r]];
+    end[r] = off[vl[r] + 1];
+    old[r] = 0;
+    att[r] = mi_attempt<ALGO, K>(g, vb + vl[r], k, ln, old[r]) && ok;
+    if (!ok) vl[r] = -1;
   }
 #pragma unroll
   for (int r = 0; r < MI_ROUNDS; ++r) {
     T x = R::identity();
     if (att[r]) {
-      for (int e = beg[r] + ein; e < end[r]; e += GE) {
-        const uint32_t q = src[e];
-        x = R::combine(x, R::edge(g, (int32_t)(q & g.src_mask), mi_weight<ALGO>(g, q, wt, e), k, ln));
+      // batches of 4 edges per lane: word loads, then gathers, in flight together
+      for (int e0 = beg[r] + ein; e0 < end[r]; e0 += 4 * GE) {
+        int32_t ei[4];
+        uint32_t q[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          ei[j] = e0 + j * GE < end[r] ? e0 + j * GE : e0;
+          q[j] = src[ei[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const T y = R::edge(g, (int32_t)(q[j] & g.src_mask), mi_weight<ALGO>(g, q[j], wt, ei[j]), k, ln);
+          if (e0 + j * GE < end[r]) x = R::combine(x, y);
+        }
       }
     }
 #pragma unroll
@@ -229,7 +242,7 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
   }
 }
 
-// edge loop of bins 6 and 7: 64/K edge lanes, 4 edges in flight per lane
+// edge loop of bins 6 and 7: 64/K edge lanes, 8 edges in flight per lane
 template <int ALGO, int K>
 __device__ inline typename MiRed<ALGO, K>::T mi_edges(const MiGroup &g, const uint32_t *src, const uint32_t *wt,
                                                       int32_t e0, int32_t e1, int k, int el, const Lane &ln) {
@@ -237,19 +250,20 @@ __device__ inline typename MiRed<ALGO, K>::T mi_edges(const MiGroup &g, const ui
   using T = typename R::T;
   constexpr int EL = 64 / K;
   T x = R::identity();
-  int e = e0 + el;
-  for (; e + 3 * EL < e1; e += 4 * EL) {
-    const uint32_t q0 = src[e], q1 = src[e + EL], q2 = src[e + 2 * EL], q3 = src[e + 3 * EL];
-    const uint32_t w0 = mi_weight<ALGO>(g, q0, wt, e), w1 = mi_weight<ALGO>(g, q1, wt, e + EL);
-    const uint32_t w2 = mi_weight<ALGO>(g, q2, wt, e + 2 * EL), w3 = mi_weight<ALGO>(g, q3, wt, e + 3 * EL);
-    const uint32_t m = g.src_mask;
-    T y0 = R::edge(g, (int32_t)(q0 & m), w0, k, ln), y1 = R::edge(g, (int32_t)(q1 & m), w1, k, ln);
-    T y2 = R::edge(g, (int32_t)(q2 & m), w2, k, ln), y3 = R::edge(g, (int32_t)(q3 & m), w3, k, ln);
-    x = R::combine(x, R::combine(R::combine(y0, y1), R::combine(y2, y3)));
-  }
-  for (; e < e1; e += EL) {
-    const uint32_t q = src[e];
-    x = R::combine(x, R::edge(g, (int32_t)(q & g.src_mask), mi_weight<ALGO>(g, q, wt, e), k, ln));
+  constexpr int B = 8;
+  for (int e = e0 + el; e < e1; e += B * EL) {
+    int32_t ei[B];
+    uint32_t q[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      ei[j] = e + j * EL < e1 ? e + j * EL : e;  // past the range: reread a real edge
+      q[j] = src[ei[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const T y = R::edge(g, (int32_t)(q[j] & g.src_mask), mi_weight<ALGO>(g, q[j], wt, ei[j]), k, ln);
+      if (e + j * EL < e1) x = R::combine(x, y);
+    }
   }
 #pragma unroll
   for (int m = K; m < 64; m <<= 1) x = R::combine(x, shfl_xor(x, m));

@@ -265,18 +265,15 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
   bool act[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
+    // loads are unconditional (lanes past the tile reread its first vertex)
+    // so the offset, value and state loads of both vertices overlap
     const int i = 2 * tid + j;
-    lv[j] = t0 + i;
-    act[j] = false;
-    eb[j] = 0;
-    d[j] = 0;
-    gt[j] = Gate{false, 0, 0u};
-    if (i < nv) {
-      eb[j] = p.off[lv[j]];
-      d[j] = p.off[lv[j] + 1] - eb[j];
-      gt[j] = gate_of(r, p.v_begin + lv[j]);
-      act[j] = (gt[j].attempt || r.audit) && (d[j] > 0 || is_pr<ALGO>());
-    }
+    const bool in = i < nv;
+    lv[j] = t0 + (in ? i : 0);
+    eb[j] = p.off[lv[j]];
+    d[j] = p.off[lv[j] + 1] - eb[j];
+    gt[j] = gate_of(r, p.v_begin + lv[j]);
+    act[j] = in && (gt[j].attempt || r.audit) && (d[j] > 0 || is_pr<ALGO>());
   }
   int na = (int)act[0] + (int)act[1];
   int ne = (act[0] ? d[0] : 0) + (act[1] ? d[1] : 0);
@@ -334,17 +331,22 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
       kk[j] = q < At ? k : -1;
       e[j] = s.eb[k] + (q - s.pos[k]);
     }
-    int32_t u[EDGES_PER_THREAD];
-    uint32_t w[EDGES_PER_THREAD];
+    // every load is issued unconditionally (positions past the tile reread
+    // the thread's first edge, which is real since p0 < At), so the
+    // EDGES_PER_THREAD edge-word loads and then the EDGES_PER_THREAD gathers
+    // are all in flight together instead of one masked load at a time
 #pragma unroll
-    for (int j = 0; j < EDGES_PER_THREAD; ++j) {
-      const uint32_t word = kk[j] >= 0 ? p.src[e[j]] : 0u;
-      u[j] = src_of(p, word);
-      w[j] = (ALGO == A_SSSP && kk[j] >= 0) ? weight_of(p, word, e[j]) : 0u;
-    }
+    for (int j = 0; j < EDGES_PER_THREAD; ++j) e[j] = kk[j] >= 0 ? e[j] : e[0];
+    uint32_t word[EDGES_PER_THREAD];
+#pragma unroll
+    for (int j = 0; j < EDGES_PER_THREAD; ++j) word[j] = p.src[e[j]];
     T x[EDGES_PER_THREAD];
 #pragma unroll
-    for (int j = 0; j < EDGES_PER_THREAD; ++j) x[j] = kk[j] >= 0 ? R::edge(r, u[j], w[j]) : R::identity();
+    for (int j = 0; j < EDGES_PER_THREAD; ++j) {
+      const uint32_t w = ALGO == A_SSSP ? weight_of(p, word[j], e[j]) : 0u;
+      const T y = R::edge(r, src_of(p, word[j]), w);
+      x[j] = kk[j] >= 0 ? y : R::identity();
+    }
     int ck = kk[0];
     T cur = x[0];
 #pragma unroll
@@ -394,21 +396,22 @@ __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
   bool comp = g.attempt || r.audit;
   T x = R::identity();
   if (comp) {
-    int e = c.e_begin + lane;
-    for (; e + 192 < c.e_end; e += 256) {
-      const uint32_t q0 = p.src[e], q1 = p.src[e + 64], q2 = p.src[e + 128], q3 = p.src[e + 192];
-      uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-      if (ALGO == A_SSSP) {
-        a0 = weight_of(p, q0, e); a1 = weight_of(p, q1, e + 64);
-        a2 = weight_of(p, q2, e + 128); a3 = weight_of(p, q3, e + 192);
+    // batches of 8 edges per lane: 8 edge-word loads, then 8 gathers, all
+    // in flight together (lanes past the chunk reread its first edge)
+    constexpr int B = 8;
+    for (int e0 = c.e_begin + lane; e0 < c.e_end; e0 += B * 64) {
+      int32_t ei[B];
+      uint32_t q[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        ei[j] = e0 + j * 64 < c.e_end ? e0 + j * 64 : c.e_begin;
+        q[j] = p.src[ei[j]];
       }
-      T y0 = R::edge(r, src_of(p, q0), a0), y1 = R::edge(r, src_of(p, q1), a1);
-      T y2 = R::edge(r, src_of(p, q2), a2), y3 = R::edge(r, src_of(p, q3), a3);
-      x = R::combine(x, R::combine(R::combine(y0, y1), R::combine(y2, y3)));
-    }
-    for (; e < c.e_end; e += 64) {
-      const uint32_t q = p.src[e];
-      x = R::combine(x, R::edge(r, src_of(p, q), ALGO == A_SSSP ? weight_of(p, q, e) : 0u));
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const T y = R::edge(r, src_of(p, q[j]), ALGO == A_SSSP ? weight_of(p, q[j], ei[j]) : 0u);
+        if (e0 + j * 64 < c.e_end) x = R::combine(x, y);
+      }
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) x = R::combine(x, shfl_xor(x, m));
