@@ -31,11 +31,10 @@ constexpr int BLOCK = 256;        // threads per workgroup (4 wavefronts)
 constexpr int WAVES = BLOCK / 64;
 
 // Tiles of the single-instance sweep: runs of consecutive non-heavy
-// vertices with at most TILE_V vertices and tile_e in-edges (a page
-// parameter, TILE_E_MIN or TILE_E_MAX), one block each.
+// vertices with at most TILE_V vertices and TILE_E in-edges, one block
+// each (8 edges per thread).
 constexpr int TILE_V = 2 * BLOCK;
-constexpr int TILE_E_MIN = 8 * BLOCK;
-constexpr int TILE_E_MAX = 16 * BLOCK;
+constexpr int TILE_E = 8 * BLOCK;
 
 // vertices per block for bins 0..6 and chunks per block for bin 7
 constexpr int SMALL_ROUNDS = 4;   // vertices per lane group in bins 0..5
@@ -108,7 +107,7 @@ struct alignas(256) PageHeader {
   int32_t max_indeg;
   int32_t n_tiles;
   int32_t w_bytes;               // 4: separate u32 weight section; 0: none (unweighted or packed)
-  int32_t tile_e;                // in-edge cap of a tile: TILE_E_MIN or TILE_E_MAX
+  int32_t tile_e;                // in-edge cap of a tile (TILE_E)
   int32_t packed;                // edge words carry the weight in their top byte
 };
 static_assert(sizeof(PageHeader) == 256, "page header is one 256-byte line");

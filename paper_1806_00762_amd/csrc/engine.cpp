@@ -479,7 +479,9 @@ struct Runner {
     a.fr_count = g->state.fr_count;
     a.fr_cap = g->state.fr_cap;
     a.nblocks = std::max<int32_t>(blk, 1);  // an empty window still closes its sweep
-    a.tile_e = pages.empty() ? TILE_E_MIN : g->pages[pages[0]].hdr.tile_e;
+    // the masked decode also serves unweighted graphs whose ids fit 24 bits
+    // (it needs fewer registers than the plain one)
+    a.packed = (g->weighted ? g->packed : (int64_t)g->n <= ((int64_t)1 << 24)) ? 1 : 0;
     return SR_OK;
   }
 

@@ -119,7 +119,6 @@ int32_t auto_parts(const sr_graph *g, uint64_t slot_bytes);
 void free_pages(sr_graph *g);
 uint64_t graph_bytes(const sr_graph *g);
 int host_threads();
-int tile_edges();
 // sparse.cpp
 void build_out_csr(sr_graph *g);
 int64_t sparse_push(const sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,

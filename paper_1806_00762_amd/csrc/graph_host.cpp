@@ -35,12 +35,6 @@ static void parallel_for(int64_t n, int T, F f, int64_t min_n = 4096) {
   for (auto &x : th) x.join();
 }
 
-// In-edges per tile (SR_TILE_E = 2048 or 4096; 2048 unless set).
-int tile_edges() {
-  const char *e = getenv("SR_TILE_E");
-  if (e && atoi(e) >= TILE_E_MAX) return TILE_E_MAX;
-  return TILE_E_MIN;
-}
 
 uint64_t graph_bytes(const sr_graph *g) {
   return 4ull * ((uint64_t)g->n + 1) + 4ull * (uint64_t)g->m * (g->weighted ? 2 : 1);
@@ -265,7 +259,7 @@ static PageHeader page_header(const sr_graph *g, int32_t vb, int32_t ve) {
   }
   h.packed = g->weighted && g->packed ? 1 : 0;
   h.w_bytes = g->weighted && !g->packed ? 4 : 0;
-  h.tile_e = tile_edges();
+  h.tile_e = TILE_E;
   uint64_t o = sizeof(PageHeader);
   h.off_offsets = o; o = align256(o + 4ull * ((uint64_t)h.n_p + 1));
   // tiles: greedy runs of consecutive non-heavy vertices

@@ -60,8 +60,6 @@ struct PageCtx {
   const Chunk *chunks;
   const uint32_t *src;       // edge words: source id, or source | weight << 24 when packed
   const uint32_t *w;         // separate u32 weights (unpacked weighted pages)
-  uint32_t src_mask;         // source id bits of an edge word
-  int32_t packed;
   int32_t bin_count, bin_start;
   unsigned long long *partial;  // heavy-vertex accumulators, at each vertex's first chunk
 };
@@ -116,9 +114,14 @@ __device__ inline Gate gate_of(const Run &r, int32_t v) {
 }
 
 // Source and weight of page-local in-edge e from its edge word.
-__device__ inline int32_t src_of(const PageCtx &p, uint32_t word) { return (int32_t)(word & p.src_mask); }
+// PACKED: the word is source | weight << 24; else the source id, with the
+// weight (SSSP) in the separate u32 section.
+template <bool PACKED>
+__device__ inline int32_t src_of(uint32_t word) { return (int32_t)(PACKED ? word & PACKED_SRC_MASK : word); }
+template <bool PACKED>
 __device__ inline uint32_t weight_of(const PageCtx &p, uint32_t word, int32_t e) {
-  return p.packed ? word >> 24 : p.w[e];
+  if constexpr (PACKED) return word >> 24;
+  else return p.w[e];
 }
 
 // Contribution of one in-edge (u -> v, weight w) to the reduction.
@@ -231,10 +234,10 @@ __device__ inline void frontier_push(const Run &r, bool changed, int32_t v) {
 }
 
 // ------------------------------------------------------------------ tiles
-// One block per tile of consecutive vertices (<= TILE_V vertices, <= tile_e
+// One block per tile of consecutive vertices (<= TILE_V vertices, <= TILE_E
 // in-edges). Phase 1 gates the vertices (two consecutive ones per thread)
 // and compacts the attempting ones with a block-wide scan into LDS. Phase 2
-// assigns every thread tile_e/256 consecutive positions of the compacted edge list
+// assigns every thread TILE_E/256 consecutive positions of the compacted edge list
 // (merge-path style: one binary search, then a forward walk), so the in-edge
 // reads of a wavefront cover one contiguous range; the source loads and
 // gathers of a thread are independent, and runs of edges of the same vertex
@@ -252,7 +255,7 @@ struct TileLds {
   int32_t wsum[WAVES][2];
 };
 
-template <int ALGO, int EDGES_PER_THREAD>
+template <int ALGO, int EDGES_PER_THREAD, bool PACKED>
 __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, TileLds &s) {
   using R = Red<ALGO>;
   using T = typename R::T;
@@ -343,8 +346,8 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
     T x[EDGES_PER_THREAD];
 #pragma unroll
     for (int j = 0; j < EDGES_PER_THREAD; ++j) {
-      const uint32_t w = ALGO == A_SSSP ? weight_of(p, word[j], e[j]) : 0u;
-      const T y = R::edge(r, src_of(p, word[j]), w);
+      const uint32_t w = ALGO == A_SSSP ? weight_of<PACKED>(p, word[j], e[j]) : 0u;
+      const T y = R::edge(r, src_of<PACKED>(word[j]), w);
       x[j] = kk[j] >= 0 ? y : R::identity();
     }
     int ck = kk[0];
@@ -383,7 +386,7 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
 // or an exact fixed-point add for PageRank sums); the close kernel, after
 // the sweep has finished, takes the accumulator (resetting it) and runs the
 // vertex's epilogue, so no fence or arrival counter is needed in the sweep.
-template <int ALGO>
+template <int ALGO, bool PACKED>
 __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
   using R = Red<ALGO>;
   using T = typename R::T;
@@ -409,7 +412,7 @@ __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
       }
 #pragma unroll
       for (int j = 0; j < B; ++j) {
-        const T y = R::edge(r, src_of(p, q[j]), ALGO == A_SSSP ? weight_of(p, q[j], ei[j]) : 0u);
+        const T y = R::edge(r, src_of<PACKED>(q[j]), ALGO == A_SSSP ? weight_of<PACKED>(p, q[j], ei[j]) : 0u);
         if (e0 + j * 64 < c.e_end) x = R::combine(x, y);
       }
     }
@@ -516,7 +519,7 @@ __device__ inline void publish_record(const SweepRecord *src, SweepRecord *dst) 
 }
 
 // ------------------------------------------------------------ the sweep
-template <int ALGO, int EPT>
+template <int ALGO, int EPT, bool PACKED>
 __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   Ctl *ctl = a.ctl;
   if (ctl->done) return;  // converged: every block leaves before counting
@@ -544,8 +547,6 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   p.chunks = reinterpret_cast<const Chunk *>(base + h->off_chunks);
   p.src = reinterpret_cast<const uint32_t *>(base + h->off_src);
   p.w = reinterpret_cast<const uint32_t *>(base + h->off_w);
-  p.packed = h->packed;
-  p.src_mask = h->packed ? PACKED_SRC_MASK : 0xFFFFFFFFu;
   p.bin_count = h->bin_count[BIN_CHUNK];
   p.bin_start = 0;
   p.partial = a.partial[ent];
@@ -577,8 +578,8 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   // a launch over pages without any work still runs one block, so the
   // sweep (and the pass) is closed the same way
   if (b < a.blk_prefix[a.nent * NSEC]) {
-    if (sec == 0) sweep_tile<ALGO, EPT>(r, p, item, acc, s_tile);
-    else sweep_chunk<ALGO>(r, p, item);
+    if (sec == 0) sweep_tile<ALGO, EPT, PACKED>(r, p, item, acc, s_tile);
+    else sweep_chunk<ALGO, PACKED>(r, p, item);
   }
 
   // block reduction of the counters, then one set of device-scope atomics
@@ -815,10 +816,11 @@ __global__ void init_ctl_kernel(Ctl *ctl, Ctl init) {
 
 template <int ALGO>
 static void launch_pair(const SweepArgs &a, hipStream_t s) {
-  if (a.tile_e == TILE_E_MAX)
-    hipLaunchKernelGGL((sweep_kernel<ALGO, TILE_E_MAX / BLOCK>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+  constexpr int EPT = TILE_E / BLOCK;
+  if (a.packed)
+    hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
   else
-    hipLaunchKernelGGL((sweep_kernel<ALGO, TILE_E_MIN / BLOCK>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, false>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
   hipLaunchKernelGGL(close_kernel<ALGO>, dim3(1), dim3(CLOSE_THREADS), 0, s, a);
 }
 

@@ -18,7 +18,7 @@ struct SweepArgs {
   int32_t audit;           // evaluate skipped vertices too, count would-be changes
   int32_t pr_seed;         // personalized PageRank seed, -1 = uniform teleport
   int32_t nblocks;         // grid size
-  int32_t tile_e;          // in-edges per tile of every page of the launch
+  int32_t packed;          // edge words carry the weight in their top byte
   float damping;
   float pr_eps;
   Ctl *ctl;                // device control block
