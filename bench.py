@@ -245,6 +245,40 @@ def ablation(args, G, parts, dist):
     return out
 
 
+def bench_lattice(args):
+    """Page skipping on a high-diameter graph with locality: SSSP from a corner
+    of a 1024 x 1024 lattice (weights 1-9), pages streamed through 4 slots
+    within a quarter of the graph bytes, with and without skipping the pages
+    no changed vertex points into."""
+    import graphgen
+    import oracle
+    import paper_1806_00762_amd as sr
+    g = graphgen.grid(1024, 1024, weights=(1, 9, 2024))
+    ref = oracle.sssp(g, 0)
+    budget = (4 * (g.n + 1) + 8 * g.m) // 4
+    ctx = sr.Context(0, budget)
+    G = ctx.load(g)
+    G.partition(0, 4)
+    out = {"workload": "sssp_grid1024x1024_w1-9_corner_streamed_budget_quarter", "n": g.n, "m": g.m,
+           "pages": G.info()["num_parts"]}
+    for name, skip in (("all_pages", False), ("skip_clean", True)):
+        kw = dict(source=0, pvu="strong", force_stream=True, copy_depth=2, skip_clean=skip, max_passes=100000)
+        G.run("sssp", **kw)
+        sync()
+        t0 = time.perf_counter()
+        st = G.run("sssp", **kw)
+        sync()
+        el = time.perf_counter() - t0
+        assert np.array_equal(G.values(), ref), name
+        out[name] = {"ms_per_solve": round(el * 1e3, 2), "passes": st["passes"], "sweeps": st["sweeps"],
+                     "h2d_bytes": st["h2d_bytes"], "pages_skipped": st["pages_skipped"],
+                     "solve_gteps": round(g.m / el / 1e9, 4)}
+    out["parity"] = "bit-exact"
+    G.close()
+    ctx.close()
+    return out
+
+
 def bench_batched(args):
     """256 personalized-PageRank instances over 32 R-MAT graphs (scales 12-20,
     edge factor 8/16/32), 8 seeds per graph: one batched call vs a loop of
@@ -448,6 +482,8 @@ def main():
         return
     res = bench_sssp22(args)
     if not args.no_extras:
+        res["lattice"] = bench_lattice(args)
+        log(f"[bench] lattice: {res['lattice']}")
         res["batched"] = bench_batched(args)
         log(f"[bench] batched: {res['batched']}")
         res["served"] = bench_served(args)

@@ -167,6 +167,23 @@ def from_edges(n: int, src, dst, w=None, *, symmetrize=False, drop_self_loops=Tr
                  None if ww is None else ww.astype(np.uint32), name)
 
 
+def grid(rows: int, cols: int, *, weights=None, name="") -> Graph:
+    """2-D lattice with row-major ids and arcs both ways between 4-neighbours:
+    a high-diameter graph with locality (page-level skipping has work to save).
+    ``weights`` = (lo, hi, seed) draws one weight per arc."""
+    n = rows * cols
+    ids = np.arange(n, dtype=np.int64).reshape(rows, cols)
+    right = (ids[:, :-1].ravel(), ids[:, 1:].ravel())
+    down = (ids[:-1, :].ravel(), ids[1:, :].ravel())
+    src = np.concatenate([right[0], right[1], down[0], down[1]])
+    dst = np.concatenate([right[1], right[0], down[1], down[0]])
+    w = None
+    if weights is not None:
+        lo, hi, seed = weights
+        w = bounded_draws(seed, 3, src.size, lo, hi)
+    return from_edges(n, src, dst, w, name=name or f"grid{rows}x{cols}")
+
+
 # --- workload recipes -------------------------------------------------------
 # Seeds and shapes of the synthetic workloads; each returns a Graph.
 

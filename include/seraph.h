@@ -67,6 +67,11 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
                                      (mispredictions) without applying them */
 #define SR_RUN_FORCE_STREAM 0x2u  /* stream pages through slots even if the graph fits */
 #define SR_RUN_RESUME 0x4u        /* continue from the values/state left by the last run */
+#define SR_RUN_SKIP_CLEAN 0x20u   /* streamed min programs (strong or no prediction): a pass copies
+                                     and sweeps only the pages with an in-edge from a vertex that
+                                     changed in the previous pass (the others are at their local
+                                     fixed point); falls back to every page when that pass changed
+                                     more vertices than the frontier holds (n / 16) */
 #define SR_RUN_HETERO 0x10u       /* heterogeneous model of Section 3.1: once a pass of a min
                                      program (BFS/SSSP/CC, strong or no prediction) changes at most
                                      sparse_switch vertices, the host finishes the run with push
@@ -217,6 +222,7 @@ typedef struct {
   int64_t sparse_frontier;   /* vertices it started from (changed in the last device pass) */
   int64_t sparse_relaxations;/* edges it relaxed */
   double sparse_ms;          /* its wall time, transfers included */
+  int64_t pages_skipped;     /* SR_RUN_SKIP_CLEAN: page visits left out because no in-edge changed */
 } sr_run_stats;
 
 /* Run a vertex program to convergence on the graph (partitioned with

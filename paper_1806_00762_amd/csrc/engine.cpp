@@ -608,13 +608,15 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (p.max_passes == 0) p.max_passes = 10000;
   if (p.max_inner_iters == 0) p.max_inner_iters = 4;
   if (p.max_passes < 0 || p.max_inner_iters < 0) return c->fail(SR_EINVAL, "negative limits");
-  if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_FORCE_STREAM | SR_RUN_RESUME | SR_RUN_FIXED_INNER | SR_RUN_HETERO))
+  if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_FORCE_STREAM | SR_RUN_RESUME | SR_RUN_FIXED_INNER | SR_RUN_HETERO |
+                  SR_RUN_SKIP_CLEAN))
     return c->fail(SR_EINVAL, "unknown run flags");
   const bool pr = R.algo == A_PR || R.algo == A_PPR;
   // defaults (Section 4.3 discussion): BFS/CC strong, SSSP/PageRank weak;
   // with the host sparse stage SSSP takes the strong conditions too
   if (p.pvu == SR_PVU_DEFAULT)
-    p.pvu = (R.algo == A_BFS || R.algo == A_CC || (R.algo == A_SSSP && (p.flags & SR_RUN_HETERO)))
+    p.pvu = (R.algo == A_BFS || R.algo == A_CC ||
+             (R.algo == A_SSSP && (p.flags & (SR_RUN_HETERO | SR_RUN_SKIP_CLEAN))))
                 ? SR_PVU_STRONG : SR_PVU_WEAK;
   if (p.pvu < SR_PVU_OFF || p.pvu > SR_PVU_WEAK) return c->fail(SR_EINVAL, "unknown pvu mode");
   if (pr && p.pvu == SR_PVU_STRONG) return c->fail(SR_EINVAL, "PageRank has no strong condition (Table I)");
@@ -660,19 +662,42 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   // once a pass changes few vertices; exact when every vertex of that pass
   // was pulled or provably final (strong or no prediction)
   const bool hetero = (p.flags & SR_RUN_HETERO) != 0;
-  uint32_t sparse_thr = 0;
+  // page skipping: only streamed passes have copies and sweeps to leave out
+  const bool skip = (p.flags & SR_RUN_SKIP_CLEAN) != 0 && !g->res.resident;
+  uint32_t sparse_thr = 0, fr_need = 0;
+  if (hetero || (p.flags & SR_RUN_SKIP_CLEAN)) {
+    if (pr) return c->fail(SR_EINVAL, "the sparse stage and page skipping serve BFS, SSSP and CC");
+    if (R.pvu == P_WEAK)
+      return c->fail(SR_EINVAL, "the sparse stage and page skipping need strong or no prediction");
+  }
   if (hetero) {
-    if (pr) return c->fail(SR_EINVAL, "the sparse stage serves BFS, SSSP and CC");
-    if (R.pvu == P_WEAK) return c->fail(SR_EINVAL, "the sparse stage needs strong or no prediction");
     if (p.sparse_switch < 0) return c->fail(SR_EINVAL, "sparse_switch must be >= 0");
     sparse_thr = p.sparse_switch > 0 ? (uint32_t)p.sparse_switch : (uint32_t)std::max<int32_t>(1024, g->n / 512);
     sparse_thr = std::min<uint32_t>(sparse_thr, (uint32_t)g->n);
-    if (g->state.fr_cap < sparse_thr) {
+    fr_need = sparse_thr;
+  }
+  if (skip) {
+    fr_need = std::max<uint32_t>(fr_need, std::min<uint32_t>((uint32_t)g->n, std::max<uint32_t>(1024, g->n / 16)));
+    sr::build_out_masks(g);
+  }
+  if (fr_need > 0) {
+    // the frontier takes what the budget has left, up to fr_need entries: a
+    // smaller one only means more passes overflow it (then every page is
+    // visited, and the sparse stage waits for a pass that fits)
+    if (g->state.fr_cap < fr_need) {
+      const uint64_t room = c->budget > c->used + 1024 ? c->budget - c->used - 1024 : 0;
+      const uint64_t mine = 4ull * g->state.fr_cap;  // freed below
+      const uint32_t want = fr_need;
+      fr_need = (uint32_t)std::min<uint64_t>(want, (room + mine) / 4);
+      if (fr_need < std::min<uint32_t>(want, 256))
+        return c->fail(SR_EBUDGET, "budget has no room for the pass frontier");
+    }
+    if (g->state.fr_cap < fr_need) {
       c->dfree(g->state.frontier);
       g->state.frontier = nullptr;
       g->state.fr_cap = 0;
-      if ((s = c->dalloc((void **)&g->state.frontier, 4ull * sparse_thr, "pass frontier")) != SR_OK) return s;
-      g->state.fr_cap = sparse_thr;
+      if ((s = c->dalloc((void **)&g->state.frontier, 4ull * fr_need, "pass frontier")) != SR_OK) return s;
+      g->state.fr_cap = fr_need;
     }
     if (!g->state.fr_count && (s = c->dalloc((void **)&g->state.fr_count, 256, "frontier count")) != SR_OK)
       return s;
@@ -740,42 +765,63 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   // already satisfied (its target was pulled after the source's last change,
   // or is final by Table I), so the push from the frontier is exact.
   auto begin_pass = [&]() -> sr_status {
-    R.collect = (hetero && (R.last_pass_changed <= 32ull * sparse_thr || (uint64_t)g->n <= 32ull * sparse_thr)) ? 1 : 0;
+    R.collect = (skip || (hetero && (R.last_pass_changed <= 32ull * sparse_thr ||
+                                     (uint64_t)g->n <= 32ull * sparse_thr))) ? 1 : 0;
     if (R.collect) {
       hipError_t e2 = launch_fill_u32(g->state.fr_count, 0u, 1, c->compute);
       if (e2 != hipSuccess) return c->hip_fail(e2, "frontier reset");
     }
     return SR_OK;
   };
-  auto sparse_stage = [&](bool *fin) -> sr_status {
-    *fin = false;
-    if (!R.collect || R.last_pass_changed > sparse_thr) return SR_OK;
-    const double t1 = now_ms();
+  // the frontier of the pass just closed (false when it overflowed)
+  std::vector<uint32_t> fr;
+  auto read_frontier = [&](bool *complete) -> sr_status {
+    *complete = false;
     uint32_t cnt = 0;
     HIP_TRY(c, hipMemcpyAsync(&cnt, g->state.fr_count, 4, hipMemcpyDeviceToHost, c->compute), "frontier count");
     HIP_TRY(c, hipStreamSynchronize(c->compute), "frontier count");
-    if (cnt > g->state.fr_cap) return SR_OK;  // incomplete: the device goes on
-    std::vector<uint32_t> val((size_t)g->n), fr((size_t)cnt + 1);
-    HIP_TRY(c, hipMemcpyAsync(val.data(), g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute),
-            "values to host");
-    if (cnt)
+    if (cnt > g->state.fr_cap) return SR_OK;  // incomplete
+    fr.resize(cnt);
+    if (cnt) {
       HIP_TRY(c, hipMemcpyAsync(fr.data(), g->state.frontier, 4ull * cnt, hipMemcpyDeviceToHost, c->compute),
               "frontier to host");
+      HIP_TRY(c, hipStreamSynchronize(c->compute), "frontier to host");
+    }
+    *complete = true;
+    return SR_OK;
+  };
+  auto sparse_stage = [&](bool have_fr, bool *fin) -> sr_status {
+    *fin = false;
+    if (!hetero || !R.collect || !have_fr || R.last_pass_changed > sparse_thr) return SR_OK;
+    const double t1 = now_ms();
+    std::vector<uint32_t> val((size_t)g->n);
+    HIP_TRY(c, hipMemcpyAsync(val.data(), g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute),
+            "values to host");
     HIP_TRY(c, hipStreamSynchronize(c->compute), "values to host");
     sr::build_out_csr(g);
     int32_t rounds = 0;
-    const int64_t relaxed = sr::sparse_push(g, R.algo, val.data(), fr.data(), (int64_t)cnt, &rounds);
+    const int64_t relaxed = sr::sparse_push(g, R.algo, val.data(), fr.data(), (int64_t)fr.size(), &rounds);
     HIP_TRY(c, hipMemcpyAsync(g->state.value, val.data(), 4ull * g->n, hipMemcpyHostToDevice, c->compute),
             "values to device");
     HIP_TRY(c, hipStreamSynchronize(c->compute), "values to device");
     R.st.sparse_stage = 1;
     R.st.sparse_rounds = rounds;
-    R.st.sparse_frontier = (int64_t)cnt;
+    R.st.sparse_frontier = (int64_t)fr.size();
     R.st.sparse_relaxations = relaxed;
     R.st.sparse_ms = now_ms() - t1;
     R.st.stop_reason = SR_STOP_CONVERGED;
     *fin = true;
     return SR_OK;
+  };
+  // after a pass: the host sparse stage if it applies
+  auto pass_end_host = [&](bool *fin) -> sr_status {
+    *fin = false;
+    bool have = false;
+    if (R.collect) {
+      sr_status s2 = read_frontier(&have);
+      if (s2 != SR_OK) return s2;
+    }
+    return sparse_stage(have, fin);
   };
 
   bool done = false;
@@ -809,7 +855,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       R.harvest(&done);
       if (!done) {
         bool fin = false;
-        if ((s = sparse_stage(&fin)) != SR_OK) return s;
+        if ((s = pass_end_host(&fin)) != SR_OK) return s;
         done = fin;
       }
       if (launched > p.max_passes + 8) break;
@@ -875,10 +921,11 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     while (!done) {
       // pass start: every earlier sweep has finished (host synced at the pass end)
       if ((s = begin_pass()) != SR_OK) return s;
-      if (page_slot[ord[0]] < 0) {
+      const int32_t NP = (int32_t)ord.size();  // pages of this pass
+      if (NP > 0 && page_slot[ord[0]] < 0) {
         if ((s = copy_page(ord[0], free_slot({}), false)) != SR_OK) return s;
       }
-      for (int32_t j = 0; j < P && !done; ++j) {
+      for (int32_t j = 0; j < NP && !done; ++j) {
         std::vector<int32_t> win;
         for (int32_t q = std::max(0, j - W + 1); q <= j; ++q) win.push_back(ord[q]);
         for (int32_t q : win) HIP_TRY(c, hipStreamWaitEvent(c->compute, copy_done[page_slot[q]], 0), "compute wait");
@@ -886,7 +933,9 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
         // first pages); a free slot was last read by an earlier step's sweeps
         std::vector<int32_t> keep = win;
         for (int32_t q = 1; q <= D; ++q) {
-          const int32_t page = ord[(j + q) % P];
+          // skipping decides the next pass's pages at the pass end: no wrap
+          if (skip && j + q >= NP) break;
+          const int32_t page = ord[(j + q) % NP];
           if (std::find(keep.begin(), keep.end(), page) != keep.end()) continue;
           if (page_slot[page] < 0) {
             const int32_t sl = free_slot(keep);
@@ -896,7 +945,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
           keep.push_back(page);
         }
         // the window slides once the page it takes next has landed
-        const int32_t next_slot = page_slot[ord[(j + 1) % P]];
+        const int32_t next_slot = page_slot[ord[(j + 1) % NP]];
         const bool copying = next_slot >= 0 && hipEventQuery(copy_done[next_slot]) != hipSuccess;
         std::vector<int32_t> ws;
         for (int32_t q : win) { ws.push_back(page_slot[q]); last_use[page_slot[q]] = step_clock; }
@@ -923,9 +972,23 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       if ((s = R.sync_compute()) != SR_OK) return s;
       R.harvest(&done);
       if (!done) {
-        bool fin = false;
-        if ((s = sparse_stage(&fin)) != SR_OK) return s;
+        bool fin = false, have = false;
+        if (R.collect && (s = read_frontier(&have)) != SR_OK) return s;
+        if ((s = sparse_stage(have, &fin)) != SR_OK) return s;
         done = fin;
+        if (!done && skip) {
+          // next pass: the pages an edge from a changed vertex enters; all
+          // of them when the frontier overflowed
+          ord.clear();
+          if (have) {
+            const uint64_t m = sr::frontier_pages(g, fr.data(), (int64_t)fr.size());
+            for (int32_t i = 0; i < P; ++i)
+              if (m >> (P <= 64 ? i : (int)((int64_t)i * 64 / P)) & 1ull) ord.push_back(i);
+          } else {
+            for (int32_t i = 0; i < P; ++i) ord.push_back(i);
+          }
+          R.st.pages_skipped += P - (int64_t)ord.size();
+        }
       }
       pass++;
       if (pass > p.max_passes + 2) break;

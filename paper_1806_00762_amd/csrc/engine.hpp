@@ -106,6 +106,10 @@ struct sr_graph {
   std::vector<int64_t> out_off;
   std::vector<int32_t> out_dst;
   std::vector<uint32_t> out_w;
+  // per vertex, the pages its out-edges enter (bit page * 64 / P), for
+  // SR_RUN_SKIP_CLEAN; built for the partition with out_mask_parts pages
+  std::vector<uint64_t> out_mask;
+  int32_t out_mask_parts = 0;
 };
 
 namespace sr {
@@ -121,6 +125,9 @@ uint64_t graph_bytes(const sr_graph *g);
 int host_threads();
 // sparse.cpp
 void build_out_csr(sr_graph *g);
+void build_out_masks(sr_graph *g);
+// OR of the out-page masks of the frontier's vertices
+uint64_t frontier_pages(const sr_graph *g, const uint32_t *front, int64_t nf);
 int64_t sparse_push(const sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
                     int32_t *rounds);
 // engine.cpp

@@ -110,3 +110,37 @@ int64_t sparse_push(const sr_graph *g, int algo, uint32_t *val, const uint32_t *
 }
 
 }  // namespace sr
+
+namespace sr {
+
+// Bit of page p in a 64-bit page mask (pages share bits when P > 64, which
+// only makes the dirty test more conservative).
+static inline int page_bit(int32_t p, int32_t P) { return P <= 64 ? p : (int)((int64_t)p * 64 / P); }
+
+void build_out_masks(sr_graph *g) {
+  const int32_t P = (int32_t)g->pages.size();
+  if (g->out_mask_parts == P && (int64_t)g->out_mask.size() == (int64_t)g->n) return;
+  build_out_csr(g);
+  std::vector<uint8_t> bit((size_t)g->n);
+  for (int32_t p = 0; p < P; ++p) {
+    const int b = page_bit(p, P);
+    for (int32_t v = g->pages[p].hdr.v_begin; v < g->pages[p].hdr.v_begin + g->pages[p].hdr.n_p; ++v)
+      bit[v] = (uint8_t)b;
+  }
+  g->out_mask.assign((size_t)g->n, 0ull);
+  for (int32_t u = 0; u < g->n; ++u) {
+    uint64_t m = 0;
+    for (int64_t e = g->out_off[u]; e < g->out_off[u + 1]; ++e) m |= 1ull << bit[g->out_dst[e]];
+    g->out_mask[u] = m;
+  }
+  g->out_mask_parts = P;
+}
+
+uint64_t frontier_pages(const sr_graph *g, const uint32_t *front, int64_t nf) {
+  uint64_t m = 0;
+  for (int64_t i = 0; i < nf; ++i)
+    if (front[i] < (uint32_t)g->n) m |= g->out_mask[front[i]];
+  return m;
+}
+
+}  // namespace sr

@@ -98,3 +98,17 @@ def test_batched_recipe_shapes(i):
     g = graphgen.recipes.batched_graph(i) if scale <= 16 else None
     if g is not None:
         assert g.n == 1 << scale
+
+
+def test_grid_lattice_shape():
+    """The lattice has 2*(r*(c-1) + c*(r-1)) arcs, both directions of every
+    4-neighbour pair, and hop distances from a corner are Manhattan distances."""
+    import oracle
+    r, c = 7, 11
+    g = graphgen.grid(r, c, weights=(1, 9, 5))
+    assert g.n == r * c and g.m == 2 * (r * (c - 1) + c * (r - 1))
+    deg = np.diff(g.offsets)
+    assert deg.min() == 2 and deg.max() == 4
+    assert g.weights.min() >= 1 and g.weights.max() <= 9
+    rr, cc = np.divmod(np.arange(g.n), c)
+    assert np.array_equal(oracle.bfs(g, 0), (rr + cc).astype(np.uint32))
