@@ -54,7 +54,8 @@ typedef enum { SR_BFS = 0, SR_SSSP = 1, SR_CC = 2, SR_PAGERANK = 3, SR_PPR = 4 }
 /* Predictive vertex updating (Section 4). STRONG uses the Table I
  * thresholds (BFS, SSSP, CC only); WEAK uses the state-transition diagram of
  * Section 4.3 / Fig. 6; DEFAULT picks STRONG for BFS and CC and WEAK for SSSP
- * and PageRank, as the paper evaluates them (Section 4.3 Discussion, 5.1). */
+ * and PageRank, as the paper evaluates them (Section 4.3 Discussion, 5.1),
+ * except STRONG for SSSP under SR_RUN_HETERO or SR_RUN_SKIP_CLEAN. */
 typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAULT = 3 } sr_pvu_mode;
 
 /* sr_graph_load_csr flags */
@@ -67,22 +68,25 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
                                      (mispredictions) without applying them */
 #define SR_RUN_FORCE_STREAM 0x2u  /* stream pages through slots even if the graph fits */
 #define SR_RUN_RESUME 0x4u        /* continue from the values/state left by the last run */
-#define SR_RUN_SKIP_CLEAN 0x20u   /* streamed min programs (strong or no prediction): a pass copies
-                                     and sweeps only the pages with an in-edge from a vertex that
-                                     changed in the previous pass (the others are at their local
-                                     fixed point); falls back to every page when that pass changed
-                                     more vertices than the frontier holds (n / 16) */
+#define SR_RUN_FIXED_INNER 0x8u   /* every window step runs exactly max_inner_iters sweeps; with
+                                     num_slots = 2 this is CLIP's loaded-data re-entry (Section 3.2),
+                                     with max_inner_iters = 1 the single-pass baseline of Section 5.4 */
 #define SR_RUN_HETERO 0x10u       /* heterogeneous model of Section 3.1: once a pass of a min
                                      program (BFS/SSSP/CC, strong or no prediction) changes at most
                                      sparse_switch vertices, the host finishes the run with push
                                      relaxations from that pass's frontier (the sparse stage) */
-#define SR_RUN_FIXED_INNER 0x8u   /* every window step runs exactly max_inner_iters sweeps; with
-                                     num_slots = 2 this is CLIP's loaded-data re-entry (Section 3.2),
-                                     with max_inner_iters = 1 the single-pass baseline of Section 5.4 */
+#define SR_RUN_SKIP_CLEAN 0x20u   /* streamed min programs (strong or no prediction): a pass copies
+                                     and sweeps only the pages with an in-edge from a vertex that
+                                     changed in the previous pass (the others are at their local
+                                     fixed point); falls back to every page when that pass changed
+                                     more vertices than the frontier holds (n / 16 entries, fewer if
+                                     the device budget has less room) */
 
 /* stop reasons reported in sr_run_stats.stop_reason */
-#define SR_STOP_CONVERGED 1   /* a full un-predicted pass changed nothing (min programs)
-                                 or its L1 change fell below tol_l1 (PageRank) */
+#define SR_STOP_CONVERGED 1   /* min programs: a full pass changed nothing (with weak prediction,
+                                 a verification pass without prediction), or the host sparse stage
+                                 reached the fixed point; PageRank: the L1 change of a pass without
+                                 prediction fell below tol_l1 */
 #define SR_STOP_FP32_FLOOR 2  /* PageRank: L1 stalled below 1e-6 for 3 full passes */
 #define SR_STOP_MAX_PASSES 3
 
