@@ -458,10 +458,12 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=32)
     ap.add_argument("--requests", type=int, default=20000)
     ap.add_argument("--rate", type=float, default=2000.0)
-    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (for HBM counter scaling)")
     ap.add_argument("--served-timeout", type=float, default=90.0)
+    ap.add_argument("--only", choices=["batched", "served", "lattice"],
+                    help="run one extra leg alone and print its JSON object")
     ap.add_argument("--copy-depth", type=int, default=2,
                     help="page copies kept in flight ahead of the window (1 = the paper's layout)")
     ap.add_argument("--no-other", action="store_true", help="skip the other predictor's solves")
@@ -479,6 +481,11 @@ def main():
     torch.cuda.init()
     if args.copy_calibration:
         print(json.dumps(copy_calibration()), flush=True)
+        return
+    if args.only:
+        # one extra leg alone (for profiling it): its JSON object only
+        fn = {"batched": bench_batched, "served": bench_served, "lattice": bench_lattice}[args.only]
+        print(json.dumps(fn(args)), flush=True)
         return
     res = bench_sssp22(args)
     if not args.no_extras:

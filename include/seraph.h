@@ -303,7 +303,7 @@ sr_status sr_batch_run(sr_ctx *ctx, const sr_instance *instances, int32_t count,
 
 /* A continuous-batching query server (beyond the paper): SSSP and BFS
  * source queries on resident graphs. Each graph owns max_slots_per_graph
- * (8 or 16) query slots whose state (4 B distance per vertex per slot) is
+ * (8, 16 or 32) query slots whose state (4 B distance per vertex per slot) is
  * allocated up front if state_budget_bytes allows, else as many slots as
  * fit. A progress thread admits queued queries into free slots as they
  * free up, sweeps every graph with active slots (one multi-source sweep

@@ -1,15 +1,17 @@
 // batch.hip -- multi-instance pull sweep for gfx950: K instances (K = 8 or
-// 16) of personalized PageRank, SSSP or BFS on resident graphs, several
+// 16; 32 for SSSP/BFS) of personalized PageRank, SSSP or BFS on resident graphs, several
 // graphs in one persistent launch. A wavefront is split into 64/K edge
 // lanes x K instance lanes: the K lanes of one edge lane load the same
 // in-edge source (one broadcast load) and gather the K contiguous values of
 // that neighbour (one 4K-byte access), so every index and weight read is
 // shared by K instances. Blocks take work items from a device queue until
 // it is empty and accumulate per-instance counters in LDS, flushed once per
-// block; a one-block close kernel then combines the heavy-vertex chunks and
-// closes the sweep for every instance (convergence, thresholds, PageRank
-// dangling mass). The pair is replayed from a captured graph with no host
-// work in between; no fence is executed inside the sweep.
+// block. Heavy-vertex chunks fold their partials into per-vertex
+// accumulators with device-scope atomics; a heavy-vertex kernel (one thread
+// per vertex and instance) then runs their epilogues, and a one-block close
+// kernel closes the sweep for every instance (convergence, thresholds,
+// PageRank dangling mass). The three launches are replayed from a captured
+// graph with no host work in between; no fence is executed inside the sweep.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -28,13 +30,19 @@ __device__ inline T shfl_xor(T v, int m) { return __shfl_xor(v, m, 64); }
 
 // vertices (bins 0..6, 8) or chunks (bin 7) per work item of the multi-
 // instance sweep with K instance lanes
+// A heavy-vertex chunk is split over K/8 wavefronts (at least one): with
+// 64/K edge lanes per wavefront, wide instance groups would otherwise leave
+// one wavefront a long serial edge loop.
+__host__ __device__ constexpr int mi_subchunks(int K) { return K >= 16 ? K / 8 : 1; }
+
 __host__ __device__ inline int mi_items_per_block(int b, int K) {
   const int EL = 64 / K;
   if (b <= 5) {
     int GE = (1 << b) < EL ? (1 << b) : EL;
     return WAVES * MI_ROUNDS * (EL / GE);
   }
-  if (b == BIN_WAVE || b == BIN_CHUNK) return WAVES;
+  if (b == BIN_WAVE) return WAVES;
+  if (b == BIN_CHUNK) return WAVES / mi_subchunks(K);  // chunks: WAVES sub-chunks per item
   return MI_ROUNDS * (BLOCK / K);
 }
 
@@ -289,25 +297,36 @@ __device__ void mi_wave(const MiGroup &g, const char *base, const PageHeader *h,
   if (att && el == 0) mi_epilogue<ALGO, K>(g, v, k, ln, old, x, (uint32_t)(off[vl + 1] - off[vl]), damping, acc);
 }
 
-// bin 7: one wavefront per chunk; the partial of each instance column is a
-// plain store, combined by the close kernel after the sweep
+// bin 7: one wavefront per chunk; each instance column folds its partial
+// into the heavy vertex's accumulator
 template <int ALGO, int K>
 __device__ void mi_chunk(const MiGroup &g, const MiUnit &u, const char *base, const PageHeader *h, int item,
                          const Lane &ln) {
   using R = MiRed<ALGO, K>;
   using T = typename R::T;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, k = lane % K, el = lane / K;
-  int idx = item * WAVES + wave;
+  constexpr int S = mi_subchunks(K);
+  const int sidx = item * WAVES + wave;
+  const int idx = sidx / S, sub = sidx % S;
   if (idx >= h->bin_count[BIN_CHUNK]) return;
   const Chunk c = reinterpret_cast<const Chunk *>(base + h->off_chunks)[idx];
+  const int32_t len = (c.e_end - c.e_begin + S - 1) / S;
+  const int32_t sb = c.e_begin + sub * len, se = min(c.e_end, sb + len);
+  if (sb >= se) return;
   const uint32_t *src = reinterpret_cast<const uint32_t *>(base + h->off_src);
   const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
   const int32_t v = h->v_begin + c.vl;
   uint32_t old;
   bool att = mi_attempt<ALGO, K>(g, v, k, ln, old);
   T x = R::identity();
-  if (__any(att)) x = mi_edges<ALGO, K>(g, src, wt, c.e_begin, c.e_end, k, el, ln);
-  if (el == 0) u.partial[(size_t)idx * K + k] = R::bits(x);
+  if (__any(att)) x = mi_edges<ALGO, K>(g, src, wt, sb, se, k, el, ln);
+  // fold into the vertex's accumulator (one device-scope atomic per chunk
+  // and instance); the heavy-vertex kernel takes it after the sweep
+  if (el == 0 && att) {
+    unsigned long long *slot = &u.acc[(size_t)((uint32_t)c.first_count & 0xFFFFFu) * K + k];
+    if constexpr (mi_pr<ALGO>()) atomicAdd(slot, (unsigned long long)llrint((double)x * FIX_ONE));
+    else if (x != INF) atomicMin(reinterpret_cast<uint32_t *>(slot), (uint32_t)x);
+  }
 }
 
 // bin 8 (PPR only): zero in-degree, the value still follows the teleport term
@@ -392,56 +411,66 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
   }
 }
 
-// Close a sweep: combine the chunk partials of every heavy vertex of every
-// live group (chunk order) and run their epilogues, then close every
-// instance (convergence, thresholds, dangling mass) and reset the queue.
-// One block, launched after the sweep.
+// Heavy vertices after a sweep: one thread per (heavy vertex, instance)
+// takes the vertex's accumulator with an exchange (leaving the identity),
+// runs the epilogue and adds its counters to the instance's sweep totals.
 template <int ALGO, int K>
-__global__ void __launch_bounds__(MI_CLOSE_THREADS) mi_close_kernel(MiArgs a) {
+__global__ void __launch_bounds__(BLOCK) mi_heavy_kernel(MiArgs a) {
   using R = MiRed<ALGO, K>;
   using T = typename R::T;
   if (a.ctl->remaining == 0 && !a.tuning) return;
-  extern __shared__ MiLds lds[];
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int32_t hh = (int32_t)(p / K), k = (int32_t)(p % K);
+  if (hh >= a.total_heavy) return;
+  int lo = 0, hi = a.nunits;  // units[lo].heavy_base <= hh < units[lo + 1].heavy_base
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.units[mid].heavy_base <= hh) lo = mid; else hi = mid;
+  }
+  const MiUnit &u = a.units[lo];
+  if (a.group_active[u.group] == 0) return;  // the sweep skipped the group: accumulators untouched
+  const MiGroup &g = a.groups[u.group];
+  const PageHeader *h = reinterpret_cast<const PageHeader *>(u.page);
+  const Heavy x = reinterpret_cast<const Heavy *>(u.page + h->off_heavy)[hh - u.heavy_base];
+  const int32_t *off = reinterpret_cast<const int32_t *>(u.page + h->off_offsets);
+  unsigned long long *slot = &u.acc[(size_t)((uint32_t)x.first_count & 0xFFFFFu) * K + k];
+  T t;
+  if constexpr (mi_pr<ALGO>()) t = (float)((double)(long long)atomicExch(slot, 0ull) / FIX_ONE);
+  else t = atomicExch(reinterpret_cast<uint32_t *>(slot), INF);
+  const int32_t v = h->v_begin + x.vl;
+  const Lane ln = lane_of(g.inst[k]);
+  uint32_t old;
+  if (!mi_attempt<ALGO, K>(g, v, k, ln, old)) return;
+  MiAcc acc;
+  mi_epilogue<ALGO, K>(g, v, k, ln, old, t, (uint32_t)(off[x.vl + 1] - off[x.vl]), a.damping, acc);
+  MiInst &in = g.inst[k];
+  if (acc.changed) atomicAdd(&in.sw_changed, acc.changed);
+  if (acc.min_changed != INF) atomicMin(&in.sw_min_changed, acc.min_changed);
+  if (acc.edges) atomicAdd(&in.sw_edges, (unsigned long long)acc.edges);
+  if constexpr (mi_pr<ALGO>()) {
+    if (acc.l1 != 0.0) atomicAdd(&in.sw_l1, acc.l1);
+    if (acc.ddelta != 0.0) atomicAdd(&in.sw_ddelta, acc.ddelta);
+  }
+}
+
+// Close a sweep: close every instance (convergence, thresholds, dangling
+// mass) from its sweep totals and reset the queue. One block, after the
+// sweep and the heavy-vertex kernel.
+template <int ALGO, int K>
+__global__ void __launch_bounds__(MI_CLOSE_THREADS) mi_close_kernel(MiArgs a) {
+  if (a.ctl->remaining == 0 && !a.tuning) return;
   __shared__ uint32_t s_rem;
   const int ninst = a.ngroups * K;
-  lds_clear(lds, ninst, MI_CLOSE_THREADS);
   if (threadIdx.x == 0) s_rem = 0;
-  __syncthreads();
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = MI_CLOSE_THREADS / 64;
-  if (lane < K) {
-    for (int ui = 0; ui < a.nunits; ++ui) {
-      const MiUnit &u = a.units[ui];
-      if (a.group_active[u.group] == 0) continue;
-      const MiGroup &g = a.groups[u.group];
-      const PageHeader *h = reinterpret_cast<const PageHeader *>(u.page);
-      const Heavy *hv = reinterpret_cast<const Heavy *>(u.page + h->off_heavy);
-      const int32_t *off = reinterpret_cast<const int32_t *>(u.page + h->off_offsets);
-      const Lane ln = lane_of(g.inst[lane]);
-      for (int i = wave; i < h->n_heavy; i += nw) {
-        const Heavy x = hv[i];
-        const int first = (int)((uint32_t)x.first_count & 0xFFFFFu), count = (int)((uint32_t)x.first_count >> 20);
-        const int32_t v = h->v_begin + x.vl;
-        uint32_t old;
-        if (!mi_attempt<ALGO, K>(g, v, lane, ln, old)) continue;
-        T t = R::identity();
-        for (int j = 0; j < count; ++j) t = R::combine(t, R::from_bits(u.partial[(size_t)(first + j) * K + lane]));
-        MiAcc acc;
-        mi_epilogue<ALGO, K>(g, v, lane, ln, old, t, (uint32_t)(off[x.vl + 1] - off[x.vl]), a.damping, acc);
-        lds_add<ALGO>(lds[u.group * K + lane], acc);
-      }
-    }
-  }
-  __syncthreads();
   for (int gi = threadIdx.x; gi < a.ngroups; gi += MI_CLOSE_THREADS) a.group_active[gi] = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < ninst; i += MI_CLOSE_THREADS) {
     MiInst &in = a.groups[i / K].inst[i % K];
     if (!in.active) continue;
-    const MiLds &e = lds[i];
-    const uint32_t changed = in.sw_changed + e.changed;
-    const uint32_t minc = min(in.sw_min_changed, e.min_changed);
-    const double l1 = in.sw_l1 + e.l1, dd = in.sw_ddelta + e.ddelta;
-    in.edges_total += in.sw_edges + e.edges;
+    const uint32_t changed = in.sw_changed;
+    const uint32_t minc = in.sw_min_changed;
+    const double l1 = in.sw_l1, dd = in.sw_ddelta;
+    in.edges_total += in.sw_edges;
     in.sweeps += 1;
     bool done = false;
     if constexpr (mi_pr<ALGO>()) {
@@ -508,7 +537,8 @@ template <int ALGO, int K>
 void mi_pair(const MiArgs &a, hipStream_t s) {
   const size_t lds = sizeof(MiLds) * (size_t)a.ngroups * K;
   hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
-  hipLaunchKernelGGL((mi_close_kernel<ALGO, K>), dim3(1), dim3(MI_CLOSE_THREADS), lds, s, a);
+  hipLaunchKernelGGL((mi_heavy_kernel<ALGO, K>), dim3(a.heavy_blocks), dim3(BLOCK), 0, s, a);
+  hipLaunchKernelGGL((mi_close_kernel<ALGO, K>), dim3(1), dim3(MI_CLOSE_THREADS), 0, s, a);
 }
 
 }  // namespace
@@ -522,6 +552,7 @@ hipError_t launch_mi_sweep(int algo, int K, const MiArgs &a, hipStream_t s) {
   else if (algo == A_PPR && K == 16) mi_pair<A_PPR, 16>(a, s);
   else if (algo == A_SSSP && K == 8) mi_pair<A_SSSP, 8>(a, s);
   else if (algo == A_SSSP && K == 16) mi_pair<A_SSSP, 16>(a, s);
+  else if (algo == A_SSSP && K == 32) mi_pair<A_SSSP, 32>(a, s);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -533,6 +564,7 @@ hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contri
   else if (algo == A_PPR && K == 16) hipLaunchKernelGGL((mi_init_column_kernel<A_PPR, 16>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
   else if (algo == A_SSSP && K == 8) hipLaunchKernelGGL((mi_init_column_kernel<A_SSSP, 8>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
   else if (algo == A_SSSP && K == 16) hipLaunchKernelGGL((mi_init_column_kernel<A_SSSP, 16>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
+  else if (algo == A_SSSP && K == 32) hipLaunchKernelGGL((mi_init_column_kernel<A_SSSP, 32>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -541,6 +573,7 @@ hipError_t launch_mi_extract(int K, const uint32_t *value, int32_t n, int32_t co
   dim3 grid((n + 255) / 256), block(256);
   if (K == 8) hipLaunchKernelGGL(mi_extract_kernel<8>, grid, block, 0, s, value, n, col, out);
   else if (K == 16) hipLaunchKernelGGL(mi_extract_kernel<16>, grid, block, 0, s, value, n, col, out);
+  else if (K == 32) hipLaunchKernelGGL(mi_extract_kernel<32>, grid, block, 0, s, value, n, col, out);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

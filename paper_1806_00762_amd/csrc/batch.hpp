@@ -52,9 +52,9 @@ struct MiGroup {
 // One unit of work: a resident page of a group's graph.
 struct MiUnit {
   int32_t group;
-  int32_t pad;
+  int32_t heavy_base;       // heavy vertices of the units before this one
   const char *page;
-  uint32_t *partial;        // [n_chunks][K]
+  unsigned long long *acc;  // [n_chunks][K] heavy-vertex accumulators (at each vertex's first chunk)
   int32_t blk_prefix[NBINS + 1];  // items per bin within this unit
 };
 
@@ -72,6 +72,8 @@ struct MiArgs {
   const int32_t *unit_prefix;  // [nunits + 1] items
   int32_t ngroups, nunits;
   int32_t total_items;
+  int32_t total_heavy;      // heavy vertices over all units
+  int32_t heavy_blocks;     // blocks of the heavy-vertex kernel
   int32_t grab;             // items taken per queue access
   int32_t nblocks;
   float damping;

@@ -103,6 +103,7 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
   sr_status s;
   units.clear();
   unit_prefix.assign(1, 0);
+  int32_t total_heavy = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     sr_graph *g = group_graph[gi];
     if (!g->res.resident) return c->fail(SR_EBUDGET, "batched graphs must be resident");
@@ -112,7 +113,16 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
       u.group = (int32_t)gi;
       u.page = g->res.buf[p];
       uint64_t nch = (uint64_t)std::max<int32_t>(h.n_chunks, 1);
-      if ((s = alloc((void **)&u.partial, 4ull * nch * K, "chunk partials")) != SR_OK) return s;
+      if ((s = alloc((void **)&u.acc, 8ull * nch * K, "heavy-vertex accumulators")) != SR_OK) return s;
+      {
+        // the reduction's identity: all ones (min; INF in the low word) or a
+        // fixed-point zero (PageRank sums); the heavy kernel restores it
+        std::vector<unsigned long long> idv(nch * K, algo == A_PPR ? 0ull : ~0ull);
+        hipError_t e = hipMemcpy(u.acc, idv.data(), 8ull * nch * K, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return c->hip_fail(e, "accumulator init");
+      }
+      u.heavy_base = total_heavy;
+      total_heavy += h.n_heavy;
       int32_t acc = 0;
       u.blk_prefix[0] = 0;
       for (int b = 0; b < NBINS; ++b) {
@@ -155,6 +165,8 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
   args.ngroups = (int32_t)groups.size();
   args.nunits = (int32_t)units.size();
   args.total_items = unit_prefix.back();
+  args.total_heavy = total_heavy;
+  args.heavy_blocks = (int32_t)std::max<int64_t>(1, ((int64_t)total_heavy * K + BLOCK - 1) / BLOCK);
   args.grab = 1;
   args.damping = (float)damping;
   args.tol_l1 = tol_l1;

@@ -177,7 +177,8 @@ extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_
                                       int32_t max_slots, sr_server **out) {
   if (!c) return SR_EINVAL;
   if (!graphs || ngraphs < 1 || ngraphs > 8 || !out) return c->fail(SR_EINVAL, "need 1..8 graphs and out");
-  if (max_slots != 8 && max_slots != 16) return c->fail(SR_EINVAL, "max_slots_per_graph must be 8 or 16");
+  if (max_slots != 8 && max_slots != 16 && max_slots != 32)
+    return c->fail(SR_EINVAL, "max_slots_per_graph must be 8, 16 or 32");
   if (c->host_only) return c->fail(SR_EDEVICE, "host-only context cannot serve");
   hipError_t he = hipSetDevice(c->device);
   if (he != hipSuccess) return c->hip_fail(he, "set device");

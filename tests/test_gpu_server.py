@@ -37,10 +37,13 @@ def wait_all(srv, tickets, outs, timeout=60.0):
     return lat
 
 
-@pytest.mark.parametrize("slots", [8, 16])
+@pytest.mark.parametrize("slots", [8, 16, 32])
 def test_server_alone_vs_mix(sr, slots):
+    # the scale-16 graph has vertices of in-degree above 2048 (heavy chunks,
+    # split over several wavefronts for the wider slot groups)
     graphs = [graphgen.rmat(12, 16, seed=81, weights=(1, 255, 82)),
-              graphgen.rmat(14, 8, seed=83, weights=(1, 255, 84))]
+              graphgen.rmat(14, 8, seed=83, weights=(1, 255, 84)),
+              graphgen.rmat(16, 16, seed=85, weights=(1, 255, 86))]
     ctx = sr.Context(0, 0)
     Gs = [ctx.load(g) for g in graphs]
     srv = sr.Server(ctx, Gs, state_budget_bytes=0, slots=slots)
@@ -48,7 +51,7 @@ def test_server_alone_vs_mix(sr, slots):
     reqs = []
     r = np.random.default_rng(slots)
     for i in range(60):
-        gi = int(r.integers(0, 2))
+        gi = int(r.integers(0, 3))
         algo = "sssp" if r.random() < 0.5 else "bfs"
         src = int(graphgen.sources_with_outedges(graphs[gi], 1, seed=100 + i)[0])
         reqs.append((gi, algo, src))
