@@ -528,9 +528,13 @@ __global__ void mi_set_ctl_kernel(MiCtl *dst, MiCtl val) {
 }
 
 template <int K>
-__global__ void mi_extract_kernel(const uint32_t *value, int32_t n, int32_t col, uint32_t *out) {
+__global__ void mi_extract_kernel(uint32_t *value, int32_t n, int32_t col, uint32_t *out, int32_t reset,
+                                  uint32_t reset_to) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) out[v] = value[(size_t)v * K + col];
+  if (v >= n) return;
+  const size_t i = (size_t)v * K + col;
+  out[v] = value[i];
+  if (reset) value[i] = reset_to;
 }
 
 template <int ALGO, int K>
@@ -569,11 +573,13 @@ hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contri
   return hipGetLastError();
 }
 
-hipError_t launch_mi_extract(int K, const uint32_t *value, int32_t n, int32_t col, uint32_t *out, hipStream_t s) {
+hipError_t launch_mi_extract(int K, uint32_t *value, int32_t n, int32_t col, uint32_t *out, hipStream_t s,
+                             bool reset, uint32_t reset_to) {
   dim3 grid((n + 255) / 256), block(256);
-  if (K == 8) hipLaunchKernelGGL(mi_extract_kernel<8>, grid, block, 0, s, value, n, col, out);
-  else if (K == 16) hipLaunchKernelGGL(mi_extract_kernel<16>, grid, block, 0, s, value, n, col, out);
-  else if (K == 32) hipLaunchKernelGGL(mi_extract_kernel<32>, grid, block, 0, s, value, n, col, out);
+  const int32_t r = reset ? 1 : 0;
+  if (K == 8) hipLaunchKernelGGL(mi_extract_kernel<8>, grid, block, 0, s, value, n, col, out, r, reset_to);
+  else if (K == 16) hipLaunchKernelGGL(mi_extract_kernel<16>, grid, block, 0, s, value, n, col, out, r, reset_to);
+  else if (K == 32) hipLaunchKernelGGL(mi_extract_kernel<32>, grid, block, 0, s, value, n, col, out, r, reset_to);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

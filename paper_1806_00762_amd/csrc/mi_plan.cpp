@@ -13,6 +13,7 @@
 #include <mutex>
 #include <sstream>
 
+#include "kernels.hpp"
 #include "mi_plan.hpp"
 
 namespace sr {
@@ -184,7 +185,15 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
   return SR_OK;
 }
 
-sr_status MiPlan::set_column(int gi, int col, int32_t source, bool unit, bool active, hipStream_t s) {
+sr_status MiPlan::clear_values(hipStream_t s) {
+  for (auto &gr : groups) {
+    hipError_t e = launch_fill_u32(gr.value, INF, (size_t)gr.n * K, s);
+    if (e != hipSuccess) return c->hip_fail(e, "column reset");
+  }
+  return SR_OK;
+}
+
+sr_status MiPlan::set_column(int gi, int col, int32_t source, bool unit, bool active, hipStream_t s, bool clean) {
   MiGroup &gr = groups[gi];
   sr_graph *g = group_graph[gi];
   MiInst in;
@@ -198,7 +207,9 @@ sr_status MiPlan::set_column(int gi, int col, int32_t source, bool unit, bool ac
   in.last_l1 = -1.0;
   if (algo == A_PPR) in.dangling = (source >= 0 && g->outdeg[source] == 0) ? 1.0 : 0.0;
   hipError_t e = hipSuccess;
-  if (source >= 0)
+  if (source >= 0 && clean && algo != A_PPR)
+    e = launch_fill_u32(gr.value + (size_t)source * K + col, 0u, 1, s);
+  else if (source >= 0)
     e = launch_mi_init_column(algo, K, gr.value, gr.contrib, gr.inv_outdeg, gr.n, col, source, s);
   if (e == hipSuccess) e = launch_mi_set_inst(gr.inst + col, in, s);
   if (e != hipSuccess) return c->hip_fail(e, "column init");

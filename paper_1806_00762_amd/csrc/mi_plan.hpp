@@ -43,7 +43,11 @@ struct MiPlan {
   // build units/prefix for all groups and upload the tables
   sr_status finalize(double damping, double tol_l1, int32_t max_sweeps);
   // (re)initialise column `col` of group `gi` and its control record
-  sr_status set_column(int gi, int col, int32_t source, bool unit, bool active, hipStream_t s);
+  // clean: the column already holds the initial value everywhere (SSSP/BFS
+  // INF), so only the source entry is written
+  sr_status set_column(int gi, int col, int32_t source, bool unit, bool active, hipStream_t s, bool clean = false);
+  // every column of every group back to INF (SSSP/BFS plans)
+  sr_status clear_values(hipStream_t s);
   sr_status set_remaining(uint32_t r, hipStream_t s);
   // pick grid size and grab by timing candidate sweeps; restores nothing
   // (callers re-initialise their columns afterwards)

@@ -91,7 +91,8 @@ void sr_server::progress() {
         qq.result = free_results[gi].back();
         free_results[gi].pop_back();
         slot_ticket[gi][col] = *it;
-        sr_status s = plan->set_column(gi, col, qq.source, qq.algo == SR_BFS, true, stream);
+        // retired columns are left at INF, so admission writes the source only
+        sr_status s = plan->set_column(gi, col, qq.source, qq.algo == SR_BFS, true, stream, true);
         if (s != SR_OK) { thread_error = s; thread_msg = c->err; }
         it = queue.erase(it);
       }
@@ -148,7 +149,7 @@ void sr_server::progress() {
         std::lock_guard<std::mutex> lk(mu);
         dst = q[f.first].result;
       }
-      e = launch_mi_extract(K, plan->groups[gi].value, plan->groups[gi].n, k, dst, stream);
+      e = launch_mi_extract(K, plan->groups[gi].value, plan->groups[gi].n, k, dst, stream, true, INF);
       if (e != hipSuccess) break;
     }
     if (!finished.empty() && e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -244,6 +245,7 @@ extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_
     for (int gi = 0; gi < ngraphs; ++gi)
       for (int k = 0; k < s->K; ++k)
         if ((st = s->plan->set_column(gi, k, -1, false, false, s->stream)) != SR_OK) return fail(st);
+    if ((st = s->plan->clear_values(s->stream)) != SR_OK) return fail(st);
     if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(c->fail(SR_EDEVICE, "server init"));
   }
   for (auto *g : s->graphs) g->server_refs++;
