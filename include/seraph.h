@@ -62,6 +62,12 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
 #define SR_LOAD_SYMMETRIZE 0x1u  /* build in-edges of the undirected graph (needed for CC) */
 #define SR_LOAD_SYMMETRIC 0x2u   /* the input is already symmetric with sorted rows: in-edges =
                                     out-edges; verified (SR_EINVAL if not), marks the graph undirected */
+#define SR_LOAD_REORDER 0x4u     /* renumber vertices internally by descending in-degree (total
+                                    degree when symmetrized), ties by id: hubs share the first pages
+                                    and cache lines. Sources, results and CC labels stay in the
+                                    caller's ids (CC labels: smallest caller id of the component);
+                                    page views show internal ids (sr_graph_order maps them).
+                                    sr_run only: batched and serving calls refuse such a graph. */
 
 /* sr_run_params.flags */
 #define SR_RUN_AUDIT_PVU 0x1u     /* also evaluate skipped vertices; count would-be changes
@@ -151,6 +157,7 @@ typedef struct {
   uint64_t page_bytes_total; /* sum of page buffer bytes (incl. work lists) */
   uint64_t max_page_bytes;
   int32_t resident;          /* pages currently resident on the device */
+  int32_t reordered;         /* loaded with SR_LOAD_REORDER */
 } sr_graph_info;
 sr_status sr_graph_info_get(const sr_graph *g, sr_graph_info *out);
 
@@ -172,6 +179,11 @@ typedef struct {
   uint64_t stream_bytes;     /* prefix a single-instance sweep copies (with weights) */
 } sr_page_view;
 sr_status sr_graph_page(const sr_graph *g, int32_t page, sr_page_view *out);
+/* Vertex numbering of a graph loaded with SR_LOAD_REORDER (host arrays of n
+ * entries, either may be NULL): internal_of[v] = internal id of the caller's
+ * vertex v; caller_of[i] = caller's id of internal vertex i. SR_ESTATE if
+ * the graph was loaded without reordering. */
+sr_status sr_graph_order(const sr_graph *g, int32_t *internal_of, int32_t *caller_of);
 void sr_graph_destroy(sr_graph *g);
 
 /* -------------------------------------------------------------------- run */

@@ -25,6 +25,7 @@ SR_BFS, SR_SSSP, SR_CC, SR_PAGERANK, SR_PPR = 0, 1, 2, 3, 4
 SR_PVU_OFF, SR_PVU_STRONG, SR_PVU_WEAK, SR_PVU_DEFAULT = 0, 1, 2, 3
 SR_LOAD_SYMMETRIZE = 0x1
 SR_LOAD_SYMMETRIC = 0x2
+SR_LOAD_REORDER = 0x4
 SR_RUN_AUDIT_PVU, SR_RUN_FORCE_STREAM, SR_RUN_RESUME, SR_RUN_FIXED_INNER, SR_RUN_HETERO = 0x1, 0x2, 0x4, 0x8, 0x10
 SR_RUN_SKIP_CLEAN = 0x20
 SR_STOP_CONVERGED, SR_STOP_FP32_FLOOR, SR_STOP_MAX_PASSES = 1, 2, 3
@@ -42,7 +43,7 @@ class sr_graph_info(ctypes.Structure):
                 ("symmetric", ctypes.c_int32), ("num_parts", ctypes.c_int32),
                 ("num_slots", ctypes.c_int32), ("graph_bytes", ctypes.c_uint64),
                 ("page_bytes_total", ctypes.c_uint64), ("max_page_bytes", ctypes.c_uint64),
-                ("resident", ctypes.c_int32)]
+                ("resident", ctypes.c_int32), ("reordered", ctypes.c_int32)]
 
 
 class sr_page_view(ctypes.Structure):
@@ -103,6 +104,7 @@ _SIGNATURES = {
     "sr_graph_partition": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "sr_graph_info_get": (ctypes.c_int, [_P, ctypes.POINTER(sr_graph_info)]),
     "sr_graph_page": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(sr_page_view)]),
+    "sr_graph_order": (ctypes.c_int, [_P, _P, _P]),
     "sr_graph_destroy": (None, [_P]),
     "sr_pvu_default_diagram": (ctypes.c_int, [ctypes.POINTER(sr_pvu_diagram)]),
     "sr_run": (ctypes.c_int, [_P, ctypes.POINTER(sr_run_params), ctypes.POINTER(sr_run_stats)]),
@@ -221,14 +223,15 @@ class Context:
         _check(lib().sr_ctx_memory(self.h, ctypes.byref(u), ctypes.byref(b)), self.h)
         return u.value, b.value
 
-    def load(self, g, symmetrize: bool = False, weights: Optional[bool] = None, symmetric: bool = False) -> "Graph":
-        return Graph(self, g, symmetrize=symmetrize, weights=weights, symmetric=symmetric)
+    def load(self, g, symmetrize: bool = False, weights: Optional[bool] = None, symmetric: bool = False,
+             reorder: bool = False) -> "Graph":
+        return Graph(self, g, symmetrize=symmetrize, weights=weights, symmetric=symmetric, reorder=reorder)
 
 
 class Graph:
     """A graph loaded into a context (C handle sr_graph)."""
 
-    def __init__(self, ctx: Context, g, symmetrize=False, weights=None, symmetric=False):
+    def __init__(self, ctx: Context, g, symmetrize=False, weights=None, symmetric=False, reorder=False):
         self.ctx = ctx
         off = np.ascontiguousarray(g.offsets, dtype=np.int64)
         col = np.ascontiguousarray(g.col, dtype=np.int32)
@@ -240,7 +243,8 @@ class Graph:
         h = _P()
         rc = lib().sr_graph_load_csr(ctx.h, int(g.n), int(off[-1]), off.ctypes.data, col.ctypes.data,
                                      None if w is None else w.ctypes.data,
-                                     (SR_LOAD_SYMMETRIZE if symmetrize else 0) | (SR_LOAD_SYMMETRIC if symmetric else 0),
+                                     (SR_LOAD_SYMMETRIZE if symmetrize else 0) | (SR_LOAD_SYMMETRIC if symmetric else 0)
+                                     | (SR_LOAD_REORDER if reorder else 0),
                                      ctypes.byref(h))
         _check(rc, ctx.h)
         self.h = h
@@ -258,6 +262,13 @@ class Graph:
         i = sr_graph_info()
         _check(lib().sr_graph_info_get(self.h, ctypes.byref(i)), self.ctx.h)
         return {k: getattr(i, k) for k, _ in i._fields_}
+
+    def order(self):
+        """(internal_of, caller_of) vertex maps of a graph loaded with reorder=True."""
+        a = np.empty(self.n, dtype=np.int32)
+        b = np.empty(self.n, dtype=np.int32)
+        _check(lib().sr_graph_order(self.h, a.ctypes.data, b.ctypes.data), self.ctx.h)
+        return a, b
 
     def page(self, p: int) -> dict:
         v = sr_page_view()

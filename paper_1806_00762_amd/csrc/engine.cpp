@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
 
 #include "engine.hpp"
 
@@ -166,7 +167,8 @@ extern "C" sr_status sr_graph_load_csr(sr_ctx *c, int32_t n, int64_t m, const in
   if (!c) return SR_EINVAL;
   if (!out || !ro || (m > 0 && !ci)) return c->fail(SR_EINVAL, "null argument");
   if (n < 1 || m < 0) return c->fail(SR_EINVAL, "need n >= 1 and m >= 0");
-  if (flags & ~(SR_LOAD_SYMMETRIZE | SR_LOAD_SYMMETRIC)) return c->fail(SR_EINVAL, "unknown load flags");
+  if (flags & ~(SR_LOAD_SYMMETRIZE | SR_LOAD_SYMMETRIC | SR_LOAD_REORDER))
+    return c->fail(SR_EINVAL, "unknown load flags");
   if ((flags & SR_LOAD_SYMMETRIZE) && (flags & SR_LOAD_SYMMETRIC))
     return c->fail(SR_EINVAL, "SR_LOAD_SYMMETRIZE and SR_LOAD_SYMMETRIC are exclusive");
   if (ro[0] != 0 || ro[n] != m) return c->fail(SR_EINVAL, "row_offsets must start at 0 and end at m");
@@ -181,8 +183,20 @@ extern "C" sr_status sr_graph_load_csr(sr_ctx *c, int32_t n, int64_t m, const in
   g->n = n;
   g->weighted = w != nullptr;
   g->symmetric = (flags & (SR_LOAD_SYMMETRIZE | SR_LOAD_SYMMETRIC)) != 0;
-  sr_status st;
+  sr_status st = SR_OK;
+  // relabeled copy of the input (SR_LOAD_REORDER); everything below works
+  // on internal ids
+  std::vector<int64_t> ro2;
+  std::vector<int32_t> ci2;
+  std::vector<uint32_t> w2;
   try {
+    if (flags & SR_LOAD_REORDER) {
+      sr::relabel_by_degree(n, ro, ci, w, (flags & SR_LOAD_SYMMETRIZE) != 0, g->rank, g->perm, ro2, ci2, w2);
+      g->reordered = true;
+      ro = ro2.data();
+      ci = ci2.data();
+      if (w) w = w2.data();
+    }
     st = build_in_csr(g, ro, ci, w, (flags & SR_LOAD_SYMMETRIZE) != 0);
   } catch (const std::bad_alloc &) {
     st = c->fail(SR_ENOMEM, "out of host memory building in-edges");
@@ -259,6 +273,15 @@ extern "C" sr_status sr_graph_info_get(const sr_graph *g, sr_graph_info *o) {
     o->max_page_bytes = std::max(o->max_page_bytes, p.bytes);
   }
   o->resident = g->res.resident;
+  o->reordered = g->reordered ? 1 : 0;
+  return SR_OK;
+}
+
+extern "C" sr_status sr_graph_order(const sr_graph *g, int32_t *internal_of, int32_t *caller_of) {
+  if (!g) return SR_EINVAL;
+  if (!g->reordered) return g->ctx->fail(SR_ESTATE, "graph was loaded without SR_LOAD_REORDER");
+  if (internal_of) std::memcpy(internal_of, g->rank.data(), 4ull * g->n);
+  if (caller_of) std::memcpy(caller_of, g->perm.data(), 4ull * g->n);
   return SR_OK;
 }
 
@@ -625,6 +648,8 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     return c->fail(SR_EINVAL, "source out of range");
   if (R.algo == A_CC && !g->symmetric)
     return c->fail(SR_EINVAL, "CC needs the undirected graph: load with SR_LOAD_SYMMETRIZE");
+  // the caller's source id to the internal one
+  if (g->reordered && (R.algo == A_BFS || R.algo == A_SSSP || R.algo == A_PPR)) p.source = g->rank[p.source];
   if (R.algo == A_SSSP && !g->weighted) return c->fail(SR_EINVAL, "SSSP needs weights");
   sr_pvu_diagram d;
   if (p.diagram) d = *p.diagram; else sr_pvu_default_diagram(&d);
@@ -736,6 +761,9 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     if (pr) e = launch_init_pr((float *)rs.value, rs.contrib, rs.inv_outdeg, g->n,
                                R.algo == A_PPR ? p.source : -1, c->compute);
     else e = launch_init_min(R.algo, rs.value, g->n, p.source, c->compute);
+    // CC labels are the caller's ids, so the smallest one of a component wins
+    if (e == hipSuccess && R.algo == A_CC && g->reordered)
+      e = hipMemcpyAsync(rs.value, g->perm.data(), 4ull * g->n, hipMemcpyHostToDevice, c->compute);
     if (e == hipSuccess) e = launch_fill_u8(rs.status, (uint8_t)d.initial_state, (size_t)g->n, c->compute);
   }
   if (resume) {
@@ -1019,7 +1047,24 @@ extern "C" sr_status sr_read_values(const sr_graph *g, void *dst, uint64_t bytes
   if (!g->state.valid) return c->fail(SR_ESTATE, "no run has produced values");
   if (bytes < 4ull * g->n) return c->fail(SR_EINVAL, "dst_bytes < 4n");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
-  HIP_TRY(c, hipMemcpyAsync(dst, g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute), "read values");
+  if (!g->reordered) {
+    HIP_TRY(c, hipMemcpyAsync(dst, g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute), "read values");
+    HIP_TRY(c, hipStreamSynchronize(c->compute), "read values");
+    return SR_OK;
+  }
+  // internal order to the caller's: dst[v] = value[rank[v]]
+  std::vector<uint32_t> tmp((size_t)g->n);
+  HIP_TRY(c, hipMemcpyAsync(tmp.data(), g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute), "read values");
   HIP_TRY(c, hipStreamSynchronize(c->compute), "read values");
+  uint32_t *out = (uint32_t *)dst;
+  const int32_t *rk = g->rank.data();
+  const int T = sr::host_threads();
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t)
+    th.emplace_back([&, t] {
+      const int64_t lo = (int64_t)g->n * t / T, hi = (int64_t)g->n * (t + 1) / T;
+      for (int64_t v = lo; v < hi; ++v) out[v] = tmp[(size_t)rk[v]];
+    });
+  for (auto &x : th) x.join();
   return SR_OK;
 }

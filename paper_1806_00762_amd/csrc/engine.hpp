@@ -90,6 +90,10 @@ struct sr_graph {
   int64_t m = 0;
   bool weighted = false, symmetric = false;
   bool packed = false;  // weights < 256 and n <= 2^24: pages store source | weight << 24
+  // SR_LOAD_REORDER: internal ids by descending degree; rank maps the
+  // caller's ids to internal ones, perm the other way (both empty otherwise)
+  bool reordered = false;
+  std::vector<int32_t> rank, perm;
   std::vector<int64_t> in_off;
   std::vector<int32_t> in_src;
   std::vector<uint32_t> in_w;
@@ -116,6 +120,9 @@ namespace sr {
 // graph_host.cpp
 sr_status build_in_csr(sr_graph *g, const int64_t *row_offsets, const int32_t *col_idx,
                        const uint32_t *weights, bool symmetrize);
+void relabel_by_degree(int32_t n, const int64_t *ro, const int32_t *ci, const uint32_t *wi, bool symmetrize,
+                       std::vector<int32_t> &rank, std::vector<int32_t> &perm, std::vector<int64_t> &ro2,
+                       std::vector<int32_t> &ci2, std::vector<uint32_t> &w2);
 sr_status make_pages(sr_graph *g, int32_t nparts);
 // Smallest page count whose largest streamed page (with its chunk scratch)
 // fits slot_bytes; -1 if none does.

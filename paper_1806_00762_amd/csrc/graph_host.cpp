@@ -44,6 +44,53 @@ uint64_t graph_bytes(const sr_graph *g) {
 // Counting sort by destination with per-thread cursors over contiguous
 // source ranges, so every in-row lists its sources in increasing order and
 // the result does not depend on the thread count.
+// Vertex order for SR_LOAD_REORDER: new ids by descending in-degree (plus
+// out-degree when the graph is symmetrized), ties by old id; a counting
+// sort over the degrees. Fills rank (old -> new) and perm (new -> old) and
+// the out-CSR of the relabeled graph, each row's heads sorted (weights
+// follow their arcs).
+void relabel_by_degree(int32_t n, const int64_t *ro, const int32_t *ci, const uint32_t *wi, bool symmetrize,
+                       std::vector<int32_t> &rank, std::vector<int32_t> &perm, std::vector<int64_t> &ro2,
+                       std::vector<int32_t> &ci2, std::vector<uint32_t> &w2) {
+  const int64_t m = ro[n];
+  std::vector<int64_t> deg((size_t)n, 0);
+  for (int64_t e = 0; e < m; ++e) deg[ci[e]]++;
+  if (symmetrize)
+    for (int32_t u = 0; u < n; ++u) deg[u] += ro[u + 1] - ro[u];
+  int64_t maxd = 0;
+  for (int32_t v = 0; v < n; ++v) maxd = std::max(maxd, deg[v]);
+  std::vector<int64_t> start((size_t)maxd + 2, 0);  // bucket d holds vertices of degree d
+  for (int32_t v = 0; v < n; ++v) start[(size_t)(maxd - deg[v]) + 1]++;
+  for (int64_t d = 0; d <= maxd; ++d) start[(size_t)d + 1] += start[(size_t)d];
+  perm.assign((size_t)n, 0);
+  rank.assign((size_t)n, 0);
+  for (int32_t v = 0; v < n; ++v) {
+    const int64_t p = start[(size_t)(maxd - deg[v])]++;
+    perm[(size_t)p] = v;
+    rank[(size_t)v] = (int32_t)p;
+  }
+  ro2.assign((size_t)n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) ro2[(size_t)i + 1] = ro2[(size_t)i] + (ro[perm[i] + 1] - ro[perm[i]]);
+  ci2.assign((size_t)m, 0);
+  if (wi) w2.assign((size_t)m, 0);
+  const int T = host_threads();
+  parallel_for(n, T, [&](int, int64_t lo, int64_t hi) {
+    std::vector<std::pair<int32_t, uint32_t>> row;
+    for (int64_t i = lo; i < hi; ++i) {
+      const int32_t u = perm[i];
+      row.clear();
+      for (int64_t e = ro[u]; e < ro[u + 1]; ++e) row.push_back({rank[ci[e]], wi ? wi[e] : 0u});
+      std::sort(row.begin(), row.end());
+      int64_t k = ro2[i];
+      for (auto &x : row) {
+        ci2[k] = x.first;
+        if (wi) w2[k] = x.second;
+        ++k;
+      }
+    }
+  }, 1);
+}
+
 sr_status build_in_csr(sr_graph *g, const int64_t *ro, const int32_t *ci, const uint32_t *wi,
                        bool symmetrize) {
   const int32_t n = g->n;

@@ -327,6 +327,7 @@ extern "C" sr_status sr_batch_run(sr_ctx *c, const sr_instance *inst, int32_t co
   for (int32_t i = 0; i < count; ++i) {
     const sr_instance &x = inst[i];
     if (!x.g || x.g->ctx != c) return c->fail(SR_EINVAL, "instance graph missing or from another context");
+    if (x.g->reordered) return c->fail(SR_EINVAL, "batched runs take graphs loaded without SR_LOAD_REORDER");
     if (ppr != (x.algo == SR_PPR)) return c->fail(SR_EINVAL, "mix PPR with SSSP/BFS in separate calls");
     if (x.algo != SR_PPR && x.algo != SR_SSSP && x.algo != SR_BFS)
       return c->fail(SR_EINVAL, "batched algorithms are PPR, SSSP and BFS");

@@ -185,6 +185,8 @@ extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_
   if (he != hipSuccess) return c->hip_fail(he, "set device");
   for (int i = 0; i < ngraphs; ++i)
     if (!graphs[i] || graphs[i]->ctx != c) return c->fail(SR_EINVAL, "graph missing or from another context");
+  for (int i = 0; i < ngraphs; ++i)
+    if (graphs[i]->reordered) return c->fail(SR_EINVAL, "served graphs must be loaded without SR_LOAD_REORDER");
   sr_server *s = new sr_server();
   s->c = c;
   s->K = max_slots;

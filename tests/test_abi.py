@@ -172,3 +172,57 @@ def test_packing_needs_24_bit_ids(sr):
     assert sorted(pg["weights"].tolist()) == [7, 9, 11]
     G.close()
     c.close()
+
+
+@pytest.mark.parametrize("symmetrize", [False, True])
+def test_reorder_relabels_by_degree(sr, symmetrize):
+    """SR_LOAD_REORDER: internal ids by descending in-degree (total degree
+    when symmetrized), ties by the caller's id; the pages are the in-edge CSR
+    of the relabeled graph."""
+    src = graphgen.rmat(10, 8, seed=21, weights=(1, 255, 22))
+    c = sr.Context(-1, 1 << 30)
+    G = c.load(src, symmetrize=symmetrize, reorder=True)
+    internal_of, caller_of = G.order()
+    n = src.n
+    assert np.array_equal(np.sort(internal_of), np.arange(n))
+    assert np.array_equal(caller_of[internal_of], np.arange(n))
+    A = sp.csr_matrix((src.weights.astype(np.int64), src.col, src.offsets), shape=(n, n))
+    deg = np.asarray((A != 0).sum(axis=0)).ravel()          # in-degree
+    if symmetrize:
+        deg = deg + np.diff(src.offsets)
+    key = np.lexsort((np.arange(n), -deg))                  # descending degree, then id
+    assert np.array_equal(caller_of, key)
+    # expected in-CSR of the relabeled graph
+    P = sp.csr_matrix((np.ones(n), (internal_of, np.arange(n))), shape=(n, n))
+    B = (P @ A @ P.T).tocsr()
+    G.partition(3, 4)
+    offs, srcs, vb = [0], [], 0
+    for p in range(G.info()["num_parts"]):
+        pg = G.page(p)
+        assert pg["v_begin"] == vb
+        vb = pg["v_end"]
+        offs.extend((pg["offsets"][1:] + offs[-1]).tolist())
+        srcs.append(pg["src"])
+    if not symmetrize:
+        IN = B.T.tocsr()
+        IN.sort_indices()
+        assert np.array_equal(np.array(offs), IN.indptr)
+        assert np.array_equal(np.concatenate(srcs), IN.indices)
+    else:
+        # undirected: row v lists the internal ids adjacent to v
+        U = sp.csr_matrix((np.ones(src.m), (internal_of[np.repeat(np.arange(n), np.diff(src.offsets))],
+                                            internal_of[src.col])), shape=(n, n))
+        U = ((U + U.T) > 0).astype(np.int8).tocsr()
+        U.setdiag(0)
+        U.eliminate_zeros()
+        U.sort_indices()
+        assert np.array_equal(np.array(offs), U.indptr)
+        assert np.array_equal(np.concatenate(srcs), U.indices)
+    assert G.info()["reordered"] == 1
+    G.close()
+    H = c.load(src)
+    with pytest.raises(sr.SeraphError) as e:
+        H.order()
+    assert e.value.status == sr.SR_ESTATE
+    H.close()
+    c.close()
