@@ -66,8 +66,7 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
                                     degree when symmetrized), ties by id: hubs share the first pages
                                     and cache lines. Sources, results and CC labels stay in the
                                     caller's ids (CC labels: smallest caller id of the component);
-                                    page views show internal ids (sr_graph_order maps them).
-                                    sr_run only: batched and serving calls refuse such a graph. */
+                                    page views show internal ids (sr_graph_order maps them). */
 
 /* sr_run_params.flags */
 #define SR_RUN_AUDIT_PVU 0x1u     /* also evaluate skipped vertices; count would-be changes

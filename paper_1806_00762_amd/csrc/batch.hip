@@ -529,10 +529,10 @@ __global__ void mi_set_ctl_kernel(MiCtl *dst, MiCtl val) {
 
 template <int K>
 __global__ void mi_extract_kernel(uint32_t *value, int32_t n, int32_t col, uint32_t *out, int32_t reset,
-                                  uint32_t reset_to) {
+                                  uint32_t reset_to, const int32_t *rank) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const size_t i = (size_t)v * K + col;
+  const size_t i = (size_t)(rank ? rank[v] : v) * K + col;
   out[v] = value[i];
   if (reset) value[i] = reset_to;
 }
@@ -574,12 +574,12 @@ hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contri
 }
 
 hipError_t launch_mi_extract(int K, uint32_t *value, int32_t n, int32_t col, uint32_t *out, hipStream_t s,
-                             bool reset, uint32_t reset_to) {
+                             bool reset, uint32_t reset_to, const int32_t *rank) {
   dim3 grid((n + 255) / 256), block(256);
   const int32_t r = reset ? 1 : 0;
-  if (K == 8) hipLaunchKernelGGL(mi_extract_kernel<8>, grid, block, 0, s, value, n, col, out, r, reset_to);
-  else if (K == 16) hipLaunchKernelGGL(mi_extract_kernel<16>, grid, block, 0, s, value, n, col, out, r, reset_to);
-  else if (K == 32) hipLaunchKernelGGL(mi_extract_kernel<32>, grid, block, 0, s, value, n, col, out, r, reset_to);
+  if (K == 8) hipLaunchKernelGGL(mi_extract_kernel<8>, grid, block, 0, s, value, n, col, out, r, reset_to, rank);
+  else if (K == 16) hipLaunchKernelGGL(mi_extract_kernel<16>, grid, block, 0, s, value, n, col, out, r, reset_to, rank);
+  else if (K == 32) hipLaunchKernelGGL(mi_extract_kernel<32>, grid, block, 0, s, value, n, col, out, r, reset_to, rank);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -91,9 +91,10 @@ hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contri
                                  int32_t n, int32_t col, int32_t source, hipStream_t s);
 hipError_t launch_mi_set_inst(MiInst *dst, const MiInst &val, hipStream_t s);
 hipError_t launch_mi_set_ctl(MiCtl *dst, const MiCtl &val, hipStream_t s);
-// Copy column col of value[n][K] to out; with reset, leave `reset_to` in
-// the column (so the next query on it only has to set its source).
+// Copy column col of value[n][K] to out (out[v] = value[rank[v]][col] when
+// rank is given: internal ids of a reordered graph); with reset, leave
+// `reset_to` in the column (so the next query on it only sets its source).
 hipError_t launch_mi_extract(int K, uint32_t *value, int32_t n, int32_t col, uint32_t *out, hipStream_t s,
-                             bool reset = false, uint32_t reset_to = 0u);
+                             bool reset = false, uint32_t reset_to = 0u, const int32_t *rank = nullptr);
 
 }  // namespace sr

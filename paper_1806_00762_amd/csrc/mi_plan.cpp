@@ -94,6 +94,20 @@ sr_status MiPlan::add_group(sr_graph *g, int pvu, int *out_index) {
   std::memset(z.data(), 0, sizeof(MiInst) * K);
   hipError_t e = hipMemcpy(gr.inst, z.data(), sizeof(MiInst) * K, hipMemcpyHostToDevice);
   if (e != hipSuccess) return c->hip_fail(e, "instance control init");
+  const int32_t *rk = nullptr;
+  if (g->reordered) {
+    for (auto &kv : rank)
+      if (kv.first == g) rk = kv.second;
+    if (!rk) {
+      int32_t *d = nullptr;
+      if ((s = alloc((void **)&d, 4ull * g->n, "vertex order")) != SR_OK) return s;
+      hipError_t e2 = hipMemcpy(d, g->rank.data(), 4ull * g->n, hipMemcpyHostToDevice);
+      if (e2 != hipSuccess) return c->hip_fail(e2, "copy vertex order");
+      rank.push_back({g, d});
+      rk = d;
+    }
+  }
+  group_rank.push_back(rk);
   groups.push_back(gr);
   group_graph.push_back(g);
   *out_index = (int)groups.size() - 1;
@@ -196,6 +210,7 @@ sr_status MiPlan::clear_values(hipStream_t s) {
 sr_status MiPlan::set_column(int gi, int col, int32_t source, bool unit, bool active, hipStream_t s, bool clean) {
   MiGroup &gr = groups[gi];
   sr_graph *g = group_graph[gi];
+  if (source >= 0 && g->reordered) source = g->rank[source];
   MiInst in;
   std::memset(&in, 0, sizeof(in));
   in.active = active ? 1u : 0u;
@@ -327,7 +342,6 @@ extern "C" sr_status sr_batch_run(sr_ctx *c, const sr_instance *inst, int32_t co
   for (int32_t i = 0; i < count; ++i) {
     const sr_instance &x = inst[i];
     if (!x.g || x.g->ctx != c) return c->fail(SR_EINVAL, "instance graph missing or from another context");
-    if (x.g->reordered) return c->fail(SR_EINVAL, "batched runs take graphs loaded without SR_LOAD_REORDER");
     if (ppr != (x.algo == SR_PPR)) return c->fail(SR_EINVAL, "mix PPR with SSSP/BFS in separate calls");
     if (x.algo != SR_PPR && x.algo != SR_SSSP && x.algo != SR_BFS)
       return c->fail(SR_EINVAL, "batched algorithms are PPR, SSSP and BFS");
@@ -440,7 +454,7 @@ extern "C" sr_status sr_batch_run(sr_ctx *c, const sr_instance *inst, int32_t co
   std::vector<int32_t> group_sweeps(plan.groups.size(), 0);
   for (int32_t i = 0; i < count; ++i) {
     const MiGroup &gr = plan.groups[where[i].group];
-    he = launch_mi_extract(K, gr.value, gr.n, where[i].col, tmp, st);
+    he = launch_mi_extract(K, gr.value, gr.n, where[i].col, tmp, st, false, 0u, plan.group_rank[where[i].group]);
     if (he == hipSuccess) he = hipMemcpyAsync(dsts[i], tmp, 4ull * gr.n, hipMemcpyDeviceToHost, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
     if (he != hipSuccess) return c->hip_fail(he, "batch results");

@@ -29,6 +29,8 @@ struct MiPlan {
   uint32_t *d_remaining = nullptr;
   std::vector<void *> dev;           // device allocations owned by the plan
   std::vector<std::pair<sr_graph *, float *>> iod;  // 1/outdeg per graph (PPR)
+  std::vector<std::pair<sr_graph *, int32_t *>> rank;  // caller -> internal ids (reordered graphs)
+  std::vector<const int32_t *> group_rank;            // per group: device rank map or null
   MiArgs args{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -42,7 +44,8 @@ struct MiPlan {
   sr_status add_group(sr_graph *g, int pvu, int *out_index);
   // build units/prefix for all groups and upload the tables
   sr_status finalize(double damping, double tol_l1, int32_t max_sweeps);
-  // (re)initialise column `col` of group `gi` and its control record
+  // (re)initialise column `col` of group `gi` and its control record; the
+  // source is the caller's id (mapped for reordered graphs)
   // clean: the column already holds the initial value everywhere (SSSP/BFS
   // INF), so only the source entry is written
   sr_status set_column(int gi, int col, int32_t source, bool unit, bool active, hipStream_t s, bool clean = false);

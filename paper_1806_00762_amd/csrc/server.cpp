@@ -149,7 +149,8 @@ void sr_server::progress() {
         std::lock_guard<std::mutex> lk(mu);
         dst = q[f.first].result;
       }
-      e = launch_mi_extract(K, plan->groups[gi].value, plan->groups[gi].n, k, dst, stream, true, INF);
+      e = launch_mi_extract(K, plan->groups[gi].value, plan->groups[gi].n, k, dst, stream, true, INF,
+                            plan->group_rank[gi]);
       if (e != hipSuccess) break;
     }
     if (!finished.empty() && e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -185,8 +186,6 @@ extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_
   if (he != hipSuccess) return c->hip_fail(he, "set device");
   for (int i = 0; i < ngraphs; ++i)
     if (!graphs[i] || graphs[i]->ctx != c) return c->fail(SR_EINVAL, "graph missing or from another context");
-  for (int i = 0; i < ngraphs; ++i)
-    if (graphs[i]->reordered) return c->fail(SR_EINVAL, "served graphs must be loaded without SR_LOAD_REORDER");
   sr_server *s = new sr_server();
   s->c = c;
   s->K = max_slots;

@@ -82,15 +82,37 @@ def test_reorder_pagerank(sr, ctx, sched):
         G.close()
 
 
-def test_reorder_refused_by_batch_and_server(sr, ctx):
+def test_reorder_batch_and_server(sr, ctx):
+    """Batched and served queries take sources and return values in the
+    caller's ids on a reordered graph."""
+    import time
     g = GRAPHS["rmat14w"]()
     G = ctx.load(g, reorder=True)
     try:
-        with pytest.raises(sr.SeraphError) as e:
-            sr.batch_run(ctx, [(G, "sssp", 0)])
-        assert e.value.status == sr.SR_EINVAL
-        with pytest.raises(sr.SeraphError) as e:
-            sr.Server(ctx, [G], slots=8)
-        assert e.value.status == sr.SR_EINVAL
+        srcs = [int(s) for s in graphgen.sources_with_outedges(g, 10, seed=31)]
+        outs, _, _ = sr.batch_run(ctx, [(G, "sssp" if i % 2 else "bfs", s) for i, s in enumerate(srcs)])
+        for i, (s, x) in enumerate(zip(srcs, outs)):
+            ref = oracle.sssp(g, s) if i % 2 else oracle.bfs(g, s)
+            assert np.array_equal(x, ref), (i, s)
+        outs, _, _ = sr.batch_run(ctx, [(G, "ppr", s) for s in srcs[:4]])
+        for s, x in zip(srcs[:4], outs):
+            ref, _, _ = oracle.pagerank(g, seed=s, tol=1e-13)
+            assert np.max(np.abs(x.view(np.float32).astype(np.float64) - ref)) <= 1e-6
+        srv = sr.Server(ctx, [G], slots=32)
+        tickets = [srv.submit(0, "sssp", s) for s in srcs]
+        res = {}
+        t0 = time.time()
+        while len(res) < len(tickets) and time.time() - t0 < 60:
+            for t, s in zip(tickets, srcs):
+                if t in res:
+                    continue
+                buf = np.empty(g.n, dtype=np.uint32)
+                done, _ = srv.poll(t, buf)
+                if done:
+                    res[t] = buf
+            time.sleep(0.001)
+        srv.close()
+        for t, s in zip(tickets, srcs):
+            assert np.array_equal(res[t], oracle.sssp(g, s)), s
     finally:
         G.close()
