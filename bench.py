@@ -315,7 +315,7 @@ def bench_batched(args):
     graphs = [graphgen.recipes.batched_graph(i) for i in range(32)]
     log(f"[bench] batched: generated 32 graphs, m total {sum(g.m for g in graphs)} in {time.perf_counter() - t:.1f}s")
     ctx = sr.Context(0, 0)
-    Gs = [ctx.load(g) for g in graphs]
+    Gs = [ctx.load(g, reorder=args.order == "degree") for g in graphs]
     for G in Gs:
         G.partition(1, 4)
     insts = []
@@ -354,7 +354,7 @@ def bench_batched(args):
     for G in Gs:
         G.close()
     ctx.close()
-    return {"workload": "ppr256_over_32_rmat_s12-20_ef8-32", "instances": len(insts),
+    return {"workload": "ppr256_over_32_rmat_s12-20_ef8-32", "instances": len(insts), "vertex_order": args.order,
             "solves_per_s": round(len(insts) / tb, 1), "batched_ms": round(tb * 1e3, 2),
             "plain_solves_per_s": round(1.0 / tp, 1), "plain_sample": nplain,
             "speedup_vs_plain": round(tp * len(insts) / tb, 2),
@@ -422,7 +422,7 @@ def bench_served(args):
     graphs = [graphgen.recipes.serving_graph(s) for s in (20, 22, 23)]
     log(f"[bench] served: generated graphs in {time.perf_counter() - t:.1f}s")
     ctx = sr.Context(0, 0)
-    Gs = [ctx.load(g) for g in graphs]
+    Gs = [ctx.load(g, reorder=args.order == "degree") for g in graphs]
     for G in Gs:
         G.partition(1, 4)
     nreq = args.requests
@@ -459,7 +459,7 @@ def bench_served(args):
     for G in Gs:
         G.close()
     ctx.close()
-    return {"workload": "poisson2000_sssp_bfs_rmat20_22_23_ef16", "requests": nreq,
+    return {"workload": "poisson2000_sssp_bfs_rmat20_22_23_ef16", "requests": nreq, "vertex_order": args.order,
             "completed": int(done_lat.size), "offered_qps": args.rate,
             "achieved_qps": round(achieved, 1),
             "p50_ms": round(float(np.percentile(done_lat, 50)), 2) if done_lat.size else None,
