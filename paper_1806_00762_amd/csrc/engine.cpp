@@ -308,6 +308,7 @@ extern "C" void sr_graph_destroy(sr_graph *g) {
     (void)hipDeviceSynchronize();
     release_residency(g);
     release_state(g);
+    if (g->host_val) (void)hipHostFree(g->host_val);
   }
   sr::free_pages(g);
   delete g;
@@ -822,14 +823,17 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     *fin = false;
     if (!hetero || !R.collect || !have_fr || R.last_pass_changed > sparse_thr) return SR_OK;
     const double t1 = now_ms();
-    std::vector<uint32_t> val((size_t)g->n);
-    HIP_TRY(c, hipMemcpyAsync(val.data(), g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute),
+    if (!g->host_val && g->n > 0) {
+      HIP_TRY(c, hipHostMalloc((void **)&g->host_val, 4ull * g->n, hipHostMallocDefault), "pinned value mirror");
+    }
+    uint32_t *val = g->host_val;
+    HIP_TRY(c, hipMemcpyAsync(val, g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute),
             "values to host");
     HIP_TRY(c, hipStreamSynchronize(c->compute), "values to host");
     sr::build_out_csr(g);
     int32_t rounds = 0;
-    const int64_t relaxed = sr::sparse_push(g, R.algo, val.data(), fr.data(), (int64_t)fr.size(), &rounds);
-    HIP_TRY(c, hipMemcpyAsync(g->state.value, val.data(), 4ull * g->n, hipMemcpyHostToDevice, c->compute),
+    const int64_t relaxed = sr::sparse_push(g, R.algo, val, fr.data(), (int64_t)fr.size(), &rounds);
+    HIP_TRY(c, hipMemcpyAsync(g->state.value, val, 4ull * g->n, hipMemcpyHostToDevice, c->compute),
             "values to device");
     HIP_TRY(c, hipStreamSynchronize(c->compute), "values to device");
     R.st.sparse_stage = 1;

@@ -114,6 +114,11 @@ struct sr_graph {
   // SR_RUN_SKIP_CLEAN; built for the partition with out_mask_parts pages
   std::vector<uint64_t> out_mask;
   int32_t out_mask_parts = 0;
+  // host sparse stage: pinned mirror of the value array (n words, so both
+  // transfers run at the pinned copy rate) and the per-vertex queue flags,
+  // which are all zero between calls
+  uint32_t *host_val = nullptr;
+  std::vector<uint8_t> push_inq;
 };
 
 namespace sr {
@@ -135,7 +140,7 @@ void build_out_csr(sr_graph *g);
 void build_out_masks(sr_graph *g);
 // OR of the out-page masks of the frontier's vertices
 uint64_t frontier_pages(const sr_graph *g, const uint32_t *front, int64_t nf);
-int64_t sparse_push(const sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
+int64_t sparse_push(sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
                     int32_t *rounds);
 // engine.cpp
 sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream, bool bins = false);

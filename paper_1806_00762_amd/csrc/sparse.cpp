@@ -47,10 +47,13 @@ static inline uint32_t relax_value(int algo, uint32_t xu, uint32_t w) {
 // correction, each round's list split over host threads, atomic minimum on
 // the values and an in-list flag per vertex. Monotone min relaxations reach
 // the same least fixed point in any order, so the result is exact.
-int64_t sparse_push(const sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
+int64_t sparse_push(sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
                     int32_t *rounds_out) {
   const int32_t n = g->n;
-  std::vector<uint8_t> inq((size_t)n, 0);
+  // flags are set when a vertex enters the next round and cleared when that
+  // round starts, so the array is all zero again on return
+  std::vector<uint8_t> &inq = g->push_inq;
+  if ((int64_t)inq.size() != (int64_t)n) inq.assign((size_t)n, 0);
   std::vector<int32_t> cur;
   cur.reserve((size_t)nf);
   for (int64_t i = 0; i < nf; ++i) {
