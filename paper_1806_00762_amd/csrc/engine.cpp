@@ -950,10 +950,17 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     const bool fixed_inner = (p.flags & SR_RUN_FIXED_INNER) != 0;
     std::vector<int32_t> ord(P);
     for (int32_t i = 0; i < P; ++i) ord[i] = i;
+    // A pass of a min program that has changed nothing by its last steps is
+    // most likely the final one (under strong or no prediction, or a weak
+    // run's verification pass, its end finds no change and stops the run),
+    // so the first pages of a next pass are not fetched ahead then; a wrong
+    // guess only delays that pass's first copy.
+    const bool guess_last = !pr;
     while (!done) {
       // pass start: every earlier sweep has finished (host synced at the pass end)
       if ((s = begin_pass()) != SR_OK) return s;
       const int32_t NP = (int32_t)ord.size();  // pages of this pass
+      bool pass_changed = false, pass_verify = false;
       if (NP > 0 && page_slot[ord[0]] < 0) {
         if ((s = copy_page(ord[0], free_slot({}), false)) != SR_OK) return s;
       }
@@ -967,6 +974,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
         for (int32_t q = 1; q <= D; ++q) {
           // skipping decides the next pass's pages at the pass end: no wrap
           if (skip && j + q >= NP) break;
+          if (guess_last && pass > 0 && !pass_changed && (R.pvu != P_WEAK || pass_verify) && j + q >= NP) break;
           const int32_t page = ord[(j + q) % NP];
           if (std::find(keep.begin(), keep.end(), page) != keep.end()) continue;
           if (page_slot[page] < 0) {
@@ -991,7 +999,11 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
           R.harvest(&done);
           if (done) break;
           bool changed = false;
-          for (uint64_t q = before; q < R.seq_next; ++q) changed |= c->ring_host[q & c->ring_mask].changed > 0;
+          for (uint64_t q = before; q < R.seq_next; ++q) {
+            changed |= c->ring_host[q & c->ring_mask].changed > 0;
+            pass_verify = c->ring_host[q & c->ring_mask].phase == 1;
+          }
+          pass_changed |= changed;
           if (fixed_inner) continue;                // fixed re-entry count (ablation schedules)
           if (!changed) break;                      // the window reached its local fixed point
           if (!copying) break;                      // nothing in flight to wait for
