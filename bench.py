@@ -189,6 +189,9 @@ def bench_sssp22(args):
                          "h2d_bytes_per_solve": h["h2d_bytes"],
                          "note": "device dense passes + host push sparse stage; not the headline value"}
         log(f"[bench] hetero: {res['hetero']}")
+    if not args.no_other:
+        res["bfs_early_break"] = bench_bfs_early_break(args, g, G)
+        log(f"[bench] bfs early break: {res['bfs_early_break']}")
     if args.ablation:
         res["ablation"] = ablation(args, G, info["num_parts"], dist)
     if args.resident:
@@ -267,6 +270,41 @@ def ablation(args, G, parts, dist):
         out[name] = row
         log(f"[bench] ablation {name}: {row['ms_per_solve']} ms, {row['passes']} passes, {row['sweeps']} sweeps")
     G.partition(parts, args.slots)
+    return out
+
+
+def bench_bfs_early_break(args, g, G):
+    """BFS from vertex 0 on the same graph with strong prediction, resident
+    (each sweep closes a pass) and streamed like the headline solve, with
+    and without the dense-pull early break; levels checked against the
+    oracle's queue BFS."""
+    import oracle
+    import paper_1806_00762_amd as sr
+    ref = oracle.bfs(g, 0)
+    out = {"workload": "bfs_rmat22_ef16_src0", "parity": "bit-exact"}
+    ctx_r = sr.Context(0, 0)
+    Gr = ctx_r.load(g, reorder=args.order == "degree")
+    Gr.partition(1, 4)
+    legs = (("resident", Gr, dict(source=0, pvu="strong")),
+            ("streamed", G, dict(source=0, pvu="strong", max_inner_iters=args.inner, force_stream=True,
+                                 copy_depth=args.copy_depth)))
+    for name, H, kw in legs:
+        row = {}
+        for tag, eb in (("break", True), ("full", False)):
+            H.run("bfs", early_break=eb, **kw)
+            sync()
+            t0 = time.perf_counter()
+            sts = [H.run("bfs", early_break=eb, **kw) for _ in range(args.steps)]
+            sync()
+            el = (time.perf_counter() - t0) / args.steps
+            assert np.array_equal(H.values(), ref), (name, tag)
+            km = sum(s["kernel_ms"] for s in sts) / args.steps
+            row[tag] = {"ms_per_solve": round(el * 1e3, 3), "solve_gteps": round(g.m / el / 1e9, 3),
+                        "kernel_ms": round(km, 3), "passes": sts[-1]["passes"], "sweeps": sts[-1]["sweeps"],
+                        "edges_read": sts[-1]["edges_scanned"]}
+        out[name] = row
+    Gr.close()
+    ctx_r.close()
     return out
 
 

@@ -86,6 +86,11 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
                                      fixed point); falls back to every page when that pass changed
                                      more vertices than the frontier holds (n / 16 entries, fewer if
                                      the device budget has less room) */
+#define SR_RUN_NO_EARLY_BREAK 0x40u /* BFS with strong prediction reads a vertex's first in-edge
+                                     first and, when that neighbour is on the threshold level k of
+                                     Table I, sets level k + 1 without reading the other in-edges
+                                     (the dense-pull early break of Section 5.5, RQ4); this flag
+                                     turns it off (results are identical either way) */
 
 /* stop reasons reported in sr_run_stats.stop_reason */
 #define SR_STOP_CONVERGED 1   /* min programs: a full pass changed nothing (with weak prediction,

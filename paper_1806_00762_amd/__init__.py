@@ -28,6 +28,7 @@ SR_LOAD_SYMMETRIC = 0x2
 SR_LOAD_REORDER = 0x4
 SR_RUN_AUDIT_PVU, SR_RUN_FORCE_STREAM, SR_RUN_RESUME, SR_RUN_FIXED_INNER, SR_RUN_HETERO = 0x1, 0x2, 0x4, 0x8, 0x10
 SR_RUN_SKIP_CLEAN = 0x20
+SR_RUN_NO_EARLY_BREAK = 0x40
 SR_STOP_CONVERGED, SR_STOP_FP32_FLOOR, SR_STOP_MAX_PASSES = 1, 2, 3
 SR_INF = 0xFFFFFFFF
 
@@ -292,7 +293,8 @@ class Graph:
             max_passes: int = 0, max_inner_iters: int = 0, diagram: Optional[sr_pvu_diagram] = None,
             pr_change_eps: float = 0.0, audit: bool = False, force_stream: bool = False,
             resume: bool = False, fixed_inner: bool = False, copy_depth: int = 0, hetero: bool = False,
-            sparse_switch: int = 0, skip_clean: bool = False, check: bool = True) -> dict:
+            sparse_switch: int = 0, skip_clean: bool = False, early_break: bool = True,
+            check: bool = True) -> dict:
         p = sr_run_params()
         p.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
         p.source = source
@@ -305,7 +307,8 @@ class Graph:
         p.pr_change_eps = pr_change_eps
         p.flags = ((SR_RUN_AUDIT_PVU if audit else 0) | (SR_RUN_FORCE_STREAM if force_stream else 0)
                    | (SR_RUN_RESUME if resume else 0) | (SR_RUN_FIXED_INNER if fixed_inner else 0)
-                   | (SR_RUN_HETERO if hetero else 0) | (SR_RUN_SKIP_CLEAN if skip_clean else 0))
+                   | (SR_RUN_HETERO if hetero else 0) | (SR_RUN_SKIP_CLEAN if skip_clean else 0)
+                   | (0 if early_break else SR_RUN_NO_EARLY_BREAK))
         p.copy_depth = copy_depth
         p.sparse_switch = sparse_switch
         st = sr_run_stats()

@@ -475,6 +475,7 @@ struct Runner {
     a.end_of_pass = end_of_pass;
     a.n = g->n;
     a.audit = (prm.flags & SR_RUN_AUDIT_PVU) ? 1 : 0;
+    a.early = (algo == A_BFS && !(prm.flags & SR_RUN_NO_EARLY_BREAK)) ? 1 : 0;
     a.pr_seed = algo == A_PPR ? prm.source : -1;
     a.damping = (float)prm.damping;
     a.pr_eps = prm.pr_change_eps;
@@ -633,7 +634,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (p.max_inner_iters == 0) p.max_inner_iters = 4;
   if (p.max_passes < 0 || p.max_inner_iters < 0) return c->fail(SR_EINVAL, "negative limits");
   if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_FORCE_STREAM | SR_RUN_RESUME | SR_RUN_FIXED_INNER | SR_RUN_HETERO |
-                  SR_RUN_SKIP_CLEAN))
+                  SR_RUN_SKIP_CLEAN | SR_RUN_NO_EARLY_BREAK))
     return c->fail(SR_EINVAL, "unknown run flags");
   const bool pr = R.algo == A_PR || R.algo == A_PPR;
   // defaults (Section 4.3 discussion): BFS/CC strong, SSSP/PageRank weak;

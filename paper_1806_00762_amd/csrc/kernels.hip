@@ -74,6 +74,7 @@ struct Acc {
 // Per-block view of the run state.
 struct Run {
   int algo, pvu, phase, audit;
+  int early;  // BFS early break (strong prediction, normal phase)
   uint32_t threshold;
   uint32_t *value;
   float *contrib;
@@ -278,6 +279,27 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
     gt[j] = gate_of(r, p.v_begin + lv[j]);
     act[j] = in && (gt[j].attempt || r.audit) && (d[j] > 0 || is_pr<ALGO>());
   }
+  // BFS early break (Section 5.5): after the threshold's k passes every level <= k is
+  // final and every other vertex is at level >= k + 1, so a vertex whose
+  // first in-neighbour (the smallest internal id: the highest-degree one
+  // under degree numbering) is at level k is at level k + 1 and its other
+  // in-edges are not read. Otherwise the probed edge seeds the reduction
+  // and the scan starts after it, so no edge is read twice.
+  uint32_t seed[2] = {INF, INF};
+  if constexpr (ALGO == A_BFS) {
+    if (r.early) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (act[j]) {
+          const uint32_t x = r.value[src_of<PACKED>(p.src[eb[j]])];
+          acc.edges += 1;
+          seed[j] = x == INF ? INF : x + 1u;
+          eb[j] += 1;
+          d[j] = x == r.threshold ? 0 : d[j] - 1;
+        }
+      }
+    }
+  }
   int na = (int)act[0] + (int)act[1];
   int ne = (act[0] ? d[0] : 0) + (act[1] ? d[1] : 0);
   int ina = na, ine = ne;  // inclusive scan within the wavefront
@@ -302,7 +324,8 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
       s.pos[ka] = pe;
       s.eb[ka] = eb[j];
       s.vl[ka] = lv[j];
-      s.acc[ka] = R::bits(R::identity());
+      // the early break's probe (BFS) seeds the reduction
+      s.acc[ka] = ALGO == A_BFS ? seed[j] : R::bits(R::identity());
       s.old[ka] = gt[j].old;
       s.att[ka] = gt[j].attempt ? 1 : 0;
       s.st[ka] = gt[j].st;
@@ -398,7 +421,17 @@ __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
   Gate g = gate_of(r, v);
   bool comp = g.attempt || r.audit;
   T x = R::identity();
-  if (comp) {
+  bool scan = comp;
+  if constexpr (ALGO == A_BFS) {
+    // early break, as in tiles: every chunk of the vertex probes its first in-edge
+    if (comp && r.early) {
+      if (r.value[src_of<PACKED>(p.src[p.off[c.vl]])] == r.threshold) {
+        x = r.threshold + 1u;
+        scan = false;
+      }
+    }
+  }
+  if (scan) {
     // batches of 8 edges per lane: 8 edge-word loads, then 8 gathers, all
     // in flight together (lanes past the chunk reread its first edge)
     constexpr int B = 8;
@@ -556,6 +589,7 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   r.pvu = ctl->pvu;
   r.phase = ctl->phase;
   r.audit = a.audit && r.phase == 0 && r.pvu != P_OFF;
+  r.early = ALGO == A_BFS && a.early && !a.audit && r.phase == 0 && r.pvu == P_STRONG;
   r.threshold = ctl->threshold;
   r.value = a.value;
   r.contrib = a.contrib;

@@ -19,6 +19,7 @@ struct SweepArgs {
   int32_t pr_seed;         // personalized PageRank seed, -1 = uniform teleport
   int32_t nblocks;         // grid size
   int32_t packed;          // edge words carry the weight in their top byte
+  int32_t early;           // BFS under strong prediction: stop at a first in-neighbour on the threshold level
   float damping;
   float pr_eps;
   Ctl *ctl;                // device control block
