@@ -55,7 +55,7 @@ constexpr bool mi_pr() { return ALGO == A_PPR; }
 struct Lane {
   uint32_t active, unit, threshold;
   int32_t source;
-  float dangling;
+  double dangling, inv_mass;
 };
 
 __device__ inline Lane lane_of(const MiInst &in) {
@@ -64,7 +64,8 @@ __device__ inline Lane lane_of(const MiInst &in) {
   ln.unit = in.unit;
   ln.threshold = in.threshold;
   ln.source = in.source;
-  ln.dangling = (float)in.dangling;
+  ln.dangling = in.dangling;
+  ln.inv_mass = in.mass > 0.0 ? 1.0 / in.mass : 1.0;
   return ln;
 }
 
@@ -97,13 +98,13 @@ struct MiRed {
 
 struct MiAcc {
   uint32_t changed = 0, min_changed = INF, edges = 0;
-  double l1 = 0.0, ddelta = 0.0;
+  double l1 = 0.0, ddelta = 0.0, dmass = 0.0;
 };
 
 // Per-instance counters of one block, in LDS (instance i = group * K + k).
 struct MiLds {
   uint32_t changed, min_changed, edges, pad;
-  double l1, ddelta;
+  double l1, ddelta, dmass;
 };
 
 __device__ inline void lds_clear(MiLds *lds, int n, int nthreads) {
@@ -114,6 +115,7 @@ __device__ inline void lds_clear(MiLds *lds, int n, int nthreads) {
     lds[i].pad = 0;
     lds[i].l1 = 0.0;
     lds[i].ddelta = 0.0;
+    lds[i].dmass = 0.0;
   }
 }
 
@@ -125,6 +127,7 @@ __device__ inline void lds_add(MiLds &e, const MiAcc &acc) {
   if constexpr (mi_pr<ALGO>()) {
     if (acc.l1 != 0.0) atomicAdd(&e.l1, acc.l1);
     if (acc.ddelta != 0.0) atomicAdd(&e.ddelta, acc.ddelta);
+    if (acc.dmass != 0.0) atomicAdd(&e.dmass, acc.dmass);
   }
 }
 
@@ -140,18 +143,20 @@ __device__ inline bool mi_attempt(const MiGroup &g, int32_t v, int k, const Lane
 
 template <int ALGO, int K>
 __device__ inline void mi_epilogue(const MiGroup &g, int32_t v, int k, const Lane &ln, uint32_t old,
-                                   typename MiRed<ALGO, K>::T red, uint32_t deg, float damping, MiAcc &acc) {
+                                   typename MiRed<ALGO, K>::T red, uint32_t deg, double damping, MiAcc &acc) {
   acc.edges += deg;
   const size_t i = (size_t)v * K + k;
   if constexpr (mi_pr<ALGO>()) {
-    float t = (v == ln.source) ? 1.0f : 0.0f;
+    // the update of x / mass (see the single-instance epilogue)
+    const double t = (v == ln.source) ? 1.0 : 0.0;
     float oldf = __uint_as_float(old);
-    float nv = (1.0f - damping) * t + damping * (red + ln.dangling * t);
+    float nv = (float)((1.0 - damping) * t + damping * ln.inv_mass * ((double)red + ln.dangling * t));
     g.value[i] = __float_as_uint(nv);
     float iod = g.inv_outdeg[v];
     g.contrib[i] = nv * iod;
     double dd = (double)nv - (double)oldf;
     acc.l1 += fabs(dd);
+    acc.dmass += dd;
     if (iod == 0.0f) acc.ddelta += dd;
     if (nv != oldf) acc.changed++;
   } else {
@@ -177,6 +182,7 @@ __device__ inline void mi_flush(MiLds *lds, int group, MiAcc &acc) {
     if constexpr (mi_pr<ALGO>()) {
       acc.l1 += shfl_xor(acc.l1, m);
       acc.ddelta += shfl_xor(acc.ddelta, m);
+      acc.dmass += shfl_xor(acc.dmass, m);
     }
   }
   if (lane < K) lds_add<ALGO>(lds[group * K + lane], acc);
@@ -194,7 +200,7 @@ __device__ inline uint32_t mi_weight(const MiGroup &g, uint32_t q, const uint32_
 
 template <int ALGO, int K, int GE>
 __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h, int bin, int item,
-                         const Lane &ln, float damping, MiAcc &acc) {
+                         const Lane &ln, double damping, MiAcc &acc) {
   using R = MiRed<ALGO, K>;
   using T = typename R::T;
   constexpr int EL = 64 / K;
@@ -281,7 +287,7 @@ __device__ inline typename MiRed<ALGO, K>::T mi_edges(const MiGroup &g, const ui
 // bin 6: one wavefront per vertex
 template <int ALGO, int K>
 __device__ void mi_wave(const MiGroup &g, const char *base, const PageHeader *h, int item, const Lane &ln,
-                        float damping, MiAcc &acc) {
+                        double damping, MiAcc &acc) {
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, k = lane % K, el = lane / K;
   int idx = item * WAVES + wave;
   if (idx >= h->bin_count[BIN_WAVE]) return;
@@ -332,7 +338,7 @@ __device__ void mi_chunk(const MiGroup &g, const MiUnit &u, const char *base, co
 // bin 8 (PPR only): zero in-degree, the value still follows the teleport term
 template <int ALGO, int K>
 __device__ void mi_zero(const MiGroup &g, const char *base, const PageHeader *h, int item, const Lane &ln,
-                        float damping, MiAcc &acc) {
+                        double damping, MiAcc &acc) {
   const int k = threadIdx.x % K, vs = threadIdx.x / K;
   const int32_t *bins = reinterpret_cast<const int32_t *>(base + h->off_bins) + h->bin_start[BIN_ZERO];
   const int cnt = h->bin_count[BIN_ZERO];
@@ -399,7 +405,9 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
   __syncthreads();
   for (int i = threadIdx.x; i < ninst; i += BLOCK) {
     const MiLds &e = lds[i];
-    if (e.changed == 0 && e.edges == 0 && e.min_changed == INF && e.l1 == 0.0 && e.ddelta == 0.0) continue;
+    if (e.changed == 0 && e.edges == 0 && e.min_changed == INF && e.l1 == 0.0 && e.ddelta == 0.0 &&
+        e.dmass == 0.0)
+      continue;
     MiInst &in = a.groups[i / K].inst[i % K];
     if (e.changed) atomicAdd(&in.sw_changed, e.changed);
     if (e.min_changed != INF) atomicMin(&in.sw_min_changed, e.min_changed);
@@ -407,6 +415,7 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
     if constexpr (mi_pr<ALGO>()) {
       if (e.l1 != 0.0) atomicAdd(&in.sw_l1, e.l1);
       if (e.ddelta != 0.0) atomicAdd(&in.sw_ddelta, e.ddelta);
+      if (e.dmass != 0.0) atomicAdd(&in.sw_dmass, e.dmass);
     }
   }
 }
@@ -450,6 +459,7 @@ __global__ void __launch_bounds__(BLOCK) mi_heavy_kernel(MiArgs a) {
   if constexpr (mi_pr<ALGO>()) {
     if (acc.l1 != 0.0) atomicAdd(&in.sw_l1, acc.l1);
     if (acc.ddelta != 0.0) atomicAdd(&in.sw_ddelta, acc.ddelta);
+    if (acc.dmass != 0.0) atomicAdd(&in.sw_dmass, acc.dmass);
   }
 }
 
@@ -469,12 +479,13 @@ __global__ void __launch_bounds__(MI_CLOSE_THREADS) mi_close_kernel(MiArgs a) {
     if (!in.active) continue;
     const uint32_t changed = in.sw_changed;
     const uint32_t minc = in.sw_min_changed;
-    const double l1 = in.sw_l1, dd = in.sw_ddelta;
+    const double l1 = in.sw_l1, dd = in.sw_ddelta, dm = in.sw_dmass;
     in.edges_total += in.sw_edges;
     in.sweeps += 1;
     bool done = false;
     if constexpr (mi_pr<ALGO>()) {
       in.dangling += dd;
+      in.mass += dm;
       in.last_l1 = l1;
       if (l1 < in.best_l1) { in.best_l1 = l1; in.no_improve = 0; }
       else in.no_improve += 1;
@@ -491,6 +502,7 @@ __global__ void __launch_bounds__(MI_CLOSE_THREADS) mi_close_kernel(MiArgs a) {
     in.sw_edges = 0;
     in.sw_l1 = 0.0;
     in.sw_ddelta = 0.0;
+    in.sw_dmass = 0.0;
     if (done) { in.done = 1; in.active = 0; }
     else { atomicAdd(&s_rem, 1u); atomicAdd(&a.group_active[i / K], 1u); }
   }

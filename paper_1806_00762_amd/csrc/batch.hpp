@@ -28,8 +28,10 @@ struct MiInst {
   unsigned long long sw_edges;
   double sw_l1;
   double sw_ddelta;
+  double sw_dmass;
   // PageRank state
   double dangling;
+  double mass;           // sum of the column's ranks (updates are scaled by 1 / mass)
   double best_l1;
   double last_l1;
   unsigned long long edges_total;
@@ -76,7 +78,7 @@ struct MiArgs {
   int32_t heavy_blocks;     // blocks of the heavy-vertex kernel
   int32_t grab;             // items taken per queue access
   int32_t nblocks;
-  float damping;
+  double damping;
   double tol_l1, floor_cap;
   int32_t max_sweeps;
   int32_t tuning;           // 1: never retire instances (timing runs)

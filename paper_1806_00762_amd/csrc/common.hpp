@@ -74,6 +74,7 @@ struct alignas(128) Stripe {
   unsigned long long edges;
   unsigned long long l1;       // PageRank: sum |delta|, fixed point
   unsigned long long dd;       // PageRank: dangling-mass change, two's complement fixed point
+  unsigned long long dm;       // PageRank: change of the rank sum (mass), two's complement fixed point
   unsigned long long hist[4];  // weak predictor states, two 32-bit counts per word
   uint32_t min_changed;        // smallest new value among changed vertices (min programs)
 };
@@ -161,7 +162,8 @@ struct Ctl {
   uint32_t pass_min_changed, pad1;
   double pass_l1;
   double best_l1;
-  double dangling;        // PageRank: D used by the sweeps
+  double dangling;        // PageRank: D used by the sweeps (sum of the dangling ranks)
+  double mass;            // PageRank: sum of all ranks; a sweep scales its update by 1 / mass
   // run constants
   int32_t algo, pvu, max_passes, pad2;
   double tol_l1;

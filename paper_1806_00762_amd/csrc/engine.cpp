@@ -477,7 +477,7 @@ struct Runner {
     a.audit = (prm.flags & SR_RUN_AUDIT_PVU) ? 1 : 0;
     a.early = (algo == A_BFS && !(prm.flags & SR_RUN_NO_EARLY_BREAK)) ? 1 : 0;
     a.pr_seed = algo == A_PPR ? prm.source : -1;
-    a.damping = (float)prm.damping;
+    a.damping = prm.damping;
     a.pr_eps = prm.pr_change_eps;
     a.ctl = g->state.ctl;
     a.ring = c->ring_dev;
@@ -747,17 +747,9 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   init.floor_cap = 1e-6;
   // a PageRank pass of single plain sweeps is already a verification pass
   if (pr && R.pvu == P_OFF && (p.max_inner_iters == 1 || g->res.resident)) init.phase = 1;
-  if (pr) {
-    double D = 0.0;
-    if (R.algo == A_PR) {
-      int64_t nd = 0;
-      for (int32_t v = 0; v < g->n; ++v) nd += g->outdeg[v] == 0;
-      D = (double)(float)(1.0f / (float)g->n) * (double)nd;
-    } else {
-      D = g->outdeg[p.source] == 0 ? 1.0 : 0.0;
-    }
-    init.dangling = D;
-  }
+  // PageRank: the rank sum and dangling sum are taken from the ranks on the
+  // device once they are set (fresh or resumed)
+  init.mass = 1.0;
   hipError_t e = hipSuccess;
   if (!resume) {
     if (pr) e = launch_init_pr((float *)rs.value, rs.contrib, rs.inv_outdeg, g->n,
@@ -773,6 +765,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     init.phase = init.phase;  // thresholds restart from the safe initial value
   }
   if (e == hipSuccess) e = launch_init_ctl(rs.ctl, init, c->compute);
+  if (e == hipSuccess && pr) e = launch_pr_sums((const float *)rs.value, rs.inv_outdeg, g->n, rs.ctl, c->compute);
   if (e == hipSuccess) e = launch_init_stripes(rs.stripes, c->compute);
   // heavy-vertex accumulators start at the reduction's identity (min: all
   // ones; PageRank: fixed-point zero); the close kernel restores it after

@@ -68,7 +68,7 @@ struct PageCtx {
 struct Acc {
   uint32_t changed = 0, attempted = 0, skipped = 0, mispred = 0, edges = 0;
   uint32_t min_changed = INF;
-  double l1 = 0.0, ddelta = 0.0;
+  double l1 = 0.0, ddelta = 0.0, dmass = 0.0;
 };
 
 // Per-block view of the run state.
@@ -81,7 +81,8 @@ struct Run {
   const float *inv_outdeg;
   uint8_t *status;
   const Diagram *dia;
-  float damping, pr_eps, base_uniform, dangling;
+  double damping, dangling, inv_mass;
+  float pr_eps, base_uniform;
   int32_t pr_seed;
   uint32_t *hist;  // LDS histogram of predictor states
   // frontier of the pass (vertices that changed), for the host sparse stage
@@ -168,9 +169,12 @@ __device__ inline bool epilogue(const Run &r, int32_t v, const Gate &g, bool com
   bool changed = false;
   if (computed) {
     if constexpr (is_pr<ALGO>()) {
-      float t = r.pr_seed < 0 ? r.base_uniform : (v == r.pr_seed ? 1.0f : 0.0f);
+      // x = (1 - d) t + d (P^T x + D t) applied to x / mass: in-place
+      // sweeps do not keep the rank sum at 1, and the drift would otherwise
+      // decay only at rate d; the fixed point (mass 1) is the same
+      const double t = r.pr_seed < 0 ? (double)r.base_uniform : (v == r.pr_seed ? 1.0 : 0.0);
       float oldf = __uint_as_float(g.old);
-      float nv = (1.0f - r.damping) * t + r.damping * (red + r.dangling * t);
+      float nv = (float)((1.0 - r.damping) * t + r.damping * r.inv_mass * ((double)red + r.dangling * t));
       float diff = nv - oldf;
       bool would = fabsf(diff) > r.pr_eps;
       if (g.attempt) {
@@ -179,6 +183,7 @@ __device__ inline bool epilogue(const Run &r, int32_t v, const Gate &g, bool com
         float iod = r.inv_outdeg[v];
         r.contrib[v] = nv * iod;
         acc.l1 += fabs((double)nv - (double)oldf);
+        acc.dmass += (double)nv - (double)oldf;
         if (iod == 0.0f) acc.ddelta += (double)nv - (double)oldf;
       } else if (would) {
         acc.mispred++;
@@ -512,7 +517,7 @@ __device__ void close_pass(Ctl *c, SweepRecord *rec) {
 struct SweepTotals {
   unsigned long long changed, edges, attempted, skipped, mispred, hist[8];
   uint32_t min_changed;
-  double l1, ddelta;
+  double l1, ddelta, dmass;
 };
 
 // Fold a sweep into the pass (one thread) and fill its record in `rec`
@@ -535,6 +540,7 @@ __device__ void close_sweep(Ctl *c, SweepRecord *rec, int end_of_pass, const Swe
   c->pass_min_changed = min(c->pass_min_changed, t.min_changed);
   c->pass_l1 += t.l1;
   c->dangling += t.ddelta;
+  c->mass += t.dmass;
   c->sweep_seq = seq + 1;
   if (end_of_pass) close_pass(c, rec);
   if (!end_of_pass) { rec->done_after = c->done; rec->pass_after = c->pass; rec->stop_reason = c->stop_reason; }
@@ -558,7 +564,7 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   if (ctl->done) return;  // converged: every block leaves before counting
   __shared__ uint32_t s_hist[8];
   __shared__ uint32_t s_u32[WAVES][6];
-  __shared__ double s_f64[WAVES][2];
+  __shared__ double s_f64[WAVES][3];
   __shared__ TileLds s_tile;
   if (threadIdx.x < 8) s_hist[threadIdx.x] = 0;
 
@@ -599,7 +605,8 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   r.damping = a.damping;
   r.pr_eps = a.pr_eps;
   r.base_uniform = 1.0f / (float)a.n;
-  r.dangling = (float)ctl->dangling;
+  r.dangling = ctl->dangling;
+  r.inv_mass = 1.0 / ctl->mass;
   r.pr_seed = a.pr_seed;
   r.hist = s_hist;
   r.collect = a.collect;
@@ -622,22 +629,24 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   uint32_t v0 = wave_sum_u32(acc.changed), v1 = wave_sum_u32(acc.attempted),
            v2 = wave_sum_u32(acc.skipped), v3 = wave_sum_u32(acc.mispred),
            v4 = wave_sum_u32(acc.edges), v5 = wave_min_u32(acc.min_changed);
-  double f0 = 0.0, f1 = 0.0;
-  if constexpr (is_pr<ALGO>()) { f0 = wave_sum_f64(acc.l1); f1 = wave_sum_f64(acc.ddelta); }
+  double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+  if constexpr (is_pr<ALGO>()) {
+    f0 = wave_sum_f64(acc.l1); f1 = wave_sum_f64(acc.ddelta); f2 = wave_sum_f64(acc.dmass);
+  }
   if (lane == 0) {
     s_u32[wave][0] = v0; s_u32[wave][1] = v1; s_u32[wave][2] = v2;
     s_u32[wave][3] = v3; s_u32[wave][4] = v4; s_u32[wave][5] = v5;
-    s_f64[wave][0] = f0; s_f64[wave][1] = f1;
+    s_f64[wave][0] = f0; s_f64[wave][1] = f1; s_f64[wave][2] = f2;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long ch = 0, at = 0, sk = 0, mp = 0, ed = 0;
     uint32_t mn = INF;
-    double l1 = 0.0, dd = 0.0;
+    double l1 = 0.0, dd = 0.0, dm = 0.0;
     for (int w = 0; w < WAVES; ++w) {
       ch += s_u32[w][0]; at += s_u32[w][1]; sk += s_u32[w][2]; mp += s_u32[w][3]; ed += s_u32[w][4];
       mn = min(mn, s_u32[w][5]);
-      l1 += s_f64[w][0]; dd += s_f64[w][1];
+      l1 += s_f64[w][0]; dd += s_f64[w][1]; dm += s_f64[w][2];
     }
     Stripe &st = a.stripes[blockIdx.x % NSTRIPE];
     if (ch | at) atomicAdd(&st.ca, ch | at << 32);
@@ -647,6 +656,7 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
     if constexpr (is_pr<ALGO>()) {
       if (l1 != 0.0) atomicAdd(&st.l1, (unsigned long long)llrint(l1 * FIX_ONE));
       if (dd != 0.0) atomicAdd(&st.dd, (unsigned long long)llrint(dd * FIX_ONE));
+      if (dm != 0.0) atomicAdd(&st.dm, (unsigned long long)llrint(dm * FIX_ONE));
     }
   }
   if (r.pvu == P_WEAK && threadIdx.x < 4) {
@@ -672,7 +682,7 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   __shared__ uint32_t s_hist[8];
   __shared__ unsigned long long s_red[CLOSE_THREADS / 64][5];
   __shared__ uint32_t s_min[CLOSE_THREADS / 64];
-  __shared__ double s_fl[CLOSE_THREADS / 64][2];
+  __shared__ double s_fl[CLOSE_THREADS / 64][3];
   __shared__ __align__(16) SweepRecord s_rec;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, nw = CLOSE_THREADS / 64;
   // independent loads first: the control block is staged in LDS (all of the
@@ -682,7 +692,7 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   if (tid < 8) s_hist[tid] = 0;
   unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, hw[4] = {0, 0, 0, 0};
   uint32_t mn = INF;
-  double l1 = 0.0, dd = 0.0;
+  double l1 = 0.0, dd = 0.0, dm = 0.0;
   if (wave == 1 && lane < NSTRIPE) {
     Stripe &st = a.stripes[lane];
     const unsigned long long ca = atomicExch(&st.ca, 0ull), sm = atomicExch(&st.sm, 0ull);
@@ -693,6 +703,7 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
     if constexpr (is_pr<ALGO>()) {
       l1 = (double)atomicExch(&st.l1, 0ull) / FIX_ONE;
       dd = (double)(long long)atomicExch(&st.dd, 0ull) / FIX_ONE;
+      dm = (double)(long long)atomicExch(&st.dm, 0ull) / FIX_ONE;
     }
     for (int k = 0; k < 4; ++k) hw[k] = atomicExch(&st.hist[k], 0ull);
   }
@@ -712,7 +723,8 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   r.damping = a.damping;
   r.pr_eps = a.pr_eps;
   r.base_uniform = 1.0f / (float)a.n;
-  r.dangling = (float)s_ctl.dangling;
+  r.dangling = s_ctl.dangling;
+  r.inv_mass = 1.0 / s_ctl.mass;
   r.pr_seed = a.pr_seed;
   r.hist = s_hist;
   r.collect = a.collect;
@@ -752,18 +764,18 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   }
   c0 += acc.changed; c1 += acc.attempted; c2 += acc.skipped; c3 += acc.mispred; c4 += acc.edges;
   mn = min(mn, acc.min_changed);
-  l1 += acc.l1; dd += acc.ddelta;
+  l1 += acc.l1; dd += acc.ddelta; dm += acc.dmass;
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
     c0 += shfl_xor(c0, m); c1 += shfl_xor(c1, m); c2 += shfl_xor(c2, m);
     c3 += shfl_xor(c3, m); c4 += shfl_xor(c4, m);
     mn = min(mn, shfl_xor(mn, m));
-    l1 += shfl_xor(l1, m); dd += shfl_xor(dd, m);
+    l1 += shfl_xor(l1, m); dd += shfl_xor(dd, m); dm += shfl_xor(dm, m);
   }
   if (lane == 0) {
     s_red[wave][0] = c0; s_red[wave][1] = c1; s_red[wave][2] = c2; s_red[wave][3] = c3; s_red[wave][4] = c4;
     s_min[wave] = mn;
-    s_fl[wave][0] = l1; s_fl[wave][1] = dd;
+    s_fl[wave][0] = l1; s_fl[wave][1] = dd; s_fl[wave][2] = dm;
   }
   __syncthreads();
   if (tid == 0) {
@@ -773,7 +785,7 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
       t.changed += s_red[w][0]; t.attempted += s_red[w][1]; t.skipped += s_red[w][2];
       t.mispred += s_red[w][3]; t.edges += s_red[w][4];
       t.min_changed = min(t.min_changed, s_min[w]);
-      t.l1 += s_fl[w][0]; t.ddelta += s_fl[w][1];
+      t.l1 += s_fl[w][0]; t.ddelta += s_fl[w][1]; t.dmass += s_fl[w][2];
     }
     for (int k = 0; k < 8; ++k) t.hist[k] = s_hist[k];  // sweep blocks and heavy vertices
     close_sweep(&s_ctl, &s_rec, a.end_of_pass, t);
@@ -819,6 +831,30 @@ __global__ void init_pr_kernel(float *rank, float *contrib, const float *inv_out
   contrib[v] = x * inv_outdeg[v];
 }
 
+// PageRank run start: the rank sum and the dangling sum of the current
+// ranks (fresh or resumed) into the control block. One block; FP64 sums.
+constexpr int SUMS_THREADS = 1024;
+__global__ void __launch_bounds__(SUMS_THREADS) pr_sums_kernel(const float *rank, const float *inv_outdeg,
+                                                               int32_t n, Ctl *ctl) {
+  __shared__ double s[SUMS_THREADS / 64][2];
+  double m = 0.0, dg = 0.0;
+  for (int32_t v = threadIdx.x; v < n; v += SUMS_THREADS) {
+    const double x = (double)rank[v];
+    m += x;
+    if (inv_outdeg[v] == 0.0f) dg += x;
+  }
+  m = wave_sum_f64(m);
+  dg = wave_sum_f64(dg);
+  if (threadIdx.x % 64 == 0) { s[threadIdx.x / 64][0] = m; s[threadIdx.x / 64][1] = dg; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tm = 0.0, td = 0.0;
+    for (int w = 0; w < SUMS_THREADS / 64; ++w) { tm += s[w][0]; td += s[w][1]; }
+    ctl->mass = tm;
+    ctl->dangling = td;
+  }
+}
+
 __global__ void fill_u8_kernel(uint8_t *p, uint8_t v, size_t count) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -835,7 +871,7 @@ __global__ void init_stripes_kernel(Stripe *s) {
   const int i = threadIdx.x;
   if (i < NSTRIPE) {
     Stripe z;
-    z.ca = z.sm = z.edges = z.l1 = z.dd = 0ull;
+    z.ca = z.sm = z.edges = z.l1 = z.dd = z.dm = 0ull;
     for (int k = 0; k < 4; ++k) z.hist[k] = 0ull;
     z.min_changed = INF;
     s[i] = z;
@@ -887,6 +923,11 @@ hipError_t launch_init_pr(float *rank, float *contrib, const float *inv_outdeg, 
                           int32_t seed, hipStream_t s) {
   hipLaunchKernelGGL(init_pr_kernel, dim3((n + 255) / 256), dim3(256), 0, s, rank, contrib,
                      inv_outdeg, n, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_pr_sums(const float *rank, const float *inv_outdeg, int32_t n, Ctl *ctl, hipStream_t s) {
+  hipLaunchKernelGGL(pr_sums_kernel, dim3(1), dim3(SUMS_THREADS), 0, s, rank, inv_outdeg, n, ctl);
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ struct SweepArgs {
   int32_t nblocks;         // grid size
   int32_t packed;          // edge words carry the weight in their top byte
   int32_t early;           // BFS under strong prediction: stop at a first in-neighbour on the threshold level
-  float damping;
+  double damping;
   float pr_eps;
   Ctl *ctl;                // device control block
   SweepRecord *ring;       // host-mapped per-sweep records
@@ -50,6 +50,8 @@ hipError_t launch_end_pass(Ctl *ctl, SweepRecord *ring, uint32_t ring_mask, hipS
 hipError_t launch_init_min(int algo, uint32_t *value, int32_t n, int32_t source, hipStream_t s);
 hipError_t launch_init_pr(float *rank, float *contrib, const float *inv_outdeg, int32_t n,
                           int32_t seed, hipStream_t s);
+// PageRank: sum of the ranks and of the dangling ranks into ctl->mass, ctl->dangling
+hipError_t launch_pr_sums(const float *rank, const float *inv_outdeg, int32_t n, Ctl *ctl, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
 hipError_t launch_init_stripes(Stripe *s, hipStream_t st);

@@ -183,7 +183,7 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
   args.total_heavy = total_heavy;
   args.heavy_blocks = (int32_t)std::max<int64_t>(1, ((int64_t)total_heavy * K + BLOCK - 1) / BLOCK);
   args.grab = 1;
-  args.damping = (float)damping;
+  args.damping = damping;
   args.tol_l1 = tol_l1;
   args.floor_cap = 1e-6;
   args.max_sweeps = max_sweeps;
@@ -220,7 +220,10 @@ sr_status MiPlan::set_column(int gi, int col, int32_t source, bool unit, bool ac
   in.sw_min_changed = INF;
   in.best_l1 = 1e300;
   in.last_l1 = -1.0;
-  if (algo == A_PPR) in.dangling = (source >= 0 && g->outdeg[source] == 0) ? 1.0 : 0.0;
+  if (algo == A_PPR) {
+    in.dangling = (source >= 0 && g->outdeg[source] == 0) ? 1.0 : 0.0;
+    in.mass = 1.0;  // the column starts at e_source
+  }
   hipError_t e = hipSuccess;
   if (source >= 0 && clean && algo != A_PPR)
     e = launch_fill_u32(gr.value + (size_t)source * K + col, 0u, 1, s);
