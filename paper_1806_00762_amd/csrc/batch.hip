@@ -539,14 +539,18 @@ __global__ void mi_set_ctl_kernel(MiCtl *dst, MiCtl val) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = val;
 }
 
+// Several columns in one pass: the columns of a vertex share its row of
+// 4K bytes, so the row is fetched from memory once for all of them.
 template <int K>
-__global__ void mi_extract_kernel(uint32_t *value, int32_t n, int32_t col, uint32_t *out, int32_t reset,
-                                  uint32_t reset_to, const int32_t *rank) {
+__global__ void mi_extract_kernel(uint32_t *value, int32_t n, MiExtract x, int32_t reset, uint32_t reset_to,
+                                  const int32_t *rank) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const size_t i = (size_t)(rank ? rank[v] : v) * K + col;
-  out[v] = value[i];
-  if (reset) value[i] = reset_to;
+  uint32_t *row = value + (size_t)(rank ? rank[v] : v) * K;
+  for (int j = 0; j < x.count; ++j) {
+    x.out[j][v] = row[x.col[j]];
+    if (reset) row[x.col[j]] = reset_to;
+  }
 }
 
 template <int ALGO, int K>
@@ -585,13 +589,17 @@ hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contri
   return hipGetLastError();
 }
 
-hipError_t launch_mi_extract(int K, uint32_t *value, int32_t n, int32_t col, uint32_t *out, hipStream_t s,
+hipError_t launch_mi_extract(int K, uint32_t *value, int32_t n, const MiExtract &x, hipStream_t s,
                              bool reset, uint32_t reset_to, const int32_t *rank) {
+  if (x.count < 1 || x.count > MI_EXTRACT_MAX) return hipErrorInvalidValue;
+  for (int j = 0; j < x.count; ++j)
+    if (x.col[j] < 0 || x.col[j] >= K || !x.out[j]) return hipErrorInvalidValue;
+  if (n <= 0) return hipSuccess;
   dim3 grid((n + 255) / 256), block(256);
   const int32_t r = reset ? 1 : 0;
-  if (K == 8) hipLaunchKernelGGL(mi_extract_kernel<8>, grid, block, 0, s, value, n, col, out, r, reset_to, rank);
-  else if (K == 16) hipLaunchKernelGGL(mi_extract_kernel<16>, grid, block, 0, s, value, n, col, out, r, reset_to, rank);
-  else if (K == 32) hipLaunchKernelGGL(mi_extract_kernel<32>, grid, block, 0, s, value, n, col, out, r, reset_to, rank);
+  if (K == 8) hipLaunchKernelGGL(mi_extract_kernel<8>, grid, block, 0, s, value, n, x, r, reset_to, rank);
+  else if (K == 16) hipLaunchKernelGGL(mi_extract_kernel<16>, grid, block, 0, s, value, n, x, r, reset_to, rank);
+  else if (K == 32) hipLaunchKernelGGL(mi_extract_kernel<32>, grid, block, 0, s, value, n, x, r, reset_to, rank);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -93,10 +93,17 @@ hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contri
                                  int32_t n, int32_t col, int32_t source, hipStream_t s);
 hipError_t launch_mi_set_inst(MiInst *dst, const MiInst &val, hipStream_t s);
 hipError_t launch_mi_set_ctl(MiCtl *dst, const MiCtl &val, hipStream_t s);
-// Copy column col of value[n][K] to out (out[v] = value[rank[v]][col] when
-// rank is given: internal ids of a reordered graph); with reset, leave
-// `reset_to` in the column (so the next query on it only sets its source).
-hipError_t launch_mi_extract(int K, uint32_t *value, int32_t n, int32_t col, uint32_t *out, hipStream_t s,
+// Columns to copy out of value[n][K] in one pass: out[j][v] = value[v][col[j]].
+constexpr int MI_EXTRACT_MAX = 32;
+struct MiExtract {
+  int32_t count;
+  int32_t col[MI_EXTRACT_MAX];
+  uint32_t *out[MI_EXTRACT_MAX];  // device buffers of n words
+};
+// Copy the listed columns (row rank[v] for vertex v when rank is given:
+// internal ids of a reordered graph); with reset, leave `reset_to` in them
+// (so the next query on a column only sets its source).
+hipError_t launch_mi_extract(int K, uint32_t *value, int32_t n, const MiExtract &x, hipStream_t s,
                              bool reset = false, uint32_t reset_to = 0u, const int32_t *rank = nullptr);
 
 }  // namespace sr

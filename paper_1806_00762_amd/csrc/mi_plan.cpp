@@ -449,18 +449,34 @@ extern "C" sr_status sr_batch_run(sr_ctx *c, const sr_instance *inst, int32_t co
   }
   int32_t maxn = 0;
   for (auto *g : order) maxn = std::max(maxn, g->n);
+  // one extraction pass per group (its K columns share each row)
   uint32_t *tmp = nullptr;
-  if ((s = plan.alloc((void **)&tmp, 4ull * maxn, "extract buffer")) != SR_OK) return s;
+  if ((s = plan.alloc((void **)&tmp, 4ull * maxn * K, "extract buffer")) != SR_OK) return s;
+  std::vector<int32_t> extracted_group(count, -1);
   bool all_conv = true;
   uint64_t algo_bytes = 0;
   int32_t dev_sweeps = 0;
   std::vector<int32_t> group_sweeps(plan.groups.size(), 0);
   for (int32_t i = 0; i < count; ++i) {
-    const MiGroup &gr = plan.groups[where[i].group];
-    he = launch_mi_extract(K, gr.value, gr.n, where[i].col, tmp, st, false, 0u, plan.group_rank[where[i].group]);
-    if (he == hipSuccess) he = hipMemcpyAsync(dsts[i], tmp, 4ull * gr.n, hipMemcpyDeviceToHost, st);
-    if (he == hipSuccess) he = hipStreamSynchronize(st);
-    if (he != hipSuccess) return c->hip_fail(he, "batch results");
+    const int gi = where[i].group;
+    const MiGroup &gr = plan.groups[gi];
+    if (extracted_group[i] < 0) {
+      // every instance of this group: one pass, then all its copies
+      MiExtract x{};
+      for (int32_t j = i; j < count; ++j)
+        if (where[j].group == gi) {
+          x.col[x.count] = where[j].col;
+          x.out[x.count] = tmp + (size_t)where[j].col * maxn;
+          x.count++;
+          extracted_group[j] = gi;
+        }
+      he = launch_mi_extract(K, gr.value, gr.n, x, st, false, 0u, plan.group_rank[gi]);
+      for (int32_t j = i; j < count && he == hipSuccess; ++j)
+        if (where[j].group == gi)
+          he = hipMemcpyAsync(dsts[j], tmp + (size_t)where[j].col * maxn, 4ull * gr.n, hipMemcpyDeviceToHost, st);
+      if (he == hipSuccess) he = hipStreamSynchronize(st);
+      if (he != hipSuccess) return c->hip_fail(he, "batch results");
+    }
     const MiInst &r = ih[where[i].group][where[i].col];
     all_conv &= r.done && (r.stop_reason == 1 || r.stop_reason == 2);
     dev_sweeps = std::max<int32_t>(dev_sweeps, (int32_t)r.sweeps);

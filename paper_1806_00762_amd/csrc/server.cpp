@@ -142,16 +142,21 @@ void sr_server::progress() {
           if (r.done) finished.push_back({t, gi * K + k});
         }
     }
-    for (auto &f : finished) {
-      int gi = f.second / K, k = f.second % K;
-      uint32_t *dst;
+    // one extraction pass per graph for all of its retiring columns
+    for (int gi = 0; gi < G && e == hipSuccess; ++gi) {
+      MiExtract x{};
       {
         std::lock_guard<std::mutex> lk(mu);
-        dst = q[f.first].result;
+        for (auto &f : finished)
+          if (f.second / K == gi) {
+            x.col[x.count] = f.second % K;
+            x.out[x.count] = q[f.first].result;
+            x.count++;
+          }
       }
-      e = launch_mi_extract(K, plan->groups[gi].value, plan->groups[gi].n, k, dst, stream, true, INF,
+      if (x.count == 0) continue;
+      e = launch_mi_extract(K, plan->groups[gi].value, plan->groups[gi].n, x, stream, true, INF,
                             plan->group_rank[gi]);
-      if (e != hipSuccess) break;
     }
     if (!finished.empty() && e == hipSuccess) e = hipStreamSynchronize(stream);
     const double t1 = now_ms();

@@ -83,3 +83,28 @@ def test_batched_pvu_off_equals_strong(sr, ctx):
         assert np.array_equal(x, y)
         assert np.array_equal(x, oracle.sssp(g, s))
     G.close()
+
+
+def test_batched_interleaved_graphs_and_sizes(sr, ctx):
+    """Instances listed alternately over graphs of different sizes (results
+    are extracted one group at a time; every instance must still get its own
+    column of its own graph)."""
+    graphs = [graphgen.rmat(13, 8, seed=81, weights=(1, 255, 82)), graphgen.uniform(11, 1 << 14, seed=83,
+                                                                                   weights=(1, 255, 84))]
+    Gs = [ctx.load(g, reorder=(gi == 1)) for gi, g in enumerate(graphs)]
+    srcs = [[int(s) for s in graphgen.sources_with_outedges(g, 11, seed=85 + gi)] for gi, g in enumerate(graphs)]
+    insts = []
+    for j in range(11):
+        for gi in (0, 1):
+            insts.append((gi, "sssp" if (j + gi) % 2 == 0 else "bfs", srcs[gi][j]))
+    say(f"case batched interleaved {len(insts)}")
+    outs, _, _ = sr.batch_run(ctx, [(Gs[gi], a, s) for gi, a, s in insts])
+    for (gi, a, s), x in zip(insts, outs):
+        ref = oracle.sssp(graphs[gi], s) if a == "sssp" else oracle.bfs(graphs[gi], s)
+        assert np.array_equal(x, ref), (gi, a, s)
+    outs, _, _ = sr.batch_run(ctx, [(Gs[gi], "ppr", s) for gi, _, s in insts[:10]])
+    for (gi, _, s), x in zip(insts[:10], outs):
+        ref, _, _ = oracle.pagerank(graphs[gi], seed=s, tol=1e-13)
+        assert np.max(np.abs(x.view(np.float32).astype(np.float64) - ref)) <= 1e-6, (gi, s)
+    for G in Gs:
+        G.close()
