@@ -760,10 +760,9 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       e = hipMemcpyAsync(rs.value, g->perm.data(), 4ull * g->n, hipMemcpyHostToDevice, c->compute);
     if (e == hipSuccess) e = launch_fill_u8(rs.status, (uint8_t)d.initial_state, (size_t)g->n, c->compute);
   }
-  if (resume) {
-    // keep values and predictor states; restart the pass bookkeeping
-    init.phase = init.phase;  // thresholds restart from the safe initial value
-  }
+  // on resume the values and predictor states stay; the control block
+  // (pass bookkeeping, thresholds back at their safe initial value) and, for
+  // PageRank, the rank and dangling sums start afresh from the values
   if (e == hipSuccess) e = launch_init_ctl(rs.ctl, init, c->compute);
   if (e == hipSuccess && pr) e = launch_pr_sums((const float *)rs.value, rs.inv_outdeg, g->n, rs.ctl, c->compute);
   if (e == hipSuccess) e = launch_init_stripes(rs.stripes, c->compute);
