@@ -230,7 +230,8 @@ typedef struct {
   int64_t edges_scanned;     /* in-edges read by attempted vertices */
   int64_t vertices_attempted, vertices_skipped, mispredicted;
   uint64_t h2d_bytes;        /* page bytes copied host -> device */
-  double kernel_ms;          /* summed sweep-kernel time (HIP events) */
+  double kernel_ms;          /* summed time of the sweep kernels and the kernels closing each sweep
+                                (HIP events) */
   double h2d_ms;             /* summed page-copy time (HIP events) */
   double wall_ms;            /* host wall time of sr_run */
   double final_l1;           /* PageRank: L1 change of the last full pass */
@@ -243,6 +244,8 @@ typedef struct {
   int64_t sparse_relaxations;/* edges it relaxed */
   double sparse_ms;          /* its wall time, transfers included */
   int64_t pages_skipped;     /* SR_RUN_SKIP_CLEAN: page visits left out because no in-edge changed */
+  double sweep_kernel_ms;    /* the part of kernel_ms spent in the sweep kernels alone (without the
+                                kernels that close each sweep) */
 } sr_run_stats;
 
 /* Run a vertex program to convergence on the graph (partitioned with

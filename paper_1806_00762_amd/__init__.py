@@ -79,7 +79,7 @@ class sr_run_stats(ctypes.Structure):
                 ("algo_bytes", ctypes.c_uint64), ("sparse_stage", ctypes.c_int32),
                 ("sparse_rounds", ctypes.c_int32), ("sparse_frontier", ctypes.c_int64),
                 ("sparse_relaxations", ctypes.c_int64), ("sparse_ms", ctypes.c_double),
-                ("pages_skipped", ctypes.c_int64)]
+                ("pages_skipped", ctypes.c_int64), ("sweep_kernel_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}

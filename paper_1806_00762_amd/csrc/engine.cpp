@@ -384,7 +384,7 @@ struct Runner {
   int32_t collect = 0;                      // sweeps append changed vertices to the frontier
   // timing events: a free list, and start/end pairs not yet read
   std::vector<hipEvent_t> ev_all, ev_free;
-  struct Pair { hipEvent_t a, b; bool copy; };
+  struct Pair { hipEvent_t a, b; bool copy; hipEvent_t mid = nullptr; };  // mid: sweep kernel end
   std::vector<Pair> pending;
 
   ~Runner() {
@@ -397,9 +397,9 @@ struct Runner {
     ev_all.push_back(e);
     return e;
   }
-  void track(hipEvent_t a, hipEvent_t b, bool copy) {
-    if (a && b) pending.push_back({a, b, copy});
-    else { if (a) ev_free.push_back(a); if (b) ev_free.push_back(b); }
+  void track(hipEvent_t a, hipEvent_t b, bool copy, hipEvent_t mid = nullptr) {
+    if (a && b) pending.push_back({a, b, copy, mid});
+    else { if (a) ev_free.push_back(a); if (b) ev_free.push_back(b); if (mid) ev_free.push_back(mid); }
   }
   // read the timings of completed pairs; pairs still in flight stay pending
   void harvest_events() {
@@ -408,8 +408,10 @@ struct Runner {
       if (hipEventQuery(p.b) != hipSuccess) { keep.push_back(p); continue; }
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) (p.copy ? st.h2d_ms : st.kernel_ms) += ms;
+      if (p.mid && hipEventElapsedTime(&ms, p.a, p.mid) == hipSuccess) st.sweep_kernel_ms += ms;
       ev_free.push_back(p.a);
       ev_free.push_back(p.b);
+      if (p.mid) ev_free.push_back(p.mid);
     }
     pending.swap(keep);
   }
@@ -458,12 +460,12 @@ struct Runner {
   }
 
   sr_status launch(const SweepArgs &a) {
-    hipEvent_t e0 = ev(), e1 = ev();
+    hipEvent_t e0 = ev(), em = ev(), e1 = ev();
     if (e0) (void)hipEventRecord(e0, c->compute);
-    hipError_t e = launch_sweep(algo, a, c->compute);
+    hipError_t e = launch_sweep(algo, a, c->compute, em);
     if (e != hipSuccess) return c->hip_fail(e, "sweep launch");
     if (e1) (void)hipEventRecord(e1, c->compute);
-    track(e0, e1, false);
+    track(e0, e1, false, em);
     return SR_OK;
   }
 

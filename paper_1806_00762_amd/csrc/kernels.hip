@@ -885,23 +885,24 @@ __global__ void init_ctl_kernel(Ctl *ctl, Ctl init) {
 }  // namespace
 
 template <int ALGO>
-static void launch_pair(const SweepArgs &a, hipStream_t s) {
+static void launch_pair(const SweepArgs &a, hipStream_t s, hipEvent_t mid) {
   constexpr int EPT = TILE_E / BLOCK;
   if (a.packed)
     hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
   else
     hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, false>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+  if (mid) (void)hipEventRecord(mid, s);
   hipLaunchKernelGGL(close_kernel<ALGO>, dim3(1), dim3(CLOSE_THREADS), 0, s, a);
 }
 
-hipError_t launch_sweep(int algo, const SweepArgs &a, hipStream_t s) {
+hipError_t launch_sweep(int algo, const SweepArgs &a, hipStream_t s, hipEvent_t mid) {
   if (a.nblocks <= 0) return hipErrorInvalidValue;
   switch (algo) {
-    case A_BFS: launch_pair<A_BFS>(a, s); break;
-    case A_SSSP: launch_pair<A_SSSP>(a, s); break;
-    case A_CC: launch_pair<A_CC>(a, s); break;
-    case A_PR: launch_pair<A_PR>(a, s); break;
-    case A_PPR: launch_pair<A_PPR>(a, s); break;
+    case A_BFS: launch_pair<A_BFS>(a, s, mid); break;
+    case A_SSSP: launch_pair<A_SSSP>(a, s, mid); break;
+    case A_CC: launch_pair<A_CC>(a, s, mid); break;
+    case A_PR: launch_pair<A_PR>(a, s, mid); break;
+    case A_PPR: launch_pair<A_PPR>(a, s, mid); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

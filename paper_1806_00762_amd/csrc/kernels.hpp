@@ -45,7 +45,9 @@ inline int sec_blocks(const PageHeader &h, int sec) {
   return sec == 0 ? h.n_tiles : (h.n_chunks + WAVES - 1) / WAVES;
 }
 
-hipError_t launch_sweep(int algo, const SweepArgs &a, hipStream_t s);
+// the sweep kernel, then the kernel that closes the sweep; `mid` (optional)
+// is recorded between the two
+hipError_t launch_sweep(int algo, const SweepArgs &a, hipStream_t s, hipEvent_t mid = nullptr);
 hipError_t launch_end_pass(Ctl *ctl, SweepRecord *ring, uint32_t ring_mask, hipStream_t s);
 hipError_t launch_init_min(int algo, uint32_t *value, int32_t n, int32_t source, hipStream_t s);
 hipError_t launch_init_pr(float *rank, float *contrib, const float *inv_outdeg, int32_t n,
