@@ -193,6 +193,10 @@ def bench_sssp22(args):
                          "h2d_bytes_per_solve": h["h2d_bytes"],
                          "note": "device dense passes + host push sparse stage; not the headline value"}
         log(f"[bench] hetero: {res['hetero']}")
+    probe = gather_probe(args, g, G, dist)
+    res["roofline"]["gather_probe"] = probe
+    res["roofline"]["sweep_scan_vs_probe"] = round(res["scan_gteps"] / probe["edges_per_s"], 3)
+    log(f"[bench] gather probe: {probe}")
     if not args.no_other:
         res["bfs_early_break"] = bench_bfs_early_break(args, g, G)
         log(f"[bench] bfs early break: {res['bfs_early_break']}")
@@ -275,6 +279,35 @@ def ablation(args, G, parts, dist):
         log(f"[bench] ablation {name}: {row['ms_per_solve']} ms, {row['passes']} passes, {row['sweeps']} sweeps")
     G.partition(parts, args.slots)
     return out
+
+
+def gather_probe(args, g, G, dist):
+    """The sweep's practical ceiling: the same edge words in the same order
+    (all pages of the graph, vertices as numbered on the device) and the same
+    value array, read with the sweep kernel's tiling by a kernel that only
+    gathers (no gate, no reduction, no writes): sr_probe_gather."""
+    import paper_1806_00762_amd as sr
+    info = G.info()
+    words, packed = [], False
+    for p in range(info["num_parts"]):
+        pg = G.page(p)
+        w = pg["src"].astype(np.uint32)
+        if pg["src_packed"]:
+            packed = True
+            w = w | (pg["weights"].astype(np.uint32) << np.uint32(24))
+        words.append(w)
+    words = np.concatenate(words)
+    vals = dist
+    if args.order == "degree":
+        _, caller_of = G.order()
+        vals = dist[caller_of]
+    ctx = sr.Context(0, 0)
+    ms, _ = sr.probe_gather(ctx, words, 0x00FFFFFF if packed else 0xFFFFFFFF, vals.astype(np.uint32), repeats=20)
+    ctx.close()
+    rate = words.size / (ms * 1e-3)
+    return {"kernel": "gather_probe_kernel", "edges": int(words.size), "ms_per_launch": round(ms, 4),
+            "edges_per_s": round(rate / 1e9, 2), "unit_edges": "G/s",
+            "GBps_8B_per_edge": round(8 * rate / 1e9, 1)}
 
 
 def bench_bfs_early_break(args, g, G):

@@ -352,6 +352,27 @@ sr_status sr_server_stats_get(sr_server *srv, sr_server_stats *out);
  * server's device state. Results not yet polled are discarded. */
 sr_status sr_server_destroy(sr_server *srv);
 
+/* Diagnostic, not part of any solve: the rate of the pull's random gather
+ * alone (the gather of in-neighbour values in the pull of Section 4.1, the
+ * memory-bound step Section 5.3 finds limiting). The m edge words at src
+ * and the n u32 values at values (host memory, owned by the caller; the
+ * source id of a word is word & src_mask) are copied to device memory the
+ * library allocates within the context's budget and frees on return. The
+ * probe reads every word and the value it names with the sweep kernel's
+ * tiling (2048 words per block
+ * of 256 threads, 8 consecutive words per thread, the 8 word loads and then
+ * the 8 gathers issued together), with no gate, reduction or write beyond
+ * one checksum add per block. One untimed launch gives *checksum = the sum of
+ * values[word & src_mask] over all words, modulo 2^64; then `repeats`
+ * launches are timed with HIP events on the context's compute stream and
+ * *ms_per_launch receives their average. Ids at or above n are clamped to
+ * n - 1, so nothing outside the values is read. SR_EINVAL: a null pointer,
+ * m < 1, n < 1, repeats < 1 or m above 2^31 * 2048; SR_EBUDGET: the copies
+ * do not fit the budget; SR_EDEVICE: a host-only context or a HIP error. */
+sr_status sr_probe_gather(sr_ctx *ctx, const uint32_t *src, int64_t m, uint32_t src_mask,
+                          const uint32_t *values, int32_t n, int32_t repeats, double *ms_per_launch,
+                          uint64_t *checksum);
+
 #ifdef __cplusplus
 }
 #endif

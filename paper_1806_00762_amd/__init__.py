@@ -140,6 +140,9 @@ EXTRA_SIGNATURES: dict = {
                                       ctypes.POINTER(ctypes.c_double)]),
     "sr_server_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(sr_server_stats)]),
     "sr_server_destroy": (ctypes.c_int, [_P]),
+    "sr_probe_gather": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_uint32, _P,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_uint64)]),
 }
 
 _lib = None
@@ -339,6 +342,19 @@ class Graph:
         if dtype is not None:
             return out.view(dtype)
         return out
+
+
+def probe_gather(ctx: Context, words, src_mask: int, values, repeats: int = 10):
+    """Gather-rate probe (sr_probe_gather): u32 edge words and u32 values
+    (host arrays). Returns (ms per launch, checksum)."""
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    v = np.ascontiguousarray(values, dtype=np.uint32)
+    ms = ctypes.c_double()
+    cs = ctypes.c_uint64()
+    _check(lib().sr_probe_gather(ctx.h, w.ctypes.data if w.size else None, int(w.size), src_mask,
+                                 v.ctypes.data if v.size else None, int(v.size), repeats,
+                                 ctypes.byref(ms), ctypes.byref(cs)), ctx.h)
+    return ms.value, cs.value
 
 
 def batch_run(ctx: Context, instances, damping: float = 0.85, tol_l1: float = 1e-9, max_sweeps: int = 0,

@@ -1043,6 +1043,53 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   return SR_OK;
 }
 
+extern "C" sr_status sr_probe_gather(sr_ctx *c, const uint32_t *src, int64_t m, uint32_t src_mask,
+                                     const uint32_t *values, int32_t n, int32_t repeats, double *ms_per_launch,
+                                     uint64_t *checksum) {
+  if (!c) return SR_EINVAL;
+  if (!src || !values || !ms_per_launch || !checksum || m < 1 || n < 1 || repeats < 1 ||
+      (m + TILE_E - 1) / TILE_E > 0x7FFFFFFF)
+    return c->fail(SR_EINVAL, "probe: null pointer or bad size");
+  if (c->host_only) return c->fail(SR_EDEVICE, "host-only context has no device");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  unsigned long long *sink = nullptr;
+  uint32_t *d_src = nullptr, *d_values = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto done = [&](sr_status st) {
+    (void)hipStreamSynchronize(c->compute);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (sink) c->dfree(sink);
+    if (d_src) c->dfree(d_src);
+    if (d_values) c->dfree(d_values);
+    return st;
+  };
+  sr_status s = c->dalloc((void **)&sink, 8, "probe checksum");
+  if (s == SR_OK) s = c->dalloc((void **)&d_src, 4ull * (uint64_t)m, "probe words");
+  if (s == SR_OK) s = c->dalloc((void **)&d_values, 4ull * (uint64_t)n, "probe values");
+  if (s != SR_OK) return done(s);
+  hipError_t e = hipMemcpyAsync(d_src, src, 4ull * (uint64_t)m, hipMemcpyHostToDevice, c->compute);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_values, values, 4ull * (uint64_t)n, hipMemcpyHostToDevice, c->compute);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t *)sink, 0u, 2, c->compute);
+  if (e == hipSuccess) e = launch_gather_probe(d_src, m, src_mask, d_values, n, sink, c->compute);
+  unsigned long long sum = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&sum, sink, 8, hipMemcpyDeviceToHost, c->compute);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->compute);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, c->compute);
+  for (int32_t i = 0; i < repeats && e == hipSuccess; ++i)
+    e = launch_gather_probe(d_src, m, src_mask, d_values, n, sink, c->compute);
+  if (e == hipSuccess) e = hipEventRecord(e1, c->compute);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e != hipSuccess) return done(c->hip_fail(e, "gather probe"));
+  *ms_per_launch = (double)ms / repeats;
+  *checksum = sum;
+  return done(SR_OK);
+}
+
 extern "C" sr_status sr_run_sweeps(const sr_graph *g, sr_sweep_record *out, int32_t max, int32_t *count) {
   if (!g || !count || max < 0 || (max > 0 && !out)) return g ? g->ctx->fail(SR_EINVAL, "bad arguments") : SR_EINVAL;
   const int32_t n = (int32_t)g->sweeps.size();

@@ -831,6 +831,37 @@ __global__ void init_pr_kernel(float *rank, float *contrib, const float *inv_out
   contrib[v] = x * inv_outdeg[v];
 }
 
+// Gather-rate probe: the sweep's tiling (TILE_E words per block, EPT
+// consecutive words per thread, loads issued together) over a plain word
+// array, every word's value gathered and summed; one add per block.
+__global__ void __launch_bounds__(BLOCK) gather_probe_kernel(const uint32_t *src, int64_t m, uint32_t mask,
+                                                             const uint32_t *val, int32_t n,
+                                                             unsigned long long *sink) {
+  constexpr int EPT = TILE_E / BLOCK;
+  __shared__ unsigned long long s[WAVES];
+  const int64_t p0 = (int64_t)blockIdx.x * TILE_E + (int64_t)threadIdx.x * EPT;
+  unsigned long long acc = 0;
+  if (p0 < m) {
+    uint32_t w[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) w[j] = src[p0 + j < m ? p0 + j : p0];
+    uint32_t x[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) x[j] = val[min(w[j] & mask, (uint32_t)(n - 1))];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) acc += p0 + j < m ? x[j] : 0u;
+  }
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) acc += shfl_xor(acc, k);
+  if (threadIdx.x % 64 == 0) s[threadIdx.x / 64] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < WAVES; ++w) t += s[w];
+    atomicAdd(sink, t);
+  }
+}
+
 // PageRank run start: the rank sum and the dangling sum of the current
 // ranks (fresh or resumed) into the control block. One block; FP64 sums.
 constexpr int SUMS_THREADS = 1024;
@@ -924,6 +955,14 @@ hipError_t launch_init_pr(float *rank, float *contrib, const float *inv_outdeg, 
                           int32_t seed, hipStream_t s) {
   hipLaunchKernelGGL(init_pr_kernel, dim3((n + 255) / 256), dim3(256), 0, s, rank, contrib,
                      inv_outdeg, n, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_probe(const uint32_t *src, int64_t m, uint32_t mask, const uint32_t *val, int32_t n,
+                               unsigned long long *sink, hipStream_t s) {
+  const int64_t blocks = (m + TILE_E - 1) / TILE_E;
+  if (m < 1 || n < 1 || blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gather_probe_kernel, dim3((unsigned)blocks), dim3(BLOCK), 0, s, src, m, mask, val, n, sink);
   return hipGetLastError();
 }
 

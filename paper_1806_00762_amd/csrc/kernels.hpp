@@ -52,6 +52,10 @@ hipError_t launch_end_pass(Ctl *ctl, SweepRecord *ring, uint32_t ring_mask, hipS
 hipError_t launch_init_min(int algo, uint32_t *value, int32_t n, int32_t source, hipStream_t s);
 hipError_t launch_init_pr(float *rank, float *contrib, const float *inv_outdeg, int32_t n,
                           int32_t seed, hipStream_t s);
+// gather-rate probe over m words (ids masked, clamped below n); adds the sum
+// of the gathered values to *sink
+hipError_t launch_gather_probe(const uint32_t *src, int64_t m, uint32_t mask, const uint32_t *val, int32_t n,
+                               unsigned long long *sink, hipStream_t s);
 // PageRank: sum of the ranks and of the dangling ranks into ctl->mass, ctl->dangling
 hipError_t launch_pr_sums(const float *rank, const float *inv_outdeg, int32_t n, Ctl *ctl, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t count, hipStream_t s);

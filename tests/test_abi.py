@@ -54,6 +54,23 @@ def test_host_only_context_refuses_device_work(sr):
     g.close(); c.close()
 
 
+def test_gather_probe_argument_checks(sr):
+    """The probe checks its arguments before touching a device, and a
+    host-only context has none to probe."""
+    import numpy as np
+    c = sr.Context(-1, 1 << 30)
+    w = np.arange(16, dtype=np.uint32)
+    v = np.arange(4, dtype=np.uint32)
+    for words, vals, reps in ((w[:0], v, 1), (w, v[:0], 1), (w, v, 0)):
+        with pytest.raises(sr.SeraphError) as e:
+            sr.probe_gather(c, words, 0xFFFFFFFF, vals, repeats=reps)
+        assert e.value.status == sr.SR_EINVAL
+    with pytest.raises(sr.SeraphError) as e:
+        sr.probe_gather(c, w, 0xFFFFFFFF, v)
+    assert e.value.status == sr.SR_EDEVICE
+    c.close()
+
+
 @pytest.mark.parametrize("sym", [False, True])
 def test_in_csr_and_pages(sr, sym):
     c = sr.Context(-1, 1 << 30)
