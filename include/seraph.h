@@ -359,15 +359,15 @@ sr_status sr_server_destroy(sr_server *srv);
  * source id of a word is word & src_mask) are copied to device memory the
  * library allocates within the context's budget and frees on return. The
  * probe reads every word and the value it names with the sweep kernel's
- * tiling (2048 words per block
- * of 256 threads, 8 consecutive words per thread, the 8 word loads and then
- * the 8 gathers issued together), with no gate, reduction or write beyond
+ * tiling (4096 words per block of 256 threads; thread t reads 8 groups of
+ * 2 consecutive words starting at g * 512 + 2t, the 16 word loads and then
+ * the 16 gathers issued together), with no gate, reduction or write beyond
  * one checksum add per block. One untimed launch gives *checksum = the sum of
  * values[word & src_mask] over all words, modulo 2^64; then `repeats`
  * launches are timed with HIP events on the context's compute stream and
  * *ms_per_launch receives their average. Ids at or above n are clamped to
  * n - 1, so nothing outside the values is read. SR_EINVAL: a null pointer,
- * m < 1, n < 1, repeats < 1 or m above 2^31 * 2048; SR_EBUDGET: the copies
+ * m < 1, n < 1, repeats < 1 or m above 2^31 * 4096; SR_EBUDGET: the copies
  * do not fit the budget; SR_EDEVICE: a host-only context or a HIP error. */
 sr_status sr_probe_gather(sr_ctx *ctx, const uint32_t *src, int64_t m, uint32_t src_mask,
                           const uint32_t *values, int32_t n, int32_t repeats, double *ms_per_launch,

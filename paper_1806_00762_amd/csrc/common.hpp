@@ -32,9 +32,9 @@ constexpr int WAVES = BLOCK / 64;
 
 // Tiles of the single-instance sweep: runs of consecutive non-heavy
 // vertices with at most TILE_V vertices and TILE_E in-edges, one block
-// each (8 edges per thread).
+// each (16 edges per thread, so 16 gathers per thread are in flight).
 constexpr int TILE_V = 2 * BLOCK;
-constexpr int TILE_E = 8 * BLOCK;
+constexpr int TILE_E = 16 * BLOCK;
 
 // vertices per block for bins 0..6 and chunks per block for bin 7
 constexpr int SMALL_ROUNDS = 4;   // vertices per lane group in bins 0..5

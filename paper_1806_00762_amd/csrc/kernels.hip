@@ -343,59 +343,87 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
   }
   if (tid == 0) s.pos[Kt] = At;
   __syncthreads();
-  // phase 2: EDGES_PER_THREAD consecutive compacted edge positions per thread
-  const int p0 = tid * EDGES_PER_THREAD;
-  if (p0 < At) {
-    int lo = 0, hi = Kt;  // pos[lo] <= p0 < pos[hi]
-    while (hi - lo > 1) {
-      int mid = (lo + hi) >> 1;
-      if (s.pos[mid] <= p0) lo = mid; else hi = mid;
+  // phase 2: EDGES_PER_THREAD compacted edge positions per thread, in
+  // groups of RUN consecutive ones: group g of thread t starts at
+  // g * BLOCK * RUN + t * RUN, so a load instruction of a wavefront covers
+  // 64 * RUN consecutive positions and each thread keeps EDGES_PER_THREAD
+  // gathers in flight. A group finds its first position's vertex by binary
+  // search (monotone over the groups) and walks forward; runs of one vertex
+  // within a group are reduced in registers before one LDS atomic.
+  {
+    constexpr int EPT = EDGES_PER_THREAD;
+    constexpr int RUN = 2;
+    constexpr int G = EPT / RUN;
+    static_assert(EPT % RUN == 0, "groups of RUN positions");
+    int kk[EPT];
+    int32_t e[EPT];
+    int lo = 0;
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+      const int q0 = gi * BLOCK * RUN + tid * RUN;
+      int k = -1, next = 0;
+      if (q0 < At) {
+        int l = lo, h = Kt;  // pos[l] <= q0 < pos[h]
+        while (h - l > 1) {
+          const int mid = (l + h) >> 1;
+          if (s.pos[mid] <= q0) l = mid; else h = mid;
+        }
+        lo = l;
+        k = l;
+        next = s.pos[k + 1];
+      }
+#pragma unroll
+      for (int i = 0; i < RUN; ++i) {
+        const int q = q0 + i;
+        const int j = gi * RUN + i;
+        if (k >= 0 && q < At) {
+          while (q >= next) { ++k; next = s.pos[k + 1]; }
+          kk[j] = k;
+          e[j] = s.eb[k] + (q - s.pos[k]);
+        } else {
+          kk[j] = -1;
+          e[j] = 0;
+        }
+      }
     }
-    int kk[EDGES_PER_THREAD];
-    int32_t e[EDGES_PER_THREAD];
-    int k = lo;
-    int next = s.pos[k + 1];
+    if (tid * RUN < At) {
+      // unconditional loads: positions past the tile reread the thread's
+      // first edge (a real one, since its first position is below At)
 #pragma unroll
-    for (int j = 0; j < EDGES_PER_THREAD; ++j) {
-      const int q = p0 + j;
-      while (q >= next && k + 1 < Kt) { ++k; next = s.pos[k + 1]; }
-      kk[j] = q < At ? k : -1;
-      e[j] = s.eb[k] + (q - s.pos[k]);
-    }
-    // every load is issued unconditionally (positions past the tile reread
-    // the thread's first edge, which is real since p0 < At), so the
-    // EDGES_PER_THREAD edge-word loads and then the EDGES_PER_THREAD gathers
-    // are all in flight together instead of one masked load at a time
+      for (int j = 0; j < EPT; ++j) e[j] = kk[j] >= 0 ? e[j] : e[0];
+      uint32_t word[EPT];
 #pragma unroll
-    for (int j = 0; j < EDGES_PER_THREAD; ++j) e[j] = kk[j] >= 0 ? e[j] : e[0];
-    uint32_t word[EDGES_PER_THREAD];
+      for (int j = 0; j < EPT; ++j) word[j] = p.src[e[j]];
+      T x[EPT];
 #pragma unroll
-    for (int j = 0; j < EDGES_PER_THREAD; ++j) word[j] = p.src[e[j]];
-    T x[EDGES_PER_THREAD];
+      for (int j = 0; j < EPT; ++j) {
+        const uint32_t w = ALGO == A_SSSP ? weight_of<PACKED>(p, word[j], e[j]) : 0u;
+        const T y = R::edge(r, src_of<PACKED>(word[j]), w);
+        x[j] = kk[j] >= 0 ? y : R::identity();
+      }
 #pragma unroll
-    for (int j = 0; j < EDGES_PER_THREAD; ++j) {
-      const uint32_t w = ALGO == A_SSSP ? weight_of<PACKED>(p, word[j], e[j]) : 0u;
-      const T y = R::edge(r, src_of<PACKED>(word[j]), w);
-      x[j] = kk[j] >= 0 ? y : R::identity();
-    }
-    int ck = kk[0];
-    T cur = x[0];
+      for (int gi = 0; gi < G; ++gi) {
+        int ck = kk[gi * RUN];
+        T cur = x[gi * RUN];
 #pragma unroll
-    for (int j = 1; j < EDGES_PER_THREAD; ++j) {
-      if (kk[j] == ck) {
-        cur = R::combine(cur, x[j]);
-      } else {
+        for (int i = 1; i < RUN; ++i) {
+          const int j = gi * RUN + i;
+          if (kk[j] == ck) {
+            cur = R::combine(cur, x[j]);
+          } else {
+            if (ck >= 0) {
+              if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
+              else atomicMin(&s.acc[ck], cur);
+            }
+            ck = kk[j];
+            cur = x[j];
+          }
+        }
         if (ck >= 0) {
           if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
           else atomicMin(&s.acc[ck], cur);
         }
-        ck = kk[j];
-        cur = x[j];
       }
-    }
-    if (ck >= 0) {
-      if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
-      else atomicMin(&s.acc[ck], cur);
     }
   }
   __syncthreads();
@@ -831,25 +859,34 @@ __global__ void init_pr_kernel(float *rank, float *contrib, const float *inv_out
   contrib[v] = x * inv_outdeg[v];
 }
 
-// Gather-rate probe: the sweep's tiling (TILE_E words per block, EPT
-// consecutive words per thread, loads issued together) over a plain word
-// array, every word's value gathered and summed; one add per block.
+// Gather-rate probe: the sweep's tiling (TILE_E words per block; thread t
+// takes groups of 2 consecutive words starting at g * BLOCK * 2 + t * 2,
+// loads issued together) over a plain word array, every word's value
+// gathered and summed; one add per block.
 __global__ void __launch_bounds__(BLOCK) gather_probe_kernel(const uint32_t *src, int64_t m, uint32_t mask,
                                                              const uint32_t *val, int32_t n,
                                                              unsigned long long *sink) {
   constexpr int EPT = TILE_E / BLOCK;
+  constexpr int RUN = 2;
   __shared__ unsigned long long s[WAVES];
-  const int64_t p0 = (int64_t)blockIdx.x * TILE_E + (int64_t)threadIdx.x * EPT;
+  const int64_t b0 = (int64_t)blockIdx.x * TILE_E;
+  const int64_t first = b0 + (int64_t)threadIdx.x * RUN;
   unsigned long long acc = 0;
-  if (p0 < m) {
+  if (first < m) {
+    int64_t e[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int64_t q = b0 + (int64_t)(j / RUN) * (BLOCK * RUN) + (int64_t)threadIdx.x * RUN + (j % RUN);
+      e[j] = q < m ? q : -1;
+    }
     uint32_t w[EPT];
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) w[j] = src[p0 + j < m ? p0 + j : p0];
+    for (int j = 0; j < EPT; ++j) w[j] = src[e[j] >= 0 ? e[j] : first];
     uint32_t x[EPT];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) x[j] = val[min(w[j] & mask, (uint32_t)(n - 1))];
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) acc += p0 + j < m ? x[j] : 0u;
+    for (int j = 0; j < EPT; ++j) acc += e[j] >= 0 ? x[j] : 0u;
   }
 #pragma unroll
   for (int k = 32; k >= 1; k >>= 1) acc += shfl_xor(acc, k);
