@@ -243,12 +243,11 @@ __device__ inline void frontier_push(const Run &r, bool changed, int32_t v) {
 // One block per tile of consecutive vertices (<= TILE_V vertices, <= TILE_E
 // in-edges). Phase 1 gates the vertices (two consecutive ones per thread)
 // and compacts the attempting ones with a block-wide scan into LDS. Phase 2
-// assigns every thread TILE_E/256 consecutive positions of the compacted edge list
-// (merge-path style: one binary search, then a forward walk), so the in-edge
-// reads of a wavefront cover one contiguous range; the source loads and
-// gathers of a thread are independent, and runs of edges of the same vertex
-// are reduced in registers before one LDS atomic. Phase 3 runs the
-// epilogues.
+// gives every thread TILE_E/256 positions of the compacted edge list in
+// short groups of consecutive ones, so each load instruction of a wavefront
+// reads one contiguous range and a thread keeps all its gathers in flight;
+// runs of edges of the same vertex are reduced in registers before one LDS
+// atomic. Phase 3 runs the epilogues.
 
 struct TileLds {
   int32_t pos[TILE_V + 1];  // first compacted edge position of each attempting vertex
