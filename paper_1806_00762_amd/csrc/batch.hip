@@ -487,8 +487,10 @@ __global__ void __launch_bounds__(MI_CLOSE_THREADS) mi_close_kernel(MiArgs a) {
       in.dangling += dd;
       in.mass += dm;
       in.last_l1 = l1;
-      if (l1 < in.best_l1) { in.best_l1 = l1; in.no_improve = 0; }
-      else in.no_improve += 1;
+      // FP32 floor: an improvement is an L1 at least 10% below the best so far
+      const bool better = l1 < 0.9 * in.best_l1;
+      in.no_improve = better ? 0 : in.no_improve + 1;
+      in.best_l1 = better ? l1 : fmin(in.best_l1, l1);
       if (l1 < a.tol_l1) { done = true; in.stop_reason = 1; }
       else if (l1 < a.floor_cap && in.no_improve >= 3) { done = true; in.stop_reason = 2; }
     } else {

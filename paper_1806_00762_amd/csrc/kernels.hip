@@ -514,14 +514,15 @@ __device__ void close_pass(Ctl *c, SweepRecord *rec) {
     }
   } else {
     const double l1 = c->pass_l1;
+    // FP32 floor: a pass counts as an improvement only when its L1 falls at
+    // least 10% below the best so far (smaller steps are rounding noise)
+    const bool better = l1 < 0.9 * c->best_l1;
+    c->no_improve = better ? 0 : c->no_improve + 1;
+    c->best_l1 = better ? l1 : fmin(c->best_l1, l1);
     if (c->phase == 1) {
-      if (l1 < c->best_l1) { c->best_l1 = l1; c->no_improve = 0; }
-      else c->no_improve += 1;
       if (l1 < c->tol_l1) { c->done = 1; c->stop_reason = 1; }
       else if (l1 < c->floor_cap && c->no_improve >= 3) { c->done = 1; c->stop_reason = 2; }
     } else {
-      if (l1 < c->best_l1) { c->best_l1 = l1; c->no_improve = 0; }
-      else c->no_improve += 1;
       if (l1 < c->tol_l1 || (l1 < c->floor_cap && c->no_improve >= 3)) {
         c->phase = 1;
         c->best_l1 = 1e300;
