@@ -345,6 +345,39 @@ def bench_bfs_early_break(args, g, G):
     return out
 
 
+def bench_pagerank16(args):
+    """PageRank on R-MAT scale 16 (4 equal-byte pages, up to 4 sweeps per page
+    per pass, L1 < 1e-9, resident): no prediction, weak prediction, and weak
+    prediction with a change tolerance (updates below it count as failed
+    attempts: the data-driven form), each checked against the FP64 oracle."""
+    import graphgen
+    import oracle
+    import paper_1806_00762_amd as sr
+    g = graphgen.recipes.pagerank_s16()
+    ref, _, _ = oracle.pagerank(g, tol=1e-13)
+    ctx = sr.Context(0, 0)
+    G = ctx.load(g, reorder=args.order == "degree")
+    G.partition(4, 4)
+    out = {"workload": "pagerank_rmat16_ef16_4pages_inner4_tol1e-9", "n": g.n, "m": g.m}
+    for name, pvu, eps in (("off", "off", 0.0), ("weak", "weak", 0.0), ("weak_eps1e-9", "weak", 1e-9)):
+        kw = dict(pvu=pvu, pr_change_eps=eps, max_inner_iters=4, tol_l1=1e-9)
+        G.run("pagerank", **kw)
+        sync()
+        t0 = time.perf_counter()
+        sts = [G.run("pagerank", **kw) for _ in range(args.steps)]
+        sync()
+        el = (time.perf_counter() - t0) / args.steps
+        x = G.values().view(np.float32).astype(np.float64)
+        st = sts[-1]
+        out[name] = {"ms_per_solve": round(el * 1e3, 3), "solve_gteps": round(g.m / el / 1e9, 3),
+                     "edges_swept_gteps": round(g.m * st["sweeps"] / el / 1e9, 2),
+                     "sweeps": st["sweeps"], "vertex_pulls": st["vertices_attempted"],
+                     "max_abs": float(np.max(np.abs(x - ref))), "dtype": "f32"}
+    G.close()
+    ctx.close()
+    return out
+
+
 def bench_lattice(args):
     """Page skipping on a high-diameter graph with locality: SSSP from a corner
     of a 1024 x 1024 lattice (weights 1-9), pages streamed through 4 slots
@@ -588,7 +621,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (for HBM counter scaling)")
     ap.add_argument("--served-timeout", type=float, default=90.0)
-    ap.add_argument("--only", choices=["batched", "served", "lattice"],
+    ap.add_argument("--only", choices=["batched", "served", "lattice", "pagerank16"],
                     help="run one extra leg alone and print its JSON object")
     ap.add_argument("--copy-depth", type=int, default=2,
                     help="page copies kept in flight ahead of the window (1 = the paper's layout)")
@@ -612,11 +645,14 @@ def main():
         return
     if args.only:
         # one extra leg alone (for profiling it): its JSON object only
-        fn = {"batched": bench_batched, "served": bench_served, "lattice": bench_lattice}[args.only]
+        fn = {"batched": bench_batched, "served": bench_served, "lattice": bench_lattice,
+              "pagerank16": bench_pagerank16}[args.only]
         print(json.dumps(fn(args)), flush=True)
         return
     res = bench_sssp22(args)
     if not args.no_extras:
+        res["pagerank16"] = bench_pagerank16(args)
+        log(f"[bench] pagerank16: {res['pagerank16']}")
         res["lattice"] = bench_lattice(args)
         log(f"[bench] lattice: {res['lattice']}")
         res["batched"] = bench_batched(args)

@@ -190,3 +190,26 @@ def test_wide_weights_u32_path(sr, ctx):
     for s, x in zip(srcs, outs):
         assert np.array_equal(x, oracle.sssp(g, s))
     G.close()
+
+
+@pytest.mark.parametrize("eps", [1e-10, 1e-8])
+@pytest.mark.parametrize("sched", ["resident", "s3p3i4"])
+def test_pagerank_change_tolerance(sr, ctx, sched, eps):
+    """Data-driven PageRank: with weak prediction, updates smaller than
+    pr_change_eps count as failed attempts (vertices go dormant sooner); the
+    verification passes still bring the ranks to the fixed point."""
+    g = graph("rmat14w")
+    ref, _, _ = oracle.pagerank(g, tol=1e-13)
+    s = SCHEDULES[sched]
+    G = ctx.load(g)
+    try:
+        G.partition(s["parts"], s["slots"])
+        st = G.run("pagerank", pvu="weak", pr_change_eps=eps, force_stream=s["force"], max_inner_iters=s["inner"],
+                   max_passes=5000)
+        x = G.values().view(np.float32).astype(np.float64)
+        err = float(np.max(np.abs(x - ref)))
+        say(f"case pagerank eps={eps} {sched}: max-abs {err:.2e} sweeps {st['sweeps']}")
+        assert st["converged"] == 1
+        assert err <= PR_TOL
+    finally:
+        G.close()
