@@ -110,6 +110,7 @@ struct alignas(256) PageHeader {
   int32_t w_bytes;               // 4: separate u32 weight section; 0: none (unweighted or packed)
   int32_t tile_e;                // in-edge cap of a tile (TILE_E)
   int32_t packed;                // edge words carry the weight in their top byte
+  int32_t n_tiles_edges;         // tiles with at least one in-edge; they come first in the tile list
 };
 static_assert(sizeof(PageHeader) == 256, "page header is one 256-byte line");
 

@@ -494,7 +494,7 @@ struct Runner {
     for (size_t i = 0; i < pages.size(); ++i) {
       const PageHeader &h = g->pages[pages[i]].hdr;
       for (int sec = 0; sec < NSEC; ++sec) {
-        blk += sec_blocks(h, sec);
+        blk += sec_blocks(h, sec, algo == A_PR || algo == A_PPR);
         a.blk_prefix[i * NSEC + sec + 1] = blk;
       }
       a.base[i] = g->res.buf[slots[i]];

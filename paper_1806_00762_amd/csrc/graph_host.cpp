@@ -252,21 +252,29 @@ static void fill_page(const sr_graph *g, int32_t vb, int32_t ve, Page &pg) {
     bins[cur[b]++] = i;
   }
   {
+    // tiles with in-edges first, then the tiles of zero in-degree vertices
     int32_t *tl = (int32_t *)(buf + h.off_tiles);
+    std::vector<int32_t> empty;
     int32_t nt = 0, tv = 0, t0 = 0;
     int64_t te = 0;
     bool open = false;
+    auto close = [&](int32_t end) {
+      if (te > 0) { tl[2 * nt] = t0; tl[2 * nt + 1] = end; nt++; }
+      else { empty.push_back(t0); empty.push_back(end); }
+      open = false;
+    };
     for (int32_t i = 0; i < np; ++i) {
       int64_t d = g->in_off[vb + i + 1] - g->in_off[vb + i];
       if (d > HEAVY) {
-        if (open) { tl[2 * nt] = t0; tl[2 * nt + 1] = i; nt++; open = false; }
+        if (open) close(i);
         continue;
       }
-      if (open && (tv + 1 > TILE_V || te + d > h.tile_e)) { tl[2 * nt] = t0; tl[2 * nt + 1] = i; nt++; open = false; }
+      if (open && (tv + 1 > TILE_V || te + d > h.tile_e)) close(i);
       if (!open) { open = true; t0 = i; tv = 0; te = 0; }
       tv++; te += d;
     }
-    if (open) { tl[2 * nt] = t0; tl[2 * nt + 1] = np; nt++; }
+    if (open) close(np);
+    for (size_t k = 0; k < empty.size(); ++k) tl[2 * nt + k] = empty[k];
   }
   if (h.packed) {
     uint32_t *words = (uint32_t *)(buf + h.off_src);
@@ -311,18 +319,20 @@ static PageHeader page_header(const sr_graph *g, int32_t vb, int32_t ve) {
   h.off_offsets = o; o = align256(o + 4ull * ((uint64_t)h.n_p + 1));
   // tiles: greedy runs of consecutive non-heavy vertices
   {
-    int32_t nt = 0, tv = 0;
+    int32_t nt = 0, ne = 0, tv = 0;
     int64_t te = 0;
     bool open = false;
+    auto close = [&]() { nt++; ne += te > 0 ? 1 : 0; open = false; };
     for (int32_t v = vb; v < ve; ++v) {
       int64_t d = g->in_off[v + 1] - g->in_off[v];
-      if (d > HEAVY) { if (open) { nt++; open = false; } continue; }
-      if (open && (tv + 1 > TILE_V || te + d > h.tile_e)) { nt++; open = false; }
+      if (d > HEAVY) { if (open) close(); continue; }
+      if (open && (tv + 1 > TILE_V || te + d > h.tile_e)) close();
       if (!open) { open = true; tv = 0; te = 0; }
       tv++; te += d;
     }
-    if (open) nt++;
+    if (open) close();
     h.n_tiles = nt;
+    h.n_tiles_edges = ne;
   }
   h.off_tiles = o;   o = align256(o + 8ull * (uint64_t)h.n_tiles);
   h.off_chunks = o;  o = align256(o + sizeof(Chunk) * (uint64_t)chunks);

@@ -41,8 +41,10 @@ struct SweepArgs {
 };
 
 // Blocks a page needs for section sec (0: one per tile, 1: WAVES chunks each).
-inline int sec_blocks(const PageHeader &h, int sec) {
-  return sec == 0 ? h.n_tiles : (h.n_chunks + WAVES - 1) / WAVES;
+// Tiles of zero in-degree vertices only (listed last) matter to PageRank
+// alone: the min programs never pull such a vertex.
+inline int sec_blocks(const PageHeader &h, int sec, bool all_tiles) {
+  return sec == 0 ? (all_tiles ? h.n_tiles : h.n_tiles_edges) : (h.n_chunks + WAVES - 1) / WAVES;
 }
 
 // the sweep kernel, then the kernel that closes the sweep; `mid` (optional)
