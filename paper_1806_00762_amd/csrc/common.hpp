@@ -82,9 +82,10 @@ static_assert(sizeof(Stripe) == 128, "one stripe per 128-byte line");
 
 // First 256 bytes of every page buffer. Section offsets are in bytes from
 // the buffer start, all multiples of 256. Sections are ordered so that each
-// use copies a prefix: header, offsets, tiles, chunks, heavy list, sources
-// (unweighted programs stop here), weights (single-instance sweeps stop
-// here), degree-bin lists (multi-instance sweeps).
+// use copies a prefix: header, tiles, chunks, heavy list, sources, offsets
+// (unweighted programs stop here; a min program that reads no separate
+// weights stops at bytes_lead, inside the offsets), weights (single-instance
+// sweeps stop here), degree-bin lists (multi-instance sweeps).
 constexpr uint32_t PACKED_SRC_MASK = 0x00FFFFFFu;  // source id bits of a packed edge word
 struct alignas(256) PageHeader {
   uint32_t magic;
@@ -102,6 +103,8 @@ struct alignas(256) PageHeader {
   uint64_t bytes_unweighted;  // prefix a program without weights needs
   uint64_t bytes_weighted;    // prefix with weights (single-instance sweeps)
   uint64_t bytes_total;       // everything, bin lists of the multi-instance sweep included
+  uint64_t bytes_lead;        // prefix a min program without weights reads (offsets up to the last
+                              // vertex of a tile with in-edges or of a heavy vertex)
   int32_t bin_count[NBINS];      // bin 7: number of chunks
   int32_t bin_start[NBINS];      // start of bin b in the bins section (not bin 7)
   int32_t n_heavy;               // vertices in bin 7

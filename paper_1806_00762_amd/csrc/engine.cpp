@@ -917,7 +917,11 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     auto copy_page = [&](int32_t page, int32_t slot, bool wait_prev) -> sr_status {
       if (wait_prev) HIP_TRY(c, hipStreamWaitEvent(c->copy, step_done, 0), "copy wait");
       hipEvent_t a = R.ev(), b = R.ev();
-      uint64_t nb = need_bytes(g->pages[page], R.weights);
+      // a min program that reads no separate weights stops at the last
+      // offset it reads (PageRank also rewrites zero in-degree vertices)
+      const PageHeader &ph = g->pages[page].hdr;
+      const bool lead = !pr && (!R.weights || ph.w_bytes == 0);
+      uint64_t nb = lead ? ph.bytes_lead : need_bytes(g->pages[page], R.weights);
       if (a) (void)hipEventRecord(a, c->copy);
       HIP_TRY(c, hipMemcpyAsync(g->res.buf[slot], g->pages[page].host, nb, hipMemcpyHostToDevice, c->copy),
               "page copy");

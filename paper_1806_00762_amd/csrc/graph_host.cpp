@@ -316,21 +316,27 @@ static PageHeader page_header(const sr_graph *g, int32_t vb, int32_t ve) {
   h.w_bytes = g->weighted && !g->packed ? 4 : 0;
   h.tile_e = TILE_E;
   uint64_t o = sizeof(PageHeader);
-  h.off_offsets = o; o = align256(o + 4ull * ((uint64_t)h.n_p + 1));
-  // tiles: greedy runs of consecutive non-heavy vertices
+  // tiles: greedy runs of consecutive non-heavy vertices; `lead` counts the
+  // leading vertices whose offsets the min programs read (every vertex of a
+  // tile with in-edges, every heavy vertex)
+  int32_t lead = 0;
   {
     int32_t nt = 0, ne = 0, tv = 0;
     int64_t te = 0;
     bool open = false;
-    auto close = [&]() { nt++; ne += te > 0 ? 1 : 0; open = false; };
+    auto close = [&](int32_t end) {
+      nt++;
+      if (te > 0) { ne++; lead = std::max(lead, end - vb); }
+      open = false;
+    };
     for (int32_t v = vb; v < ve; ++v) {
       int64_t d = g->in_off[v + 1] - g->in_off[v];
-      if (d > HEAVY) { if (open) close(); continue; }
-      if (open && (tv + 1 > TILE_V || te + d > h.tile_e)) close();
+      if (d > HEAVY) { if (open) close(v); lead = std::max(lead, v + 1 - vb); continue; }
+      if (open && (tv + 1 > TILE_V || te + d > h.tile_e)) close(v);
       if (!open) { open = true; tv = 0; te = 0; }
       tv++; te += d;
     }
-    if (open) close();
+    if (open) close(ve);
     h.n_tiles = nt;
     h.n_tiles_edges = ne;
   }
@@ -338,6 +344,11 @@ static PageHeader page_header(const sr_graph *g, int32_t vb, int32_t ve) {
   h.off_chunks = o;  o = align256(o + sizeof(Chunk) * (uint64_t)chunks);
   h.off_heavy = o;   o = align256(o + sizeof(Heavy) * (uint64_t)heavy);
   h.off_src = o;     o = align256(o + 4ull * (uint64_t)h.m_p);
+  // offsets after the edge words, so a min program's prefix can end at the
+  // last vertex it reads (zero in-degree vertices gather up at the end of
+  // the order under degree numbering)
+  h.off_offsets = o; o = align256(o + 4ull * ((uint64_t)h.n_p + 1));
+  h.bytes_lead = h.off_offsets + 4ull * ((uint64_t)lead + 1);
   h.bytes_unweighted = o;
   h.off_w = o;
   o = align256(o + (uint64_t)h.w_bytes * (uint64_t)h.m_p);
