@@ -77,7 +77,7 @@ def bench_sssp22(args):
     log(f"[bench] loaded+partitioned in {time.perf_counter() - t:.1f}s: {info['num_parts']} pages, "
         f"budget {budget / 1e6:.1f} MB, graph {gbytes / 1e6:.1f} MB")
     run_kw = dict(source=0, pvu=args.pvu, max_inner_iters=args.inner, force_stream=True,
-                  copy_depth=args.copy_depth)
+                  copy_depth=args.copy_depth, wide_pages=args.wide_pages)
     for i in range(args.warmup):
         st = G.run("sssp", **run_kw)
         log(f"[bench] warmup {i}: {st['wall_ms']:.1f} ms, passes {st['passes']}")
@@ -99,6 +99,7 @@ def bench_sssp22(args):
     h2d_bytes = sum(s["h2d_bytes"] for s in stats)
     h2d_ms = sum(s["h2d_ms"] for s in stats)
     scanned = sum(s["edges_scanned"] for s in stats)
+    narrow = sum(s["edges_narrow"] for s in stats)
     # the sweep kernel alone moves the algorithmic bytes (events on its stream
     # around it; the one-block close kernel after it is reported separately)
     achieved = algo_bytes / (sweep_ms * 1e-3) / 1e9
@@ -121,7 +122,9 @@ def bench_sssp22(args):
                    "device_budget_bytes": budget, "graph_bytes": gbytes,
                    "pvu": args.pvu, "max_inner_iters": args.inner, "copy_depth": args.copy_depth,
                    "vertex_order": "in-degree descending (results in input ids)" if args.order == "degree"
-                   else "input"},
+                   else "input",
+                   "page_image": "full-width" if args.wide_pages else "split-width",
+                   "narrow_edge_frac": round(narrow / max(scanned, 1), 4)},
         "roofline": {"bound": "hbm", "kernel": "sweep_kernel<SSSP>",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -629,6 +632,8 @@ def main():
     ap.add_argument("--order", choices=["degree", "input"], default="degree",
                     help="internal vertex numbering of the headline graph (results are in input ids)")
     ap.add_argument("--no-hetero", action="store_true", help="skip the host sparse stage leg")
+    ap.add_argument("--wide-pages", action="store_true",
+                    help="stream full-width pages instead of split-width images")
     ap.add_argument("--ablation", action="store_true",
                     help="also time the Section 5.4 schedules (baseline, re-entry, pipelined, +predictors)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,

@@ -91,6 +91,18 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
                                      Table I, sets level k + 1 without reading the other in-edges
                                      (the dense-pull early break of Section 5.5, RQ4); this flag
                                      turns it off (results are identical either way) */
+#define SR_RUN_WIDE_PAGES 0x80u   /* streamed BFS/SSSP/CC copy split-width page images by default:
+                                     in-edges from source ids below 2^16 stored as u16 ids (u8
+                                     weights) ahead of the others, so fewer bytes cross the host
+                                     link per page (Section 3.1's streamed pages; built once, in
+                                     pinned memory, on the first such run, and used when each image
+                                     fits a slot and all of them are smaller than the full-width
+                                     pages); this flag copies the full-width pages instead
+                                     (results are identical either way) */
+#define SR_RUN_SPLIT_PAGES 0x100u /* copy the split-width images even when they are not smaller
+                                     (SR_EINVAL for PageRank, resident graphs, graphs whose edge
+                                     words are not packed, or together with SR_RUN_WIDE_PAGES;
+                                     SR_EBUDGET when an image exceeds a slot) */
 
 /* stop reasons reported in sr_run_stats.stop_reason */
 #define SR_STOP_CONVERGED 1   /* min programs: a full pass changed nothing (with weak prediction,
@@ -246,6 +258,8 @@ typedef struct {
   int64_t pages_skipped;     /* SR_RUN_SKIP_CLEAN: page visits left out because no in-edge changed */
   double sweep_kernel_ms;    /* the part of kernel_ms spent in the sweep kernels alone (without the
                                 kernels that close each sweep) */
+  int64_t edges_narrow;      /* of edges_scanned, those read as u16 ids from split-width pages (0 when
+                                the run copied full-width pages) */
 } sr_run_stats;
 
 /* Run a vertex program to convergence on the graph (partitioned with

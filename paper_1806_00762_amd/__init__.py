@@ -29,6 +29,8 @@ SR_LOAD_REORDER = 0x4
 SR_RUN_AUDIT_PVU, SR_RUN_FORCE_STREAM, SR_RUN_RESUME, SR_RUN_FIXED_INNER, SR_RUN_HETERO = 0x1, 0x2, 0x4, 0x8, 0x10
 SR_RUN_SKIP_CLEAN = 0x20
 SR_RUN_NO_EARLY_BREAK = 0x40
+SR_RUN_WIDE_PAGES = 0x80
+SR_RUN_SPLIT_PAGES = 0x100
 SR_STOP_CONVERGED, SR_STOP_FP32_FLOOR, SR_STOP_MAX_PASSES = 1, 2, 3
 SR_INF = 0xFFFFFFFF
 
@@ -79,7 +81,8 @@ class sr_run_stats(ctypes.Structure):
                 ("algo_bytes", ctypes.c_uint64), ("sparse_stage", ctypes.c_int32),
                 ("sparse_rounds", ctypes.c_int32), ("sparse_frontier", ctypes.c_int64),
                 ("sparse_relaxations", ctypes.c_int64), ("sparse_ms", ctypes.c_double),
-                ("pages_skipped", ctypes.c_int64), ("sweep_kernel_ms", ctypes.c_double)]
+                ("pages_skipped", ctypes.c_int64), ("sweep_kernel_ms", ctypes.c_double),
+                ("edges_narrow", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -297,7 +300,7 @@ class Graph:
             pr_change_eps: float = 0.0, audit: bool = False, force_stream: bool = False,
             resume: bool = False, fixed_inner: bool = False, copy_depth: int = 0, hetero: bool = False,
             sparse_switch: int = 0, skip_clean: bool = False, early_break: bool = True,
-            check: bool = True) -> dict:
+            wide_pages: bool = False, split_pages: bool = False, check: bool = True) -> dict:
         p = sr_run_params()
         p.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
         p.source = source
@@ -311,7 +314,8 @@ class Graph:
         p.flags = ((SR_RUN_AUDIT_PVU if audit else 0) | (SR_RUN_FORCE_STREAM if force_stream else 0)
                    | (SR_RUN_RESUME if resume else 0) | (SR_RUN_FIXED_INNER if fixed_inner else 0)
                    | (SR_RUN_HETERO if hetero else 0) | (SR_RUN_SKIP_CLEAN if skip_clean else 0)
-                   | (0 if early_break else SR_RUN_NO_EARLY_BREAK))
+                   | (0 if early_break else SR_RUN_NO_EARLY_BREAK)
+                   | (SR_RUN_WIDE_PAGES if wide_pages else 0) | (SR_RUN_SPLIT_PAGES if split_pages else 0))
         p.copy_depth = copy_depth
         p.sparse_switch = sparse_switch
         st = sr_run_stats()

@@ -75,6 +75,7 @@ struct alignas(128) Stripe {
   unsigned long long l1;       // PageRank: sum |delta|, fixed point
   unsigned long long dd;       // PageRank: dangling-mass change, two's complement fixed point
   unsigned long long dm;       // PageRank: change of the rank sum (mass), two's complement fixed point
+  unsigned long long narrow;   // split images: scanned edges read from the narrow section
   unsigned long long hist[4];  // weak predictor states, two 32-bit counts per word
   uint32_t min_changed;        // smallest new value among changed vertices (min programs)
 };
@@ -114,8 +115,20 @@ struct alignas(256) PageHeader {
   int32_t tile_e;                // in-edge cap of a tile (TILE_E)
   int32_t packed;                // edge words carry the weight in their top byte
   int32_t n_tiles_edges;         // tiles with at least one in-edge; they come first in the tile list
+  // Split-width image (split = 1), streamed to the min programs: each
+  // vertex's in-edges from sources below 2^16 ("narrow": a u16 id and, for
+  // weighted graphs, a u8 weight) come apart from the others ("wide": the
+  // usual edge words, at off_src). off_hoff holds, per vertex, the narrow
+  // edges before it; the wide ones before vertex i are offsets[i] - hoff[i].
+  // Layout: header | tiles | chunks | heavy | hoff | narrow ids | wide words |
+  // narrow weights (off_w) | offsets, every section up to the last vertex
+  // the min programs read; bytes_lead is the whole image.
+  int32_t split;
+  uint64_t off_hoff;             // int32 narrow-edge prefix per vertex
+  uint64_t off_hsrc;             // u16 narrow source ids
 };
 static_assert(sizeof(PageHeader) == 256, "page header is one 256-byte line");
+constexpr uint32_t NARROW_LIMIT = 1u << 16;  // narrow source ids are below this
 
 enum Algo : int32_t { A_BFS = 0, A_SSSP = 1, A_CC = 2, A_PR = 3, A_PPR = 4 };
 enum Pvu : int32_t { P_OFF = 0, P_STRONG = 1, P_WEAK = 2 };
@@ -145,6 +158,8 @@ struct alignas(16) SweepRecord {
   uint64_t hist[8];
   double dangling;        // PageRank dangling mass after the sweep
   double pass_l1_closed;  // L1 of the pass closed by this sweep (if any)
+  uint64_t edges_narrow;  // scanned edges read from the narrow section of split images
+  uint64_t pad_;
 };
 static_assert(sizeof(SweepRecord) % 16 == 0, "record copied in 16-byte words");
 

@@ -341,11 +341,14 @@ struct Launch {
 // in-edge the edge word, a separate u32 weight when the page is not packed
 // (SSSP), and the gathered value; per changed vertex the value write;
 // PageRank also writes rank and contrib and reads 1/outdeg per attempted
-// vertex.
-uint64_t algo_bytes(int algo, int pvu, bool sep_weights, const SweepRecord &r) {
+// vertex. On split-width pages an edge read from the narrow section costs
+// its u16 id (and the u8 weight for SSSP) instead of the u32 word, and each
+// visited vertex reads its narrow-prefix offset too.
+uint64_t algo_bytes(int algo, int pvu, bool sep_weights, bool split, const SweepRecord &r) {
   const uint64_t visited = r.attempted + r.skipped;
   const uint64_t eb = (algo == A_SSSP && sep_weights) ? 12 : 8;
   uint64_t b = r.edges * eb + visited * 8;
+  if (split) b = b + visited * 4 - r.edges_narrow * (algo == A_SSSP ? 1 : 2);
   if (pvu == P_WEAK) b += visited * 2;
   if (algo == A_PR || algo == A_PPR) b += r.attempted * 12;
   else b += r.changed * 4;
@@ -377,6 +380,7 @@ struct Runner {
   sr_run_params prm;
   Diagram dia;
   bool weights;
+  bool split = false;  // the slots receive split-width page images
   sr_run_stats st{};
   uint64_t seq_next = 0;  // next expected sweep record
   uint64_t cur_pass_changed = 0;            // vertices changed so far in the open pass
@@ -441,7 +445,8 @@ struct Runner {
       st.vertices_skipped += (int64_t)r.skipped;
       st.mispredicted += (int64_t)r.mispred;
       for (int i = 0; i < 8; ++i) st.state_hist[i] += (int64_t)r.hist[i];
-      st.algo_bytes += algo_bytes(algo, pvu, g->weighted && !g->packed, r);
+      st.algo_bytes += algo_bytes(algo, pvu, g->weighted && !g->packed, split, r);
+      st.edges_narrow += (int64_t)r.edges_narrow;
       cur_pass_changed += r.changed;
       if (r.pass_l1_closed >= 0.0) {
         last_pass_changed = cur_pass_changed;
@@ -509,6 +514,7 @@ struct Runner {
     // the masked decode also serves unweighted graphs whose ids fit 24 bits
     // (it needs fewer registers than the plain one)
     a.packed = (g->weighted ? g->packed : (int64_t)g->n <= ((int64_t)1 << 24)) ? 1 : 0;
+    a.split = split ? 1 : 0;
     return SR_OK;
   }
 
@@ -549,10 +555,10 @@ static sr_status ensure_state(sr_graph *g, int algo) {
 }
 
 // Make the pages resident (all of them) or allocate the streaming slots.
-sr_status sr::ensure_residency(sr_graph *g, bool weights, bool force_stream, bool bins) {
+sr_status sr::ensure_residency(sr_graph *g, bool weights, bool force_stream, bool bins, uint64_t min_slot) {
   sr_ctx *c = g->ctx;
   auto &r = g->res;
-  uint64_t all = 0, mx = 0, smx = 0;
+  uint64_t all = 0, mx = min_slot, smx = 0;
   for (auto &p : g->pages) {
     all += need_bytes(p, weights, bins) + scratch_bytes(p);
     mx = std::max(mx, need_bytes(p, weights, bins));
@@ -636,7 +642,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (p.max_inner_iters == 0) p.max_inner_iters = 4;
   if (p.max_passes < 0 || p.max_inner_iters < 0) return c->fail(SR_EINVAL, "negative limits");
   if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_FORCE_STREAM | SR_RUN_RESUME | SR_RUN_FIXED_INNER | SR_RUN_HETERO |
-                  SR_RUN_SKIP_CLEAN | SR_RUN_NO_EARLY_BREAK))
+                  SR_RUN_SKIP_CLEAN | SR_RUN_NO_EARLY_BREAK | SR_RUN_WIDE_PAGES | SR_RUN_SPLIT_PAGES))
     return c->fail(SR_EINVAL, "unknown run flags");
   const bool pr = R.algo == A_PR || R.algo == A_PPR;
   // defaults (Section 4.3 discussion): BFS/CC strong, SSSP/PageRank weak;
@@ -670,10 +676,25 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     return c->fail(SR_ESTATE, "nothing to resume for this algorithm");
 
   sr_status s;
+  if ((p.flags & SR_RUN_WIDE_PAGES) && (p.flags & SR_RUN_SPLIT_PAGES))
+    return c->fail(SR_EINVAL, "SR_RUN_WIDE_PAGES and SR_RUN_SPLIT_PAGES exclude each other");
+  const bool force_split = (p.flags & SR_RUN_SPLIT_PAGES) != 0;
+  if (force_split && (pr || !sr::split_eligible(g)))
+    return c->fail(SR_EINVAL, "split-width pages serve streamed BFS/SSSP/CC on graphs with packed edge words");
   if (g->pages.empty())
     if ((s = sr_graph_partition(g, 0, 0)) != SR_OK) return s;
   if ((s = ensure_state(g, R.algo)) != SR_OK) return s;
-  s = ensure_residency(g, R.weights, (p.flags & SR_RUN_FORCE_STREAM) != 0);
+  // forced split-width images: the slots are sized to hold them too
+  auto residency = [&]() -> sr_status {
+    uint64_t min_slot = 0;
+    if (force_split) {
+      sr_status b = sr::build_split_pages(g);
+      if (b != SR_OK) return b;
+      for (auto &pg : g->pages) min_slot = std::max(min_slot, pg.shdr.bytes_lead);
+    }
+    return ensure_residency(g, R.weights, (p.flags & SR_RUN_FORCE_STREAM) != 0, false, min_slot);
+  };
+  s = residency();
   if (s == SR_EBUDGET && g->auto_parts) {
     // pages sized for a min program do not fit next to this state: recut
     uint64_t st_b = state_bytes(g->n, R.algo);
@@ -681,7 +702,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       for (int32_t P = (int32_t)g->pages.size() * 2; P <= g->n && s == SR_EBUDGET; P *= 2) {
         release_residency(g);
         if ((s = sr::make_pages(g, P)) != SR_OK) return s;
-        s = ensure_residency(g, R.weights, (p.flags & SR_RUN_FORCE_STREAM) != 0);
+        s = residency();
       }
     }
   }
@@ -733,6 +754,23 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   }
   if (!g->res.resident && (depth < 1 || depth >= g->res.nslots))
     return c->fail(SR_EINVAL, "copy_depth must be in [1, num_slots)");
+  // streamed min programs copy split-width images when every one fits a slot
+  // and together they are smaller than the full-width prefixes they replace
+  if (force_split && g->res.resident)
+    return c->fail(SR_EINVAL, "split-width pages serve streamed runs; this graph is resident");
+  if (!pr && !g->res.resident && !(p.flags & SR_RUN_WIDE_PAGES) && sr::split_eligible(g)) {
+    if ((s = sr::build_split_pages(g)) != SR_OK) return s;
+    uint64_t wide = 0, narrow = 0, mx = 0;
+    for (auto &pg : g->pages) {
+      const bool lead = !R.weights || pg.hdr.w_bytes == 0;
+      wide += lead ? pg.hdr.bytes_lead : need_bytes(pg, R.weights);
+      narrow += pg.shdr.bytes_lead;
+      mx = std::max(mx, pg.shdr.bytes_lead);
+    }
+    if (force_split && mx > g->res.slot_bytes)
+      return c->fail(SR_EBUDGET, "a split-width page image is larger than a slot");
+    R.split = mx <= g->res.slot_bytes && (force_split || narrow < wide);
+  }
 
   // initial values, predictor states and control block
   RunState &rs = g->state;
@@ -922,9 +960,10 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       const PageHeader &ph = g->pages[page].hdr;
       const bool lead = !pr && (!R.weights || ph.w_bytes == 0);
       uint64_t nb = lead ? ph.bytes_lead : need_bytes(g->pages[page], R.weights);
+      const char *src = g->pages[page].host;
+      if (R.split) { nb = g->pages[page].shdr.bytes_lead; src = g->pages[page].split; }
       if (a) (void)hipEventRecord(a, c->copy);
-      HIP_TRY(c, hipMemcpyAsync(g->res.buf[slot], g->pages[page].host, nb, hipMemcpyHostToDevice, c->copy),
-              "page copy");
+      HIP_TRY(c, hipMemcpyAsync(g->res.buf[slot], src, nb, hipMemcpyHostToDevice, c->copy), "page copy");
       if (b) (void)hipEventRecord(b, c->copy);
       R.track(a, b, true);
       HIP_TRY(c, hipEventRecord(copy_done[slot], c->copy), "copy event");

@@ -20,6 +20,9 @@ struct Page {
   char *host = nullptr;     // pinned (device context) or aligned malloc (host-only)
   uint64_t bytes = 0;
   PageHeader hdr{};
+  // split-width image for streamed min programs (built on first use)
+  char *split = nullptr;
+  PageHeader shdr{};
 };
 
 // Per-run device state; kept after a run so values can be read back and a
@@ -129,6 +132,10 @@ void relabel_by_degree(int32_t n, const int64_t *ro, const int32_t *ci, const ui
                        std::vector<int32_t> &rank, std::vector<int32_t> &perm, std::vector<int64_t> &ro2,
                        std::vector<int32_t> &ci2, std::vector<uint32_t> &w2);
 sr_status make_pages(sr_graph *g, int32_t nparts);
+// split-width images of every page (PageHeader::split), for streamed min
+// programs; built once per partition
+bool split_eligible(const sr_graph *g);
+sr_status build_split_pages(sr_graph *g);
 // Smallest page count whose largest streamed page (with its chunk scratch)
 // fits slot_bytes; -1 if none does.
 int32_t auto_parts(const sr_graph *g, uint64_t slot_bytes);
@@ -143,6 +150,8 @@ uint64_t frontier_pages(const sr_graph *g, const uint32_t *front, int64_t nf);
 int64_t sparse_push(sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
                     int32_t *rounds);
 // engine.cpp
-sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream, bool bins = false);
+// min_slot: streaming slots hold at least this many bytes (forced split-width images)
+sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream, bool bins = false,
+                           uint64_t min_slot = 0);
 void release_residency(sr_graph *g);
 }  // namespace sr

@@ -209,8 +209,90 @@ static void free_page_buffer(sr_ctx *ctx, char *p) {
 }
 
 void free_pages(sr_graph *g) {
-  for (auto &p : g->pages) free_page_buffer(g->ctx, p.host);
+  for (auto &p : g->pages) {
+    free_page_buffer(g->ctx, p.host);
+    free_page_buffer(g->ctx, p.split);
+  }
   g->pages.clear();
+}
+
+bool split_eligible(const sr_graph *g) {
+  return g->weighted ? g->packed : (int64_t)g->n <= ((int64_t)1 << 24);
+}
+
+// Split-width image of one page (see PageHeader): the sections the min
+// programs read, with each vertex's in-edges from sources below
+// NARROW_LIMIT stored as u16 ids (and u8 weights) ahead of the others.
+static sr_status split_page(sr_graph *g, Page &pg) {
+  const PageHeader &h = pg.hdr;
+  const int32_t vb = h.v_begin;
+  const int64_t eb = g->in_off[vb];
+  const int32_t lead = (int32_t)((h.bytes_lead - h.off_offsets) / 4) - 1;
+  int64_t mh = 0;
+  for (int64_t e = eb; e < g->in_off[vb + lead]; ++e) mh += (uint32_t)g->in_src[e] < NARROW_LIMIT;
+  const int64_t mt = (g->in_off[vb + lead] - eb) - mh;
+  PageHeader s = h;
+  s.split = 1;
+  uint64_t o = sizeof(PageHeader);
+  s.off_tiles = o;   o = align256(o + 8ull * (uint64_t)h.n_tiles);
+  s.off_chunks = o;  o = align256(o + sizeof(Chunk) * (uint64_t)h.n_chunks);
+  s.off_heavy = o;   o = align256(o + sizeof(Heavy) * (uint64_t)h.n_heavy);
+  s.off_hoff = o;    o = align256(o + 4ull * ((uint64_t)lead + 1));
+  s.off_hsrc = o;    o = align256(o + 2ull * (uint64_t)mh);
+  s.off_src = o;     o = align256(o + 4ull * (uint64_t)mt);
+  s.off_w = o;       o = align256(o + (g->weighted ? (uint64_t)mh : 0ull));
+  s.off_offsets = o; o = o + 4ull * ((uint64_t)lead + 1);
+  s.off_bins = 0;
+  s.bytes_lead = s.bytes_unweighted = s.bytes_weighted = s.bytes_total = o;
+  s.w_bytes = 0;
+  char *buf = alloc_page_buffer(g->ctx, align256(o));
+  if (!buf) return SR_ENOMEM;
+  std::memcpy(buf + s.off_tiles, pg.host + h.off_tiles, 8ull * (uint64_t)h.n_tiles);
+  std::memcpy(buf + s.off_chunks, pg.host + h.off_chunks, sizeof(Chunk) * (uint64_t)h.n_chunks);
+  std::memcpy(buf + s.off_heavy, pg.host + h.off_heavy, sizeof(Heavy) * (uint64_t)h.n_heavy);
+  std::memcpy(buf + s.off_offsets, pg.host + h.off_offsets, 4ull * ((uint64_t)lead + 1));
+  int32_t *hoff = (int32_t *)(buf + s.off_hoff);
+  uint16_t *hsrc = (uint16_t *)(buf + s.off_hsrc);
+  uint32_t *words = (uint32_t *)(buf + s.off_src);
+  uint8_t *hw = (uint8_t *)(buf + s.off_w);
+  int64_t nh = 0, nt = 0;
+  for (int32_t i = 0; i < lead; ++i) {
+    hoff[i] = (int32_t)nh;
+    for (int64_t e = g->in_off[vb + i]; e < g->in_off[vb + i + 1]; ++e) {
+      const uint32_t u = (uint32_t)g->in_src[e];
+      const uint32_t w = g->weighted ? g->in_w[e] : 0u;
+      if (u < NARROW_LIMIT) {
+        hsrc[nh] = (uint16_t)u;
+        if (g->weighted) hw[nh] = (uint8_t)w;
+        nh++;
+      } else {
+        words[nt++] = u | (g->weighted ? w << 24 : 0u);
+      }
+    }
+  }
+  hoff[lead] = (int32_t)nh;
+  std::memcpy(buf, &s, sizeof(PageHeader));
+  pg.split = buf;
+  pg.shdr = s;
+  return SR_OK;
+}
+
+sr_status build_split_pages(sr_graph *g) {
+  if (!g->pages.empty() && g->pages[0].split) return SR_OK;
+  if (!split_eligible(g)) return g->ctx->fail(SR_EINVAL, "graph has no split-width pages");
+  const int32_t P = (int32_t)g->pages.size();
+  std::vector<sr_status> st((size_t)P, SR_OK);
+  const int T = std::min<int>(host_threads(), std::max<int32_t>(P, 1));
+  parallel_for(P, T > 0 ? T : 1, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t p = lo; p < hi; ++p) st[p] = split_page(g, g->pages[p]);
+  }, 1);
+  for (int32_t p = 0; p < P; ++p) {
+    if (st[p] != SR_OK) {
+      for (auto &pg : g->pages) { free_page_buffer(g->ctx, pg.split); pg.split = nullptr; }
+      return g->ctx->fail(SR_ENOMEM, "split page allocation failed");
+    }
+  }
+  return SR_OK;
 }
 
 // Fill one page buffer for destination range [vb, ve).

@@ -60,6 +60,9 @@ struct PageCtx {
   const Chunk *chunks;
   const uint32_t *src;       // edge words: source id, or source | weight << 24 when packed
   const uint32_t *w;         // separate u32 weights (unpacked weighted pages)
+  const int32_t *hoff;       // split images: narrow edges before each vertex
+  const uint16_t *hsrc;      // split images: narrow source ids
+  const uint8_t *hw;         // split images: narrow weights
   int32_t bin_count, bin_start;
   unsigned long long *partial;  // heavy-vertex accumulators, at each vertex's first chunk
 };
@@ -67,6 +70,7 @@ struct PageCtx {
 // Thread-local sweep counters, reduced per block at the end.
 struct Acc {
   uint32_t changed = 0, attempted = 0, skipped = 0, mispred = 0, edges = 0;
+  uint32_t narrow = 0;  // scanned edges read from the narrow section of a split image
   uint32_t min_changed = INF;
   double l1 = 0.0, ddelta = 0.0, dmass = 0.0;
 };
@@ -250,25 +254,131 @@ __device__ inline void frontier_push(const Run &r, bool changed, int32_t v) {
 // atomic. Phase 3 runs the epilogues.
 
 struct TileLds {
-  int32_t pos[TILE_V + 1];  // first compacted edge position of each attempting vertex
-  int32_t eb[TILE_V];       // its first in-edge (page-local)
+  int32_t pos[TILE_V + 1];  // first compacted (wide) edge position of each attempting vertex
+  int32_t eb[TILE_V];       // its first (wide) in-edge (page-local)
+  int32_t pos_n[TILE_V + 1];  // split images: first compacted narrow edge position
+  int32_t eb_n[TILE_V];       // split images: its first narrow edge
   int32_t vl[TILE_V];       // its page-local vertex id
   uint32_t acc[TILE_V];     // reduction (u32 min, or f32 sum bits)
   uint32_t old[TILE_V];
   uint8_t att[TILE_V];
   uint8_t st[TILE_V];
-  int32_t wsum[WAVES][2];
+  int32_t wsum[WAVES][3];
 };
 
-template <int ALGO, int EDGES_PER_THREAD, bool PACKED>
-__device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, TileLds &s) {
+// Phase 2 of a tile over one compacted edge list (pos/base in LDS, At
+// positions, Kt vertices): EDGES_PER_THREAD positions per thread, in groups
+// of RUN consecutive ones; group g of thread t starts at g * BLOCK * RUN +
+// t * RUN, so a load instruction of a wavefront covers 64 * RUN consecutive
+// positions and each thread keeps EDGES_PER_THREAD gathers in flight. A
+// group finds its first position's vertex by binary search (monotone over
+// the groups) and walks forward; runs of one vertex within a group are
+// reduced in registers before one LDS atomic. NARROW: u16 ids (and u8
+// weights) of a split image; else edge words.
+template <int ALGO, int EPT, bool PACKED, bool NARROW>
+__device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds &s, const int32_t *pos,
+                                   const int32_t *base, int At, int Kt) {
   using R = Red<ALGO>;
   using T = typename R::T;
+  const int tid = threadIdx.x;
+  constexpr int RUN = 2;
+  constexpr int G = EPT / RUN;
+  static_assert(EPT % RUN == 0, "groups of RUN positions");
+  int kk[EPT];
+  int32_t e[EPT];
+  int lo = 0;
+#pragma unroll
+  for (int gi = 0; gi < G; ++gi) {
+    const int q0 = gi * BLOCK * RUN + tid * RUN;
+    int k = -1, next = 0;
+    if (q0 < At) {
+      int l = lo, h = Kt;  // pos[l] <= q0 < pos[h]
+      while (h - l > 1) {
+        const int mid = (l + h) >> 1;
+        if (pos[mid] <= q0) l = mid; else h = mid;
+      }
+      lo = l;
+      k = l;
+      next = pos[k + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < RUN; ++i) {
+      const int q = q0 + i;
+      const int j = gi * RUN + i;
+      if (k >= 0 && q < At) {
+        while (q >= next) { ++k; next = pos[k + 1]; }
+        kk[j] = k;
+        e[j] = base[k] + (q - pos[k]);
+      } else {
+        kk[j] = -1;
+        e[j] = 0;
+      }
+    }
+  }
+  if (tid * RUN >= At) return;
+  // unconditional loads: positions past the list reread the thread's first
+  // edge (a real one, since its first position is below At)
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) e[j] = kk[j] >= 0 ? e[j] : e[0];
+  T x[EPT];
+  if constexpr (NARROW) {
+    uint32_t u[EPT], w[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) u[j] = p.hsrc[e[j]];
+    if constexpr (ALGO == A_SSSP) {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) w[j] = p.hw[e[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const T y = R::edge(r, (int32_t)u[j], ALGO == A_SSSP ? w[j] : 0u);
+      x[j] = kk[j] >= 0 ? y : R::identity();
+    }
+  } else {
+    uint32_t word[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) word[j] = p.src[e[j]];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const uint32_t w = ALGO == A_SSSP ? weight_of<PACKED>(p, word[j], e[j]) : 0u;
+      const T y = R::edge(r, src_of<PACKED>(word[j]), w);
+      x[j] = kk[j] >= 0 ? y : R::identity();
+    }
+  }
+#pragma unroll
+  for (int gi = 0; gi < G; ++gi) {
+    int ck = kk[gi * RUN];
+    T cur = x[gi * RUN];
+#pragma unroll
+    for (int i = 1; i < RUN; ++i) {
+      const int j = gi * RUN + i;
+      if (kk[j] == ck) {
+        cur = R::combine(cur, x[j]);
+      } else {
+        if (ck >= 0) {
+          if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
+          else atomicMin(&s.acc[ck], cur);
+        }
+        ck = kk[j];
+        cur = x[j];
+      }
+    }
+    if (ck >= 0) {
+      if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
+      else atomicMin(&s.acc[ck], cur);
+    }
+  }
+}
+
+template <int ALGO, int EDGES_PER_THREAD, bool PACKED, bool SPLIT>
+__device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, TileLds &s) {
+  using R = Red<ALGO>;
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int32_t t0 = p.tiles[2 * item], t1 = p.tiles[2 * item + 1];
   const int nv = t1 - t0;
   // phase 1: gate, degrees, block scan of (attempting vertices, their edges)
-  int32_t lv[2], eb[2], d[2];
+  // (split images: narrow edges [nb, nb + dn) and wide edges [eb, eb + d))
+  int32_t lv[2], eb[2], d[2], nb[2] = {0, 0}, dn[2] = {0, 0};
   Gate gt[2];
   bool act[2];
 #pragma unroll
@@ -280,8 +390,14 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
     lv[j] = t0 + (in ? i : 0);
     eb[j] = p.off[lv[j]];
     d[j] = p.off[lv[j] + 1] - eb[j];
+    if constexpr (SPLIT) {
+      nb[j] = p.hoff[lv[j]];
+      dn[j] = p.hoff[lv[j] + 1] - nb[j];
+      eb[j] -= nb[j];  // wide edges before the vertex
+      d[j] -= dn[j];
+    }
     gt[j] = gate_of(r, p.v_begin + lv[j]);
-    act[j] = in && (gt[j].attempt || r.audit) && (d[j] > 0 || is_pr<ALGO>());
+    act[j] = in && (gt[j].attempt || r.audit) && (d[j] + dn[j] > 0 || is_pr<ALGO>());
   }
   // BFS early break (Section 5.5): after the threshold's k passes every level <= k is
   // final and every other vertex is at level >= k + 1, so a vertex whose
@@ -295,38 +411,49 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         if (act[j]) {
-          const uint32_t x = r.value[src_of<PACKED>(p.src[eb[j]])];
+          const bool nar = SPLIT && dn[j] > 0;
+          const int32_t u = nar ? (int32_t)p.hsrc[nb[j]] : src_of<PACKED>(p.src[eb[j]]);
+          const uint32_t x = r.value[u];
           acc.edges += 1;
+          if (nar) acc.narrow += 1;
           seed[j] = x == INF ? INF : x + 1u;
-          eb[j] += 1;
-          d[j] = x == r.threshold ? 0 : d[j] - 1;
+          if (nar) { nb[j] += 1; dn[j] -= 1; } else { eb[j] += 1; d[j] -= 1; }
+          if (x == r.threshold) { d[j] = 0; dn[j] = 0; }
         }
       }
     }
   }
   int na = (int)act[0] + (int)act[1];
   int ne = (act[0] ? d[0] : 0) + (act[1] ? d[1] : 0);
-  int ina = na, ine = ne;  // inclusive scan within the wavefront
+  int nn = (act[0] ? dn[0] : 0) + (act[1] ? dn[1] : 0);
+  int ina = na, ine = ne, inn = nn;  // inclusive scan within the wavefront
 #pragma unroll
   for (int m = 1; m < 64; m <<= 1) {
     int a = __shfl_up(ina, m, 64), b = __shfl_up(ine, m, 64);
-    if (lane >= m) { ina += a; ine += b; }
+    int c = SPLIT ? __shfl_up(inn, m, 64) : 0;
+    if (lane >= m) { ina += a; ine += b; inn += c; }
   }
-  if (lane == 63) { s.wsum[wave][0] = ina; s.wsum[wave][1] = ine; }
+  if (lane == 63) { s.wsum[wave][0] = ina; s.wsum[wave][1] = ine; s.wsum[wave][2] = inn; }
   __syncthreads();
-  int ka = 0, pe = 0, Kt = 0, At = 0;
+  int ka = 0, pe = 0, pn = 0, Kt = 0, At = 0, An = 0;
   for (int w = 0; w < WAVES; ++w) {
-    if (w < wave) { ka += s.wsum[w][0]; pe += s.wsum[w][1]; }
+    if (w < wave) { ka += s.wsum[w][0]; pe += s.wsum[w][1]; pn += s.wsum[w][2]; }
     Kt += s.wsum[w][0];
     At += s.wsum[w][1];
+    An += s.wsum[w][2];
   }
   ka += ina - na;
   pe += ine - ne;
+  pn += inn - nn;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     if (act[j]) {
       s.pos[ka] = pe;
       s.eb[ka] = eb[j];
+      if constexpr (SPLIT) {
+        s.pos_n[ka] = pn;
+        s.eb_n[ka] = nb[j];
+      }
       s.vl[ka] = lv[j];
       // the early break's probe (BFS) seeds the reduction
       s.acc[ka] = ALGO == A_BFS ? seed[j] : R::bits(R::identity());
@@ -335,102 +462,28 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
       s.st[ka] = gt[j].st;
       ++ka;
       pe += d[j];
+      pn += dn[j];
     } else if (2 * tid + j < nv) {
       // not pulled this sweep: skipped by the predictor, or no in-edge
-      epilogue<ALGO>(r, p.v_begin + lv[j], gt[j], false, R::identity(), (uint32_t)d[j], acc);
+      epilogue<ALGO>(r, p.v_begin + lv[j], gt[j], false, R::identity(), (uint32_t)(d[j] + dn[j]), acc);
     }
   }
-  if (tid == 0) s.pos[Kt] = At;
+  if (tid == 0) {
+    s.pos[Kt] = At;
+    if constexpr (SPLIT) s.pos_n[Kt] = An;
+  }
   __syncthreads();
-  // phase 2: EDGES_PER_THREAD compacted edge positions per thread, in
-  // groups of RUN consecutive ones: group g of thread t starts at
-  // g * BLOCK * RUN + t * RUN, so a load instruction of a wavefront covers
-  // 64 * RUN consecutive positions and each thread keeps EDGES_PER_THREAD
-  // gathers in flight. A group finds its first position's vertex by binary
-  // search (monotone over the groups) and walks forward; runs of one vertex
-  // within a group are reduced in registers before one LDS atomic.
-  {
-    constexpr int EPT = EDGES_PER_THREAD;
-    constexpr int RUN = 2;
-    constexpr int G = EPT / RUN;
-    static_assert(EPT % RUN == 0, "groups of RUN positions");
-    int kk[EPT];
-    int32_t e[EPT];
-    int lo = 0;
-#pragma unroll
-    for (int gi = 0; gi < G; ++gi) {
-      const int q0 = gi * BLOCK * RUN + tid * RUN;
-      int k = -1, next = 0;
-      if (q0 < At) {
-        int l = lo, h = Kt;  // pos[l] <= q0 < pos[h]
-        while (h - l > 1) {
-          const int mid = (l + h) >> 1;
-          if (s.pos[mid] <= q0) l = mid; else h = mid;
-        }
-        lo = l;
-        k = l;
-        next = s.pos[k + 1];
-      }
-#pragma unroll
-      for (int i = 0; i < RUN; ++i) {
-        const int q = q0 + i;
-        const int j = gi * RUN + i;
-        if (k >= 0 && q < At) {
-          while (q >= next) { ++k; next = s.pos[k + 1]; }
-          kk[j] = k;
-          e[j] = s.eb[k] + (q - s.pos[k]);
-        } else {
-          kk[j] = -1;
-          e[j] = 0;
-        }
-      }
-    }
-    if (tid * RUN < At) {
-      // unconditional loads: positions past the tile reread the thread's
-      // first edge (a real one, since its first position is below At)
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) e[j] = kk[j] >= 0 ? e[j] : e[0];
-      uint32_t word[EPT];
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) word[j] = p.src[e[j]];
-      T x[EPT];
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        const uint32_t w = ALGO == A_SSSP ? weight_of<PACKED>(p, word[j], e[j]) : 0u;
-        const T y = R::edge(r, src_of<PACKED>(word[j]), w);
-        x[j] = kk[j] >= 0 ? y : R::identity();
-      }
-#pragma unroll
-      for (int gi = 0; gi < G; ++gi) {
-        int ck = kk[gi * RUN];
-        T cur = x[gi * RUN];
-#pragma unroll
-        for (int i = 1; i < RUN; ++i) {
-          const int j = gi * RUN + i;
-          if (kk[j] == ck) {
-            cur = R::combine(cur, x[j]);
-          } else {
-            if (ck >= 0) {
-              if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
-              else atomicMin(&s.acc[ck], cur);
-            }
-            ck = kk[j];
-            cur = x[j];
-          }
-        }
-        if (ck >= 0) {
-          if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
-          else atomicMin(&s.acc[ck], cur);
-        }
-      }
-    }
-  }
+  // phase 2: the wide edges, then (split images) the narrow ones
+  tile_gather<ALGO, EDGES_PER_THREAD, PACKED, false>(r, p, s, s.pos, s.eb, At, Kt);
+  if constexpr (SPLIT) tile_gather<ALGO, EDGES_PER_THREAD, PACKED, true>(r, p, s, s.pos_n, s.eb_n, An, Kt);
   __syncthreads();
   // phase 3: epilogues of the pulled vertices
   for (int k = tid; k < Kt; k += BLOCK) {
     Gate g{s.att[k] != 0, s.st[k], s.old[k]};
+    const uint32_t dn_k = SPLIT ? (uint32_t)(s.pos_n[k + 1] - s.pos_n[k]) : 0u;
+    if (SPLIT && g.attempt) acc.narrow += dn_k;
     const bool ch = epilogue<ALGO>(r, p.v_begin + s.vl[k], g, true, R::from_bits(s.acc[k]),
-                                   (uint32_t)(s.pos[k + 1] - s.pos[k]), acc);
+                                   (uint32_t)(s.pos[k + 1] - s.pos[k]) + dn_k, acc);
     frontier_push(r, ch, p.v_begin + s.vl[k]);
   }
 }
@@ -441,7 +494,41 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
 // or an exact fixed-point add for PageRank sums); the close kernel, after
 // the sweep has finished, takes the accumulator (resetting it) and runs the
 // vertex's epilogue, so no fence or arrival counter is needed in the sweep.
-template <int ALGO, bool PACKED>
+// Edges [a, b) of one chunk list, lanes strided, batches of B per lane:
+// B loads, then B gathers, all in flight together (lanes past the range
+// reread its first edge). NARROW: u16 ids and u8 weights of a split image.
+template <int ALGO, bool PACKED, bool NARROW>
+__device__ inline typename Red<ALGO>::T chunk_range(const Run &r, const PageCtx &p, int32_t a, int32_t b,
+                                                    typename Red<ALGO>::T x) {
+  using R = Red<ALGO>;
+  using T = typename R::T;
+  const int lane = threadIdx.x % 64;
+  constexpr int B = 8;
+  for (int e0 = a + lane; e0 < b; e0 += B * 64) {
+    int32_t ei[B];
+    uint32_t q[B], w[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      ei[j] = e0 + j * 64 < b ? e0 + j * 64 : a;
+      if constexpr (NARROW) {
+        q[j] = p.hsrc[ei[j]];
+        w[j] = ALGO == A_SSSP ? (uint32_t)p.hw[ei[j]] : 0u;
+      } else {
+        q[j] = p.src[ei[j]];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      T y;
+      if constexpr (NARROW) y = R::edge(r, (int32_t)q[j], w[j]);
+      else y = R::edge(r, src_of<PACKED>(q[j]), ALGO == A_SSSP ? weight_of<PACKED>(p, q[j], ei[j]) : 0u);
+      if (e0 + j * 64 < b) x = R::combine(x, y);
+    }
+  }
+  return x;
+}
+
+template <int ALGO, bool PACKED, bool SPLIT>
 __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
   using R = Red<ALGO>;
   using T = typename R::T;
@@ -453,33 +540,38 @@ __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
   Gate g = gate_of(r, v);
   bool comp = g.attempt || r.audit;
   T x = R::identity();
+  // split images: the vertex's edges are its narrow ones, then its wide
+  // ones; the chunk covers [e_begin, e_end) of that order
+  int32_t v0 = 0, nb = 0, dn = 0;
+  if constexpr (SPLIT) {
+    v0 = p.off[c.vl];
+    nb = p.hoff[c.vl];
+    dn = p.hoff[c.vl + 1] - nb;
+  }
   bool scan = comp;
   if constexpr (ALGO == A_BFS) {
     // early break, as in tiles: every chunk of the vertex probes its first in-edge
     if (comp && r.early) {
-      if (r.value[src_of<PACKED>(p.src[p.off[c.vl]])] == r.threshold) {
+      int32_t u;
+      if (SPLIT && dn > 0) u = (int32_t)p.hsrc[nb];
+      else if (SPLIT) u = src_of<PACKED>(p.src[v0 - nb]);
+      else u = src_of<PACKED>(p.src[p.off[c.vl]]);
+      if (r.value[u] == r.threshold) {
         x = r.threshold + 1u;
         scan = false;
       }
     }
   }
   if (scan) {
-    // batches of 8 edges per lane: 8 edge-word loads, then 8 gathers, all
-    // in flight together (lanes past the chunk reread its first edge)
-    constexpr int B = 8;
-    for (int e0 = c.e_begin + lane; e0 < c.e_end; e0 += B * 64) {
-      int32_t ei[B];
-      uint32_t q[B];
-#pragma unroll
-      for (int j = 0; j < B; ++j) {
-        ei[j] = e0 + j * 64 < c.e_end ? e0 + j * 64 : c.e_begin;
-        q[j] = p.src[ei[j]];
-      }
-#pragma unroll
-      for (int j = 0; j < B; ++j) {
-        const T y = R::edge(r, src_of<PACKED>(q[j]), ALGO == A_SSSP ? weight_of<PACKED>(p, q[j], ei[j]) : 0u);
-        if (e0 + j * 64 < c.e_end) x = R::combine(x, y);
-      }
+    if constexpr (SPLIT) {
+      // narrow part: combined positions [v0, v0 + dn) -> narrow entries from nb
+      const int32_t na = max(c.e_begin, v0), nz = min(c.e_end, v0 + dn);
+      if (na < nz) x = chunk_range<ALGO, PACKED, true>(r, p, nb + (na - v0), nb + (nz - v0), x);
+      // wide part: combined positions [v0 + dn, ...) -> wide words from v0 - nb
+      const int32_t wa = max(c.e_begin, v0 + dn), wz = c.e_end;
+      if (wa < wz) x = chunk_range<ALGO, PACKED, false>(r, p, wa - nb - dn, wz - nb - dn, x);
+    } else {
+      x = chunk_range<ALGO, PACKED, false>(r, p, c.e_begin, c.e_end, x);
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) x = R::combine(x, shfl_xor(x, m));
@@ -543,7 +635,7 @@ __device__ void close_pass(Ctl *c, SweepRecord *rec) {
 
 // Totals of one sweep, as reduced by the close kernel.
 struct SweepTotals {
-  unsigned long long changed, edges, attempted, skipped, mispred, hist[8];
+  unsigned long long changed, edges, attempted, skipped, mispred, hist[8], narrow;
   uint32_t min_changed;
   double l1, ddelta, dmass;
 };
@@ -555,6 +647,7 @@ __device__ void close_sweep(Ctl *c, SweepRecord *rec, int end_of_pass, const Swe
   rec->seq = seq;
   rec->changed = t.changed;
   rec->edges = t.edges;
+  rec->edges_narrow = t.narrow;
   rec->attempted = t.attempted;
   rec->skipped = t.skipped;
   rec->mispred = t.mispred;
@@ -586,12 +679,12 @@ __device__ inline void publish_record(const SweepRecord *src, SweepRecord *dst) 
 }
 
 // ------------------------------------------------------------ the sweep
-template <int ALGO, int EPT, bool PACKED>
+template <int ALGO, int EPT, bool PACKED, bool SPLIT>
 __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   Ctl *ctl = a.ctl;
   if (ctl->done) return;  // converged: every block leaves before counting
   __shared__ uint32_t s_hist[8];
-  __shared__ uint32_t s_u32[WAVES][6];
+  __shared__ uint32_t s_u32[WAVES][7];
   __shared__ double s_f64[WAVES][3];
   __shared__ TileLds s_tile;
   if (threadIdx.x < 8) s_hist[threadIdx.x] = 0;
@@ -614,6 +707,9 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   p.chunks = reinterpret_cast<const Chunk *>(base + h->off_chunks);
   p.src = reinterpret_cast<const uint32_t *>(base + h->off_src);
   p.w = reinterpret_cast<const uint32_t *>(base + h->off_w);
+  p.hoff = reinterpret_cast<const int32_t *>(base + h->off_hoff);
+  p.hsrc = reinterpret_cast<const uint16_t *>(base + h->off_hsrc);
+  p.hw = reinterpret_cast<const uint8_t *>(base + h->off_w);
   p.bin_count = h->bin_count[BIN_CHUNK];
   p.bin_start = 0;
   p.partial = a.partial[ent];
@@ -647,8 +743,8 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   // a launch over pages without any work still runs one block, so the
   // sweep (and the pass) is closed the same way
   if (b < a.blk_prefix[a.nent * NSEC]) {
-    if (sec == 0) sweep_tile<ALGO, EPT, PACKED>(r, p, item, acc, s_tile);
-    else sweep_chunk<ALGO, PACKED>(r, p, item);
+    if (sec == 0) sweep_tile<ALGO, EPT, PACKED, SPLIT>(r, p, item, acc, s_tile);
+    else sweep_chunk<ALGO, PACKED, SPLIT>(r, p, item);
   }
 
   // block reduction of the counters, then one set of device-scope atomics
@@ -656,30 +752,33 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   uint32_t v0 = wave_sum_u32(acc.changed), v1 = wave_sum_u32(acc.attempted),
            v2 = wave_sum_u32(acc.skipped), v3 = wave_sum_u32(acc.mispred),
-           v4 = wave_sum_u32(acc.edges), v5 = wave_min_u32(acc.min_changed);
+           v4 = wave_sum_u32(acc.edges), v5 = wave_min_u32(acc.min_changed),
+           v6 = SPLIT ? wave_sum_u32(acc.narrow) : 0u;
   double f0 = 0.0, f1 = 0.0, f2 = 0.0;
   if constexpr (is_pr<ALGO>()) {
     f0 = wave_sum_f64(acc.l1); f1 = wave_sum_f64(acc.ddelta); f2 = wave_sum_f64(acc.dmass);
   }
   if (lane == 0) {
     s_u32[wave][0] = v0; s_u32[wave][1] = v1; s_u32[wave][2] = v2;
-    s_u32[wave][3] = v3; s_u32[wave][4] = v4; s_u32[wave][5] = v5;
+    s_u32[wave][3] = v3; s_u32[wave][4] = v4; s_u32[wave][5] = v5; s_u32[wave][6] = v6;
     s_f64[wave][0] = f0; s_f64[wave][1] = f1; s_f64[wave][2] = f2;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long ch = 0, at = 0, sk = 0, mp = 0, ed = 0;
+    unsigned long long ch = 0, at = 0, sk = 0, mp = 0, ed = 0, nr = 0;
     uint32_t mn = INF;
     double l1 = 0.0, dd = 0.0, dm = 0.0;
     for (int w = 0; w < WAVES; ++w) {
       ch += s_u32[w][0]; at += s_u32[w][1]; sk += s_u32[w][2]; mp += s_u32[w][3]; ed += s_u32[w][4];
       mn = min(mn, s_u32[w][5]);
+      nr += s_u32[w][6];
       l1 += s_f64[w][0]; dd += s_f64[w][1]; dm += s_f64[w][2];
     }
     Stripe &st = a.stripes[blockIdx.x % NSTRIPE];
     if (ch | at) atomicAdd(&st.ca, ch | at << 32);
     if (sk | mp) atomicAdd(&st.sm, sk | mp << 32);
     if (ed) atomicAdd(&st.edges, ed);
+    if (nr) atomicAdd(&st.narrow, nr);
     if (mn != INF) atomicMin(&st.min_changed, mn);
     if constexpr (is_pr<ALGO>()) {
       if (l1 != 0.0) atomicAdd(&st.l1, (unsigned long long)llrint(l1 * FIX_ONE));
@@ -708,7 +807,7 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   static_assert(CW <= 64 && NSTRIPE <= 64, "the first wavefront stages the control block, the second takes the stripes");
   __shared__ Ctl s_ctl;
   __shared__ uint32_t s_hist[8];
-  __shared__ unsigned long long s_red[CLOSE_THREADS / 64][5];
+  __shared__ unsigned long long s_red[CLOSE_THREADS / 64][6];
   __shared__ uint32_t s_min[CLOSE_THREADS / 64];
   __shared__ double s_fl[CLOSE_THREADS / 64][3];
   __shared__ __align__(16) SweepRecord s_rec;
@@ -718,7 +817,7 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   // counter stripes (a stripe is the identity when its sweep did nothing)
   if (tid < CW) reinterpret_cast<uint32_t *>(&s_ctl)[tid] = reinterpret_cast<const uint32_t *>(a.ctl)[tid];
   if (tid < 8) s_hist[tid] = 0;
-  unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, hw[4] = {0, 0, 0, 0};
+  unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, hw[4] = {0, 0, 0, 0};
   uint32_t mn = INF;
   double l1 = 0.0, dd = 0.0, dm = 0.0;
   if (wave == 1 && lane < NSTRIPE) {
@@ -727,6 +826,7 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
     c0 = ca & 0xFFFFFFFFull; c1 = ca >> 32;
     c2 = sm & 0xFFFFFFFFull; c3 = sm >> 32;
     c4 = atomicExch(&st.edges, 0ull);
+    c5 = atomicExch(&st.narrow, 0ull);
     mn = atomicExch(&st.min_changed, INF);
     if constexpr (is_pr<ALGO>()) {
       l1 = (double)atomicExch(&st.l1, 0ull) / FIX_ONE;
@@ -773,6 +873,8 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
     const PageHeader *h = reinterpret_cast<const PageHeader *>(base);
     const Heavy *hv = reinterpret_cast<const Heavy *>(base + h->off_heavy);
     const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
+    const int32_t *hoff = reinterpret_cast<const int32_t *>(base + h->off_hoff);
+    const bool split = h->split != 0;
     unsigned long long *part = a.partial[ent];
     for (int i = tid; i < h->n_heavy; i += CLOSE_THREADS) {
       const Heavy x = hv[i];
@@ -786,22 +888,25 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
       Gate g = gate_of(r, v);
       bool comp = g.attempt || r.audit;
       if (!comp) t = R::identity();
+      if (split && g.attempt) acc.narrow += (uint32_t)(hoff[x.vl + 1] - hoff[x.vl]);
       const bool ch = epilogue<ALGO>(r, v, g, comp, t, (uint32_t)(off[x.vl + 1] - off[x.vl]), acc);
       frontier_push(r, ch, v);
     }
   }
   c0 += acc.changed; c1 += acc.attempted; c2 += acc.skipped; c3 += acc.mispred; c4 += acc.edges;
+  c5 += acc.narrow;
   mn = min(mn, acc.min_changed);
   l1 += acc.l1; dd += acc.ddelta; dm += acc.dmass;
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
     c0 += shfl_xor(c0, m); c1 += shfl_xor(c1, m); c2 += shfl_xor(c2, m);
-    c3 += shfl_xor(c3, m); c4 += shfl_xor(c4, m);
+    c3 += shfl_xor(c3, m); c4 += shfl_xor(c4, m); c5 += shfl_xor(c5, m);
     mn = min(mn, shfl_xor(mn, m));
     l1 += shfl_xor(l1, m); dd += shfl_xor(dd, m); dm += shfl_xor(dm, m);
   }
   if (lane == 0) {
     s_red[wave][0] = c0; s_red[wave][1] = c1; s_red[wave][2] = c2; s_red[wave][3] = c3; s_red[wave][4] = c4;
+    s_red[wave][5] = c5;
     s_min[wave] = mn;
     s_fl[wave][0] = l1; s_fl[wave][1] = dd; s_fl[wave][2] = dm;
   }
@@ -811,7 +916,7 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
     t.min_changed = INF;
     for (int w = 0; w < nw; ++w) {
       t.changed += s_red[w][0]; t.attempted += s_red[w][1]; t.skipped += s_red[w][2];
-      t.mispred += s_red[w][3]; t.edges += s_red[w][4];
+      t.mispred += s_red[w][3]; t.edges += s_red[w][4]; t.narrow += s_red[w][5];
       t.min_changed = min(t.min_changed, s_min[w]);
       t.l1 += s_fl[w][0]; t.ddelta += s_fl[w][1]; t.dmass += s_fl[w][2];
     }
@@ -834,6 +939,8 @@ __global__ void end_pass_kernel(Ctl *ctl, SweepRecord *ring, uint32_t mask) {
     rec.mispred = 0; rec.l1 = 0.0; rec.min_changed = INF; rec.threshold = ctl->threshold;
     rec.phase = ctl->phase;
     for (int i = 0; i < 8; ++i) rec.hist[i] = 0;
+    rec.edges_narrow = 0;
+    rec.pad_ = 0;
     ctl->sweep_seq = seq + 1;
     close_pass(ctl, &rec);
     rec.dangling = ctl->dangling;
@@ -939,7 +1046,7 @@ __global__ void init_stripes_kernel(Stripe *s) {
   const int i = threadIdx.x;
   if (i < NSTRIPE) {
     Stripe z;
-    z.ca = z.sm = z.edges = z.l1 = z.dd = z.dm = 0ull;
+    z.ca = z.sm = z.edges = z.l1 = z.dd = z.dm = z.narrow = 0ull;
     for (int k = 0; k < 4; ++k) z.hist[k] = 0ull;
     z.min_changed = INF;
     s[i] = z;
@@ -955,10 +1062,19 @@ __global__ void init_ctl_kernel(Ctl *ctl, Ctl init) {
 template <int ALGO>
 static void launch_pair(const SweepArgs &a, hipStream_t s, hipEvent_t mid) {
   constexpr int EPT = TILE_E / BLOCK;
-  if (a.packed)
-    hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
-  else
-    hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, false>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+  // split-width images exist only for the min programs (their pages carry no
+  // value-dependent weights beyond the packed ones)
+  constexpr bool CAN_SPLIT = ALGO == A_BFS || ALGO == A_SSSP || ALGO == A_CC;
+  if (CAN_SPLIT && a.split) {
+    if (a.packed)
+      hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true, CAN_SPLIT>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+    else
+      hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, false, CAN_SPLIT>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+  } else if (a.packed) {
+    hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true, false>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, false, false>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+  }
   if (mid) (void)hipEventRecord(mid, s);
   hipLaunchKernelGGL(close_kernel<ALGO>, dim3(1), dim3(CLOSE_THREADS), 0, s, a);
 }

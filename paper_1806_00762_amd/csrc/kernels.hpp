@@ -20,6 +20,7 @@ struct SweepArgs {
   int32_t nblocks;         // grid size
   int32_t packed;          // edge words carry the weight in their top byte
   int32_t early;           // BFS under strong prediction: stop at a first in-neighbour on the threshold level
+  int32_t split;           // the pages in the slots are split-width images (min programs)
   double damping;
   float pr_eps;
   Ctl *ctl;                // device control block
