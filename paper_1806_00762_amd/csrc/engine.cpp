@@ -515,6 +515,7 @@ struct Runner {
     // (it needs fewer registers than the plain one)
     a.packed = (g->weighted ? g->packed : (int64_t)g->n <= ((int64_t)1 << 24)) ? 1 : 0;
     a.split = split ? 1 : 0;
+    if (split && !a.packed) return c->fail(SR_EINVAL, "split-width pages need packed edge words");
     return SR_OK;
   }
 

@@ -266,24 +266,55 @@ struct TileLds {
   int32_t wsum[WAVES][3];
 };
 
-// Phase 2 of a tile over one compacted edge list (pos/base in LDS, At
+// Folds a thread's gathered values into the LDS accumulators: runs of one
+// vertex (kk) within a group are combined in registers first.
+template <int ALGO, int EPT, int RUN>
+__device__ inline void tile_fold(TileLds &s, const int (&kk)[EPT], const typename Red<ALGO>::T (&x)[EPT]) {
+  using R = Red<ALGO>;
+  using T = typename R::T;
+  constexpr int G = EPT / RUN;
+#pragma unroll
+  for (int gi = 0; gi < G; ++gi) {
+    int ck = kk[gi * RUN];
+    T cur = x[gi * RUN];
+#pragma unroll
+    for (int i = 1; i < RUN; ++i) {
+      const int j = gi * RUN + i;
+      if (kk[j] == ck) {
+        cur = R::combine(cur, x[j]);
+      } else {
+        if (ck >= 0) {
+          if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
+          else atomicMin(&s.acc[ck], cur);
+        }
+        ck = kk[j];
+        cur = x[j];
+      }
+    }
+    if (ck >= 0) {
+      if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
+      else atomicMin(&s.acc[ck], cur);
+    }
+  }
+}
+
+// Phase 2 of a tile over its compacted edge list (pos/eb in LDS, At
 // positions, Kt vertices): EDGES_PER_THREAD positions per thread, in groups
 // of RUN consecutive ones; group g of thread t starts at g * BLOCK * RUN +
 // t * RUN, so a load instruction of a wavefront covers 64 * RUN consecutive
 // positions and each thread keeps EDGES_PER_THREAD gathers in flight. A
 // group finds its first position's vertex by binary search (monotone over
 // the groups) and walks forward; runs of one vertex within a group are
-// reduced in registers before one LDS atomic. NARROW: u16 ids (and u8
-// weights) of a split image; else edge words.
-template <int ALGO, int EPT, bool PACKED, bool NARROW>
-__device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds &s, const int32_t *pos,
-                                   const int32_t *base, int At, int Kt) {
+// reduced in registers before one LDS atomic.
+template <int ALGO, int EPT, bool PACKED>
+__device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds &s, int At, int Kt) {
   using R = Red<ALGO>;
   using T = typename R::T;
   const int tid = threadIdx.x;
   constexpr int RUN = 2;
   constexpr int G = EPT / RUN;
   static_assert(EPT % RUN == 0, "groups of RUN positions");
+  const int32_t *pos = s.pos;
   int kk[EPT];
   int32_t e[EPT];
   int lo = 0;
@@ -308,7 +339,7 @@ __device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds &s, c
       if (k >= 0 && q < At) {
         while (q >= next) { ++k; next = pos[k + 1]; }
         kk[j] = k;
-        e[j] = base[k] + (q - pos[k]);
+        e[j] = s.eb[k] + (q - pos[k]);
       } else {
         kk[j] = -1;
         e[j] = 0;
@@ -321,53 +352,98 @@ __device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds &s, c
 #pragma unroll
   for (int j = 0; j < EPT; ++j) e[j] = kk[j] >= 0 ? e[j] : e[0];
   T x[EPT];
-  if constexpr (NARROW) {
-    uint32_t u[EPT], w[EPT];
+  uint32_t word[EPT];
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) u[j] = p.hsrc[e[j]];
-    if constexpr (ALGO == A_SSSP) {
+  for (int j = 0; j < EPT; ++j) word[j] = p.src[e[j]];
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) w[j] = p.hw[e[j]];
-    }
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const T y = R::edge(r, (int32_t)u[j], ALGO == A_SSSP ? w[j] : 0u);
-      x[j] = kk[j] >= 0 ? y : R::identity();
-    }
-  } else {
-    uint32_t word[EPT];
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) word[j] = p.src[e[j]];
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const uint32_t w = ALGO == A_SSSP ? weight_of<PACKED>(p, word[j], e[j]) : 0u;
-      const T y = R::edge(r, src_of<PACKED>(word[j]), w);
-      x[j] = kk[j] >= 0 ? y : R::identity();
-    }
+  for (int j = 0; j < EPT; ++j) {
+    const uint32_t w = ALGO == A_SSSP ? weight_of<PACKED>(p, word[j], e[j]) : 0u;
+    const T y = R::edge(r, src_of<PACKED>(word[j]), w);
+    x[j] = kk[j] >= 0 ? y : R::identity();
   }
+  tile_fold<ALGO, EPT, RUN>(s, kk, x);
+}
+
+// Phase 2 of a tile of a split image: its narrow list (u16 ids at positions
+// [0, An)) and its wide list (edge words at [An, An + At)) form one position
+// space covered as above, so a thread's gathers of both lists are in flight
+// together. Every position issues one aligned 32-bit load: the edge word, or
+// the word holding the u16 id; SSSP also loads the u8 weight of narrow
+// positions (wide positions read the first one, unused).
+template <int ALGO, int EPT>
+__device__ inline void tile_gather_split(const Run &r, const PageCtx &p, TileLds &s, int An, int At, int Kt) {
+  using R = Red<ALGO>;
+  using T = typename R::T;
+  const int tid = threadIdx.x;
+  constexpr int RUN = 2;
+  constexpr int G = EPT / RUN;
+  const int Ac = An + At;
+  int kk[EPT];
+  int32_t e[EPT];
+  bool nar[EPT];
+  int lo_n = 0, lo_w = 0;  // binary-search floors, monotone over the groups in each list
 #pragma unroll
   for (int gi = 0; gi < G; ++gi) {
-    int ck = kk[gi * RUN];
-    T cur = x[gi * RUN];
+    const int q0 = gi * BLOCK * RUN + tid * RUN;
+    int k = -1, next = 0;
+    bool in_n = false;
 #pragma unroll
-    for (int i = 1; i < RUN; ++i) {
-      const int j = gi * RUN + i;
-      if (kk[j] == ck) {
-        cur = R::combine(cur, x[j]);
-      } else {
-        if (ck >= 0) {
-          if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
-          else atomicMin(&s.acc[ck], cur);
+    for (int i = 0; i < RUN; ++i) {
+      const int q = q0 + i, j = gi * RUN + i;
+      kk[j] = -1;
+      e[j] = 0;
+      nar[j] = false;
+      if (q < Ac) {
+        const bool qn = q < An;
+        const int ql = qn ? q : q - An;
+        const int32_t *pos = qn ? s.pos_n : s.pos;
+        if (k < 0 || qn != in_n) {
+          int l = qn ? lo_n : lo_w, h = Kt;  // pos[l] <= ql < pos[h]
+          while (h - l > 1) {
+            const int mid = (l + h) >> 1;
+            if (pos[mid] <= ql) l = mid; else h = mid;
+          }
+          if (qn) lo_n = l; else lo_w = l;
+          k = l;
+          next = pos[k + 1];
+          in_n = qn;
         }
-        ck = kk[j];
-        cur = x[j];
+        while (ql >= next) { ++k; next = pos[k + 1]; }
+        kk[j] = k;
+        nar[j] = qn;
+        e[j] = (qn ? s.eb_n[k] : s.eb[k]) + (ql - pos[k]);
       }
     }
-    if (ck >= 0) {
-      if constexpr (is_pr<ALGO>()) atomicAdd(reinterpret_cast<float *>(&s.acc[ck]), cur);
-      else atomicMin(&s.acc[ck], cur);
-    }
   }
+  if (tid * RUN >= Ac) return;
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    e[j] = kk[j] >= 0 ? e[j] : e[0];
+    nar[j] = kk[j] >= 0 ? nar[j] : nar[0];
+  }
+  const char *hs = reinterpret_cast<const char *>(p.hsrc);
+  const char *ws = reinterpret_cast<const char *>(p.src);
+  uint32_t word[EPT], wt[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const char *a = nar[j] ? hs + ((2 * e[j]) & ~3) : ws + 4 * e[j];
+    word[j] = *reinterpret_cast<const uint32_t *>(a);
+  }
+  if constexpr (ALGO == A_SSSP) {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) wt[j] = p.hw[nar[j] ? e[j] : 0];
+  }
+  T x[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const uint32_t un = (word[j] >> (16 * (e[j] & 1))) & 0xFFFFu;
+    const uint32_t u = nar[j] ? un : src_of<true>(word[j]);
+    uint32_t w = 0u;
+    if constexpr (ALGO == A_SSSP) w = nar[j] ? wt[j] : (word[j] >> 24);
+    const T y = R::edge(r, (int32_t)u, w);
+    x[j] = kk[j] >= 0 ? y : R::identity();
+  }
+  tile_fold<ALGO, EPT, RUN>(s, kk, x);
 }
 
 template <int ALGO, int EDGES_PER_THREAD, bool PACKED, bool SPLIT>
@@ -474,8 +550,8 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
   }
   __syncthreads();
   // phase 2: the wide edges, then (split images) the narrow ones
-  tile_gather<ALGO, EDGES_PER_THREAD, PACKED, false>(r, p, s, s.pos, s.eb, At, Kt);
-  if constexpr (SPLIT) tile_gather<ALGO, EDGES_PER_THREAD, PACKED, true>(r, p, s, s.pos_n, s.eb_n, An, Kt);
+  if constexpr (SPLIT) tile_gather_split<ALGO, EDGES_PER_THREAD>(r, p, s, An, At, Kt);
+  else tile_gather<ALGO, EDGES_PER_THREAD, PACKED>(r, p, s, At, Kt);
   __syncthreads();
   // phase 3: epilogues of the pulled vertices
   for (int k = tid; k < Kt; k += BLOCK) {
@@ -1062,14 +1138,11 @@ __global__ void init_ctl_kernel(Ctl *ctl, Ctl init) {
 template <int ALGO>
 static void launch_pair(const SweepArgs &a, hipStream_t s, hipEvent_t mid) {
   constexpr int EPT = TILE_E / BLOCK;
-  // split-width images exist only for the min programs (their pages carry no
-  // value-dependent weights beyond the packed ones)
+  // split-width images serve only the min programs, and their wide edge
+  // words are always packed
   constexpr bool CAN_SPLIT = ALGO == A_BFS || ALGO == A_SSSP || ALGO == A_CC;
-  if (CAN_SPLIT && a.split) {
-    if (a.packed)
-      hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true, CAN_SPLIT>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
-    else
-      hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, false, CAN_SPLIT>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+  if (CAN_SPLIT && a.split && a.packed) {
+    hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true, CAN_SPLIT>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
   } else if (a.packed) {
     hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true, false>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
   } else {
