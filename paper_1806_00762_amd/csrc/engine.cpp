@@ -756,11 +756,15 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (!g->res.resident && (depth < 1 || depth >= g->res.nslots))
     return c->fail(SR_EINVAL, "copy_depth must be in [1, num_slots)");
   // streamed min programs copy split-width images when every one fits a slot
-  // and together they are smaller than the full-width prefixes they replace
+  // and together they are smaller than the full-width prefixes they replace;
+  // when the pinned images cannot be allocated the run streams the
+  // full-width pages, unless the images were asked for
   if (force_split && g->res.resident)
     return c->fail(SR_EINVAL, "split-width pages serve streamed runs; this graph is resident");
-  if (!pr && !g->res.resident && !(p.flags & SR_RUN_WIDE_PAGES) && sr::split_eligible(g)) {
-    if ((s = sr::build_split_pages(g)) != SR_OK) return s;
+  const bool try_split = !pr && !g->res.resident && !(p.flags & SR_RUN_WIDE_PAGES) && sr::split_eligible(g);
+  const sr_status built = try_split ? sr::build_split_pages(g) : SR_EINVAL;
+  if (force_split && built != SR_OK) return built;
+  if (try_split && built == SR_OK) {
     uint64_t wide = 0, narrow = 0, mx = 0;
     for (auto &pg : g->pages) {
       const bool lead = !R.weights || pg.hdr.w_bytes == 0;
