@@ -118,14 +118,24 @@ struct alignas(256) PageHeader {
   // Split-width image (split = 1), streamed to the min programs: each
   // vertex's in-edges from sources below 2^16 ("narrow": a u16 id and, for
   // weighted graphs, a u8 weight) come apart from the others ("wide": the
-  // usual edge words, at off_src). off_hoff holds, per vertex, the narrow
-  // edges before it; the wide ones before vertex i are offsets[i] - hoff[i].
-  // Layout: header | tiles | chunks | heavy | hoff | narrow ids | wide words |
-  // narrow weights (off_w) | offsets, every section up to the last vertex
-  // the min programs read; bytes_lead is the whole image.
+  // usual edge words, at off_src); a vertex's narrow edges precede its
+  // wide ones. The image has no offsets: a tile with in-edges has a base
+  // (int2: its first vertex's in-edges before it, and its narrow edges
+  // before it), and each of its vertices a u32 of its narrow and wide edge
+  // ends relative to the tile's bases (low and high 16 bits; a tile holds at
+  // most TILE_E edges). The entry of a heavy vertex is its index in the
+  // heavy table (int4: in-edges before it, narrow edges before it, narrow
+  // edges, in-degree). The wide edges before a vertex with e in-edges and n
+  // narrow edges before it are e - n.
+  // Layout: header | tiles | chunks | heavy | tile bases | heavy table |
+  // vertex entries | narrow ids | wide words | narrow weights (off_w), the
+  // entries up to the last vertex the min programs read; bytes_lead is the
+  // whole image.
   int32_t split;
-  uint64_t off_hoff;             // int32 narrow-edge prefix per vertex
+  uint64_t off_vpk;              // u32 per vertex (see above)
   uint64_t off_hsrc;             // u16 narrow source ids
+  uint64_t off_tbase;            // int2 per tile with in-edges
+  uint64_t off_hside;            // int4 per heavy vertex
 };
 static_assert(sizeof(PageHeader) == 256, "page header is one 256-byte line");
 constexpr uint32_t NARROW_LIMIT = 1u << 16;  // narrow source ids are below this

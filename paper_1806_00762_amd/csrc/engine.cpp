@@ -342,13 +342,13 @@ struct Launch {
 // (SSSP), and the gathered value; per changed vertex the value write;
 // PageRank also writes rank and contrib and reads 1/outdeg per attempted
 // vertex. On split-width pages an edge read from the narrow section costs
-// its u16 id (and the u8 weight for SSSP) instead of the u32 word, and each
-// visited vertex reads its narrow-prefix offset too.
+// its u16 id (and the u8 weight for SSSP) instead of the u32 word (a
+// visited vertex reads its packed tile-relative ends in place of its offset).
 uint64_t algo_bytes(int algo, int pvu, bool sep_weights, bool split, const SweepRecord &r) {
   const uint64_t visited = r.attempted + r.skipped;
   const uint64_t eb = (algo == A_SSSP && sep_weights) ? 12 : 8;
   uint64_t b = r.edges * eb + visited * 8;
-  if (split) b = b + visited * 4 - r.edges_narrow * (algo == A_SSSP ? 1 : 2);
+  if (split) b -= r.edges_narrow * (algo == A_SSSP ? 1 : 2);
   if (pvu == P_WEAK) b += visited * 2;
   if (algo == A_PR || algo == A_PPR) b += r.attempted * 12;
   else b += r.changed * 4;

@@ -222,55 +222,86 @@ bool split_eligible(const sr_graph *g) {
 
 // Split-width image of one page (see PageHeader): the sections the min
 // programs read, with each vertex's in-edges from sources below
-// NARROW_LIMIT stored as u16 ids (and u8 weights) ahead of the others.
+// NARROW_LIMIT stored as u16 ids (and u8 weights) ahead of the others, and
+// tile-relative edge ends in place of the offsets.
 static sr_status split_page(sr_graph *g, Page &pg) {
   const PageHeader &h = pg.hdr;
   const int32_t vb = h.v_begin;
   const int64_t eb = g->in_off[vb];
   const int32_t lead = (int32_t)((h.bytes_lead - h.off_offsets) / 4) - 1;
+  // narrow in-edges before each vertex (page-local), and their total
+  std::vector<int32_t> nbefore((size_t)lead + 1);
   int64_t mh = 0;
-  for (int64_t e = eb; e < g->in_off[vb + lead]; ++e) mh += (uint32_t)g->in_src[e] < NARROW_LIMIT;
-  const int64_t mt = (g->in_off[vb + lead] - eb) - mh;
+  for (int32_t i = 0; i < lead; ++i) {
+    nbefore[i] = (int32_t)mh;
+    for (int64_t e = g->in_off[vb + i]; e < g->in_off[vb + i + 1]; ++e) mh += (uint32_t)g->in_src[e] < NARROW_LIMIT;
+  }
+  nbefore[lead] = (int32_t)mh;
+  auto ebefore = [&](int32_t i) { return (int32_t)(g->in_off[vb + i] - eb); };
+  const int64_t mt = (int64_t)ebefore(lead) - mh;
+  const int32_t nte = h.n_tiles_edges;
   PageHeader s = h;
   s.split = 1;
   uint64_t o = sizeof(PageHeader);
   s.off_tiles = o;   o = align256(o + 8ull * (uint64_t)h.n_tiles);
   s.off_chunks = o;  o = align256(o + sizeof(Chunk) * (uint64_t)h.n_chunks);
   s.off_heavy = o;   o = align256(o + sizeof(Heavy) * (uint64_t)h.n_heavy);
-  s.off_hoff = o;    o = align256(o + 4ull * ((uint64_t)lead + 1));
+  s.off_tbase = o;   o = align256(o + 8ull * (uint64_t)nte);
+  s.off_hside = o;   o = align256(o + 16ull * (uint64_t)h.n_heavy);
+  s.off_vpk = o;     o = align256(o + 4ull * (uint64_t)lead);
   s.off_hsrc = o;    o = align256(o + 2ull * (uint64_t)mh);
   s.off_src = o;     o = align256(o + 4ull * (uint64_t)mt);
-  s.off_w = o;       o = align256(o + (g->weighted ? (uint64_t)mh : 0ull));
-  s.off_offsets = o; o = o + 4ull * ((uint64_t)lead + 1);
+  s.off_w = o;       o = o + (g->weighted ? (uint64_t)mh : 0ull);
+  s.off_offsets = 0;  // none: tile bases and vertex entries replace them
   s.off_bins = 0;
   s.bytes_lead = s.bytes_unweighted = s.bytes_weighted = s.bytes_total = o;
   s.w_bytes = 0;
   char *buf = alloc_page_buffer(g->ctx, align256(o));
   if (!buf) return SR_ENOMEM;
+  std::memset(buf, 0, align256(o));
   std::memcpy(buf + s.off_tiles, pg.host + h.off_tiles, 8ull * (uint64_t)h.n_tiles);
   std::memcpy(buf + s.off_chunks, pg.host + h.off_chunks, sizeof(Chunk) * (uint64_t)h.n_chunks);
   std::memcpy(buf + s.off_heavy, pg.host + h.off_heavy, sizeof(Heavy) * (uint64_t)h.n_heavy);
-  std::memcpy(buf + s.off_offsets, pg.host + h.off_offsets, 4ull * ((uint64_t)lead + 1));
-  int32_t *hoff = (int32_t *)(buf + s.off_hoff);
+  const int32_t *tiles = (const int32_t *)(pg.host + h.off_tiles);
+  const Heavy *heavy = (const Heavy *)(pg.host + h.off_heavy);
+  int32_t *tbase = (int32_t *)(buf + s.off_tbase);
+  int32_t *hside = (int32_t *)(buf + s.off_hside);
+  uint32_t *vpk = (uint32_t *)(buf + s.off_vpk);
+  for (int32_t k = 0; k < nte; ++k) {
+    const int32_t t0 = tiles[2 * k], t1 = tiles[2 * k + 1];
+    tbase[2 * k] = ebefore(t0);
+    tbase[2 * k + 1] = nbefore[t0];
+    for (int32_t i = t0; i < t1; ++i) {
+      const uint32_t ne = (uint32_t)(nbefore[i + 1] - nbefore[t0]);
+      const uint32_t we = (uint32_t)((ebefore(i + 1) - nbefore[i + 1]) - (ebefore(t0) - nbefore[t0]));
+      if (ne > 0xFFFFu || we > 0xFFFFu) { free_page_buffer(g->ctx, buf); return SR_EINVAL; }
+      vpk[i] = ne | we << 16;
+    }
+  }
+  for (int32_t k = 0; k < h.n_heavy; ++k) {
+    const int32_t v = heavy[k].vl;
+    hside[4 * k] = ebefore(v);
+    hside[4 * k + 1] = nbefore[v];
+    hside[4 * k + 2] = nbefore[v + 1] - nbefore[v];
+    hside[4 * k + 3] = ebefore(v + 1) - ebefore(v);
+    vpk[v] = (uint32_t)k;
+  }
   uint16_t *hsrc = (uint16_t *)(buf + s.off_hsrc);
   uint32_t *words = (uint32_t *)(buf + s.off_src);
   uint8_t *hw = (uint8_t *)(buf + s.off_w);
   int64_t nh = 0, nt = 0;
-  for (int32_t i = 0; i < lead; ++i) {
-    hoff[i] = (int32_t)nh;
-    for (int64_t e = g->in_off[vb + i]; e < g->in_off[vb + i + 1]; ++e) {
-      const uint32_t u = (uint32_t)g->in_src[e];
-      const uint32_t w = g->weighted ? g->in_w[e] : 0u;
-      if (u < NARROW_LIMIT) {
-        hsrc[nh] = (uint16_t)u;
-        if (g->weighted) hw[nh] = (uint8_t)w;
-        nh++;
-      } else {
-        words[nt++] = u | (g->weighted ? w << 24 : 0u);
-      }
+  for (int64_t e = eb; e < g->in_off[vb + lead]; ++e) {
+    // per vertex the narrow edges land in order in hsrc, the wide in words
+    const uint32_t u = (uint32_t)g->in_src[e];
+    const uint32_t w = g->weighted ? g->in_w[e] : 0u;
+    if (u < NARROW_LIMIT) {
+      hsrc[nh] = (uint16_t)u;
+      if (g->weighted) hw[nh] = (uint8_t)w;
+      nh++;
+    } else {
+      words[nt++] = u | (g->weighted ? w << 24 : 0u);
     }
   }
-  hoff[lead] = (int32_t)nh;
   std::memcpy(buf, &s, sizeof(PageHeader));
   pg.split = buf;
   pg.shdr = s;

@@ -60,7 +60,9 @@ struct PageCtx {
   const Chunk *chunks;
   const uint32_t *src;       // edge words: source id, or source | weight << 24 when packed
   const uint32_t *w;         // separate u32 weights (unpacked weighted pages)
-  const int32_t *hoff;       // split images: narrow edges before each vertex
+  const uint32_t *vpk;       // split images: per-vertex tile-relative ends, or heavy index
+  const int2 *tbase;         // split images: per-tile bases
+  const int4 *hside;         // split images: heavy-vertex table
   const uint16_t *hsrc;      // split images: narrow source ids
   const uint8_t *hw;         // split images: narrow weights
   int32_t bin_count, bin_start;
@@ -464,13 +466,20 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
     const int i = 2 * tid + j;
     const bool in = i < nv;
     lv[j] = t0 + (in ? i : 0);
-    eb[j] = p.off[lv[j]];
-    d[j] = p.off[lv[j] + 1] - eb[j];
     if constexpr (SPLIT) {
-      nb[j] = p.hoff[lv[j]];
-      dn[j] = p.hoff[lv[j] + 1] - nb[j];
-      eb[j] -= nb[j];  // wide edges before the vertex
-      d[j] -= dn[j];
+      // ends of this vertex and of the one before it (0 at the tile's start),
+      // narrow in the low and wide in the high 16 bits
+      const int2 tb = p.tbase[item];  // (in-edges, narrow edges) before the tile
+      const uint32_t e1 = p.vpk[lv[j]];
+      const uint32_t e0r = p.vpk[lv[j] > 0 ? lv[j] - 1 : 0];
+      const uint32_t e0 = lv[j] > t0 ? e0r : 0u;
+      nb[j] = tb.y + (int32_t)(e0 & 0xFFFFu);
+      dn[j] = (int32_t)(e1 & 0xFFFFu) - (int32_t)(e0 & 0xFFFFu);
+      eb[j] = tb.x - tb.y + (int32_t)(e0 >> 16);  // wide edges before the vertex
+      d[j] = (int32_t)(e1 >> 16) - (int32_t)(e0 >> 16);
+    } else {
+      eb[j] = p.off[lv[j]];
+      d[j] = p.off[lv[j] + 1] - eb[j];
     }
     gt[j] = gate_of(r, p.v_begin + lv[j]);
     act[j] = in && (gt[j].attempt || r.audit) && (d[j] + dn[j] > 0 || is_pr<ALGO>());
@@ -620,9 +629,10 @@ __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
   // ones; the chunk covers [e_begin, e_end) of that order
   int32_t v0 = 0, nb = 0, dn = 0;
   if constexpr (SPLIT) {
-    v0 = p.off[c.vl];
-    nb = p.hoff[c.vl];
-    dn = p.hoff[c.vl + 1] - nb;
+    const int4 hs = p.hside[p.vpk[c.vl]];
+    v0 = hs.x;
+    nb = hs.y;
+    dn = hs.z;
   }
   bool scan = comp;
   if constexpr (ALGO == A_BFS) {
@@ -783,7 +793,9 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   p.chunks = reinterpret_cast<const Chunk *>(base + h->off_chunks);
   p.src = reinterpret_cast<const uint32_t *>(base + h->off_src);
   p.w = reinterpret_cast<const uint32_t *>(base + h->off_w);
-  p.hoff = reinterpret_cast<const int32_t *>(base + h->off_hoff);
+  p.vpk = reinterpret_cast<const uint32_t *>(base + h->off_vpk);
+  p.tbase = reinterpret_cast<const int2 *>(base + h->off_tbase);
+  p.hside = reinterpret_cast<const int4 *>(base + h->off_hside);
   p.hsrc = reinterpret_cast<const uint16_t *>(base + h->off_hsrc);
   p.hw = reinterpret_cast<const uint8_t *>(base + h->off_w);
   p.bin_count = h->bin_count[BIN_CHUNK];
@@ -949,7 +961,7 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
     const PageHeader *h = reinterpret_cast<const PageHeader *>(base);
     const Heavy *hv = reinterpret_cast<const Heavy *>(base + h->off_heavy);
     const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
-    const int32_t *hoff = reinterpret_cast<const int32_t *>(base + h->off_hoff);
+    const int4 *hside = reinterpret_cast<const int4 *>(base + h->off_hside);
     const bool split = h->split != 0;
     unsigned long long *part = a.partial[ent];
     for (int i = tid; i < h->n_heavy; i += CLOSE_THREADS) {
@@ -964,8 +976,12 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
       Gate g = gate_of(r, v);
       bool comp = g.attempt || r.audit;
       if (!comp) t = R::identity();
-      if (split && g.attempt) acc.narrow += (uint32_t)(hoff[x.vl + 1] - hoff[x.vl]);
-      const bool ch = epilogue<ALGO>(r, v, g, comp, t, (uint32_t)(off[x.vl + 1] - off[x.vl]), acc);
+      // split images have no offsets: the heavy table holds the in-degree
+      int4 hs = make_int4(0, 0, 0, 0);
+      if (split) hs = hside[i];
+      if (split && g.attempt) acc.narrow += (uint32_t)hs.z;
+      const uint32_t deg = split ? (uint32_t)hs.w : (uint32_t)(off[x.vl + 1] - off[x.vl]);
+      const bool ch = epilogue<ALGO>(r, v, g, comp, t, deg, acc);
       frontier_push(r, ch, v);
     }
   }
