@@ -97,8 +97,9 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
                                      link per page (Section 3.1's streamed pages; built once, in
                                      pinned memory, on the first such run, and used when each image
                                      fits a slot and all of them are smaller than the full-width
-                                     pages); this flag copies the full-width pages instead
-                                     (results are identical either way) */
+                                     pages; when the pinned images cannot be allocated the run
+                                     copies the full-width pages); this flag copies the full-width
+                                     pages instead (results are identical either way) */
 #define SR_RUN_SPLIT_PAGES 0x100u /* copy the split-width images even when they are not smaller
                                      (SR_EINVAL for PageRank, resident graphs, graphs whose edge
                                      words are not packed, or together with SR_RUN_WIDE_PAGES;
