@@ -154,3 +154,49 @@ def test_split_not_for_resident_or_pagerank(sr, ctx):
         assert st["status"] == sr.SR_EINVAL
     finally:
         G.close()
+
+
+def boundary_graph():
+    """Sources on both sides of the narrow limit (65534..65537) and at the
+    ends of the id range, into: a chain that needs many passes, a vertex with
+    exactly the heavy bound of in-edges (2048: still in a tile), one just
+    above it (2049: two chunks) and one with 5000, each mixing narrow and
+    wide sources; plus a 4096-edge tile of 2048 + 2048 in-edges."""
+    n = 70000
+    rng = np.random.default_rng(65536)
+    src, dst = [], []
+    for a, b in ((0, 65534), (65534, 65535), (65535, 65536), (65536, 65537), (65537, 69999),
+                 (69999, 1), (1, 65535), (65536, 2)):
+        src.append(a); dst.append(b)
+    for v, d in ((3, 2048), (4, 2049), (5, 5000), (6, 2048), (7, 2048)):
+        s = rng.choice(np.arange(8, n), size=d, replace=False)
+        src.extend(s.tolist()); dst.extend([v] * d)
+    # every vertex gets three in-edges from random sources
+    t = np.arange(8, n)
+    for _ in range(3):
+        src.extend(rng.integers(0, n, size=t.size).tolist()); dst.extend(t.tolist())
+    src = np.array(src); dst = np.array(dst)
+    w = rng.integers(1, 256, size=src.size).astype(np.uint32)
+    return graphgen.from_edges(n, src, dst, w)
+
+
+@pytest.mark.parametrize("parts,slots,depth", [(3, 3, 1), (6, 4, 2)])
+@pytest.mark.parametrize("reorder", [False, True])
+def test_split_pages_boundaries(sr, ctx, parts, slots, depth, reorder):
+    g = boundary_graph()
+    G = ctx.load(g, reorder=reorder)
+    try:
+        G.partition(parts, slots)
+        for algo in ("bfs", "sssp"):
+            for s in (0, 65535, 65536, 69999):
+                say(f"case boundary parts={parts} reorder={reorder} {algo} source {s}")
+                want = ref(algo, g, s)
+                for pvu in ("strong", "off"):
+                    kw = dict(source=s, pvu=pvu, force_stream=True, copy_depth=depth)
+                    st = G.run(algo, split_pages=True, **kw)
+                    assert np.array_equal(G.values(), want), (algo, s, pvu)
+                    assert st["edges_narrow"] > 0
+                    G.run(algo, wide_pages=True, **kw)
+                    assert np.array_equal(G.values(), want), (algo, s, pvu)
+    finally:
+        G.close()
