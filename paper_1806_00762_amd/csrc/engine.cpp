@@ -689,9 +689,8 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   auto residency = [&]() -> sr_status {
     uint64_t min_slot = 0;
     if (force_split) {
-      sr_status b = sr::build_split_pages(g);
-      if (b != SR_OK) return b;
-      for (auto &pg : g->pages) min_slot = std::max(min_slot, pg.shdr.bytes_lead);
+      sr::size_split_pages(g);
+      for (auto &pg : g->pages) min_slot = std::max(min_slot, pg.split_bytes);
     }
     return ensure_residency(g, R.weights, (p.flags & SR_RUN_FORCE_STREAM) != 0, false, min_slot);
   };
@@ -761,20 +760,34 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   // full-width pages, unless the images were asked for
   if (force_split && g->res.resident)
     return c->fail(SR_EINVAL, "split-width pages serve streamed runs; this graph is resident");
-  const bool try_split = !pr && !g->res.resident && !(p.flags & SR_RUN_WIDE_PAGES) && sr::split_eligible(g);
-  const sr_status built = try_split ? sr::build_split_pages(g) : SR_EINVAL;
-  if (force_split && built != SR_OK) return built;
-  if (try_split && built == SR_OK) {
+  if (!pr && !g->res.resident && !(p.flags & SR_RUN_WIDE_PAGES) && sr::split_eligible(g)) {
     uint64_t wide = 0, narrow = 0, mx = 0;
     for (auto &pg : g->pages) {
       const bool lead = !R.weights || pg.hdr.w_bytes == 0;
       wide += lead ? pg.hdr.bytes_lead : need_bytes(pg, R.weights);
-      narrow += pg.shdr.bytes_lead;
-      mx = std::max(mx, pg.shdr.bytes_lead);
+    }
+    // a sampled estimate first, so graphs whose images would not be clearly
+    // smaller are not read whole; then exact sizes (one count of the narrow
+    // in-edges per partition), and the images are built only when taken
+    const bool counted = !g->pages.empty() && g->pages[0].narrow >= 0;
+    if (!counted && !g->pages.empty() && g->pages[0].split_est == 0)
+      g->pages[0].split_est = sr::estimate_split_bytes(g);
+    if (force_split || counted || (double)g->pages[0].split_est < 0.97 * (double)wide) {
+      sr::size_split_pages(g);
+      for (auto &pg : g->pages) {
+        narrow += pg.split_bytes;
+        mx = std::max(mx, pg.split_bytes);
+      }
+    } else {
+      narrow = wide;  // not taken
     }
     if (force_split && mx > g->res.slot_bytes)
       return c->fail(SR_EBUDGET, "a split-width page image is larger than a slot");
     R.split = mx <= g->res.slot_bytes && (force_split || narrow < wide);
+    if (R.split && (s = sr::build_split_pages(g)) != SR_OK) {
+      if (force_split) return s;
+      R.split = false;
+    }
   }
 
   // initial values, predictor states and control block

@@ -22,6 +22,9 @@ struct Page {
   PageHeader hdr{};
   // split-width image for streamed min programs (built on first use)
   char *split = nullptr;
+  int64_t narrow = -1;      // in-edges from sources below NARROW_LIMIT (-1: not counted yet)
+  uint64_t split_bytes = 0; // size of its split-width image (valid once narrow is counted)
+  uint64_t split_est = 0;   // page 0 only: sampled estimate of all images' size (0: none yet)
   PageHeader shdr{};
 };
 
@@ -135,6 +138,12 @@ sr_status make_pages(sr_graph *g, int32_t nparts);
 // split-width images of every page (PageHeader::split), for streamed min
 // programs; built once per partition
 bool split_eligible(const sr_graph *g);
+// counts each page's narrow in-edges (once per partition) and sets the
+// sizes its split-width image would have, without building it
+void size_split_pages(sr_graph *g);
+// total size of the split-width images estimated from every 1024th in-edge
+// (a few MB read instead of the whole in-edge array)
+uint64_t estimate_split_bytes(const sr_graph *g);
 sr_status build_split_pages(sr_graph *g);
 // Smallest page count whose largest streamed page (with its chunk scratch)
 // fits slot_bytes; -1 if none does.

@@ -220,6 +220,64 @@ bool split_eligible(const sr_graph *g) {
   return g->weighted ? g->packed : (int64_t)g->n <= ((int64_t)1 << 24);
 }
 
+// Section offsets of a page's split-width image (see PageHeader) for mh
+// narrow and mt wide in-edges among its first `lead` vertices; returns its size.
+static uint64_t split_layout(const sr_graph *g, const PageHeader &h, int32_t lead, int64_t mh, int64_t mt,
+                             PageHeader &s) {
+  s = h;
+  s.split = 1;
+  uint64_t o = sizeof(PageHeader);
+  s.off_tiles = o;   o = align256(o + 8ull * (uint64_t)h.n_tiles);
+  s.off_chunks = o;  o = align256(o + sizeof(Chunk) * (uint64_t)h.n_chunks);
+  s.off_heavy = o;   o = align256(o + sizeof(Heavy) * (uint64_t)h.n_heavy);
+  s.off_tbase = o;   o = align256(o + 8ull * (uint64_t)h.n_tiles_edges);
+  s.off_hside = o;   o = align256(o + 16ull * (uint64_t)h.n_heavy);
+  s.off_vpk = o;     o = align256(o + 4ull * (uint64_t)lead);
+  s.off_hsrc = o;    o = align256(o + 2ull * (uint64_t)mh);
+  s.off_src = o;     o = align256(o + 4ull * (uint64_t)mt);
+  s.off_w = o;       o = o + (g->weighted ? (uint64_t)mh : 0ull);
+  s.off_offsets = 0;  // none: tile bases and vertex entries replace them
+  s.off_bins = 0;
+  s.bytes_lead = s.bytes_unweighted = s.bytes_weighted = s.bytes_total = o;
+  s.w_bytes = 0;
+  return o;
+}
+
+static int32_t lead_vertices(const PageHeader &h) { return (int32_t)((h.bytes_lead - h.off_offsets) / 4) - 1; }
+
+void size_split_pages(sr_graph *g) {
+  const int32_t P = (int32_t)g->pages.size();
+  if (P == 0 || g->pages[0].narrow >= 0) return;
+  const int T = std::min<int>(host_threads(), std::max<int32_t>(P, 1));
+  parallel_for(P, T > 0 ? T : 1, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t p = lo; p < hi; ++p) {
+      Page &pg = g->pages[p];
+      const int32_t vb = pg.hdr.v_begin, lead = lead_vertices(pg.hdr);
+      int64_t mh = 0;
+      for (int64_t e = g->in_off[vb]; e < g->in_off[vb + lead]; ++e) mh += (uint32_t)g->in_src[e] < NARROW_LIMIT;
+      const int64_t mt = (g->in_off[vb + lead] - g->in_off[vb]) - mh;
+      PageHeader s;
+      pg.split_bytes = split_layout(g, pg.hdr, lead, mh, mt, s);
+      pg.narrow = mh;
+    }
+  }, 1);
+}
+
+uint64_t estimate_split_bytes(const sr_graph *g) {
+  constexpr int64_t STRIDE = 1024;
+  uint64_t total = 0;
+  for (const Page &pg : g->pages) {
+    const int32_t vb = pg.hdr.v_begin, lead = lead_vertices(pg.hdr);
+    const int64_t e0 = g->in_off[vb], e1 = g->in_off[vb + lead];
+    int64_t hit = 0, seen = 0;
+    for (int64_t e = e0; e < e1; e += STRIDE, ++seen) hit += (uint32_t)g->in_src[e] < NARROW_LIMIT;
+    const int64_t mh = seen ? (int64_t)((double)hit / (double)seen * (double)(e1 - e0)) : 0;
+    PageHeader s;
+    total += split_layout(g, pg.hdr, lead, mh, (e1 - e0) - mh, s);
+  }
+  return total;
+}
+
 // Split-width image of one page (see PageHeader): the sections the min
 // programs read, with each vertex's in-edges from sources below
 // NARROW_LIMIT stored as u16 ids (and u8 weights) ahead of the others, and
@@ -228,7 +286,7 @@ static sr_status split_page(sr_graph *g, Page &pg) {
   const PageHeader &h = pg.hdr;
   const int32_t vb = h.v_begin;
   const int64_t eb = g->in_off[vb];
-  const int32_t lead = (int32_t)((h.bytes_lead - h.off_offsets) / 4) - 1;
+  const int32_t lead = lead_vertices(h);
   // narrow in-edges before each vertex (page-local), and their total
   std::vector<int32_t> nbefore((size_t)lead + 1);
   int64_t mh = 0;
@@ -240,22 +298,9 @@ static sr_status split_page(sr_graph *g, Page &pg) {
   auto ebefore = [&](int32_t i) { return (int32_t)(g->in_off[vb + i] - eb); };
   const int64_t mt = (int64_t)ebefore(lead) - mh;
   const int32_t nte = h.n_tiles_edges;
-  PageHeader s = h;
-  s.split = 1;
-  uint64_t o = sizeof(PageHeader);
-  s.off_tiles = o;   o = align256(o + 8ull * (uint64_t)h.n_tiles);
-  s.off_chunks = o;  o = align256(o + sizeof(Chunk) * (uint64_t)h.n_chunks);
-  s.off_heavy = o;   o = align256(o + sizeof(Heavy) * (uint64_t)h.n_heavy);
-  s.off_tbase = o;   o = align256(o + 8ull * (uint64_t)nte);
-  s.off_hside = o;   o = align256(o + 16ull * (uint64_t)h.n_heavy);
-  s.off_vpk = o;     o = align256(o + 4ull * (uint64_t)lead);
-  s.off_hsrc = o;    o = align256(o + 2ull * (uint64_t)mh);
-  s.off_src = o;     o = align256(o + 4ull * (uint64_t)mt);
-  s.off_w = o;       o = o + (g->weighted ? (uint64_t)mh : 0ull);
-  s.off_offsets = 0;  // none: tile bases and vertex entries replace them
-  s.off_bins = 0;
-  s.bytes_lead = s.bytes_unweighted = s.bytes_weighted = s.bytes_total = o;
-  s.w_bytes = 0;
+  PageHeader s;
+  const uint64_t o = split_layout(g, h, lead, mh, mt, s);
+  if (pg.narrow >= 0 && (pg.narrow != mh || pg.split_bytes != o)) return SR_EINVAL;  // sizing disagrees
   char *buf = alloc_page_buffer(g->ctx, align256(o));
   if (!buf) return SR_ENOMEM;
   std::memset(buf, 0, align256(o));
@@ -320,7 +365,8 @@ sr_status build_split_pages(sr_graph *g) {
   for (int32_t p = 0; p < P; ++p) {
     if (st[p] != SR_OK) {
       for (auto &pg : g->pages) { free_page_buffer(g->ctx, pg.split); pg.split = nullptr; }
-      return g->ctx->fail(SR_ENOMEM, "split page allocation failed");
+      return g->ctx->fail(st[p], st[p] == SR_ENOMEM ? "split page allocation failed"
+                                                    : "split page image disagrees with its sizing");
     }
   }
   return SR_OK;
