@@ -432,8 +432,18 @@ __device__ inline void tile_gather_split(const Run &r, const PageCtx &p, TileLds
     word[j] = *reinterpret_cast<const uint32_t *>(a);
   }
   if constexpr (ALGO == A_SSSP) {
+    // a wavefront's group covers 128 consecutive positions, so it is
+    // narrow or wide as a whole except at the lists' boundary: a wholly
+    // wide group loads no weights
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) wt[j] = p.hw[nar[j] ? e[j] : 0];
+    for (int gi = 0; gi < G; ++gi) {
+      const bool any = __ballot(nar[gi * RUN] || nar[gi * RUN + 1]) != 0ull;
+#pragma unroll
+      for (int i = 0; i < RUN; ++i) {
+        const int j = gi * RUN + i;
+        wt[j] = any ? (uint32_t)p.hw[nar[j] ? e[j] : 0] : 0u;
+      }
+    }
   }
   T x[EPT];
 #pragma unroll
