@@ -767,16 +767,21 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       wide += lead ? pg.hdr.bytes_lead : need_bytes(pg, R.weights);
     }
     // a sampled estimate first, so graphs whose images would not be clearly
-    // smaller are not read whole; then exact sizes (one count of the narrow
-    // in-edges per partition), and the images are built only when taken
+    // smaller are not read whole; the images are built (which sizes them
+    // exactly) when the estimate takes them, and used when each fits a slot
+    // and together they are smaller
     const bool counted = !g->pages.empty() && g->pages[0].narrow >= 0;
     if (!counted && !g->pages.empty() && g->pages[0].split_est == 0)
       g->pages[0].split_est = sr::estimate_split_bytes(g);
     if (force_split || counted || (double)g->pages[0].split_est < 0.97 * (double)wide) {
-      sr::size_split_pages(g);
-      for (auto &pg : g->pages) {
-        narrow += pg.split_bytes;
-        mx = std::max(mx, pg.split_bytes);
+      if ((s = sr::build_split_pages(g)) != SR_OK) {
+        if (force_split) return s;
+        narrow = wide;  // not taken
+      } else {
+        for (auto &pg : g->pages) {
+          narrow += pg.split_bytes;
+          mx = std::max(mx, pg.split_bytes);
+        }
       }
     } else {
       narrow = wide;  // not taken
@@ -784,10 +789,6 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     if (force_split && mx > g->res.slot_bytes)
       return c->fail(SR_EBUDGET, "a split-width page image is larger than a slot");
     R.split = mx <= g->res.slot_bytes && (force_split || narrow < wide);
-    if (R.split && (s = sr::build_split_pages(g)) != SR_OK) {
-      if (force_split) return s;
-      R.split = false;
-    }
   }
 
   // initial values, predictor states and control block

@@ -303,7 +303,9 @@ static sr_status split_page(sr_graph *g, Page &pg) {
   if (pg.narrow >= 0 && (pg.narrow != mh || pg.split_bytes != o)) return SR_EINVAL;  // sizing disagrees
   char *buf = alloc_page_buffer(g->ctx, align256(o));
   if (!buf) return SR_ENOMEM;
-  std::memset(buf, 0, align256(o));
+  // the gaps between sections are never used; entries of vertices outside
+  // the tiles with in-edges are read only by lanes whose result is dropped
+  std::memset(buf + s.off_vpk, 0, 4ull * (uint64_t)lead);
   std::memcpy(buf + s.off_tiles, pg.host + h.off_tiles, 8ull * (uint64_t)h.n_tiles);
   std::memcpy(buf + s.off_chunks, pg.host + h.off_chunks, sizeof(Chunk) * (uint64_t)h.n_chunks);
   std::memcpy(buf + s.off_heavy, pg.host + h.off_heavy, sizeof(Heavy) * (uint64_t)h.n_heavy);
@@ -350,6 +352,8 @@ static sr_status split_page(sr_graph *g, Page &pg) {
   std::memcpy(buf, &s, sizeof(PageHeader));
   pg.split = buf;
   pg.shdr = s;
+  pg.narrow = mh;
+  pg.split_bytes = o;
   return SR_OK;
 }
 
