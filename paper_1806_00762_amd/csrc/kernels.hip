@@ -266,7 +266,61 @@ struct TileLds {
   uint8_t att[TILE_V];
   uint8_t st[TILE_V];
   int32_t wsum[WAVES][3];
+  uint32_t wmax[WAVES];
+  // position -> covering vertex: k for the narrow list, TILE_V + k for the
+  // wide one (split images put the narrow positions first)
+  __attribute__((aligned(16))) uint16_t map[TILE_E];
 };
+
+// Builds s.map over the tile's An + At compacted positions: the start of
+// every non-empty edge range is marked with its (list, vertex) code, and an
+// inclusive max-scan carries each mark over its range (codes grow with the
+// position, since the wide codes lie above the narrow ones). Called by every
+// thread of the block.
+__device__ inline void tile_map(TileLds &s, int An, int At, int Kt, bool split) {
+  constexpr int PER = TILE_E / BLOCK;  // consecutive entries per thread in the scan
+  static_assert(PER == 16, "two 16-byte LDS words per thread");
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int Ac = An + At;
+  uint4 *m4 = reinterpret_cast<uint4 *>(s.map);
+  if (tid * PER < Ac) { m4[2 * tid] = make_uint4(0, 0, 0, 0); m4[2 * tid + 1] = make_uint4(0, 0, 0, 0); }
+  __syncthreads();
+  for (int k = tid; k < Kt; k += BLOCK) {
+    if (split && s.pos_n[k] < s.pos_n[k + 1]) s.map[s.pos_n[k]] = (uint16_t)k;
+    if (s.pos[k] < s.pos[k + 1]) s.map[An + s.pos[k]] = (uint16_t)(TILE_V + k);
+  }
+  __syncthreads();
+  uint32_t v[PER];
+  uint32_t run = 0;
+  if (tid * PER < Ac) {
+    const uint4 a = m4[2 * tid], b = m4[2 * tid + 1];
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      run = max(run, w[i] & 0xFFFFu); v[2 * i] = run;
+      run = max(run, w[i] >> 16);     v[2 * i + 1] = run;
+    }
+  }
+  uint32_t inc = run;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const uint32_t o = __shfl_up(inc, m, 64);
+    if (lane >= m) inc = max(inc, o);
+  }
+  if (lane == 63) s.wmax[wave] = inc;
+  __syncthreads();
+  uint32_t pre = __shfl_up(inc, 1, 64);
+  if (lane == 0) pre = 0;
+  for (int w = 0; w < wave; ++w) pre = max(pre, s.wmax[w]);
+  if (tid * PER < Ac) {
+    uint32_t w[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = max(v[2 * i], pre) | max(v[2 * i + 1], pre) << 16;
+    m4[2 * tid] = make_uint4(w[0], w[1], w[2], w[3]);
+    m4[2 * tid + 1] = make_uint4(w[4], w[5], w[6], w[7]);
+  }
+  __syncthreads();
+}
 
 // Folds a thread's gathered values into the LDS accumulators: runs of one
 // vertex (kk) within a group are combined in registers first.
@@ -316,35 +370,21 @@ __device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds &s, i
   constexpr int RUN = 2;
   constexpr int G = EPT / RUN;
   static_assert(EPT % RUN == 0, "groups of RUN positions");
-  const int32_t *pos = s.pos;
+  tile_map(s, 0, At, Kt, false);
   int kk[EPT];
   int32_t e[EPT];
-  int lo = 0;
 #pragma unroll
   for (int gi = 0; gi < G; ++gi) {
-    const int q0 = gi * BLOCK * RUN + tid * RUN;
-    int k = -1, next = 0;
-    if (q0 < At) {
-      int l = lo, h = Kt;  // pos[l] <= q0 < pos[h]
-      while (h - l > 1) {
-        const int mid = (l + h) >> 1;
-        if (pos[mid] <= q0) l = mid; else h = mid;
-      }
-      lo = l;
-      k = l;
-      next = pos[k + 1];
-    }
 #pragma unroll
     for (int i = 0; i < RUN; ++i) {
-      const int q = q0 + i;
+      const int q = gi * BLOCK * RUN + tid * RUN + i;
       const int j = gi * RUN + i;
-      if (k >= 0 && q < At) {
-        while (q >= next) { ++k; next = pos[k + 1]; }
+      kk[j] = -1;
+      e[j] = 0;
+      if (q < At) {
+        const int k = (int)s.map[q] - TILE_V;
         kk[j] = k;
-        e[j] = s.eb[k] + (q - pos[k]);
-      } else {
-        kk[j] = -1;
-        e[j] = 0;
+        e[j] = s.eb[k] + (q - s.pos[k]);
       }
     }
   }
@@ -380,40 +420,25 @@ __device__ inline void tile_gather_split(const Run &r, const PageCtx &p, TileLds
   constexpr int RUN = 2;
   constexpr int G = EPT / RUN;
   const int Ac = An + At;
+  tile_map(s, An, At, Kt, true);
   int kk[EPT];
   int32_t e[EPT];
   bool nar[EPT];
-  int lo_n = 0, lo_w = 0;  // binary-search floors, monotone over the groups in each list
 #pragma unroll
   for (int gi = 0; gi < G; ++gi) {
-    const int q0 = gi * BLOCK * RUN + tid * RUN;
-    int k = -1, next = 0;
-    bool in_n = false;
 #pragma unroll
     for (int i = 0; i < RUN; ++i) {
-      const int q = q0 + i, j = gi * RUN + i;
+      const int q = gi * BLOCK * RUN + tid * RUN + i, j = gi * RUN + i;
       kk[j] = -1;
       e[j] = 0;
       nar[j] = false;
       if (q < Ac) {
-        const bool qn = q < An;
-        const int ql = qn ? q : q - An;
-        const int32_t *pos = qn ? s.pos_n : s.pos;
-        if (k < 0 || qn != in_n) {
-          int l = qn ? lo_n : lo_w, h = Kt;  // pos[l] <= ql < pos[h]
-          while (h - l > 1) {
-            const int mid = (l + h) >> 1;
-            if (pos[mid] <= ql) l = mid; else h = mid;
-          }
-          if (qn) lo_n = l; else lo_w = l;
-          k = l;
-          next = pos[k + 1];
-          in_n = qn;
-        }
-        while (ql >= next) { ++k; next = pos[k + 1]; }
+        const int code = s.map[q];
+        const bool qn = code < TILE_V;
+        const int k = qn ? code : code - TILE_V;
         kk[j] = k;
         nar[j] = qn;
-        e[j] = (qn ? s.eb_n[k] : s.eb[k]) + (ql - pos[k]);
+        e[j] = qn ? s.eb_n[k] + (q - s.pos_n[k]) : s.eb[k] + (q - An - s.pos[k]);
       }
     }
   }
