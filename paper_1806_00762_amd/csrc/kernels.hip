@@ -255,11 +255,13 @@ __device__ inline void frontier_push(const Run &r, bool changed, int32_t v) {
 // runs of edges of the same vertex are reduced in registers before one LDS
 // atomic. Phase 3 runs the epilogues.
 
+template <bool SPLIT>
 struct TileLds {
   int32_t pos[TILE_V + 1];  // first compacted (wide) edge position of each attempting vertex
-  int32_t eb[TILE_V];       // its first (wide) in-edge (page-local)
-  int32_t pos_n[TILE_V + 1];  // split images: first compacted narrow edge position
-  int32_t eb_n[TILE_V];       // split images: its first narrow edge
+  int32_t eb[TILE_V];       // its first (wide) in-edge (page-local) minus that position
+  // split images: the same for the narrow list (one unused entry otherwise)
+  int32_t pos_n[SPLIT ? TILE_V + 1 : 1];
+  int32_t eb_n[SPLIT ? TILE_V : 1];
   int32_t vl[TILE_V];       // its page-local vertex id
   uint32_t acc[TILE_V];     // reduction (u32 min, or f32 sum bits)
   uint32_t old[TILE_V];
@@ -277,7 +279,8 @@ struct TileLds {
 // inclusive max-scan carries each mark over its range (codes grow with the
 // position, since the wide codes lie above the narrow ones). Called by every
 // thread of the block.
-__device__ inline void tile_map(TileLds &s, int An, int At, int Kt, bool split) {
+template <bool SPLIT>
+__device__ inline void tile_map(TileLds<SPLIT> &s, int An, int At, int Kt) {
   constexpr int PER = TILE_E / BLOCK;  // consecutive entries per thread in the scan
   static_assert(PER == 16, "two 16-byte LDS words per thread");
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
@@ -286,7 +289,9 @@ __device__ inline void tile_map(TileLds &s, int An, int At, int Kt, bool split) 
   if (tid * PER < Ac) { m4[2 * tid] = make_uint4(0, 0, 0, 0); m4[2 * tid + 1] = make_uint4(0, 0, 0, 0); }
   __syncthreads();
   for (int k = tid; k < Kt; k += BLOCK) {
-    if (split && s.pos_n[k] < s.pos_n[k + 1]) s.map[s.pos_n[k]] = (uint16_t)k;
+    if constexpr (SPLIT) {
+      if (s.pos_n[k] < s.pos_n[k + 1]) s.map[s.pos_n[k]] = (uint16_t)k;
+    }
     if (s.pos[k] < s.pos[k + 1]) s.map[An + s.pos[k]] = (uint16_t)(TILE_V + k);
   }
   __syncthreads();
@@ -324,8 +329,8 @@ __device__ inline void tile_map(TileLds &s, int An, int At, int Kt, bool split) 
 
 // Folds a thread's gathered values into the LDS accumulators: runs of one
 // vertex (kk) within a group are combined in registers first.
-template <int ALGO, int EPT, int RUN>
-__device__ inline void tile_fold(TileLds &s, const int (&kk)[EPT], const typename Red<ALGO>::T (&x)[EPT]) {
+template <int ALGO, int EPT, int RUN, bool SPLIT>
+__device__ inline void tile_fold(TileLds<SPLIT> &s, const int (&kk)[EPT], const typename Red<ALGO>::T (&x)[EPT]) {
   using R = Red<ALGO>;
   using T = typename R::T;
   constexpr int G = EPT / RUN;
@@ -363,14 +368,14 @@ __device__ inline void tile_fold(TileLds &s, const int (&kk)[EPT], const typenam
 // the groups) and walks forward; runs of one vertex within a group are
 // reduced in registers before one LDS atomic.
 template <int ALGO, int EPT, bool PACKED>
-__device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds &s, int At, int Kt) {
+__device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds<false> &s, int At, int Kt) {
   using R = Red<ALGO>;
   using T = typename R::T;
   const int tid = threadIdx.x;
   constexpr int RUN = 2;
   constexpr int G = EPT / RUN;
   static_assert(EPT % RUN == 0, "groups of RUN positions");
-  tile_map(s, 0, At, Kt, false);
+  tile_map(s, 0, At, Kt);
   int kk[EPT];
   int32_t e[EPT];
 #pragma unroll
@@ -384,7 +389,7 @@ __device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds &s, i
       if (q < At) {
         const int k = (int)s.map[q] - TILE_V;
         kk[j] = k;
-        e[j] = s.eb[k] + (q - s.pos[k]);
+        e[j] = s.eb[k] + q;
       }
     }
   }
@@ -413,14 +418,14 @@ __device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds &s, i
 // the word holding the u16 id; SSSP also loads the u8 weight of narrow
 // positions (wide positions read the first one, unused).
 template <int ALGO, int EPT>
-__device__ inline void tile_gather_split(const Run &r, const PageCtx &p, TileLds &s, int An, int At, int Kt) {
+__device__ inline void tile_gather_split(const Run &r, const PageCtx &p, TileLds<true> &s, int An, int At, int Kt) {
   using R = Red<ALGO>;
   using T = typename R::T;
   const int tid = threadIdx.x;
   constexpr int RUN = 2;
   constexpr int G = EPT / RUN;
   const int Ac = An + At;
-  tile_map(s, An, At, Kt, true);
+  tile_map(s, An, At, Kt);
   int kk[EPT];
   int32_t e[EPT];
   bool nar[EPT];
@@ -438,7 +443,7 @@ __device__ inline void tile_gather_split(const Run &r, const PageCtx &p, TileLds
         const int k = qn ? code : code - TILE_V;
         kk[j] = k;
         nar[j] = qn;
-        e[j] = qn ? s.eb_n[k] + (q - s.pos_n[k]) : s.eb[k] + (q - An - s.pos[k]);
+        e[j] = qn ? s.eb_n[k] + q : s.eb[k] + (q - An);
       }
     }
   }
@@ -484,7 +489,7 @@ __device__ inline void tile_gather_split(const Run &r, const PageCtx &p, TileLds
 }
 
 template <int ALGO, int EDGES_PER_THREAD, bool PACKED, bool SPLIT>
-__device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, TileLds &s) {
+__device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, TileLds<SPLIT> &s) {
   using R = Red<ALGO>;
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int32_t t0 = p.tiles[2 * item], t1 = p.tiles[2 * item + 1];
@@ -569,10 +574,10 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
   for (int j = 0; j < 2; ++j) {
     if (act[j]) {
       s.pos[ka] = pe;
-      s.eb[ka] = eb[j];
+      s.eb[ka] = eb[j] - pe;  // so that a position's edge is eb + position
       if constexpr (SPLIT) {
         s.pos_n[ka] = pn;
-        s.eb_n[ka] = nb[j];
+        s.eb_n[ka] = nb[j] - pn;
       }
       s.vl[ka] = lv[j];
       // the early break's probe (BFS) seeds the reduction
@@ -600,7 +605,8 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
   // phase 3: epilogues of the pulled vertices
   for (int k = tid; k < Kt; k += BLOCK) {
     Gate g{s.att[k] != 0, s.st[k], s.old[k]};
-    const uint32_t dn_k = SPLIT ? (uint32_t)(s.pos_n[k + 1] - s.pos_n[k]) : 0u;
+    uint32_t dn_k = 0u;
+    if constexpr (SPLIT) dn_k = (uint32_t)(s.pos_n[k + 1] - s.pos_n[k]);
     if (SPLIT && g.attempt) acc.narrow += dn_k;
     const bool ch = epilogue<ALGO>(r, p.v_begin + s.vl[k], g, true, R::from_bits(s.acc[k]),
                                    (uint32_t)(s.pos[k + 1] - s.pos[k]) + dn_k, acc);
@@ -807,7 +813,7 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   __shared__ uint32_t s_hist[8];
   __shared__ uint32_t s_u32[WAVES][7];
   __shared__ double s_f64[WAVES][3];
-  __shared__ TileLds s_tile;
+  __shared__ TileLds<SPLIT> s_tile;
   if (threadIdx.x < 8) s_hist[threadIdx.x] = 0;
 
   // locate (page, section, item) of this block: section 0 = tiles, 1 = chunks
