@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the streamed subgraph pass on one MI355X.
 
-Default workload: SSSP from vertex 0 on a seeded R-MAT graph of scale 22
-(edge factor 16, uint32 weights in [1, 255]), in-edge pages, with the
-library's device budget capped at 1/4 of the graph bytes so the pages stream
-from pinned host memory every pass (Seraph's out-of-GPU-memory regime). The
-library numbers the vertices internally by descending in-degree (results
-are returned in the input's ids; --order input keeps the input numbering,
-and the input-order solve is reported beside it).
-One step = one solve to convergence through the C ABI (sr_run).
+Headline workload (the largest single-GPU one): connected components by
+min-label propagation on a seeded R-MAT graph of scale 24 (edge factor 32,
+symmetrized: 1.02 G arcs), in-edge pages, with the library's page slots
+capped at 1/4 of the graph bytes so the pages stream from pinned host memory
+every pass (Seraph's out-of-GPU-memory regime); its uniform-random twin
+(same vertex and edge counts, the dense always-active regime) is the second
+leg. The library numbers vertices internally by descending degree (results
+are returned in the input's ids). One step = one CC solve to convergence
+through the C ABI (sr_run), labels checked bit-exact against union-find.
 
-Prints one JSON line: solve GTEPS (m / time to convergence, page streaming
-included as the paper times it), the roofline of the sweep kernel (its
-algorithmic bytes over its HIP-event time, against the 8 TB/s HBM peak), the
-host-to-device rate of the page stream, and the CPU oracle (Dijkstra) timed
-on the host as the baseline.
+Prints one JSON line: solve GTEPS (arcs / time to convergence, page
+streaming included as the paper times it), the roofline of the sweep kernel
+(its algorithmic bytes over its HIP-event time, against the 8 TB/s HBM
+peak), the host-to-device rate of the page stream, and the CPU oracle timed
+on the host: synchronous label propagation over all host cores (the CPU
+baseline, core count and CPU model stated) and single-thread union-find.
+Further legs: streamed SSSP on R-MAT scale 22, PageRank on scale 16, the
+batched PPR set and the query server.
 """
 from __future__ import annotations
 
@@ -56,9 +60,155 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_info():
+    """CPU of the host the benchmark runs on: logical CPUs, the ones this
+    process may use, and the model name."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "model": model}
+
+
 def sync():
     import torch
     torch.cuda.synchronize()
+
+
+def _cc_leg(args, g, workload, traffic_name, cpu=True):
+    """Streamed CC on a symmetric graph: pages within a quarter of the graph
+    bytes (plus the vertex state), strong prediction, timed solves; labels
+    checked bit-exact against the oracle's union-find (timed, one thread)
+    and, with cpu=True, the multi-core CPU baseline timed too."""
+    import oracle
+    import paper_1806_00762_amd as sr
+    gbytes = 4 * (g.n + 1) + 4 * g.m
+    budget = gbytes // 4 + 5 * g.n + (1 << 20)
+    ctx = sr.Context(0, budget)
+    t = time.perf_counter()
+    G = ctx.load(g, symmetric=True, reorder=args.order == "degree")
+    G.partition(0, args.slots)
+    info = G.info()
+    log(f"[bench] {workload}: loaded+partitioned in {time.perf_counter() - t:.1f}s: {info['num_parts']} pages, "
+        f"budget {budget / 1e6:.1f} MB, graph {gbytes / 1e6:.1f} MB")
+    run_kw = dict(pvu="strong", max_inner_iters=args.inner, force_stream=True, copy_depth=args.copy_depth,
+                  wide_pages=args.wide_pages)
+    for i in range(args.warmup):
+        st = G.run("cc", **run_kw)
+        log(f"[bench] {workload} warmup {i}: {st['wall_ms']:.1f} ms, passes {st['passes']}")
+    sync()
+    t0 = time.perf_counter()
+    stats = [G.run("cc", **run_kw) for _ in range(args.steps)]
+    sync()
+    elapsed = time.perf_counter() - t0
+    lab = G.values()
+    st = stats[-1]
+    log(f"[bench] {workload}: {elapsed * 1e3 / args.steps:.1f} ms per solve, passes {st['passes']} sweeps "
+        f"{st['sweeps']} kernel {st['kernel_ms']:.1f} ms h2d {st['h2d_ms']:.1f} ms ({st['h2d_bytes'] / 1e9:.2f} GB)")
+    sweep_ms = sum(x["sweep_kernel_ms"] for x in stats)
+    kernel_ms = sum(x["kernel_ms"] for x in stats)
+    algo_bytes = sum(x["algo_bytes"] for x in stats)
+    sweeps = sum(x["sweeps"] for x in stats)
+    h2d_bytes = sum(x["h2d_bytes"] for x in stats)
+    h2d_ms = sum(x["h2d_ms"] for x in stats)
+    scanned = sum(x["edges_scanned"] for x in stats)
+    narrow = sum(x["edges_narrow"] for x in stats)
+    achieved = algo_bytes / (sweep_ms * 1e-3) / 1e9
+    traffic, traffic_algo = kernel_traffic(traffic_name)
+    out = {
+        "value": round(g.m * args.steps / elapsed / 1e9, 4),
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "config": {"workload": workload, "n": g.n, "m": g.m, "pages": info["num_parts"], "slots": args.slots,
+                   "device_budget_bytes": budget, "graph_bytes": gbytes, "pvu": "strong",
+                   "max_inner_iters": args.inner, "copy_depth": args.copy_depth,
+                   "vertex_order": "degree descending (labels in input ids)" if args.order == "degree"
+                   else "input",
+                   "page_image": "full-width" if args.wide_pages else "split-width when smaller",
+                   "narrow_edge_frac": round(narrow / max(scanned, 1), 4)},
+        "roofline": {"bound": "hbm", "kernel": "sweep_kernel<CC>",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_algo_bytes_per_launch": traffic_algo,
+                     "algo_bytes_per_launch": round(algo_bytes / max(sweeps, 1)),
+                     "avg_launch_us": round(sweep_ms * 1e3 / max(sweeps, 1), 2),
+                     "close_kernel_avg_us": round((kernel_ms - sweep_ms) * 1e3 / max(sweeps, 1), 2)},
+        "h2d": {"achieved": round(h2d_bytes / (h2d_ms * 1e-3) / 1e9, 2) if h2d_ms else None,
+                "peak": H2D_PEAK_GBS, "unit": "GB/s",
+                "frac": round(h2d_bytes / (h2d_ms * 1e-3) / 1e9 / H2D_PEAK_GBS, 4) if h2d_ms else None,
+                "bytes_per_solve": h2d_bytes // args.steps},
+        "scan_gteps": round(scanned / (sweep_ms * 1e-3) / 1e9, 3),
+        "passes_per_solve": st["passes"],
+        "sweeps_per_solve": st["sweeps"],
+        "kernel_busy_frac": round(kernel_ms / (elapsed * 1e3), 3),
+    }
+    G.close()
+    ctx.close()
+    t = time.perf_counter()
+    ref = oracle.cc(g)
+    tu = time.perf_counter() - t
+    out["parity"] = "bit-exact" if np.array_equal(ref, lab) else f"MISMATCH {int(np.sum(ref != lab))}"
+    single = {"value": round(g.m / tu / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+              "sample": f"one union-find solve of the whole graph ({tu:.1f} s, one thread)"}
+    if cpu and not args.no_cpu:
+        t = time.perf_counter()
+        lp, iters, used = oracle.cc_labelprop_parallel(g)
+        tl = time.perf_counter() - t
+        assert np.array_equal(lp, ref)
+        out["cpu_baseline"] = {"value": round(g.m / tl / 1e9, 5), "unit": "GTEPS", "cores": used, "kind": "oracle",
+                               "sample": f"one synchronous label-propagation solve of the whole graph over "
+                                         f"{used} OpenMP threads ({iters} iterations, {tl:.1f} s), labels equal "
+                                         f"to union-find",
+                               "host": host_info(), "single_thread": single}
+    else:
+        out["cpu_single_thread"] = single
+    log(f"[bench] {workload}: parity {out['parity']}, union-find {tu:.1f}s")
+    return out
+
+
+def bench_cc24(args):
+    """The headline: streamed CC on the scale-24 R-MAT graph, then its uniform twin."""
+    import gc
+    import graphgen
+    t = time.perf_counter()
+    g = graphgen.recipes.cc_rmat_s24()
+    log(f"[bench] generated rmat24 ef32 sym n={g.n} m={g.m} in {time.perf_counter() - t:.1f}s")
+    head = _cc_leg(args, g, "cc_rmat24_ef32_sym_streamed_budget_quarter", "sweep_kernel_cc_rmat24_streamed")
+    del g
+    gc.collect()
+    res = {
+        "metric": METRIC,
+        "value": head.pop("value"),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head.pop("ms_per_step"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+    }
+    res.update(head)
+    if not args.no_twin:
+        t = time.perf_counter()
+        g = graphgen.recipes.cc_uniform_s24()
+        log(f"[bench] generated uniform24 twin n={g.n} m={g.m} in {time.perf_counter() - t:.1f}s")
+        twin = _cc_leg(args, g, "cc_uniform24_m2^29_sym_streamed_budget_quarter",
+                       "sweep_kernel_cc_uniform24_streamed", cpu=False)
+        twin["solve_gteps"] = twin.pop("value")
+        res["uniform_twin"] = twin
+        del g
+        gc.collect()
+    return res
 
 
 def bench_sssp22(args):
@@ -156,7 +306,7 @@ def bench_sssp22(args):
                                "h2d_bytes_per_solve": ost[-1]["h2d_bytes"],
                                "sweep_GBps": round(sum(s["algo_bytes"] for s in ost) /
                                                    (sum(s["sweep_kernel_ms"] for s in ost) * 1e-3) / 1e9, 1)}
-    if args.order == "degree" and not args.no_other:
+    if args.order == "degree" and not args.no_other and args.input_order:
         # the same solve with the input's vertex numbering
         ctxn = sr.Context(0, budget)
         Gn = ctxn.load(g)
@@ -233,7 +383,8 @@ def bench_sssp22(args):
             ref = oracle.sssp(g, 0)
             solves += 1
             tc = time.perf_counter() - t0
-            if tc >= args.cpu_seconds:
+            # as a secondary leg one solve gives parity and a single-thread rate
+            if tc >= args.cpu_seconds or args.headline != "sssp22":
                 break
         res["cpu_baseline"] = {"value": round(g.m * solves / tc / 1e9, 5), "unit": "GTEPS", "cores": 1,
                                "kind": "oracle",
@@ -632,6 +783,13 @@ def main():
     ap.add_argument("--order", choices=["degree", "input"], default="degree",
                     help="internal vertex numbering of the headline graph (results are in input ids)")
     ap.add_argument("--no-hetero", action="store_true", help="skip the host sparse stage leg")
+    ap.add_argument("--headline", choices=["cc24", "sssp22"], default="cc24",
+                    help="workload of the headline line: streamed CC on R-MAT scale 24 (and its uniform "
+                         "twin), or streamed SSSP on R-MAT scale 22")
+    ap.add_argument("--no-twin", action="store_true", help="skip the uniform twin of the CC workload")
+    ap.add_argument("--no-sssp", action="store_true", help="skip the streamed SSSP leg")
+    ap.add_argument("--input-order", action="store_true",
+                    help="also time the streamed SSSP solve with the input's vertex numbering")
     ap.add_argument("--wide-pages", action="store_true",
                     help="stream full-width pages instead of split-width images")
     ap.add_argument("--ablation", action="store_true",
@@ -654,7 +812,19 @@ def main():
               "pagerank16": bench_pagerank16}[args.only]
         print(json.dumps(fn(args)), flush=True)
         return
-    res = bench_sssp22(args)
+    if args.headline == "cc24":
+        res = bench_cc24(args)
+        log(f"[bench] headline cc24: {res['value']} GTEPS")
+        if not args.no_sssp:
+            s22 = bench_sssp22(args)
+            for k in ("metric", "unit", "n_gpus", "steps", "warmup", "higher_is_better", "scaling",
+                      "vs_baseline", "data"):
+                s22.pop(k, None)
+            s22["solve_gteps"] = s22.pop("value")
+            res["sssp22"] = s22
+            log(f"[bench] sssp22: {s22['solve_gteps']} GTEPS")
+    else:
+        res = bench_sssp22(args)
     if not args.no_extras:
         res["pagerank16"] = bench_pagerank16(args)
         log(f"[bench] pagerank16: {res['pagerank16']}")

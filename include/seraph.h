@@ -104,6 +104,18 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
                                      (SR_EINVAL for PageRank, resident graphs, graphs whose edge
                                      words are not packed, or together with SR_RUN_WIDE_PAGES;
                                      SR_EBUDGET when an image exceeds a slot) */
+#define SR_RUN_DETERMINISTIC 0x200u /* PageRank / PPR: bit-reproducible results. Each sweep reads a
+                                     snapshot of the gathered terms (rank / out-degree as they were
+                                     when the sweep started: Jacobi within a sweep, Gauss-Seidel
+                                     between the sweeps of a window) and sums every vertex's in-edge
+                                     terms in 2^-54 fixed point, which adds exactly in any order;
+                                     a streamed window is re-swept up to max_inner_iters times or
+                                     until a sweep changes nothing, never "until the next page has
+                                     landed" (a timing-dependent rule). Costs 4 bytes per vertex of
+                                     device memory (the snapshot's second buffer) and one copy of
+                                     the window's terms per sweep. Min programs (BFS, SSSP, CC)
+                                     reach their unique fixed point in any order, so this flag only
+                                     fixes their schedule. */
 
 /* stop reasons reported in sr_run_stats.stop_reason */
 #define SR_STOP_CONVERGED 1   /* min programs: a full pass changed nothing (with weak prediction,
@@ -120,9 +132,15 @@ typedef struct sr_server sr_server;
 /* ---------------------------------------------------------------- context */
 
 /* Create a context on HIP device `device` with a device-memory budget in
- * bytes (0 = the device's free memory). device = -1 creates a host-only
- * context: graphs can be loaded, partitioned and inspected, but sr_run and
- * every other device call return SR_EDEVICE. *out receives the handle. */
+ * bytes (0 = the device's free memory). The budget models the paper's
+ * setting (Section 1, Section 3.1): the graph lives in host memory, while
+ * GPU memory holds the vertex data and only as many subgraph pages as fit,
+ * so a budget below the graph size makes every pass stream its pages.
+ * Every device byte the library allocates for the context (vertex state,
+ * page slots, work lists, scratch) is charged to it. device = -1 creates a
+ * host-only context: graphs can be loaded, partitioned and inspected, but
+ * sr_run and every other device call return SR_EDEVICE. *out receives the
+ * handle; the caller destroys it with sr_ctx_destroy. */
 sr_status sr_ctx_create(int device, uint64_t device_budget_bytes, sr_ctx **out);
 void sr_ctx_destroy(sr_ctx *ctx);
 /* Message of the last error on this context ("" if none). Valid until the
@@ -132,6 +150,21 @@ const char *sr_ctx_last_error(const sr_ctx *ctx);
  * and for host-to-device page copies. NULL restores the library's own
  * streams. The streams must outlive their use by the context. */
 sr_status sr_ctx_set_streams(sr_ctx *ctx, void *compute_stream, void *copy_stream);
+/* Device memory from the caller, e.g. PyTorch's caching allocator. When set,
+ * every device allocation the library makes for this context afterwards
+ * calls alloc(bytes, user), which returns device memory of the context's
+ * GPU aligned to 256 bytes (NULL = out of memory, reported as SR_ENOMEM),
+ * and hands it back with release(ptr, user) once the library is done with
+ * it (after the device work that used it has finished). Allocations stay
+ * charged to the device budget. Memory obtained before the call is still
+ * released the way it was obtained. alloc = NULL restores hipMalloc (release
+ * and user are then ignored). Both functions must stay callable until the
+ * context is destroyed; they are called from the thread that makes the
+ * library call that needs the memory. SR_EINVAL: alloc without release;
+ * SR_EDEVICE: a host-only context. */
+typedef void *(*sr_alloc_fn)(size_t bytes, void *user);
+typedef void (*sr_release_fn)(void *ptr, void *user);
+sr_status sr_ctx_set_allocator(sr_ctx *ctx, sr_alloc_fn alloc, sr_release_fn release, void *user);
 /* Device bytes currently charged to the budget, and the budget itself. */
 sr_status sr_ctx_memory(const sr_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
 
@@ -162,6 +195,13 @@ sr_status sr_graph_load_csr(sr_ctx *ctx, int32_t n, int64_t m, const int64_t *ro
  * copy_depth pages are copied). Pages live in pinned host memory owned by
  * the graph. */
 sr_status sr_graph_partition(sr_graph *g, int32_t num_parts, int32_t num_slots);
+/* sr_graph_partition_ex flags */
+#define SR_PART_EQUAL_EDGES 0x1u  /* boundary i is the first vertex whose in-edges start at or after
+                                     ceil(i * m / num_parts) (equal in-edge counts rather than equal
+                                     streamed bytes; a vertex still never straddles two pages, and
+                                     empty ranges are dropped, so fewer pages can result) */
+/* sr_graph_partition with flags (0 = the equal-byte split above). */
+sr_status sr_graph_partition_ex(sr_graph *g, int32_t num_parts, int32_t num_slots, uint32_t flags);
 
 typedef struct {
   int32_t n;
@@ -176,6 +216,9 @@ typedef struct {
   int32_t resident;          /* pages currently resident on the device */
   int32_t reordered;         /* loaded with SR_LOAD_REORDER */
 } sr_graph_info;
+/* Fill *out (host) with the graph's sizes and partition. Named with a _get
+ * suffix because C does not allow a function and a typedef to share the
+ * name sr_graph_info. */
 sr_status sr_graph_info_get(const sr_graph *g, sr_graph_info *out);
 
 /* Read-only view of page `page` (host pointers into the graph's pinned
@@ -286,7 +329,11 @@ sr_status sr_run_sweeps(const sr_graph *g, sr_sweep_record *out, int32_t max, in
 
 /* Copy the last run's vertex values to host memory: uint32 per vertex for
  * BFS (levels), SSSP (distances) and CC (labels), SR_INF if unreached;
- * float32 ranks for PageRank/PPR. dst_bytes must be >= 4n. */
+ * float32 ranks for PageRank/PPR, in the caller's vertex ids. This is the
+ * device-to-host transfer of the result that the paper counts in a solve's
+ * time (Section 5.2: times include data transfers). host_dst (host memory,
+ * owned by the caller) receives 4n bytes; dst_bytes must be >= 4n
+ * (SR_EINVAL otherwise); SR_ESTATE if no run has produced values. */
 sr_status sr_read_values(const sr_graph *g, void *host_dst, uint64_t dst_bytes);
 
 

@@ -7,7 +7,9 @@ never does. It shares no code with the GPU library.
 Plain definitions in FP64 / 64-bit integers, written in ``oracle.c``:
   * SSSP: Dijkstra (indexed binary heap); Bellman-Ford as a cross-check.
   * BFS: FIFO queue.
-  * CC: union-find; label = smallest vertex id of the component (Section 4.1).
+  * CC: union-find; label = smallest vertex id of the component (Section 4.1);
+    synchronous label propagation over OpenMP threads (the multi-core CPU
+    baseline), pinned to union-find.
   * PageRank / personalized PageRank: Jacobi power iteration,
     x = (1-d) t + d (P^T x + D t), D = dangling mass (the paper names PageRank
     in Section 4.3 but does not define it; this is the textbook form).
@@ -38,7 +40,7 @@ _i32, _i64, _u32, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -56,6 +58,7 @@ def _load():
         "or_bfs": [_i32, _p, _p, _i32, _p],
         "or_cc_union_find": [_i32, _p, _p, _p],
         "or_cc_labelprop_sync": [_i32, _p, _p, _i32, _p, _p, _p],
+        "or_cc_labelprop_parallel": [_i32, _p, _p, _i32, _p, _p, _p],
         "or_pagerank": [_i32, _p, _p, _dbl, _i32, _dbl, _i32, _p, _p, _p],
         "or_pagerank_residual": [_i32, _p, _p, _dbl, _i32, _p, _p],
         "or_sssp_certificate": [_i32, _p, _p, _p, _i32, _p, _p],
@@ -136,6 +139,18 @@ def cc_labelprop_sync(g, iters: int):
     _check(_load().or_cc_labelprop_sync(g.n, _ptr(off), _ptr(col), iters, _ptr(lab), _ptr(hist),
                                         ctypes.byref(nch)), "labelprop")
     return lab, hist, nch.value
+
+
+def cc_labelprop_parallel(g, threads: int = 0):
+    """Synchronous min-label propagation to the fixed point over `threads`
+    OpenMP threads (0 = all); g must be symmetric. Returns (labels, iterations,
+    threads used)."""
+    off, col, _ = _csr(g)
+    lab = np.empty(g.n, dtype=np.uint32)
+    it = ctypes.c_int32(); tu = ctypes.c_int32()
+    _check(_load().or_cc_labelprop_parallel(g.n, _ptr(off), _ptr(col), threads, _ptr(lab), ctypes.byref(it),
+                                            ctypes.byref(tu)), "parallel labelprop")
+    return lab, it.value, tu.value
 
 
 def pagerank(g, damping=0.85, seed: int = -1, tol=1e-13, max_iter=100000):

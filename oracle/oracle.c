@@ -27,6 +27,7 @@
  * Every function returns 0 on success and a negative code on bad input.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -226,6 +227,43 @@ int or_cc_labelprop_sync(int32_t n, const int64_t *off, const int32_t *col, int3
     if (hist) memcpy(hist + (size_t)it * (size_t)n, label, sizeof(uint32_t) * (size_t)n);
   }
   if (changed_iters) *changed_iters = nch;
+  free(old);
+  return 0;
+}
+
+/* Synchronous min-label propagation to the fixed point, every iteration
+ * split over `threads` OpenMP threads (0 = all): label_0 = id; in each
+ * iteration every vertex takes the minimum of its own label and its
+ * neighbours' labels from the previous iteration (two arrays, so the result
+ * and the iteration count do not depend on the thread count). The input
+ * must be symmetric (row v lists v's neighbours), so each vertex pulls from
+ * its own row. The fixed point gives every vertex the smallest id of its
+ * component (Section 4.1's example run to the end). Returns the iterations
+ * run, the last one changing nothing, in *iters, and the threads used in
+ * *threads_used. */
+int or_cc_labelprop_parallel(int32_t n, const int64_t *off, const int32_t *col, int32_t threads,
+                             uint32_t *label, int32_t *iters, int32_t *threads_used) {
+  if (n <= 0 || threads < 0) return -1;
+  uint32_t *old = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+  if (!old) return -2;
+  int T = threads > 0 ? threads : omp_get_max_threads();
+  for (int32_t v = 0; v < n; ++v) label[v] = (uint32_t)v;
+  int32_t it = 0;
+  int changed = 1;
+  while (changed) {
+    memcpy(old, label, sizeof(uint32_t) * (size_t)n);
+    changed = 0;
+#pragma omp parallel for num_threads(T) schedule(dynamic, 4096) reduction(| : changed)
+    for (int32_t v = 0; v < n; ++v) {
+      uint32_t x = old[v];
+      for (int64_t e = off[v]; e < off[v + 1]; ++e)
+        if (old[col[e]] < x) x = old[col[e]];
+      if (x < old[v]) { label[v] = x; changed = 1; }
+    }
+    it++;
+  }
+  if (iters) *iters = it;
+  if (threads_used) *threads_used = T;
   free(old);
   return 0;
 }

@@ -31,6 +31,8 @@ SR_RUN_SKIP_CLEAN = 0x20
 SR_RUN_NO_EARLY_BREAK = 0x40
 SR_RUN_WIDE_PAGES = 0x80
 SR_RUN_SPLIT_PAGES = 0x100
+SR_RUN_DETERMINISTIC = 0x200
+SR_PART_EQUAL_EDGES = 0x1
 SR_STOP_CONVERGED, SR_STOP_FP32_FLOOR, SR_STOP_MAX_PASSES = 1, 2, 3
 SR_INF = 0xFFFFFFFF
 
@@ -102,10 +104,12 @@ _SIGNATURES = {
     "sr_ctx_destroy": (None, [_P]),
     "sr_ctx_last_error": (ctypes.c_char_p, [_P]),
     "sr_ctx_set_streams": (ctypes.c_int, [_P, _P, _P]),
+    "sr_ctx_set_allocator": (ctypes.c_int, [_P, _P, _P, _P]),
     "sr_ctx_memory": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
     "sr_graph_load_csr": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, ctypes.c_uint32,
                                          ctypes.POINTER(_P)]),
     "sr_graph_partition": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "sr_graph_partition_ex": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]),
     "sr_graph_info_get": (ctypes.c_int, [_P, ctypes.POINTER(sr_graph_info)]),
     "sr_graph_page": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(sr_page_view)]),
     "sr_graph_order": (ctypes.c_int, [_P, _P, _P]),
@@ -171,6 +175,11 @@ def exported_symbols() -> list:
     return sorted(set(_SIGNATURES) | set(EXTRA_SIGNATURES))
 
 
+# sr_alloc_fn / sr_release_fn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class SeraphError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
@@ -225,6 +234,43 @@ class Context:
         """hipStream_t handles as integers (e.g. torch.cuda.Stream().cuda_stream)."""
         _check(lib().sr_ctx_set_streams(self.h, _P(compute or None), _P(copy or None)), self.h)
 
+    def set_allocator(self, alloc=None, release=None):
+        """Device memory from the caller (sr_ctx_set_allocator): alloc(nbytes) -> device
+        address (int, 0 = out of memory), release(address). None restores hipMalloc.
+        The callbacks stay referenced by the context object."""
+        if alloc is None:
+            self._alloc_cb = self._release_cb = None
+            _check(lib().sr_ctx_set_allocator(self.h, None, None, None), self.h)
+            return
+
+        def _a(nbytes, _user):
+            try:
+                return int(alloc(int(nbytes))) or None
+            except Exception:
+                return None
+
+        def _r(ptr, _user):
+            release(int(ptr))
+
+        self._alloc_cb, self._release_cb = ALLOC_FN(_a), RELEASE_FN(_r)
+        _check(lib().sr_ctx_set_allocator(self.h, ctypes.cast(self._alloc_cb, _P),
+                                          ctypes.cast(self._release_cb, _P), None), self.h)
+
+    def set_torch_allocator(self, stream=None):
+        """Device memory from PyTorch's caching allocator on the context's device
+        (blocks are associated with `stream`, default the current stream)."""
+        import torch
+        dev = self.device
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+
+        def _alloc(nbytes):
+            return torch.cuda.caching_allocator_alloc(nbytes, dev, st)
+
+        def _release(ptr):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self.set_allocator(_alloc, _release)
+
     def memory(self):
         u, b = ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib().sr_ctx_memory(self.h, ctypes.byref(u), ctypes.byref(b)), self.h)
@@ -262,8 +308,10 @@ class Graph:
             lib().sr_graph_destroy(self.h)
             self.h = None
 
-    def partition(self, num_parts: int = 0, num_slots: int = 0):
-        _check(lib().sr_graph_partition(self.h, num_parts, num_slots), self.ctx.h)
+    def partition(self, num_parts: int = 0, num_slots: int = 0, equal_edges: bool = False):
+        """Cut into pages: equal streamed bytes (default) or equal in-edge counts."""
+        _check(lib().sr_graph_partition_ex(self.h, num_parts, num_slots,
+                                           SR_PART_EQUAL_EDGES if equal_edges else 0), self.ctx.h)
 
     def info(self) -> dict:
         i = sr_graph_info()
@@ -300,7 +348,8 @@ class Graph:
             pr_change_eps: float = 0.0, audit: bool = False, force_stream: bool = False,
             resume: bool = False, fixed_inner: bool = False, copy_depth: int = 0, hetero: bool = False,
             sparse_switch: int = 0, skip_clean: bool = False, early_break: bool = True,
-            wide_pages: bool = False, split_pages: bool = False, check: bool = True) -> dict:
+            wide_pages: bool = False, split_pages: bool = False, deterministic: bool = False,
+            check: bool = True) -> dict:
         p = sr_run_params()
         p.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
         p.source = source
@@ -315,7 +364,8 @@ class Graph:
                    | (SR_RUN_RESUME if resume else 0) | (SR_RUN_FIXED_INNER if fixed_inner else 0)
                    | (SR_RUN_HETERO if hetero else 0) | (SR_RUN_SKIP_CLEAN if skip_clean else 0)
                    | (0 if early_break else SR_RUN_NO_EARLY_BREAK)
-                   | (SR_RUN_WIDE_PAGES if wide_pages else 0) | (SR_RUN_SPLIT_PAGES if split_pages else 0))
+                   | (SR_RUN_WIDE_PAGES if wide_pages else 0) | (SR_RUN_SPLIT_PAGES if split_pages else 0)
+                   | (SR_RUN_DETERMINISTIC if deterministic else 0))
         p.copy_depth = copy_depth
         p.sparse_switch = sparse_switch
         st = sr_run_stats()

@@ -45,21 +45,42 @@ sr_status sr_ctx::dalloc(void **p, uint64_t bytes, const char *what) {
     return fail(SR_EBUDGET, std::string("device budget exceeded allocating ") + what + " (" +
                                 std::to_string(bytes) + " B, used " + std::to_string(used) +
                                 " of " + std::to_string(budget) + ")");
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) { *p = nullptr; return hip_fail(e, what); }
+  Alloc rec;
+  rec.bytes = bytes;
+  if (hook_alloc) {
+    void *q = hook_alloc((size_t)bytes, hook_user);
+    if (!q) return fail(SR_ENOMEM, std::string("caller's allocator returned NULL for ") + what);
+    if ((uintptr_t)q & 255u) {
+      hook_release(q, hook_user);
+      return fail(SR_EDEVICE, std::string("caller's allocator returned memory not aligned to 256 bytes for ") +
+                                  what);
+    }
+    *p = q;
+    rec.release = hook_release;
+    rec.user = hook_user;
+  } else {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) { *p = nullptr; return hip_fail(e, what); }
+  }
   used += bytes;
-  allocs[*p] = bytes;
+  allocs[*p] = rec;
   return SR_OK;
 }
 
 void sr_ctx::dfree(void *p) {
   if (!p) return;
   auto it = allocs.find(p);
-  if (it != allocs.end()) {
-    used -= it->second;
-    allocs.erase(it);
+  if (it == allocs.end()) { (void)hipFree(p); return; }
+  const Alloc rec = it->second;
+  used -= rec.bytes;
+  allocs.erase(it);
+  if (rec.release) {
+    // the caller may hand the memory to other work at once: finish ours first
+    (void)hipDeviceSynchronize();
+    rec.release(p, rec.user);
+  } else {
+    (void)hipFree(p);
   }
-  (void)hipFree(p);
 }
 
 // --------------------------------------------------------------- context
@@ -112,7 +133,10 @@ extern "C" void sr_ctx_destroy(sr_ctx *c) {
   if (!c->host_only) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    for (auto &kv : c->allocs) (void)hipFree(kv.first);
+    for (auto &kv : c->allocs) {
+      if (kv.second.release) kv.second.release(kv.first, kv.second.user);
+      else (void)hipFree(kv.first);
+    }
     if (c->ring_host) (void)hipHostFree(c->ring_host);
     if (c->own_compute) (void)hipStreamDestroy(c->own_compute);
     if (c->own_copy) (void)hipStreamDestroy(c->own_copy);
@@ -129,6 +153,16 @@ extern "C" sr_status sr_ctx_set_streams(sr_ctx *c, void *compute, void *copy) {
   if (c->host_only) return c->fail(SR_EDEVICE, "host-only context has no device");
   c->compute = compute ? (hipStream_t)compute : c->own_compute;
   c->copy = copy ? (hipStream_t)copy : c->own_copy;
+  return SR_OK;
+}
+
+extern "C" sr_status sr_ctx_set_allocator(sr_ctx *c, sr_alloc_fn alloc, sr_release_fn release, void *user) {
+  if (!c) return SR_EINVAL;
+  if (c->host_only) return c->fail(SR_EDEVICE, "host-only context has no device");
+  if (alloc && !release) return c->fail(SR_EINVAL, "an allocator needs its release function");
+  c->hook_alloc = alloc;
+  c->hook_release = alloc ? release : nullptr;
+  c->hook_user = alloc ? user : nullptr;
   return SR_OK;
 }
 
@@ -152,6 +186,7 @@ static void release_state(sr_graph *g) {
   auto &s = g->state;
   g->ctx->dfree(s.value);
   g->ctx->dfree(s.contrib);
+  g->ctx->dfree(s.contrib_next);
   g->ctx->dfree(s.inv_outdeg);
   g->ctx->dfree(s.status);
   g->ctx->dfree(s.ctl);
@@ -235,8 +270,14 @@ static uint64_t scratch_bytes(const Page &p) {
 }
 
 extern "C" sr_status sr_graph_partition(sr_graph *g, int32_t nparts, int32_t nslots) {
+  return sr_graph_partition_ex(g, nparts, nslots, 0u);
+}
+
+extern "C" sr_status sr_graph_partition_ex(sr_graph *g, int32_t nparts, int32_t nslots, uint32_t flags) {
   if (!g) return SR_EINVAL;
   sr_ctx *c = g->ctx;
+  if (flags & ~SR_PART_EQUAL_EDGES) return c->fail(SR_EINVAL, "unknown partition flags");
+  const bool eq = (flags & SR_PART_EQUAL_EDGES) != 0;
   if (nparts < 0) return c->fail(SR_EINVAL, "num_parts must be >= 0");
   if (nslots == 0) nslots = 4;
   if (nslots < 2 || nslots > MAXW + 1) return c->fail(SR_EINVAL, "num_slots must be in [2, 17]");
@@ -251,11 +292,11 @@ extern "C" sr_status sr_graph_partition(sr_graph *g, int32_t nparts, int32_t nsl
     uint64_t st = state_bytes(g->n, A_SSSP);
     if (c->budget <= st) return c->fail(SR_EBUDGET, "budget cannot hold the vertex state");
     const uint64_t slot = (c->budget - st) / (uint64_t)nslots - 4096;
-    const int32_t P = sr::auto_parts(g, slot);
+    const int32_t P = sr::auto_parts(g, slot, eq);
     if (P < 1) return c->fail(SR_EBUDGET, "no partition fits the budget");
-    return sr::make_pages(g, P);
+    return sr::make_pages(g, P, eq);
   }
-  return sr::make_pages(g, nparts);
+  return sr::make_pages(g, nparts, eq);
 }
 
 extern "C" sr_status sr_graph_info_get(const sr_graph *g, sr_graph_info *o) {
@@ -377,6 +418,7 @@ struct Runner {
   sr_graph *g;
   sr_ctx *c;
   int algo, pvu;
+  bool det = false;    // deterministic PageRank sweeps
   sr_run_params prm;
   Diagram dia;
   bool weights;
@@ -491,6 +533,8 @@ struct Runner {
     a.ring_mask = c->ring_mask;
     a.value = g->state.value;
     a.contrib = g->state.contrib;
+    a.det = det ? 1 : 0;
+    a.contrib_next = det ? g->state.contrib_next : nullptr;
     a.inv_outdeg = g->state.inv_outdeg;
     a.status = g->state.status;
     a.dia = dia;
@@ -567,8 +611,8 @@ sr_status sr::ensure_residency(sr_graph *g, bool weights, bool force_stream, boo
   }
   const uint64_t freeb = c->budget - c->used + [&] {
     uint64_t mine = 0;
-    for (auto p : r.buf) { auto it = c->allocs.find(p); if (it != c->allocs.end()) mine += it->second; }
-    for (auto p : r.partial) { auto it = c->allocs.find(p); if (it != c->allocs.end()) mine += it->second; }
+    for (auto p : r.buf) { auto it = c->allocs.find(p); if (it != c->allocs.end()) mine += it->second.bytes; }
+    for (auto p : r.partial) { auto it = c->allocs.find(p); if (it != c->allocs.end()) mine += it->second.bytes; }
     return mine;
   }();
   const bool want_resident = !force_stream && all + 4096 <= freeb;
@@ -643,7 +687,8 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (p.max_inner_iters == 0) p.max_inner_iters = 4;
   if (p.max_passes < 0 || p.max_inner_iters < 0) return c->fail(SR_EINVAL, "negative limits");
   if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_FORCE_STREAM | SR_RUN_RESUME | SR_RUN_FIXED_INNER | SR_RUN_HETERO |
-                  SR_RUN_SKIP_CLEAN | SR_RUN_NO_EARLY_BREAK | SR_RUN_WIDE_PAGES | SR_RUN_SPLIT_PAGES))
+                  SR_RUN_SKIP_CLEAN | SR_RUN_NO_EARLY_BREAK | SR_RUN_WIDE_PAGES | SR_RUN_SPLIT_PAGES |
+                  SR_RUN_DETERMINISTIC))
     return c->fail(SR_EINVAL, "unknown run flags");
   const bool pr = R.algo == A_PR || R.algo == A_PPR;
   // defaults (Section 4.3 discussion): BFS/CC strong, SSSP/PageRank weak;
@@ -685,6 +730,12 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (g->pages.empty())
     if ((s = sr_graph_partition(g, 0, 0)) != SR_OK) return s;
   if ((s = ensure_state(g, R.algo)) != SR_OK) return s;
+  // deterministic schedule; PageRank also reads a per-sweep snapshot of the
+  // gathered terms (second buffer, allocated once and kept with the state)
+  R.det = (p.flags & SR_RUN_DETERMINISTIC) != 0;
+  if (R.det && pr && !g->state.contrib_next &&
+      (s = c->dalloc((void **)&g->state.contrib_next, 4ull * g->n, "pagerank contrib snapshot")) != SR_OK)
+    return s;
   // forced split-width images: the slots are sized to hold them too
   auto residency = [&]() -> sr_status {
     uint64_t min_slot = 0;
@@ -701,7 +752,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     if (c->budget > st_b + c->used) {
       for (int32_t P = (int32_t)g->pages.size() * 2; P <= g->n && s == SR_EBUDGET; P *= 2) {
         release_residency(g);
-        if ((s = sr::make_pages(g, P)) != SR_OK) return s;
+        if ((s = sr::make_pages(g, P, g->equal_edges)) != SR_OK) return s;
         s = residency();
       }
     }
@@ -824,6 +875,9 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   // PageRank, the rank and dangling sums start afresh from the values
   if (e == hipSuccess) e = launch_init_ctl(rs.ctl, init, c->compute);
   if (e == hipSuccess && pr) e = launch_pr_sums((const float *)rs.value, rs.inv_outdeg, g->n, rs.ctl, c->compute);
+  // the snapshot's second buffer starts equal to the gathered terms
+  if (e == hipSuccess && pr && R.det)
+    e = hipMemcpyAsync(rs.contrib_next, rs.contrib, 4ull * g->n, hipMemcpyDeviceToDevice, c->compute);
   if (e == hipSuccess) e = launch_init_stripes(rs.stripes, c->compute);
   // heavy-vertex accumulators start at the reduction's identity (min: all
   // ones; PageRank: fixed-point zero); the close kernel restores it after
@@ -1063,6 +1117,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
           pass_changed |= changed;
           if (fixed_inner) continue;                // fixed re-entry count (ablation schedules)
           if (!changed) break;                      // the window reached its local fixed point
+          if (R.det) continue;                      // deterministic: the copy's timing does not decide
           if (!copying) break;                      // nothing in flight to wait for
           if (hipEventQuery(copy_done[next_slot]) == hipSuccess) break;  // next page landed: slide
         }

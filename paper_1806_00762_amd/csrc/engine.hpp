@@ -35,6 +35,7 @@ struct RunState {
   int32_t n = 0;
   uint32_t *value = nullptr;
   float *contrib = nullptr;
+  float *contrib_next = nullptr;  // deterministic PageRank sweeps (allocated on first use)
   float *inv_outdeg = nullptr;
   uint8_t *status = nullptr;
   Ctl *ctl = nullptr;
@@ -70,7 +71,18 @@ struct sr_ctx {
   mutable std::string err;
   hipStream_t own_compute = nullptr, own_copy = nullptr;
   hipStream_t compute = nullptr, copy = nullptr;
-  std::unordered_map<void *, uint64_t> allocs;
+  // one entry per live device allocation: its charged size and, when it
+  // came from the caller's allocator, how to give it back
+  struct Alloc {
+    uint64_t bytes = 0;
+    sr_release_fn release = nullptr;  // null: hipMalloc'd
+    void *user = nullptr;
+  };
+  std::unordered_map<void *, Alloc> allocs;
+  // caller-provided device allocator (sr_ctx_set_allocator), null = hipMalloc
+  sr_alloc_fn hook_alloc = nullptr;
+  sr_release_fn hook_release = nullptr;
+  void *hook_user = nullptr;
   // host-mapped per-sweep record ring
   sr::SweepRecord *ring_host = nullptr;
   sr::SweepRecord *ring_dev = nullptr;
@@ -106,6 +118,7 @@ struct sr_graph {
   std::vector<int32_t> outdeg;
   int32_t nparts = 0, nslots = 0;
   bool auto_parts = false;
+  bool equal_edges = false;  // pages cut by in-edge count (SR_PART_EQUAL_EDGES)
   std::vector<sr::Page> pages;
   sr::Residency res;
   sr::RunState state;
@@ -134,7 +147,8 @@ sr_status build_in_csr(sr_graph *g, const int64_t *row_offsets, const int32_t *c
 void relabel_by_degree(int32_t n, const int64_t *ro, const int32_t *ci, const uint32_t *wi, bool symmetrize,
                        std::vector<int32_t> &rank, std::vector<int32_t> &perm, std::vector<int64_t> &ro2,
                        std::vector<int32_t> &ci2, std::vector<uint32_t> &w2);
-sr_status make_pages(sr_graph *g, int32_t nparts);
+// equal_edges: boundaries by in-edge count instead of streamed bytes
+sr_status make_pages(sr_graph *g, int32_t nparts, bool equal_edges = false);
 // split-width images of every page (PageHeader::split), for streamed min
 // programs; built once per partition
 bool split_eligible(const sr_graph *g);
@@ -147,7 +161,7 @@ uint64_t estimate_split_bytes(const sr_graph *g);
 sr_status build_split_pages(sr_graph *g);
 // Smallest page count whose largest streamed page (with its chunk scratch)
 // fits slot_bytes; -1 if none does.
-int32_t auto_parts(const sr_graph *g, uint64_t slot_bytes);
+int32_t auto_parts(const sr_graph *g, uint64_t slot_bytes, bool equal_edges = false);
 void free_pages(sr_graph *g);
 uint64_t graph_bytes(const sr_graph *g);
 int host_threads();

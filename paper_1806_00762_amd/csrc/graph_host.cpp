@@ -521,29 +521,29 @@ static PageHeader page_header(const sr_graph *g, int32_t vb, int32_t ve) {
   return h;
 }
 
-// Equal-edge split into nparts contiguous destination ranges: boundary i is
-// the first vertex whose in-edges start at or after ceil(i * m / nparts).
-// Empty ranges (a vertex heavier than m / nparts) are dropped.
 // Streamed bytes of the vertices [0, v): one offset per vertex and one edge
 // word per in-edge (plus a separate u32 weight when weights are not packed).
-static uint64_t stream_cost(const sr_graph *g, int32_t v) {
+// With equal_edges the cost is the in-edge count alone.
+static uint64_t stream_cost(const sr_graph *g, int32_t v, bool equal_edges = false) {
+  if (equal_edges) return (uint64_t)g->in_off[v];
   const uint64_t eb = (g->weighted && !g->packed) ? 8 : 4;
   return 4ull * (uint64_t)v + eb * (uint64_t)g->in_off[v];
 }
 
 // Split into nparts contiguous destination ranges of about equal streamed
-// bytes: boundary i is the first vertex whose prefix cost reaches
-// ceil(i * total / nparts); a vertex never straddles two pages.
-static std::vector<int32_t> split_bounds(const sr_graph *g, int32_t nparts) {
+// bytes (or equal in-edge counts): boundary i is the first vertex whose
+// prefix cost reaches ceil(i * total / nparts); a vertex never straddles two
+// pages, and empty ranges (a vertex heavier than a share) are dropped.
+static std::vector<int32_t> split_bounds(const sr_graph *g, int32_t nparts, bool equal_edges = false) {
   std::vector<int32_t> bounds;
   bounds.push_back(0);
-  const uint64_t total = stream_cost(g, g->n);
+  const uint64_t total = stream_cost(g, g->n, equal_edges);
   for (int32_t i = 1; i < nparts; ++i) {
     const uint64_t target = (total * (uint64_t)i + nparts - 1) / (uint64_t)nparts;
     int32_t lo = 0, hi = g->n;  // smallest b with stream_cost(b) >= target
     while (lo < hi) {
       const int32_t mid = lo + (hi - lo) / 2;
-      if (stream_cost(g, mid) >= target) hi = mid; else lo = mid + 1;
+      if (stream_cost(g, mid, equal_edges) >= target) hi = mid; else lo = mid + 1;
     }
     if (lo > bounds.back() && lo < g->n) bounds.push_back(lo);
   }
@@ -551,11 +551,11 @@ static std::vector<int32_t> split_bounds(const sr_graph *g, int32_t nparts) {
   return bounds;
 }
 
-int32_t auto_parts(const sr_graph *g, uint64_t slot_bytes) {
+int32_t auto_parts(const sr_graph *g, uint64_t slot_bytes, bool equal_edges) {
   const uint64_t total = stream_cost(g, g->n);
   int32_t P = (int32_t)std::max<uint64_t>(1, (total + slot_bytes - 1) / std::max<uint64_t>(slot_bytes, 1));
   while (P < g->n) {
-    const std::vector<int32_t> b = split_bounds(g, P);
+    const std::vector<int32_t> b = split_bounds(g, P, equal_edges);
     uint64_t mx = 0;
     for (size_t i = 0; i + 1 < b.size(); ++i) {
       const PageHeader h = page_header(g, b[i], b[i + 1]);
@@ -568,10 +568,10 @@ int32_t auto_parts(const sr_graph *g, uint64_t slot_bytes) {
   return -1;
 }
 
-sr_status make_pages(sr_graph *g, int32_t nparts) {
+sr_status make_pages(sr_graph *g, int32_t nparts, bool equal_edges) {
   if (nparts < 1) return g->ctx->fail(SR_EINVAL, "num_parts must be >= 1");
   if (nparts > g->n) nparts = g->n;
-  const std::vector<int32_t> bounds = split_bounds(g, nparts);
+  const std::vector<int32_t> bounds = split_bounds(g, nparts, equal_edges);
   free_pages(g);
   const int32_t P = (int32_t)bounds.size() - 1;
   g->pages.resize(P);
@@ -593,6 +593,7 @@ sr_status make_pages(sr_graph *g, int32_t nparts) {
     for (int64_t p = lo; p < hi; ++p) fill_page(g, bounds[p], bounds[p + 1], g->pages[p]);
   }, 2);
   g->nparts = P;
+  g->equal_edges = equal_edges;
   return SR_OK;
 }
 

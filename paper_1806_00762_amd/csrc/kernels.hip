@@ -83,7 +83,8 @@ struct Run {
   int early;  // BFS early break (strong prediction, normal phase)
   uint32_t threshold;
   uint32_t *value;
-  float *contrib;
+  float *contrib;    // gathered terms (a snapshot under deterministic sweeps)
+  float *contrib_w;  // where a pull writes its vertex's new term (contrib, or the snapshot's next buffer)
   const float *inv_outdeg;
   uint8_t *status;
   const Diagram *dia;
@@ -167,11 +168,17 @@ struct Red {
   }
 };
 
+// Pull result handed to the epilogue: the u32 minimum, or the PageRank sum
+// in double (exact for a float sum, and for the fixed-point sums of
+// deterministic sweeps and heavy-vertex chunks).
+template <int ALGO>
+using RedArg = typename std::conditional<is_pr<ALGO>(), double, uint32_t>::type;
+
 // Epilogue of one vertex: compare, write, advance the predictor state,
 // count. `computed` says whether red holds the pull result.
 template <int ALGO>
 __device__ inline bool epilogue(const Run &r, int32_t v, const Gate &g, bool computed,
-                                typename Red<ALGO>::T red, uint32_t deg, Acc &acc) {
+                                RedArg<ALGO> red, uint32_t deg, Acc &acc) {
   bool changed = false;
   if (computed) {
     if constexpr (is_pr<ALGO>()) {
@@ -180,14 +187,14 @@ __device__ inline bool epilogue(const Run &r, int32_t v, const Gate &g, bool com
       // decay only at rate d; the fixed point (mass 1) is the same
       const double t = r.pr_seed < 0 ? (double)r.base_uniform : (v == r.pr_seed ? 1.0 : 0.0);
       float oldf = __uint_as_float(g.old);
-      float nv = (float)((1.0 - r.damping) * t + r.damping * r.inv_mass * ((double)red + r.dangling * t));
+      float nv = (float)((1.0 - r.damping) * t + r.damping * r.inv_mass * (red + r.dangling * t));
       float diff = nv - oldf;
       bool would = fabsf(diff) > r.pr_eps;
       if (g.attempt) {
         changed = would;
         r.value[v] = __float_as_uint(nv);
         float iod = r.inv_outdeg[v];
-        r.contrib[v] = nv * iod;
+        r.contrib_w[v] = nv * iod;
         acc.l1 += fabs((double)nv - (double)oldf);
         acc.dmass += (double)nv - (double)oldf;
         if (iod == 0.0f) acc.ddelta += (double)nv - (double)oldf;
@@ -255,8 +262,10 @@ __device__ inline void frontier_push(const Run &r, bool changed, int32_t v) {
 // runs of edges of the same vertex are reduced in registers before one LDS
 // atomic. Phase 3 runs the epilogues.
 
-template <bool SPLIT>
+template <bool SPLIT_, bool DET_ = false>
 struct TileLds {
+  static constexpr bool SPLIT = SPLIT_;
+  static constexpr bool DET = DET_;
   int32_t pos[TILE_V + 1];  // first compacted (wide) edge position of each attempting vertex
   int32_t eb[TILE_V];       // its first (wide) in-edge (page-local) minus that position
   // split images: the same for the narrow list (one unused entry otherwise)
@@ -264,6 +273,8 @@ struct TileLds {
   int32_t eb_n[SPLIT ? TILE_V : 1];
   int32_t vl[TILE_V];       // its page-local vertex id
   uint32_t acc[TILE_V];     // reduction (u32 min, or f32 sum bits)
+  // deterministic PageRank sweeps: the sum in 2^-54 fixed point (exact, order-free)
+  unsigned long long acc64[DET_ ? TILE_V : 1];
   uint32_t old[TILE_V];
   uint8_t att[TILE_V];
   uint8_t st[TILE_V];
@@ -279,8 +290,9 @@ struct TileLds {
 // inclusive max-scan carries each mark over its range (codes grow with the
 // position, since the wide codes lie above the narrow ones). Called by every
 // thread of the block.
-template <bool SPLIT>
-__device__ inline void tile_map(TileLds<SPLIT> &s, int An, int At, int Kt) {
+template <typename L>
+__device__ inline void tile_map(L &s, int An, int At, int Kt) {
+  constexpr bool SPLIT = L::SPLIT;
   constexpr int PER = TILE_E / BLOCK;  // consecutive entries per thread in the scan
   static_assert(PER == 16, "two 16-byte LDS words per thread");
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
@@ -329,11 +341,34 @@ __device__ inline void tile_map(TileLds<SPLIT> &s, int An, int At, int Kt) {
 
 // Folds a thread's gathered values into the LDS accumulators: runs of one
 // vertex (kk) within a group are combined in registers first.
-template <int ALGO, int EPT, int RUN, bool SPLIT>
-__device__ inline void tile_fold(TileLds<SPLIT> &s, const int (&kk)[EPT], const typename Red<ALGO>::T (&x)[EPT]) {
+template <int ALGO, int EPT, int RUN, typename L>
+__device__ inline void tile_fold(L &s, const int (&kk)[EPT], const typename Red<ALGO>::T (&x)[EPT]) {
   using R = Red<ALGO>;
   using T = typename R::T;
   constexpr int G = EPT / RUN;
+  if constexpr (is_pr<ALGO>() && L::DET) {
+    // each term rounded to fixed point once, so the sum does not depend on
+    // which thread adds which run, or in which order
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+      int ck = kk[gi * RUN];
+      unsigned long long cur = (unsigned long long)llrint((double)x[gi * RUN] * FIX_ONE);
+#pragma unroll
+      for (int i = 1; i < RUN; ++i) {
+        const int j = gi * RUN + i;
+        const unsigned long long q = (unsigned long long)llrint((double)x[j] * FIX_ONE);
+        if (kk[j] == ck) {
+          cur += q;
+        } else {
+          if (ck >= 0) atomicAdd(&s.acc64[ck], cur);
+          ck = kk[j];
+          cur = q;
+        }
+      }
+      if (ck >= 0) atomicAdd(&s.acc64[ck], cur);
+    }
+    return;
+  }
 #pragma unroll
   for (int gi = 0; gi < G; ++gi) {
     int ck = kk[gi * RUN];
@@ -367,8 +402,8 @@ __device__ inline void tile_fold(TileLds<SPLIT> &s, const int (&kk)[EPT], const 
 // group finds its first position's vertex by binary search (monotone over
 // the groups) and walks forward; runs of one vertex within a group are
 // reduced in registers before one LDS atomic.
-template <int ALGO, int EPT, bool PACKED>
-__device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds<false> &s, int At, int Kt) {
+template <int ALGO, int EPT, bool PACKED, typename L>
+__device__ inline void tile_gather(const Run &r, const PageCtx &p, L &s, int At, int Kt) {
   using R = Red<ALGO>;
   using T = typename R::T;
   const int tid = threadIdx.x;
@@ -417,8 +452,8 @@ __device__ inline void tile_gather(const Run &r, const PageCtx &p, TileLds<false
 // together. Every position issues one aligned 32-bit load: the edge word, or
 // the word holding the u16 id; SSSP also loads the u8 weight of narrow
 // positions (wide positions read the first one, unused).
-template <int ALGO, int EPT>
-__device__ inline void tile_gather_split(const Run &r, const PageCtx &p, TileLds<true> &s, int An, int At, int Kt) {
+template <int ALGO, int EPT, typename L>
+__device__ inline void tile_gather_split(const Run &r, const PageCtx &p, L &s, int An, int At, int Kt) {
   using R = Red<ALGO>;
   using T = typename R::T;
   const int tid = threadIdx.x;
@@ -488,8 +523,9 @@ __device__ inline void tile_gather_split(const Run &r, const PageCtx &p, TileLds
   tile_fold<ALGO, EPT, RUN>(s, kk, x);
 }
 
-template <int ALGO, int EDGES_PER_THREAD, bool PACKED, bool SPLIT>
-__device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, TileLds<SPLIT> &s) {
+template <int ALGO, int EDGES_PER_THREAD, bool PACKED, typename L>
+__device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, L &s) {
+  constexpr bool SPLIT = L::SPLIT;
   using R = Red<ALGO>;
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int32_t t0 = p.tiles[2 * item], t1 = p.tiles[2 * item + 1];
@@ -582,6 +618,7 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
       s.vl[ka] = lv[j];
       // the early break's probe (BFS) seeds the reduction
       s.acc[ka] = ALGO == A_BFS ? seed[j] : R::bits(R::identity());
+      if constexpr (L::DET) s.acc64[ka] = 0ull;
       s.old[ka] = gt[j].old;
       s.att[ka] = gt[j].attempt ? 1 : 0;
       s.st[ka] = gt[j].st;
@@ -608,7 +645,10 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, T
     uint32_t dn_k = 0u;
     if constexpr (SPLIT) dn_k = (uint32_t)(s.pos_n[k + 1] - s.pos_n[k]);
     if (SPLIT && g.attempt) acc.narrow += dn_k;
-    const bool ch = epilogue<ALGO>(r, p.v_begin + s.vl[k], g, true, R::from_bits(s.acc[k]),
+    RedArg<ALGO> red;
+    if constexpr (L::DET && is_pr<ALGO>()) red = (double)s.acc64[k] / FIX_ONE;
+    else red = R::from_bits(s.acc[k]);
+    const bool ch = epilogue<ALGO>(r, p.v_begin + s.vl[k], g, true, red,
                                    (uint32_t)(s.pos[k + 1] - s.pos[k]) + dn_k, acc);
     frontier_push(r, ch, p.v_begin + s.vl[k]);
   }
@@ -806,14 +846,14 @@ __device__ inline void publish_record(const SweepRecord *src, SweepRecord *dst) 
 }
 
 // ------------------------------------------------------------ the sweep
-template <int ALGO, int EPT, bool PACKED, bool SPLIT>
+template <int ALGO, int EPT, bool PACKED, bool SPLIT, bool DET = false>
 __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   Ctl *ctl = a.ctl;
   if (ctl->done) return;  // converged: every block leaves before counting
   __shared__ uint32_t s_hist[8];
   __shared__ uint32_t s_u32[WAVES][7];
   __shared__ double s_f64[WAVES][3];
-  __shared__ TileLds<SPLIT> s_tile;
+  __shared__ TileLds<SPLIT, DET> s_tile;
   if (threadIdx.x < 8) s_hist[threadIdx.x] = 0;
 
   // locate (page, section, item) of this block: section 0 = tiles, 1 = chunks
@@ -852,6 +892,7 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   r.threshold = ctl->threshold;
   r.value = a.value;
   r.contrib = a.contrib;
+  r.contrib_w = a.det ? a.contrib_next : a.contrib;
   r.inv_outdeg = a.inv_outdeg;
   r.status = a.status;
   r.dia = &a.dia;
@@ -872,7 +913,7 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   // a launch over pages without any work still runs one block, so the
   // sweep (and the pass) is closed the same way
   if (b < a.blk_prefix[a.nent * NSEC]) {
-    if (sec == 0) sweep_tile<ALGO, EPT, PACKED, SPLIT>(r, p, item, acc, s_tile);
+    if (sec == 0) sweep_tile<ALGO, EPT, PACKED>(r, p, item, acc, s_tile);
     else sweep_chunk<ALGO, PACKED, SPLIT>(r, p, item);
   }
 
@@ -974,6 +1015,7 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   r.threshold = s_ctl.threshold;
   r.value = a.value;
   r.contrib = a.contrib;
+  r.contrib_w = a.det ? a.contrib_next : a.contrib;
   r.inv_outdeg = a.inv_outdeg;
   r.status = a.status;
   r.dia = &a.dia;
@@ -1011,8 +1053,8 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
       const int32_t v = h->v_begin + x.vl;
       // taken even when the gate says skip, so every accumulator is back at
       // the identity when the next sweep starts
-      T t;
-      if constexpr (is_pr<ALGO>()) t = (float)((double)(long long)atomicExch(&part[first], 0ull) / FIX_ONE);
+      RedArg<ALGO> t;
+      if constexpr (is_pr<ALGO>()) t = (double)(long long)atomicExch(&part[first], 0ull) / FIX_ONE;
       else t = R::from_bits(atomicExch(reinterpret_cast<uint32_t *>(&part[first]), INF));
       Gate g = gate_of(r, v);
       bool comp = g.attempt || r.audit;
@@ -1059,6 +1101,20 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   __syncthreads();
   if (tid < CW) reinterpret_cast<uint32_t *>(a.ctl)[tid] = reinterpret_cast<const uint32_t *>(&s_ctl)[tid];
   if (a.ring) publish_record(&s_rec, &a.ring[s_rec.seq & a.ring_mask]);
+}
+
+// Deterministic PageRank sweeps: copy the terms the sweep wrote for the
+// window's vertices back into the gathered array. contrib_next equals
+// contrib everywhere outside a sweep (it starts as a copy and every sweep is
+// followed by this copy), so a sweep that did nothing copies equal values.
+// Grid: x strides over a page's vertices, y = page of the window.
+__global__ void __launch_bounds__(BLOCK) det_commit_kernel(SweepArgs a) {
+  const int ent = blockIdx.y;
+  if (ent >= a.nent) return;
+  const PageHeader *h = reinterpret_cast<const PageHeader *>(a.base[ent]);
+  const int32_t v0 = h->v_begin, v1 = h->v_begin + h->n_p;
+  for (int32_t v = v0 + (int32_t)(blockIdx.x * BLOCK + threadIdx.x); v < v1; v += (int32_t)(gridDim.x * BLOCK))
+    a.contrib[v] = a.contrib_next[v];
 }
 
 __global__ void end_pass_kernel(Ctl *ctl, SweepRecord *ring, uint32_t mask) {
@@ -1198,6 +1254,15 @@ static void launch_pair(const SweepArgs &a, hipStream_t s, hipEvent_t mid) {
   // split-width images serve only the min programs, and their wide edge
   // words are always packed
   constexpr bool CAN_SPLIT = ALGO == A_BFS || ALGO == A_SSSP || ALGO == A_CC;
+  constexpr bool PR = ALGO == A_PR || ALGO == A_PPR;
+  if (PR && a.det) {
+    if (a.packed) hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true, false, PR>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, false, false, PR>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+    if (mid) (void)hipEventRecord(mid, s);
+    hipLaunchKernelGGL(close_kernel<ALGO>, dim3(1), dim3(CLOSE_THREADS), 0, s, a);
+    if (a.nent > 0) hipLaunchKernelGGL(det_commit_kernel, dim3(64, a.nent), dim3(BLOCK), 0, s, a);
+    return;
+  }
   if (CAN_SPLIT && a.split && a.packed) {
     hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true, CAN_SPLIT>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
   } else if (a.packed) {

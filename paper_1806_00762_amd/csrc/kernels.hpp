@@ -21,6 +21,8 @@ struct SweepArgs {
   int32_t packed;          // edge words carry the weight in their top byte
   int32_t early;           // BFS under strong prediction: stop at a first in-neighbour on the threshold level
   int32_t split;           // the pages in the slots are split-width images (min programs)
+  int32_t det;             // PageRank: deterministic sweep (gathers read contrib, pulls write
+                           // contrib_next, whose window ranges are copied back after the sweep)
   double damping;
   float pr_eps;
   Ctl *ctl;                // device control block
@@ -28,6 +30,7 @@ struct SweepArgs {
   uint32_t ring_mask;
   uint32_t *value;         // BFS level / SSSP distance / CC label (u32), or PageRank rank (f32 bits)
   float *contrib;          // PageRank: rank / outdeg, gathered by the pull
+  float *contrib_next;     // deterministic PageRank: the terms this sweep writes
   const float *inv_outdeg; // PageRank: 1 / outdeg (0 for dangling vertices)
   uint8_t *status;         // weak predictor state per vertex
   Stripe *stripes;         // NSTRIPE counter stripes (identity outside a sweep)

@@ -115,6 +115,35 @@ def test_in_csr_and_pages(sr, sym):
     G.close(); c.close()
 
 
+@pytest.mark.parametrize("parts", [1, 2, 4, 7, 64])
+def test_equal_edge_pages(sr, parts):
+    """SR_PART_EQUAL_EDGES: boundary i is the first vertex whose in-edges
+    start at or after ceil(i * m / parts), empty ranges dropped (a vertex
+    never straddles two pages). The expected cut is computed here from the
+    in-degree counts of the input, not read back from the library."""
+    c = sr.Context(-1, 1 << 30)
+    src = graphgen.recipes.pagerank_s16() if parts == 4 else graphgen.rmat(12, 8, seed=11)
+    G = c.load(src)
+    G.partition(parts, 4, equal_edges=True)
+    indeg = np.bincount(src.col, minlength=src.n).astype(np.int64)
+    start = np.concatenate([[0], np.cumsum(indeg)])          # in-edges before each vertex
+    m = int(start[-1])
+    want = [0]
+    for i in range(1, parts):
+        b = int(np.searchsorted(start, -(-i * m // parts), side="left"))
+        if want[-1] < b < src.n:
+            want.append(b)
+    want.append(src.n)
+    info = G.info()
+    got = [G.page(p)["v_begin"] for p in range(info["num_parts"])] + [src.n]
+    assert got == want
+    for p in range(info["num_parts"]):
+        pg = G.page(p)
+        # each page holds at most a share plus one vertex's in-edges
+        assert int(pg["offsets"][-1]) <= -(-m // parts) + int(indeg.max())
+    G.close(); c.close()
+
+
 def test_argument_checks(sr):
     c = sr.Context(-1, 1 << 30)
     bad = graphgen.Graph(3, np.array([0, 1, 2, 2]), np.array([1, 5], dtype=np.int32), None)

@@ -1,10 +1,12 @@
-"""Full-size workloads: PageRank on R-MAT scale 16 (4 equal-byte pages, up to
+"""Full-size workloads: PageRank on R-MAT scale 16 (4 equal-edge pages, up to
 4 in-GPU sweeps per page per pass), streamed SSSP on R-MAT scale 22 under a
-device budget of 1/4 of the graph bytes (the benchmark's configuration),
-streamed CC on R-MAT scale 24 / edge factor 32 and its uniform twin, the
+device budget of 1/4 of the graph bytes, streamed CC on R-MAT scale 24 /
+edge factor 32 and its uniform twin (the benchmark's headline workload), the
 256-instance batched PPR set, and a Poisson serving stream. Each result is
-compared with the oracle (bit-exact for integer programs, 1e-6 max-abs for
-PageRank)."""
+compared with the oracle: bit-exact for integer programs (directly, or by
+the O(m) exactness certificate where the oracle cannot run per result), and
+1e-6 max-abs for PageRank (directly, or through the certified bound
+max-abs <= ||x - x*||_1 <= ||T(x) - x||_1 / (1 - d))."""
 import sys
 import time
 
@@ -28,20 +30,27 @@ def sr():
     return sr
 
 
-def test_pagerank_s16_four_pages_four_inner(sr):
+@pytest.mark.parametrize("equal_edges", [True, False])
+def test_pagerank_s16_four_pages_four_inner(sr, equal_edges):
+    """4 equal-edge pages as the workload states (and the equal-byte cut the
+    streamed programs use), one page resident at a time. Gate: 1e-6 max-abs
+    as stated, and 1e-8 (the mean rank here is 1.5e-5, so 1e-6 alone would
+    admit 7% relative error; the runs measure below 1e-9)."""
     g = graphgen.recipes.pagerank_s16()
     ref, _, _ = oracle.pagerank(g, tol=1e-13)
     with sr.Context(0, 0) as ctx:
         G = ctx.load(g)
-        G.partition(4, 2)   # one page resident at a time, iterated up to 4 times
+        G.partition(4, 2, equal_edges=equal_edges)   # one page resident at a time, iterated up to 4 times
         for pvu in ("weak", "off"):
             st = G.run("pagerank", pvu=pvu, max_inner_iters=4, force_stream=True, tol_l1=1e-9)
             x = G.values(np.float32).astype(np.float64)
             err = float(np.max(np.abs(x - ref)))
-            say(f"pagerank s16 {pvu}: max-abs {err:.3e} passes {st['passes']} stop {st['stop_reason']} "
-                f"L1 {st['final_l1']:.3e}")
+            rel = float(np.max(np.abs(x - ref) / ref))
+            say(f"pagerank s16 equal_edges={equal_edges} {pvu}: max-abs {err:.3e} max-rel {rel:.3e} "
+                f"passes {st['passes']} stop {st['stop_reason']} L1 {st['final_l1']:.3e}")
             assert st["stop_reason"] in (1, 2)
             assert err <= 1e-6
+            assert err <= 1e-8
             assert G.info()["num_parts"] == 4
         G.close()
 
@@ -124,12 +133,20 @@ def test_batched_ppr_256_over_32_graphs(sr):
                 worst_exact = max(worst_exact, err)
                 assert err <= 1e-6
         say(f"batched ppr: worst exact max-abs {worst_exact:.3e}, worst certified L1 bound {worst_bound:.3e}")
-        assert worst_bound <= 1e-5
+        # every one of the 256 instances: max-abs <= L1 distance <= the certified bound
+        assert worst_bound <= 1e-6
         for G in Gs:
             G.close()
+        ctx.close()
 
 
 def test_serving_stream_three_graphs(sr):
+    """1,500 Poisson arrivals at 2,000/s over the three resident graphs. Every
+    result on the scale-20 graph and a seeded sample of 100 per larger graph
+    is checked bit-exact: by the exactness certificate (O(m): d[src] = 0, no
+    edge violates d[v] <= d[u] + w, every reached vertex has a tight in-edge,
+    unreached ones no reached in-neighbour), and every 50th of them against
+    the oracle's own Dijkstra / BFS as well."""
     graphs = [graphgen.recipes.serving_graph(s) for s in (20, 22, 23)]
     nreq = 1500
     arr = graphgen.poisson_arrivals(2000.0, nreq, seed=4000)
@@ -137,33 +154,52 @@ def test_serving_stream_three_graphs(sr):
     kind = graphgen.bounded_draws(4002, 1, nreq, 0, 1)
     srcs = [graphgen.sources_with_outedges(graphs[gi], nreq, seed=4003 + gi) for gi in range(3)]
     reqs = [(int(pick[i]), "sssp" if kind[i] == 0 else "bfs", int(srcs[int(pick[i])][i])) for i in range(nreq)]
+    check = set(i for i in range(nreq) if reqs[i][0] == 0)
+    for gi in (1, 2):
+        on = [i for i in range(nreq) if reqs[i][0] == gi]
+        take = graphgen.bounded_draws(4100 + gi, 1, 100, 0, len(on) - 1)
+        check |= set(on[int(t)] for t in take)
+    n_checked = {0: 0, 1: 0, 2: 0}
     with sr.Context(0, 0) as ctx:
-        Gs = [ctx.load(g) for g in graphs]
-        srv = sr.Server(ctx, Gs, slots=16)
+        Gs = [ctx.load(g, reorder=True) for g in graphs]
+        srv = sr.Server(ctx, Gs, slots=32)
         t0 = time.time()
         tickets = []
         for i, (gi, algo, s) in enumerate(reqs):
             while time.time() - t0 < arr[i]:
                 time.sleep(0.0001)
             tickets.append(srv.submit(gi, algo, s))
-        check = list(range(0, nreq, 100))
-        outs = {i: np.empty(graphs[reqs[i][0]].n, dtype=np.uint32) for i in check}
+        t_sub = time.time() - t0
         pending = set(range(nreq))
         lat = {}
-        while pending and time.time() - t0 < 100:
-            for i in list(pending):
-                done, l = srv.poll(tickets[i], outs.get(i))
-                if done:
-                    lat[i] = l
-                    pending.discard(i)
+        bufs = [np.empty(g.n, dtype=np.uint32) for g in graphs]
+        direct = 0
+        while pending and time.time() - t0 < 300:
+            for i in sorted(pending):
+                gi, algo, s = reqs[i]
+                out = bufs[gi] if i in check else None
+                done, l = srv.poll(tickets[i], out)
+                if not done:
+                    continue
+                lat[i] = l
+                pending.discard(i)
+                if out is None:
+                    continue
+                cert = oracle.sssp_certificate(graphs[gi], s, out, weights=(algo == "sssp"))
+                assert cert == 0, (i, gi, algo, s, cert)
+                n_checked[gi] += 1
+                if n_checked[gi] % 50 == 1:
+                    ref = oracle.sssp(graphs[gi], s) if algo == "sssp" else oracle.bfs(graphs[gi], s)
+                    assert np.array_equal(out, ref), (i, gi, algo, s)
+                    direct += 1
             time.sleep(0.0005)
+        elapsed = time.time() - t0
         assert not pending
-        say(f"serving: p50 {np.percentile(list(lat.values()), 50):.1f} ms p99 "
-            f"{np.percentile(list(lat.values()), 99):.1f} ms, {srv.stats()}")
+        v = np.array(list(lat.values()))
+        say(f"serving: submitted over {t_sub:.2f} s, all done after {elapsed:.2f} s; p50 {np.percentile(v, 50):.1f} ms "
+            f"p99 {np.percentile(v, 99):.1f} ms; certified {n_checked}, {direct} also vs the oracle; {srv.stats()}")
+        assert n_checked[0] == sum(1 for r in reqs if r[0] == 0)
+        assert n_checked[1] >= 90 and n_checked[2] >= 90   # 100 seeded draws, a few repeats
         srv.close()
-        for i in check:
-            gi, algo, s = reqs[i]
-            ref = oracle.sssp(graphs[gi], s) if algo == "sssp" else oracle.bfs(graphs[gi], s)
-            assert np.array_equal(outs[i], ref), (i, gi, algo, s)
         for G in Gs:
             G.close()

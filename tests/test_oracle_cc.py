@@ -137,3 +137,35 @@ def test_labelprop_treats_arcs_as_undirected():
     chain = graphgen.from_edges(5, [4, 3, 2, 1], [3, 2, 1, 0])
     lp, _, _ = oracle.cc_labelprop_sync(chain, 5)
     assert lp.tolist() == [0, 0, 0, 0, 0]
+
+
+def test_parallel_labelprop_equals_closure_and_union_find():
+    """The multi-core CPU baseline (OpenMP synchronous label propagation) is
+    pinned to the Warshall closure on every undirected graph on 5 vertices,
+    to union-find on R-MAT / uniform graphs with isolated vertices, and gives
+    the same labels and iteration count whatever the thread count; on a path
+    0-1-...-k its iteration count is the diameter bound k + 1 (k rounds move
+    label 0 to the far end, one more sees no change)."""
+    n = 5
+    pairs = list(itertools.combinations(range(n), 2))
+    for mask in range(0, 1 << len(pairs), 7):
+        es = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
+        adj = np.zeros((n, n), dtype=bool)
+        for u, v in es:
+            adj[u, v] = True
+        g = graphgen.from_edges(n, [u for u, _ in es], [v for _, v in es], symmetrize=True)
+        lab, _, _ = oracle.cc_labelprop_parallel(g, threads=2)
+        assert np.array_equal(lab, closure_labels(n, adj)), mask
+    for g in (graphgen.rmat(13, 8, seed=6, symmetrize=True),
+              graphgen.uniform(12, 3000, seed=9, symmetrize=True)):
+        ref = oracle.cc(g)
+        runs = [oracle.cc_labelprop_parallel(g, threads=t) for t in (1, 3, 0)]
+        for lab, it, used in runs:
+            assert np.array_equal(lab, ref)
+            assert it == runs[0][1]
+        assert runs[0][2] == 1 and runs[1][2] == 3
+    k = 9
+    path = graphgen.from_edges(k + 1, list(range(k)), list(range(1, k + 1)), symmetrize=True)
+    lab, it, _ = oracle.cc_labelprop_parallel(path, threads=2)
+    assert lab.tolist() == [0] * (k + 1)
+    assert it == k + 1
