@@ -99,8 +99,11 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
     info = G.info()
     log(f"[bench] {workload}: loaded+partitioned in {time.perf_counter() - t:.1f}s: {info['num_parts']} pages, "
         f"budget {budget / 1e6:.1f} MB, graph {gbytes / 1e6:.1f} MB")
+    # the fixed schedule (a window is re-swept until a sweep changes nothing, at
+    # most max_inner_iters times) does not depend on when a copy lands, so a
+    # profiled run makes the same sweeps as the timed one
     run_kw = dict(pvu="strong", max_inner_iters=args.inner, force_stream=True, copy_depth=args.copy_depth,
-                  wide_pages=args.wide_pages)
+                  wide_pages=args.wide_pages, deterministic=args.schedule == "fixed")
     for i in range(args.warmup):
         st = G.run("cc", **run_kw)
         log(f"[bench] {workload} warmup {i}: {st['wall_ms']:.1f} ms, passes {st['passes']}")
@@ -132,6 +135,8 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
                    "vertex_order": "degree descending (labels in input ids)" if args.order == "degree"
                    else "input",
                    "page_image": "full-width" if args.wide_pages else "split-width when smaller",
+                   "schedule": "fixed re-entry (until no change, <= max_inner_iters)" if args.schedule == "fixed"
+                   else "re-entry until the next page lands",
                    "narrow_edge_frac": round(narrow / max(scanned, 1), 4)},
         "roofline": {"bound": "hbm", "kernel": "sweep_kernel<CC>",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -147,6 +152,7 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
         "scan_gteps": round(scanned / (sweep_ms * 1e-3) / 1e9, 3),
         "passes_per_solve": st["passes"],
         "sweeps_per_solve": st["sweeps"],
+        "timed_sweeps": sweeps,
         "kernel_busy_frac": round(kernel_ms / (elapsed * 1e3), 3),
     }
     G.close()
@@ -794,6 +800,9 @@ def main():
                     help="stream full-width pages instead of split-width images")
     ap.add_argument("--ablation", action="store_true",
                     help="also time the Section 5.4 schedules (baseline, re-entry, pipelined, +predictors)")
+    ap.add_argument("--schedule", choices=["fixed", "copy"], default="fixed",
+                    help="streamed CC windows: re-swept until no change (fixed, timing-independent) or until "
+                         "the next page has landed (copy)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work of the oracle baseline (repeated solves)")
     args = ap.parse_args()

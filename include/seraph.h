@@ -76,10 +76,15 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
 #define SR_RUN_FIXED_INNER 0x8u   /* every window step runs exactly max_inner_iters sweeps; with
                                      num_slots = 2 this is CLIP's loaded-data re-entry (Section 3.2),
                                      with max_inner_iters = 1 the single-pass baseline of Section 5.4 */
-#define SR_RUN_HETERO 0x10u       /* heterogeneous model of Section 3.1: once a pass of a min
-                                     program (BFS/SSSP/CC, strong or no prediction) changes at most
-                                     sparse_switch vertices, the host finishes the run with push
-                                     relaxations from that pass's frontier (the sparse stage) */
+#define SR_RUN_HETERO 0x10u       /* heterogeneous model of Section 3.1 (BFS/SSSP/CC): once a pass
+                                     changes at most sparse_switch vertices, the host continues with
+                                     push relaxations from that pass's frontier (the sparse stage).
+                                     With weak prediction the switch first runs one verification
+                                     pass (prediction off: the all-pull of Section 4.3) and hands
+                                     over that pass's frontier. When the host's frontier grows past
+                                     sparse_return vertices, the run returns to the device passes
+                                     (the switch taken back to dense); otherwise the host reaches
+                                     the fixed point and ends the run */
 #define SR_RUN_SKIP_CLEAN 0x20u   /* streamed min programs (strong or no prediction): a pass copies
                                      and sweeps only the pages with an in-edge from a vertex that
                                      changed in the previous pass (the others are at their local
@@ -116,6 +121,23 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
                                      the window's terms per sweep. Min programs (BFS, SSSP, CC)
                                      reach their unique fixed point in any order, so this flag only
                                      fixes their schedule. */
+
+#define SR_RUN_PR_DELTA 0x400u   /* PageRank / PPR as PageRank-delta, the data-driven form of Section
+                                     4.3: every vertex keeps a residual (received rank mass not yet
+                                     applied), starting at (1 - d) t with ranks at 0. In each pass a
+                                     vertex adds the terms d r_u / outdeg(u) its in-neighbours sent in
+                                     the previous pass (and d t_v times the mass sent by vertices
+                                     without out-edges); when the residual exceeds pr_change_eps it
+                                     applies it to its rank and sends it (a valid update in Fig. 6),
+                                     otherwise it keeps it. Passes are Jacobi (each page swept once
+                                     per pass; the sent terms live in a second buffer, 4 B per
+                                     vertex, plus 4 B per vertex of residuals). With weak prediction
+                                     a dormant vertex drops the terms of the passes it skips. When a
+                                     pass's applied mass falls below tol_l1 (or stalls below 1e-6),
+                                     the run turns its ranks into rank-form terms and ends with the
+                                     plain verification passes of PageRank, which recover every
+                                     dropped or unsent residual. OFF or WEAK prediction; excludes
+                                     SR_RUN_DETERMINISTIC, SR_RUN_RESUME and SR_RUN_AUDIT_PVU */
 
 /* stop reasons reported in sr_run_stats.stop_reason */
 #define SR_STOP_CONVERGED 1   /* min programs: a full pass changed nothing (with weak prediction,
@@ -279,6 +301,8 @@ typedef struct {
                                 the window holds num_slots - D pages. 1 <= D < num_slots. */
   int32_t sparse_switch;     /* SR_RUN_HETERO: frontier size that switches to the host sparse
                                 stage (0 = max(1024, n / 512)) */
+  int32_t sparse_return;     /* SR_RUN_HETERO: host frontier size that sends the run back to the
+                                device (0 = 32 * sparse_switch) */
 } sr_run_params;
 
 typedef struct {
@@ -295,15 +319,19 @@ typedef struct {
   uint64_t algo_bytes;       /* algorithmic bytes of all sweeps: edge words, gathered values,
                                 offsets, gate reads, value writes */
   int32_t sparse_stage;      /* SR_RUN_HETERO: 1 if the host sparse stage finished the run */
-  int32_t sparse_rounds;     /* push rounds of the sparse stage */
-  int64_t sparse_frontier;   /* vertices it started from (changed in the last device pass) */
-  int64_t sparse_relaxations;/* edges it relaxed */
-  double sparse_ms;          /* its wall time, transfers included */
+  int32_t sparse_rounds;     /* push rounds of the sparse stage (all entries) */
+  int64_t sparse_frontier;   /* vertices its last entry started from (changed in the last device pass) */
+  int64_t sparse_relaxations;/* edges it relaxed (all entries) */
+  double sparse_ms;          /* its wall time, transfers included (all entries) */
   int64_t pages_skipped;     /* SR_RUN_SKIP_CLEAN: page visits left out because no in-edge changed */
   double sweep_kernel_ms;    /* the part of kernel_ms spent in the sweep kernels alone (without the
                                 kernels that close each sweep) */
   int64_t edges_narrow;      /* of edges_scanned, those read as u16 ids from split-width pages (0 when
                                 the run copied full-width pages) */
+  int32_t sparse_entries;    /* SR_RUN_HETERO: times the run switched to the host stage */
+  int32_t sparse_returns;    /* ... and times the host stage gave the run back to the device */
+  int32_t pr_delta_passes;   /* SR_RUN_PR_DELTA: passes of the residual phase */
+  int32_t pad_;
 } sr_run_stats;
 
 /* Run a vertex program to convergence on the graph (partitioned with

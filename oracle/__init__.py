@@ -60,6 +60,7 @@ def _load():
         "or_cc_labelprop_sync": [_i32, _p, _p, _i32, _p, _p, _p],
         "or_cc_labelprop_parallel": [_i32, _p, _p, _i32, _p, _p, _p],
         "or_pagerank": [_i32, _p, _p, _dbl, _i32, _dbl, _i32, _p, _p, _p],
+        "or_pagerank_partial": [_i32, _p, _p, _dbl, _i32, _i32, _p],
         "or_pagerank_residual": [_i32, _p, _p, _dbl, _i32, _p, _p],
         "or_sssp_certificate": [_i32, _p, _p, _p, _i32, _p, _p],
         "or_cc_check": [_i32, _p, _p, _p, _p],
@@ -162,6 +163,15 @@ def pagerank(g, damping=0.85, seed: int = -1, tol=1e-13, max_iter=100000):
     _check(_load().or_pagerank(g.n, _ptr(off), _ptr(col), damping, seed, tol, max_iter, _ptr(x),
                                ctypes.byref(it), ctypes.byref(l1)), "pagerank")
     return x, it.value, l1.value
+
+
+def pagerank_partial(g, k: int, damping=0.85, seed: int = -1) -> np.ndarray:
+    """The first k terms of the PageRank series (k steps from x0 = 0): the
+    state of residual propagation after k synchronous passes."""
+    off, col, _ = _csr(g)
+    x = np.empty(g.n, dtype=np.float64)
+    _check(_load().or_pagerank_partial(g.n, _ptr(off), _ptr(col), damping, seed, k, _ptr(x)), "pagerank_partial")
+    return x
 
 
 def pagerank_residual(g, x, damping=0.85, seed: int = -1) -> float:

@@ -321,6 +321,25 @@ int or_pagerank(int32_t n, const int64_t *off, const int32_t *col, double d, int
   return 0;
 }
 
+/* The first k terms of PageRank's Neumann series: k steps of the same map
+ * from x0 = 0, so x_k = sum_{j<k} A^j (1 - d) t with A y = d (P^T y + D(y) t).
+ * This is the state that propagating rank mass as residuals (the data-driven
+ * PageRank-delta of Section 4.3, no vertex held back) reaches after k
+ * synchronous passes; the sum of x_k is 1 - d^k. */
+int or_pagerank_partial(int32_t n, const int64_t *off, const int32_t *col, double d, int32_t seed,
+                        int32_t k, double *x) {
+  if (n <= 0 || !(d >= 0.0 && d < 1.0) || seed >= n || k < 0) return -1;
+  double *y = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!y) return -2;
+  for (int32_t v = 0; v < n; ++v) x[v] = 0.0;
+  for (int32_t it = 0; it < k; ++it) {
+    pr_step(n, off, col, d, seed, x, y);
+    memcpy(x, y, sizeof(double) * (size_t)n);
+  }
+  free(y);
+  return 0;
+}
+
 /* ||T(x) - x||_1 for a given x (FP64). For the d-contraction T this bounds
  * the distance to the fixed point: ||x - x*||_1 <= ||T(x) - x||_1 / (1 - d). */
 int or_pagerank_residual(int32_t n, const int64_t *off, const int32_t *col, double d,

@@ -32,6 +32,7 @@ SR_RUN_NO_EARLY_BREAK = 0x40
 SR_RUN_WIDE_PAGES = 0x80
 SR_RUN_SPLIT_PAGES = 0x100
 SR_RUN_DETERMINISTIC = 0x200
+SR_RUN_PR_DELTA = 0x400
 SR_PART_EQUAL_EDGES = 0x1
 SR_STOP_CONVERGED, SR_STOP_FP32_FLOOR, SR_STOP_MAX_PASSES = 1, 2, 3
 SR_INF = 0xFFFFFFFF
@@ -69,7 +70,8 @@ class sr_run_params(ctypes.Structure):
                 ("tol_l1", ctypes.c_double), ("max_passes", ctypes.c_int32),
                 ("max_inner_iters", ctypes.c_int32), ("pvu", ctypes.c_int),
                 ("diagram", ctypes.POINTER(sr_pvu_diagram)), ("pr_change_eps", ctypes.c_float),
-                ("flags", ctypes.c_uint32), ("copy_depth", ctypes.c_int32), ("sparse_switch", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("copy_depth", ctypes.c_int32), ("sparse_switch", ctypes.c_int32),
+                ("sparse_return", ctypes.c_int32)]
 
 
 class sr_run_stats(ctypes.Structure):
@@ -84,7 +86,9 @@ class sr_run_stats(ctypes.Structure):
                 ("sparse_rounds", ctypes.c_int32), ("sparse_frontier", ctypes.c_int64),
                 ("sparse_relaxations", ctypes.c_int64), ("sparse_ms", ctypes.c_double),
                 ("pages_skipped", ctypes.c_int64), ("sweep_kernel_ms", ctypes.c_double),
-                ("edges_narrow", ctypes.c_int64)]
+                ("edges_narrow", ctypes.c_int64), ("sparse_entries", ctypes.c_int32),
+                ("sparse_returns", ctypes.c_int32), ("pr_delta_passes", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -155,13 +159,38 @@ EXTRA_SIGNATURES: dict = {
 _lib = None
 
 
+def torch_hip_runtime() -> Optional[str]:
+    """Path of the HIP runtime that PyTorch's ROCm build ships in its own lib
+    folder (None when torch is not installed or brings none), found without
+    importing torch."""
+    import importlib.util
+    try:
+        spec = importlib.util.find_spec("torch")
+    except (ImportError, ValueError):
+        return None
+    if spec is None or not spec.origin:
+        return None
+    p = os.path.join(os.path.dirname(spec.origin), "lib", "libamdhip64.so")
+    return p if os.path.exists(p) else None
+
+
 def lib():
-    """Load libseraph.so (raises if it has not been built: no fallback exists)."""
+    """Load libseraph.so (raises if it has not been built: no fallback exists).
+
+    A process must hold one HIP runtime: PyTorch's ROCm build ships its own
+    copy (with its own HSA runtime), and a second copy loaded beside it finds
+    no device once the first has opened it, and could not take torch's streams
+    or memory anyway. So when torch is installed its runtime is loaded first,
+    globally, and libseraph's references to libamdhip64.so.7 bind to it
+    (same soname); otherwise the system's ROCm runtime serves."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libseraph.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    rt = torch_hip_runtime()
+    if rt is not None:
+        ctypes.CDLL(rt, mode=os.RTLD_NOW | os.RTLD_GLOBAL)
     l = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in {**_SIGNATURES, **EXTRA_SIGNATURES}.items():
         fn = getattr(l, name)
@@ -347,9 +376,10 @@ class Graph:
             max_passes: int = 0, max_inner_iters: int = 0, diagram: Optional[sr_pvu_diagram] = None,
             pr_change_eps: float = 0.0, audit: bool = False, force_stream: bool = False,
             resume: bool = False, fixed_inner: bool = False, copy_depth: int = 0, hetero: bool = False,
-            sparse_switch: int = 0, skip_clean: bool = False, early_break: bool = True,
+            sparse_switch: int = 0, sparse_return: int = 0, skip_clean: bool = False,
+            early_break: bool = True,
             wide_pages: bool = False, split_pages: bool = False, deterministic: bool = False,
-            check: bool = True) -> dict:
+            pr_delta: bool = False, check: bool = True) -> dict:
         p = sr_run_params()
         p.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
         p.source = source
@@ -365,9 +395,10 @@ class Graph:
                    | (SR_RUN_HETERO if hetero else 0) | (SR_RUN_SKIP_CLEAN if skip_clean else 0)
                    | (0 if early_break else SR_RUN_NO_EARLY_BREAK)
                    | (SR_RUN_WIDE_PAGES if wide_pages else 0) | (SR_RUN_SPLIT_PAGES if split_pages else 0)
-                   | (SR_RUN_DETERMINISTIC if deterministic else 0))
+                   | (SR_RUN_DETERMINISTIC if deterministic else 0) | (SR_RUN_PR_DELTA if pr_delta else 0))
         p.copy_depth = copy_depth
         p.sparse_switch = sparse_switch
+        p.sparse_return = sparse_return
         st = sr_run_stats()
         rc = lib().sr_run(self.h, ctypes.byref(p), ctypes.byref(st))
         d = st.as_dict()

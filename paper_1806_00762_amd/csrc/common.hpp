@@ -169,7 +169,8 @@ struct alignas(16) SweepRecord {
   double dangling;        // PageRank dangling mass after the sweep
   double pass_l1_closed;  // L1 of the pass closed by this sweep (if any)
   uint64_t edges_narrow;  // scanned edges read from the narrow section of split images
-  uint64_t pad_;
+  uint32_t phase_after;   // phase of the next sweep (after this sweep's end-of-pass step)
+  uint32_t pad_;
 };
 static_assert(sizeof(SweepRecord) % 16 == 0, "record copied in 16-byte words");
 
@@ -185,7 +186,7 @@ struct Ctl {
   uint32_t stop_reason;
   uint32_t sweep_seq;
   uint32_t no_improve;
-  uint32_t pad0;
+  uint32_t delta;         // PageRank-delta: the residual-propagation phase is on
   // current pass accumulators
   unsigned long long pass_changed;
   uint32_t pass_min_changed, pad1;
@@ -193,6 +194,7 @@ struct Ctl {
   double best_l1;
   double dangling;        // PageRank: D used by the sweeps (sum of the dangling ranks)
   double mass;            // PageRank: sum of all ranks; a sweep scales its update by 1 / mass
+  double dangling_next;   // PageRank-delta: residual mass sent by dangling vertices in this pass
   // run constants
   int32_t algo, pvu, max_passes, pad2;
   double tol_l1;

@@ -187,6 +187,7 @@ static void release_state(sr_graph *g) {
   g->ctx->dfree(s.value);
   g->ctx->dfree(s.contrib);
   g->ctx->dfree(s.contrib_next);
+  g->ctx->dfree(s.resid);
   g->ctx->dfree(s.inv_outdeg);
   g->ctx->dfree(s.status);
   g->ctx->dfree(s.ctl);
@@ -419,6 +420,9 @@ struct Runner {
   sr_ctx *c;
   int algo, pvu;
   bool det = false;    // deterministic PageRank sweeps
+  bool delta = false;  // PageRank-delta run (residual phase first, then rank-form verification)
+  bool delta_on = false;        // ... still in its residual phase
+  uint32_t last_phase_after = 0;  // phase after the last closed pass
   sr_run_params prm;
   Diagram dia;
   bool weights;
@@ -427,6 +431,7 @@ struct Runner {
   uint64_t seq_next = 0;  // next expected sweep record
   uint64_t cur_pass_changed = 0;            // vertices changed so far in the open pass
   uint64_t last_pass_changed = ~0ull;       // ... in the last closed pass
+  uint32_t last_pass_phase = 0;             // phase of the last closed pass (1 = verification)
   int32_t collect = 0;                      // sweeps append changed vertices to the frontier
   // timing events: a free list, and start/end pairs not yet read
   std::vector<hipEvent_t> ev_all, ev_free;
@@ -492,6 +497,9 @@ struct Runner {
       cur_pass_changed += r.changed;
       if (r.pass_l1_closed >= 0.0) {
         last_pass_changed = cur_pass_changed;
+        last_pass_phase = r.phase;
+        last_phase_after = r.phase_after;
+        if (delta_on) st.pr_delta_passes++;
         cur_pass_changed = 0;
         st.final_l1 = r.pass_l1_closed;
         if (r.phase == 1) st.verify_passes++;
@@ -534,7 +542,9 @@ struct Runner {
     a.value = g->state.value;
     a.contrib = g->state.contrib;
     a.det = det ? 1 : 0;
-    a.contrib_next = det ? g->state.contrib_next : nullptr;
+    a.delta = delta ? 1 : 0;
+    a.contrib_next = (det || delta) ? g->state.contrib_next : nullptr;
+    a.resid = delta ? g->state.resid : nullptr;
     a.inv_outdeg = g->state.inv_outdeg;
     a.status = g->state.status;
     a.dia = dia;
@@ -688,7 +698,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   if (p.max_passes < 0 || p.max_inner_iters < 0) return c->fail(SR_EINVAL, "negative limits");
   if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_FORCE_STREAM | SR_RUN_RESUME | SR_RUN_FIXED_INNER | SR_RUN_HETERO |
                   SR_RUN_SKIP_CLEAN | SR_RUN_NO_EARLY_BREAK | SR_RUN_WIDE_PAGES | SR_RUN_SPLIT_PAGES |
-                  SR_RUN_DETERMINISTIC))
+                  SR_RUN_DETERMINISTIC | SR_RUN_PR_DELTA))
     return c->fail(SR_EINVAL, "unknown run flags");
   const bool pr = R.algo == A_PR || R.algo == A_PPR;
   // defaults (Section 4.3 discussion): BFS/CC strong, SSSP/PageRank weak;
@@ -733,9 +743,19 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   // deterministic schedule; PageRank also reads a per-sweep snapshot of the
   // gathered terms (second buffer, allocated once and kept with the state)
   R.det = (p.flags & SR_RUN_DETERMINISTIC) != 0;
-  if (R.det && pr && !g->state.contrib_next &&
+  R.delta = (p.flags & SR_RUN_PR_DELTA) != 0;
+  if (R.delta) {
+    if (!pr) return c->fail(SR_EINVAL, "SR_RUN_PR_DELTA serves PageRank and PPR");
+    if (R.det || resume || (p.flags & SR_RUN_AUDIT_PVU))
+      return c->fail(SR_EINVAL, "SR_RUN_PR_DELTA excludes SR_RUN_DETERMINISTIC, SR_RUN_RESUME and SR_RUN_AUDIT_PVU");
+  }
+  if ((R.det || R.delta) && pr && !g->state.contrib_next &&
       (s = c->dalloc((void **)&g->state.contrib_next, 4ull * g->n, "pagerank contrib snapshot")) != SR_OK)
     return s;
+  if (R.delta && !g->state.resid &&
+      (s = c->dalloc((void **)&g->state.resid, 4ull * g->n, "pagerank-delta residuals")) != SR_OK)
+    return s;
+  R.delta_on = R.delta;
   // forced split-width images: the slots are sized to hold them too
   auto residency = [&]() -> sr_status {
     uint64_t min_slot = 0;
@@ -768,13 +788,16 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   uint32_t sparse_thr = 0, fr_need = 0;
   if (hetero || (p.flags & SR_RUN_SKIP_CLEAN)) {
     if (pr) return c->fail(SR_EINVAL, "the sparse stage and page skipping serve BFS, SSSP and CC");
-    if (R.pvu == P_WEAK)
-      return c->fail(SR_EINVAL, "the sparse stage and page skipping need strong or no prediction");
+    if (R.pvu == P_WEAK && (p.flags & SR_RUN_SKIP_CLEAN))
+      return c->fail(SR_EINVAL, "page skipping needs strong or no prediction");
   }
+  int64_t sparse_ret = 0;  // host frontier size that sends the run back to the device
   if (hetero) {
     if (p.sparse_switch < 0) return c->fail(SR_EINVAL, "sparse_switch must be >= 0");
+    if (p.sparse_return < 0) return c->fail(SR_EINVAL, "sparse_return must be >= 0");
     sparse_thr = p.sparse_switch > 0 ? (uint32_t)p.sparse_switch : (uint32_t)std::max<int32_t>(1024, g->n / 512);
     sparse_thr = std::min<uint32_t>(sparse_thr, (uint32_t)g->n);
+    sparse_ret = p.sparse_return > 0 ? p.sparse_return : 32ll * sparse_thr;
     fr_need = sparse_thr;
   }
   if (skip) {
@@ -856,14 +879,19 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   init.tol_l1 = p.tol_l1;
   init.floor_cap = 1e-6;
   // a PageRank pass of single plain sweeps is already a verification pass
-  if (pr && R.pvu == P_OFF && (p.max_inner_iters == 1 || g->res.resident)) init.phase = 1;
+  // (not for PageRank-delta, whose residual phase comes first)
+  if (pr && !R.delta && R.pvu == P_OFF && (p.max_inner_iters == 1 || g->res.resident)) init.phase = 1;
+  init.delta = R.delta ? 1u : 0u;
+  init.dangling_next = 0.0;
   // PageRank: the rank sum and dangling sum are taken from the ranks on the
   // device once they are set (fresh or resumed)
   init.mass = 1.0;
   hipError_t e = hipSuccess;
   if (!resume) {
-    if (pr) e = launch_init_pr((float *)rs.value, rs.contrib, rs.inv_outdeg, g->n,
-                               R.algo == A_PPR ? p.source : -1, c->compute);
+    if (R.delta) e = launch_init_prd((float *)rs.value, rs.resid, rs.contrib, rs.contrib_next, g->n,
+                                     R.algo == A_PPR ? p.source : -1, p.damping, c->compute);
+    else if (pr) e = launch_init_pr((float *)rs.value, rs.contrib, rs.inv_outdeg, g->n,
+                                    R.algo == A_PPR ? p.source : -1, c->compute);
     else e = launch_init_min(R.algo, rs.value, g->n, p.source, c->compute);
     // CC labels are the caller's ids, so the smallest one of a component wins
     if (e == hipSuccess && R.algo == A_CC && g->reordered)
@@ -874,7 +902,10 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   // (pass bookkeeping, thresholds back at their safe initial value) and, for
   // PageRank, the rank and dangling sums start afresh from the values
   if (e == hipSuccess) e = launch_init_ctl(rs.ctl, init, c->compute);
-  if (e == hipSuccess && pr) e = launch_pr_sums((const float *)rs.value, rs.inv_outdeg, g->n, rs.ctl, c->compute);
+  // (PageRank-delta: nothing sent yet, so no dangling mass; the sums are
+  // taken when its residual phase ends)
+  if (e == hipSuccess && pr && !R.delta)
+    e = launch_pr_sums((const float *)rs.value, rs.inv_outdeg, g->n, rs.ctl, c->compute);
   // the snapshot's second buffer starts equal to the gathered terms
   if (e == hipSuccess && pr && R.det)
     e = hipMemcpyAsync(rs.contrib_next, rs.contrib, 4ull * g->n, hipMemcpyDeviceToDevice, c->compute);
@@ -899,7 +930,19 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
   // the fixed point. Every edge whose source did not change in that pass is
   // already satisfied (its target was pulled after the source's last change,
   // or is final by Table I), so the push from the frontier is exact.
+  // With weak prediction a skipped vertex is not provably final, so the
+  // switch first runs a verification pass (prediction off, every vertex
+  // pulled once, Section 4.3's all-pull at the dense to sparse switch) and
+  // hands over after it; so does a run the host stage gave back.
+  bool force_verify = false;
+  bool returned = false;  // the host stage gave the run back in the last pass end
   auto begin_pass = [&]() -> sr_status {
+    if (hetero && R.pvu == P_WEAK &&
+        (force_verify || (R.last_pass_phase == 0 && R.last_pass_changed <= sparse_thr))) {
+      hipError_t e2 = launch_set_phase(g->state.ctl, 1u, c->compute);
+      if (e2 != hipSuccess) return c->hip_fail(e2, "verification switch");
+      force_verify = false;
+    }
     R.collect = (skip || (hetero && (R.last_pass_changed <= 32ull * sparse_thr ||
                                      (uint64_t)g->n <= 32ull * sparse_thr))) ? 1 : 0;
     if (R.collect) {
@@ -925,9 +968,12 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     *complete = true;
     return SR_OK;
   };
+  std::vector<uint32_t> rest;  // host frontier handed back to the device
   auto sparse_stage = [&](bool have_fr, bool *fin) -> sr_status {
     *fin = false;
+    returned = false;
     if (!hetero || !R.collect || !have_fr || R.last_pass_changed > sparse_thr) return SR_OK;
+    if (R.pvu == P_WEAK && R.last_pass_phase != 1) return SR_OK;  // not after a verification pass
     const double t1 = now_ms();
     if (!g->host_val && g->n > 0) {
       HIP_TRY(c, hipHostMalloc((void **)&g->host_val, 4ull * g->n, hipHostMallocDefault), "pinned value mirror");
@@ -938,15 +984,29 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     HIP_TRY(c, hipStreamSynchronize(c->compute), "values to host");
     sr::build_out_csr(g);
     int32_t rounds = 0;
-    const int64_t relaxed = sr::sparse_push(g, R.algo, val, fr.data(), (int64_t)fr.size(), &rounds);
+    const int64_t relaxed = sr::sparse_push(g, R.algo, val, fr.data(), (int64_t)fr.size(), &rounds,
+                                            sparse_ret, &rest);
     HIP_TRY(c, hipMemcpyAsync(g->state.value, val, 4ull * g->n, hipMemcpyHostToDevice, c->compute),
             "values to device");
     HIP_TRY(c, hipStreamSynchronize(c->compute), "values to device");
-    R.st.sparse_stage = 1;
-    R.st.sparse_rounds = rounds;
+    R.st.sparse_entries++;
+    R.st.sparse_rounds += rounds;
     R.st.sparse_frontier = (int64_t)fr.size();
-    R.st.sparse_relaxations = relaxed;
-    R.st.sparse_ms = now_ms() - t1;
+    R.st.sparse_relaxations += relaxed;
+    R.st.sparse_ms += now_ms() - t1;
+    if (!rest.empty()) {
+      // the frontier grew dense again: the device passes take over. Every
+      // value is still an upper bound reached along real paths, and every
+      // value the host produced is at least the smallest value the last
+      // device pass changed, so the Table I threshold stays sound; with weak
+      // prediction the next pass is a verification pass.
+      R.st.sparse_returns++;
+      R.last_pass_changed = (uint64_t)rest.size();
+      if (R.pvu == P_WEAK) force_verify = true;
+      returned = true;
+      return SR_OK;
+    }
+    R.st.sparse_stage = 1;
     R.st.stop_reason = SR_STOP_CONVERGED;
     *fin = true;
     return SR_OK;
@@ -960,6 +1020,24 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       if (s2 != SR_OK) return s2;
     }
     return sparse_stage(have, fin);
+  };
+
+  // PageRank-delta: after every pass of its residual phase the terms that
+  // pass sent become the ones the next pass gathers; when the phase ends
+  // (close_pass turned the verification phase on) the ranks are turned into
+  // rank-form terms and the rank and dangling sums are taken afresh
+  auto delta_pass_end = [&]() -> sr_status {
+    if (!R.delta_on) return SR_OK;
+    std::swap(g->state.contrib, g->state.contrib_next);
+    if (R.last_phase_after == 1) {
+      R.delta_on = false;
+      hipError_t e2 = launch_rank_terms((const float *)g->state.value, g->state.contrib, g->state.inv_outdeg,
+                                        g->n, c->compute);
+      if (e2 == hipSuccess)
+        e2 = launch_pr_sums((const float *)g->state.value, g->state.inv_outdeg, g->n, g->state.ctl, c->compute);
+      if (e2 != hipSuccess) return c->hip_fail(e2, "rank-form terms");
+    }
+    return SR_OK;
   };
 
   bool done = false;
@@ -980,8 +1058,9 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     int32_t launched = 0;
     while (!done) {
       if ((s = begin_pass()) != SR_OK) return s;
-      // a collecting pass runs alone so its frontier can be handed over
-      const int nb = R.collect ? 1 : batch;
+      // a collecting pass runs alone so its frontier can be handed over, and
+      // so does a pass of PageRank-delta's residual phase (its buffers swap)
+      const int nb = (R.collect || R.delta_on) ? 1 : batch;
       for (int b = 0; b < nb; ++b) {
         for (auto &a : args) {
           a.collect = R.collect;
@@ -991,6 +1070,11 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       }
       if ((s = R.sync_compute()) != SR_OK) return s;
       R.harvest(&done);
+      if (!done && R.delta_on) {
+        if ((s = delta_pass_end()) != SR_OK) return s;
+        for (size_t k = 0; k < groups.size(); ++k)
+          R.make_args(groups[k], groups[k], k + 1 == groups.size() ? 1 : 0, args[k]);
+      }
       if (!done) {
         bool fin = false;
         if ((s = pass_end_host(&fin)) != SR_OK) return s;
@@ -1076,8 +1160,10 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
         if ((s = copy_page(ord[0], free_slot({}), false)) != SR_OK) return s;
       }
       for (int32_t j = 0; j < NP && !done; ++j) {
+        // PageRank-delta's residual phase sweeps every page once per pass
+        // (each sent term is received once): the window is the newest page
         std::vector<int32_t> win;
-        for (int32_t q = std::max(0, j - W + 1); q <= j; ++q) win.push_back(ord[q]);
+        for (int32_t q = R.delta_on ? j : std::max(0, j - W + 1); q <= j; ++q) win.push_back(ord[q]);
         for (int32_t q : win) HIP_TRY(c, hipStreamWaitEvent(c->compute, copy_done[page_slot[q]], 0), "compute wait");
         // keep the next D pages coming (past the pass end: the next pass's
         // first pages); a free slot was last read by an earlier step's sweeps
@@ -1115,6 +1201,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
             pass_verify = c->ring_host[q & c->ring_mask].phase == 1;
           }
           pass_changed |= changed;
+          if (R.delta_on) break;                    // one sweep per page and pass
           if (fixed_inner) continue;                // fixed re-entry count (ablation schedules)
           if (!changed) break;                      // the window reached its local fixed point
           if (R.det) continue;                      // deterministic: the copy's timing does not decide
@@ -1127,6 +1214,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       HIP_TRY(c, launch_end_pass(g->state.ctl, c->ring_dev, c->ring_mask, c->compute), "end pass");
       if ((s = R.sync_compute()) != SR_OK) return s;
       R.harvest(&done);
+      if (!done && (s = delta_pass_end()) != SR_OK) return s;
       if (!done) {
         bool fin = false, have = false;
         if (R.collect && (s = read_frontier(&have)) != SR_OK) return s;
@@ -1136,7 +1224,7 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
           // next pass: the pages an edge from a changed vertex enters; all
           // of them when the frontier overflowed
           ord.clear();
-          if (have) {
+          if (have && !returned) {
             const uint64_t m = sr::frontier_pages(g, fr.data(), (int64_t)fr.size());
             for (int32_t i = 0; i < P; ++i)
               if (m >> (P <= 64 ? i : (int)((int64_t)i * 64 / P)) & 1ull) ord.push_back(i);

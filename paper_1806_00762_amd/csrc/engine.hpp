@@ -35,7 +35,8 @@ struct RunState {
   int32_t n = 0;
   uint32_t *value = nullptr;
   float *contrib = nullptr;
-  float *contrib_next = nullptr;  // deterministic PageRank sweeps (allocated on first use)
+  float *contrib_next = nullptr;  // deterministic PageRank / PageRank-delta (allocated on first use)
+  float *resid = nullptr;         // PageRank-delta residuals (allocated on first use)
   float *inv_outdeg = nullptr;
   uint8_t *status = nullptr;
   Ctl *ctl = nullptr;
@@ -170,8 +171,11 @@ void build_out_csr(sr_graph *g);
 void build_out_masks(sr_graph *g);
 // OR of the out-page masks of the frontier's vertices
 uint64_t frontier_pages(const sr_graph *g, const uint32_t *front, int64_t nf);
+// push from a frontier to the fixed point, or until a round's list exceeds
+// limit (> 0): then *rest receives that list and the caller resumes on the
+// device; returns the edges relaxed
 int64_t sparse_push(sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
-                    int32_t *rounds);
+                    int32_t *rounds, int64_t limit = 0, std::vector<uint32_t> *rest = nullptr);
 // engine.cpp
 // min_slot: streaming slots hold at least this many bytes (forced split-width images)
 sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream, bool bins = false,

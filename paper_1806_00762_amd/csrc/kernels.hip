@@ -91,6 +91,8 @@ struct Run {
   double damping, dangling, inv_mass;
   float pr_eps, base_uniform;
   int32_t pr_seed;
+  int delta;       // PageRank-delta phase: residual propagation (dangling = mass sent last pass)
+  float *resid;
   uint32_t *hist;  // LDS histogram of predictor states
   // frontier of the pass (vertices that changed), for the host sparse stage
   int32_t collect;
@@ -180,6 +182,48 @@ template <int ALGO>
 __device__ inline bool epilogue(const Run &r, int32_t v, const Gate &g, bool computed,
                                 RedArg<ALGO> red, uint32_t deg, Acc &acc) {
   bool changed = false;
+  if constexpr (is_pr<ALGO>()) {
+    if (r.delta) {
+      // PageRank-delta (Section 4.3's data-driven PageRank), as residual
+      // propagation: the gathered sum holds d r_u / outdeg(u) of every
+      // in-neighbour that sent in the last pass, and the dangling vertices'
+      // sent mass reaches every vertex through the teleport vector. A vertex
+      // whose residual exceeds pr_eps applies it to its rank and sends it
+      // (success in Fig. 6); otherwise it keeps it. A vertex that does not
+      // pull (weak prediction) drops this pass's in-delta: the rank-form
+      // verification passes that end the run recover it.
+      const uint32_t att = g.attempt ? 1u : 0u;
+      if (computed && g.attempt) {
+        const double t = r.pr_seed < 0 ? (double)r.base_uniform : (v == r.pr_seed ? 1.0 : 0.0);
+        const float rv = (float)((double)r.resid[v] + red + r.damping * r.dangling * t);
+        const float iod = r.inv_outdeg[v];
+        if (fabsf(rv) > r.pr_eps) {
+          changed = true;
+          r.value[v] = __float_as_uint(__uint_as_float(g.old) + rv);
+          r.contrib_w[v] = (float)(r.damping * (double)rv * (double)iod);
+          r.resid[v] = 0.0f;
+          acc.l1 += fabs((double)rv);
+          acc.dmass += (double)rv;
+          if (iod == 0.0f) acc.ddelta += (double)rv;
+        } else {
+          r.resid[v] = rv;
+          r.contrib_w[v] = 0.0f;
+        }
+      } else {
+        r.contrib_w[v] = 0.0f;
+      }
+      acc.attempted += att;
+      acc.skipped += 1u - att;
+      acc.edges += att * deg;
+      acc.changed += changed ? 1u : 0u;
+      if (r.pvu == P_WEAK) {
+        uint8_t nx = (g.attempt && changed) ? r.dia->succ[g.st] : r.dia->fail[g.st];
+        if (nx != g.st) r.status[v] = nx;
+        atomicAdd(&r.hist[g.st], 1u);
+      }
+      return changed;
+    }
+  }
   if (computed) {
     if constexpr (is_pr<ALGO>()) {
       // x = (1 - d) t + d (P^T x + D t) applied to x / mass: in-place
@@ -773,6 +817,11 @@ __device__ void close_pass(Ctl *c, SweepRecord *rec) {
     }
   } else {
     const double l1 = c->pass_l1;
+    if (c->delta) {
+      // the dangling mass sent in this pass is received in the next one
+      c->dangling = c->dangling_next;
+      c->dangling_next = 0.0;
+    }
     // FP32 floor: a pass counts as an improvement only when its L1 falls at
     // least 10% below the best so far (smaller steps are rounding noise)
     const bool better = l1 < 0.9 * c->best_l1;
@@ -783,7 +832,10 @@ __device__ void close_pass(Ctl *c, SweepRecord *rec) {
       else if (l1 < c->floor_cap && c->no_improve >= 3) { c->done = 1; c->stop_reason = 2; }
     } else {
       if (l1 < c->tol_l1 || (l1 < c->floor_cap && c->no_improve >= 3)) {
+        // PageRank-delta leaves its residual phase here; the host turns the
+        // ranks into rank-form terms before the verification passes
         c->phase = 1;
+        c->delta = 0;
         c->best_l1 = 1e300;
         c->no_improve = 0;
       }
@@ -827,12 +879,15 @@ __device__ void close_sweep(Ctl *c, SweepRecord *rec, int end_of_pass, const Swe
   c->pass_changed += t.changed;
   c->pass_min_changed = min(c->pass_min_changed, t.min_changed);
   c->pass_l1 += t.l1;
-  c->dangling += t.ddelta;
+  if (c->delta) c->dangling_next += t.ddelta;  // sent mass, received in the next pass
+  else c->dangling += t.ddelta;
   c->mass += t.dmass;
   c->sweep_seq = seq + 1;
   if (end_of_pass) close_pass(c, rec);
   if (!end_of_pass) { rec->done_after = c->done; rec->pass_after = c->pass; rec->stop_reason = c->stop_reason; }
   rec->dangling = c->dangling;
+  rec->phase_after = c->phase;
+  rec->pad_ = 0;
 }
 
 // Copy a record staged in LDS to the host-mapped ring: one 16-byte store
@@ -891,8 +946,10 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   r.early = ALGO == A_BFS && a.early && !a.audit && r.phase == 0 && r.pvu == P_STRONG;
   r.threshold = ctl->threshold;
   r.value = a.value;
+  r.delta = a.delta && ctl->delta;
+  r.resid = a.resid;
   r.contrib = a.contrib;
-  r.contrib_w = a.det ? a.contrib_next : a.contrib;
+  r.contrib_w = (a.det || r.delta) ? a.contrib_next : a.contrib;
   r.inv_outdeg = a.inv_outdeg;
   r.status = a.status;
   r.dia = &a.dia;
@@ -1014,8 +1071,10 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   r.audit = a.audit && r.phase == 0 && r.pvu != P_OFF;
   r.threshold = s_ctl.threshold;
   r.value = a.value;
+  r.delta = a.delta && s_ctl.delta;
+  r.resid = a.resid;
   r.contrib = a.contrib;
-  r.contrib_w = a.det ? a.contrib_next : a.contrib;
+  r.contrib_w = (a.det || r.delta) ? a.contrib_next : a.contrib;
   r.inv_outdeg = a.inv_outdeg;
   r.status = a.status;
   r.dia = &a.dia;
@@ -1133,6 +1192,7 @@ __global__ void end_pass_kernel(Ctl *ctl, SweepRecord *ring, uint32_t mask) {
     ctl->sweep_seq = seq + 1;
     close_pass(ctl, &rec);
     rec.dangling = ctl->dangling;
+    rec.phase_after = ctl->phase;
   }
   __syncthreads();
   if (ring) publish_record(&s_rec, &ring[s_rec.seq & mask]);
@@ -1153,6 +1213,23 @@ __global__ void init_pr_kernel(float *rank, float *contrib, const float *inv_out
   float x = seed < 0 ? 1.0f / (float)n : (v == seed ? 1.0f : 0.0f);
   rank[v] = x;
   contrib[v] = x * inv_outdeg[v];
+}
+
+__global__ void init_prd_kernel(float *rank, float *resid, float *contrib, float *contrib_next, int32_t n,
+                                int32_t seed, double damping) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const double t = seed < 0 ? 1.0 / (double)n : (v == seed ? 1.0 : 0.0);
+  rank[v] = 0.0f;
+  resid[v] = (float)((1.0 - damping) * t);
+  contrib[v] = 0.0f;
+  contrib_next[v] = 0.0f;
+}
+
+__global__ void rank_terms_kernel(const float *rank, float *contrib, const float *inv_outdeg, int32_t n) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  contrib[v] = rank[v] * inv_outdeg[v];
 }
 
 // Gather-rate probe: the sweep's tiling (TILE_E words per block; thread t
@@ -1246,6 +1323,13 @@ __global__ void init_ctl_kernel(Ctl *ctl, Ctl init) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *ctl = init;
 }
 
+// The host's density switch (Section 3.1) under weak prediction: the next
+// pass is a verification pass (prediction off), so every vertex is pulled
+// once before the sparse stage takes over.
+__global__ void set_phase_kernel(Ctl *ctl, uint32_t phase) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && !ctl->done) ctl->phase = phase;
+}
+
 }  // namespace
 
 template <int ALGO>
@@ -1337,6 +1421,25 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s)
 
 hipError_t launch_init_stripes(Stripe *s, hipStream_t st) {
   hipLaunchKernelGGL(init_stripes_kernel, dim3(1), dim3(NSTRIPE), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_prd(float *rank, float *resid, float *contrib, float *contrib_next, int32_t n,
+                           int32_t seed, double damping, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(init_prd_kernel, dim3((n + 255) / 256), dim3(256), 0, s, rank, resid, contrib, contrib_next,
+                     n, seed, damping);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_terms(const float *rank, float *contrib, const float *inv_outdeg, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_terms_kernel, dim3((n + 255) / 256), dim3(256), 0, s, rank, contrib, inv_outdeg, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_phase(Ctl *ctl, uint32_t phase, hipStream_t s) {
+  hipLaunchKernelGGL(set_phase_kernel, dim3(1), dim3(64), 0, s, ctl, phase);
   return hipGetLastError();
 }
 

@@ -23,6 +23,9 @@ struct SweepArgs {
   int32_t split;           // the pages in the slots are split-width images (min programs)
   int32_t det;             // PageRank: deterministic sweep (gathers read contrib, pulls write
                            // contrib_next, whose window ranges are copied back after the sweep)
+  int32_t delta;           // PageRank-delta run: while the control block's delta phase is on, the
+                           // gathers read the terms sent in the last pass (contrib) and the pulls
+                           // write this pass's (contrib_next)
   double damping;
   float pr_eps;
   Ctl *ctl;                // device control block
@@ -30,7 +33,8 @@ struct SweepArgs {
   uint32_t ring_mask;
   uint32_t *value;         // BFS level / SSSP distance / CC label (u32), or PageRank rank (f32 bits)
   float *contrib;          // PageRank: rank / outdeg, gathered by the pull
-  float *contrib_next;     // deterministic PageRank: the terms this sweep writes
+  float *contrib_next;     // deterministic PageRank / PageRank-delta: the terms this sweep writes
+  float *resid;            // PageRank-delta: residual per vertex (received, not yet applied)
   const float *inv_outdeg; // PageRank: 1 / outdeg (0 for dangling vertices)
   uint8_t *status;         // weak predictor state per vertex
   Stripe *stripes;         // NSTRIPE counter stripes (identity outside a sweep)
@@ -68,5 +72,12 @@ hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
 hipError_t launch_init_stripes(Stripe *s, hipStream_t st);
 hipError_t launch_init_ctl(Ctl *ctl, const Ctl &init, hipStream_t s);
+// PageRank-delta run start: rank 0, residual (1 - d) t, no terms sent yet
+hipError_t launch_init_prd(float *rank, float *resid, float *contrib, float *contrib_next, int32_t n,
+                           int32_t seed, double damping, hipStream_t s);
+// rank-form terms contrib = rank / outdeg, when a PageRank-delta run leaves its delta phase
+hipError_t launch_rank_terms(const float *rank, float *contrib, const float *inv_outdeg, int32_t n, hipStream_t s);
+// set the phase of the next pass (1 = verification) unless the run is done
+hipError_t launch_set_phase(Ctl *ctl, uint32_t phase, hipStream_t s);
 
 }  // namespace sr

@@ -47,8 +47,12 @@ static inline uint32_t relax_value(int algo, uint32_t xu, uint32_t w) {
 // correction, each round's list split over host threads, atomic minimum on
 // the values and an in-list flag per vertex. Monotone min relaxations reach
 // the same least fixed point in any order, so the result is exact.
+// When a round's list grows beyond `limit` entries (limit > 0) the stage
+// stops before that round: the list goes to `rest` (every vertex whose
+// out-edges are not yet relaxed since its last decrease) and the run goes
+// back to the device (the density switch taken the other way, Section 3.1).
 int64_t sparse_push(sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
-                    int32_t *rounds_out) {
+                    int32_t *rounds_out, int64_t limit, std::vector<uint32_t> *rest) {
   const int32_t n = g->n;
   // flags are set when a vertex enters the next round and cleared when that
   // round starts, so the array is all zero again on return
@@ -65,7 +69,14 @@ int64_t sparse_push(sr_graph *g, int algo, uint32_t *val, const uint32_t *front,
   int32_t rounds = 0;
   std::vector<std::vector<int32_t>> next(T);
   std::vector<int64_t> cnt(T);
+  if (rest) rest->clear();
   while (!cur.empty()) {
+    if (limit > 0 && (int64_t)cur.size() > limit && rest) {
+      // dense again: hand the unrelaxed list back and clear its flags
+      rest->reserve(cur.size());
+      for (int32_t u : cur) { inq[u] = 0; rest->push_back((uint32_t)u); }
+      break;
+    }
     ++rounds;
     for (int32_t u : cur) inq[u] = 0;  // a later decrease puts u back
     auto work = [&](int t, size_t lo, size_t hi) {

@@ -1,7 +1,10 @@
 """Heterogeneous execution (Section 3.1): the device runs dense pull passes
-and, once a pass changes few vertices, the host finishes with push
-relaxations from that pass's frontier. The result must equal the oracle
-exactly, whatever the switch point, schedule or graph."""
+and, once a pass changes few vertices, the host continues with push
+relaxations from that pass's frontier; with weak prediction the switch first
+runs an all-pull verification pass (Section 4.3), and a host frontier that
+grows dense again sends the run back to the device. The result must equal
+the oracle exactly, whatever the switch point, predictor, schedule or
+graph."""
 import sys
 
 import numpy as np
@@ -72,7 +75,7 @@ def test_hetero_exact(sr, ctx, gname, sched, switch):
     src = int(np.argmax(np.diff(g.offsets)))
     cases = (("sssp", oracle.sssp(g, src), False), ("bfs", oracle.bfs(g, src), False), ("cc", oracle.cc(g), True))
     for algo, ref, sym in cases:
-        for pvu in ("strong", "off"):
+        for pvu in ("strong", "off", "weak"):
             got, st = run(ctx, g, algo, sched, sym=sym, source=src, pvu=pvu, sparse_switch=switch)
             say(f"case hetero {gname} {sched} switch={switch} {algo} {pvu}: passes {st['passes']} "
                 f"sparse {st['sparse_stage']} frontier {st['sparse_frontier']} rounds {st['sparse_rounds']}")
@@ -107,12 +110,17 @@ def test_hetero_refused_cases(sr, ctx):
     G = ctx.load(g)
     try:
         G.partition(1, 4)
-        for algo, pvu in (("sssp", "weak"), ("pagerank", "weak"), ("pagerank", "off")):
+        for algo, pvu in (("pagerank", "weak"), ("pagerank", "off")):
             with pytest.raises(sr.SeraphError) as e:
                 G.run(algo, source=0, pvu=pvu, hetero=True)
             assert e.value.status == sr.SR_EINVAL
         with pytest.raises(sr.SeraphError):
             G.run("sssp", source=0, pvu="strong", hetero=True, sparse_switch=-1)
+        with pytest.raises(sr.SeraphError):
+            G.run("sssp", source=0, pvu="strong", hetero=True, sparse_return=-1)
+        with pytest.raises(sr.SeraphError) as e:
+            G.run("sssp", source=0, pvu="weak", skip_clean=True, force_stream=True)
+        assert e.value.status == sr.SR_EINVAL
         st = G.run("sssp", source=0, hetero=True)  # default prediction becomes strong
         assert np.array_equal(G.values(), oracle.sssp(g, 0))
     finally:
@@ -132,3 +140,66 @@ def test_hetero_tiny_graphs(sr, ctx):
             assert np.array_equal(got, oracle.sssp(g, 0))
             got, _ = run(ctx, g, "cc", sched, sym=True, pvu="strong", sparse_switch=1 << 30)
             assert np.array_equal(got, oracle.cc(g))
+
+
+def test_hetero_weak_switch_after_verification(sr, ctx):
+    """Weak prediction (the paper's SSSP default): the switch runs one
+    verification pass with prediction off and hands its frontier to the
+    host, which finishes exactly."""
+    g = graph("rmat14w")
+    src = int(np.argmax(np.diff(g.offsets)))
+    ref = oracle.sssp(g, src)
+    G = ctx.load(g)
+    try:
+        G.partition(7, 4)
+        for sched_kw in (dict(force_stream=True, copy_depth=2), dict(force_stream=False)):
+            st = G.run("sssp", source=src, pvu="weak", hetero=True, sparse_switch=2048, **sched_kw)
+            tr = G.sweeps()
+            say(f"case weak hetero {sched_kw}: passes {st['passes']} verify {st['verify_passes']} "
+                f"entries {st['sparse_entries']} frontier {st['sparse_frontier']}")
+            assert np.array_equal(G.values(), ref)
+            assert st["sparse_stage"] == 1 and st["sparse_entries"] >= 1
+            # the last device pass was a verification pass
+            assert tr[-1]["phase"] == 1
+            assert st["verify_passes"] >= 1
+    finally:
+        G.close()
+
+
+def chain_fan(n_leaves=5000, chain=300, pad=700, seed=31):
+    """A chain that runs against the sweep order (from the highest id down)
+    and then fans out to every leaf: device passes change a few chain
+    vertices each, the host walks the chain one vertex per round, and the
+    fan makes its frontier dense again."""
+    n = n_leaves + pad + chain
+    top = n - 1
+    src = list(range(top, top - chain + 1, -1))
+    dst = list(range(top - 1, top - chain, -1))
+    hub = top - chain + 1
+    src += [hub] * n_leaves
+    dst += list(range(n_leaves))
+    # leaves point back into the chain's first part, so the return also has work to do
+    rng = np.random.default_rng(seed)
+    extra_s = rng.integers(0, n_leaves, 2000)
+    extra_d = rng.integers(0, n_leaves, 2000)
+    src += extra_s.tolist()
+    dst += extra_d.tolist()
+    w = rng.integers(1, 10, len(src)).tolist()
+    return graphgen.from_edges(n, src, dst, w), top
+
+
+@pytest.mark.parametrize("sched", ["resident", "s3p3", "s4p7d2"])
+def test_hetero_two_way_switch(sr, ctx, sched):
+    """The host stage gives the run back to the device when its frontier
+    passes sparse_return, and takes it again later: SSSP and BFS bit-exact
+    with every predictor, with at least one return."""
+    g, src = chain_fan()
+    for algo, ref in (("sssp", oracle.sssp(g, src)), ("bfs", oracle.bfs(g, src))):
+        for pvu in ("strong", "off", "weak"):
+            got, st = run(ctx, g, algo, sched, source=src, pvu=pvu, sparse_switch=64, sparse_return=256)
+            say(f"case two-way {sched} {algo} {pvu}: passes {st['passes']} entries {st['sparse_entries']} "
+                f"returns {st['sparse_returns']} rounds {st['sparse_rounds']} finished {st['sparse_stage']}")
+            assert np.array_equal(got, ref), f"{algo} {pvu}: {np.sum(got != ref)} mismatches"
+            assert st["converged"] == 1
+            assert st["sparse_returns"] >= 1
+            assert st["sparse_entries"] >= st["sparse_returns"]

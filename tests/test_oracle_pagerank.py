@@ -102,3 +102,42 @@ def test_damping_and_orientation_matter():
     x, _, _ = oracle.pagerank(g)
     assert np.max(np.abs(x - dense_solve(g))) < 1e-12
     assert x[0] > x[1]
+
+
+def test_partial_sums_first_terms():
+    """k = 0 gives zero and k = 1 the teleport term (1 - d) t."""
+    g = graphgen.rmat(9, 8, seed=4)
+    assert np.all(oracle.pagerank_partial(g, 0) == 0.0)
+    assert np.max(np.abs(oracle.pagerank_partial(g, 1) - (1 - D) / g.n)) < 1e-18
+    x1 = oracle.pagerank_partial(g, 1, seed=7)
+    assert x1[7] == pytest.approx(1 - D) and np.count_nonzero(x1) == 1
+
+
+@pytest.mark.parametrize("trial", range(6))
+def test_partial_sums_mass_and_limit(trial):
+    """sum x_k = 1 - d^k (each term carries d times the mass of the one before,
+    dangling mass included), the sums grow monotonically, and many terms reach
+    the dense solve."""
+    r = np.random.default_rng(100 + trial)
+    n = int(r.integers(3, 150)); m = int(r.integers(1, 4 * n))
+    g = graphgen.from_edges(n, r.integers(0, n, m), r.integers(0, n, m))
+    s = int(r.integers(0, n)) if trial % 2 else -1
+    prev = np.zeros(n)
+    for k in (1, 2, 3, 7, 20):
+        x = oracle.pagerank_partial(g, k, seed=s)
+        assert abs(x.sum() - (1 - D ** k)) < 1e-13
+        assert np.all(x >= prev - 1e-18)
+        prev = x
+    x = oracle.pagerank_partial(g, 400, seed=s)
+    assert np.max(np.abs(x - dense_solve(g, seed=s))) < 1e-12
+
+
+def test_partial_sums_cycle_closed_form():
+    """On a directed N-cycle with PPR seed s the mass moves one step per term:
+    x_k[s + j] = (1 - d) d^j for j < k <= N, and 0 beyond."""
+    n, s, k = 29, 4, 11
+    g = graphgen.from_edges(n, np.arange(n), (np.arange(n) + 1) % n)
+    x = oracle.pagerank_partial(g, k, seed=s)
+    j = (np.arange(n) - s) % n
+    exp = np.where(j < k, (1 - D) * D ** j, 0.0)
+    assert np.max(np.abs(x - exp)) < 1e-15
