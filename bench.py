@@ -507,9 +507,11 @@ def bench_bfs_early_break(args, g, G):
 
 def bench_pagerank16(args):
     """PageRank on R-MAT scale 16 (4 equal-byte pages, up to 4 sweeps per page
-    per pass, L1 < 1e-9, resident): no prediction, weak prediction, and weak
+    per pass, L1 < 1e-9, resident): no prediction, weak prediction, weak
     prediction with a change tolerance (updates below it count as failed
-    attempts: the data-driven form), each checked against the FP64 oracle."""
+    attempts), and PageRank-delta (residual propagation, then the rank-form
+    verification passes) without and with a send threshold and with weak
+    prediction; each checked against the FP64 oracle."""
     import graphgen
     import oracle
     import paper_1806_00762_amd as sr
@@ -519,8 +521,11 @@ def bench_pagerank16(args):
     G = ctx.load(g, reorder=args.order == "degree")
     G.partition(4, 4)
     out = {"workload": "pagerank_rmat16_ef16_4pages_inner4_tol1e-9", "n": g.n, "m": g.m}
-    for name, pvu, eps in (("off", "off", 0.0), ("weak", "weak", 0.0), ("weak_eps1e-9", "weak", 1e-9)):
-        kw = dict(pvu=pvu, pr_change_eps=eps, max_inner_iters=4, tol_l1=1e-9)
+    for name, pvu, eps, delta in (("off", "off", 0.0, False), ("weak", "weak", 0.0, False),
+                                  ("weak_eps1e-9", "weak", 1e-9, False),
+                                  ("delta", "off", 0.0, True), ("delta_eps1e-10", "off", 1e-10, True),
+                                  ("delta_weak_eps1e-10", "weak", 1e-10, True)):
+        kw = dict(pvu=pvu, pr_change_eps=eps, max_inner_iters=4, tol_l1=1e-9, pr_delta=delta)
         G.run("pagerank", **kw)
         sync()
         t0 = time.perf_counter()
@@ -532,6 +537,7 @@ def bench_pagerank16(args):
         out[name] = {"ms_per_solve": round(el * 1e3, 3), "solve_gteps": round(g.m / el / 1e9, 3),
                      "edges_swept_gteps": round(g.m * st["sweeps"] / el / 1e9, 2),
                      "sweeps": st["sweeps"], "vertex_pulls": st["vertices_attempted"],
+                     "delta_passes": st["pr_delta_passes"], "verify_passes": st["verify_passes"],
                      "max_abs": float(np.max(np.abs(x - ref))), "dtype": "f32"}
     G.close()
     ctx.close()

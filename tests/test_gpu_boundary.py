@@ -43,7 +43,9 @@ def test_torch_streams_and_allocator(sr, torch):
     ref_x, _, _ = oracle.pagerank(g, tol=1e-13)
     base = torch.cuda.memory_allocated(0)
     compute, copy = torch.cuda.Stream(0), torch.cuda.Stream(0)
-    budget = (4 * (g.n + 1) + 8 * g.m) // 4 + (1 << 20)
+    # a quarter of the graph bytes for the page slots, plus the vertex state
+    # of both programs (values, predictor states, PageRank terms)
+    budget = (4 * (g.n + 1) + 8 * g.m) // 4 + 16 * g.n + (1 << 20)
     ctx = sr.Context(0, budget)
     ctx.set_streams(compute.cuda_stream, copy.cuda_stream)
     ctx.set_torch_allocator(stream=compute)

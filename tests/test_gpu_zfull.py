@@ -5,8 +5,8 @@ edge factor 32 and its uniform twin (the benchmark's headline workload), the
 256-instance batched PPR set, and a Poisson serving stream. Each result is
 compared with the oracle: bit-exact for integer programs (directly, or by
 the O(m) exactness certificate where the oracle cannot run per result), and
-1e-6 max-abs for PageRank (directly, or through the certified bound
-max-abs <= ||x - x*||_1 <= ||T(x) - x||_1 / (1 - d))."""
+1e-6 max-abs for PageRank against the FP64 oracle's own solve of every
+instance."""
 import sys
 import time
 
@@ -114,6 +114,13 @@ def test_cc_uniform_twin_s24_streamed(sr):
 
 
 def test_batched_ppr_256_over_32_graphs(sr):
+    """Every one of the 256 instances against its own FP64 oracle solve, held
+    to the stated 1e-6 max-abs (the runs measure ~1.7e-7 at worst, on the
+    seed vertex of a scale-19/20 graph, whose rank ~0.15-0.3 has an FP32 ulp
+    of ~1.5e-8); the oracle solves run in a thread pool (the C oracle
+    releases the GIL)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
     graphs = [graphgen.recipes.batched_graph(i) for i in range(32)]
     with sr.Context(0, 0) as ctx:
         Gs = [ctx.load(g) for g in graphs]
@@ -121,23 +128,27 @@ def test_batched_ppr_256_over_32_graphs(sr):
                  for s in graphgen.sources_with_outedges(g, 8, seed=2000 + gi)]
         outs, per, bs = sr.batch_run(ctx, [(Gs[gi], "ppr", s) for gi, s in insts])
         say(f"batched ppr: {bs}")
-        worst_bound, worst_exact = 0.0, 0.0
-        for (gi, s), x, st in zip(insts, outs, per):
-            assert st["converged"] == 1
-            xf = x.view(np.float32).astype(np.float64)
-            bound = oracle.pagerank_residual(graphs[gi], xf, seed=s) / 0.15
-            worst_bound = max(worst_bound, bound)
-            if graphs[gi].n <= 1 << 15:
-                ref, _, _ = oracle.pagerank(graphs[gi], seed=s, tol=1e-13)
-                err = float(np.max(np.abs(xf - ref)))
-                worst_exact = max(worst_exact, err)
-                assert err <= 1e-6
-        say(f"batched ppr: worst exact max-abs {worst_exact:.3e}, worst certified L1 bound {worst_bound:.3e}")
-        # every one of the 256 instances: max-abs <= L1 distance <= the certified bound
-        assert worst_bound <= 1e-6
         for G in Gs:
             G.close()
         ctx.close()
+    assert all(st["converged"] == 1 for st in per)
+
+    def err_of(k):
+        gi, s = insts[k]
+        ref, _, _ = oracle.pagerank(graphs[gi], seed=s, tol=1e-13)
+        return float(np.max(np.abs(outs[k].view(np.float32).astype(np.float64) - ref)))
+
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    t = time.time()
+    # largest graphs first, so the pool ends together
+    order = sorted(range(len(insts)), key=lambda k: -graphs[insts[k][0]].m)
+    with ThreadPoolExecutor(workers) as ex:
+        errs = dict(zip(order, ex.map(err_of, order)))
+    worst = max(errs.values())
+    say(f"batched ppr: {len(errs)} instances vs the FP64 oracle in {time.time() - t:.1f}s "
+        f"({workers} threads): worst max-abs {worst:.3e}")
+    assert len(errs) == 256
+    assert worst <= 1e-6
 
 
 def test_serving_stream_three_graphs(sr):
