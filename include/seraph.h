@@ -342,6 +342,39 @@ typedef struct {
  * stats may be NULL. */
 sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_stats *stats);
 
+/* Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): sr_run for BFS, SSSP or CC on a graph whose pages are already
+ * resident on the device (an earlier sr_run made them resident: the graph
+ * fits the budget and it ran without SR_RUN_FORCE_STREAM; SSSP needs pages
+ * made resident by an SSSP run, since other programs copy no weights). The
+ * graph must be loaded without SR_LOAD_REORDER, so the values are in the
+ * caller's vertex ids.
+ *   values_dev: device memory owned by the caller, 4n bytes: receives the
+ *     u32 values (levels, distances or labels; SR_INF if unreached).
+ *   status_dev: device memory owned by the caller, n bytes, the weak
+ *     predictor's per-vertex states (workspace, contents undefined on
+ *     return); may be NULL unless the predictor is weak (SR_PVU_DEFAULT
+ *     resolves to weak for SSSP).
+ * The control block and the counter stripes live in a static device array
+ * of SR_NOALLOC_SCRATCH_BYTES that each GPU holds from library load to
+ * process end; the heavy-vertex accumulators are the resident pages' own.
+ * No device memory, event or stream is created and nothing is freed; the
+ * call synchronises the context's compute stream. Every call on one GPU
+ * shares that GPU's scratch array, and calls on one graph share its
+ * accumulators, so calls that overlap on one GPU race (run them one at a
+ * time). params as for sr_run; flags other than SR_RUN_AUDIT_PVU,
+ * SR_RUN_NO_EARLY_BREAK and SR_RUN_DETERMINISTIC are refused; stats (may be
+ * NULL) has no kernel timings. The values sr_read_values returns stay those
+ * of the last sr_run. Errors: SR_EINVAL (bad argument, a reordered graph,
+ * PageRank, a refused flag, status_dev NULL under weak prediction),
+ * SR_ESTATE (pages not resident), SR_EBUSY (graph attached to a server),
+ * SR_EDEVICE (host-only context, no scratch address, HIP error),
+ * SR_ENOTCONV (max_passes ran out; values_dev holds the partial values). */
+#define SR_NOALLOC_SCRATCH_BYTES 16384u
+sr_status sr_run_noalloc(sr_graph *g, const sr_run_params *params, uint32_t *values_dev, uint8_t *status_dev,
+                         sr_run_stats *stats);
+
 /* Per-sweep trace of the last sr_run (the Fig. 10 / Section 5.4 instrumentation):
  * one record per sweep, in order. */
 typedef struct {

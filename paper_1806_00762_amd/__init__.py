@@ -120,6 +120,7 @@ _SIGNATURES = {
     "sr_graph_destroy": (None, [_P]),
     "sr_pvu_default_diagram": (ctypes.c_int, [ctypes.POINTER(sr_pvu_diagram)]),
     "sr_run": (ctypes.c_int, [_P, ctypes.POINTER(sr_run_params), ctypes.POINTER(sr_run_stats)]),
+    "sr_run_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(sr_run_params), _P, _P, ctypes.POINTER(sr_run_stats)]),
     "sr_read_values": (ctypes.c_int, [_P, _P, ctypes.c_uint64]),
     "sr_run_sweeps": (ctypes.c_int, [_P, ctypes.POINTER(sr_sweep_record), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32)]),
@@ -372,14 +373,15 @@ class Graph:
         return {"v_begin": v.v_begin, "v_end": v.v_end, "offsets": off, "src": src, "weights": w,
                 "src_packed": bool(v.src_packed), "bytes": int(v.bytes), "stream_bytes": int(v.stream_bytes)}
 
-    def run(self, algo, source: int = 0, pvu="default", damping: float = 0.85, tol_l1: float = 1e-9,
-            max_passes: int = 0, max_inner_iters: int = 0, diagram: Optional[sr_pvu_diagram] = None,
-            pr_change_eps: float = 0.0, audit: bool = False, force_stream: bool = False,
-            resume: bool = False, fixed_inner: bool = False, copy_depth: int = 0, hetero: bool = False,
-            sparse_switch: int = 0, sparse_return: int = 0, skip_clean: bool = False,
-            early_break: bool = True,
-            wide_pages: bool = False, split_pages: bool = False, deterministic: bool = False,
-            pr_delta: bool = False, check: bool = True) -> dict:
+    @staticmethod
+    def _params(algo, source: int = 0, pvu="default", damping: float = 0.85, tol_l1: float = 1e-9,
+                max_passes: int = 0, max_inner_iters: int = 0, diagram: Optional[sr_pvu_diagram] = None,
+                pr_change_eps: float = 0.0, audit: bool = False, force_stream: bool = False,
+                resume: bool = False, fixed_inner: bool = False, copy_depth: int = 0, hetero: bool = False,
+                sparse_switch: int = 0, sparse_return: int = 0, skip_clean: bool = False,
+                early_break: bool = True,
+                wide_pages: bool = False, split_pages: bool = False, deterministic: bool = False,
+                pr_delta: bool = False) -> sr_run_params:
         p = sr_run_params()
         p.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
         p.source = source
@@ -399,8 +401,28 @@ class Graph:
         p.copy_depth = copy_depth
         p.sparse_switch = sparse_switch
         p.sparse_return = sparse_return
+        return p
+
+    def run(self, algo, check: bool = True, **kw) -> dict:
+        """sr_run: keyword arguments as the fields and flags of sr_run_params
+        (see _params); returns the run statistics as a dict."""
+        p = self._params(algo, **kw)
         st = sr_run_stats()
         rc = lib().sr_run(self.h, ctypes.byref(p), ctypes.byref(st))
+        d = st.as_dict()
+        d["status"] = rc
+        if check and rc not in (SR_OK,):
+            _check(rc, self.ctx.h)
+        return d
+
+    def run_noalloc(self, algo, values_dev: int, status_dev: int = 0, check: bool = True, **kw) -> dict:
+        """sr_run_noalloc: the allocation-free solve on a resident graph, values
+        written to the caller's device buffer at address values_dev (4n bytes),
+        weak predictor states to status_dev (n bytes, or 0 when not weak)."""
+        p = self._params(algo, **kw)
+        st = sr_run_stats()
+        rc = lib().sr_run_noalloc(self.h, ctypes.byref(p), ctypes.c_void_p(values_dev),
+                                  ctypes.c_void_p(status_dev or None), ctypes.byref(st))
         d = st.as_dict()
         d["status"] = rc
         if check and rc not in (SR_OK,):

@@ -118,6 +118,10 @@ extern "C" sr_status sr_ctx_create(int device, uint64_t budget, sr_ctx **out) {
     if (hipHostGetDevicePointer(&dptr, ring, 0) != hipSuccess) dptr = ring;
     c->ring_dev = (SweepRecord *)dptr;
     c->ring_mask = RING - 1;
+    // the allocation-free solve's scratch: its device address, looked up once
+    // for this device (a failure only disables that entry point)
+    void *scr = nullptr;
+    if (sr::noalloc_scratch(device, &scr) == hipSuccess) c->scratch_dev = scr;
     c->compute = c->own_compute;
     c->copy = c->own_copy;
     c->budget = budget ? budget : (uint64_t)freeb;
@@ -418,6 +422,8 @@ bool valid_diagram(const sr_pvu_diagram &d) {
 struct Runner {
   sr_graph *g;
   sr_ctx *c;
+  RunState *rs = nullptr;  // device state the sweeps use (null: the graph's own)
+  bool timed = true;       // record HIP events around each sweep
   int algo, pvu;
   bool det = false;    // deterministic PageRank sweeps
   bool delta = false;  // PageRank-delta run (residual phase first, then rank-form verification)
@@ -515,6 +521,10 @@ struct Runner {
   }
 
   sr_status launch(const SweepArgs &a) {
+    if (!timed) {
+      hipError_t e = launch_sweep(algo, a, c->compute, nullptr);
+      return e == hipSuccess ? SR_OK : c->hip_fail(e, "sweep launch");
+    }
     hipEvent_t e0 = ev(), em = ev(), e1 = ev();
     if (e0) (void)hipEventRecord(e0, c->compute);
     hipError_t e = launch_sweep(algo, a, c->compute, em);
@@ -527,6 +537,7 @@ struct Runner {
   // Fill the per-launch fields for pages [list] resident at bufs.
   sr_status make_args(const std::vector<int32_t> &pages, const std::vector<int32_t> &slots,
                       int end_of_pass, SweepArgs &a) {
+    const RunState &S = rs ? *rs : g->state;
     std::memset(&a, 0, sizeof(a));
     a.nent = (int32_t)pages.size();
     a.end_of_pass = end_of_pass;
@@ -536,17 +547,17 @@ struct Runner {
     a.pr_seed = algo == A_PPR ? prm.source : -1;
     a.damping = prm.damping;
     a.pr_eps = prm.pr_change_eps;
-    a.ctl = g->state.ctl;
+    a.ctl = S.ctl;
     a.ring = c->ring_dev;
     a.ring_mask = c->ring_mask;
-    a.value = g->state.value;
-    a.contrib = g->state.contrib;
+    a.value = S.value;
+    a.contrib = S.contrib;
     a.det = det ? 1 : 0;
     a.delta = delta ? 1 : 0;
-    a.contrib_next = (det || delta) ? g->state.contrib_next : nullptr;
-    a.resid = delta ? g->state.resid : nullptr;
-    a.inv_outdeg = g->state.inv_outdeg;
-    a.status = g->state.status;
+    a.contrib_next = (det || delta) ? S.contrib_next : nullptr;
+    a.resid = delta ? S.resid : nullptr;
+    a.inv_outdeg = S.inv_outdeg;
+    a.status = S.status;
     a.dia = dia;
     int32_t blk = 0;
     a.blk_prefix[0] = 0;
@@ -559,11 +570,11 @@ struct Runner {
       a.base[i] = g->res.buf[slots[i]];
       a.partial[i] = g->res.partial[slots[i]];
     }
-    a.stripes = g->state.stripes;
+    a.stripes = S.stripes;
     a.collect = collect;
-    a.frontier = g->state.frontier;
-    a.fr_count = g->state.fr_count;
-    a.fr_cap = g->state.fr_cap;
+    a.frontier = S.frontier;
+    a.fr_count = S.fr_count;
+    a.fr_cap = S.fr_cap;
     a.nblocks = std::max<int32_t>(blk, 1);  // an empty window still closes its sweep
     // the masked decode also serves unweighted graphs whose ids fit 24 bits
     // (it needs fewer registers than the plain one)
@@ -1241,6 +1252,130 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     R.harvest_events();
   }
   R.st.converged = R.st.stop_reason == SR_STOP_CONVERGED || R.st.stop_reason == SR_STOP_FP32_FLOOR;
+  R.st.wall_ms = now_ms() - t0;
+  if (stats) *stats = R.st;
+  if (R.st.stop_reason == SR_STOP_MAX_PASSES || !done)
+    return c->fail(SR_ENOTCONV, "max_passes reached before convergence");
+  return SR_OK;
+}
+
+static_assert(SR_NOALLOC_SCRATCH_BYTES == NOALLOC_SCRATCH_BYTES, "header and kernels agree on the scratch size");
+
+// Allocation-free variant of sr_run for a graph already resident on the
+// device: the same sweep and close kernels, the vertex values and predictor
+// states in the caller's device buffers, the control block and counter
+// stripes in the static scratch array (its address looked up per device at
+// context creation), the heavy-vertex accumulators those of the resident
+// pages. No device memory, event or stream is created.
+extern "C" sr_status sr_run_noalloc(sr_graph *g, const sr_run_params *params, uint32_t *values_dev,
+                                    uint8_t *status_dev, sr_run_stats *stats) {
+  if (!g || !params) return g ? g->ctx->fail(SR_EINVAL, "params is NULL") : SR_EINVAL;
+  sr_ctx *c = g->ctx;
+  if (c->host_only) return c->fail(SR_EDEVICE, "host-only context cannot run");
+  if (!c->scratch_dev) return c->fail(SR_EDEVICE, "static scratch address unavailable on this device");
+  if (g->server_refs > 0) return c->fail(SR_EBUSY, "graph is attached to a server");
+  if (!values_dev) return c->fail(SR_EINVAL, "values_dev is NULL");
+  const double t0 = now_ms();
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  Runner R;
+  R.g = g;
+  R.c = c;
+  R.timed = false;
+  R.prm = *params;
+  sr_run_params &p = R.prm;
+  if (p.algo != SR_BFS && p.algo != SR_SSSP && p.algo != SR_CC)
+    return c->fail(SR_EINVAL, "the allocation-free run serves BFS, SSSP and CC");
+  R.algo = (int)p.algo;
+  if (p.max_passes == 0) p.max_passes = 10000;
+  if (p.max_passes < 0) return c->fail(SR_EINVAL, "negative limits");
+  if (p.flags & ~(SR_RUN_AUDIT_PVU | SR_RUN_NO_EARLY_BREAK | SR_RUN_DETERMINISTIC))
+    return c->fail(SR_EINVAL, "the allocation-free run takes SR_RUN_AUDIT_PVU, SR_RUN_NO_EARLY_BREAK and "
+                              "SR_RUN_DETERMINISTIC only");
+  if (p.pvu == SR_PVU_DEFAULT) p.pvu = (R.algo == A_SSSP) ? SR_PVU_WEAK : SR_PVU_STRONG;
+  if (p.pvu < SR_PVU_OFF || p.pvu > SR_PVU_WEAK) return c->fail(SR_EINVAL, "unknown pvu mode");
+  R.pvu = (int)p.pvu;
+  if (R.pvu == P_WEAK && !status_dev) return c->fail(SR_EINVAL, "weak prediction needs status_dev");
+  if (R.algo != A_CC && (p.source < 0 || p.source >= g->n)) return c->fail(SR_EINVAL, "source out of range");
+  if (R.algo == A_CC && !g->symmetric)
+    return c->fail(SR_EINVAL, "CC needs the undirected graph: load with SR_LOAD_SYMMETRIZE");
+  if (R.algo == A_SSSP && !g->weighted) return c->fail(SR_EINVAL, "SSSP needs weights");
+  if (g->reordered)
+    return c->fail(SR_EINVAL, "the allocation-free run writes values in the caller's ids: load without "
+                              "SR_LOAD_REORDER");
+  R.weights = R.algo == A_SSSP;
+  if (g->pages.empty() || !g->res.resident || (R.weights && !g->res.weights) || g->res.buf.empty())
+    return c->fail(SR_ESTATE, "pages are not resident on the device: run sr_run on this graph first");
+  sr_pvu_diagram d;
+  if (p.diagram) d = *p.diagram; else sr_pvu_default_diagram(&d);
+  if (!valid_diagram(d)) return c->fail(SR_EINVAL, "invalid predictor diagram");
+  std::memset(&R.dia, 0, sizeof(R.dia));
+  R.dia.num_states = d.num_states;
+  R.dia.initial = d.initial_state;
+  R.dia.attempt_mask = d.attempt_mask;
+  std::memcpy(R.dia.succ, d.on_success, 8);
+  std::memcpy(R.dia.fail, d.on_fail, 8);
+  R.det = (p.flags & SR_RUN_DETERMINISTIC) != 0;
+
+  // the state the kernels use: caller buffers and the static scratch
+  RunState st;
+  st.algo = R.algo;
+  st.n = g->n;
+  st.value = values_dev;
+  st.status = status_dev;
+  st.ctl = reinterpret_cast<Ctl *>(c->scratch_dev);
+  st.stripes = reinterpret_cast<Stripe *>(reinterpret_cast<char *>(c->scratch_dev) + NOALLOC_CTL_BYTES);
+  R.rs = &st;
+
+  Ctl init;
+  std::memset(&init, 0, sizeof(init));
+  init.threshold = 0;
+  init.phase = 0;
+  init.pass_min_changed = INF;
+  init.best_l1 = 1e300;
+  init.algo = R.algo;
+  init.pvu = R.pvu;
+  init.max_passes = p.max_passes;
+  init.tol_l1 = 1e-9;
+  init.floor_cap = 1e-6;
+  init.mass = 1.0;
+  // every buffer is set by a kernel (no memset or copy nodes), in stream order
+  hipError_t e = launch_init_min(R.algo, values_dev, g->n, p.source, c->compute);
+  if (e == hipSuccess && status_dev) e = launch_fill_u8(status_dev, (uint8_t)d.initial_state, (size_t)g->n, c->compute);
+  if (e == hipSuccess) e = launch_init_ctl(st.ctl, init, c->compute);
+  if (e == hipSuccess) e = launch_init_stripes(st.stripes, c->compute);
+  for (size_t i = 0; i < g->res.partial.size() && e == hipSuccess; ++i)
+    e = launch_fill_u32((uint32_t *)g->res.partial[i], INF, 2 * g->res.partial_words[i], c->compute);
+  if (e != hipSuccess) return c->hip_fail(e, "init");
+  for (uint32_t i = 0; i < RING; ++i) c->ring_host[i].seq = ~0ull;
+  g->sweeps.clear();
+  R.seq_next = 0;
+
+  // resident sweeps: each covers every page and closes a pass; batches of
+  // sweeps are enqueued with one host check per batch (the control block
+  // turns the sweeps after convergence into no-ops)
+  std::vector<std::vector<int32_t>> groups;
+  for (int32_t i = 0; i < (int32_t)g->pages.size(); i += MAXW) {
+    std::vector<int32_t> grp;
+    for (int32_t j = i; j < std::min<int32_t>(i + MAXW, (int32_t)g->pages.size()); ++j) grp.push_back(j);
+    groups.push_back(grp);
+  }
+  std::vector<SweepArgs> args(groups.size());
+  sr_status s;
+  for (size_t k = 0; k < groups.size(); ++k)
+    if ((s = R.make_args(groups[k], groups[k], k + 1 == groups.size() ? 1 : 0, args[k])) != SR_OK) return s;
+  bool done = false;
+  int32_t launched = 0;
+  while (!done) {
+    for (int b = 0; b < 4; ++b) {
+      for (auto &a : args)
+        if ((s = R.launch(a)) != SR_OK) return s;
+      launched++;
+    }
+    if ((s = R.sync_compute()) != SR_OK) return s;
+    R.harvest(&done);
+    if (launched > p.max_passes + 8) break;
+  }
+  R.st.converged = R.st.stop_reason == SR_STOP_CONVERGED;
   R.st.wall_ms = now_ms() - t0;
   if (stats) *stats = R.st;
   if (R.st.stop_reason == SR_STOP_MAX_PASSES || !done)

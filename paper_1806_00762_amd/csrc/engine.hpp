@@ -88,6 +88,9 @@ struct sr_ctx {
   sr::SweepRecord *ring_host = nullptr;
   sr::SweepRecord *ring_dev = nullptr;
   uint32_t ring_mask = 0;
+  // device address of the allocation-free solve's static scratch array
+  // (null on a host-only context, or if the lookup failed)
+  void *scratch_dev = nullptr;
   std::mutex mu;
 
   sr_status fail(sr_status st, const std::string &msg) const {

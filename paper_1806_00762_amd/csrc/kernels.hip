@@ -15,7 +15,9 @@
 // for the per-sweep counters (one set per block).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -1446,6 +1448,34 @@ hipError_t launch_set_phase(Ctl *ctl, uint32_t phase, hipStream_t s) {
 hipError_t launch_init_ctl(Ctl *ctl, const Ctl &init, hipStream_t s) {
   hipLaunchKernelGGL(init_ctl_kernel, dim3(1), dim3(64), 0, s, ctl, init);
   return hipGetLastError();
+}
+
+// Per-run scratch of the allocation-free solve: the control block and the
+// counter stripes, in a static array every device holds from library load
+// to process end. Host code never passes the array's name to a kernel (on
+// the host it is only a stand-in for the symbol): it takes the device
+// address hipGetSymbolAddress gives, once per device, with that device
+// current, and hands that address to the kernels.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static_assert(sizeof(Ctl) <= NOALLOC_CTL_BYTES, "control block fits its scratch section");
+static_assert(NOALLOC_CTL_BYTES + sizeof(Stripe) * NSTRIPE <= NOALLOC_SCRATCH_BYTES,
+              "control block and stripes fit the scratch array");
+
+hipError_t noalloc_scratch(int device, void **out) {
+  static std::mutex mu;
+  static std::vector<void *> ptr;  // per device, null until looked up
+  std::lock_guard<std::mutex> lk(mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((size_t)device >= ptr.size()) ptr.resize((size_t)device + 1, nullptr);
+  if (!ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    ptr[device] = p;
+  }
+  *out = ptr[device];
+  return hipSuccess;
 }
 
 }  // namespace sr

@@ -72,6 +72,11 @@ hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
 hipError_t launch_init_stripes(Stripe *s, hipStream_t st);
 hipError_t launch_init_ctl(Ctl *ctl, const Ctl &init, hipStream_t s);
+// Device address of the allocation-free solve's static scratch array on
+// `device` (which must be current): looked up once per device, then cached.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 16384;
+constexpr size_t NOALLOC_CTL_BYTES = 512;  // the control block's section; the stripes follow
+hipError_t noalloc_scratch(int device, void **out);
 // PageRank-delta run start: rank 0, residual (1 - d) t, no terms sent yet
 hipError_t launch_init_prd(float *rank, float *resid, float *contrib, float *contrib_next, int32_t n,
                            int32_t seed, double damping, hipStream_t s);
