@@ -189,7 +189,8 @@ struct Ctl {
   uint32_t delta;         // PageRank-delta: the residual-propagation phase is on
   // current pass accumulators
   unsigned long long pass_changed;
-  uint32_t pass_min_changed, pad1;
+  uint32_t pass_min_changed;
+  uint32_t win_quiet;     // the last sweep changed nothing (later sweeps of its window may exit at once)
   double pass_l1;
   double best_l1;
   double dangling;        // PageRank: D used by the sweeps (sum of the dangling ranks)

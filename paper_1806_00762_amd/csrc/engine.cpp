@@ -474,9 +474,12 @@ struct Runner {
   }
 
   // harvest event timings and sweep records up to what the device wrote
-  sr_status harvest(bool *done) {
+  // (limit: read no record numbered limit or above; records written while
+  // later kernels are still running may not have fully landed)
+  sr_status harvest(bool *done, uint64_t limit = ~0ull) {
     harvest_events();
     for (;;) {
+      if (seq_next >= limit) break;
       const SweepRecord &r = c->ring_host[seq_next & c->ring_mask];
       if (r.seq != seq_next) break;
       if (r.attempted + r.skipped > 0 || r.edges > 0) {
@@ -1113,6 +1116,19 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     auto mk = [&]() { hipEvent_t ev; if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return (hipEvent_t) nullptr; own.push_back(ev); return ev; };
     for (int32_t i = 0; i < S; ++i) copy_done[i] = mk();
     step_done = mk();
+    // Deterministic schedule: every sweep of a window step is enqueued at
+    // once; the close kernel marks a window whose sweep changed nothing and
+    // that window's later sweeps exit at once. The host never waits between
+    // sweeps: before a step it waits for the step LAG back (so the device
+    // always holds queued work) and reads the records written so far.
+    const bool devq = R.det && !(p.flags & SR_RUN_FIXED_INNER);
+    constexpr int LAG = 2;
+    std::vector<hipEvent_t> lag_ev(LAG + 1, nullptr);
+    std::vector<uint64_t> lag_rec(LAG + 1, 0);  // records written once that step has ended
+    if (devq)
+      for (auto &ev : lag_ev) ev = mk();
+    int64_t step_idx = 0;
+    uint64_t rec_launched = 0;  // records the enqueued kernels will have written (devq: one per sweep)
     struct Cleanup { std::vector<hipEvent_t> *v; ~Cleanup() { for (auto e : *v) (void)hipEventDestroy(e); } } cl{&own};
     for (auto ev : own) if (!ev) return c->fail(SR_EDEVICE, "event creation failed");
     std::vector<int32_t> &slot_page = g->res.slot_page;
@@ -1170,7 +1186,25 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
       if (NP > 0 && page_slot[ord[0]] < 0) {
         if ((s = copy_page(ord[0], free_slot({}), false)) != SR_OK) return s;
       }
+      // records harvested so far: did this pass change anything, is it a
+      // verification pass
+      auto absorb = [&](uint64_t limit) {
+        const uint64_t before = R.seq_next;
+        R.harvest(&done, limit);
+        bool changed = false;
+        for (uint64_t q = before; q < R.seq_next; ++q) {
+          changed |= c->ring_host[q & c->ring_mask].changed > 0;
+          pass_verify = c->ring_host[q & c->ring_mask].phase == 1;
+        }
+        pass_changed |= changed;
+        return changed;
+      };
       for (int32_t j = 0; j < NP && !done; ++j) {
+        if (devq && step_idx >= LAG) {
+          HIP_TRY(c, hipEventSynchronize(lag_ev[(step_idx - LAG) % (LAG + 1)]), "step wait");
+          absorb(lag_rec[(step_idx - LAG) % (LAG + 1)]);
+          if (done) break;
+        }
         // PageRank-delta's residual phase sweeps every page once per pass
         // (each sent term is received once): the window is the newest page
         std::vector<int32_t> win;
@@ -1200,18 +1234,20 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
         ++step_clock;
         SweepArgs a;
         if ((s = R.make_args(win, ws, 0, a)) != SR_OK) return s;
-        for (int32_t it = 0; it < p.max_inner_iters; ++it) {
+        if (devq) {
+          const int32_t iters = R.delta_on ? 1 : p.max_inner_iters;  // delta: one sweep per page and pass
+          a.win_skip = 1;
+          for (int32_t it = 0; it < iters; ++it) {
+            a.win_first = it == 0 ? 1 : 0;
+            if ((s = R.launch(a)) != SR_OK) return s;
+            ++rec_launched;
+          }
+        }
+        for (int32_t it = 0; !devq && it < p.max_inner_iters; ++it) {
           if ((s = R.launch(a)) != SR_OK) return s;
           if ((s = R.sync_compute()) != SR_OK) return s;
-          const uint64_t before = R.seq_next;
-          R.harvest(&done);
+          const bool changed = absorb(~0ull);
           if (done) break;
-          bool changed = false;
-          for (uint64_t q = before; q < R.seq_next; ++q) {
-            changed |= c->ring_host[q & c->ring_mask].changed > 0;
-            pass_verify = c->ring_host[q & c->ring_mask].phase == 1;
-          }
-          pass_changed |= changed;
           if (R.delta_on) break;                    // one sweep per page and pass
           if (fixed_inner) continue;                // fixed re-entry count (ablation schedules)
           if (!changed) break;                      // the window reached its local fixed point
@@ -1220,9 +1256,15 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
           if (hipEventQuery(copy_done[next_slot]) == hipSuccess) break;  // next page landed: slide
         }
         HIP_TRY(c, hipEventRecord(step_done, c->compute), "step event");
+        if (devq) {
+          HIP_TRY(c, hipEventRecord(lag_ev[step_idx % (LAG + 1)], c->compute), "step event");
+          lag_rec[step_idx % (LAG + 1)] = rec_launched;
+        }
+        ++step_idx;
       }
       if (done) break;
       HIP_TRY(c, launch_end_pass(g->state.ctl, c->ring_dev, c->ring_mask, c->compute), "end pass");
+      ++rec_launched;
       if ((s = R.sync_compute()) != SR_OK) return s;
       R.harvest(&done);
       if (!done && (s = delta_pass_end()) != SR_OK) return s;

@@ -884,6 +884,7 @@ __device__ void close_sweep(Ctl *c, SweepRecord *rec, int end_of_pass, const Swe
   if (c->delta) c->dangling_next += t.ddelta;  // sent mass, received in the next pass
   else c->dangling += t.ddelta;
   c->mass += t.dmass;
+  c->win_quiet = t.changed == 0 ? 1u : 0u;
   c->sweep_seq = seq + 1;
   if (end_of_pass) close_pass(c, rec);
   if (!end_of_pass) { rec->done_after = c->done; rec->pass_after = c->pass; rec->stop_reason = c->stop_reason; }
@@ -906,7 +907,9 @@ __device__ inline void publish_record(const SweepRecord *src, SweepRecord *dst) 
 template <int ALGO, int EPT, bool PACKED, bool SPLIT, bool DET = false>
 __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   Ctl *ctl = a.ctl;
-  if (ctl->done) return;  // converged: every block leaves before counting
+  // converged, or a later sweep of a window whose last sweep changed
+  // nothing: every block leaves before counting
+  if (ctl->done || (a.win_skip && !a.win_first && ctl->win_quiet)) return;
   __shared__ uint32_t s_hist[8];
   __shared__ uint32_t s_u32[WAVES][7];
   __shared__ double s_f64[WAVES][3];
@@ -1066,6 +1069,29 @@ __global__ void __launch_bounds__(CLOSE_THREADS) close_kernel(SweepArgs a) {
   }
   __syncthreads();
   if (s_ctl.done) return;  // the sweep was a no-op as well
+  if (a.win_skip && !a.win_first && s_ctl.win_quiet) {
+    // a sweep its window skipped still leaves a record (no counts), so the
+    // records number the launches and a host that has waited for launch k
+    // reads records up to k only
+    if (tid == 0) {
+      SweepRecord &rec = s_rec;
+      rec = SweepRecord{};
+      rec.seq = s_ctl.sweep_seq;
+      rec.min_changed = INF;
+      rec.threshold = s_ctl.threshold;
+      rec.phase = s_ctl.phase;
+      rec.done_after = s_ctl.done;
+      rec.pass_after = s_ctl.pass;
+      rec.stop_reason = s_ctl.stop_reason;
+      rec.dangling = s_ctl.dangling;
+      rec.pass_l1_closed = -1.0;
+      rec.phase_after = s_ctl.phase;
+      a.ctl->sweep_seq = s_ctl.sweep_seq + 1;
+    }
+    __syncthreads();
+    if (a.ring) publish_record(&s_rec, &a.ring[s_rec.seq & a.ring_mask]);
+    return;
+  }
   Run r;
   r.algo = ALGO;
   r.pvu = s_ctl.pvu;

@@ -26,6 +26,9 @@ struct SweepArgs {
   int32_t delta;           // PageRank-delta run: while the control block's delta phase is on, the
                            // gathers read the terms sent in the last pass (contrib) and the pulls
                            // write this pass's (contrib_next)
+  int32_t win_first;       // first sweep of a window step
+  int32_t win_skip;        // a sweep after the first of its window exits at once when the sweep
+                           // before it changed nothing (its window is at a local fixed point)
   double damping;
   float pr_eps;
   Ctl *ctl;                // device control block
