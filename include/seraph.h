@@ -331,7 +331,8 @@ typedef struct {
   int32_t sparse_entries;    /* SR_RUN_HETERO: times the run switched to the host stage */
   int32_t sparse_returns;    /* ... and times the host stage gave the run back to the device */
   int32_t pr_delta_passes;   /* SR_RUN_PR_DELTA: passes of the residual phase */
-  int32_t pad_;
+  int32_t sweep_launches;    /* launches of the sweep kernel, including those of a window that had
+                                already stopped changing (they exit at once and count no sweep) */
 } sr_run_stats;
 
 /* Run a vertex program to convergence on the graph (partitioned with
@@ -408,10 +409,17 @@ sr_status sr_read_values(const sr_graph *g, void *host_dst, uint64_t dst_bytes);
  * from a device queue; the sweep is captured once in a HIP graph and
  * replayed until every instance has converged (PPR: L1 change of a sweep
  * below tol_l1, or the FP32 floor rule; SSSP/BFS: a sweep without change,
- * with the Table I strong conditions per instance). The persistent grid
- * size and the items taken per queue access are chosen by a built-in
- * autotuner (timed candidate sweeps), cached per process and in the JSON
- * file named by SR_TUNE_CACHE if set. Graphs must fit the budget resident. */
+ * with the Table I strong conditions per instance). The schedule is chosen
+ * by a built-in autotuner that times one sweep over every instance for each
+ * candidate: the group width K (instance columns sharing each gathered row:
+ * 8 or 16 for PPR, 8, 16 or 32 for SSSP/BFS), the vertex rounds per work item
+ * (2, 4 or 8), the persistent grid size and the items taken per queue
+ * access. The choice is cached per process, keyed by the algorithm and each
+ * graph's scale bucket, edge factor and instance count, and in the text
+ * file named by SR_TUNE_CACHE if set. The environment variable
+ * SR_BATCH_SCHEDULE="K,rounds" fixes the width and rounds of a call (grid
+ * and grab are still tuned; SR_EINVAL if malformed). Graphs must fit the
+ * budget resident. */
 typedef struct {
   sr_graph *g;
   sr_algo algo;      /* SR_PPR, SR_SSSP or SR_BFS; one family per call
@@ -429,6 +437,8 @@ typedef struct {
   double kernel_ms;      /* device time of the replays (HIP events) */
   double wall_ms;        /* host wall time of the whole call */
   uint64_t algo_bytes;   /* algorithmic bytes of all sweeps */
+  int32_t rounds;        /* chosen vertex rounds per wavefront and work item (small in-degree bins) */
+  int32_t width_candidates; /* group widths timed by the autotuner in this call (1: cached or fixed) */
 } sr_batch_stats;
 
 /* Run `count` instances to convergence. host_dsts[i] (host, 4n_i bytes)

@@ -88,7 +88,7 @@ class sr_run_stats(ctypes.Structure):
                 ("pages_skipped", ctypes.c_int64), ("sweep_kernel_ms", ctypes.c_double),
                 ("edges_narrow", ctypes.c_int64), ("sparse_entries", ctypes.c_int32),
                 ("sparse_returns", ctypes.c_int32), ("pr_delta_passes", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("sweep_launches", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -132,7 +132,8 @@ class sr_instance(ctypes.Structure):
 class sr_batch_stats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("groups", ctypes.c_int32), ("group_width", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("grab", ctypes.c_int32), ("tuned", ctypes.c_int32),
-                ("kernel_ms", ctypes.c_double), ("wall_ms", ctypes.c_double), ("algo_bytes", ctypes.c_uint64)]
+                ("kernel_ms", ctypes.c_double), ("wall_ms", ctypes.c_double), ("algo_bytes", ctypes.c_uint64),
+                ("rounds", ctypes.c_int32), ("width_candidates", ctypes.c_int32)]
 
 
 class sr_server_stats(ctypes.Structure):

@@ -21,7 +21,6 @@
 namespace sr {
 
 namespace {
-constexpr int MI_ROUNDS = 4;
 constexpr int MI_CLOSE_THREADS = 1024;
 
 template <typename T>
@@ -35,15 +34,17 @@ __device__ inline T shfl_xor(T v, int m) { return __shfl_xor(v, m, 64); }
 // one wavefront a long serial edge loop.
 __host__ __device__ constexpr int mi_subchunks(int K) { return K >= 16 ? K / 8 : 1; }
 
-__host__ __device__ inline int mi_items_per_block(int b, int K) {
+// ROUNDS: rounds of vertices a wavefront takes per item in the small-degree
+// bins (the items-per-block choice of the schedule)
+__host__ __device__ inline int mi_items_per_block(int b, int K, int ROUNDS) {
   const int EL = 64 / K;
   if (b <= 5) {
     int GE = (1 << b) < EL ? (1 << b) : EL;
-    return WAVES * MI_ROUNDS * (EL / GE);
+    return WAVES * ROUNDS * (EL / GE);
   }
   if (b == BIN_WAVE) return WAVES;
   if (b == BIN_CHUNK) return WAVES / mi_subchunks(K);  // chunks: WAVES sub-chunks per item
-  return MI_ROUNDS * (BLOCK / K);
+  return ROUNDS * (BLOCK / K);
 }
 
 namespace {
@@ -189,7 +190,7 @@ __device__ inline void mi_flush(MiLds *lds, int group, MiAcc &acc) {
   acc = MiAcc();
 }
 
-// bins 0..5: GE edge lanes per vertex (GE = min(2^b, 64/K)), MI_ROUNDS
+// bins 0..5: GE edge lanes per vertex (GE = min(2^b, 64/K)), ROUNDS
 // rounds of 64/K/GE vertices per wavefront
 // Weight of in-edge e with edge word q (1 for unweighted programs).
 template <int ALGO>
@@ -198,7 +199,7 @@ __device__ inline uint32_t mi_weight(const MiGroup &g, uint32_t q, const uint32_
   return g.packed ? q >> 24 : wt[e];
 }
 
-template <int ALGO, int K, int GE>
+template <int ALGO, int K, int GE, int ROUNDS>
 __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h, int bin, int item,
                          const Lane &ln, double damping, MiAcc &acc) {
   using R = MiRed<ALGO, K>;
@@ -213,14 +214,14 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
   const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
   const int cnt = h->bin_count[bin];
   const int vb = h->v_begin;
-  int32_t vl[MI_ROUNDS], beg[MI_ROUNDS], end[MI_ROUNDS];
-  uint32_t old[MI_ROUNDS];
-  bool att[MI_ROUNDS];
+  int32_t vl[ROUNDS], beg[ROUNDS], end[ROUNDS];
+  uint32_t old[ROUNDS];
+  bool att[ROUNDS];
 #pragma unroll
-  for (int r = 0; r < MI_ROUNDS; ++r) {
+  for (int r = 0; r < ROUNDS; ++r) {
     // loads are unconditional (lanes past the bin reread its first vertex)
     // so the rounds' bin, offset and value loads overlap
-    const int idx = ((item * WAVES + wave) * MI_ROUNDS + r) * VPW + vs;
+    const int idx = ((item * WAVES + wave) * ROUNDS + r) * VPW + vs;
     const bool ok = idx < cnt;
     vl[r] = cnt > 0 ? bins[ok ? idx : 0] : 0;  // an empty bin rereads the page's vertex 0
     beg[r] = off[vl[r]];
@@ -230,7 +231,7 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
     if (!ok) vl[r] = -1;
   }
 #pragma unroll
-  for (int r = 0; r < MI_ROUNDS; ++r) {
+  for (int r = 0; r < ROUNDS; ++r) {
     T x = R::identity();
     if (att[r]) {
       // batches of 4 edges per lane: word loads, then gathers, in flight together
@@ -336,14 +337,14 @@ __device__ void mi_chunk(const MiGroup &g, const MiUnit &u, const char *base, co
 }
 
 // bin 8 (PPR only): zero in-degree, the value still follows the teleport term
-template <int ALGO, int K>
+template <int ALGO, int K, int ROUNDS>
 __device__ void mi_zero(const MiGroup &g, const char *base, const PageHeader *h, int item, const Lane &ln,
                         double damping, MiAcc &acc) {
   const int k = threadIdx.x % K, vs = threadIdx.x / K;
   const int32_t *bins = reinterpret_cast<const int32_t *>(base + h->off_bins) + h->bin_start[BIN_ZERO];
   const int cnt = h->bin_count[BIN_ZERO];
-  for (int r = 0; r < MI_ROUNDS; ++r) {
-    int idx = (item * MI_ROUNDS + r) * (BLOCK / K) + vs;
+  for (int r = 0; r < ROUNDS; ++r) {
+    int idx = (item * ROUNDS + r) * (BLOCK / K) + vs;
     if (idx >= cnt) break;
     int32_t v = h->v_begin + bins[idx];
     uint32_t old;
@@ -352,7 +353,7 @@ __device__ void mi_zero(const MiGroup &g, const char *base, const PageHeader *h,
   }
 }
 
-template <int ALGO, int K>
+template <int ALGO, int K, int ROUNDS>
 __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
   if (a.ctl->remaining == 0 && !a.tuning) return;  // everything converged: replays are no-ops
   extern __shared__ MiLds lds[];
@@ -385,16 +386,16 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
       const Lane ln = lane_of(g.inst[k]);
       MiAcc acc;
       switch (bin) {
-        case 0: mi_small<ALGO, K, 1>(g, bp, h, 0, item, ln, a.damping, acc); break;
-        case 1: mi_small<ALGO, K, (2 < 64 / K ? 2 : 64 / K)>(g, bp, h, 1, item, ln, a.damping, acc); break;
-        case 2: mi_small<ALGO, K, (4 < 64 / K ? 4 : 64 / K)>(g, bp, h, 2, item, ln, a.damping, acc); break;
-        case 3: mi_small<ALGO, K, (8 < 64 / K ? 8 : 64 / K)>(g, bp, h, 3, item, ln, a.damping, acc); break;
-        case 4: mi_small<ALGO, K, (16 < 64 / K ? 16 : 64 / K)>(g, bp, h, 4, item, ln, a.damping, acc); break;
-        case 5: mi_small<ALGO, K, (32 < 64 / K ? 32 : 64 / K)>(g, bp, h, 5, item, ln, a.damping, acc); break;
+        case 0: mi_small<ALGO, K, 1, ROUNDS>(g, bp, h, 0, item, ln, a.damping, acc); break;
+        case 1: mi_small<ALGO, K, (2 < 64 / K ? 2 : 64 / K), ROUNDS>(g, bp, h, 1, item, ln, a.damping, acc); break;
+        case 2: mi_small<ALGO, K, (4 < 64 / K ? 4 : 64 / K), ROUNDS>(g, bp, h, 2, item, ln, a.damping, acc); break;
+        case 3: mi_small<ALGO, K, (8 < 64 / K ? 8 : 64 / K), ROUNDS>(g, bp, h, 3, item, ln, a.damping, acc); break;
+        case 4: mi_small<ALGO, K, (16 < 64 / K ? 16 : 64 / K), ROUNDS>(g, bp, h, 4, item, ln, a.damping, acc); break;
+        case 5: mi_small<ALGO, K, (32 < 64 / K ? 32 : 64 / K), ROUNDS>(g, bp, h, 5, item, ln, a.damping, acc); break;
         case BIN_WAVE: mi_wave<ALGO, K>(g, bp, h, item, ln, a.damping, acc); break;
         case BIN_CHUNK: mi_chunk<ALGO, K>(g, u, bp, h, item, ln); break;
         default:
-          if constexpr (mi_pr<ALGO>()) mi_zero<ALGO, K>(g, bp, h, item, ln, a.damping, acc);
+          if constexpr (mi_pr<ALGO>()) mi_zero<ALGO, K, ROUNDS>(g, bp, h, item, ln, a.damping, acc);
           break;
       }
       mi_flush<ALGO, K>(lds, u.group, acc);
@@ -558,18 +559,21 @@ __global__ void mi_extract_kernel(uint32_t *value, int32_t n, MiExtract x, int32
 template <int ALGO, int K>
 void mi_pair(const MiArgs &a, hipStream_t s) {
   const size_t lds = sizeof(MiLds) * (size_t)a.ngroups * K;
-  hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
+  if (a.rounds == 2) hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K, 2>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
+  else if (a.rounds == 8) hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K, 8>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
+  else hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K, 4>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
   hipLaunchKernelGGL((mi_heavy_kernel<ALGO, K>), dim3(a.heavy_blocks), dim3(BLOCK), 0, s, a);
   hipLaunchKernelGGL((mi_close_kernel<ALGO, K>), dim3(1), dim3(MI_CLOSE_THREADS), 0, s, a);
 }
 
 }  // namespace
 
-int mi_items_per_block_host(int b, int K) { return mi_items_per_block(b, K); }
+int mi_items_per_block_host(int b, int K, int rounds) { return mi_items_per_block(b, K, rounds); }
 
 hipError_t launch_mi_sweep(int algo, int K, const MiArgs &a, hipStream_t s) {
   if (a.nblocks <= 0) return hipErrorInvalidValue;
   if (a.ngroups * K > MI_MAX_INSTANCES) return hipErrorInvalidValue;
+  if (a.rounds != 2 && a.rounds != 4 && a.rounds != 8) return hipErrorInvalidValue;
   if (algo == A_PPR && K == 8) mi_pair<A_PPR, 8>(a, s);
   else if (algo == A_PPR && K == 16) mi_pair<A_PPR, 16>(a, s);
   else if (algo == A_SSSP && K == 8) mi_pair<A_SSSP, 8>(a, s);

@@ -77,6 +77,7 @@ struct MiArgs {
   int32_t total_heavy;      // heavy vertices over all units
   int32_t heavy_blocks;     // blocks of the heavy-vertex kernel
   int32_t grab;             // items taken per queue access
+  int32_t rounds;           // vertex rounds per wavefront and item in the small-degree bins (2, 4, 8)
   int32_t nblocks;
   double damping;
   double tol_l1, floor_cap;
@@ -87,7 +88,7 @@ struct MiArgs {
   uint32_t *host_remaining; // host-mapped copy of ctl->remaining
 };
 
-int mi_items_per_block_host(int b, int K);
+int mi_items_per_block_host(int b, int K, int rounds);
 hipError_t launch_mi_sweep(int algo, int K, const MiArgs &a, hipStream_t s);
 hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contrib, const float *inv_outdeg,
                                  int32_t n, int32_t col, int32_t source, hipStream_t s);

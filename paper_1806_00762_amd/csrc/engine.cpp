@@ -524,6 +524,7 @@ struct Runner {
   }
 
   sr_status launch(const SweepArgs &a) {
+    st.sweep_launches++;
     if (!timed) {
       hipError_t e = launch_sweep(algo, a, c->compute, nullptr);
       return e == hipSuccess ? SR_OK : c->hip_fail(e, "sweep launch");
@@ -1113,23 +1114,34 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     std::vector<hipEvent_t> copy_done(S, nullptr);
     hipEvent_t step_done = nullptr;
     std::vector<hipEvent_t> own;
-    auto mk = [&]() { hipEvent_t ev; if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return (hipEvent_t) nullptr; own.push_back(ev); return ev; };
+    // (a failed creation leaves a null entry, which the check below reports)
+    auto mk = [&]() {
+      hipEvent_t ev = nullptr;
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+      own.push_back(ev);
+      return ev;
+    };
     for (int32_t i = 0; i < S; ++i) copy_done[i] = mk();
     step_done = mk();
-    // Deterministic schedule: every sweep of a window step is enqueued at
-    // once; the close kernel marks a window whose sweep changed nothing and
-    // that window's later sweeps exit at once. The host never waits between
-    // sweeps: before a step it waits for the step LAG back (so the device
-    // always holds queued work) and reads the records written so far.
+    // Deterministic schedule: the host keeps the device one sweep ahead of
+    // what it has seen finish. The close kernel marks a window whose sweep
+    // changed nothing, and a sweep of that window already queued exits at
+    // once (leaving an empty record, so records number the launches). Before
+    // a step the host also waits for the step LAG back and reads the records
+    // written up to it.
     const bool devq = R.det && !(p.flags & SR_RUN_FIXED_INNER);
     constexpr int LAG = 2;
     std::vector<hipEvent_t> lag_ev(LAG + 1, nullptr);
     std::vector<uint64_t> lag_rec(LAG + 1, 0);  // records written once that step has ended
-    if (devq)
+    hipEvent_t sw_ev[3] = {nullptr, nullptr, nullptr};  // after each of the last three sweeps of a step
+    uint64_t sw_rec[3] = {0, 0, 0};
+    if (devq) {
       for (auto &ev : lag_ev) ev = mk();
+      for (auto &ev : sw_ev) ev = mk();
+    }
     int64_t step_idx = 0;
     uint64_t rec_launched = 0;  // records the enqueued kernels will have written (devq: one per sweep)
-    struct Cleanup { std::vector<hipEvent_t> *v; ~Cleanup() { for (auto e : *v) (void)hipEventDestroy(e); } } cl{&own};
+    struct Cleanup { std::vector<hipEvent_t> *v; ~Cleanup() { for (auto e : *v) if (e) (void)hipEventDestroy(e); } } cl{&own};
     for (auto ev : own) if (!ev) return c->fail(SR_EDEVICE, "event creation failed");
     std::vector<int32_t> &slot_page = g->res.slot_page;
     std::fill(slot_page.begin(), slot_page.end(), -1);  // slot contents of older runs are not trusted
@@ -1235,12 +1247,26 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
         SweepArgs a;
         if ((s = R.make_args(win, ws, 0, a)) != SR_OK) return s;
         if (devq) {
+          // one sweep stays queued beyond the newest one the host has seen
+          // finish: before launching sweep k the host waits for sweep k-2 and
+          // stops when it changed nothing (sweep k-1, already queued, then
+          // exits at once), so a window step launches at most one sweep that
+          // does no work and the device never waits for the host
           const int32_t iters = R.delta_on ? 1 : p.max_inner_iters;  // delta: one sweep per page and pass
           a.win_skip = 1;
           for (int32_t it = 0; it < iters; ++it) {
+            if (it >= 2) {
+              const int k = (it - 2) % 3;
+              HIP_TRY(c, hipEventSynchronize(sw_ev[k]), "sweep wait");
+              absorb(sw_rec[k]);
+              if (done) break;
+              if (c->ring_host[(sw_rec[k] - 1) & c->ring_mask].changed == 0) break;
+            }
             a.win_first = it == 0 ? 1 : 0;
             if ((s = R.launch(a)) != SR_OK) return s;
             ++rec_launched;
+            HIP_TRY(c, hipEventRecord(sw_ev[it % 3], c->compute), "sweep event");
+            sw_rec[it % 3] = rec_launched;
           }
         }
         for (int32_t it = 0; !devq && it < p.max_inner_iters; ++it) {

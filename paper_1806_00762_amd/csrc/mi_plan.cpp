@@ -10,6 +10,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <sstream>
 
@@ -25,7 +26,9 @@ double now_ms() {
 }
 
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune_cache;  // key -> (grid blocks, grab)
+// key -> chosen schedule: group width, vertex rounds per item, grid blocks, grab
+struct Tuned { int K, rounds, grid, grab; };
+std::map<std::string, Tuned> g_tune_cache;
 
 void load_tune_file() {
   static bool loaded = false;
@@ -35,12 +38,14 @@ void load_tune_file() {
   if (!path) return;
   std::ifstream f(path);
   std::string line;
-  // one entry per line: key grid grab
+  // one entry per line: key K rounds grid grab
   while (std::getline(f, line)) {
     std::istringstream is(line);
     std::string key;
-    int grid = 0, grab = 0;
-    if (is >> key >> grid >> grab && grid > 0 && grab > 0) g_tune_cache[key] = {grid, grab};
+    Tuned t{};
+    if (is >> key >> t.K >> t.rounds >> t.grid >> t.grab && t.grid > 0 && t.grab > 0 &&
+        (t.rounds == 2 || t.rounds == 4 || t.rounds == 8) && (t.K == 8 || t.K == 16 || t.K == 32))
+      g_tune_cache[key] = t;
   }
 }
 
@@ -48,7 +53,9 @@ void save_tune_file() {
   const char *path = getenv("SR_TUNE_CACHE");
   if (!path) return;
   std::ofstream f(path, std::ios::trunc);
-  for (auto &kv : g_tune_cache) f << kv.first << " " << kv.second.first << " " << kv.second.second << "\n";
+  for (auto &kv : g_tune_cache)
+    f << kv.first << " " << kv.second.K << " " << kv.second.rounds << " " << kv.second.grid << " "
+      << kv.second.grab << "\n";
 }
 }  // namespace
 
@@ -117,6 +124,7 @@ sr_status MiPlan::add_group(sr_graph *g, int pvu, int *out_index) {
 sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
   sr_status s;
   units.clear();
+  unit_hdr.clear();
   unit_prefix.assign(1, 0);
   int32_t total_heavy = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -138,19 +146,12 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
       }
       u.heavy_base = total_heavy;
       total_heavy += h.n_heavy;
-      int32_t acc = 0;
-      u.blk_prefix[0] = 0;
-      for (int b = 0; b < NBINS; ++b) {
-        int per = mi_items_per_block_host(b, K);
-        int nb = (b == BIN_ZERO && algo != A_PPR) ? 0 : (h.bin_count[b] + per - 1) / per;
-        acc += nb;
-        u.blk_prefix[b + 1] = acc;
-      }
       units.push_back(u);
-      unit_prefix.push_back(unit_prefix.back() + acc);
+      unit_hdr.push_back(h);
     }
   }
   if (units.empty()) return c->fail(SR_EINVAL, "no work units");
+  prefix_tables();
   if ((int)groups.size() * K > MI_MAX_INSTANCES)
     return c->fail(SR_EINVAL, "too many instances in one call (at most " + std::to_string(MI_MAX_INSTANCES) + ")");
   if ((s = alloc((void **)&d_groups, sizeof(MiGroup) * groups.size(), "group table")) != SR_OK) return s;
@@ -183,6 +184,7 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
   args.total_heavy = total_heavy;
   args.heavy_blocks = (int32_t)std::max<int64_t>(1, ((int64_t)total_heavy * K + BLOCK - 1) / BLOCK);
   args.grab = 1;
+  args.rounds = rounds;
   args.damping = damping;
   args.tol_l1 = tol_l1;
   args.floor_cap = 1e-6;
@@ -195,6 +197,37 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   grid_blocks = std::max(1, std::min(cus * 4, args.total_items));
+  args.nblocks = grid_blocks;
+  return SR_OK;
+}
+
+void MiPlan::prefix_tables() {
+  unit_prefix.assign(1, 0);
+  for (size_t i = 0; i < units.size(); ++i) {
+    const PageHeader &h = unit_hdr[i];
+    MiUnit &u = units[i];
+    int32_t acc = 0;
+    u.blk_prefix[0] = 0;
+    for (int b = 0; b < NBINS; ++b) {
+      const int per = mi_items_per_block_host(b, K, rounds);
+      const int nb = (b == BIN_ZERO && algo != A_PPR) ? 0 : (h.bin_count[b] + per - 1) / per;
+      acc += nb;
+      u.blk_prefix[b + 1] = acc;
+    }
+    unit_prefix.push_back(unit_prefix.back() + acc);
+  }
+}
+
+sr_status MiPlan::set_rounds(int r) {
+  if (r != 2 && r != 4 && r != 8) return c->fail(SR_EINVAL, "rounds must be 2, 4 or 8");
+  rounds = r;
+  prefix_tables();
+  hipError_t e = hipMemcpy(d_units, units.data(), sizeof(MiUnit) * units.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_prefix, unit_prefix.data(), 4ull * unit_prefix.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return c->hip_fail(e, "schedule tables");
+  args.rounds = r;
+  args.total_items = unit_prefix.back();
+  grid_blocks = std::max(1, std::min(grid_blocks, args.total_items));
   args.nblocks = grid_blocks;
   return SR_OK;
 }
@@ -249,14 +282,17 @@ sr_status MiPlan::launch(hipStream_t s) {
   return SR_OK;
 }
 
-sr_status MiPlan::autotune(hipStream_t s, const std::string &key) {
+sr_status MiPlan::autotune(hipStream_t s, const std::string &key, int only_rounds) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file();
     auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      grid_blocks = std::min(it->second.first, std::max(1, args.total_items));
-      grab = it->second.second;
+    if (it != g_tune_cache.end() && it->second.K == K) {
+      const Tuned t = it->second;
+      sr_status st = set_rounds(t.rounds);
+      if (st != SR_OK) return st;
+      grid_blocks = std::min(t.grid, std::max(1, args.total_items));
+      grab = t.grab;
       args.nblocks = grid_blocks;
       args.grab = grab;
       tuned = false;
@@ -266,30 +302,36 @@ sr_status MiPlan::autotune(hipStream_t s, const std::string &key) {
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  std::vector<int> roundss = {2, 4, 8};
+  if (only_rounds) roundss = {only_rounds};
   const int mults[] = {1, 2, 4, 8, 16};
   const int grabs[] = {1, 2, 4, 8};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return c->fail(SR_EDEVICE, "event creation failed");
   float best = 1e30f;
-  int best_grid = grid_blocks, best_grab = 1;
+  int best_grid = grid_blocks, best_grab = 1, best_rounds = rounds;
   args.tuning = 1;
   sr_status st = SR_OK;
-  for (int m : mults) {
-    for (int gb : grabs) {
-      int grid = std::max(1, std::min(cus * m, (args.total_items + gb - 1) / gb));
-      args.nblocks = grid;
-      args.grab = gb;
-      if ((st = launch(s)) != SR_OK) break;  // warm
-      (void)hipEventRecord(e0, s);
-      for (int r = 0; r < 3; ++r)
-        if ((st = launch(s)) != SR_OK) break;
-      (void)hipEventRecord(e1, s);
+  for (int rd : roundss) {
+    if ((st = set_rounds(rd)) != SR_OK) break;
+    for (int m : mults) {
+      for (int gb : grabs) {
+        int grid = std::max(1, std::min(cus * m, (args.total_items + gb - 1) / gb));
+        args.nblocks = grid;
+        args.grab = gb;
+        if ((st = launch(s)) != SR_OK) break;  // warm
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 3; ++r)
+          if ((st = launch(s)) != SR_OK) break;
+        (void)hipEventRecord(e1, s);
+        if (st != SR_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) { st = c->fail(SR_EDEVICE, "tuning sync"); break; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; best_grid = grid; best_grab = gb; best_rounds = rd; }
+      }
       if (st != SR_OK) break;
-      if (hipEventSynchronize(e1) != hipSuccess) { st = c->fail(SR_EDEVICE, "tuning sync"); break; }
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) { best = ms; best_grid = grid; best_grab = gb; }
     }
     if (st != SR_OK) break;
   }
@@ -297,13 +339,15 @@ sr_status MiPlan::autotune(hipStream_t s, const std::string &key) {
   (void)hipEventDestroy(e1);
   args.tuning = 0;
   if (st != SR_OK) return st;
+  if ((st = set_rounds(best_rounds)) != SR_OK) return st;
   grid_blocks = best_grid;
   grab = best_grab;
   args.nblocks = grid_blocks;
   args.grab = grab;
   tuned = true;
+  tuned_ms = best / 3.0f;
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_cache[key] = {grid_blocks, grab};
+  g_tune_cache[key] = {K, rounds, grid_blocks, grab};
   save_tune_file();
   return SR_OK;
 }
@@ -359,8 +403,6 @@ extern "C" sr_status sr_batch_run(sr_ctx *c, const sr_instance *inst, int32_t co
   if (common && common->pvu == SR_PVU_OFF) pvu = P_OFF;
   if (common && common->pvu == SR_PVU_WEAK) return c->fail(SR_EINVAL, "batched runs use OFF or STRONG prediction");
   if (ppr) pvu = P_OFF;
-  const int K = 8;
-  MiPlan plan(c, ppr ? A_PPR : A_SSSP, K);
   // group instances by graph (first appearance order), K per group
   std::vector<sr_graph *> order;
   for (int32_t i = 0; i < count; ++i)
@@ -376,49 +418,120 @@ extern "C" sr_status sr_batch_run(sr_ctx *c, const sr_instance *inst, int32_t co
       if ((s = sr_graph_partition(g, 1, 0)) != SR_OK) return s;
     if ((s = ensure_residency(g, weights, false, true)) != SR_OK) return s;
     if (!g->res.resident) return c->fail(SR_EBUDGET, "a batched graph does not fit the budget resident");
-    int gi = -1, col = K;
-    for (int32_t i = 0; i < count; ++i) {
-      if (inst[i].g != g) continue;
-      if (col == K) {
-        if ((s = plan.add_group(g, pvu, &gi)) != SR_OK) return s;
-        col = 0;
-      }
-      where[i] = {gi, col++};
-    }
   }
-  if ((s = plan.finalize(damping, tol, max_sweeps)) != SR_OK) return s;
   hipStream_t st = c->compute;
-  auto init_all = [&]() -> sr_status {
-    std::vector<uint32_t> gact(plan.groups.size(), 0);
-    for (size_t gi = 0; gi < plan.groups.size(); ++gi)
-      for (int col = 0; col < K; ++col) {
+  // a plan of groups K columns wide over the graphs, every instance set
+  auto build = [&](int K, std::unique_ptr<MiPlan> &out) -> sr_status {
+    out.reset(new MiPlan(c, ppr ? A_PPR : A_SSSP, K));
+    MiPlan &pl = *out;
+    sr_status q;
+    for (sr_graph *g : order) {
+      int gi = -1, col = K;
+      for (int32_t i = 0; i < count; ++i) {
+        if (inst[i].g != g) continue;
+        if (col == K) {
+          if ((q = pl.add_group(g, pvu, &gi)) != SR_OK) return q;
+          col = 0;
+        }
+        where[i] = {gi, col++};
+      }
+    }
+    return pl.finalize(damping, tol, max_sweeps);
+  };
+  auto init_all = [&](MiPlan &pl) -> sr_status {
+    std::vector<uint32_t> gact(pl.groups.size(), 0);
+    for (size_t gi = 0; gi < pl.groups.size(); ++gi)
+      for (int col = 0; col < pl.K; ++col) {
         // unused columns of a partial group stay inactive
-        sr_status q = plan.set_column((int)gi, col, -1, false, false, st);
+        sr_status q = pl.set_column((int)gi, col, -1, false, false, st);
         if (q != SR_OK) return q;
       }
     for (int32_t i = 0; i < count; ++i) {
-      sr_status q = plan.set_column(where[i].group, where[i].col, inst[i].source, inst[i].algo == SR_BFS, true, st);
+      sr_status q = pl.set_column(where[i].group, where[i].col, inst[i].source, inst[i].algo == SR_BFS, true, st);
       if (q != SR_OK) return q;
       gact[where[i].group]++;
     }
-    hipError_t e = hipMemcpyAsync(plan.args.group_active, gact.data(), 4 * gact.size(), hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(pl.args.group_active, gact.data(), 4 * gact.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return c->hip_fail(e, "group activity");
-    sr_status q = plan.set_remaining((uint32_t)count, st);
+    sr_status q = pl.set_remaining((uint32_t)count, st);
     if (q != SR_OK) return q;
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return c->hip_fail(e, "batch init");
     return SR_OK;
   };
-  if ((s = init_all()) != SR_OK) return s;
+  // The schedule: group width K (instance columns sharing each gathered row),
+  // vertex rounds per work item, grid size and grab, tuned by timing one
+  // sweep over every instance and cached under the workload's signature:
+  // the algorithm and, per graph, its scale bucket (ceil log2 n), edge
+  // factor (m / n rounded) and instance count.
+  std::string key;
   {
-    uint64_t edges = 0;
-    for (auto *g : order) edges += (uint64_t)g->m;
-    char key[160];
-    std::snprintf(key, sizeof(key), "a%d_K%d_u%d_items%d_m%llu", plan.algo, K, (int)plan.units.size(),
-                  plan.args.total_items / 64, (unsigned long long)(edges >> 20));
-    if ((s = plan.autotune(st, key)) != SR_OK) return s;
-    if (plan.tuned && (s = init_all()) != SR_OK) return s;
+    std::vector<std::string> parts;
+    for (sr_graph *g : order) {
+      int per = 0;
+      for (int32_t i = 0; i < count; ++i) per += inst[i].g == g;
+      int sc = 0;
+      while ((1ll << sc) < (long long)g->n) ++sc;
+      const long long ef = g->n ? ((long long)g->m + g->n / 2) / g->n : 0;
+      parts.push_back("s" + std::to_string(sc) + "e" + std::to_string(ef) + "x" + std::to_string(per));
+    }
+    std::sort(parts.begin(), parts.end());
+    key = ppr ? "ppr" : "min";
+    for (auto &x : parts) key += "_" + x;
   }
+  std::vector<int> widths = ppr ? std::vector<int>{8, 16} : std::vector<int>{8, 16, 32};
+  // SR_BATCH_SCHEDULE="K,rounds" fixes both (grid and grab still tuned)
+  int force_rounds = 0;
+  if (const char *fs = getenv("SR_BATCH_SCHEDULE")) {
+    int fk = 0, fr = 0;
+    if (std::sscanf(fs, "%d,%d", &fk, &fr) != 2 || std::find(widths.begin(), widths.end(), fk) == widths.end() ||
+        (fr != 2 && fr != 4 && fr != 8))
+      return c->fail(SR_EINVAL, "SR_BATCH_SCHEDULE must be \"K,rounds\" with a valid width and rounds 2, 4 or 8");
+    widths = {fk};
+    force_rounds = fr;
+    key += "_forced" + std::to_string(fk) + "r" + std::to_string(fr);
+  }
+  if (!force_rounds) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file();
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end() && std::find(widths.begin(), widths.end(), it->second.K) != widths.end())
+      widths = {it->second.K};
+  }
+  std::unique_ptr<MiPlan> best;
+  int candidates = 0;
+  for (int K : widths) {
+    std::unique_ptr<MiPlan> pl;
+    if ((s = build(K, pl)) != SR_OK) {
+      // a wider plan that does not fit the budget is skipped
+      if (s == SR_EBUDGET && best) continue;
+      return s;
+    }
+    if ((s = init_all(*pl)) != SR_OK) return s;
+    if ((s = pl->autotune(st, key, force_rounds)) != SR_OK) return s;
+    candidates++;
+    if (!best || (pl->tuned && best->tuned && pl->tuned_ms < best->tuned_ms)) best = std::move(pl);
+  }
+  MiPlan &plan = *best;
+  const int K = plan.K;
+  // the instance slots of the chosen plan (building the others overwrote them)
+  {
+    int gi = -1;
+    for (sr_graph *g : order) {
+      int col = K;
+      for (int32_t i = 0; i < count; ++i) {
+        if (inst[i].g != g) continue;
+        if (col == K) { ++gi; col = 0; }
+        where[i] = {gi, col++};
+      }
+    }
+  }
+  if (candidates > 1 || plan.tuned) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {plan.K, plan.rounds, plan.grid_blocks, plan.grab};
+    save_tune_file();
+  }
+  if ((s = init_all(plan)) != SR_OK) return s;
   if ((s = plan.capture(st)) != SR_OK) return s;
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
@@ -510,6 +623,8 @@ extern "C" sr_status sr_batch_run(sr_ctx *c, const sr_instance *inst, int32_t co
     bst->grid_blocks = plan.grid_blocks;
     bst->grab = plan.grab;
     bst->tuned = plan.tuned ? 1 : 0;
+    bst->rounds = plan.rounds;
+    bst->width_candidates = candidates;
     bst->kernel_ms = kms;
     bst->wall_ms = now_ms() - t0;
     bst->algo_bytes = algo_bytes;

@@ -35,7 +35,10 @@ struct MiPlan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int grid_blocks = 0, grab = 1;
+  int rounds = 4;                    // vertex rounds per wavefront and item (small-degree bins)
   bool tuned = false;
+  float tuned_ms = 0.f;              // time of one sweep with the chosen schedule (when tuned)
+  std::vector<PageHeader> unit_hdr;  // host copy of each unit's page header (bin counts)
 
   explicit MiPlan(sr_ctx *ctx, int algo_, int K_) : c(ctx), algo(algo_), K(K_) {}
   ~MiPlan();
@@ -52,9 +55,15 @@ struct MiPlan {
   // every column of every group back to INF (SSSP/BFS plans)
   sr_status clear_values(hipStream_t s);
   sr_status set_remaining(uint32_t r, hipStream_t s);
-  // pick grid size and grab by timing candidate sweeps; restores nothing
-  // (callers re-initialise their columns afterwards)
-  sr_status autotune(hipStream_t s, const std::string &key);
+  // work items per unit and bin for the current rounds (host tables)
+  void prefix_tables();
+  // work items per unit and bin for `rounds`, uploaded (the tables keep their size)
+  sr_status set_rounds(int r);
+  // pick rounds, grid size and grab by timing candidate sweeps (or take them
+  // from the cache under `key`); restores nothing (callers re-initialise
+  // their columns afterwards)
+  // (only_rounds != 0: that rounds value alone)
+  sr_status autotune(hipStream_t s, const std::string &key, int only_rounds = 0);
   sr_status launch(hipStream_t s);
   sr_status capture(hipStream_t s);
   sr_status replay(hipStream_t s, int times);

@@ -108,3 +108,54 @@ def test_batched_interleaved_graphs_and_sizes(sr, ctx):
         assert np.max(np.abs(x.view(np.float32).astype(np.float64) - ref)) <= 1e-6, (gi, s)
     for G in Gs:
         G.close()
+
+
+@pytest.mark.parametrize("family,K,rounds", [("ppr", 8, 2), ("ppr", 16, 8), ("ppr", 16, 4),
+                                             ("min", 8, 8), ("min", 16, 2), ("min", 32, 4), ("min", 32, 8)])
+def test_batched_schedule_widths_and_rounds(sr, ctx, family, K, rounds, monkeypatch):
+    """Every group width and vertex-rounds choice the autotuner can pick gives
+    the oracle's results: PPR within 1e-6 max-abs, SSSP/BFS bit-exact
+    (SR_BATCH_SCHEDULE fixes K and rounds; grid and grab are still tuned)."""
+    monkeypatch.setenv("SR_BATCH_SCHEDULE", f"{K},{rounds}")
+    graphs = [graphgen.rmat(11, 16, seed=71, weights=(1, 255, 72)), graphgen.rmat(13, 8, seed=73, weights=(1, 255, 74))]
+    Gs = [ctx.load(g, reorder=gi == 1) for gi, g in enumerate(graphs)]
+    insts = []
+    for gi, g in enumerate(graphs):
+        for j, s in enumerate(graphgen.sources_with_outedges(g, 19, seed=3000 + gi)):
+            algo = "ppr" if family == "ppr" else ("sssp" if j % 2 == 0 else "bfs")
+            insts.append((gi, algo, int(s)))
+    say(f"case batched schedule {family} K={K} rounds={rounds}")
+    outs, per, bs = sr.batch_run(ctx, [(Gs[gi], a, s) for gi, a, s in insts])
+    assert bs["group_width"] == K and bs["rounds"] == rounds
+    for (gi, a, s), x, st in zip(insts, outs, per):
+        assert st["converged"] == 1
+        if a == "ppr":
+            ref, _, _ = oracle.pagerank(graphs[gi], seed=s, tol=1e-13)
+            assert float(np.max(np.abs(x.view(np.float32).astype(np.float64) - ref))) <= 1e-6
+        else:
+            ref = oracle.sssp(graphs[gi], s) if a == "sssp" else oracle.bfs(graphs[gi], s)
+            assert np.array_equal(x, ref), (gi, a, s)
+    for G in Gs:
+        G.close()
+
+
+def test_batched_autotuner_times_every_width(sr, ctx, monkeypatch):
+    """Without a fixed schedule the first call times every group width (a
+    fresh workload signature), picks one, and a repeat call takes it from the
+    cache; results stay bit-exact."""
+    monkeypatch.delenv("SR_BATCH_SCHEDULE", raising=False)
+    g = graphgen.rmat(12, 12, seed=81, weights=(1, 255, 82))
+    G = ctx.load(g)
+    srcs = [int(s) for s in graphgen.sources_with_outedges(g, 32, seed=3100)]
+    outs, per, bs = sr.batch_run(ctx, [(G, "sssp", s) for s in srcs])
+    say(f"  first call schedule {bs}")
+    assert bs["width_candidates"] == 3 and bs["tuned"] == 1
+    assert bs["group_width"] in (8, 16, 32) and bs["rounds"] in (2, 4, 8)
+    outs2, _, bs2 = sr.batch_run(ctx, [(G, "sssp", s) for s in srcs])
+    assert bs2["width_candidates"] == 1 and bs2["tuned"] == 0
+    assert (bs2["group_width"], bs2["rounds"], bs2["grid_blocks"], bs2["grab"]) == \
+        (bs["group_width"], bs["rounds"], bs["grid_blocks"], bs["grab"])
+    for s, x, x2 in zip(srcs, outs, outs2):
+        ref = oracle.sssp(g, s)
+        assert np.array_equal(x, ref) and np.array_equal(x2, ref)
+    G.close()
