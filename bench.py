@@ -236,8 +236,10 @@ def bench_sssp22(args):
     info = G.info()
     log(f"[bench] loaded+partitioned in {time.perf_counter() - t:.1f}s: {info['num_parts']} pages, "
         f"budget {budget / 1e6:.1f} MB, graph {gbytes / 1e6:.1f} MB")
+    # the fixed schedule (see the CC leg) makes profiled runs sweep as the timed ones do
     run_kw = dict(source=0, pvu=args.pvu, max_inner_iters=args.inner, force_stream=True,
-                  copy_depth=args.copy_depth, wide_pages=args.wide_pages)
+                  copy_depth=args.copy_depth, wide_pages=args.wide_pages,
+                  deterministic=args.schedule == "fixed")
     for i in range(args.warmup):
         st = G.run("sssp", **run_kw)
         log(f"[bench] warmup {i}: {st['wall_ms']:.1f} ms, passes {st['passes']}")
@@ -285,6 +287,8 @@ def bench_sssp22(args):
                    "vertex_order": "in-degree descending (results in input ids)" if args.order == "degree"
                    else "input",
                    "page_image": "full-width" if args.wide_pages else "split-width",
+                   "schedule": "fixed re-entry (until no change, <= max_inner_iters)" if args.schedule == "fixed"
+                   else "re-entry until the next page lands",
                    "narrow_edge_frac": round(narrow / max(scanned, 1), 4)},
         "roofline": {"bound": "hbm", "kernel": "sweep_kernel<SSSP>",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -446,6 +450,24 @@ def ablation(args, G, parts, dist):
         out[name] = row
         log(f"[bench] ablation {name}: {row['ms_per_solve']} ms, {row['passes']} passes, {row['sweeps']} sweeps")
     G.partition(parts, args.slots)
+    return out
+
+
+def bench_probe(args):
+    """The gather probe alone on the streamed SSSP workload's edge words
+    (R-MAT scale 22, device numbering): for hardware counters on the bare
+    gather (sr_probe_gather, 20 timed launches)."""
+    import graphgen
+    import oracle
+    import paper_1806_00762_amd as sr
+    g = graphgen.recipes.sssp_s22()
+    ctx = sr.Context(0, 0)
+    G = ctx.load(g, reorder=args.order == "degree")
+    G.partition(0, args.slots)
+    dist = oracle.sssp(g, 0)
+    out = gather_probe(args, g, G, dist)
+    G.close()
+    ctx.close()
     return out
 
 
@@ -798,7 +820,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (for HBM counter scaling)")
     ap.add_argument("--served-timeout", type=float, default=90.0)
-    ap.add_argument("--only", choices=["batched", "served", "lattice", "pagerank16"],
+    ap.add_argument("--only", choices=["batched", "served", "lattice", "pagerank16", "probe"],
                     help="run one extra leg alone and print its JSON object")
     ap.add_argument("--copy-depth", type=int, default=2,
                     help="page copies kept in flight ahead of the window (1 = the paper's layout)")
@@ -818,7 +840,7 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="also time the Section 5.4 schedules (baseline, re-entry, pipelined, +predictors)")
     ap.add_argument("--schedule", choices=["fixed", "copy"], default="fixed",
-                    help="streamed CC windows: re-swept until no change (fixed, timing-independent) or until "
+                    help="streamed windows: re-swept until no change (fixed, timing-independent) or until "
                          "the next page has landed (copy)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work of the oracle baseline (repeated solves)")
@@ -835,7 +857,7 @@ def main():
     if args.only:
         # one extra leg alone (for profiling it): its JSON object only
         fn = {"batched": bench_batched, "served": bench_served, "lattice": bench_lattice,
-              "pagerank16": bench_pagerank16}[args.only]
+              "pagerank16": bench_pagerank16, "probe": bench_probe}[args.only]
         print(json.dumps(fn(args)), flush=True)
         return
     if args.headline == "cc24":

@@ -455,13 +455,18 @@ sr_status sr_batch_run(sr_ctx *ctx, const sr_instance *instances, int32_t count,
 
 /* A continuous-batching query server (beyond the paper): SSSP and BFS
  * source queries on resident graphs. Each graph owns max_slots_per_graph
- * (8, 16 or 32) query slots whose state (4 B distance per vertex per slot) is
- * allocated up front if state_budget_bytes allows, else as many slots as
+ * (8, 16 or 32) query slots whose state (a 16-bit distance or level per
+ * vertex per slot, plus one 4 B-per-vertex result buffer per running query)
+ * is allocated up front if state_budget_bytes allows, else as many slots as
  * fit. A progress thread admits queued queries into free slots as they
  * free up, sweeps every graph with active slots (one multi-source sweep
  * per graph, all its active slots together), retires converged slots (a
  * sweep without change under the Table I strong conditions), copies their
- * values to host and records latency = completion - submission. */
+ * values to host and records latency = completion - submission. Results
+ * are exact u32 values: a slot whose distances do not all fit 16 bits
+ * (some vertex at distance 65535 or more) is completed on the host when it
+ * retires (label-correcting push from every reached vertex), which the
+ * stats count. */
 sr_status sr_server_create(sr_ctx *ctx, sr_graph *const *graphs, int32_t ngraphs,
                            uint64_t state_budget_bytes, int32_t max_slots_per_graph,
                            sr_server **out);
@@ -479,6 +484,8 @@ typedef struct {
   uint64_t submitted, completed, sweeps;
   int32_t slots_per_graph[8];
   double busy_ms;        /* progress-thread time spent with work in flight */
+  uint64_t narrow_fallbacks; /* retired queries whose 16-bit slot column overflowed and were completed
+                                exactly on the host */
 } sr_server_stats;
 sr_status sr_server_stats_get(sr_server *srv, sr_server_stats *out);
 /* Stop the progress thread after finishing admitted queries, free the

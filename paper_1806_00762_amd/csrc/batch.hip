@@ -52,6 +52,60 @@ namespace {
 template <int ALGO>
 constexpr bool mi_pr() { return ALGO == A_PPR; }
 
+// SSSP/BFS columns whose values are stored as 16 bits ([n][K] u16, 0xFFFF =
+// unreached): rows half as wide. A candidate that does not fit 16 bits is
+// not stored (the vertex keeps its old value) and sets the column's overflow
+// flag; the caller then completes that column exactly on the host.
+constexpr int A_MIN16 = 100;
+template <int ALGO>
+constexpr bool mi_narrow() { return ALGO == A_MIN16; }
+constexpr uint32_t INF16 = 0xFFFFu;
+
+// Loads through pointers the compiler cannot place (they come from the
+// group and unit tables): declared global, so they compile to global loads
+// whose waits count vector memory only, not to flat loads.
+typedef __attribute__((address_space(1))) const uint32_t g_u32;
+typedef __attribute__((address_space(1))) const uint16_t g_u16;
+typedef __attribute__((address_space(1))) const int32_t g_i32;
+typedef __attribute__((address_space(1))) const float g_f32;
+__device__ inline uint32_t ldg(const uint32_t *p) { return *(g_u32 *)p; }
+__device__ inline uint32_t ldg(const uint16_t *p) { return *(g_u16 *)p; }
+__device__ inline int32_t ldg(const int32_t *p) { return *(g_i32 *)p; }
+__device__ inline float ldg(const float *p) { return *(g_f32 *)p; }
+
+// Stored value of column k at row i (16 or 32 bits), and its u32-domain
+// reading (INF for an unreached vertex).
+template <int ALGO>
+__device__ inline uint32_t mi_ld_raw(const MiGroup &g, size_t i) {
+  if constexpr (mi_narrow<ALGO>()) return ldg(reinterpret_cast<const uint16_t *>(g.value) + i);
+  else return ldg(g.value + i);
+}
+template <int ALGO>
+__device__ inline uint32_t mi_cvt(uint32_t x) {
+  if constexpr (mi_narrow<ALGO>()) return x == INF16 ? INF : x;
+  else return x;
+}
+template <int ALGO>
+__device__ inline uint32_t mi_ld(const MiGroup &g, size_t i) {
+  return mi_cvt<ALGO>(mi_ld_raw<ALGO>(g, i));
+}
+
+// Weight of an in-edge, by the group's weight mode (fixed per work item, so
+// the edge loops have no branch around a load): 0 unit weights (BFS columns
+// and PageRank ignore it), 1 packed in the top byte of the edge word, 2 a
+// separate u32 weight array.
+template <int WM>
+__device__ inline uint32_t mi_w(uint32_t q, const uint32_t *wt, int32_t e) {
+  if constexpr (WM == 1) return q >> 24;
+  else if constexpr (WM == 2) return ldg(wt + e);
+  else return 1u;
+}
+template <int ALGO>
+__device__ inline int mi_wmode(const MiGroup &g) {
+  if constexpr (ALGO == A_SSSP || ALGO == A_MIN16) return g.has_w ? (g.packed ? 1 : 2) : 0;
+  else return 0;
+}
+
 // Per-lane state of one instance column for the current item.
 struct Lane {
   uint32_t active, unit, threshold;
@@ -80,10 +134,19 @@ struct MiRed {
     if constexpr (mi_pr<ALGO>()) return a + b; else return min(a, b);
   }
   __device__ static inline T edge(const MiGroup &g, int32_t u, uint32_t w, int k, const Lane &ln) {
+    return cand(raw(g, u, k), w, ln);
+  }
+  // the gathered value of in-neighbour u as stored (the load alone) ...
+  __device__ static inline uint32_t raw(const MiGroup &g, int32_t u, int k) {
+    if constexpr (mi_pr<ALGO>()) return __float_as_uint(ldg(g.contrib + (size_t)u * K + k));
+    else return mi_ld_raw<ALGO>(g, (size_t)u * K + k);
+  }
+  // ... and its contribution through an edge of weight w
+  __device__ static inline T cand(uint32_t xs, uint32_t w, const Lane &ln) {
     if constexpr (mi_pr<ALGO>()) {
-      return g.contrib[(size_t)u * K + k];
+      return __uint_as_float(xs);
     } else {
-      uint32_t x = g.value[(size_t)u * K + k];
+      const uint32_t x = mi_cvt<ALGO>(xs);
       if (x == INF) return INF;
       uint64_t c = (uint64_t)x + (ln.unit ? 1ull : (uint64_t)w);
       return c >= (uint64_t)INF ? INF : (uint32_t)c;
@@ -134,7 +197,7 @@ __device__ inline void lds_add(MiLds &e, const MiAcc &acc) {
 
 template <int ALGO, int K>
 __device__ inline bool mi_attempt(const MiGroup &g, int32_t v, int k, const Lane &ln, uint32_t &old) {
-  old = g.value[(size_t)v * K + k];
+  old = mi_ld<ALGO>(g, (size_t)v * K + k);
   if (!ln.active) return false;
   if constexpr (!mi_pr<ALGO>()) {
     if (g.pvu == P_STRONG && old <= ln.threshold) return false;  // Table I
@@ -163,9 +226,15 @@ __device__ inline void mi_epilogue(const MiGroup &g, int32_t v, int k, const Lan
   } else {
     uint32_t nv = min(old, red);
     if (nv < old) {
-      g.value[i] = nv;
-      acc.changed++;
-      acc.min_changed = min(acc.min_changed, nv);
+      if (mi_narrow<ALGO>() && nv >= INF16) {
+        // not representable: the vertex stays unreached in this column
+        atomicOr(&g.inst[k].overflow, 1u);
+      } else {
+        if constexpr (mi_narrow<ALGO>()) reinterpret_cast<uint16_t *>(g.value)[i] = (uint16_t)nv;
+        else g.value[i] = nv;
+        acc.changed++;
+        acc.min_changed = min(acc.min_changed, nv);
+      }
     }
   }
 }
@@ -192,14 +261,7 @@ __device__ inline void mi_flush(MiLds *lds, int group, MiAcc &acc) {
 
 // bins 0..5: GE edge lanes per vertex (GE = min(2^b, 64/K)), ROUNDS
 // rounds of 64/K/GE vertices per wavefront
-// Weight of in-edge e with edge word q (1 for unweighted programs).
-template <int ALGO>
-__device__ inline uint32_t mi_weight(const MiGroup &g, uint32_t q, const uint32_t *wt, int32_t e) {
-  if (ALGO != A_SSSP || !g.has_w) return 1u;
-  return g.packed ? q >> 24 : wt[e];
-}
-
-template <int ALGO, int K, int GE, int ROUNDS>
+template <int ALGO, int K, int GE, int ROUNDS, int WM>
 __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h, int bin, int item,
                          const Lane &ln, double damping, MiAcc &acc) {
   using R = MiRed<ALGO, K>;
@@ -223,9 +285,9 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
     // so the rounds' bin, offset and value loads overlap
     const int idx = ((item * WAVES + wave) * ROUNDS + r) * VPW + vs;
     const bool ok = idx < cnt;
-    vl[r] = cnt > 0 ? bins[ok ? idx : 0] : 0;  // an empty bin rereads the page's vertex 0
-    beg[r] = off[vl[r]];
-    end[r] = off[vl[r] + 1];
+    vl[r] = cnt > 0 ? ldg(bins + (ok ? idx : 0)) : 0;  // an empty bin rereads the page's vertex 0
+    beg[r] = ldg(off + vl[r]);
+    end[r] = ldg(off + vl[r] + 1);
     old[r] = 0;
     att[r] = mi_attempt<ALGO, K>(g, vb + vl[r], k, ln, old[r]) && ok;
     if (!ok) vl[r] = -1;
@@ -241,11 +303,11 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           ei[j] = e0 + j * GE < end[r] ? e0 + j * GE : e0;
-          q[j] = src[ei[j]];
+          q[j] = ldg(src + ei[j]);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const T y = R::edge(g, (int32_t)(q[j] & g.src_mask), mi_weight<ALGO>(g, q[j], wt, ei[j]), k, ln);
+          const T y = R::edge(g, (int32_t)(q[j] & g.src_mask), mi_w<WM>(q[j], wt, ei[j]), k, ln);
           if (e0 + j * GE < end[r]) x = R::combine(x, y);
         }
       }
@@ -257,27 +319,53 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
   }
 }
 
-// edge loop of bins 6 and 7: 64/K edge lanes, 8 edges in flight per lane
-template <int ALGO, int K>
+// edge loop of bins 6 and 7: 64/K edge lanes, 8 edges in flight per lane.
+// Software-pipelined: the edge words of the next batch are loaded while the
+// value rows of this batch are gathered, so a batch costs one memory round
+// trip instead of two (words, then the rows they name).
+template <int ALGO, int K, int WM>
 __device__ inline typename MiRed<ALGO, K>::T mi_edges(const MiGroup &g, const uint32_t *src, const uint32_t *wt,
                                                       int32_t e0, int32_t e1, int k, int el, const Lane &ln) {
   using R = MiRed<ALGO, K>;
   using T = typename R::T;
   constexpr int EL = 64 / K;
-  T x = R::identity();
   constexpr int B = 8;
-  for (int e = e0 + el; e < e1; e += B * EL) {
-    int32_t ei[B];
-    uint32_t q[B];
+  // (callers pass e0 < e1; lanes that start past the range load its first
+  // edge and skip the loop, and every lane reaches the final reduction)
+  T x = R::identity();
+  int e = e0 + el;
+  const int eb = e < e1 ? e : e0;
+  int32_t ei[B];
+  uint32_t q[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    ei[j] = e + j * EL < e1 ? e + j * EL : eb;  // past the range: reread a real edge
+    q[j] = ldg(src + ei[j]);
+  }
+  for (; e < e1; e += B * EL) {
+    // the next batch's words, then this batch's gathers: both in flight
+    // together, so the wait for the gathers also covers the next words
+    const int en = e + B * EL;
+    int32_t ein[B];
+    uint32_t qn[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) {
-      ei[j] = e + j * EL < e1 ? e + j * EL : e;  // past the range: reread a real edge
-      q[j] = src[ei[j]];
+      ein[j] = en + j * EL < e1 ? en + j * EL : e;  // past the range: reread this batch's first edge
+      qn[j] = ldg(src + ein[j]);
+    }
+    uint32_t xr[B], w[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      xr[j] = R::raw(g, (int32_t)(q[j] & g.src_mask), k);
+      w[j] = mi_w<WM>(q[j], wt, ei[j]);
     }
 #pragma unroll
+    for (int j = 0; j < B; ++j)
+      if (e + j * EL < e1) x = R::combine(x, R::cand(xr[j], w[j], ln));
+#pragma unroll
     for (int j = 0; j < B; ++j) {
-      const T y = R::edge(g, (int32_t)(q[j] & g.src_mask), mi_weight<ALGO>(g, q[j], wt, ei[j]), k, ln);
-      if (e + j * EL < e1) x = R::combine(x, y);
+      ei[j] = ein[j];
+      q[j] = qn[j];
     }
   }
 #pragma unroll
@@ -286,27 +374,28 @@ __device__ inline typename MiRed<ALGO, K>::T mi_edges(const MiGroup &g, const ui
 }
 
 // bin 6: one wavefront per vertex
-template <int ALGO, int K>
+template <int ALGO, int K, int WM>
 __device__ void mi_wave(const MiGroup &g, const char *base, const PageHeader *h, int item, const Lane &ln,
                         double damping, MiAcc &acc) {
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, k = lane % K, el = lane / K;
   int idx = item * WAVES + wave;
   if (idx >= h->bin_count[BIN_WAVE]) return;
   const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
-  const int32_t vl = reinterpret_cast<const int32_t *>(base + h->off_bins)[h->bin_start[BIN_WAVE] + idx];
+  const int32_t vl = ldg(reinterpret_cast<const int32_t *>(base + h->off_bins) + h->bin_start[BIN_WAVE] + idx);
   const uint32_t *src = reinterpret_cast<const uint32_t *>(base + h->off_src);
   const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
   const int32_t v = h->v_begin + vl;
   uint32_t old;
   bool att = mi_attempt<ALGO, K>(g, v, k, ln, old);
   if (!__any(att)) return;  // lanes of other instances still share the index loads
-  auto x = mi_edges<ALGO, K>(g, src, wt, off[vl], off[vl + 1], k, el, ln);
-  if (att && el == 0) mi_epilogue<ALGO, K>(g, v, k, ln, old, x, (uint32_t)(off[vl + 1] - off[vl]), damping, acc);
+  const int32_t b0 = ldg(off + vl), b1 = ldg(off + vl + 1);
+  auto x = mi_edges<ALGO, K, WM>(g, src, wt, b0, b1, k, el, ln);
+  if (att && el == 0) mi_epilogue<ALGO, K>(g, v, k, ln, old, x, (uint32_t)(b1 - b0), damping, acc);
 }
 
 // bin 7: one wavefront per chunk; each instance column folds its partial
 // into the heavy vertex's accumulator
-template <int ALGO, int K>
+template <int ALGO, int K, int WM>
 __device__ void mi_chunk(const MiGroup &g, const MiUnit &u, const char *base, const PageHeader *h, int item,
                          const Lane &ln) {
   using R = MiRed<ALGO, K>;
@@ -326,7 +415,7 @@ __device__ void mi_chunk(const MiGroup &g, const MiUnit &u, const char *base, co
   uint32_t old;
   bool att = mi_attempt<ALGO, K>(g, v, k, ln, old);
   T x = R::identity();
-  if (__any(att)) x = mi_edges<ALGO, K>(g, src, wt, sb, se, k, el, ln);
+  if (__any(att)) x = mi_edges<ALGO, K, WM>(g, src, wt, sb, se, k, el, ln);
   // fold into the vertex's accumulator (one device-scope atomic per chunk
   // and instance); the heavy-vertex kernel takes it after the sweep
   if (el == 0 && att) {
@@ -353,7 +442,10 @@ __device__ void mi_zero(const MiGroup &g, const char *base, const PageHeader *h,
   }
 }
 
-template <int ALGO, int K, int ROUNDS>
+// WMK: the weight mode of every group of the plan (0, 1, 2), or 3 when the
+// groups differ (then chosen per work item; that kernel needs the registers
+// of the widest mode)
+template <int ALGO, int K, int ROUNDS, int WMK>
 __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
   if (a.ctl->remaining == 0 && !a.tuning) return;  // everything converged: replays are no-ops
   extern __shared__ MiLds lds[];
@@ -385,19 +477,29 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
       const PageHeader *h = reinterpret_cast<const PageHeader *>(bp);
       const Lane ln = lane_of(g.inst[k]);
       MiAcc acc;
+      // the weight mode: the plan's, or the group's when the plan mixes them
+      const int wm = WMK < 3 ? WMK : mi_wmode<ALGO>(g);
+#define MI_WM(CALL)                                                                 \
+  do {                                                                              \
+    if constexpr (WMK < 3) { constexpr int WM = mi_pr<ALGO>() ? 0 : WMK; CALL; }    \
+    else if (wm == 1) { constexpr int WM = mi_pr<ALGO>() ? 0 : 1; CALL; }           \
+    else if (wm == 2) { constexpr int WM = mi_pr<ALGO>() ? 0 : 2; CALL; }           \
+    else { constexpr int WM = 0; CALL; }                                            \
+  } while (0)
       switch (bin) {
-        case 0: mi_small<ALGO, K, 1, ROUNDS>(g, bp, h, 0, item, ln, a.damping, acc); break;
-        case 1: mi_small<ALGO, K, (2 < 64 / K ? 2 : 64 / K), ROUNDS>(g, bp, h, 1, item, ln, a.damping, acc); break;
-        case 2: mi_small<ALGO, K, (4 < 64 / K ? 4 : 64 / K), ROUNDS>(g, bp, h, 2, item, ln, a.damping, acc); break;
-        case 3: mi_small<ALGO, K, (8 < 64 / K ? 8 : 64 / K), ROUNDS>(g, bp, h, 3, item, ln, a.damping, acc); break;
-        case 4: mi_small<ALGO, K, (16 < 64 / K ? 16 : 64 / K), ROUNDS>(g, bp, h, 4, item, ln, a.damping, acc); break;
-        case 5: mi_small<ALGO, K, (32 < 64 / K ? 32 : 64 / K), ROUNDS>(g, bp, h, 5, item, ln, a.damping, acc); break;
-        case BIN_WAVE: mi_wave<ALGO, K>(g, bp, h, item, ln, a.damping, acc); break;
-        case BIN_CHUNK: mi_chunk<ALGO, K>(g, u, bp, h, item, ln); break;
+        case 0: MI_WM((mi_small<ALGO, K, 1, ROUNDS, WM>(g, bp, h, 0, item, ln, a.damping, acc))); break;
+        case 1: MI_WM((mi_small<ALGO, K, (2 < 64 / K ? 2 : 64 / K), ROUNDS, WM>(g, bp, h, 1, item, ln, a.damping, acc))); break;
+        case 2: MI_WM((mi_small<ALGO, K, (4 < 64 / K ? 4 : 64 / K), ROUNDS, WM>(g, bp, h, 2, item, ln, a.damping, acc))); break;
+        case 3: MI_WM((mi_small<ALGO, K, (8 < 64 / K ? 8 : 64 / K), ROUNDS, WM>(g, bp, h, 3, item, ln, a.damping, acc))); break;
+        case 4: MI_WM((mi_small<ALGO, K, (16 < 64 / K ? 16 : 64 / K), ROUNDS, WM>(g, bp, h, 4, item, ln, a.damping, acc))); break;
+        case 5: MI_WM((mi_small<ALGO, K, (32 < 64 / K ? 32 : 64 / K), ROUNDS, WM>(g, bp, h, 5, item, ln, a.damping, acc))); break;
+        case BIN_WAVE: MI_WM((mi_wave<ALGO, K, WM>(g, bp, h, item, ln, a.damping, acc))); break;
+        case BIN_CHUNK: MI_WM((mi_chunk<ALGO, K, WM>(g, u, bp, h, item, ln))); break;
         default:
           if constexpr (mi_pr<ALGO>()) mi_zero<ALGO, K, ROUNDS>(g, bp, h, item, ln, a.damping, acc);
           break;
       }
+#undef MI_WM
       mi_flush<ALGO, K>(lds, u.group, acc);
     }
   }
@@ -529,9 +631,16 @@ __global__ void mi_init_column_kernel(uint32_t *value, float *contrib, const flo
     float x = v == source ? 1.0f : 0.0f;
     value[i] = __float_as_uint(x);
     contrib[i] = x * inv_outdeg[v];
+  } else if constexpr (mi_narrow<ALGO>()) {
+    reinterpret_cast<uint16_t *>(value)[i] = v == source ? (uint16_t)0 : (uint16_t)INF16;
   } else {
     value[i] = v == source ? 0u : INF;
   }
+}
+
+// One entry of a 16-bit column (the source of an admitted query).
+__global__ void mi_set_u16_kernel(uint32_t *value, size_t index, uint32_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) reinterpret_cast<uint16_t *>(value)[index] = (uint16_t)v;
 }
 
 __global__ void mi_set_inst_kernel(MiInst *dst, MiInst val) {
@@ -544,24 +653,45 @@ __global__ void mi_set_ctl_kernel(MiCtl *dst, MiCtl val) {
 
 // Several columns in one pass: the columns of a vertex share its row of
 // 4K bytes, so the row is fetched from memory once for all of them.
-template <int K>
+// NARROW: 16-bit columns, widened to u32 (0xFFFF -> INF) on the way out.
+template <int K, bool NARROW>
 __global__ void mi_extract_kernel(uint32_t *value, int32_t n, MiExtract x, int32_t reset, uint32_t reset_to,
                                   const int32_t *rank) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  uint32_t *row = value + (size_t)(rank ? rank[v] : v) * K;
+  const size_t r = (size_t)(rank ? rank[v] : v) * K;
   for (int j = 0; j < x.count; ++j) {
-    x.out[j][v] = row[x.col[j]];
-    if (reset) row[x.col[j]] = reset_to;
+    if constexpr (NARROW) {
+      uint16_t *row = reinterpret_cast<uint16_t *>(value) + r;
+      const uint32_t y = row[x.col[j]];
+      x.out[j][v] = y == INF16 ? INF : y;
+      if (reset) row[x.col[j]] = (uint16_t)(reset_to >= INF16 ? INF16 : reset_to);
+    } else {
+      uint32_t *row = value + r;
+      x.out[j][v] = row[x.col[j]];
+      if (reset) row[x.col[j]] = reset_to;
+    }
+  }
+}
+
+template <int ALGO, int K, int ROUNDS>
+void mi_sweep_wm(const MiArgs &a, hipStream_t s, size_t lds) {
+  if constexpr (mi_pr<ALGO>()) {
+    hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K, ROUNDS, 0>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
+  } else {
+    if (a.wmode == 0) hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K, ROUNDS, 0>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
+    else if (a.wmode == 1) hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K, ROUNDS, 1>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
+    else if (a.wmode == 2) hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K, ROUNDS, 2>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
+    else hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K, ROUNDS, 3>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
   }
 }
 
 template <int ALGO, int K>
 void mi_pair(const MiArgs &a, hipStream_t s) {
   const size_t lds = sizeof(MiLds) * (size_t)a.ngroups * K;
-  if (a.rounds == 2) hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K, 2>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
-  else if (a.rounds == 8) hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K, 8>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
-  else hipLaunchKernelGGL((mi_sweep_kernel<ALGO, K, 4>), dim3(a.nblocks), dim3(BLOCK), lds, s, a);
+  if (a.rounds == 2) mi_sweep_wm<ALGO, K, 2>(a, s, lds);
+  else if (a.rounds == 8) mi_sweep_wm<ALGO, K, 8>(a, s, lds);
+  else mi_sweep_wm<ALGO, K, 4>(a, s, lds);
   hipLaunchKernelGGL((mi_heavy_kernel<ALGO, K>), dim3(a.heavy_blocks), dim3(BLOCK), 0, s, a);
   hipLaunchKernelGGL((mi_close_kernel<ALGO, K>), dim3(1), dim3(MI_CLOSE_THREADS), 0, s, a);
 }
@@ -574,8 +704,12 @@ hipError_t launch_mi_sweep(int algo, int K, const MiArgs &a, hipStream_t s) {
   if (a.nblocks <= 0) return hipErrorInvalidValue;
   if (a.ngroups * K > MI_MAX_INSTANCES) return hipErrorInvalidValue;
   if (a.rounds != 2 && a.rounds != 4 && a.rounds != 8) return hipErrorInvalidValue;
+  if (a.wmode < 0 || a.wmode > 3) return hipErrorInvalidValue;
   if (algo == A_PPR && K == 8) mi_pair<A_PPR, 8>(a, s);
   else if (algo == A_PPR && K == 16) mi_pair<A_PPR, 16>(a, s);
+  else if (algo == A_SSSP && a.narrow && K == 8) mi_pair<A_MIN16, 8>(a, s);
+  else if (algo == A_SSSP && a.narrow && K == 16) mi_pair<A_MIN16, 16>(a, s);
+  else if (algo == A_SSSP && a.narrow && K == 32) mi_pair<A_MIN16, 32>(a, s);
   else if (algo == A_SSSP && K == 8) mi_pair<A_SSSP, 8>(a, s);
   else if (algo == A_SSSP && K == 16) mi_pair<A_SSSP, 16>(a, s);
   else if (algo == A_SSSP && K == 32) mi_pair<A_SSSP, 32>(a, s);
@@ -584,8 +718,16 @@ hipError_t launch_mi_sweep(int algo, int K, const MiArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contrib, const float *inv_outdeg,
-                                 int32_t n, int32_t col, int32_t source, hipStream_t s) {
+                                 int32_t n, int32_t col, int32_t source, hipStream_t s, bool narrow) {
   dim3 grid((n + 255) / 256), block(256);
+  if (narrow) {
+    if (algo != A_SSSP) return hipErrorInvalidValue;
+    if (K == 8) hipLaunchKernelGGL((mi_init_column_kernel<A_MIN16, 8>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
+    else if (K == 16) hipLaunchKernelGGL((mi_init_column_kernel<A_MIN16, 16>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
+    else if (K == 32) hipLaunchKernelGGL((mi_init_column_kernel<A_MIN16, 32>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (algo == A_PPR && K == 8) hipLaunchKernelGGL((mi_init_column_kernel<A_PPR, 8>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
   else if (algo == A_PPR && K == 16) hipLaunchKernelGGL((mi_init_column_kernel<A_PPR, 16>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
   else if (algo == A_SSSP && K == 8) hipLaunchKernelGGL((mi_init_column_kernel<A_SSSP, 8>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
@@ -596,17 +738,29 @@ hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contri
 }
 
 hipError_t launch_mi_extract(int K, uint32_t *value, int32_t n, const MiExtract &x, hipStream_t s,
-                             bool reset, uint32_t reset_to, const int32_t *rank) {
+                             bool reset, uint32_t reset_to, const int32_t *rank, bool narrow) {
   if (x.count < 1 || x.count > MI_EXTRACT_MAX) return hipErrorInvalidValue;
   for (int j = 0; j < x.count; ++j)
     if (x.col[j] < 0 || x.col[j] >= K || !x.out[j]) return hipErrorInvalidValue;
   if (n <= 0) return hipSuccess;
   dim3 grid((n + 255) / 256), block(256);
   const int32_t r = reset ? 1 : 0;
-  if (K == 8) hipLaunchKernelGGL(mi_extract_kernel<8>, grid, block, 0, s, value, n, x, r, reset_to, rank);
-  else if (K == 16) hipLaunchKernelGGL(mi_extract_kernel<16>, grid, block, 0, s, value, n, x, r, reset_to, rank);
-  else if (K == 32) hipLaunchKernelGGL(mi_extract_kernel<32>, grid, block, 0, s, value, n, x, r, reset_to, rank);
+  if (narrow) {
+    if (K == 8) hipLaunchKernelGGL((mi_extract_kernel<8, true>), grid, block, 0, s, value, n, x, r, reset_to, rank);
+    else if (K == 16) hipLaunchKernelGGL((mi_extract_kernel<16, true>), grid, block, 0, s, value, n, x, r, reset_to, rank);
+    else if (K == 32) hipLaunchKernelGGL((mi_extract_kernel<32, true>), grid, block, 0, s, value, n, x, r, reset_to, rank);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  if (K == 8) hipLaunchKernelGGL((mi_extract_kernel<8, false>), grid, block, 0, s, value, n, x, r, reset_to, rank);
+  else if (K == 16) hipLaunchKernelGGL((mi_extract_kernel<16, false>), grid, block, 0, s, value, n, x, r, reset_to, rank);
+  else if (K == 32) hipLaunchKernelGGL((mi_extract_kernel<32, false>), grid, block, 0, s, value, n, x, r, reset_to, rank);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_mi_set_u16(uint32_t *value, size_t index, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(mi_set_u16_kernel, dim3(1), dim3(64), 0, s, value, index, v);
   return hipGetLastError();
 }
 

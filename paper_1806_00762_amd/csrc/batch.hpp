@@ -35,7 +35,8 @@ struct MiInst {
   double best_l1;
   double last_l1;
   unsigned long long edges_total;
-  uint32_t pad[2];
+  uint32_t overflow;     // 16-bit columns: a candidate did not fit (the host completes the column)
+  uint32_t pad;
 };
 
 // One group: K columns over one graph.
@@ -78,6 +79,9 @@ struct MiArgs {
   int32_t heavy_blocks;     // blocks of the heavy-vertex kernel
   int32_t grab;             // items taken per queue access
   int32_t rounds;           // vertex rounds per wavefront and item in the small-degree bins (2, 4, 8)
+  int32_t narrow;           // SSSP/BFS columns stored as 16 bits (0xFFFF = unreached)
+  int32_t wmode;            // edge weights of every group: 0 none (or PPR), 1 packed in the edge word,
+                            // 2 separate array; 3 when the groups differ
   int32_t nblocks;
   double damping;
   double tol_l1, floor_cap;
@@ -91,7 +95,9 @@ struct MiArgs {
 int mi_items_per_block_host(int b, int K, int rounds);
 hipError_t launch_mi_sweep(int algo, int K, const MiArgs &a, hipStream_t s);
 hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contrib, const float *inv_outdeg,
-                                 int32_t n, int32_t col, int32_t source, hipStream_t s);
+                                 int32_t n, int32_t col, int32_t source, hipStream_t s, bool narrow = false);
+// entry `index` of a 16-bit value array
+hipError_t launch_mi_set_u16(uint32_t *value, size_t index, uint32_t v, hipStream_t s);
 hipError_t launch_mi_set_inst(MiInst *dst, const MiInst &val, hipStream_t s);
 hipError_t launch_mi_set_ctl(MiCtl *dst, const MiCtl &val, hipStream_t s);
 // Columns to copy out of value[n][K] in one pass: out[j][v] = value[v][col[j]].
@@ -105,6 +111,7 @@ struct MiExtract {
 // internal ids of a reordered graph); with reset, leave `reset_to` in them
 // (so the next query on a column only sets its source).
 hipError_t launch_mi_extract(int K, uint32_t *value, int32_t n, const MiExtract &x, hipStream_t s,
-                             bool reset = false, uint32_t reset_to = 0u, const int32_t *rank = nullptr);
+                             bool reset = false, uint32_t reset_to = 0u, const int32_t *rank = nullptr,
+                             bool narrow = false);
 
 }  // namespace sr

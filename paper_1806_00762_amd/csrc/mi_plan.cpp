@@ -80,7 +80,8 @@ sr_status MiPlan::add_group(sr_graph *g, int pvu, int *out_index) {
   gr.packed = g->packed ? 1 : 0;
   gr.src_mask = g->packed ? PACKED_SRC_MASK : 0xFFFFFFFFu;
   sr_status s;
-  if ((s = alloc((void **)&gr.value, 4ull * g->n * K, "instance values")) != SR_OK) return s;
+  if (narrow && algo != A_SSSP) return c->fail(SR_EINVAL, "16-bit columns serve SSSP and BFS");
+  if ((s = alloc((void **)&gr.value, (narrow ? 2ull : 4ull) * g->n * K, "instance values")) != SR_OK) return s;
   if (algo == A_PPR) {
     if ((s = alloc((void **)&gr.contrib, 4ull * g->n * K, "instance contrib")) != SR_OK) return s;
     float *iod = nullptr;
@@ -185,6 +186,17 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
   args.heavy_blocks = (int32_t)std::max<int64_t>(1, ((int64_t)total_heavy * K + BLOCK - 1) / BLOCK);
   args.grab = 1;
   args.rounds = rounds;
+  args.narrow = narrow ? 1 : 0;
+  {
+    // one weight mode for the whole plan lets the sweep kernel be compiled
+    // for it alone (fewer registers than a kernel that chooses per item)
+    int wm = -1;
+    for (auto &gr : groups) {
+      const int m = algo == A_SSSP && gr.has_w ? (gr.packed ? 1 : 2) : 0;
+      wm = wm < 0 ? m : (wm == m ? wm : 3);
+    }
+    args.wmode = wm < 0 ? 0 : wm;
+  }
   args.damping = damping;
   args.tol_l1 = tol_l1;
   args.floor_cap = 1e-6;
@@ -234,7 +246,8 @@ sr_status MiPlan::set_rounds(int r) {
 
 sr_status MiPlan::clear_values(hipStream_t s) {
   for (auto &gr : groups) {
-    hipError_t e = launch_fill_u32(gr.value, INF, (size_t)gr.n * K, s);
+    // (16-bit columns: two 0xFFFF entries per word)
+    hipError_t e = launch_fill_u32(gr.value, INF, (size_t)gr.n * K / (narrow ? 2 : 1), s);
     if (e != hipSuccess) return c->hip_fail(e, "column reset");
   }
   return SR_OK;
@@ -258,10 +271,12 @@ sr_status MiPlan::set_column(int gi, int col, int32_t source, bool unit, bool ac
     in.mass = 1.0;  // the column starts at e_source
   }
   hipError_t e = hipSuccess;
-  if (source >= 0 && clean && algo != A_PPR)
+  if (source >= 0 && clean && algo != A_PPR && narrow)
+    e = launch_mi_set_u16(gr.value, (size_t)source * K + col, 0u, s);
+  else if (source >= 0 && clean && algo != A_PPR)
     e = launch_fill_u32(gr.value + (size_t)source * K + col, 0u, 1, s);
   else if (source >= 0)
-    e = launch_mi_init_column(algo, K, gr.value, gr.contrib, gr.inv_outdeg, gr.n, col, source, s);
+    e = launch_mi_init_column(algo, K, gr.value, gr.contrib, gr.inv_outdeg, gr.n, col, source, s, narrow);
   if (e == hipSuccess) e = launch_mi_set_inst(gr.inst + col, in, s);
   if (e != hipSuccess) return c->hip_fail(e, "column init");
   return SR_OK;
@@ -583,7 +598,7 @@ extern "C" sr_status sr_batch_run(sr_ctx *c, const sr_instance *inst, int32_t co
           x.count++;
           extracted_group[j] = gi;
         }
-      he = launch_mi_extract(K, gr.value, gr.n, x, st, false, 0u, plan.group_rank[gi]);
+      he = launch_mi_extract(K, gr.value, gr.n, x, st, false, 0u, plan.group_rank[gi], plan.narrow);
       for (int32_t j = i; j < count && he == hipSuccess; ++j)
         if (where[j].group == gi)
           he = hipMemcpyAsync(dsts[j], tmp + (size_t)where[j].col * maxn, 4ull * gr.n, hipMemcpyDeviceToHost, st);

@@ -36,6 +36,7 @@ struct MiPlan {
   hipGraphExec_t exec = nullptr;
   int grid_blocks = 0, grab = 1;
   int rounds = 4;                    // vertex rounds per wavefront and item (small-degree bins)
+  bool narrow = false;               // SSSP/BFS values stored as 16 bits (set before add_group)
   bool tuned = false;
   float tuned_ms = 0.f;              // time of one sweep with the chosen schedule (when tuned)
   std::vector<PageHeader> unit_hdr;  // host copy of each unit's page header (bin counts)

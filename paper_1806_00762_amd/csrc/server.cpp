@@ -59,13 +59,44 @@ struct sr_server {
   std::thread th;
   bool stop = false;
   hipStream_t stream = nullptr, poll_stream = nullptr;
-  std::atomic<uint64_t> submitted{0}, completed{0}, sweeps{0};
+  std::atomic<uint64_t> submitted{0}, completed{0}, sweeps{0}, fallbacks{0};
   double busy_ms = 0;
   sr_status thread_error = SR_OK;
   std::string thread_msg;
 
   void progress();
+  // exact completion on the host of a retired 16-bit column that overflowed
+  sr_status complete_on_host(int gi, int32_t algo, uint32_t *result);
 };
+
+// A column stored as 16 bits holds exact values for every vertex whose
+// distance (or level) fits 16 bits and leaves the others unreached: a
+// shortest path to a vertex that fits passes only through vertices that fit
+// (weights are at least 1), and every stored value is the length of a real
+// path. Pushing relaxations on the host from every reached vertex therefore
+// reaches the exact least fixed point (the label-correcting push of the
+// sparse stage). Rare: it needs a distance of at least 65535.
+sr_status sr_server::complete_on_host(int gi, int32_t algo, uint32_t *result) {
+  sr_graph *g = graphs[gi];
+  const int32_t n = g->n;
+  std::vector<uint32_t> caller((size_t)n), val((size_t)n);
+  hipError_t e = hipMemcpyAsync(caller.data(), result, 4ull * n, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return c->hip_fail(e, "overflow completion");
+  for (int32_t v = 0; v < n; ++v) val[g->reordered ? g->rank[v] : v] = caller[v];
+  std::vector<uint32_t> front;
+  for (int32_t v = 0; v < n; ++v)
+    if (val[v] != INF) front.push_back((uint32_t)v);
+  build_out_csr(g);
+  int32_t rounds = 0;
+  sparse_push(g, algo == SR_BFS ? A_BFS : A_SSSP, val.data(), front.data(), (int64_t)front.size(), &rounds);
+  for (int32_t v = 0; v < n; ++v) caller[v] = val[g->reordered ? g->rank[v] : v];
+  e = hipMemcpyAsync(result, caller.data(), 4ull * n, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return c->hip_fail(e, "overflow completion");
+  fallbacks++;
+  return SR_OK;
+}
 
 void sr_server::progress() {
   (void)hipSetDevice(c->device);
@@ -156,9 +187,21 @@ void sr_server::progress() {
       }
       if (x.count == 0) continue;
       e = launch_mi_extract(K, plan->groups[gi].value, plan->groups[gi].n, x, stream, true, INF,
-                            plan->group_rank[gi]);
+                            plan->group_rank[gi], plan->narrow);
     }
     if (!finished.empty() && e == hipSuccess) e = hipStreamSynchronize(stream);
+    // 16-bit columns whose values did not all fit: completed exactly on the host
+    for (auto &f : finished) {
+      if (e != hipSuccess || !ih[(size_t)f.second].overflow) continue;
+      int32_t algo;
+      uint32_t *res;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        algo = q[f.first].algo;
+        res = q[f.first].result;
+      }
+      if (complete_on_host(f.second / K, algo, res) != SR_OK) e = hipErrorUnknown;
+    }
     const double t1 = now_ms();
     {
       std::lock_guard<std::mutex> lk(mu);
@@ -207,12 +250,15 @@ extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_
   // per graph: K slot columns (4 B per vertex each) plus result buffers;
   // the state budget decides how many queries each graph runs at once
   uint64_t col_bytes = 0, per_result = 0;
-  for (auto *g : s->graphs) { col_bytes += 4ull * g->n * s->K; per_result += 4ull * g->n; }
+  // slot columns hold 16-bit values (exact: a column whose values do not all
+  // fit is completed on the host when it retires)
+  for (auto *g : s->graphs) { col_bytes += 2ull * g->n * s->K; per_result += 4ull * g->n; }
   if (state_budget && col_bytes + per_result > state_budget)
     return fail(c->fail(SR_EBUDGET, "state budget cannot hold the slot columns and one result per graph"));
   uint64_t left = state_budget ? state_budget - col_bytes : ~0ull;
   int R = (int)std::min<uint64_t>(s->K, left / std::max<uint64_t>(per_result, 1));
   s->plan = new MiPlan(c, A_SSSP, s->K);
+  s->plan->narrow = true;
   for (auto *g : s->graphs) {
     int gi;
     if ((st = s->plan->add_group(g, P_STRONG, &gi)) != SR_OK) return fail(st);
@@ -327,6 +373,7 @@ extern "C" sr_status sr_server_stats_get(sr_server *s, sr_server_stats *o) {
   std::lock_guard<std::mutex> lk(s->mu);
   for (size_t i = 0; i < s->usable.size() && i < 8; ++i) o->slots_per_graph[i] = s->usable[i];
   o->busy_ms = s->busy_ms;
+  o->narrow_fallbacks = s->fallbacks;
   return SR_OK;
 }
 

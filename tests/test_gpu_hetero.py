@@ -70,13 +70,17 @@ def run(ctx, g, algo, sched, sym=False, source=0, **kw):
 @pytest.mark.parametrize("gname", list(GRAPHS))
 @pytest.mark.parametrize("sched", list(SCHED))
 @pytest.mark.parametrize("switch", [0, 64, 1 << 30])
-def test_hetero_exact(sr, ctx, gname, sched, switch):
+@pytest.mark.parametrize("det", [False, True])
+def test_hetero_exact(sr, ctx, gname, sched, switch, det):
+    """det: the deterministic window schedule (the device keeps a sweep
+    queued ahead of the host) under the sparse stage's pass-end handovers."""
     g = graph(gname)
     src = int(np.argmax(np.diff(g.offsets)))
     cases = (("sssp", oracle.sssp(g, src), False), ("bfs", oracle.bfs(g, src), False), ("cc", oracle.cc(g), True))
     for algo, ref, sym in cases:
         for pvu in ("strong", "off", "weak"):
-            got, st = run(ctx, g, algo, sched, sym=sym, source=src, pvu=pvu, sparse_switch=switch)
+            got, st = run(ctx, g, algo, sched, sym=sym, source=src, pvu=pvu, sparse_switch=switch,
+                          deterministic=det)
             say(f"case hetero {gname} {sched} switch={switch} {algo} {pvu}: passes {st['passes']} "
                 f"sparse {st['sparse_stage']} frontier {st['sparse_frontier']} rounds {st['sparse_rounds']}")
             assert st["converged"] == 1

@@ -98,3 +98,41 @@ def test_server_rejects_bad_requests(sr):
     srv.close()
     G.close()
     ctx.close()
+
+
+def test_server_wide_distances_completed_exactly(sr):
+    """Served slots hold 16-bit values. On a weighted path (weight 250 per
+    hop) the vertices past hop 262 lie beyond distance 65535; queries from
+    its start overflow their slot and are completed on the host when they
+    retire, a query from the middle does not. Every result stays bit-exact
+    (BFS levels fit), and the stats count the completions; queries on a
+    small graph in the same server do not need it."""
+    n = 400
+    src = list(range(n - 1)) + [0]
+    dst = list(range(1, n)) + [n - 1]
+    w = [250] * (n - 1) + [255]
+    path = graphgen.from_edges(n, src, dst, w)
+    small = graphgen.rmat(10, 8, seed=91, weights=(1, 255, 92))
+    ctx = sr.Context(0, 0)
+    Gs = [ctx.load(path), ctx.load(small, reorder=True)]
+    srv = sr.Server(ctx, Gs, slots=8)
+    reqs = [(0, "sssp", 0), (0, "sssp", 3), (1, "sssp", 0), (1, "bfs", 1), (0, "bfs", 0), (0, "sssp", 250)]
+    tickets, outs = [], {}
+    for gi, algo, s in reqs:
+        t = srv.submit(gi, algo, s)
+        tickets.append(t)
+        outs[t] = np.empty(Gs[gi].n, dtype=np.uint32)
+    wait_all(srv, tickets, outs)
+    st = srv.stats()
+    say(f"  wide distances: stats {st}")
+    graphs = [path, small]
+    for t, (gi, algo, s) in zip(tickets, reqs):
+        ref = oracle.sssp(graphs[gi], s) if algo == "sssp" else oracle.bfs(graphs[gi], s)
+        assert np.array_equal(outs[t], ref), (gi, algo, s)
+    # sources 0 and 3 reach distances beyond 65535 along the path
+    assert int(oracle.sssp(path, 0)[n - 2]) > 65535
+    assert st["narrow_fallbacks"] >= 2
+    srv.close()
+    for G in Gs:
+        G.close()
+    ctx.close()

@@ -60,13 +60,15 @@ def test_skip_lattice_exact_and_saves_copies(sr, ctx, layout):
                 assert st["h2d_bytes"] < base["h2d_bytes"]
 
 
-def test_skip_rmat_exact(sr, ctx):
+@pytest.mark.parametrize("det", [False, True])
+def test_skip_rmat_exact(sr, ctx, det):
     g = graphgen.rmat(14, 16, seed=14, weights=(1, 255, 5))
     src = int(np.argmax(np.diff(g.offsets)))
     for algo, ref, sym in (("sssp", oracle.sssp(g, src), False), ("bfs", oracle.bfs(g, src), False),
                            ("cc", oracle.cc(g), True)):
-        got, st = solve(ctx, g, algo, 7, 4, sym=sym, source=src, pvu="strong", copy_depth=2, skip_clean=True)
-        say(f"case skip rmat14 {algo}: passes {st['passes']} skipped {st['pages_skipped']}")
+        got, st = solve(ctx, g, algo, 7, 4, sym=sym, source=src, pvu="strong", copy_depth=2, skip_clean=True,
+                        deterministic=det)
+        say(f"case skip rmat14 det={det} {algo}: passes {st['passes']} skipped {st['pages_skipped']}")
         assert np.array_equal(got, ref)
 
 
