@@ -136,15 +136,29 @@ struct MiRed {
   __device__ static inline T edge(const MiGroup &g, int32_t u, uint32_t w, int k, const Lane &ln) {
     return cand(raw(g, u, k), w, ln);
   }
-  // the gathered value of in-neighbour u as stored (the load alone) ...
+  // the gathered value of in-neighbour u as stored (the load alone); the
+  // row offset is 32-bit (plans keep every [n][K] array below 4 GiB), so
+  // the load takes the group's base from scalar registers ...
   __device__ static inline uint32_t raw(const MiGroup &g, int32_t u, int k) {
-    if constexpr (mi_pr<ALGO>()) return __float_as_uint(ldg(g.contrib + (size_t)u * K + k));
-    else return mi_ld_raw<ALGO>(g, (size_t)u * K + k);
+    const uint32_t i = (uint32_t)u * (uint32_t)K + (uint32_t)k;
+    if constexpr (mi_pr<ALGO>()) {
+      return __float_as_uint(ldg(reinterpret_cast<const float *>(reinterpret_cast<const char *>(g.contrib) + 4u * i)));
+    } else if constexpr (mi_narrow<ALGO>()) {
+      return ldg(reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(g.value) + 2u * i));
+    } else {
+      return ldg(reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(g.value) + 4u * i));
+    }
   }
   // ... and its contribution through an edge of weight w
   __device__ static inline T cand(uint32_t xs, uint32_t w, const Lane &ln) {
     if constexpr (mi_pr<ALGO>()) {
       return __uint_as_float(xs);
+    } else if constexpr (mi_narrow<ALGO>()) {
+      // a 16-bit value plus a weight: a sum that wraps 32 bits saturates
+      // just below INF, so the epilogue still flags the candidate as not
+      // fitting 16 bits (INF would read as no candidate)
+      const uint32_t c = xs + (ln.unit ? 1u : w);
+      return xs == INF16 ? INF : (c < xs ? INF - 1u : c);
     } else {
       const uint32_t x = mi_cvt<ALGO>(xs);
       if (x == INF) return INF;
@@ -292,30 +306,52 @@ __device__ void mi_small(const MiGroup &g, const char *base, const PageHeader *h
     att[r] = mi_attempt<ALGO, K>(g, vb + vl[r], k, ln, old[r]) && ok;
     if (!ok) vl[r] = -1;
   }
+  // The rounds' edges in lockstep: each step loads EB edge words of every
+  // round that still has edges (a finished or non-attempting round rereads
+  // its vertex's first edge, masked), then all their value gathers, so
+  // ROUNDS * EB gathers are in flight together instead of one round's.
+  constexpr int EB = ROUNDS >= 8 ? 1 : (ROUNDS >= 4 ? 2 : 4);
+  int32_t ec[ROUNDS];
+  T x[ROUNDS];
 #pragma unroll
   for (int r = 0; r < ROUNDS; ++r) {
-    T x = R::identity();
-    if (att[r]) {
-      // batches of 4 edges per lane: word loads, then gathers, in flight together
-      for (int e0 = beg[r] + ein; e0 < end[r]; e0 += 4 * GE) {
-        int32_t ei[4];
-        uint32_t q[4];
+    x[r] = R::identity();
+    ec[r] = beg[r] + ein;
+  }
+  for (;;) {
+    bool more = false;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          ei[j] = e0 + j * GE < end[r] ? e0 + j * GE : e0;
-          q[j] = ldg(src + ei[j]);
-        }
+    for (int r = 0; r < ROUNDS; ++r) more |= att[r] && ec[r] < end[r];
+    if (!more) break;
+    int32_t ei[ROUNDS][EB];
+    uint32_t q[ROUNDS][EB], xr[ROUNDS][EB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const T y = R::edge(g, (int32_t)(q[j] & g.src_mask), mi_w<WM>(q[j], wt, ei[j]), k, ln);
-          if (e0 + j * GE < end[r]) x = R::combine(x, y);
-        }
+    for (int r = 0; r < ROUNDS; ++r)
+#pragma unroll
+      for (int j = 0; j < EB; ++j) {
+        const int e = ec[r] + j * GE;
+        ei[r][j] = att[r] && e < end[r] ? e : beg[r];
+        q[r][j] = ldg(src + ei[r][j]);
       }
-    }
 #pragma unroll
-    for (int m = K; m < K * GE; m <<= 1) x = R::combine(x, shfl_xor(x, m));
+    for (int r = 0; r < ROUNDS; ++r)
+#pragma unroll
+      for (int j = 0; j < EB; ++j) xr[r][j] = R::raw(g, (int32_t)(q[r][j] & g.src_mask), k);
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+#pragma unroll
+      for (int j = 0; j < EB; ++j)
+        if (att[r] && ec[r] + j * GE < end[r])
+          x[r] = R::combine(x[r], R::cand(xr[r][j], mi_w<WM>(q[r][j], wt, ei[r][j]), ln));
+      ec[r] += EB * GE;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+#pragma unroll
+    for (int m = K; m < K * GE; m <<= 1) x[r] = R::combine(x[r], shfl_xor(x[r], m));
     if (att[r] && ein == 0)
-      mi_epilogue<ALGO, K>(g, vb + vl[r], k, ln, old[r], x, (uint32_t)(end[r] - beg[r]), damping, acc);
+      mi_epilogue<ALGO, K>(g, vb + vl[r], k, ln, old[r], x[r], (uint32_t)(end[r] - beg[r]), damping, acc);
   }
 }
 

@@ -81,6 +81,9 @@ sr_status MiPlan::add_group(sr_graph *g, int pvu, int *out_index) {
   gr.src_mask = g->packed ? PACKED_SRC_MASK : 0xFFFFFFFFu;
   sr_status s;
   if (narrow && algo != A_SSSP) return c->fail(SR_EINVAL, "16-bit columns serve SSSP and BFS");
+  // the sweep addresses a group's [n][K] arrays with 32-bit byte offsets
+  if ((uint64_t)g->n * (uint64_t)K * 4ull >= (1ull << 32))
+    return c->fail(SR_EINVAL, "graph too large for instance groups of this width (n * K * 4 bytes must stay below 4 GiB)");
   if ((s = alloc((void **)&gr.value, (narrow ? 2ull : 4ull) * g->n * K, "instance values")) != SR_OK) return s;
   if (algo == A_PPR) {
     if ((s = alloc((void **)&gr.contrib, 4ull * g->n * K, "instance contrib")) != SR_OK) return s;
