@@ -737,6 +737,7 @@ def bench_served(args):
     srv = sr.Server(ctx, Gs, state_budget_bytes=0, slots=args.serve_slots)
     check = set(range(0, nreq, max(1, nreq // 12)))
     lat, elapsed, outs = _serve_stream(srv, graphs, reqs, arr, args.served_timeout, check)
+    st1 = srv.stats()
     ok = 0
     for i in check:
         gi, algo, s = reqs[i]
@@ -777,6 +778,17 @@ def bench_served(args):
                           "p99_ms": round(float(np.percentile(lat2, 99)), 2) if lat2.size else None},
             "plain_solves_per_s": round(1.0 / tp, 1), "plain_sample": nplain,
             "sweeps": st["sweeps"], "slots_per_graph": st["slots_per_graph"],
+            # the sweep replays of the offered-rate stream: algorithmic bytes
+            # (shared edge words, offsets and bins per live graph and sweep,
+            # one 16-bit value per scanned in-edge and query) over their
+            # HIP-event time
+            "sweep": {"replays": st1["sweeps"], "ms_per_replay": round(st1["kernel_ms"] / max(st1["sweeps"], 1), 3),
+                      "device_busy_frac": round(st1["kernel_ms"] * 1e-3 / elapsed, 3),
+                      "algo_GBps": round(st1["algo_bytes"] / (st1["kernel_ms"] * 1e-3) / 1e9, 1)
+                      if st1["kernel_ms"] else None,
+                      "frac_hbm_peak": round(st1["algo_bytes"] / (st1["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                      if st1["kernel_ms"] else None},
+            "narrow_fallbacks": st["narrow_fallbacks"],
             "checked_vs_oracle": f"{ok}/{len(check)} bit-exact"}
 
 
@@ -816,7 +828,7 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=32)
     ap.add_argument("--requests", type=int, default=20000)
     ap.add_argument("--rate", type=float, default=2000.0)
-    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy kernel of known size (for HBM counter scaling)")
     ap.add_argument("--served-timeout", type=float, default=90.0)

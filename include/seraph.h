@@ -455,7 +455,7 @@ sr_status sr_batch_run(sr_ctx *ctx, const sr_instance *instances, int32_t count,
 
 /* A continuous-batching query server (beyond the paper): SSSP and BFS
  * source queries on resident graphs. Each graph owns max_slots_per_graph
- * (8, 16 or 32) query slots whose state (a 16-bit distance or level per
+ * (8, 16, 32 or 64) query slots whose state (a 16-bit distance or level per
  * vertex per slot, plus one 4 B-per-vertex result buffer per running query)
  * is allocated up front if state_budget_bytes allows, else as many slots as
  * fit. A progress thread admits queued queries into free slots as they
@@ -463,8 +463,9 @@ sr_status sr_batch_run(sr_ctx *ctx, const sr_instance *instances, int32_t count,
  * per graph, all its active slots together), retires converged slots (a
  * sweep without change under the Table I strong conditions), copies their
  * values to host and records latency = completion - submission. Results
- * are exact u32 values: a slot whose distances do not all fit 16 bits
- * (some vertex at distance 65535 or more) is completed on the host when it
+ * are exact u32 values: a slot whose distances do not all fit (some vertex
+ * at distance 32767 or more; the slots store values below 2^15 - 1 so that
+ * a value plus an edge weight never wraps) is completed on the host when it
  * retires (label-correcting push from every reached vertex), which the
  * stats count. */
 sr_status sr_server_create(sr_ctx *ctx, sr_graph *const *graphs, int32_t ngraphs,
@@ -486,6 +487,11 @@ typedef struct {
   double busy_ms;        /* progress-thread time spent with work in flight */
   uint64_t narrow_fallbacks; /* retired queries whose 16-bit slot column overflowed and were completed
                                 exactly on the host */
+  double kernel_ms;      /* device time of the sweep replays (multi-source sweep, heavy-vertex and
+                            close kernels; HIP events) */
+  uint64_t algo_bytes;   /* algorithmic bytes of those sweeps: per sweep and live graph, its edge words
+                            (and separate weights), offsets, bin lists and own values (4m (+4m) + 12n);
+                            per retired query, 2 bytes (one 16-bit value) per in-edge its column scanned */
 } sr_server_stats;
 sr_status sr_server_stats_get(sr_server *srv, sr_server_stats *out);
 /* Stop the progress thread after finishing admitted queries, free the

@@ -139,7 +139,8 @@ class sr_batch_stats(ctypes.Structure):
 class sr_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("sweeps", ctypes.c_uint64),
                 ("slots_per_graph", ctypes.c_int32 * 8), ("busy_ms", ctypes.c_double),
-                ("narrow_fallbacks", ctypes.c_uint64)]
+                ("narrow_fallbacks", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
+                ("algo_bytes", ctypes.c_uint64)]
 
 
 EXTRA_SIGNATURES: dict = {

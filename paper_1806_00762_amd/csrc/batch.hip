@@ -53,13 +53,14 @@ template <int ALGO>
 constexpr bool mi_pr() { return ALGO == A_PPR; }
 
 // SSSP/BFS columns whose values are stored as 16 bits ([n][K] u16, 0xFFFF =
-// unreached): rows half as wide. A candidate that does not fit 16 bits is
+// unreached): rows half as wide. A candidate of CAP16 or more is
 // not stored (the vertex keeps its old value) and sets the column's overflow
 // flag; the caller then completes that column exactly on the host.
 constexpr int A_MIN16 = 100;
 template <int ALGO>
 constexpr bool mi_narrow() { return ALGO == A_MIN16; }
 constexpr uint32_t INF16 = 0xFFFFu;
+constexpr uint32_t CAP16 = 0x7FFFu;  // stored 16-bit values are below this
 
 // Loads through pointers the compiler cannot place (they come from the
 // group and unit tables): declared global, so they compile to global loads
@@ -143,8 +144,6 @@ struct MiRed {
     const uint32_t i = (uint32_t)u * (uint32_t)K + (uint32_t)k;
     if constexpr (mi_pr<ALGO>()) {
       return __float_as_uint(ldg(reinterpret_cast<const float *>(reinterpret_cast<const char *>(g.contrib) + 4u * i)));
-    } else if constexpr (mi_narrow<ALGO>()) {
-      return ldg(reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(g.value) + 2u * i));
     } else {
       return ldg(reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(g.value) + 4u * i));
     }
@@ -153,12 +152,6 @@ struct MiRed {
   __device__ static inline T cand(uint32_t xs, uint32_t w, const Lane &ln) {
     if constexpr (mi_pr<ALGO>()) {
       return __uint_as_float(xs);
-    } else if constexpr (mi_narrow<ALGO>()) {
-      // a 16-bit value plus a weight: a sum that wraps 32 bits saturates
-      // just below INF, so the epilogue still flags the candidate as not
-      // fitting 16 bits (INF would read as no candidate)
-      const uint32_t c = xs + (ln.unit ? 1u : w);
-      return xs == INF16 ? INF : (c < xs ? INF - 1u : c);
     } else {
       const uint32_t x = mi_cvt<ALGO>(xs);
       if (x == INF) return INF;
@@ -240,7 +233,7 @@ __device__ inline void mi_epilogue(const MiGroup &g, int32_t v, int k, const Lan
   } else {
     uint32_t nv = min(old, red);
     if (nv < old) {
-      if (mi_narrow<ALGO>() && nv >= INF16) {
+      if (mi_narrow<ALGO>() && nv >= CAP16) {
         // not representable: the vertex stays unreached in this column
         atomicOr(&g.inst[k].overflow, 1u);
       } else {
@@ -478,6 +471,331 @@ __device__ void mi_zero(const MiGroup &g, const char *base, const PageHeader *h,
   }
 }
 
+// ---------------------------------------------------------------------------
+// 16-bit SSSP/BFS columns, four per lane. A lane holds columns 4c..4c+3 of a
+// row as two u16 pairs (one 8-byte load) and relaxes them with packed 16-bit
+// saturating adds and mins, so the index, address and weight work of an
+// in-edge is shared by four columns and a wavefront covers 64 / (K/4) edges
+// per step. Values stored are below CAP16; 0xFFFF is unreached and stays so
+// under the saturating add. Weights are clamped to CAP16 (a candidate through
+// a heavier edge is at least CAP16 either way), so a reached value plus a
+// weight never saturates and every candidate of CAP16 or more is seen as
+// such: it is not stored and flags the column's overflow. Row n of every
+// group is a sentinel of unreached values: an edge lane past its range
+// gathers it and needs no mask.
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t pk_addsat(uint32_t x, uint32_t y) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_add_sat(__builtin_bit_cast(u16x2, x),
+                                                                     __builtin_bit_cast(u16x2, y)));
+}
+__device__ inline uint32_t pk_min(uint32_t x, uint32_t y) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, x),
+                                                                 __builtin_bit_cast(u16x2, y)));
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const u32x2 g_u32x2;
+// columns 4c..4c+3 of row u (byte offset below 4 GiB)
+template <int K>
+__device__ inline uint2 mp_row(const MiGroup &g, uint32_t u, int c) {
+  const u32x2 x = *(g_u32x2 *)(reinterpret_cast<const char *>(g.value) + (u * (uint32_t)(2 * K) + 8u * (uint32_t)c));
+  return make_uint2(x.x, x.y);
+}
+__device__ inline uint32_t half16(uint2 x, int j) {
+  const uint32_t w = j < 2 ? x.x : x.y;
+  return (j & 1) ? w >> 16 : w & 0xFFFFu;
+}
+
+// Per-lane state of four instance columns.
+struct Lane4 {
+  uint32_t thr[4];      // a column attempts a vertex whose value exceeds thr (0xFFFF: inactive)
+  uint32_t wm01, wa01;  // pair weight of columns 0, 1: w * wm + wa (unit columns: 1)
+  uint32_t wm23, wa23;
+};
+
+// (ungated: every active column attempts every vertex but its source, as in
+// the autotuner's timing sweeps, whose cost must not depend on the state the
+// previous candidates left)
+template <int K>
+__device__ inline Lane4 lane4_of(const MiGroup &g, int c, bool ungated) {
+  Lane4 l;
+  uint32_t unit[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const MiInst &in = g.inst[4 * c + j];
+    unit[j] = in.unit;
+    // Table I: under strong prediction a value at or below the threshold is
+    // final; otherwise every vertex is attempted (the source, at 0, cannot
+    // improve and is left out)
+    l.thr[j] = !in.active ? 0xFFFFu : (g.pvu == P_STRONG && !ungated ? min(in.threshold, 0xFFFEu) : 0u);
+  }
+  l.wm01 = (unit[0] ? 0u : 1u) | (unit[1] ? 0u : 0x10000u);
+  l.wa01 = (unit[0] ? 1u : 0u) | (unit[1] ? 0x10000u : 0u);
+  l.wm23 = (unit[2] ? 0u : 1u) | (unit[3] ? 0u : 0x10000u);
+  l.wa23 = (unit[2] ? 1u : 0u) | (unit[3] ? 0x10000u : 0u);
+  return l;
+}
+
+__device__ inline uint32_t mp_attempt(const Lane4 &ln, uint2 old) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) m |= (half16(old, j) > ln.thr[j] ? 1u : 0u) << j;
+  return m;
+}
+
+// weight of an in-edge as the clamped value the packed add takes
+template <int WM>
+__device__ inline uint32_t mp_w(uint32_t q, const uint32_t *wt, int32_t e) {
+  if constexpr (WM == 1) return q >> 24;
+  else if constexpr (WM == 2) return min(ldg(wt + e), CAP16);
+  else return 1u;
+}
+
+// relax the four columns of one gathered row through an edge of weight w
+__device__ inline void mp_relax(uint2 row, uint32_t w, const Lane4 &ln, uint32_t &x01, uint32_t &x23) {
+  x01 = pk_min(x01, pk_addsat(row.x, __umul24(w, ln.wm01) + ln.wa01));
+  x23 = pk_min(x23, pk_addsat(row.y, __umul24(w, ln.wm23) + ln.wa23));
+}
+
+struct Acc4 {
+  uint32_t changed[4] = {0, 0, 0, 0};
+  uint32_t min_changed[4] = {INF, INF, INF, INF};
+  uint32_t edges[4] = {0, 0, 0, 0};
+};
+
+template <int K>
+__device__ inline void mp_epilogue(const MiGroup &g, int32_t v, int c, uint32_t attm, uint2 old, uint32_t x01,
+                                   uint32_t x23, uint32_t deg, Acc4 &acc) {
+  const uint2 red = make_uint2(x01, x23);
+  uint32_t nw[4];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t o = half16(old, j), r = half16(red, j);
+    nw[j] = o;
+    if (!((attm >> j) & 1u)) continue;
+    acc.edges[j] += deg;
+    if (r < o) {
+      if (r >= CAP16) {
+        atomicOr(&g.inst[4 * c + j].overflow, 1u);
+      } else {
+        nw[j] = r;
+        acc.changed[j]++;
+        acc.min_changed[j] = min(acc.min_changed[j], r);
+        any = true;
+      }
+    }
+  }
+  if (any)
+    *reinterpret_cast<uint2 *>(reinterpret_cast<char *>(g.value) + ((uint32_t)v * (uint32_t)(2 * K) + 8u * (uint32_t)c)) =
+        make_uint2(nw[0] | (nw[1] << 16), nw[2] | (nw[3] << 16));
+}
+
+// lanes of the same column quad reduce over the edge lanes; lanes 0..K/4-1
+// add the totals of their four columns to the block's LDS counters
+template <int K>
+__device__ inline void mp_flush(MiLds *lds, int group, Acc4 &acc) {
+  constexpr int KL = K / 4;
+  const int lane = threadIdx.x % 64;
+#pragma unroll
+  for (int m = KL; m < 64; m <<= 1)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc.changed[j] += shfl_xor(acc.changed[j], m);
+      acc.min_changed[j] = min(acc.min_changed[j], shfl_xor(acc.min_changed[j], m));
+      acc.edges[j] += shfl_xor(acc.edges[j], m);
+    }
+  if (lane < KL) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      MiLds &e = lds[group * K + 4 * lane + j];
+      if (acc.changed[j]) atomicAdd(&e.changed, acc.changed[j]);
+      if (acc.min_changed[j] != INF) atomicMin(&e.min_changed, acc.min_changed[j]);
+      if (acc.edges[j]) atomicAdd(&e.edges, acc.edges[j]);
+    }
+  }
+  acc = Acc4();
+}
+
+// bins 0..5: GE edge lanes per vertex, ROUNDS rounds of EL/GE vertices per
+// wavefront, the rounds' edges in lockstep (as mi_small)
+template <int K, int GE, int ROUNDS, int WM>
+__device__ void mp_small(const MiGroup &g, const char *base, const PageHeader *h, int bin, int item,
+                         const Lane4 &ln, Acc4 &acc) {
+  constexpr int KL = K / 4, EL = 64 / KL, VPW = EL / GE;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int c = lane % KL, el = lane / KL, vs = el / GE, ein = el % GE;
+  const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
+  const int32_t *bins = reinterpret_cast<const int32_t *>(base + h->off_bins) + h->bin_start[bin];
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(base + h->off_src);
+  const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
+  const int cnt = h->bin_count[bin];
+  const int vb = h->v_begin;
+  const uint32_t sentinel = (uint32_t)g.n;
+  int32_t vl[ROUNDS], beg[ROUNDS], end[ROUNDS];
+  uint2 old[ROUNDS];
+  uint32_t attm[ROUNDS];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int idx = ((item * WAVES + wave) * ROUNDS + r) * VPW + vs;
+    const bool ok = idx < cnt;
+    vl[r] = cnt > 0 ? ldg(bins + (ok ? idx : 0)) : 0;  // an empty bin rereads the page's vertex 0
+    beg[r] = ldg(off + vl[r]);
+    end[r] = ldg(off + vl[r] + 1);
+    old[r] = mp_row<K>(g, (uint32_t)(vb + vl[r]), c);
+    attm[r] = ok ? mp_attempt(ln, old[r]) : 0u;
+  }
+  constexpr int EB = ROUNDS >= 8 ? 1 : (ROUNDS >= 4 ? 2 : 4);
+  int32_t ec[ROUNDS];
+  uint32_t x01[ROUNDS], x23[ROUNDS];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    x01[r] = 0xFFFFFFFFu;
+    x23[r] = 0xFFFFFFFFu;
+    ec[r] = beg[r] + ein;
+  }
+  for (;;) {
+    bool more = false;
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) more |= attm[r] != 0u && ec[r] < end[r];
+    if (!more) break;
+    int32_t ei[ROUNDS][EB];
+    uint32_t q[ROUNDS][EB];
+    uint2 row[ROUNDS][EB];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r)
+#pragma unroll
+      for (int j = 0; j < EB; ++j) {
+        const int e = ec[r] + j * GE;
+        ei[r][j] = attm[r] != 0u && e < end[r] ? e : -1;
+        q[r][j] = ldg(src + (ei[r][j] >= 0 ? ei[r][j] : beg[r]));
+      }
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r)
+#pragma unroll
+      for (int j = 0; j < EB; ++j)
+        row[r][j] = mp_row<K>(g, ei[r][j] >= 0 ? (q[r][j] & g.src_mask) : sentinel, c);
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+#pragma unroll
+      for (int j = 0; j < EB; ++j)
+        mp_relax(row[r][j], mp_w<WM>(q[r][j], wt, ei[r][j] >= 0 ? ei[r][j] : beg[r]), ln, x01[r], x23[r]);
+      ec[r] += EB * GE;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+#pragma unroll
+    for (int m = KL; m < KL * GE; m <<= 1) {
+      x01[r] = pk_min(x01[r], shfl_xor(x01[r], m));
+      x23[r] = pk_min(x23[r], shfl_xor(x23[r], m));
+    }
+    if (attm[r] != 0u && ein == 0)
+      mp_epilogue<K>(g, vb + vl[r], c, attm[r], old[r], x01[r], x23[r], (uint32_t)(end[r] - beg[r]), acc);
+  }
+}
+
+// edge loop of bins 6 and 7 (as mi_edges): EL edge lanes, 8 edges in flight
+// per lane, the next batch's words loaded while this batch's rows are gathered
+template <int K, int WM>
+__device__ inline void mp_edges(const MiGroup &g, const uint32_t *src, const uint32_t *wt, int32_t e0, int32_t e1,
+                                int c, int el, bool live, const Lane4 &ln, uint32_t &x01, uint32_t &x23) {
+  constexpr int KL = K / 4, EL = 64 / KL, B = 8;
+  const uint32_t sentinel = (uint32_t)g.n;
+  x01 = 0xFFFFFFFFu;
+  x23 = 0xFFFFFFFFu;
+  int e = e0 + el;
+  const int eb = e < e1 ? e : e0;
+  int32_t ei[B];
+  uint32_t q[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    ei[j] = e + j * EL < e1 ? e + j * EL : eb;
+    q[j] = ldg(src + ei[j]);
+  }
+  for (; e < e1; e += B * EL) {
+    const int en = e + B * EL;
+    int32_t ein[B];
+    uint32_t qn[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      ein[j] = en + j * EL < e1 ? en + j * EL : e;
+      qn[j] = ldg(src + ein[j]);
+    }
+    uint2 row[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) row[j] = mp_row<K>(g, live && e + j * EL < e1 ? (q[j] & g.src_mask) : sentinel, c);
+#pragma unroll
+    for (int j = 0; j < B; ++j) mp_relax(row[j], mp_w<WM>(q[j], wt, ei[j]), ln, x01, x23);
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      ei[j] = ein[j];
+      q[j] = qn[j];
+    }
+  }
+#pragma unroll
+  for (int m = KL; m < 64; m <<= 1) {
+    x01 = pk_min(x01, shfl_xor(x01, m));
+    x23 = pk_min(x23, shfl_xor(x23, m));
+  }
+}
+
+// bin 6: one wavefront per vertex
+template <int K, int WM>
+__device__ void mp_wave(const MiGroup &g, const char *base, const PageHeader *h, int item, const Lane4 &ln,
+                        Acc4 &acc) {
+  constexpr int KL = K / 4;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, c = lane % KL, el = lane / KL;
+  const int idx = item * WAVES + wave;
+  if (idx >= h->bin_count[BIN_WAVE]) return;
+  const int32_t *off = reinterpret_cast<const int32_t *>(base + h->off_offsets);
+  const int32_t vl = ldg(reinterpret_cast<const int32_t *>(base + h->off_bins) + h->bin_start[BIN_WAVE] + idx);
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(base + h->off_src);
+  const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
+  const int32_t v = h->v_begin + vl;
+  const uint2 old = mp_row<K>(g, (uint32_t)v, c);
+  const uint32_t attm = mp_attempt(ln, old);
+  if (!__any(attm != 0u)) return;
+  const int32_t b0 = ldg(off + vl), b1 = ldg(off + vl + 1);
+  uint32_t x01, x23;
+  mp_edges<K, WM>(g, src, wt, b0, b1, c, el, attm != 0u, ln, x01, x23);
+  if (attm != 0u && el == 0) mp_epilogue<K>(g, v, c, attm, old, x01, x23, (uint32_t)(b1 - b0), acc);
+}
+
+// bin 7: one wavefront per sub-chunk; each column folds its partial into the
+// heavy vertex's accumulator (the heavy-vertex kernel runs the epilogue)
+template <int K, int WM>
+__device__ void mp_chunk(const MiGroup &g, const MiUnit &u, const char *base, const PageHeader *h, int item,
+                         const Lane4 &ln) {
+  constexpr int KL = K / 4;
+  constexpr int S = mi_subchunks(KL);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, c = lane % KL, el = lane / KL;
+  const int sidx = item * WAVES + wave;
+  const int idx = sidx / S, sub = sidx % S;
+  if (idx >= h->bin_count[BIN_CHUNK]) return;
+  const Chunk ch = reinterpret_cast<const Chunk *>(base + h->off_chunks)[idx];
+  const int32_t len = (ch.e_end - ch.e_begin + S - 1) / S;
+  const int32_t sb = ch.e_begin + sub * len, se = min(ch.e_end, sb + len);
+  if (sb >= se) return;
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(base + h->off_src);
+  const uint32_t *wt = reinterpret_cast<const uint32_t *>(base + h->off_w);
+  const int32_t v = h->v_begin + ch.vl;
+  const uint2 old = mp_row<K>(g, (uint32_t)v, c);
+  const uint32_t attm = mp_attempt(ln, old);
+  if (!__any(attm != 0u)) return;
+  uint32_t x01, x23;
+  mp_edges<K, WM>(g, src, wt, sb, se, c, el, attm != 0u, ln, x01, x23);
+  if (el == 0 && attm != 0u) {
+    const uint2 red = make_uint2(x01, x23);
+    unsigned long long *slot = &u.acc[(size_t)((uint32_t)ch.first_count & 0xFFFFFu) * K + 4 * c];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t r = half16(red, j);
+      if (((attm >> j) & 1u) && r != INF16) atomicMin(reinterpret_cast<uint32_t *>(slot + j), r);
+    }
+  }
+}
+
 // WMK: the weight mode of every group of the plan (0, 1, 2), or 3 when the
 // groups differ (then chosen per work item; that kernel needs the registers
 // of the widest mode)
@@ -496,7 +814,8 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
     const int32_t base = s_base;
     if (base >= a.total_items) break;
     const int32_t end = min(base + a.grab, a.total_items);
-    for (int32_t it = base; it < end; ++it) {
+    for (int32_t qi = base; qi < end; ++qi) {
+      const int32_t it = a.descending ? a.total_items - 1 - qi : qi;
       int lo = 0, hi = a.nunits;  // unit_prefix[lo] <= it < unit_prefix[hi]
       while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
@@ -511,8 +830,6 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
       const int item = local - u.blk_prefix[bin];
       const char *bp = u.page;
       const PageHeader *h = reinterpret_cast<const PageHeader *>(bp);
-      const Lane ln = lane_of(g.inst[k]);
-      MiAcc acc;
       // the weight mode: the plan's, or the group's when the plan mixes them
       const int wm = WMK < 3 ? WMK : mi_wmode<ALGO>(g);
 #define MI_WM(CALL)                                                                 \
@@ -522,6 +839,26 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
     else if (wm == 2) { constexpr int WM = mi_pr<ALGO>() ? 0 : 2; CALL; }           \
     else { constexpr int WM = 0; CALL; }                                            \
   } while (0)
+      if constexpr (mi_narrow<ALGO>()) {
+        constexpr int EL4 = 256 / K;  // edge lanes with four columns per lane
+        const Lane4 ln = lane4_of<K>(g, lane % (K / 4), a.tuning != 0);
+        Acc4 acc;
+        switch (bin) {
+          case 0: MI_WM((mp_small<K, 1, ROUNDS, WM>(g, bp, h, 0, item, ln, acc))); break;
+          case 1: MI_WM((mp_small<K, (2 < EL4 ? 2 : EL4), ROUNDS, WM>(g, bp, h, 1, item, ln, acc))); break;
+          case 2: MI_WM((mp_small<K, (4 < EL4 ? 4 : EL4), ROUNDS, WM>(g, bp, h, 2, item, ln, acc))); break;
+          case 3: MI_WM((mp_small<K, (8 < EL4 ? 8 : EL4), ROUNDS, WM>(g, bp, h, 3, item, ln, acc))); break;
+          case 4: MI_WM((mp_small<K, (16 < EL4 ? 16 : EL4), ROUNDS, WM>(g, bp, h, 4, item, ln, acc))); break;
+          case 5: MI_WM((mp_small<K, (32 < EL4 ? 32 : EL4), ROUNDS, WM>(g, bp, h, 5, item, ln, acc))); break;
+          case BIN_WAVE: MI_WM((mp_wave<K, WM>(g, bp, h, item, ln, acc))); break;
+          case BIN_CHUNK: MI_WM((mp_chunk<K, WM>(g, u, bp, h, item, ln))); break;
+          default: break;  // no zero in-degree bin outside PageRank
+        }
+        mp_flush<K>(lds, u.group, acc);
+        continue;
+      } else {
+      const Lane ln = lane_of(g.inst[k]);
+      MiAcc acc;
       switch (bin) {
         case 0: MI_WM((mi_small<ALGO, K, 1, ROUNDS, WM>(g, bp, h, 0, item, ln, a.damping, acc))); break;
         case 1: MI_WM((mi_small<ALGO, K, (2 < 64 / K ? 2 : 64 / K), ROUNDS, WM>(g, bp, h, 1, item, ln, a.damping, acc))); break;
@@ -535,8 +872,9 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
           if constexpr (mi_pr<ALGO>()) mi_zero<ALGO, K, ROUNDS>(g, bp, h, item, ln, a.damping, acc);
           break;
       }
-#undef MI_WM
       mi_flush<ALGO, K>(lds, u.group, acc);
+      }
+#undef MI_WM
     }
   }
   // publish this block's per-instance counters (device-scope atomics on
@@ -559,46 +897,70 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
   }
 }
 
-// Heavy vertices after a sweep: one thread per (heavy vertex, instance)
-// takes the vertex's accumulator with an exchange (leaving the identity),
-// runs the epilogue and adds its counters to the instance's sweep totals.
+// Heavy vertices after a sweep: each thread serves one instance column of
+// a run of MI_HEAVY_RUN consecutive heavy vertices: it takes each vertex's
+// accumulator with an exchange (leaving the identity) and runs the
+// epilogue. The counters go to the block's LDS copy and then once per block
+// and instance to the instance record, so the instance records do not take
+// one device atomic per heavy vertex.
 template <int ALGO, int K>
 __global__ void __launch_bounds__(BLOCK) mi_heavy_kernel(MiArgs a) {
   using R = MiRed<ALGO, K>;
   using T = typename R::T;
   if (a.ctl->remaining == 0 && !a.tuning) return;
+  extern __shared__ MiLds hlds[];
+  const int ninst = a.ngroups * K;
+  lds_clear(hlds, ninst, BLOCK);
+  __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const int32_t hh = (int32_t)(p / K), k = (int32_t)(p % K);
-  if (hh >= a.total_heavy) return;
-  int lo = 0, hi = a.nunits;  // units[lo].heavy_base <= hh < units[lo + 1].heavy_base
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (a.units[mid].heavy_base <= hh) lo = mid; else hi = mid;
+  const int32_t k = (int32_t)(p % K);
+  const int32_t h0 = (int32_t)(p / K) * MI_HEAVY_RUN;
+  const int32_t h1 = min(h0 + MI_HEAVY_RUN, a.total_heavy);
+  int lo = 0;
+  for (int32_t hh = h0; hh < h1; ++hh) {
+    // units[lo].heavy_base <= hh < units[lo + 1].heavy_base (runs move forward)
+    if (hh == h0) {
+      int hi = a.nunits;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.units[mid].heavy_base <= hh) lo = mid; else hi = mid;
+      }
+    } else {
+      while (lo + 1 < a.nunits && a.units[lo + 1].heavy_base <= hh) ++lo;
+    }
+    const MiUnit &u = a.units[lo];
+    if (a.group_active[u.group] == 0) continue;  // the sweep skipped the group: accumulators untouched
+    const MiGroup &g = a.groups[u.group];
+    const PageHeader *h = reinterpret_cast<const PageHeader *>(u.page);
+    const Heavy x = reinterpret_cast<const Heavy *>(u.page + h->off_heavy)[hh - u.heavy_base];
+    const int32_t *off = reinterpret_cast<const int32_t *>(u.page + h->off_offsets);
+    unsigned long long *slot = &u.acc[(size_t)((uint32_t)x.first_count & 0xFFFFFu) * K + k];
+    T t;
+    if constexpr (mi_pr<ALGO>()) t = (float)((double)(long long)atomicExch(slot, 0ull) / FIX_ONE);
+    else t = atomicExch(reinterpret_cast<uint32_t *>(slot), INF);
+    const int32_t v = h->v_begin + x.vl;
+    const Lane ln = lane_of(g.inst[k]);
+    uint32_t old;
+    if (!mi_attempt<ALGO, K>(g, v, k, ln, old)) continue;
+    MiAcc acc;
+    mi_epilogue<ALGO, K>(g, v, k, ln, old, t, (uint32_t)(off[x.vl + 1] - off[x.vl]), a.damping, acc);
+    lds_add<ALGO>(hlds[u.group * K + k], acc);
   }
-  const MiUnit &u = a.units[lo];
-  if (a.group_active[u.group] == 0) return;  // the sweep skipped the group: accumulators untouched
-  const MiGroup &g = a.groups[u.group];
-  const PageHeader *h = reinterpret_cast<const PageHeader *>(u.page);
-  const Heavy x = reinterpret_cast<const Heavy *>(u.page + h->off_heavy)[hh - u.heavy_base];
-  const int32_t *off = reinterpret_cast<const int32_t *>(u.page + h->off_offsets);
-  unsigned long long *slot = &u.acc[(size_t)((uint32_t)x.first_count & 0xFFFFFu) * K + k];
-  T t;
-  if constexpr (mi_pr<ALGO>()) t = (float)((double)(long long)atomicExch(slot, 0ull) / FIX_ONE);
-  else t = atomicExch(reinterpret_cast<uint32_t *>(slot), INF);
-  const int32_t v = h->v_begin + x.vl;
-  const Lane ln = lane_of(g.inst[k]);
-  uint32_t old;
-  if (!mi_attempt<ALGO, K>(g, v, k, ln, old)) return;
-  MiAcc acc;
-  mi_epilogue<ALGO, K>(g, v, k, ln, old, t, (uint32_t)(off[x.vl + 1] - off[x.vl]), a.damping, acc);
-  MiInst &in = g.inst[k];
-  if (acc.changed) atomicAdd(&in.sw_changed, acc.changed);
-  if (acc.min_changed != INF) atomicMin(&in.sw_min_changed, acc.min_changed);
-  if (acc.edges) atomicAdd(&in.sw_edges, (unsigned long long)acc.edges);
-  if constexpr (mi_pr<ALGO>()) {
-    if (acc.l1 != 0.0) atomicAdd(&in.sw_l1, acc.l1);
-    if (acc.ddelta != 0.0) atomicAdd(&in.sw_ddelta, acc.ddelta);
-    if (acc.dmass != 0.0) atomicAdd(&in.sw_dmass, acc.dmass);
+  __syncthreads();
+  for (int i = threadIdx.x; i < ninst; i += BLOCK) {
+    const MiLds &e = hlds[i];
+    if (e.changed == 0 && e.edges == 0 && e.min_changed == INF && e.l1 == 0.0 && e.ddelta == 0.0 &&
+        e.dmass == 0.0)
+      continue;
+    MiInst &in = a.groups[i / K].inst[i % K];
+    if (e.changed) atomicAdd(&in.sw_changed, e.changed);
+    if (e.min_changed != INF) atomicMin(&in.sw_min_changed, e.min_changed);
+    if (e.edges) atomicAdd(&in.sw_edges, (unsigned long long)e.edges);
+    if constexpr (mi_pr<ALGO>()) {
+      if (e.l1 != 0.0) atomicAdd(&in.sw_l1, e.l1);
+      if (e.ddelta != 0.0) atomicAdd(&in.sw_ddelta, e.ddelta);
+      if (e.dmass != 0.0) atomicAdd(&in.sw_dmass, e.dmass);
+    }
   }
 }
 
@@ -728,7 +1090,7 @@ void mi_pair(const MiArgs &a, hipStream_t s) {
   if (a.rounds == 2) mi_sweep_wm<ALGO, K, 2>(a, s, lds);
   else if (a.rounds == 8) mi_sweep_wm<ALGO, K, 8>(a, s, lds);
   else mi_sweep_wm<ALGO, K, 4>(a, s, lds);
-  hipLaunchKernelGGL((mi_heavy_kernel<ALGO, K>), dim3(a.heavy_blocks), dim3(BLOCK), 0, s, a);
+  hipLaunchKernelGGL((mi_heavy_kernel<ALGO, K>), dim3(a.heavy_blocks), dim3(BLOCK), lds, s, a);
   hipLaunchKernelGGL((mi_close_kernel<ALGO, K>), dim3(1), dim3(MI_CLOSE_THREADS), 0, s, a);
 }
 
@@ -746,6 +1108,7 @@ hipError_t launch_mi_sweep(int algo, int K, const MiArgs &a, hipStream_t s) {
   else if (algo == A_SSSP && a.narrow && K == 8) mi_pair<A_MIN16, 8>(a, s);
   else if (algo == A_SSSP && a.narrow && K == 16) mi_pair<A_MIN16, 16>(a, s);
   else if (algo == A_SSSP && a.narrow && K == 32) mi_pair<A_MIN16, 32>(a, s);
+  else if (algo == A_SSSP && a.narrow && K == 64) mi_pair<A_MIN16, 64>(a, s);
   else if (algo == A_SSSP && K == 8) mi_pair<A_SSSP, 8>(a, s);
   else if (algo == A_SSSP && K == 16) mi_pair<A_SSSP, 16>(a, s);
   else if (algo == A_SSSP && K == 32) mi_pair<A_SSSP, 32>(a, s);
@@ -761,6 +1124,7 @@ hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contri
     if (K == 8) hipLaunchKernelGGL((mi_init_column_kernel<A_MIN16, 8>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
     else if (K == 16) hipLaunchKernelGGL((mi_init_column_kernel<A_MIN16, 16>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
     else if (K == 32) hipLaunchKernelGGL((mi_init_column_kernel<A_MIN16, 32>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
+    else if (K == 64) hipLaunchKernelGGL((mi_init_column_kernel<A_MIN16, 64>), grid, block, 0, s, value, contrib, inv_outdeg, n, col, source);
     else return hipErrorInvalidValue;
     return hipGetLastError();
   }
@@ -785,6 +1149,7 @@ hipError_t launch_mi_extract(int K, uint32_t *value, int32_t n, const MiExtract 
     if (K == 8) hipLaunchKernelGGL((mi_extract_kernel<8, true>), grid, block, 0, s, value, n, x, r, reset_to, rank);
     else if (K == 16) hipLaunchKernelGGL((mi_extract_kernel<16, true>), grid, block, 0, s, value, n, x, r, reset_to, rank);
     else if (K == 32) hipLaunchKernelGGL((mi_extract_kernel<32, true>), grid, block, 0, s, value, n, x, r, reset_to, rank);
+    else if (K == 64) hipLaunchKernelGGL((mi_extract_kernel<64, true>), grid, block, 0, s, value, n, x, r, reset_to, rank);
     else return hipErrorInvalidValue;
     return hipGetLastError();
   }

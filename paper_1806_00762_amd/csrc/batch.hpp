@@ -11,6 +11,8 @@ namespace sr {
 
 // instances of one plan (their counters live in LDS during a sweep)
 constexpr int MI_MAX_INSTANCES = 1024;
+// consecutive heavy vertices per thread of the heavy-vertex kernel
+constexpr int MI_HEAVY_RUN = 8;
 
 // Per-instance control (device memory), one per column of a group.
 struct MiInst {
@@ -87,6 +89,8 @@ struct MiArgs {
   double tol_l1, floor_cap;
   int32_t max_sweeps;
   int32_t tuning;           // 1: never retire instances (timing runs)
+  int32_t descending;       // 1: the queue hands out items last to first (heavy chunks and
+                            // high in-degree bins of the last unit first)
   MiCtl *ctl;
   uint32_t *group_active;   // [ngroups] active instances per group (0: group skipped)
   uint32_t *host_remaining; // host-mapped copy of ctl->remaining

@@ -44,7 +44,7 @@ void load_tune_file() {
     std::string key;
     Tuned t{};
     if (is >> key >> t.K >> t.rounds >> t.grid >> t.grab && t.grid > 0 && t.grab > 0 &&
-        (t.rounds == 2 || t.rounds == 4 || t.rounds == 8) && (t.K == 8 || t.K == 16 || t.K == 32))
+        (t.rounds == 2 || t.rounds == 4 || t.rounds == 8) && (t.K == 8 || t.K == 16 || t.K == 32 || t.K == 64))
       g_tune_cache[key] = t;
   }
 }
@@ -84,7 +84,10 @@ sr_status MiPlan::add_group(sr_graph *g, int pvu, int *out_index) {
   // the sweep addresses a group's [n][K] arrays with 32-bit byte offsets
   if ((uint64_t)g->n * (uint64_t)K * 4ull >= (1ull << 32))
     return c->fail(SR_EINVAL, "graph too large for instance groups of this width (n * K * 4 bytes must stay below 4 GiB)");
-  if ((s = alloc((void **)&gr.value, (narrow ? 2ull : 4ull) * g->n * K, "instance values")) != SR_OK) return s;
+  // 16-bit columns carry one more row: a sentinel of unreached values that
+  // edge lanes past their range gather instead of being masked
+  if ((s = alloc((void **)&gr.value, narrow ? 2ull * (g->n + 1) * K : 4ull * g->n * K, "instance values")) != SR_OK)
+    return s;
   if (algo == A_PPR) {
     if ((s = alloc((void **)&gr.contrib, 4ull * g->n * K, "instance contrib")) != SR_OK) return s;
     float *iod = nullptr;
@@ -186,7 +189,9 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
   args.nunits = (int32_t)units.size();
   args.total_items = unit_prefix.back();
   args.total_heavy = total_heavy;
-  args.heavy_blocks = (int32_t)std::max<int64_t>(1, ((int64_t)total_heavy * K + BLOCK - 1) / BLOCK);
+  // one thread per instance column and run of MI_HEAVY_RUN heavy vertices
+  const int64_t runs = ((int64_t)total_heavy + MI_HEAVY_RUN - 1) / MI_HEAVY_RUN;
+  args.heavy_blocks = (int32_t)std::max<int64_t>(1, (runs * K + BLOCK - 1) / BLOCK);
   args.grab = 1;
   args.rounds = rounds;
   args.narrow = narrow ? 1 : 0;
@@ -205,6 +210,10 @@ sr_status MiPlan::finalize(double damping, double tol_l1, int32_t max_sweeps) {
   args.floor_cap = 1e-6;
   args.max_sweeps = max_sweeps;
   args.tuning = 0;
+  // last items first: the heavy chunks and high in-degree bins go out first
+  // (the longest items start early, and the in-place sweep updates the
+  // vertices most others pull from before they are read)
+  args.descending = 1;
   args.ctl = d_ctl;
   args.group_active = gact;
   args.host_remaining = d_remaining;
@@ -224,7 +233,8 @@ void MiPlan::prefix_tables() {
     int32_t acc = 0;
     u.blk_prefix[0] = 0;
     for (int b = 0; b < NBINS; ++b) {
-      const int per = mi_items_per_block_host(b, K, rounds);
+      // 16-bit columns run four per lane: the lane geometry of K/4 columns
+      const int per = mi_items_per_block_host(b, narrow ? K / 4 : K, rounds);
       const int nb = (b == BIN_ZERO && algo != A_PPR) ? 0 : (h.bin_count[b] + per - 1) / per;
       acc += nb;
       u.blk_prefix[b + 1] = acc;
@@ -250,7 +260,7 @@ sr_status MiPlan::set_rounds(int r) {
 sr_status MiPlan::clear_values(hipStream_t s) {
   for (auto &gr : groups) {
     // (16-bit columns: two 0xFFFF entries per word)
-    hipError_t e = launch_fill_u32(gr.value, INF, (size_t)gr.n * K / (narrow ? 2 : 1), s);
+    hipError_t e = launch_fill_u32(gr.value, INF, narrow ? (size_t)(gr.n + 1) * K / 2 : (size_t)gr.n * K, s);
     if (e != hipSuccess) return c->hip_fail(e, "column reset");
   }
   return SR_OK;
@@ -320,7 +330,9 @@ sr_status MiPlan::autotune(hipStream_t s, const std::string &key, int only_round
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  std::vector<int> roundss = {2, 4, 8};
+  // (16-bit columns run four per lane: 8 rounds of a lane's vertices would
+  // hold more registers than the extra loads in flight are worth)
+  std::vector<int> roundss = narrow ? std::vector<int>{2, 4} : std::vector<int>{2, 4, 8};
   if (only_rounds) roundss = {only_rounds};
   const int mults[] = {1, 2, 4, 8, 16};
   const int grabs[] = {1, 2, 4, 8};

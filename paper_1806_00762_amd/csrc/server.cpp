@@ -59,8 +59,11 @@ struct sr_server {
   std::thread th;
   bool stop = false;
   hipStream_t stream = nullptr, poll_stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around each sweep replay
   std::atomic<uint64_t> submitted{0}, completed{0}, sweeps{0}, fallbacks{0};
   double busy_ms = 0;
+  double kernel_ms = 0;     // device time of the sweep replays
+  uint64_t algo_bytes = 0;  // algorithmic bytes of the sweeps (see sr_server_stats)
   sr_status thread_error = SR_OK;
   std::string thread_msg;
 
@@ -70,12 +73,12 @@ struct sr_server {
 };
 
 // A column stored as 16 bits holds exact values for every vertex whose
-// distance (or level) fits 16 bits and leaves the others unreached: a
-// shortest path to a vertex that fits passes only through vertices that fit
-// (weights are at least 1), and every stored value is the length of a real
-// path. Pushing relaxations on the host from every reached vertex therefore
+// distance (or level) is below the stored cap (2^15 - 1) and leaves the
+// others unreached: a shortest path to a vertex that fits passes only
+// through vertices that fit (weights are at least 1), and every stored value
+// is the length of a real path. Pushing relaxations on the host from every reached vertex therefore
 // reaches the exact least fixed point (the label-correcting push of the
-// sparse stage). Rare: it needs a distance of at least 65535.
+// sparse stage). Rare: it needs a distance of at least 32767.
 sr_status sr_server::complete_on_host(int gi, int32_t algo, uint32_t *result) {
   sr_graph *g = graphs[gi];
   const int32_t n = g->n;
@@ -149,8 +152,12 @@ void sr_server::progress() {
     }
     hipError_t e = hipMemcpyAsync(plan->args.group_active, gact.data(), 4ull * G, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && plan->set_remaining(total, stream) != SR_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipEventRecord(ev0, stream);
     if (e == hipSuccess && plan->launch(stream) != SR_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipEventRecord(ev1, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    float sweep_ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&sweep_ms, ev0, ev1);
     for (int gi = 0; gi < G && e == hipSuccess; ++gi)
       e = hipMemcpyAsync(&ih[(size_t)gi * K], plan->groups[gi].inst, sizeof(MiInst) * K, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -161,6 +168,16 @@ void sr_server::progress() {
       break;
     }
     sweeps++;
+    // algorithmic bytes: each live graph's edge words (and weights), offsets,
+    // bin lists and own-value rows once per sweep; the gathered values are
+    // counted per instance when it retires
+    uint64_t shared_bytes = 0;
+    for (int gi = 0; gi < G; ++gi)
+      if (gact[gi]) {
+        const sr_graph *g = graphs[gi];
+        const bool sep_w = g->weighted && !g->packed;
+        shared_bytes += (uint64_t)g->m * (sep_w ? 8 : 4) + 12ull * g->n;
+      }
     // retire converged slots into their result buffers
     std::vector<std::pair<uint64_t, int>> finished;
     {
@@ -172,22 +189,29 @@ void sr_server::progress() {
           const MiInst &r = ih[(size_t)gi * K + k];
           if (r.done) finished.push_back({t, gi * K + k});
         }
+      kernel_ms += sweep_ms;
+      algo_bytes += shared_bytes;
+      for (auto &f : finished) algo_bytes += ih[(size_t)f.second].edges_total * (plan->narrow ? 2ull : 4ull);
     }
-    // one extraction pass per graph for all of its retiring columns
+    // one extraction pass per graph for all of its retiring columns (at most
+    // MI_EXTRACT_MAX columns per pass)
     for (int gi = 0; gi < G && e == hipSuccess; ++gi) {
-      MiExtract x{};
+      std::vector<std::pair<int32_t, uint32_t *>> cols;
       {
         std::lock_guard<std::mutex> lk(mu);
         for (auto &f : finished)
-          if (f.second / K == gi) {
-            x.col[x.count] = f.second % K;
-            x.out[x.count] = q[f.first].result;
-            x.count++;
-          }
+          if (f.second / K == gi) cols.push_back({f.second % K, q[f.first].result});
       }
-      if (x.count == 0) continue;
-      e = launch_mi_extract(K, plan->groups[gi].value, plan->groups[gi].n, x, stream, true, INF,
-                            plan->group_rank[gi], plan->narrow);
+      for (size_t b = 0; b < cols.size() && e == hipSuccess; b += MI_EXTRACT_MAX) {
+        MiExtract x{};
+        for (size_t j = b; j < cols.size() && x.count < MI_EXTRACT_MAX; ++j) {
+          x.col[x.count] = cols[j].first;
+          x.out[x.count] = cols[j].second;
+          x.count++;
+        }
+        e = launch_mi_extract(K, plan->groups[gi].value, plan->groups[gi].n, x, stream, true, INF,
+                              plan->group_rank[gi], plan->narrow);
+      }
     }
     if (!finished.empty() && e == hipSuccess) e = hipStreamSynchronize(stream);
     // 16-bit columns whose values did not all fit: completed exactly on the host
@@ -227,8 +251,8 @@ extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_
                                       int32_t max_slots, sr_server **out) {
   if (!c) return SR_EINVAL;
   if (!graphs || ngraphs < 1 || ngraphs > 8 || !out) return c->fail(SR_EINVAL, "need 1..8 graphs and out");
-  if (max_slots != 8 && max_slots != 16 && max_slots != 32)
-    return c->fail(SR_EINVAL, "max_slots_per_graph must be 8, 16 or 32");
+  if (max_slots != 8 && max_slots != 16 && max_slots != 32 && max_slots != 64)
+    return c->fail(SR_EINVAL, "max_slots_per_graph must be 8, 16, 32 or 64");
   if (c->host_only) return c->fail(SR_EDEVICE, "host-only context cannot serve");
   hipError_t he = hipSetDevice(c->device);
   if (he != hipSuccess) return c->hip_fail(he, "set device");
@@ -265,7 +289,8 @@ extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_
   }
   if ((st = s->plan->finalize(0.85, 1e-9, 1 << 30)) != SR_OK) return fail(st);
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&s->poll_stream, hipStreamNonBlocking) != hipSuccess)
+      hipStreamCreateWithFlags(&s->poll_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
     return fail(c->fail(SR_EDEVICE, "stream creation failed"));
   s->usable.assign(ngraphs, R);
   s->slot_ticket.assign(ngraphs, std::vector<uint64_t>(s->K, 0));
@@ -280,7 +305,9 @@ extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_
       if ((st = s->plan->set_column(gi, k, -1, false, false, s->stream)) != SR_OK) return fail(st);
   }
   // the schedule autotuner times the multi-source sweep with every column live
+  // (a solve from vertex 0 in each)
   {
+    if ((st = s->plan->clear_values(s->stream)) != SR_OK) return fail(st);
     for (int gi = 0; gi < ngraphs; ++gi)
       for (int k = 0; k < s->K; ++k)
         if ((st = s->plan->set_column(gi, k, 0, false, true, s->stream)) != SR_OK) return fail(st);
@@ -374,6 +401,8 @@ extern "C" sr_status sr_server_stats_get(sr_server *s, sr_server_stats *o) {
   for (size_t i = 0; i < s->usable.size() && i < 8; ++i) o->slots_per_graph[i] = s->usable[i];
   o->busy_ms = s->busy_ms;
   o->narrow_fallbacks = s->fallbacks;
+  o->kernel_ms = s->kernel_ms;
+  o->algo_bytes = s->algo_bytes;
   return SR_OK;
 }
 
@@ -391,6 +420,8 @@ extern "C" sr_status sr_server_destroy(sr_server *s) {
   sr_status st = s->thread_error;
   if (s->stream) (void)hipStreamDestroy(s->stream);
   if (s->poll_stream) (void)hipStreamDestroy(s->poll_stream);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
   delete s->plan;
   for (auto *g : s->graphs) g->server_refs--;
   delete s;

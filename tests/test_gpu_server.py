@@ -37,7 +37,7 @@ def wait_all(srv, tickets, outs, timeout=60.0):
     return lat
 
 
-@pytest.mark.parametrize("slots", [8, 16, 32])
+@pytest.mark.parametrize("slots", [8, 16, 32, 64])
 def test_server_alone_vs_mix(sr, slots):
     # the scale-16 graph has vertices of in-degree above 2048 (heavy chunks,
     # split over several wavefronts for the wider slot groups)
@@ -101,22 +101,28 @@ def test_server_rejects_bad_requests(sr):
 
 
 def test_server_wide_distances_completed_exactly(sr):
-    """Served slots hold 16-bit values. On a weighted path (weight 250 per
-    hop) the vertices past hop 262 lie beyond distance 65535; queries from
-    its start overflow their slot and are completed on the host when they
-    retire, a query from the middle does not. Every result stays bit-exact
-    (BFS levels fit), and the stats count the completions; queries on a
-    small graph in the same server do not need it."""
+    """Served slots hold 16-bit values below 32767. On a weighted path
+    (weight 250 per hop) the vertices past hop 131 lie at distance 32767 or
+    more; queries from its start overflow their slot and are completed on the
+    host when they retire, a query from hop 300 does not. A second path has
+    weights above the 16-bit range (separate u32 weights, clamped in the
+    packed relaxation): every query on it overflows at once. Every result
+    stays bit-exact (BFS levels fit), and the stats count the completions;
+    queries on a small graph in the same server do not need it."""
     n = 400
     src = list(range(n - 1)) + [0]
     dst = list(range(1, n)) + [n - 1]
     w = [250] * (n - 1) + [255]
     path = graphgen.from_edges(n, src, dst, w)
     small = graphgen.rmat(10, 8, seed=91, weights=(1, 255, 92))
+    nh = 40
+    heavy = graphgen.from_edges(nh, list(range(nh - 1)), list(range(1, nh)),
+                                [(40000, 5, 30000, 70000, 1)[i % 5] for i in range(nh - 1)])
     ctx = sr.Context(0, 0)
-    Gs = [ctx.load(path), ctx.load(small, reorder=True)]
+    Gs = [ctx.load(path), ctx.load(small, reorder=True), ctx.load(heavy)]
     srv = sr.Server(ctx, Gs, slots=8)
-    reqs = [(0, "sssp", 0), (0, "sssp", 3), (1, "sssp", 0), (1, "bfs", 1), (0, "bfs", 0), (0, "sssp", 250)]
+    reqs = [(0, "sssp", 0), (0, "sssp", 3), (1, "sssp", 0), (1, "bfs", 1), (0, "bfs", 0), (0, "sssp", 300),
+            (2, "sssp", 0), (2, "sssp", 1), (2, "bfs", 0)]
     tickets, outs = [], {}
     for gi, algo, s in reqs:
         t = srv.submit(gi, algo, s)
@@ -125,13 +131,15 @@ def test_server_wide_distances_completed_exactly(sr):
     wait_all(srv, tickets, outs)
     st = srv.stats()
     say(f"  wide distances: stats {st}")
-    graphs = [path, small]
+    graphs = [path, small, heavy]
     for t, (gi, algo, s) in zip(tickets, reqs):
         ref = oracle.sssp(graphs[gi], s) if algo == "sssp" else oracle.bfs(graphs[gi], s)
         assert np.array_equal(outs[t], ref), (gi, algo, s)
-    # sources 0 and 3 reach distances beyond 65535 along the path
-    assert int(oracle.sssp(path, 0)[n - 2]) > 65535
-    assert st["narrow_fallbacks"] >= 2
+    # sources 0 and 3 reach distances beyond 32766 along the path, 300 does not
+    assert int(oracle.sssp(path, 0)[n - 2]) > 32766
+    assert int(oracle.sssp(path, 300).max()) == 0xFFFFFFFF  # (vertices before 300 unreached)
+    assert int(oracle.sssp(path, 300)[n - 2]) < 32767
+    assert st["narrow_fallbacks"] >= 4
     srv.close()
     for G in Gs:
         G.close()

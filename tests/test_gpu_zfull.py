@@ -173,7 +173,7 @@ def test_serving_stream_three_graphs(sr):
     n_checked = {0: 0, 1: 0, 2: 0}
     with sr.Context(0, 0) as ctx:
         Gs = [ctx.load(g, reorder=True) for g in graphs]
-        srv = sr.Server(ctx, Gs, slots=32)
+        srv = sr.Server(ctx, Gs, slots=64)
         t0 = time.time()
         tickets = []
         for i, (gi, algo, s) in enumerate(reqs):
