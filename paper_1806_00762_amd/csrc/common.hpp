@@ -132,6 +132,8 @@ struct alignas(256) PageHeader {
   // entries up to the last vertex the min programs read; bytes_lead is the
   // whole image.
   int32_t split;
+  int32_t wide3;                 // unweighted graphs: the wide in-edges are 3-byte ids back to back
+                                 // (little-endian; 8 bytes of padding after the last)
   uint64_t off_vpk;              // u32 per vertex (see above)
   uint64_t off_hsrc;             // u16 narrow source ids
   uint64_t off_tbase;            // int2 per tile with in-edges

@@ -388,13 +388,15 @@ struct Launch {
 // (SSSP), and the gathered value; per changed vertex the value write;
 // PageRank also writes rank and contrib and reads 1/outdeg per attempted
 // vertex. On split-width pages an edge read from the narrow section costs
-// its u16 id (and the u8 weight for SSSP) instead of the u32 word (a
-// visited vertex reads its packed tile-relative ends in place of its offset).
-uint64_t algo_bytes(int algo, int pvu, bool sep_weights, bool split, const SweepRecord &r) {
+// its u16 id (and the u8 weight for SSSP) instead of the u32 word, and on
+// the images of unweighted graphs a wide edge its 3-byte id (a visited
+// vertex reads its packed tile-relative ends in place of its offset).
+uint64_t algo_bytes(int algo, int pvu, bool sep_weights, bool split, bool wide3, const SweepRecord &r) {
   const uint64_t visited = r.attempted + r.skipped;
   const uint64_t eb = (algo == A_SSSP && sep_weights) ? 12 : 8;
   uint64_t b = r.edges * eb + visited * 8;
   if (split) b -= r.edges_narrow * (algo == A_SSSP ? 1 : 2);
+  if (split && wide3) b -= r.edges - r.edges_narrow;
   if (pvu == P_WEAK) b += visited * 2;
   if (algo == A_PR || algo == A_PPR) b += r.attempted * 12;
   else b += r.changed * 4;
@@ -501,7 +503,7 @@ struct Runner {
       st.vertices_skipped += (int64_t)r.skipped;
       st.mispredicted += (int64_t)r.mispred;
       for (int i = 0; i < 8; ++i) st.state_hist[i] += (int64_t)r.hist[i];
-      st.algo_bytes += algo_bytes(algo, pvu, g->weighted && !g->packed, split, r);
+      st.algo_bytes += algo_bytes(algo, pvu, g->weighted && !g->packed, split, split && !g->weighted, r);
       st.edges_narrow += (int64_t)r.edges_narrow;
       cur_pass_changed += r.changed;
       if (r.pass_l1_closed >= 0.0) {
@@ -584,6 +586,7 @@ struct Runner {
     // (it needs fewer registers than the plain one)
     a.packed = (g->weighted ? g->packed : (int64_t)g->n <= ((int64_t)1 << 24)) ? 1 : 0;
     a.split = split ? 1 : 0;
+    a.wide3 = split && !g->weighted ? 1 : 0;  // the images of unweighted graphs (see split_layout)
     if (split && !a.packed) return c->fail(SR_EINVAL, "split-width pages need packed edge words");
     return SR_OK;
   }

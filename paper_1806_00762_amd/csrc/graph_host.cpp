@@ -226,6 +226,9 @@ static uint64_t split_layout(const sr_graph *g, const PageHeader &h, int32_t lea
                              PageHeader &s) {
   s = h;
   s.split = 1;
+  // an unweighted graph's wide in-edges need only their id: n <= 2^24 for
+  // every split image, so 3 bytes hold it
+  s.wide3 = g->weighted ? 0 : 1;
   uint64_t o = sizeof(PageHeader);
   s.off_tiles = o;   o = align256(o + 8ull * (uint64_t)h.n_tiles);
   s.off_chunks = o;  o = align256(o + sizeof(Chunk) * (uint64_t)h.n_chunks);
@@ -234,7 +237,7 @@ static uint64_t split_layout(const sr_graph *g, const PageHeader &h, int32_t lea
   s.off_hside = o;   o = align256(o + 16ull * (uint64_t)h.n_heavy);
   s.off_vpk = o;     o = align256(o + 4ull * (uint64_t)lead);
   s.off_hsrc = o;    o = align256(o + 2ull * (uint64_t)mh);
-  s.off_src = o;     o = align256(o + 4ull * (uint64_t)mt);
+  s.off_src = o;     o = align256(o + (s.wide3 ? 3ull * (uint64_t)mt + 8ull : 4ull * (uint64_t)mt));
   s.off_w = o;       o = o + (g->weighted ? (uint64_t)mh : 0ull);
   s.off_offsets = 0;  // none: tile bases and vertex entries replace them
   s.off_bins = 0;
@@ -335,6 +338,8 @@ static sr_status split_page(sr_graph *g, Page &pg) {
   }
   uint16_t *hsrc = (uint16_t *)(buf + s.off_hsrc);
   uint32_t *words = (uint32_t *)(buf + s.off_src);
+  uint8_t *ids3 = (uint8_t *)(buf + s.off_src);
+  if (s.wide3) std::memset(ids3 + 3ull * (uint64_t)mt, 0, 8);
   uint8_t *hw = (uint8_t *)(buf + s.off_w);
   int64_t nh = 0, nt = 0;
   for (int64_t e = eb; e < g->in_off[vb + lead]; ++e) {
@@ -345,6 +350,11 @@ static sr_status split_page(sr_graph *g, Page &pg) {
       hsrc[nh] = (uint16_t)u;
       if (g->weighted) hw[nh] = (uint8_t)w;
       nh++;
+    } else if (s.wide3) {
+      ids3[3 * nt] = (uint8_t)u;
+      ids3[3 * nt + 1] = (uint8_t)(u >> 8);
+      ids3[3 * nt + 2] = (uint8_t)(u >> 16);
+      nt++;
     } else {
       words[nt++] = u | (g->weighted ? w << 24 : 0u);
     }

@@ -71,6 +71,20 @@ struct PageCtx {
   unsigned long long *partial;  // heavy-vertex accumulators, at each vertex's first chunk
 };
 
+// Wide in-edge e of a split image: its edge word, or (W3: the image of an
+// unweighted graph stores 3-byte ids back to back, 8 bytes of padding
+// after the last) the id, taken from the two aligned words around it.
+template <bool W3>
+__device__ inline uint32_t wide_word(const PageCtx &p, int32_t e) {
+  if constexpr (W3) {
+    const uint32_t b = 3u * (uint32_t)e;
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p.src) + (b & ~3u));
+    return __builtin_amdgcn_alignbyte(w[1], w[0], b & 3u) & 0xFFFFFFu;
+  } else {
+    return p.src[e];
+  }
+}
+
 // Thread-local sweep counters, reduced per block at the end.
 struct Acc {
   uint32_t changed = 0, attempted = 0, skipped = 0, mispred = 0, edges = 0;
@@ -308,10 +322,11 @@ __device__ inline void frontier_push(const Run &r, bool changed, int32_t v) {
 // runs of edges of the same vertex are reduced in registers before one LDS
 // atomic. Phase 3 runs the epilogues.
 
-template <bool SPLIT_, bool DET_ = false>
+template <bool SPLIT_, bool DET_ = false, bool W3_ = false>
 struct TileLds {
   static constexpr bool SPLIT = SPLIT_;
   static constexpr bool DET = DET_;
+  static constexpr bool W3 = W3_;  // split image of an unweighted graph: wide ids of 3 bytes
   int32_t pos[TILE_V + 1];  // first compacted (wide) edge position of each attempting vertex
   int32_t eb[TILE_V];       // its first (wide) in-edge (page-local) minus that position
   // split images: the same for the narrow list (one unused entry otherwise)
@@ -537,10 +552,19 @@ __device__ inline void tile_gather_split(const Run &r, const PageCtx &p, L &s, i
   const char *hs = reinterpret_cast<const char *>(p.hsrc);
   const char *ws = reinterpret_cast<const char *>(p.src);
   uint32_t word[EPT], wt[EPT];
+  // 3-byte wide ids: the second aligned word after the first (a narrow
+  // position rereads its own word)
+  uint32_t word2[L::W3 ? EPT : 1];
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
-    const char *a = nar[j] ? hs + ((2 * e[j]) & ~3) : ws + 4 * e[j];
-    word[j] = *reinterpret_cast<const uint32_t *>(a);
+    if constexpr (L::W3) {
+      const char *a = nar[j] ? hs + ((2 * e[j]) & ~3) : ws + ((3u * (uint32_t)e[j]) & ~3u);
+      word[j] = *reinterpret_cast<const uint32_t *>(a);
+      word2[j] = *reinterpret_cast<const uint32_t *>(nar[j] ? a : a + 4);
+    } else {
+      const char *a = nar[j] ? hs + ((2 * e[j]) & ~3) : ws + 4 * e[j];
+      word[j] = *reinterpret_cast<const uint32_t *>(a);
+    }
   }
   if constexpr (ALGO == A_SSSP) {
     // a wavefront's group covers 128 consecutive positions, so it is
@@ -560,7 +584,10 @@ __device__ inline void tile_gather_split(const Run &r, const PageCtx &p, L &s, i
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const uint32_t un = (word[j] >> (16 * (e[j] & 1))) & 0xFFFFu;
-    const uint32_t u = nar[j] ? un : src_of<true>(word[j]);
+    uint32_t uw;
+    if constexpr (L::W3) uw = __builtin_amdgcn_alignbyte(word2[j], word[j], (3u * (uint32_t)e[j]) & 3u) & 0xFFFFFFu;
+    else uw = src_of<true>(word[j]);
+    const uint32_t u = nar[j] ? un : uw;
     uint32_t w = 0u;
     if constexpr (ALGO == A_SSSP) w = nar[j] ? wt[j] : (word[j] >> 24);
     const T y = R::edge(r, (int32_t)u, w);
@@ -619,7 +646,7 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, L
       for (int j = 0; j < 2; ++j) {
         if (act[j]) {
           const bool nar = SPLIT && dn[j] > 0;
-          const int32_t u = nar ? (int32_t)p.hsrc[nb[j]] : src_of<PACKED>(p.src[eb[j]]);
+          const int32_t u = nar ? (int32_t)p.hsrc[nb[j]] : src_of<PACKED>(wide_word<SPLIT && L::W3>(p, eb[j]));
           const uint32_t x = r.value[u];
           acc.edges += 1;
           if (nar) acc.narrow += 1;
@@ -709,7 +736,7 @@ __device__ void sweep_tile(const Run &r, const PageCtx &p, int item, Acc &acc, L
 // Edges [a, b) of one chunk list, lanes strided, batches of B per lane:
 // B loads, then B gathers, all in flight together (lanes past the range
 // reread its first edge). NARROW: u16 ids and u8 weights of a split image.
-template <int ALGO, bool PACKED, bool NARROW>
+template <int ALGO, bool PACKED, bool NARROW, bool W3 = false>
 __device__ inline typename Red<ALGO>::T chunk_range(const Run &r, const PageCtx &p, int32_t a, int32_t b,
                                                     typename Red<ALGO>::T x) {
   using R = Red<ALGO>;
@@ -726,7 +753,7 @@ __device__ inline typename Red<ALGO>::T chunk_range(const Run &r, const PageCtx 
         q[j] = p.hsrc[ei[j]];
         w[j] = ALGO == A_SSSP ? (uint32_t)p.hw[ei[j]] : 0u;
       } else {
-        q[j] = p.src[ei[j]];
+        q[j] = wide_word<W3>(p, ei[j]);
       }
     }
 #pragma unroll
@@ -740,7 +767,7 @@ __device__ inline typename Red<ALGO>::T chunk_range(const Run &r, const PageCtx 
   return x;
 }
 
-template <int ALGO, bool PACKED, bool SPLIT>
+template <int ALGO, bool PACKED, bool SPLIT, bool W3 = false>
 __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
   using R = Red<ALGO>;
   using T = typename R::T;
@@ -767,7 +794,7 @@ __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
     if (comp && r.early) {
       int32_t u;
       if (SPLIT && dn > 0) u = (int32_t)p.hsrc[nb];
-      else if (SPLIT) u = src_of<PACKED>(p.src[v0 - nb]);
+      else if (SPLIT) u = src_of<PACKED>(wide_word<W3>(p, v0 - nb));
       else u = src_of<PACKED>(p.src[p.off[c.vl]]);
       if (r.value[u] == r.threshold) {
         x = r.threshold + 1u;
@@ -782,7 +809,7 @@ __device__ void sweep_chunk(const Run &r, const PageCtx &p, int item) {
       if (na < nz) x = chunk_range<ALGO, PACKED, true>(r, p, nb + (na - v0), nb + (nz - v0), x);
       // wide part: combined positions [v0 + dn, ...) -> wide words from v0 - nb
       const int32_t wa = max(c.e_begin, v0 + dn), wz = c.e_end;
-      if (wa < wz) x = chunk_range<ALGO, PACKED, false>(r, p, wa - nb - dn, wz - nb - dn, x);
+      if (wa < wz) x = chunk_range<ALGO, PACKED, false, W3>(r, p, wa - nb - dn, wz - nb - dn, x);
     } else {
       x = chunk_range<ALGO, PACKED, false>(r, p, c.e_begin, c.e_end, x);
     }
@@ -904,7 +931,7 @@ __device__ inline void publish_record(const SweepRecord *src, SweepRecord *dst) 
 }
 
 // ------------------------------------------------------------ the sweep
-template <int ALGO, int EPT, bool PACKED, bool SPLIT, bool DET = false>
+template <int ALGO, int EPT, bool PACKED, bool SPLIT, bool DET = false, bool W3 = false>
 __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   Ctl *ctl = a.ctl;
   // converged, or a later sweep of a window whose last sweep changed
@@ -913,7 +940,7 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   __shared__ uint32_t s_hist[8];
   __shared__ uint32_t s_u32[WAVES][7];
   __shared__ double s_f64[WAVES][3];
-  __shared__ TileLds<SPLIT, DET> s_tile;
+  __shared__ TileLds<SPLIT, DET, W3> s_tile;
   if (threadIdx.x < 8) s_hist[threadIdx.x] = 0;
 
   // locate (page, section, item) of this block: section 0 = tiles, 1 = chunks
@@ -976,7 +1003,7 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs a) {
   // sweep (and the pass) is closed the same way
   if (b < a.blk_prefix[a.nent * NSEC]) {
     if (sec == 0) sweep_tile<ALGO, EPT, PACKED>(r, p, item, acc, s_tile);
-    else sweep_chunk<ALGO, PACKED, SPLIT>(r, p, item);
+    else sweep_chunk<ALGO, PACKED, SPLIT, W3>(r, p, item);
   }
 
   // block reduction of the counters, then one set of device-scope atomics
@@ -1375,7 +1402,11 @@ static void launch_pair(const SweepArgs &a, hipStream_t s, hipEvent_t mid) {
     if (a.nent > 0) hipLaunchKernelGGL(det_commit_kernel, dim3(64, a.nent), dim3(BLOCK), 0, s, a);
     return;
   }
-  if (CAN_SPLIT && a.split && a.packed) {
+  // (images of unweighted graphs hold 3-byte wide ids)
+  constexpr bool CAN_W3 = ALGO == A_BFS || ALGO == A_CC;
+  if (CAN_W3 && a.split && a.packed && a.wide3) {
+    hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true, CAN_SPLIT, false, CAN_W3>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
+  } else if (CAN_SPLIT && a.split && a.packed) {
     hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true, CAN_SPLIT>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);
   } else if (a.packed) {
     hipLaunchKernelGGL((sweep_kernel<ALGO, EPT, true, false>), dim3(a.nblocks), dim3(BLOCK), 0, s, a);

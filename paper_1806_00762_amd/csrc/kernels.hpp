@@ -21,6 +21,7 @@ struct SweepArgs {
   int32_t packed;          // edge words carry the weight in their top byte
   int32_t early;           // BFS under strong prediction: stop at a first in-neighbour on the threshold level
   int32_t split;           // the pages in the slots are split-width images (min programs)
+  int32_t wide3;           // ... of an unweighted graph: their wide in-edges are 3-byte ids
   int32_t det;             // PageRank: deterministic sweep (gathers read contrib, pulls write
                            // contrib_next, whose window ranges are copied back after the sweep)
   int32_t delta;           // PageRank-delta run: while the control block's delta phase is on, the

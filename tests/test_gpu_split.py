@@ -54,6 +54,8 @@ GRAPHS = {  # builder, programs, load keywords
     "uniform13w": (lambda: graphgen.uniform(13, 1 << 16, seed=13, weights=(1, 255, 3)), ("bfs", "sssp"),
                    {}),
     "star70000w": (lambda: star(70000, weights=True), ("bfs", "sssp", "cc"), {"symmetric": True}),
+    # unweighted: the wide ids of the images are 3 bytes (tiles and heavy chunks)
+    "star70000u": (lambda: star(70000), ("bfs", "cc"), {"symmetric": True}),
 }
 SCHED = {"s4p7d2": (7, 4, 2), "s3p3d1": (3, 3, 1)}
 _cache = {}
