@@ -85,13 +85,15 @@ def sync():
 
 def _cc_leg(args, g, workload, traffic_name, cpu=True):
     """Streamed CC on a symmetric graph: pages within a quarter of the graph
-    bytes (plus the vertex state), strong prediction, timed solves; labels
-    checked bit-exact against the oracle's union-find (timed, one thread)
-    and, with cpu=True, the multi-core CPU baseline timed too."""
+    bytes (plus the vertex state: label, predictor state and in-edge bit per
+    vertex), strong prediction, the heterogeneous model of Section 3.1 (the
+    host takes over once the vertices a pass would attempt are few), timed
+    solves; labels checked bit-exact against the oracle's union-find (timed,
+    one thread) and, with cpu=True, the multi-core CPU baseline timed too."""
     import oracle
     import paper_1806_00762_amd as sr
     gbytes = 4 * (g.n + 1) + 4 * g.m
-    budget = gbytes // 4 + 5 * g.n + (1 << 20)
+    budget = gbytes // 4 + 5 * g.n + g.n // 8 + (1 << 20)
     ctx = sr.Context(0, budget)
     t = time.perf_counter()
     G = ctx.load(g, symmetric=True, reorder=args.order == "degree")
@@ -103,7 +105,8 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
     # most max_inner_iters times) does not depend on when a copy lands, so a
     # profiled run makes the same sweeps as the timed one
     run_kw = dict(pvu="strong", max_inner_iters=args.inner, force_stream=True, copy_depth=args.copy_depth,
-                  wide_pages=args.wide_pages, deterministic=args.schedule == "fixed")
+                  wide_pages=args.wide_pages, deterministic=args.schedule == "fixed",
+                  hetero=not args.no_host_stage)
     for i in range(args.warmup):
         st = G.run("cc", **run_kw)
         log(f"[bench] {workload} warmup {i}: {st['wall_ms']:.1f} ms, passes {st['passes']}")
@@ -114,6 +117,22 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
     elapsed = time.perf_counter() - t0
     lab = G.values()
     st = stats[-1]
+    device_only = None
+    if not args.no_host_stage:
+        # the same solves with device passes only (the pass that proves
+        # convergence streams every page again)
+        dkw = dict(run_kw, hetero=False)
+        G.run("cc", **dkw)
+        sync()
+        t1 = time.perf_counter()
+        dst = [G.run("cc", **dkw) for _ in range(args.steps)]
+        sync()
+        del1 = time.perf_counter() - t1
+        assert np.array_equal(G.values(), lab)
+        device_only = {"gteps": round(g.m * args.steps / del1 / 1e9, 4),
+                       "ms_per_step": round(del1 * 1e3 / args.steps, 3), "passes_per_solve": dst[-1]["passes"],
+                       "h2d_bytes_per_solve": sum(x["h2d_bytes"] for x in dst) // args.steps}
+        log(f"[bench] {workload} device passes only: {device_only}")
     log(f"[bench] {workload}: {elapsed * 1e3 / args.steps:.1f} ms per solve, passes {st['passes']} sweeps "
         f"{st['sweeps']} kernel {st['kernel_ms']:.1f} ms h2d {st['h2d_ms']:.1f} ms ({st['h2d_bytes'] / 1e9:.2f} GB)")
     sweep_ms = sum(x["sweep_kernel_ms"] for x in stats)
@@ -138,7 +157,9 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
                    "page_image": "full-width" if args.wide_pages else "split-width when smaller",
                    "schedule": "fixed re-entry (until no change, <= max_inner_iters)" if args.schedule == "fixed"
                    else "re-entry until the next page lands",
-                   "narrow_edge_frac": round(narrow / max(scanned, 1), 4)},
+                   "narrow_edge_frac": round(narrow / max(scanned, 1), 4),
+                   "host_stage": "off" if args.no_host_stage else
+                   "on (the host pulls the vertices a pass would attempt once at most n/512 remain)"},
         "roofline": {"bound": "hbm", "kernel": "sweep_kernel<CC>",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -158,6 +179,11 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
         "sweeps_per_solve": st["sweeps"],
         "timed_sweeps": sweeps,
         "kernel_busy_frac": round(kernel_ms / (elapsed * 1e3), 3),
+        "host_stage": {"entries_per_solve": round(sum(x["sparse_entries"] for x in stats) / args.steps, 2),
+                       "finished_solves": sum(x["sparse_stage"] for x in stats),
+                       "list": st["sparse_frontier"], "edges_per_solve": st["sparse_relaxations"],
+                       "ms_per_solve": round(sum(x["sparse_ms"] for x in stats) / args.steps, 3)},
+        "device_passes_only": device_only,
     }
     G.close()
     ctx.close()
@@ -840,6 +866,8 @@ def main():
     ap.add_argument("--order", choices=["degree", "input"], default="degree",
                     help="internal vertex numbering of the headline graph (results are in input ids)")
     ap.add_argument("--no-hetero", action="store_true", help="skip the host sparse stage leg")
+    ap.add_argument("--no-host-stage", action="store_true",
+                    help="CC legs without the heterogeneous model's host stage (device passes only)")
     ap.add_argument("--headline", choices=["cc24", "sssp22"], default="cc24",
                     help="workload of the headline line: streamed CC on R-MAT scale 24 (and its uniform "
                          "twin), or streamed SSSP on R-MAT scale 22")

@@ -84,7 +84,13 @@ typedef enum { SR_PVU_OFF = 0, SR_PVU_STRONG = 1, SR_PVU_WEAK = 2, SR_PVU_DEFAUL
                                      over that pass's frontier. When the host's frontier grows past
                                      sparse_return vertices, the run returns to the device passes
                                      (the switch taken back to dense); otherwise the host reaches
-                                     the fixed point and ends the run */
+                                     the fixed point and ends the run. Streamed runs under strong
+                                     prediction also enter the host stage from the other side: after
+                                     a pass whose changed set is too large, the device lists the
+                                     vertices the next pass would attempt (an in-edge and a value
+                                     above the Table I threshold); when at most sparse_switch, the
+                                     host pulls them from its copy of the in-edges and pushes from
+                                     those that changed, instead of streaming every page again */
 #define SR_RUN_SKIP_CLEAN 0x20u   /* streamed min programs (strong or no prediction): a pass copies
                                      and sweeps only the pages with an in-edge from a vertex that
                                      changed in the previous pass (the others are at their local
@@ -319,8 +325,9 @@ typedef struct {
   uint64_t algo_bytes;       /* algorithmic bytes of all sweeps: edge words, gathered values,
                                 offsets, gate reads, value writes */
   int32_t sparse_stage;      /* SR_RUN_HETERO: 1 if the host sparse stage finished the run */
-  int32_t sparse_rounds;     /* push rounds of the sparse stage (all entries) */
-  int64_t sparse_frontier;   /* vertices its last entry started from (changed in the last device pass) */
+  int32_t sparse_rounds;     /* pull and push rounds of the sparse stage (all entries) */
+  int64_t sparse_frontier;   /* vertices its last entry started from (changed in the last device pass,
+                                or the vertices the next pass would have attempted) */
   int64_t sparse_relaxations;/* edges it relaxed (all entries) */
   double sparse_ms;          /* its wall time, transfers included (all entries) */
   int64_t pages_skipped;     /* SR_RUN_SKIP_CLEAN: page visits left out because no in-edge changed */

@@ -198,6 +198,7 @@ static void release_state(sr_graph *g) {
   g->ctx->dfree(s.stripes);
   g->ctx->dfree(s.frontier);
   g->ctx->dfree(s.fr_count);
+  g->ctx->dfree(s.has_in);
   s = RunState();
 }
 
@@ -844,6 +845,19 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     if (!g->state.fr_count && (s = c->dalloc((void **)&g->state.fr_count, 256, "frontier count")) != SR_OK)
       return s;
   }
+  // the host stage's open list (streamed runs under strong prediction)
+  // marks the vertices with an in-edge: one bit each, built once per graph;
+  // without room in the budget the run goes without that entry to the stage
+  if (hetero && R.pvu == P_STRONG && !g->res.resident && g->state.fr_cap > 0 && !g->state.has_in) {
+    const uint64_t words = ((uint64_t)g->n + 31) / 32;
+    if (c->used + 4 * words + 512 <= c->budget) {
+      std::vector<uint32_t> bits((size_t)words, 0u);
+      for (int32_t v = 0; v < g->n; ++v)
+        if (g->in_off[v + 1] > g->in_off[v]) bits[(size_t)v >> 5] |= 1u << (v & 31);
+      if ((s = c->dalloc((void **)&g->state.has_in, 4 * words, "in-edge bitmap")) != SR_OK) return s;
+      HIP_TRY(c, hipMemcpy(g->state.has_in, bits.data(), 4 * words, hipMemcpyHostToDevice), "in-edge bitmap");
+    }
+  }
   if (!g->res.resident && (depth < 1 || depth >= g->res.nslots))
     return c->fail(SR_EINVAL, "copy_depth must be in [1, num_slots)");
   // streamed min programs copy split-width images when every one fits a slot
@@ -1029,6 +1043,67 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     *fin = true;
     return SR_OK;
   };
+  // The host stage entered from the vertices the next pass would attempt
+  // (streamed runs under strong prediction): after a pass whose changed set
+  // is too large for the sparse stage above, the device lists the vertices
+  // with an in-edge and a value above the Table I threshold; when there are
+  // at most sparse_thr of them, the host pulls them over its copy of the
+  // in-edges instead of streaming every page again, and pushes from those
+  // that changed. Exact: every vertex off the list is final by Table I or
+  // has no in-edge, and every value the host lowers stays above the
+  // threshold (a vertex on the list is not final, so its true value is
+  // above it), so a hand-back to the device keeps Table I sound.
+  auto open_stage = [&](bool *fin) -> sr_status {
+    *fin = false;
+    if (!hetero || R.pvu != P_STRONG || g->res.resident || !g->state.has_in || g->state.fr_cap == 0) return SR_OK;
+    const double t1 = now_ms();
+    HIP_TRY(c, launch_fill_u32(g->state.fr_count, 0u, 1, c->compute), "open list");
+    HIP_TRY(c, launch_open_list(g->state.value, g->state.has_in, g->n, g->state.ctl, g->state.frontier,
+                                g->state.fr_cap, g->state.fr_count, c->compute), "open list");
+    uint32_t cnt = 0;
+    HIP_TRY(c, hipMemcpyAsync(&cnt, g->state.fr_count, 4, hipMemcpyDeviceToHost, c->compute), "open count");
+    HIP_TRY(c, hipStreamSynchronize(c->compute), "open count");
+    if (cnt > sparse_thr || cnt > g->state.fr_cap) return SR_OK;
+    if (!g->host_val && g->n > 0) {
+      HIP_TRY(c, hipHostMalloc((void **)&g->host_val, 4ull * g->n, hipHostMallocDefault), "pinned value mirror");
+    }
+    uint32_t *val = g->host_val;
+    std::vector<uint32_t> open((size_t)cnt);
+    if (cnt)
+      HIP_TRY(c, hipMemcpyAsync(open.data(), g->state.frontier, 4ull * cnt, hipMemcpyDeviceToHost, c->compute),
+              "open list to host");
+    HIP_TRY(c, hipMemcpyAsync(val, g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute), "values to host");
+    HIP_TRY(c, hipStreamSynchronize(c->compute), "values to host");
+    std::vector<uint32_t> changed;
+    int64_t relaxed = sr::sparse_pull(g, R.algo, val, open.data(), (int64_t)cnt, &changed);
+    int32_t rounds = 1;
+    rest.clear();
+    if (!changed.empty()) {
+      sr::build_out_csr(g);
+      int32_t pr_rounds = 0;
+      relaxed += sr::sparse_push(g, R.algo, val, changed.data(), (int64_t)changed.size(), &pr_rounds, sparse_ret,
+                                 &rest);
+      rounds += pr_rounds;
+      HIP_TRY(c, hipMemcpyAsync(g->state.value, val, 4ull * g->n, hipMemcpyHostToDevice, c->compute),
+              "values to device");
+      HIP_TRY(c, hipStreamSynchronize(c->compute), "values to device");
+    }
+    R.st.sparse_entries++;
+    R.st.sparse_rounds += rounds;
+    R.st.sparse_frontier = (int64_t)cnt;
+    R.st.sparse_relaxations += relaxed;
+    R.st.sparse_ms += now_ms() - t1;
+    if (!rest.empty()) {
+      R.st.sparse_returns++;
+      R.last_pass_changed = (uint64_t)rest.size();
+      returned = true;
+      return SR_OK;
+    }
+    R.st.sparse_stage = 1;
+    R.st.stop_reason = SR_STOP_CONVERGED;
+    *fin = true;
+    return SR_OK;
+  };
   // after a pass: the host sparse stage if it applies
   auto pass_end_host = [&](bool *fin) -> sr_status {
     *fin = false;
@@ -1193,11 +1268,19 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     // so the first pages of a next pass are not fetched ahead then; a wrong
     // guess only delays that pass's first copy.
     const bool guess_last = !pr;
+    // A pass whose end the host stage will likely take (open_stage) does not
+    // fetch the next pass's first pages ahead. The guess is taken once the
+    // window starts on the second half of the pass: the device counts the
+    // vertices of the pages it has finished that the next pass would attempt
+    // if the pass ended now; few enough, and the copies are left out (a
+    // wrong guess only delays the next pass's first copy).
+    const bool open_guess = hetero && R.pvu == P_STRONG && !skip && g->state.has_in && g->state.fr_cap > 0;
     while (!done) {
       // pass start: every earlier sweep has finished (host synced at the pass end)
       if ((s = begin_pass()) != SR_OK) return s;
       const int32_t NP = (int32_t)ord.size();  // pages of this pass
       bool pass_changed = false, pass_verify = false;
+      bool guessed = false, host_end = false;
       if (NP > 0 && page_slot[ord[0]] < 0) {
         if ((s = copy_page(ord[0], free_slot({}), false)) != SR_OK) return s;
       }
@@ -1228,9 +1311,24 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
         // keep the next D pages coming (past the pass end: the next pass's
         // first pages); a free slot was last read by an earlier step's sweeps
         std::vector<int32_t> keep = win;
+        if (open_guess && !guessed && j + D >= NP) {
+          guessed = true;
+          const int32_t first = std::max(0, j - W + 1);  // pages before it are finished
+          if (2 * first >= NP) {
+            uint32_t *cnt_dev = g->state.fr_count + 1;  // (entry 0 counts the pass frontier)
+            uint32_t cnt = 0;
+            HIP_TRY(c, launch_fill_u32(cnt_dev, 0u, 1, c->compute), "open guess");
+            HIP_TRY(c, launch_open_guess(g->state.value, g->state.has_in, g->pages[ord[first]].hdr.v_begin,
+                                         g->state.ctl, cnt_dev, c->compute), "open guess");
+            HIP_TRY(c, hipMemcpyAsync(&cnt, cnt_dev, 4, hipMemcpyDeviceToHost, c->compute), "open guess");
+            HIP_TRY(c, hipStreamSynchronize(c->compute), "open guess");
+            host_end = cnt <= sparse_thr;
+          }
+        }
         for (int32_t q = 1; q <= D; ++q) {
           // skipping decides the next pass's pages at the pass end: no wrap
           if (skip && j + q >= NP) break;
+          if (host_end && j + q >= NP) break;
           if (guess_last && pass > 0 && !pass_changed && (R.pvu != P_WEAK || pass_verify) && j + q >= NP) break;
           const int32_t page = ord[(j + q) % NP];
           if (std::find(keep.begin(), keep.end(), page) != keep.end()) continue;
@@ -1302,6 +1400,10 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
         if (R.collect && (s = read_frontier(&have)) != SR_OK) return s;
         if ((s = sparse_stage(have, &fin)) != SR_OK) return s;
         done = fin;
+        if (!done && !returned) {
+          if ((s = open_stage(&fin)) != SR_OK) return s;
+          done = fin;
+        }
         if (!done && skip) {
           // next pass: the pages an edge from a changed vertex enters; all
           // of them when the frontier overflowed

@@ -44,6 +44,7 @@ struct RunState {
   uint32_t *frontier = nullptr;  // vertices changed in a pass (host sparse stage)
   uint32_t *fr_count = nullptr;
   uint32_t fr_cap = 0;
+  uint32_t *has_in = nullptr;    // one bit per vertex with an in-edge (the host stage's open list)
   bool valid = false;
 };
 
@@ -179,6 +180,10 @@ uint64_t frontier_pages(const sr_graph *g, const uint32_t *front, int64_t nf);
 // device; returns the edges relaxed
 int64_t sparse_push(sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
                     int32_t *rounds, int64_t limit = 0, std::vector<uint32_t> *rest = nullptr);
+// one Jacobi pull over the listed vertices' in-edges; *changed receives the
+// vertices whose value decreased; returns the edges read
+int64_t sparse_pull(sr_graph *g, int algo, uint32_t *val, const uint32_t *list, int64_t nl,
+                    std::vector<uint32_t> *changed);
 // engine.cpp
 // min_slot: streaming slots hold at least this many bytes (forced split-width images)
 sr_status ensure_residency(sr_graph *g, bool weights, bool force_stream, bool bins = false,

@@ -1231,6 +1231,48 @@ __global__ void __launch_bounds__(BLOCK) det_commit_kernel(SweepArgs a) {
     a.contrib[v] = a.contrib_next[v];
 }
 
+// The vertices the next pass would attempt under strong prediction: an
+// in-edge and a value above the Table I threshold (every other vertex is
+// final or cannot change). Appended to list up to cap; *count receives how
+// many there are. In a verification phase every vertex with an in-edge is
+// attempted.
+__global__ void __launch_bounds__(BLOCK) open_list_kernel(const uint32_t *value, const uint32_t *has_in, int32_t n,
+                                                          const Ctl *ctl, uint32_t *list, uint32_t cap,
+                                                          uint32_t *count) {
+  const int32_t v = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+  bool open = false;
+  if (v < n) {
+    const bool in = (has_in[v >> 5] >> (v & 31)) & 1u;
+    open = in && (ctl->phase != 0 || value[v] > ctl->threshold);
+  }
+  const unsigned long long b = __ballot(open);
+  if (b == 0ull) return;
+  const int lane = threadIdx.x % 64;
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(count, (uint32_t)__popcll(b));
+  base = __shfl(base, 0, 64);
+  const uint32_t idx = base + (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
+  if (open && idx < cap) list[idx] = (uint32_t)v;
+}
+
+// A guess for the copy schedule near a pass end: of the vertices below
+// v_limit (the pages the pass has finished), those the next pass would
+// attempt if the pass ended now (its smallest change so far as the SSSP/CC
+// threshold; BFS: the next pass count). Counting only.
+__global__ void __launch_bounds__(BLOCK) open_guess_kernel(const uint32_t *value, const uint32_t *has_in,
+                                                           int32_t v_limit, const Ctl *ctl, uint32_t *count) {
+  const int32_t v = (int32_t)(blockIdx.x * BLOCK + threadIdx.x);
+  bool open = false;
+  if (v < v_limit) {
+    const uint32_t thr = ctl->algo == A_BFS ? ctl->pass + 1u
+                                            : (ctl->pass_changed > 0 ? ctl->pass_min_changed : ctl->threshold);
+    const bool in = (has_in[v >> 5] >> (v & 31)) & 1u;
+    open = in && (ctl->phase != 0 || value[v] > thr);
+  }
+  const unsigned long long b = __ballot(open);
+  if (b != 0ull && threadIdx.x % 64 == 0) atomicAdd(count, (uint32_t)__popcll(b));
+}
+
 __global__ void end_pass_kernel(Ctl *ctl, SweepRecord *ring, uint32_t mask) {
   // a pass closed on its own gets a record of its own (no sweep counters)
   __shared__ __align__(16) SweepRecord s_rec;
@@ -1427,6 +1469,22 @@ hipError_t launch_sweep(int algo, const SweepArgs &a, hipStream_t s, hipEvent_t 
     case A_PPR: launch_pair<A_PPR>(a, s, mid); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_open_list(const uint32_t *value, const uint32_t *has_in, int32_t n, const Ctl *ctl,
+                            uint32_t *list, uint32_t cap, uint32_t *count, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(open_list_kernel, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, value, has_in, n, ctl,
+                     list, cap, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_open_guess(const uint32_t *value, const uint32_t *has_in, int32_t v_limit, const Ctl *ctl,
+                             uint32_t *count, hipStream_t s) {
+  if (v_limit <= 0) return hipSuccess;
+  hipLaunchKernelGGL(open_guess_kernel, dim3((v_limit + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, value, has_in,
+                     v_limit, ctl, count);
   return hipGetLastError();
 }
 

@@ -63,6 +63,15 @@ inline int sec_blocks(const PageHeader &h, int sec, bool all_tiles) {
 // is recorded between the two
 hipError_t launch_sweep(int algo, const SweepArgs &a, hipStream_t s, hipEvent_t mid = nullptr);
 hipError_t launch_end_pass(Ctl *ctl, SweepRecord *ring, uint32_t ring_mask, hipStream_t s);
+// vertices the next pass would attempt (strong prediction): list (up to cap)
+// and their number in *count (which the caller zeroes); has_in: one bit per
+// vertex with an in-edge
+hipError_t launch_open_list(const uint32_t *value, const uint32_t *has_in, int32_t n, const Ctl *ctl,
+                            uint32_t *list, uint32_t cap, uint32_t *count, hipStream_t s);
+// how many vertices below v_limit the next pass would attempt if the pass
+// ended now (a guess for the copy schedule; *count zeroed by the caller)
+hipError_t launch_open_guess(const uint32_t *value, const uint32_t *has_in, int32_t v_limit, const Ctl *ctl,
+                             uint32_t *count, hipStream_t s);
 hipError_t launch_init_min(int algo, uint32_t *value, int32_t n, int32_t source, hipStream_t s);
 hipError_t launch_init_pr(float *rank, float *contrib, const float *inv_outdeg, int32_t n,
                           int32_t seed, hipStream_t s);

@@ -123,6 +123,50 @@ int64_t sparse_push(sr_graph *g, int algo, uint32_t *val, const uint32_t *front,
   return relaxed;
 }
 
+// One pull on the host over the listed vertices, with the device sweep's
+// arithmetic over their in-edges. Every new value is computed from the
+// values as they were (a Jacobi step) and written afterwards; the vertices
+// whose value decreased go to *changed. Returns the edges read.
+int64_t sparse_pull(sr_graph *g, int algo, uint32_t *val, const uint32_t *list, int64_t nl,
+                    std::vector<uint32_t> *changed) {
+  const int T = host_threads();
+  const int use = (int)std::min<int64_t>((int64_t)T, std::max<int64_t>(1, nl / 1024));
+  std::vector<std::vector<std::pair<uint32_t, uint32_t>>> upd(use);
+  std::vector<int64_t> cnt(use, 0);
+  auto work = [&](int t, int64_t lo, int64_t hi) {
+    int64_t c = 0;
+    for (int64_t i = lo; i < hi; ++i) {
+      const uint32_t v = list[i];
+      if (v >= (uint32_t)g->n) continue;
+      uint32_t best = val[v];
+      for (int64_t e = g->in_off[v]; e < g->in_off[v + 1]; ++e) {
+        const uint32_t u = (uint32_t)g->in_src[e];
+        best = std::min(best, relax_value(algo, val[u], g->weighted ? g->in_w[e] : 1u));
+        ++c;
+      }
+      if (best < val[v]) upd[t].push_back({v, best});
+    }
+    cnt[t] = c;
+  };
+  if (use <= 1) {
+    work(0, 0, nl);
+  } else {
+    std::vector<std::thread> th;
+    for (int t = 0; t < use; ++t) th.emplace_back(work, t, nl * t / use, nl * (t + 1) / use);
+    for (auto &x : th) x.join();
+  }
+  int64_t edges = 0;
+  changed->clear();
+  for (int t = 0; t < use; ++t) {
+    edges += cnt[t];
+    for (auto &kv : upd[t]) {
+      val[kv.first] = kv.second;
+      changed->push_back(kv.first);
+    }
+  }
+  return edges;
+}
+
 }  // namespace sr
 
 namespace sr {

@@ -62,6 +62,7 @@ def run(ctx, g, algo, sched, sym=False, source=0, **kw):
         G.partition(s["parts"], s["slots"])
         st = G.run(algo, source=source, max_inner_iters=4, force_stream=s["force"], copy_depth=s["depth"],
                    hetero=True, max_passes=5000, **kw)
+        st["records"] = G.sweeps()
         return G.values(), st
     finally:
         G.close()
@@ -85,9 +86,19 @@ def test_hetero_exact(sr, ctx, gname, sched, switch, det):
                 f"sparse {st['sparse_stage']} frontier {st['sparse_frontier']} rounds {st['sparse_rounds']}")
             assert st["converged"] == 1
             assert np.array_equal(got, ref), f"{algo} {pvu}: {np.sum(got != ref)} mismatches"
+            if switch == 1 << 30 and pvu == "strong" and sched != "resident":
+                # streamed under strong prediction: the vertices the second
+                # pass would attempt (at most n) go to the host after the first
+                assert st["sparse_stage"] == 1 and st["passes"] == 1
     if switch == 1 << 30:
-        # a switch threshold above n hands over after the first complete pass
-        assert st["sparse_stage"] == 1
+        # a switch threshold above n hands over once a pass's changes fit it
+        # (weak prediction: after the verification pass that follows such a
+        # pass, unless that verification pass changed nothing and so ended
+        # the run on the device)
+        recs = st["records"]
+        last = [r for r in recs if r["pass"] == recs[-1]["pass"]]
+        ended_on_device = recs[-1]["phase"] == 1 and all(r["changed"] == 0 for r in last)
+        assert st["sparse_stage"] == 1 or ended_on_device
 
 
 def test_hetero_triggers_and_saves_passes(sr, ctx):
@@ -104,7 +115,9 @@ def test_hetero_triggers_and_saves_passes(sr, ctx):
         say(f"case hetero passes {het['passes']} vs {base['passes']}, frontier {het['sparse_frontier']}")
         assert het["sparse_stage"] == 1
         assert het["passes"] < base["passes"]
-        assert 0 < het["sparse_frontier"] <= 2048
+        # (the stage may start from an empty list: then the pass before it
+        # left no vertex to attempt)
+        assert 0 <= het["sparse_frontier"] <= 2048
     finally:
         G.close()
 
@@ -207,3 +220,54 @@ def test_hetero_two_way_switch(sr, ctx, sched):
             assert st["converged"] == 1
             assert st["sparse_returns"] >= 1
             assert st["sparse_entries"] >= st["sparse_returns"]
+
+
+OPEN_GRAPHS = {
+    "rmat16_sym": (lambda: graphgen.rmat(16, 16, seed=61, symmetrize=True), ("cc", "bfs")),
+    "uniform16_sym": (lambda: graphgen.uniform(16, 1 << 20, seed=62, symmetrize=True), ("cc", "bfs")),
+    "rmat16w": (lambda: graphgen.rmat(16, 8, seed=63, weights=(1, 255, 64)), ("sssp", "bfs")),
+}
+
+
+@pytest.mark.parametrize("gname", list(OPEN_GRAPHS))
+@pytest.mark.parametrize("sched", ["s3p3", "s4p7d2"])
+@pytest.mark.parametrize("reorder", [False, True])
+def test_hetero_open_list(sr, ctx, gname, sched, reorder):
+    """Streamed runs under strong prediction enter the host stage from the
+    list of vertices the next pass would attempt (an in-edge and a value
+    above the Table I threshold) once it is short, even when the pass before
+    changed far more vertices: the host pulls them and pushes from those that
+    changed. Bit-exact against the oracle, with no more device passes than
+    without the host stage; CC on the R-MAT graph ends after one pass."""
+    g = _open_graph(gname)
+    s = SCHED[sched]
+    src = int(np.argmax(np.diff(g.offsets)))
+    for algo in OPEN_GRAPHS[gname][1]:
+        ref = oracle.cc(g) if algo == "cc" else (oracle.sssp(g, src) if algo == "sssp" else oracle.bfs(g, src))
+        G = ctx.load(g, reorder=reorder, symmetric=algo == "cc")
+        try:
+            G.partition(s["parts"], s["slots"])
+            kw = dict(source=src, pvu="strong", force_stream=True, copy_depth=s["depth"], max_inner_iters=8,
+                      deterministic=True)
+            base = G.run(algo, **kw)
+            assert np.array_equal(G.values(), ref)
+            het = G.run(algo, hetero=True, sparse_switch=1024, **kw)
+            say(f"case open {gname} {sched} reorder={reorder} {algo}: passes {het['passes']} (without "
+                f"{base['passes']}) entries {het['sparse_entries']} list {het['sparse_frontier']} rounds "
+                f"{het['sparse_rounds']} finished {het['sparse_stage']}")
+            assert np.array_equal(G.values(), ref), f"{algo}: {np.sum(G.values() != ref)} mismatches"
+            assert het["converged"] == 1
+            assert het["passes"] <= base["passes"]
+            if algo == "cc" and gname == "rmat16_sym":
+                assert het["sparse_stage"] == 1 and het["passes"] == 1
+        finally:
+            G.close()
+
+
+_open_cache = {}
+
+
+def _open_graph(name):
+    if name not in _open_cache:
+        _open_cache[name] = OPEN_GRAPHS[name][0]()
+    return _open_cache[name]
