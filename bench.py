@@ -107,6 +107,23 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
     run_kw = dict(pvu="strong", max_inner_iters=args.inner, force_stream=True, copy_depth=args.copy_depth,
                   wide_pages=args.wide_pages, deterministic=args.schedule == "fixed",
                   hetero=not args.no_host_stage)
+    device_only = None
+    if not args.no_host_stage:
+        # the same solves with device passes only (the pass that proves
+        # convergence streams every page again), before the timed ones, so
+        # that a profile's last launches are those of the timed solves
+        dkw = dict(run_kw, hetero=False)
+        G.run("cc", **dkw)
+        sync()
+        t1 = time.perf_counter()
+        dst = [G.run("cc", **dkw) for _ in range(args.steps)]
+        sync()
+        del1 = time.perf_counter() - t1
+        dlab = G.values()
+        device_only = {"gteps": round(g.m * args.steps / del1 / 1e9, 4),
+                       "ms_per_step": round(del1 * 1e3 / args.steps, 3), "passes_per_solve": dst[-1]["passes"],
+                       "h2d_bytes_per_solve": sum(x["h2d_bytes"] for x in dst) // args.steps}
+        log(f"[bench] {workload} device passes only: {device_only}")
     for i in range(args.warmup):
         st = G.run("cc", **run_kw)
         log(f"[bench] {workload} warmup {i}: {st['wall_ms']:.1f} ms, passes {st['passes']}")
@@ -117,22 +134,8 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
     elapsed = time.perf_counter() - t0
     lab = G.values()
     st = stats[-1]
-    device_only = None
-    if not args.no_host_stage:
-        # the same solves with device passes only (the pass that proves
-        # convergence streams every page again)
-        dkw = dict(run_kw, hetero=False)
-        G.run("cc", **dkw)
-        sync()
-        t1 = time.perf_counter()
-        dst = [G.run("cc", **dkw) for _ in range(args.steps)]
-        sync()
-        del1 = time.perf_counter() - t1
-        assert np.array_equal(G.values(), lab)
-        device_only = {"gteps": round(g.m * args.steps / del1 / 1e9, 4),
-                       "ms_per_step": round(del1 * 1e3 / args.steps, 3), "passes_per_solve": dst[-1]["passes"],
-                       "h2d_bytes_per_solve": sum(x["h2d_bytes"] for x in dst) // args.steps}
-        log(f"[bench] {workload} device passes only: {device_only}")
+    if device_only is not None:
+        assert np.array_equal(dlab, lab)
     log(f"[bench] {workload}: {elapsed * 1e3 / args.steps:.1f} ms per solve, passes {st['passes']} sweeps "
         f"{st['sweeps']} kernel {st['kernel_ms']:.1f} ms h2d {st['h2d_ms']:.1f} ms ({st['h2d_bytes'] / 1e9:.2f} GB)")
     sweep_ms = sum(x["sweep_kernel_ms"] for x in stats)
