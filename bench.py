@@ -56,6 +56,13 @@ def kernel_traffic(name):
     return j["traffic_bytes_per_launch"], j["algo_bytes_per_launch_same_runs"]
 
 
+def sssp_inner(args):
+    """Re-sweeps per window step of the streamed SSSP leg: 4 (under the
+    deterministic schedule 2 needs a fifth pass and 8 re-sweeps windows
+    whose gains later passes would make anyway: 3.02 / 3.74 / 3.52 GTEPS)."""
+    return args.inner or 4
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -104,7 +111,8 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
     # the fixed schedule (a window is re-swept until a sweep changes nothing, at
     # most max_inner_iters times) does not depend on when a copy lands, so a
     # profiled run makes the same sweeps as the timed one
-    run_kw = dict(pvu="strong", max_inner_iters=args.inner, force_stream=True, copy_depth=args.copy_depth,
+    inner = args.inner or 8
+    run_kw = dict(pvu="strong", max_inner_iters=inner, force_stream=True, copy_depth=args.copy_depth,
                   wide_pages=args.wide_pages, deterministic=args.schedule == "fixed",
                   hetero=not args.no_host_stage)
     device_only = None
@@ -154,7 +162,7 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
         "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
         "config": {"workload": workload, "n": g.n, "m": g.m, "pages": info["num_parts"], "slots": args.slots,
                    "device_budget_bytes": budget, "graph_bytes": gbytes, "pvu": "strong",
-                   "max_inner_iters": args.inner, "copy_depth": args.copy_depth,
+                   "max_inner_iters": inner, "copy_depth": args.copy_depth,
                    "vertex_order": "degree descending (labels in input ids)" if args.order == "degree"
                    else "input",
                    "page_image": "full-width" if args.wide_pages else "split-width when smaller",
@@ -266,7 +274,8 @@ def bench_sssp22(args):
     log(f"[bench] loaded+partitioned in {time.perf_counter() - t:.1f}s: {info['num_parts']} pages, "
         f"budget {budget / 1e6:.1f} MB, graph {gbytes / 1e6:.1f} MB")
     # the fixed schedule (see the CC leg) makes profiled runs sweep as the timed ones do
-    run_kw = dict(source=0, pvu=args.pvu, max_inner_iters=args.inner, force_stream=True,
+    inner = sssp_inner(args)
+    run_kw = dict(source=0, pvu=args.pvu, max_inner_iters=inner, force_stream=True,
                   copy_depth=args.copy_depth, wide_pages=args.wide_pages,
                   deterministic=args.schedule == "fixed")
     for i in range(args.warmup):
@@ -312,7 +321,7 @@ def bench_sssp22(args):
         "config": {"workload": "sssp_rmat22_ef16_w1-255_src0_streamed_budget_quarter",
                    "n": g.n, "m": g.m, "pages": info["num_parts"], "slots": args.slots,
                    "device_budget_bytes": budget, "graph_bytes": gbytes,
-                   "pvu": args.pvu, "max_inner_iters": args.inner, "copy_depth": args.copy_depth,
+                   "pvu": args.pvu, "max_inner_iters": inner, "copy_depth": args.copy_depth,
                    "vertex_order": "in-degree descending (results in input ids)" if args.order == "degree"
                    else "input",
                    "page_image": "full-width" if args.wide_pages else "split-width",
@@ -452,10 +461,10 @@ def ablation(args, G, parts, dist):
     and for the weak predictor the per-pass changed / skipped vertices (the
     status curves of Fig. 10)."""
     scheds = [("baseline", 2, 1, True, "off", 1), ("rsi_mrt2", 2, 2, True, "off", 1),
-              ("psi", args.slots, args.inner, False, "off", 1),
-              ("psi_strong", args.slots, args.inner, False, "strong", 1),
-              ("psi_weak", args.slots, args.inner, False, "weak", 1),
-              ("psi_strong_depth2", args.slots, args.inner, False, "strong", 2)]
+              ("psi", args.slots, sssp_inner(args), False, "off", 1),
+              ("psi_strong", args.slots, sssp_inner(args), False, "strong", 1),
+              ("psi_weak", args.slots, sssp_inner(args), False, "weak", 1),
+              ("psi_strong_depth2", args.slots, sssp_inner(args), False, "strong", 2)]
     out = {}
     for name, slots, inner, fixed, pvu, depth in scheds:
         G.partition(parts, slots)
@@ -542,7 +551,7 @@ def bench_bfs_early_break(args, g, G):
     Gr = ctx_r.load(g, reorder=args.order == "degree")
     Gr.partition(1, 4)
     legs = (("resident", Gr, dict(source=0, pvu="strong")),
-            ("streamed", G, dict(source=0, pvu="strong", max_inner_iters=args.inner, force_stream=True,
+            ("streamed", G, dict(source=0, pvu="strong", max_inner_iters=sssp_inner(args), force_stream=True,
                                  copy_depth=args.copy_depth)))
     for name, H, kw in legs:
         row = {}
@@ -848,7 +857,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--inner", type=int, default=8)
+    ap.add_argument("--inner", type=int, default=0,
+                    help="max re-sweeps per window step (0: 8 for the CC legs, 4 for the SSSP leg)")
     ap.add_argument("--pvu", default="strong",
                     help="predictor of the timed solves (the other one is reported beside it)")
     ap.add_argument("--no-cpu", action="store_true")
