@@ -807,6 +807,9 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
   const int ninst = a.ngroups * K;
   lds_clear(lds, ninst, BLOCK);
   const int lane = threadIdx.x % 64, k = lane % K;
+  // consecutive items of a block mostly lie in one unit: its item range
+  // carries over from item to item (the search runs only when an item leaves it)
+  int32_t cu = 0, cu_lo = 0, cu_hi = -1;  // the last unit and its items [cu_lo, cu_hi)
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_base = (int32_t)atomicAdd(&a.ctl->queue, (uint32_t)a.grab);
@@ -816,15 +819,20 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
     const int32_t end = min(base + a.grab, a.total_items);
     for (int32_t qi = base; qi < end; ++qi) {
       const int32_t it = a.descending ? a.total_items - 1 - qi : qi;
-      int lo = 0, hi = a.nunits;  // unit_prefix[lo] <= it < unit_prefix[hi]
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (a.unit_prefix[mid] <= it) lo = mid; else hi = mid;
+      if (it < cu_lo || it >= cu_hi) {
+        int lo = 0, hi = a.nunits;  // unit_prefix[lo] <= it < unit_prefix[hi]
+        while (hi - lo > 1) {
+          int mid = (lo + hi) >> 1;
+          if (a.unit_prefix[mid] <= it) lo = mid; else hi = mid;
+        }
+        cu = lo;
+        cu_lo = a.unit_prefix[lo];
+        cu_hi = a.unit_prefix[lo + 1];
       }
-      const MiUnit &u = a.units[lo];
+      const MiUnit &u = a.units[cu];
       if (a.group_active[u.group] == 0) continue;  // no live instance in this group
       const MiGroup &g = a.groups[u.group];
-      const int local = it - a.unit_prefix[lo];
+      const int local = it - cu_lo;
       int bin = 0;
       while (bin < NBINS - 1 && u.blk_prefix[bin + 1] <= local) ++bin;
       const int item = local - u.blk_prefix[bin];
@@ -841,38 +849,37 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
   } while (0)
       if constexpr (mi_narrow<ALGO>()) {
         constexpr int EL4 = 256 / K;  // edge lanes with four columns per lane
-        const Lane4 ln = lane4_of<K>(g, lane % (K / 4), a.tuning != 0);
-        Acc4 acc;
+        const Lane4 ln4 = lane4_of<K>(g, lane % (K / 4), a.tuning != 0);
+        Acc4 acc4;
         switch (bin) {
-          case 0: MI_WM((mp_small<K, 1, ROUNDS, WM>(g, bp, h, 0, item, ln, acc))); break;
-          case 1: MI_WM((mp_small<K, (2 < EL4 ? 2 : EL4), ROUNDS, WM>(g, bp, h, 1, item, ln, acc))); break;
-          case 2: MI_WM((mp_small<K, (4 < EL4 ? 4 : EL4), ROUNDS, WM>(g, bp, h, 2, item, ln, acc))); break;
-          case 3: MI_WM((mp_small<K, (8 < EL4 ? 8 : EL4), ROUNDS, WM>(g, bp, h, 3, item, ln, acc))); break;
-          case 4: MI_WM((mp_small<K, (16 < EL4 ? 16 : EL4), ROUNDS, WM>(g, bp, h, 4, item, ln, acc))); break;
-          case 5: MI_WM((mp_small<K, (32 < EL4 ? 32 : EL4), ROUNDS, WM>(g, bp, h, 5, item, ln, acc))); break;
-          case BIN_WAVE: MI_WM((mp_wave<K, WM>(g, bp, h, item, ln, acc))); break;
-          case BIN_CHUNK: MI_WM((mp_chunk<K, WM>(g, u, bp, h, item, ln))); break;
+          case 0: MI_WM((mp_small<K, 1, ROUNDS, WM>(g, bp, h, 0, item, ln4, acc4))); break;
+          case 1: MI_WM((mp_small<K, (2 < EL4 ? 2 : EL4), ROUNDS, WM>(g, bp, h, 1, item, ln4, acc4))); break;
+          case 2: MI_WM((mp_small<K, (4 < EL4 ? 4 : EL4), ROUNDS, WM>(g, bp, h, 2, item, ln4, acc4))); break;
+          case 3: MI_WM((mp_small<K, (8 < EL4 ? 8 : EL4), ROUNDS, WM>(g, bp, h, 3, item, ln4, acc4))); break;
+          case 4: MI_WM((mp_small<K, (16 < EL4 ? 16 : EL4), ROUNDS, WM>(g, bp, h, 4, item, ln4, acc4))); break;
+          case 5: MI_WM((mp_small<K, (32 < EL4 ? 32 : EL4), ROUNDS, WM>(g, bp, h, 5, item, ln4, acc4))); break;
+          case BIN_WAVE: MI_WM((mp_wave<K, WM>(g, bp, h, item, ln4, acc4))); break;
+          case BIN_CHUNK: MI_WM((mp_chunk<K, WM>(g, u, bp, h, item, ln4))); break;
           default: break;  // no zero in-degree bin outside PageRank
         }
-        mp_flush<K>(lds, u.group, acc);
-        continue;
+        mp_flush<K>(lds, u.group, acc4);
       } else {
-      const Lane ln = lane_of(g.inst[k]);
-      MiAcc acc;
-      switch (bin) {
-        case 0: MI_WM((mi_small<ALGO, K, 1, ROUNDS, WM>(g, bp, h, 0, item, ln, a.damping, acc))); break;
-        case 1: MI_WM((mi_small<ALGO, K, (2 < 64 / K ? 2 : 64 / K), ROUNDS, WM>(g, bp, h, 1, item, ln, a.damping, acc))); break;
-        case 2: MI_WM((mi_small<ALGO, K, (4 < 64 / K ? 4 : 64 / K), ROUNDS, WM>(g, bp, h, 2, item, ln, a.damping, acc))); break;
-        case 3: MI_WM((mi_small<ALGO, K, (8 < 64 / K ? 8 : 64 / K), ROUNDS, WM>(g, bp, h, 3, item, ln, a.damping, acc))); break;
-        case 4: MI_WM((mi_small<ALGO, K, (16 < 64 / K ? 16 : 64 / K), ROUNDS, WM>(g, bp, h, 4, item, ln, a.damping, acc))); break;
-        case 5: MI_WM((mi_small<ALGO, K, (32 < 64 / K ? 32 : 64 / K), ROUNDS, WM>(g, bp, h, 5, item, ln, a.damping, acc))); break;
-        case BIN_WAVE: MI_WM((mi_wave<ALGO, K, WM>(g, bp, h, item, ln, a.damping, acc))); break;
-        case BIN_CHUNK: MI_WM((mi_chunk<ALGO, K, WM>(g, u, bp, h, item, ln))); break;
-        default:
-          if constexpr (mi_pr<ALGO>()) mi_zero<ALGO, K, ROUNDS>(g, bp, h, item, ln, a.damping, acc);
-          break;
-      }
-      mi_flush<ALGO, K>(lds, u.group, acc);
+        const Lane ln = lane_of(g.inst[k]);
+        MiAcc acc;
+        switch (bin) {
+          case 0: MI_WM((mi_small<ALGO, K, 1, ROUNDS, WM>(g, bp, h, 0, item, ln, a.damping, acc))); break;
+          case 1: MI_WM((mi_small<ALGO, K, (2 < 64 / K ? 2 : 64 / K), ROUNDS, WM>(g, bp, h, 1, item, ln, a.damping, acc))); break;
+          case 2: MI_WM((mi_small<ALGO, K, (4 < 64 / K ? 4 : 64 / K), ROUNDS, WM>(g, bp, h, 2, item, ln, a.damping, acc))); break;
+          case 3: MI_WM((mi_small<ALGO, K, (8 < 64 / K ? 8 : 64 / K), ROUNDS, WM>(g, bp, h, 3, item, ln, a.damping, acc))); break;
+          case 4: MI_WM((mi_small<ALGO, K, (16 < 64 / K ? 16 : 64 / K), ROUNDS, WM>(g, bp, h, 4, item, ln, a.damping, acc))); break;
+          case 5: MI_WM((mi_small<ALGO, K, (32 < 64 / K ? 32 : 64 / K), ROUNDS, WM>(g, bp, h, 5, item, ln, a.damping, acc))); break;
+          case BIN_WAVE: MI_WM((mi_wave<ALGO, K, WM>(g, bp, h, item, ln, a.damping, acc))); break;
+          case BIN_CHUNK: MI_WM((mi_chunk<ALGO, K, WM>(g, u, bp, h, item, ln))); break;
+          default:
+            if constexpr (mi_pr<ALGO>()) mi_zero<ALGO, K, ROUNDS>(g, bp, h, item, ln, a.damping, acc);
+            break;
+        }
+        mi_flush<ALGO, K>(lds, u.group, acc);
       }
 #undef MI_WM
     }
