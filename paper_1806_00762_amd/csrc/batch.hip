@@ -833,9 +833,17 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
       if (a.group_active[u.group] == 0) continue;  // no live instance in this group
       const MiGroup &g = a.groups[u.group];
       const int local = it - cu_lo;
+      // the item's bin: the unit's bin starts loaded together, then counted
+      // (they grow with the bin), with no chain of dependent loads
+      int32_t pf[NBINS];
+#pragma unroll
+      for (int b = 0; b < NBINS; ++b) pf[b] = u.blk_prefix[b];
       int bin = 0;
-      while (bin < NBINS - 1 && u.blk_prefix[bin + 1] <= local) ++bin;
-      const int item = local - u.blk_prefix[bin];
+      int32_t first = 0;
+#pragma unroll
+      for (int b = 1; b < NBINS; ++b)
+        if (pf[b] <= local) { bin = b; first = pf[b]; }
+      const int item = local - first;
       const char *bp = u.page;
       const PageHeader *h = reinterpret_cast<const PageHeader *>(bp);
       // the weight mode: the plan's, or the group's when the plan mixes them
