@@ -807,6 +807,19 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
   const int ninst = a.ngroups * K;
   lds_clear(lds, ninst, BLOCK);
   const int lane = threadIdx.x % 64, k = lane % K;
+  // the lanes' instance state (gate thresholds, weights, PageRank terms),
+  // taken once per block into LDS after the counters when the launch has
+  // the room (lane_lds): items read it there instead of from the records
+  Lane *lanes = reinterpret_cast<Lane *>(lds + ninst);
+  Lane4 *lanes4 = reinterpret_cast<Lane4 *>(lds + ninst);
+  if (a.lane_lds) {
+    if constexpr (mi_narrow<ALGO>()) {
+      for (int i = threadIdx.x; i < a.ngroups * (K / 4); i += BLOCK)
+        lanes4[i] = lane4_of<K>(a.groups[i / (K / 4)], i % (K / 4), a.tuning != 0);
+    } else {
+      for (int i = threadIdx.x; i < ninst; i += BLOCK) lanes[i] = lane_of(a.groups[i / K].inst[i % K]);
+    }
+  }
   // consecutive items of a block mostly lie in one unit: its item range
   // carries over from item to item (the search runs only when an item leaves it)
   int32_t cu = 0, cu_lo = 0, cu_hi = -1;  // the last unit and its items [cu_lo, cu_hi)
@@ -857,7 +870,8 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
   } while (0)
       if constexpr (mi_narrow<ALGO>()) {
         constexpr int EL4 = 256 / K;  // edge lanes with four columns per lane
-        const Lane4 ln4 = lane4_of<K>(g, lane % (K / 4), a.tuning != 0);
+        const Lane4 ln4 = a.lane_lds ? lanes4[u.group * (K / 4) + lane % (K / 4)]
+                                     : lane4_of<K>(g, lane % (K / 4), a.tuning != 0);
         Acc4 acc4;
         switch (bin) {
           case 0: MI_WM((mp_small<K, 1, ROUNDS, WM>(g, bp, h, 0, item, ln4, acc4))); break;
@@ -872,7 +886,7 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
         }
         mp_flush<K>(lds, u.group, acc4);
       } else {
-        const Lane ln = lane_of(g.inst[k]);
+        const Lane ln = a.lane_lds ? lanes[u.group * K + k] : lane_of(g.inst[k]);
         MiAcc acc;
         switch (bin) {
           case 0: MI_WM((mi_small<ALGO, K, 1, ROUNDS, WM>(g, bp, h, 0, item, ln, a.damping, acc))); break;
@@ -1101,10 +1115,16 @@ void mi_sweep_wm(const MiArgs &a, hipStream_t s, size_t lds) {
 
 template <int ALGO, int K>
 void mi_pair(const MiArgs &a, hipStream_t s) {
+  // LDS: per-instance counters (the heavy kernel too), then the sweep's lane
+  // states when both fit 64 KiB
   const size_t lds = sizeof(MiLds) * (size_t)a.ngroups * K;
-  if (a.rounds == 2) mi_sweep_wm<ALGO, K, 2>(a, s, lds);
-  else if (a.rounds == 8) mi_sweep_wm<ALGO, K, 8>(a, s, lds);
-  else mi_sweep_wm<ALGO, K, 4>(a, s, lds);
+  const size_t lanes = mi_narrow<ALGO>() ? sizeof(Lane4) * (size_t)a.ngroups * (K / 4) : sizeof(Lane) * (size_t)a.ngroups * K;
+  MiArgs b = a;
+  b.lane_lds = lds + lanes <= 65536 ? 1 : 0;
+  const size_t sweep_lds = b.lane_lds ? lds + lanes : lds;
+  if (a.rounds == 2) mi_sweep_wm<ALGO, K, 2>(b, s, sweep_lds);
+  else if (a.rounds == 8) mi_sweep_wm<ALGO, K, 8>(b, s, sweep_lds);
+  else mi_sweep_wm<ALGO, K, 4>(b, s, sweep_lds);
   hipLaunchKernelGGL((mi_heavy_kernel<ALGO, K>), dim3(a.heavy_blocks), dim3(BLOCK), lds, s, a);
   hipLaunchKernelGGL((mi_close_kernel<ALGO, K>), dim3(1), dim3(MI_CLOSE_THREADS), 0, s, a);
 }

@@ -89,6 +89,7 @@ struct MiArgs {
   double tol_l1, floor_cap;
   int32_t max_sweeps;
   int32_t tuning;           // 1: never retire instances (timing runs)
+  int32_t lane_lds;         // set at launch: the sweep keeps the lanes' instance state in LDS
   int32_t descending;       // 1: the queue hands out items last to first (heavy chunks and
                             // high in-degree bins of the last unit first)
   MiCtl *ctl;
