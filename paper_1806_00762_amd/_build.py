@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "seraph")
 LIB = os.path.join(HERE, "libseraph.so")
 
-SOURCES = ["kernels.hip", "engine.cpp", "graph_host.cpp", "sparse.cpp", "batch.hip", "mi_plan.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "engine.cpp", "graph_host.cpp", "sparse.cpp", "batch.hip", "mi_plan.cpp", "server.cpp",
+           "stage.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

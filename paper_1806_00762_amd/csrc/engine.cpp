@@ -1069,13 +1069,46 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     }
     uint32_t *val = g->host_val;
     std::vector<uint32_t> open((size_t)cnt);
-    if (cnt)
+    if (cnt) {
       HIP_TRY(c, hipMemcpyAsync(open.data(), g->state.frontier, 4ull * cnt, hipMemcpyDeviceToHost, c->compute),
               "open list to host");
-    HIP_TRY(c, hipMemcpyAsync(val, g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute), "values to host");
-    HIP_TRY(c, hipStreamSynchronize(c->compute), "values to host");
+      HIP_TRY(c, hipStreamSynchronize(c->compute), "open list to host");
+    }
+    // a short list reads only the values the pull needs (the listed vertices
+    // and their in-neighbours, gathered on the device into the frontier's
+    // upper half); a pull that changes something, or a long list, reads the
+    // whole value array, which the push needs
     std::vector<uint32_t> changed;
-    int64_t relaxed = sr::sparse_pull(g, R.algo, val, open.data(), (int64_t)cnt, &changed);
+    int64_t relaxed = 0;
+    bool pulled = false;
+    {
+      std::vector<uint32_t> ids(open.begin(), open.end());
+      const uint32_t half = g->state.fr_cap / 2;
+      for (uint32_t v : open) {
+        for (int64_t e = g->in_off[v]; e < g->in_off[v + 1] && ids.size() <= half; ++e) ids.push_back((uint32_t)g->in_src[e]);
+        if (ids.size() > half) break;
+      }
+      if (ids.size() <= half) {
+        std::vector<uint32_t> got(ids.size());
+        uint32_t *d_ids = g->state.frontier, *d_got = g->state.frontier + half;
+        if (!ids.empty()) {
+          HIP_TRY(c, hipMemcpyAsync(d_ids, ids.data(), 4ull * ids.size(), hipMemcpyHostToDevice, c->compute),
+                  "open ids to device");
+          HIP_TRY(c, launch_gather_u32(g->state.value, d_ids, (uint32_t)ids.size(), d_got, c->compute), "open gather");
+          HIP_TRY(c, hipMemcpyAsync(got.data(), d_got, 4ull * ids.size(), hipMemcpyDeviceToHost, c->compute),
+                  "open values to host");
+          HIP_TRY(c, hipStreamSynchronize(c->compute), "open values to host");
+        }
+        for (size_t i = 0; i < ids.size(); ++i) val[ids[i]] = got[i];
+        relaxed = sr::sparse_pull(g, R.algo, val, open.data(), (int64_t)cnt, &changed);
+        pulled = changed.empty();
+      }
+    }
+    if (!pulled) {
+      HIP_TRY(c, hipMemcpyAsync(val, g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute), "values to host");
+      HIP_TRY(c, hipStreamSynchronize(c->compute), "values to host");
+      relaxed = sr::sparse_pull(g, R.algo, val, open.data(), (int64_t)cnt, &changed);
+    }
     int32_t rounds = 1;
     rest.clear();
     if (!changed.empty()) {

@@ -180,6 +180,9 @@ uint64_t frontier_pages(const sr_graph *g, const uint32_t *front, int64_t nf);
 // device; returns the edges relaxed
 int64_t sparse_push(sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
                     int32_t *rounds, int64_t limit = 0, std::vector<uint32_t> *rest = nullptr);
+// stage.hip: dst[i] = src[idx[i]] for i < count (device buffers)
+hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t count, uint32_t *dst,
+                             hipStream_t s);
 // one Jacobi pull over the listed vertices' in-edges; *changed receives the
 // vertices whose value decreased; returns the edges read
 int64_t sparse_pull(sr_graph *g, int algo, uint32_t *val, const uint32_t *list, int64_t nl,
