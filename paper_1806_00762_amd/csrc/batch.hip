@@ -823,6 +823,11 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
   // consecutive items of a block mostly lie in one unit: its item range
   // carries over from item to item (the search runs only when an item leaves it)
   int32_t cu = 0, cu_lo = 0, cu_hi = -1;  // the last unit and its items [cu_lo, cu_hi)
+  // per-instance counters of the items so far, added to LDS when the group
+  // changes or the block ends
+  int acc_group = -1;
+  MiAcc acc;
+  Acc4 acc4;
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_base = (int32_t)atomicAdd(&a.ctl->queue, (uint32_t)a.grab);
@@ -845,6 +850,13 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
       const MiUnit &u = a.units[cu];
       if (a.group_active[u.group] == 0) continue;  // no live instance in this group
       const MiGroup &g = a.groups[u.group];
+      if (u.group != acc_group) {
+        if (acc_group >= 0) {
+          if constexpr (mi_narrow<ALGO>()) mp_flush<K>(lds, acc_group, acc4);
+          else mi_flush<ALGO, K>(lds, acc_group, acc);
+        }
+        acc_group = u.group;
+      }
       const int local = it - cu_lo;
       // the item's bin: the unit's bin starts loaded together, then counted
       // (they grow with the bin), with no chain of dependent loads
@@ -872,7 +884,6 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
         constexpr int EL4 = 256 / K;  // edge lanes with four columns per lane
         const Lane4 ln4 = a.lane_lds ? lanes4[u.group * (K / 4) + lane % (K / 4)]
                                      : lane4_of<K>(g, lane % (K / 4), a.tuning != 0);
-        Acc4 acc4;
         switch (bin) {
           case 0: MI_WM((mp_small<K, 1, ROUNDS, WM>(g, bp, h, 0, item, ln4, acc4))); break;
           case 1: MI_WM((mp_small<K, (2 < EL4 ? 2 : EL4), ROUNDS, WM>(g, bp, h, 1, item, ln4, acc4))); break;
@@ -884,10 +895,8 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
           case BIN_CHUNK: MI_WM((mp_chunk<K, WM>(g, u, bp, h, item, ln4))); break;
           default: break;  // no zero in-degree bin outside PageRank
         }
-        mp_flush<K>(lds, u.group, acc4);
       } else {
         const Lane ln = a.lane_lds ? lanes[u.group * K + k] : lane_of(g.inst[k]);
-        MiAcc acc;
         switch (bin) {
           case 0: MI_WM((mi_small<ALGO, K, 1, ROUNDS, WM>(g, bp, h, 0, item, ln, a.damping, acc))); break;
           case 1: MI_WM((mi_small<ALGO, K, (2 < 64 / K ? 2 : 64 / K), ROUNDS, WM>(g, bp, h, 1, item, ln, a.damping, acc))); break;
@@ -901,10 +910,13 @@ __global__ void __launch_bounds__(BLOCK) mi_sweep_kernel(MiArgs a) {
             if constexpr (mi_pr<ALGO>()) mi_zero<ALGO, K, ROUNDS>(g, bp, h, item, ln, a.damping, acc);
             break;
         }
-        mi_flush<ALGO, K>(lds, u.group, acc);
       }
 #undef MI_WM
     }
+  }
+  if (acc_group >= 0) {
+    if constexpr (mi_narrow<ALGO>()) mp_flush<K>(lds, acc_group, acc4);
+    else mi_flush<ALGO, K>(lds, acc_group, acc);
   }
   // publish this block's per-instance counters (device-scope atomics on
   // distinct instance records; the close kernel reads them after the sweep)
