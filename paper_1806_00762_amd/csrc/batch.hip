@@ -14,6 +14,7 @@
 // graph with no host work in between; no fence is executed inside the sweep.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "batch.hpp"
@@ -1219,6 +1220,60 @@ hipError_t launch_mi_set_inst(MiInst *dst, const MiInst &val, hipStream_t s) {
 
 hipError_t launch_mi_set_ctl(MiCtl *dst, const MiCtl &val, hipStream_t s) {
   hipLaunchKernelGGL(mi_set_ctl_kernel, dim3(1), dim3(64), 0, s, dst, val);
+  return hipGetLastError();
+}
+
+namespace {
+__global__ void __launch_bounds__(256) mi_setup_kernel(const MiGroup *groups, const uint32_t *buf, int32_t ngroups,
+                                                       int32_t nadmit, uint32_t remaining, MiCtl *ctl,
+                                                       uint32_t *group_active, int32_t K, int32_t narrow) {
+  const int32_t i = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+  if (i == 0) {
+    ctl->queue = 0;
+    ctl->pad = 0;
+    ctl->remaining = remaining;
+    ctl->sweeps = 0;
+  }
+  if (i < ngroups) group_active[i] = buf[i];
+  if (i >= nadmit) return;
+  const MiAdmit ad = reinterpret_cast<const MiAdmit *>(buf + ngroups)[i];
+  const MiGroup &g = groups[ad.group];
+  const size_t idx = (size_t)ad.source * (size_t)K + (size_t)ad.col;
+  if (narrow) reinterpret_cast<uint16_t *>(g.value)[idx] = 0;
+  else g.value[idx] = 0u;
+  // the record a fresh column starts from (as the host's column set-up)
+  MiInst in;
+  in.active = 1;
+  in.unit = ad.unit;
+  in.source = ad.source;
+  in.threshold = 0;  // value 0 (the source) is final from the start
+  in.sweeps = 0;
+  in.done = 0;
+  in.stop_reason = 0;
+  in.no_improve = 0;
+  in.sw_changed = 0;
+  in.sw_min_changed = INF;
+  in.sw_edges = 0;
+  in.sw_l1 = 0.0;
+  in.sw_ddelta = 0.0;
+  in.sw_dmass = 0.0;
+  in.dangling = 0.0;
+  in.mass = 0.0;
+  in.best_l1 = 1e300;
+  in.last_l1 = -1.0;
+  in.edges_total = 0;
+  in.overflow = 0;
+  in.pad = 0;
+  g.inst[ad.col] = in;
+}
+}  // namespace
+
+hipError_t launch_mi_setup(const MiGroup *groups, const uint32_t *buf, int32_t ngroups, int32_t nadmit,
+                           uint32_t remaining, MiCtl *ctl, uint32_t *group_active, int32_t K, bool narrow,
+                           hipStream_t s) {
+  const int32_t n = std::max(1, std::max(ngroups, nadmit));
+  hipLaunchKernelGGL(mi_setup_kernel, dim3((n + 255) / 256), dim3(256), 0, s, groups, buf, ngroups, nadmit, remaining,
+                     ctl, group_active, K, narrow ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -105,6 +105,18 @@ hipError_t launch_mi_init_column(int algo, int K, uint32_t *value, float *contri
 hipError_t launch_mi_set_u16(uint32_t *value, size_t index, uint32_t v, hipStream_t s);
 hipError_t launch_mi_set_inst(MiInst *dst, const MiInst &val, hipStream_t s);
 hipError_t launch_mi_set_ctl(MiCtl *dst, const MiCtl &val, hipStream_t s);
+// One serving iteration's set-up in one launch: a query admitted into a
+// clean column (its source's entry set to 0, the column's record started),
+// the per-group active counts and the control block's reset.
+struct MiAdmit {
+  int32_t group, col, source;  // source: internal vertex id
+  uint32_t unit;               // 1 = BFS
+};
+constexpr int MI_ADMIT_MAX = 1024;
+// buf (device): ngroups u32 active counts, then nadmit MiAdmit entries
+hipError_t launch_mi_setup(const MiGroup *groups, const uint32_t *buf, int32_t ngroups, int32_t nadmit,
+                           uint32_t remaining, MiCtl *ctl, uint32_t *group_active, int32_t K, bool narrow,
+                           hipStream_t s);
 // Columns to copy out of value[n][K] in one pass: out[j][v] = value[v][col[j]].
 constexpr int MI_EXTRACT_MAX = 32;
 struct MiExtract {

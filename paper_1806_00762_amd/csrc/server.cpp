@@ -60,6 +60,10 @@ struct sr_server {
   bool stop = false;
   hipStream_t stream = nullptr, poll_stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around each sweep replay
+  // an iteration's set-up (per-graph active counts, then the admissions),
+  // staged in pinned memory and applied on the device by one launch
+  uint32_t *h_setup = nullptr, *d_setup = nullptr;
+  MiInst *h_inst = nullptr;  // pinned copy of every column's record, read after each sweep
   std::atomic<uint64_t> submitted{0}, completed{0}, sweeps{0}, fallbacks{0};
   double busy_ms = 0;
   double kernel_ms = 0;     // device time of the sweep replays
@@ -104,9 +108,11 @@ sr_status sr_server::complete_on_host(int gi, int32_t algo, uint32_t *result) {
 void sr_server::progress() {
   (void)hipSetDevice(c->device);
   const int G = (int)graphs.size();
-  std::vector<MiInst> ih((size_t)G * K);
+  MiInst *ih = h_inst;
+  MiAdmit *adm = reinterpret_cast<MiAdmit *>(h_setup + G);
   while (true) {
     bool any_active = false;
+    int32_t nadm = 0;
     {
       std::unique_lock<std::mutex> lk(mu);
       // admission: FIFO, skipping queries whose graph has no free slot
@@ -119,15 +125,19 @@ void sr_server::progress() {
         if (busy < usable[gi] && !free_results[gi].empty())
           for (int k = 0; k < K; ++k)
             if (slot_ticket[gi][k] == 0) { col = k; break; }
-        if (col < 0) { ++it; continue; }
+        if (col < 0 || nadm >= MI_ADMIT_MAX) { ++it; continue; }
         qq.slot = col;
         qq.state = Q_RUNNING;
         qq.result = free_results[gi].back();
         free_results[gi].pop_back();
         slot_ticket[gi][col] = *it;
         // retired columns are left at INF, so admission writes the source only
-        sr_status s = plan->set_column(gi, col, qq.source, qq.algo == SR_BFS, true, stream, true);
-        if (s != SR_OK) { thread_error = s; thread_msg = c->err; }
+        const sr_graph *gg = graphs[gi];
+        adm[nadm].group = gi;
+        adm[nadm].col = col;
+        adm[nadm].source = gg->reordered ? gg->rank[qq.source] : qq.source;
+        adm[nadm].unit = qq.algo == SR_BFS ? 1u : 0u;
+        nadm++;
         it = queue.erase(it);
       }
       for (int gi = 0; gi < G; ++gi)
@@ -150,17 +160,21 @@ void sr_server::progress() {
           if (t && q[t].state == Q_RUNNING) { gact[gi]++; total++; }
         }
     }
-    hipError_t e = hipMemcpyAsync(plan->args.group_active, gact.data(), 4ull * G, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess && plan->set_remaining(total, stream) != SR_OK) e = hipErrorUnknown;
+    for (int gi = 0; gi < G; ++gi) h_setup[gi] = gact[gi];
+    hipError_t e = hipMemcpyAsync(d_setup, h_setup, 4ull * G + sizeof(MiAdmit) * (size_t)nadm, hipMemcpyHostToDevice,
+                                  stream);
+    if (e == hipSuccess)
+      e = launch_mi_setup(plan->args.groups, d_setup, G, nadm, total, plan->args.ctl, plan->args.group_active, K,
+                          plan->narrow, stream);
     if (e == hipSuccess) e = hipEventRecord(ev0, stream);
     if (e == hipSuccess && plan->launch(stream) != SR_OK) e = hipErrorUnknown;
     if (e == hipSuccess) e = hipEventRecord(ev1, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    float sweep_ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&sweep_ms, ev0, ev1);
+    // the instance records into pinned memory right behind the sweep: one wait for both
     for (int gi = 0; gi < G && e == hipSuccess; ++gi)
       e = hipMemcpyAsync(&ih[(size_t)gi * K], plan->groups[gi].inst, sizeof(MiInst) * K, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    float sweep_ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&sweep_ms, ev0, ev1);
     if (e != hipSuccess) {
       std::lock_guard<std::mutex> lk(mu);
       thread_error = SR_EDEVICE;
@@ -262,7 +276,13 @@ extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_
   s->c = c;
   s->K = max_slots;
   s->graphs.assign(graphs, graphs + ngraphs);
-  auto fail = [&](sr_status st) { delete s->plan; delete s; return st; };
+  auto fail = [&](sr_status st) {
+    if (s->h_setup) (void)hipHostFree(s->h_setup);
+    if (s->h_inst) (void)hipHostFree(s->h_inst);
+    delete s->plan;
+    delete s;
+    return st;
+  };
   sr_status st;
   for (auto *g : s->graphs) {
     if (g->pages.empty())
@@ -292,6 +312,13 @@ extern "C" sr_status sr_server_create(sr_ctx *c, sr_graph *const *graphs, int32_
       hipStreamCreateWithFlags(&s->poll_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
     return fail(c->fail(SR_EDEVICE, "stream creation failed"));
+  {
+    const size_t setup_bytes = 4ull * ngraphs + sizeof(MiAdmit) * MI_ADMIT_MAX;
+    if (hipHostMalloc((void **)&s->h_setup, setup_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&s->h_inst, sizeof(MiInst) * (size_t)ngraphs * s->K, hipHostMallocDefault) != hipSuccess)
+      return fail(c->fail(SR_ENOMEM, "pinned set-up buffers"));
+    if ((st = s->plan->alloc((void **)&s->d_setup, setup_bytes, "set-up buffer")) != SR_OK) return fail(st);
+  }
   s->usable.assign(ngraphs, R);
   s->slot_ticket.assign(ngraphs, std::vector<uint64_t>(s->K, 0));
   s->free_results.resize(ngraphs);
@@ -422,6 +449,8 @@ extern "C" sr_status sr_server_destroy(sr_server *s) {
   if (s->poll_stream) (void)hipStreamDestroy(s->poll_stream);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
+  if (s->h_setup) (void)hipHostFree(s->h_setup);
+  if (s->h_inst) (void)hipHostFree(s->h_inst);
   delete s->plan;
   for (auto *g : s->graphs) g->server_refs--;
   delete s;
