@@ -356,6 +356,7 @@ extern "C" void sr_graph_destroy(sr_graph *g) {
     release_residency(g);
     release_state(g);
     if (g->host_val) (void)hipHostFree(g->host_val);
+    if (g->perm_pinned) (void)hipHostFree(g->perm_pinned);
   }
   sr::free_pages(g);
   delete g;
@@ -925,9 +926,19 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     else if (pr) e = launch_init_pr((float *)rs.value, rs.contrib, rs.inv_outdeg, g->n,
                                     R.algo == A_PPR ? p.source : -1, c->compute);
     else e = launch_init_min(R.algo, rs.value, g->n, p.source, c->compute);
-    // CC labels are the caller's ids, so the smallest one of a component wins
-    if (e == hipSuccess && R.algo == A_CC && g->reordered)
-      e = hipMemcpyAsync(rs.value, g->perm.data(), 4ull * g->n, hipMemcpyHostToDevice, c->compute);
+    // CC labels are the caller's ids, so the smallest one of a component
+    // wins; from pinned memory the copy needs no staging and overlaps the
+    // first page's
+    if (e == hipSuccess && R.algo == A_CC && g->reordered) {
+      if (!g->perm_pinned) {
+        if (hipHostMalloc((void **)&g->perm_pinned, 4ull * g->n, hipHostMallocDefault) == hipSuccess)
+          std::memcpy(g->perm_pinned, g->perm.data(), 4ull * g->n);
+        else
+          g->perm_pinned = nullptr;  // (the pageable copy below still works, staged)
+      }
+      const int32_t *src = g->perm_pinned ? g->perm_pinned : g->perm.data();
+      e = hipMemcpyAsync(rs.value, src, 4ull * g->n, hipMemcpyHostToDevice, c->compute);
+    }
     if (e == hipSuccess) e = launch_fill_u8(rs.status, (uint8_t)d.initial_state, (size_t)g->n, c->compute);
   }
   // on resume the values and predictor states stay; the control block

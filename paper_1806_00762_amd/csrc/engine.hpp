@@ -142,6 +142,7 @@ struct sr_graph {
   // transfers run at the pinned copy rate) and the per-vertex queue flags,
   // which are all zero between calls
   uint32_t *host_val = nullptr;
+  int32_t *perm_pinned = nullptr;  // perm in pinned memory: CC's first labels, copied with no staging
   std::vector<uint8_t> push_inq;
 };
 
