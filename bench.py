@@ -193,6 +193,7 @@ def _cc_leg(args, g, workload, traffic_name, cpu=True):
         "host_stage": {"entries_per_solve": round(sum(x["sparse_entries"] for x in stats) / args.steps, 2),
                        "finished_solves": sum(x["sparse_stage"] for x in stats),
                        "list": st["sparse_frontier"], "edges_per_solve": st["sparse_relaxations"],
+                       "rounds": st["sparse_rounds"], "value_bytes_copied": st["sparse_copy_bytes"],
                        "ms_per_solve": round(sum(x["sparse_ms"] for x in stats) / args.steps, 3)},
         "device_passes_only": device_only,
     }
@@ -399,6 +400,7 @@ def bench_sssp22(args):
                          "device_passes": h["passes"], "sparse_stage": h["sparse_stage"],
                          "sparse_frontier": h["sparse_frontier"], "sparse_rounds": h["sparse_rounds"],
                          "sparse_relaxations": h["sparse_relaxations"], "sparse_ms": round(h["sparse_ms"], 3),
+                         "sparse_value_bytes_copied": h["sparse_copy_bytes"],
                          "h2d_bytes_per_solve": h["h2d_bytes"],
                          "note": "device dense passes + host push sparse stage; not the headline value"}
         log(f"[bench] hetero: {res['hetero']}")

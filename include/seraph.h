@@ -340,6 +340,8 @@ typedef struct {
   int32_t pr_delta_passes;   /* SR_RUN_PR_DELTA: passes of the residual phase */
   int32_t sweep_launches;    /* launches of the sweep kernel, including those of a window that had
                                 already stopped changing (they exit at once and count no sweep) */
+  uint64_t sparse_copy_bytes;/* SR_RUN_HETERO: vertex-value bytes the host stage copied between host
+                                and device, both ways (lists and ids not counted; all entries) */
 } sr_run_stats;
 
 /* Run a vertex program to convergence on the graph (partitioned with

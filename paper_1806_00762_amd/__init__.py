@@ -88,7 +88,7 @@ class sr_run_stats(ctypes.Structure):
                 ("pages_skipped", ctypes.c_int64), ("sweep_kernel_ms", ctypes.c_double),
                 ("edges_narrow", ctypes.c_int64), ("sparse_entries", ctypes.c_int32),
                 ("sparse_returns", ctypes.c_int32), ("pr_delta_passes", ctypes.c_int32),
-                ("sweep_launches", ctypes.c_int32)]
+                ("sweep_launches", ctypes.c_int32), ("sparse_copy_bytes", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}

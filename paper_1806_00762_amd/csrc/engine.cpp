@@ -1012,26 +1012,93 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     return SR_OK;
   };
   std::vector<uint32_t> rest;  // host frontier handed back to the device
+  // A push that stays small reads only the values it needs: each round's
+  // missing values are gathered on the device into the frontier buffer's
+  // upper half (ids in its lower half), and at the end the lowered values
+  // (and `also`, vertices the caller lowered) are scattered back. *done is
+  // false, with the device values untouched, when the push outgrows half the
+  // buffer, its list passes sparse_ret, or it needs more round trips (about
+  // 40 us each) than copying the value array both ways would cost (8n bytes
+  // at ~56 GB/s, about n / 7000 us; at least 2 round trips); the caller then
+  // copies the arrays.
+  auto push_fetched = [&](std::unordered_map<uint32_t, uint32_t> &known, const std::vector<uint32_t> &front,
+                          const std::vector<uint32_t> &also, bool *done, int32_t *rounds,
+                          int64_t *relaxed) -> sr_status {
+    *done = false;
+    const uint32_t half = g->state.fr_cap / 2;
+    if (half == 0) return SR_OK;
+    uint32_t *d_ids = g->state.frontier, *d_got = g->state.frontier + half;
+    sr::build_out_csr(g);
+    hipError_t fe = hipSuccess;
+    const int64_t max_fetches = std::max<int64_t>(2, (int64_t)g->n / 350000);
+    int64_t fetches = 0;
+    auto fetch = [&](const std::vector<uint32_t> &need, std::vector<uint32_t> &vals) -> bool {
+      if (++fetches > max_fetches) return false;
+      fe = hipMemcpyAsync(d_ids, need.data(), 4ull * need.size(), hipMemcpyHostToDevice, c->compute);
+      if (fe == hipSuccess) fe = launch_gather_u32(g->state.value, d_ids, (uint32_t)need.size(), d_got, c->compute);
+      if (fe == hipSuccess) fe = hipMemcpyAsync(vals.data(), d_got, 4ull * need.size(), hipMemcpyDeviceToHost, c->compute);
+      if (fe == hipSuccess) fe = hipStreamSynchronize(c->compute);
+      R.st.sparse_copy_bytes += 4ull * need.size();
+      return fe == hipSuccess;
+    };
+    std::vector<uint32_t> lowered;
+    int32_t pr = 0;
+    int64_t rel = 0;
+    const bool ok = sr::sparse_push_partial(g, R.algo, known, front, sparse_ret, half, fetch, &lowered, &pr, &rel);
+    if (fe != hipSuccess) return c->hip_fail(fe, "push values from device");
+    if (!ok) return SR_OK;
+    std::vector<uint32_t> wid(also);
+    wid.insert(wid.end(), lowered.begin(), lowered.end());
+    std::sort(wid.begin(), wid.end());
+    wid.erase(std::unique(wid.begin(), wid.end()), wid.end());
+    if (wid.size() > half) return SR_OK;
+    if (!wid.empty()) {
+      std::vector<uint32_t> wval(wid.size());
+      for (size_t i = 0; i < wid.size(); ++i) wval[i] = known[wid[i]];
+      HIP_TRY(c, hipMemcpyAsync(d_ids, wid.data(), 4ull * wid.size(), hipMemcpyHostToDevice, c->compute),
+              "lowered ids to device");
+      HIP_TRY(c, hipMemcpyAsync(d_got, wval.data(), 4ull * wid.size(), hipMemcpyHostToDevice, c->compute),
+              "lowered values to device");
+      HIP_TRY(c, launch_scatter_u32(g->state.value, d_ids, d_got, (uint32_t)wid.size(), c->compute), "lowered values");
+      HIP_TRY(c, hipStreamSynchronize(c->compute), "lowered values");
+      R.st.sparse_copy_bytes += 4ull * wid.size();
+    }
+    *done = true;
+    *rounds = pr;
+    *relaxed = rel;
+    return SR_OK;
+  };
   auto sparse_stage = [&](bool have_fr, bool *fin) -> sr_status {
     *fin = false;
     returned = false;
     if (!hetero || !R.collect || !have_fr || R.last_pass_changed > sparse_thr) return SR_OK;
     if (R.pvu == P_WEAK && R.last_pass_phase != 1) return SR_OK;  // not after a verification pass
     const double t1 = now_ms();
-    if (!g->host_val && g->n > 0) {
-      HIP_TRY(c, hipHostMalloc((void **)&g->host_val, 4ull * g->n, hipHostMallocDefault), "pinned value mirror");
-    }
-    uint32_t *val = g->host_val;
-    HIP_TRY(c, hipMemcpyAsync(val, g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute),
-            "values to host");
-    HIP_TRY(c, hipStreamSynchronize(c->compute), "values to host");
-    sr::build_out_csr(g);
     int32_t rounds = 0;
-    const int64_t relaxed = sr::sparse_push(g, R.algo, val, fr.data(), (int64_t)fr.size(), &rounds,
-                                            sparse_ret, &rest);
-    HIP_TRY(c, hipMemcpyAsync(g->state.value, val, 4ull * g->n, hipMemcpyHostToDevice, c->compute),
-            "values to device");
-    HIP_TRY(c, hipStreamSynchronize(c->compute), "values to device");
+    int64_t relaxed = 0;
+    bool pushed = false;
+    rest.clear();
+    {
+      std::unordered_map<uint32_t, uint32_t> known;
+      sr_status s2 = push_fetched(known, fr, {}, &pushed, &rounds, &relaxed);
+      if (s2 != SR_OK) return s2;
+    }
+    if (!pushed) {
+      if (!g->host_val && g->n > 0) {
+        HIP_TRY(c, hipHostMalloc((void **)&g->host_val, 4ull * g->n, hipHostMallocDefault), "pinned value mirror");
+      }
+      uint32_t *val = g->host_val;
+      R.st.sparse_copy_bytes += 4ull * g->n;
+      HIP_TRY(c, hipMemcpyAsync(val, g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute),
+              "values to host");
+      HIP_TRY(c, hipStreamSynchronize(c->compute), "values to host");
+      sr::build_out_csr(g);
+      relaxed = sr::sparse_push(g, R.algo, val, fr.data(), (int64_t)fr.size(), &rounds, sparse_ret, &rest);
+      R.st.sparse_copy_bytes += 4ull * g->n;
+      HIP_TRY(c, hipMemcpyAsync(g->state.value, val, 4ull * g->n, hipMemcpyHostToDevice, c->compute),
+              "values to device");
+      HIP_TRY(c, hipStreamSynchronize(c->compute), "values to device");
+    }
     R.st.sparse_entries++;
     R.st.sparse_rounds += rounds;
     R.st.sparse_frontier = (int64_t)fr.size();
@@ -1087,11 +1154,15 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
     }
     // a short list reads only the values the pull needs (the listed vertices
     // and their in-neighbours, gathered on the device into the frontier's
-    // upper half); a pull that changes something, or a long list, reads the
-    // whole value array, which the push needs
+    // upper half); when the pull changes something the push goes on the same
+    // way, fetching each round's missing values and writing back only the
+    // lowered ones; a long list, or a push that outgrows the buffer, reads
+    // the whole value array
     std::vector<uint32_t> changed;
     int64_t relaxed = 0;
-    bool pulled = false;
+    int32_t rounds = 1;
+    bool pulled = false;  // the pull changed nothing
+    bool pushed = false;  // a short push reached the fixed point
     {
       std::vector<uint32_t> ids(open.begin(), open.end());
       const uint32_t half = g->state.fr_cap / 2;
@@ -1109,28 +1180,43 @@ extern "C" sr_status sr_run(sr_graph *g, const sr_run_params *params, sr_run_sta
           HIP_TRY(c, hipMemcpyAsync(got.data(), d_got, 4ull * ids.size(), hipMemcpyDeviceToHost, c->compute),
                   "open values to host");
           HIP_TRY(c, hipStreamSynchronize(c->compute), "open values to host");
+          R.st.sparse_copy_bytes += 4ull * ids.size();
         }
         for (size_t i = 0; i < ids.size(); ++i) val[ids[i]] = got[i];
         relaxed = sr::sparse_pull(g, R.algo, val, open.data(), (int64_t)cnt, &changed);
         pulled = changed.empty();
+        if (!pulled) {
+          std::unordered_map<uint32_t, uint32_t> known;
+          known.reserve(2 * ids.size());
+          for (uint32_t v : ids) known[v] = val[v];
+          int32_t prounds = 0;
+          int64_t prelaxed = 0;
+          sr_status s2 = push_fetched(known, changed, changed, &pushed, &prounds, &prelaxed);
+          if (s2 != SR_OK) return s2;
+          if (pushed) {
+            rounds += prounds;
+            relaxed += prelaxed;
+          }
+        }
       }
     }
-    if (!pulled) {
+    rest.clear();
+    if (!pulled && !pushed) {
       HIP_TRY(c, hipMemcpyAsync(val, g->state.value, 4ull * g->n, hipMemcpyDeviceToHost, c->compute), "values to host");
       HIP_TRY(c, hipStreamSynchronize(c->compute), "values to host");
+      R.st.sparse_copy_bytes += 4ull * g->n;
       relaxed = sr::sparse_pull(g, R.algo, val, open.data(), (int64_t)cnt, &changed);
-    }
-    int32_t rounds = 1;
-    rest.clear();
-    if (!changed.empty()) {
-      sr::build_out_csr(g);
-      int32_t pr_rounds = 0;
-      relaxed += sr::sparse_push(g, R.algo, val, changed.data(), (int64_t)changed.size(), &pr_rounds, sparse_ret,
-                                 &rest);
-      rounds += pr_rounds;
-      HIP_TRY(c, hipMemcpyAsync(g->state.value, val, 4ull * g->n, hipMemcpyHostToDevice, c->compute),
-              "values to device");
-      HIP_TRY(c, hipStreamSynchronize(c->compute), "values to device");
+      if (!changed.empty()) {
+        sr::build_out_csr(g);
+        int32_t pr_rounds = 0;
+        relaxed += sr::sparse_push(g, R.algo, val, changed.data(), (int64_t)changed.size(), &pr_rounds, sparse_ret,
+                                   &rest);
+        rounds += pr_rounds;
+        HIP_TRY(c, hipMemcpyAsync(g->state.value, val, 4ull * g->n, hipMemcpyHostToDevice, c->compute),
+                "values to device");
+        HIP_TRY(c, hipStreamSynchronize(c->compute), "values to device");
+        R.st.sparse_copy_bytes += 4ull * g->n;
+      }
     }
     R.st.sparse_entries++;
     R.st.sparse_rounds += rounds;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -181,9 +182,24 @@ uint64_t frontier_pages(const sr_graph *g, const uint32_t *front, int64_t nf);
 // device; returns the edges relaxed
 int64_t sparse_push(sr_graph *g, int algo, uint32_t *val, const uint32_t *front, int64_t nf,
                     int32_t *rounds, int64_t limit = 0, std::vector<uint32_t> *rest = nullptr);
+// push from a frontier over values the host holds only in part: `known`
+// maps vertices to their values; before each round `fetch(need, got)` is
+// asked for the values of the round's vertices and out-neighbours missing
+// from `known` and may refuse (returns false). Returns false, with nothing
+// written to the device, when a fetch is refused, `known` would pass cap
+// entries or a round's list exceeds limit (> 0); else true, with *lowered
+// listing every vertex whose value decreased (its new value in `known`),
+// *rounds and *relaxed set
+bool sparse_push_partial(sr_graph *g, int algo, std::unordered_map<uint32_t, uint32_t> &known,
+                         const std::vector<uint32_t> &front, int64_t limit, size_t cap,
+                         const std::function<bool(const std::vector<uint32_t> &, std::vector<uint32_t> &)> &fetch,
+                         std::vector<uint32_t> *lowered, int32_t *rounds, int64_t *relaxed);
 // stage.hip: dst[i] = src[idx[i]] for i < count (device buffers)
 hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t count, uint32_t *dst,
                              hipStream_t s);
+// stage.hip: dst[idx[i]] = vals[i] for i < count (device buffers, distinct idx)
+hipError_t launch_scatter_u32(uint32_t *dst, const uint32_t *idx, const uint32_t *vals, uint32_t count,
+                              hipStream_t s);
 // one Jacobi pull over the listed vertices' in-edges; *changed receives the
 // vertices whose value decreased; returns the edges read
 int64_t sparse_pull(sr_graph *g, int algo, uint32_t *val, const uint32_t *list, int64_t nl,

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 #include <thread>
+#include <unordered_map>
 
 #include "engine.hpp"
 
@@ -121,6 +122,76 @@ int64_t sparse_push(sr_graph *g, int algo, uint32_t *val, const uint32_t *front,
   }
   if (rounds_out) *rounds_out = rounds;
   return relaxed;
+}
+
+// The same push over a partial copy of the values: rounds relax in list
+// order with immediate updates (monotone min relaxations reach the same
+// least fixed point in any order), each preceded by one fetch of the values
+// the round will read (its list's and their out-neighbours') that the host
+// does not hold yet.
+bool sparse_push_partial(sr_graph *g, int algo, std::unordered_map<uint32_t, uint32_t> &known,
+                         const std::vector<uint32_t> &front, int64_t limit, size_t cap,
+                         const std::function<bool(const std::vector<uint32_t> &, std::vector<uint32_t> &)> &fetch,
+                         std::vector<uint32_t> *lowered, int32_t *rounds_out, int64_t *relaxed_out) {
+  const uint32_t n = (uint32_t)g->n;
+  std::vector<uint32_t> cur, next, need, got;
+  std::unordered_map<uint32_t, uint8_t> inq;  // 1: in the next round's list
+  std::unordered_map<uint32_t, uint8_t> low;  // vertices lowered so far
+  for (uint32_t v : front)
+    if (v < n && !inq[v]) { inq[v] = 1; cur.push_back(v); }
+  int32_t rounds = 0;
+  int64_t relaxed = 0;
+  lowered->clear();
+  while (!cur.empty()) {
+    if (limit > 0 && (int64_t)cur.size() > limit) return false;
+    // a round whose values the host cannot hold (more than cap in all)
+    // gives up as soon as it has collected cap of them
+    need.clear();
+    for (uint32_t u : cur)
+      if (!known.count(u)) {
+        known[u] = INF;
+        need.push_back(u);
+        if (known.size() > cap) return false;
+      }
+    for (uint32_t u : cur)
+      for (int64_t e = g->out_off[u]; e < g->out_off[u + 1]; ++e) {
+        const uint32_t v = (uint32_t)g->out_dst[e];
+        if (!known.count(v)) {
+          known[v] = INF;  // placeholder until the fetch fills it
+          need.push_back(v);
+          if (known.size() > cap) return false;
+        }
+      }
+    if (!need.empty()) {
+      got.assign(need.size(), INF);
+      if (!fetch(need, got)) return false;
+      for (size_t i = 0; i < need.size(); ++i) known[need[i]] = got[i];
+    }
+    ++rounds;
+    next.clear();
+    for (uint32_t u : cur) inq[u] = 0;
+    for (uint32_t u : cur) {
+      const uint32_t xu = known[u];
+      if (xu == INF && algo != A_CC) continue;
+      for (int64_t e = g->out_off[u]; e < g->out_off[u + 1]; ++e) {
+        const uint32_t v = (uint32_t)g->out_dst[e];
+        const uint32_t nd = relax_value(algo, xu, g->weighted ? g->out_w[e] : 1u);
+        ++relaxed;
+        uint32_t &xv = known[v];
+        if (nd < xv) {
+          xv = nd;
+          low[v] = 1;
+          if (!inq[v]) { inq[v] = 1; next.push_back(v); }
+        }
+      }
+    }
+    cur.swap(next);
+  }
+  lowered->reserve(low.size());
+  for (auto &kv : low) lowered->push_back(kv.first);
+  *rounds_out = rounds;
+  *relaxed_out = relaxed;
+  return true;
 }
 
 // One pull on the host over the listed vertices, with the device sweep's

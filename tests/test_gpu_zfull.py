@@ -85,17 +85,29 @@ def _cc_streamed(sr, g, name):
     ref = oracle.cc(g)
     say(f"{name}: union-find {time.time() - t:.1f}s, components {len(np.unique(ref))}")
     gbytes = 4 * (g.n + 1) + 4 * g.m
-    # pages stream through slots worth 1/4 of the graph next to the vertex state
-    budget = gbytes // 4 + 5 * g.n + (1 << 20)
+    # pages stream through slots worth 1/4 of the graph next to the vertex
+    # state (and the host stage's in-edge bitmap, one bit per vertex)
+    budget = gbytes // 4 + 5 * g.n + g.n // 8 + (1 << 20)
     with sr.Context(0, budget) as ctx:
         t = time.time()
         G = ctx.load(g, symmetric=True)
         G.partition(0, 4)
         say(f"{name}: load+partition {time.time() - t:.1f}s, pages {G.info()['num_parts']}")
-        st = G.run("cc", pvu="strong", max_inner_iters=4, force_stream=True)
+        st0 = st = G.run("cc", pvu="strong", max_inner_iters=4, force_stream=True)
         lab = G.values()
         say(f"{name}: passes {st['passes']} wall {st['wall_ms']:.0f} ms h2d {st['h2d_bytes'] / 1e9:.2f} GB")
         assert np.array_equal(lab, ref)
+        # with the host stage, as the CC bench legs run: device passes, then
+        # the host checks the vertices the next pass would attempt (reading
+        # only the values it touches when they fit half the frontier buffer,
+        # else the whole array, down and back once per entry)
+        st = G.run("cc", pvu="strong", max_inner_iters=8, force_stream=True, copy_depth=2, deterministic=True,
+                   hetero=True)
+        say(f"{name} host stage: passes {st['passes']} list {st['sparse_frontier']} rounds {st['sparse_rounds']} "
+            f"relaxations {st['sparse_relaxations']} copied {st['sparse_copy_bytes']} B in {st['sparse_ms']:.2f} ms")
+        assert np.array_equal(G.values(), ref)
+        assert st["sparse_stage"] == 1 and st["passes"] <= st0["passes"]
+        assert 0 < st["sparse_copy_bytes"] <= 8 * g.n * st["sparse_entries"]
         G.close()
 
 
