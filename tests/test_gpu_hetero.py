@@ -296,12 +296,20 @@ def test_hetero_short_push(sr, ctx, sched):
     g, src = layered()
     for algo, sym in (("sssp", False), ("bfs", False), ("cc", True)):
         ref = oracle.cc(g) if algo == "cc" else (oracle.sssp(g, src) if algo == "sssp" else oracle.bfs(g, src))
-        for pvu in ("strong", "off"):
+        for pvu in ("strong", "off", "weak"):
             got, st = run(ctx, g, algo, sched, sym=sym, source=src, pvu=pvu, sparse_switch=g.n)
             say(f"case short push {sched} {algo} {pvu}: passes {st['passes']} entries {st['sparse_entries']} "
                 f"rounds {st['sparse_rounds']} relaxations {st['sparse_relaxations']} "
-                f"copied {st['sparse_copy_bytes']} B")
+                f"copied {st['sparse_copy_bytes']} B finished {st['sparse_stage']}")
             assert np.array_equal(got, ref), f"{algo} {pvu}: {np.sum(got != ref)} mismatches"
-            assert st["converged"] == 1 and st["sparse_stage"] == 1
+            assert st["converged"] == 1
+            if pvu == "weak":
+                # entered only after a verification pass, from a frontier that
+                # may need more round trips than the short path allows: then
+                # it falls back to copying the array both ways, after at most
+                # half the frontier buffer's worth of fetched values
+                assert st["sparse_copy_bytes"] <= 8 * g.n * max(1, st["sparse_entries"]) + 4 * g.n
+                continue
+            assert st["sparse_stage"] == 1
             assert 0 < st["sparse_copy_bytes"] < 4 * g.n
 
